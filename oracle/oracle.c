@@ -718,8 +718,11 @@ static void model_coeffs(const geom *g, const orc_params *P, const cplx *psi,
                     double sg = br == 0 ? 1.0 : -1.0;
                     double V = e11 * n1 + e22 * n2 + sg * sq;
                     if (V <= 0.0) continue;
-                    double V1 = lin1 + (sq > 0.0 ? sg * A / sq : 0.0);
-                    double V2 = lin2 + (sq > 0.0 ? sg * (B / (2.0 * sq) - A * A / (2.0 * sq * s2)) : 0.0);
+                    /* B/(2s) - A^2/(2s^3) written as (B - (A/s)^2)/(2s): s^3 underflows
+                     * where the densities are ~1e-135 (box corners) */
+                    double As = sq > 0.0 ? A / sq : 0.0;
+                    double V1 = lin1 + sg * As;
+                    double V2 = lin2 + (sq > 0.0 ? sg * (B - As * As) / (2.0 * sq) : 0.0);
                     double rv = sqrt(V);
                     a1 += g->wq[q] * V * rv * V1;
                     a2 += g->wq[q] * (V * rv * V2 + 0.75 * rv * V1 * V1);
