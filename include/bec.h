@@ -1,0 +1,209 @@
+/*
+ * bec.h -- C ABI of the MI355X (gfx950) library for ground states of a
+ * two-component dipolar Bose-Einstein condensate with Lee-Huang-Yang (LHY)
+ * corrections, computed by the preconditioned nonlinear conjugate-gradient
+ * method on the product-of-spheres manifold of arXiv:2510.24543.
+ *
+ * Problem (Sec. II, Eq. (1); Sec. III): minimise E[psi_1, psi_2] subject to
+ * ||psi_1|| = ||psi_2|| = 1, where
+ *   E = sum_i N_i [ <psi_i, T psi_i> + int V n_i + 1/2 sum_j G_ij int n_i n_j
+ *                   + 1/2 sum_j Gdd_ij int n_i Phi_j ] + int e_LHY(n_1, n_2),
+ *   T = -1/2 Laplacian, V = 1/2 sum_d omega_d^2 x_d^2 (Eq. (2)), n_i = |psi_i|^2,
+ *   Phi_j = F^-1[ Ud F n_j ], Ud(k) = (3 kz^2/|k|^2 - 1) c(|k| r_cut), Ud(0) = 0,
+ *   c(q) = 1 + 3 cos q / q^2 - 3 sin q / q^3 (dipolar kernel cut off at radius
+ *   r_cut, field along z), and e_LHY = c_lhy sqrt(2)/(15 pi^2) int_0^1 du
+ *   sum_+- [V_+-(u)]_+^(5/2) with V_+- of Eq. (3) and couplings
+ *   eta_ij = G_ij + Gdd_ij (3u^2 - 1).  The u integral is Gauss-Legendre with
+ *   n_u nodes.  Gdd_ij is the amplitude of the k-space dipolar kernel.
+ *
+ * Discretisation: Fourier pseudo-spectral on the periodic box [lo, hi) with
+ * n[d] points per axis, x_d[j] = lo_d + j h_d, h_d = (hi_d - lo_d)/n_d,
+ * <f,g> = dV sum conj(f) g, dV = h_x h_y h_z.
+ *
+ * Conventions shared by every entry point
+ *  - Fields are DEVICE pointers to complex128 stored as interleaved (re, im)
+ *    double pairs, layout C order [2][nx][ny][nz] (component, x, y, z; z
+ *    fastest), 16-byte aligned.  The caller owns every field buffer and the
+ *    workspace; the library never allocates device memory after bec_create
+ *    and never frees caller memory.
+ *  - All device work is enqueued on the HIP stream given to bec_create.
+ *    Entry points that return host structs synchronise that stream before
+ *    returning; bec_fft3d is asynchronous.
+ *  - Supported axis lengths: 8, 16, 32, 48, 64, 96, 128, 256 (each axis
+ *    independently).  Other lengths return BEC_EUNSUPPORTED.
+ *  - Errors are reported by the status code; bec_last_error() gives a
+ *    thread-local message.  No C++ exception crosses this boundary.
+ *    A non-finite reduced scalar gives BEC_ENONFINITE.
+ *  - One context serves one stream and one thread at a time.
+ */
+#ifndef BEC_H
+#define BEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BEC_OK = 0,
+    BEC_EINVAL = 1,        /* invalid argument                                   */
+    BEC_ENOMEM = 2,        /* workspace too small                                */
+    BEC_EHIP = 3,          /* a HIP runtime call failed                          */
+    BEC_ENOTCONV = 4,      /* solve stopped at max_iter                          */
+    BEC_ESTAGNATED = 5,    /* no descent even after the beta = 0 restart         */
+    BEC_ENONFINITE = 6,    /* a reduced scalar was NaN or infinite               */
+    BEC_EUNSUPPORTED = 7   /* axis length not supported                          */
+} bec_status;
+
+/* Periodic box [lo, hi) with n points per axis (x, y, z). */
+typedef struct {
+    int32_t n[3];
+    double lo[3], hi[3];
+} bec_grid;
+
+/* Physical parameters in harmonic-oscillator units (Sec. II).  N_i G_ij and
+ * N_i Gdd_ij must be symmetric (the energy form requires it). */
+typedef struct {
+    double N[2];        /* atom numbers N_i > 0                                */
+    double omega[3];    /* trap ratios lambda_d (Eq. (2))                      */
+    double G[2][2];     /* contact couplings G_ij                              */
+    double Gdd[2][2];   /* dipolar k-space amplitudes                          */
+    double c_lhy;       /* multiplier of the LHY term (1 = the paper)          */
+    double r_cut;       /* dipolar cutoff radius, > 0                          */
+    int32_t n_u;        /* Gauss-Legendre nodes for the u integral, 1..64      */
+} bec_params;
+
+/* Preconditioners of Sec. IV.B: identity, real-space diagonal P_V, kinetic
+ * P_Delta (Fourier diagonal), and the composite P_Delta^-1 P_V^-1 (Eq. (18)). */
+typedef enum { BEC_PC_NONE = 0, BEC_PC_V = 1, BEC_PC_KIN = 2, BEC_PC_COMPOSITE = 3 } bec_precond;
+
+/* Conjugacy parameter of Sec. IV.C: Hestenes-Stiefel+, Polak-Ribiere+, or 0. */
+typedef enum { BEC_BETA_HS_PLUS = 0, BEC_BETA_PR_PLUS = 1, BEC_BETA_ZERO = 2 } bec_beta;
+
+typedef struct {
+    int32_t pc;             /* bec_precond                                     */
+    int32_t beta;           /* bec_beta                                        */
+    int32_t max_iter;       /* accepted steps before BEC_ENOTCONV              */
+    int32_t restart_period; /* beta = 0 when iter mod restart_period == 0; 0 off */
+    int32_t max_backtrack;  /* Armijo halvings per step                        */
+    int32_t pad;
+    double tol_grad;        /* stop when max_i ||H_i psi_i - mu_i psi_i|| < tol */
+    double tol_dE;          /* stop when |E_n - E_(n-1)| < tol_dE (0: off)     */
+    double sigma;           /* regularising shift of P_V and P_Delta           */
+    double armijo_c1;       /* sufficient-decrease constant                    */
+    double theta_max;       /* largest geodesic angle per step                 */
+    double tau_rel;         /* a step is accepted when E_new <= E + tau_rel|E| */
+} bec_opts;
+
+/* Energy decomposition at one state (Sec. II, Eq. (1); Sec. III, Eq. (7)). */
+typedef struct {
+    double E;
+    double E_kin[2], E_trap[2], E_c[2][2], E_dd[2][2], E_lhy;
+    double mu[2];       /* <psi_i, H_i psi_i> / <psi_i, psi_i>                  */
+    double shift[2];    /* preconditioner shift alpha_i                         */
+    double res[2];      /* ||H_i psi_i - mu_i psi_i||                           */
+    double norm2[2];    /* ||psi_i||^2                                          */
+} bec_terms;
+
+/* One line search (Sec. V).  path bits: 1 Armijo backtracking was used. */
+typedef struct {
+    double E0, E1, E2, alpha, theta[2], E_new, pnorm[2];
+    int32_t n_trials, path;
+} bec_ls_report;
+
+/* Per accepted step of bec_solve.  path bits: 1 Armijo, 2 beta = 0 retry after
+ * a failed line search, 4 fallback preconditioner (composite only). */
+typedef struct {
+    int32_t iter, n_trials, restarted, path;
+    double E, res_max, E1, E2, alpha, beta;
+} bec_iter;
+
+typedef struct {
+    int32_t iters, n_restarts, n_backtracks, status;
+    bec_terms final;
+    double seconds;     /* wall time of the solve (host clock)                 */
+} bec_report;
+
+typedef struct bec_ctx bec_ctx;
+
+/* Bytes of device workspace bec_create needs for this grid (about 370 bytes per
+ * grid point).  Returns BEC_EINVAL / BEC_EUNSUPPORTED for a bad grid. */
+bec_status bec_workspace_size(const bec_grid* grid, const bec_params* params, size_t* bytes);
+
+/* Create a context.  hip_stream: a hipStream_t (NULL = the null stream).
+ * workspace: device buffer of at least bec_workspace_size bytes, 256-byte
+ * aligned, owned by the caller and kept alive until bec_destroy.  Builds the
+ * FFT twiddle tables, the dipolar kernel table and the quadrature nodes. */
+bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_stream,
+                      void* workspace, size_t workspace_bytes, bec_ctx** out);
+
+bec_status bec_destroy(bec_ctx* ctx);
+
+/* Change the physical parameters of an existing context (same grid).  Rebuilds
+ * the dipolar table if r_cut changed and the quadrature nodes. */
+bec_status bec_set_params(bec_ctx* ctx, const bec_params* params);
+
+/* 3D DFT of nfield consecutive fields of shape [nx][ny][nz] (in, out device
+ * pointers, may alias).  sign = -1: forward, unnormalised; sign = +1: inverse
+ * including the factor 1/(nx ny nz).  Asynchronous.  nfield in 1..3. */
+bec_status bec_fft3d(bec_ctx* ctx, const double* in, double* out, int32_t nfield, int32_t sign);
+
+/* Energy terms of psi (Sec. II, Eq. (1)).  Synchronises. */
+bec_status bec_energy(bec_ctx* ctx, const double* psi, bec_terms* out_h);
+
+/* H_i psi_i of Eq. (6) for both components into hpsi (device, same layout),
+ * plus the energy terms.  Synchronises. */
+bec_status bec_hamiltonian(bec_ctx* ctx, const double* psi, double* hpsi, bec_terms* out_h);
+
+/* Gradient of E with respect to the discrete field, written to grad (device):
+ *   projected = 0: dE/dRe psi + i dE/dIm psi = 2 N_i dV H_i psi_i;
+ *   projected = 1: 2 N_i dV (H_i psi_i - mu_i psi_i), the tangent residual of
+ *   Sec. III, Eq. (8), scaled the same way.
+ * Synchronises. */
+bec_status bec_gradient(bec_ctx* ctx, const double* psi, double* grad, int32_t projected,
+                        bec_terms* out_h);
+
+/* z = P^-1 r for the preconditioner pc evaluated at psi (Sec. IV.B; shift
+ * alpha_i = <psi_i,(T + V + sum_j G_ij n_j + muLHY_i) psi_i>, regularised by
+ * sigma).  r and z are device fields (may alias).  Synchronises. */
+bec_status bec_precond_apply(bec_ctx* ctx, int32_t pc, double sigma, const double* psi,
+                             const double* r, double* z);
+
+/* One manifold line search (Sec. V): projects d onto the tangent space at psi,
+ * builds the second-order energy model, proposes alpha = -E1/E2, validates it
+ * along the exact geodesic and falls back to Armijo halving.  psi_out receives
+ * the accepted point (device; may not alias psi).  opts supplies theta_max,
+ * armijo_c1, max_backtrack and tau_rel.  Synchronises. */
+bec_status bec_linesearch(bec_ctx* ctx, const double* psi, const double* d, double* psi_out,
+                          const bec_opts* opts, bec_ls_report* out_h);
+
+/* Full preconditioned nonlinear CG solve (Sec. III, Algorithm 1, with the
+ * direction of Sec. IV and the step of Sec. V).  psi_inout (device) holds the
+ * initial state (normalised on entry) and receives the final state.  log_h is
+ * an optional host array of log_cap bec_iter records.  Returns the solve
+ * status (also in out_h->status). */
+bec_status bec_solve(bec_ctx* ctx, double* psi_inout, const bec_opts* opts, bec_report* out_h,
+                     bec_iter* log_h, int32_t log_cap);
+
+/* Derivatives of E with respect to the couplings at fixed psi, each matrix
+ * entry treated as independent: dG[i][j] = dE/dG_ij, dGdd[i][j] = dE/dGdd_ij,
+ * dc_lhy = dE/dc_lhy.  At a converged state these are the derivatives of the
+ * ground-state energy (the constraint set does not depend on the couplings).
+ * Synchronises. */
+bec_status bec_param_grad(bec_ctx* ctx, const double* psi, double dG[2][2], double dGdd[2][2],
+                          double* dc_lhy);
+
+/* Gauss-Legendre nodes u[0..n) and weights w[0..n) on [0,1] used for the LHY
+ * u integral (host memory, caller-owned, n in 1..64).  Host-only: needs no GPU. */
+bec_status bec_gauss_legendre(int32_t n, double* u, double* w);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* bec_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEC_H */

@@ -1,0 +1,1069 @@
+// C ABI of the gfx950 library (declared in include/bec.h): context and
+// workspace management, host tables, the 3D FFT driver, the energy /
+// Hamiltonian / gradient / preconditioner / line-search entry points and the
+// preconditioned nonlinear CG loop of arXiv:2510.24543 (Sec. III Algorithm 1,
+// Sec. IV direction, Sec. V step).  Every per-point operation runs in the HIP
+// kernels of fft.hip and pointwise.hip; the host only takes the scalar
+// decisions (beta, alpha, accept / backtrack / restart) from reduced sums.
+#include "bec.h"
+#include "bec_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using bec::FftPassArgs;
+using bec::PwParams;
+
+namespace {
+
+thread_local std::string g_err;
+
+bec_status fail(bec_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) return fail(BEC_EHIP, "%s: %s", #x, hipGetErrorString(e_));  \
+    } while (0)
+
+#define STCHK(x)                                 \
+    do {                                         \
+        bec_status s_ = (x);                     \
+        if (s_ != BEC_OK) return s_;             \
+    } while (0)
+
+constexpr long double kPiL = 3.141592653589793238462643383279502884L;
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Gauss-Legendre nodes/weights on [0,1] by the Golub-Welsch method: the nodes
+// are the eigenvalues of the symmetric tridiagonal Jacobi matrix of the
+// Legendre polynomials (off-diagonal k/sqrt(4k^2-1)); the weights are twice the
+// squared first components of the normalised eigenvectors (halved on [0,1]).
+// Implicit QL iteration with Wilkinson shifts, in long double, then one Newton
+// polish of each node on the Legendre recurrence.
+void gauss_legendre01(int n, std::vector<double>& u, std::vector<double>& w)
+{
+    std::vector<long double> d(n, 0.0L), e(n, 0.0L), z(n, 0.0L);
+    for (int k = 1; k < n; ++k) e[k - 1] = (long double)k / sqrtl(4.0L * k * k - 1.0L);
+    z[0] = 1.0L;
+    for (int l = 0; l < n; ++l) {
+        for (int iter = 0; iter < 200; ++iter) {
+            int m = l;
+            for (; m < n - 1; ++m) {
+                long double dd = fabsl(d[m]) + fabsl(d[m + 1]);
+                if (fabsl(e[m]) <= 1e-30L * dd || fabsl(e[m]) < 1e-300L) break;
+            }
+            if (m == l) break;
+            long double g = (d[l + 1] - d[l]) / (2.0L * e[l]);
+            long double r = hypotl(g, 1.0L);
+            g = d[m] - d[l] + e[l] / (g + (g >= 0 ? fabsl(r) : -fabsl(r)));
+            long double s = 1.0L, c = 1.0L, p = 0.0L;
+            int i = m - 1;
+            bool early = false;
+            for (; i >= l; --i) {
+                long double f = s * e[i], b = c * e[i];
+                r = hypotl(f, g);
+                e[i + 1] = r;
+                if (r == 0.0L) {
+                    d[i + 1] -= p;
+                    e[m] = 0.0L;
+                    early = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0L * c * b;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - b;
+                long double zf = z[i + 1];
+                z[i + 1] = s * z[i] + c * zf;
+                z[i] = c * z[i] - s * zf;
+            }
+            if (early) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0.0L;
+        }
+    }
+    std::vector<std::pair<long double, long double>> nw(n);
+    for (int i = 0; i < n; ++i) {
+        long double x = d[i];
+        // Newton polish on P_n(x) = 0
+        for (int it = 0; it < 3; ++it) {
+            long double p0 = 1.0L, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = x; p0 = 1.0L; }
+            long double dp = n * (x * p1 - p0) / (x * x - 1.0L);
+            x -= p1 / dp;
+        }
+        nw[i] = {0.5L * (1.0L + x), z[i] * z[i]};   // weight on [0,1] = (2 z^2)/2
+    }
+    std::sort(nw.begin(), nw.end());
+    u.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        u[i] = (double)nw[i].first;
+        w[i] = (double)nw[i].second;
+    }
+}
+
+// Spherical cutoff of the dipolar kernel (radius R in real space):
+// c(q) = 1 + 3 cos q / q^2 - 3 sin q / q^3, q = |k| R; below q = 1 its series
+// sum_{m>=1} (-1)^(m+1) 6 m q^(2m) / (2m+3)!, in long double.
+long double cutoff_factor(long double q)
+{
+    if (q >= 1.0L) return 1.0L + 3.0L * cosl(q) / (q * q) - 3.0L * sinl(q) / (q * q * q);
+    long double q2 = q * q, term = q2, fact = 120.0L, s = 0.0L;   // (2m+3)! at m = 1 is 5! = 120
+    for (int m = 1; m <= 14; ++m) {
+        s += ((m % 2) ? 1.0L : -1.0L) * 6.0L * m * term / fact;
+        term *= q2;
+        fact *= (2.0L * m + 4.0L) * (2.0L * m + 5.0L);
+    }
+    return s;
+}
+
+}  // namespace
+
+struct bec_ctx {
+    bec_grid g{};
+    bec_params p{};
+    hipStream_t st = nullptr;
+    int n[3] = {0, 0, 0};
+    long long N = 0;
+    double h[3] = {0, 0, 0}, L[3] = {0, 0, 0}, dV = 0;
+    double2 *psi[2] = {}, *hpsi[2] = {}, *aux[2] = {};
+    double2 *pdir = nullptr, *r_old = nullptr, *z = nullptr, *rho = nullptr, *W = nullptr;
+    double *udtab = nullptr, *kv[3] = {}, *vv[3] = {}, *nodes = nullptr;
+    double *partials = nullptr, *fft_partials = nullptr, *scal = nullptr;
+    double2* tw[3] = {};
+    double* host = nullptr;   // pinned scalars
+    int nblk_pw = 0;
+    int nblk_x = 0;
+    PwParams P{};
+    double last_mLn[2] = {0, 0};
+};
+
+namespace {
+
+size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
+{
+    const long long N = (long long)n[0] * n[1] * n[2];
+    const size_t c2 = sizeof(double2);
+    const long long nb_pw = std::min<long long>((N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwMaxBlocks);
+    const long long nb_x = bec::fft_blocks(n[0], (long long)n[1] * n[2]);
+    size_t sizes[] = {
+        2 * N * c2, 2 * N * c2,                    // psi[0], psi[1]
+        2 * N * c2, 2 * N * c2,                    // hpsi[0], hpsi[1]
+        2 * N * c2, 2 * N * c2,                    // aux[0], aux[1]
+        2 * N * c2,                                // pdir
+        2 * N * c2,                                // r_old
+        2 * N * c2,                                // z
+        N * c2,                                    // rho
+        3 * N * c2,                                // W
+        (size_t)(n[0] / 2 + 1) * (n[1] / 2 + 1) * (n[2] / 2 + 1) * sizeof(double),   // udtab
+        n[0] * c2, n[1] * c2, n[2] * c2,           // twiddles
+        n[0] * sizeof(double), n[1] * sizeof(double), n[2] * sizeof(double),        // k
+        n[0] * sizeof(double), n[1] * sizeof(double), n[2] * sizeof(double),        // V per axis
+        bec::kMaxNodes * bec::kNodeStride * sizeof(double),                         // nodes
+        (size_t)bec::kMaxSums * nb_pw * sizeof(double),                             // partials
+        (size_t)3 * nb_x * sizeof(double),                                          // fft partials
+        64 * sizeof(double),                                                        // scal
+    };
+    size_t total = 0;
+    for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); ++i) {
+        if (off) off[i] = total;
+        total += align256(sizes[i]);
+    }
+    return total;
+}
+
+bec_status check_grid(const bec_grid* g)
+{
+    if (!g) return fail(BEC_EINVAL, "grid is null");
+    for (int d = 0; d < 3; ++d) {
+        if (!bec::fft_supported(g->n[d]))
+            return fail(BEC_EUNSUPPORTED, "axis %d length %d not supported (8,16,32,48,64,96,128,256)", d,
+                        g->n[d]);
+        if (!(g->hi[d] > g->lo[d]) || !std::isfinite(g->lo[d]) || !std::isfinite(g->hi[d]))
+            return fail(BEC_EINVAL, "axis %d: need finite lo < hi", d);
+    }
+    return BEC_OK;
+}
+
+bec_status check_params(const bec_params* p)
+{
+    if (!p) return fail(BEC_EINVAL, "params is null");
+    if (!(p->N[0] > 0) || !(p->N[1] > 0)) return fail(BEC_EINVAL, "atom numbers must be positive");
+    if (p->n_u < 1 || p->n_u > bec::kMaxNodes) return fail(BEC_EINVAL, "n_u must be in 1..%d", bec::kMaxNodes);
+    if (!(p->r_cut > 0)) return fail(BEC_EINVAL, "r_cut must be positive");
+    const double* all[] = {p->omega, &p->G[0][0], &p->Gdd[0][0]};
+    const int cnt[] = {3, 4, 4};
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < cnt[a]; ++k)
+            if (!std::isfinite(all[a][k])) return fail(BEC_EINVAL, "non-finite parameter");
+    if (!std::isfinite(p->c_lhy) || !std::isfinite(p->r_cut)) return fail(BEC_EINVAL, "non-finite parameter");
+    const double a = p->N[0] * p->G[0][1], b = p->N[1] * p->G[1][0];
+    const double c = p->N[0] * p->Gdd[0][1], d = p->N[1] * p->Gdd[1][0];
+    if (std::fabs(a - b) > 1e-12 * std::max(std::fabs(a), std::fabs(b)) ||
+        std::fabs(c - d) > 1e-12 * std::max(std::fabs(c), std::fabs(d)))
+        return fail(BEC_EINVAL, "N_i G_ij and N_i Gdd_ij must be symmetric");
+    return BEC_OK;
+}
+
+// Host tables that depend on the parameters: quadrature nodes, couplings,
+// trap, dipolar kernel.  Uploads asynchronously, then synchronises.
+bec_status upload_params(bec_ctx* c, bool dipolar_table)
+{
+    const bec_params& p = c->p;
+    std::vector<double> u, w;
+    gauss_legendre01(p.n_u, u, w);
+    std::vector<double> nodes((size_t)bec::kMaxNodes * bec::kNodeStride, 0.0);
+    for (int q = 0; q < p.n_u; ++q) {
+        const double a = 3.0 * u[q] * u[q] - 1.0;
+        double* nd = &nodes[(size_t)q * bec::kNodeStride];
+        const double e12 = p.G[0][1] + p.Gdd[0][1] * a, e21 = p.G[1][0] + p.Gdd[1][0] * a;
+        nd[0] = p.G[0][0] + p.Gdd[0][0] * a;
+        nd[1] = p.G[1][1] + p.Gdd[1][1] * a;
+        nd[2] = e12 * e21;
+        nd[3] = w[q];
+        nd[4] = e12;
+        nd[5] = e21;
+        nd[6] = a;
+    }
+    HIPCHK(hipMemcpyAsync(c->nodes, nodes.data(), nodes.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+    std::vector<double> vv[3];
+    for (int d = 0; d < 3; ++d) {
+        vv[d].resize(c->n[d]);
+        for (int j = 0; j < c->n[d]; ++j) {
+            const double x = c->g.lo[d] + j * c->h[d];
+            vv[d][j] = 0.5 * p.omega[d] * p.omega[d] * x * x;
+        }
+        HIPCHK(hipMemcpyAsync(c->vv[d], vv[d].data(), c->n[d] * sizeof(double), hipMemcpyHostToDevice, c->st));
+    }
+    std::vector<double> ud;
+    if (dipolar_table) {
+        const int ax = c->n[0] / 2 + 1, ay = c->n[1] / 2 + 1, az = c->n[2] / 2 + 1;
+        ud.resize((size_t)ax * ay * az);
+        for (int i = 0; i < ax; ++i)
+            for (int j = 0; j < ay; ++j)
+                for (int k = 0; k < az; ++k) {
+                    const long double kx = 2.0L * kPiL * i / c->L[0], ky = 2.0L * kPiL * j / c->L[1],
+                                      kz = 2.0L * kPiL * k / c->L[2];
+                    const long double k2 = kx * kx + ky * ky + kz * kz;
+                    double v = 0.0;
+                    if (k2 > 0.0L)
+                        v = (double)((3.0L * kz * kz / k2 - 1.0L) * cutoff_factor(sqrtl(k2) * (long double)p.r_cut));
+                    ud[((size_t)i * ay + j) * az + k] = v;
+                }
+        HIPCHK(hipMemcpyAsync(c->udtab, ud.data(), ud.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+
+    PwParams& P = c->P;
+    P.nx = c->n[0];
+    P.ny = c->n[1];
+    P.nz = c->n[2];
+    P.N = c->N;
+    for (int i = 0; i < 2; ++i) {
+        P.Nat[i] = p.N[i];
+        for (int j = 0; j < 2; ++j) {
+            P.G[i][j] = p.G[i][j];
+            P.Gdd[i][j] = p.Gdd[i][j];
+        }
+    }
+    P.K5 = p.c_lhy * std::sqrt(2.0) / (15.0 * M_PI * M_PI);
+    P.K3 = p.c_lhy / (3.0 * std::sqrt(2.0) * M_PI * M_PI);
+    P.n_u = p.n_u;
+    P.lhy_on = p.c_lhy != 0.0;
+    P.nodes = c->nodes;
+    P.vx = c->vv[0];
+    P.vy = c->vv[1];
+    P.vz = c->vv[2];
+    return BEC_OK;
+}
+
+// ------------------------------------------------------------------ FFT driver
+FftPassArgs pass_args(bec_ctx* c, int axis)
+{
+    FftPassArgs A{};
+    A.nx = c->n[0];
+    A.ny = c->n[1];
+    A.nz = c->n[2];
+    A.kx = c->kv[0];
+    A.ky = c->kv[1];
+    A.kz = c->kv[2];
+    A.udtab = c->udtab;
+    A.inv_n = 1.0 / (double)c->N;
+    A.tw = c->tw[axis];
+    A.scale = 1.0;
+    A.partials = c->fft_partials;
+    A.nblk_x = c->nblk_x;
+    if (axis == 2) {
+        A.S = 1;
+        A.npencil = (long long)c->n[0] * c->n[1];
+    } else if (axis == 1) {
+        A.S = c->n[2];
+        A.npencil = (long long)c->n[0] * c->n[2];
+    } else {
+        A.S = (long long)c->n[1] * c->n[2];
+        A.npencil = A.S;
+    }
+    for (int f = 0; f < 3; ++f) A.op[f] = bec::kOpPlain;
+    return A;
+}
+
+bec_status run_pass(bec_ctx* c, int axis, const double2* const* src, double2* const* dst, int nf, int sign,
+                    double scale, const int* ops, const double* prec_a)
+{
+    FftPassArgs A = pass_args(c, axis);
+    A.nfield = nf;
+    A.sign = sign;
+    A.scale = scale;
+    for (int f = 0; f < nf; ++f) {
+        A.src[f] = src[f];
+        A.dst[f] = dst[f];
+        if (ops) A.op[f] = ops[f];
+        if (prec_a) A.prec_a[f] = prec_a[f];
+    }
+    HIPCHK(bec::fft_pass(c->n[axis], axis == 2, A, c->st));
+    return BEC_OK;
+}
+
+// Plain 3D transform of nf fields (sign -1 forward unnormalised, +1 inverse / N).
+bec_status fft3d_plain(bec_ctx* c, const double2* const* src, double2* const* dst, int nf, int sign)
+{
+    if (sign < 0) {
+        STCHK(run_pass(c, 2, src, dst, nf, -1, 1.0, nullptr, nullptr));
+        STCHK(run_pass(c, 1, dst, dst, nf, -1, 1.0, nullptr, nullptr));
+        STCHK(run_pass(c, 0, dst, dst, nf, -1, 1.0, nullptr, nullptr));
+    } else {
+        STCHK(run_pass(c, 0, src, dst, nf, +1, 1.0, nullptr, nullptr));
+        STCHK(run_pass(c, 1, dst, dst, nf, +1, 1.0, nullptr, nullptr));
+        STCHK(run_pass(c, 2, dst, dst, nf, +1, 1.0 / (double)c->N, nullptr, nullptr));
+    }
+    return BEC_OK;
+}
+
+// Diagonal k-space operators on nf fields: forward z, y, then the fused x pass
+// (ops per field), then inverse y, z for the fields that are stored.
+// Parseval fields come first in the list (they end at the x pass).
+bec_status kspace_apply(bec_ctx* c, const double2* const* src, double2* const* dst, int nf, const int* ops,
+                        const double* prec_a)
+{
+    STCHK(run_pass(c, 2, src, dst, nf, -1, 1.0, nullptr, nullptr));
+    STCHK(run_pass(c, 1, dst, dst, nf, -1, 1.0, nullptr, nullptr));
+    STCHK(run_pass(c, 0, dst, dst, nf, -1, 1.0, ops, prec_a));
+    int first = 0;
+    while (first < nf && ops[first] == bec::kOpParseval) ++first;
+    if (first < nf) {
+        STCHK(run_pass(c, 1, dst + first, dst + first, nf - first, +1, 1.0, nullptr, nullptr));
+        STCHK(run_pass(c, 2, dst + first, dst + first, nf - first, +1, 1.0, nullptr, nullptr));
+    }
+    return BEC_OK;
+}
+
+// ------------------------------------------------------------------ reductions
+bec_status fetch(bec_ctx* c, int M)
+{
+    HIPCHK(hipMemcpyAsync(c->host, c->scal, M * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return BEC_OK;
+}
+
+bec_status reduce_pw(bec_ctx* c, int M, int out_off)
+{
+    HIPCHK(bec::launch_reduce_final(c->partials, c->nblk_pw, M, c->scal + out_off, c->st));
+    return BEC_OK;
+}
+
+// ------------------------------------------------------------------ H evaluation
+struct Eval {
+    bec_terms t{};
+    double sums[bec::kHevalSums]{};
+};
+
+// psi[set] = a_i src + b_i p (p may be null), then H psi, Phi, muLHY and the
+// energy sums for that state.
+bec_status heval(bec_ctx* c, const double2* src, const double2* p, const double a[2], const double b[2], int set,
+                 Eval* out)
+{
+    const long long N = c->N;
+    bec::TrialArgs ta{};
+    ta.psi_src = src;
+    ta.p = p;
+    for (int i = 0; i < 2; ++i) {
+        ta.a[i] = a[i];
+        ta.b[i] = b[i];
+    }
+    ta.psi_dst = c->psi[set];
+    ta.dens = c->W + 2 * N;
+    HIPCHK(bec::launch_trial(c->P, ta, c->st));
+    const double2* fsrc[3] = {c->psi[set], c->psi[set] + N, c->W + 2 * N};
+    double2* fdst[3] = {c->W, c->W + N, c->W + 2 * N};
+    const int ops[3] = {bec::kOpMulKin, bec::kOpMulKin, bec::kOpMulDip};
+    STCHK(kspace_apply(c, fsrc, fdst, 3, ops, nullptr));
+    bec::HevalArgs ha{};
+    ha.psi = c->psi[set];
+    ha.Tpsi = c->W;
+    ha.phi = c->W + 2 * N;
+    ha.hpsi = c->hpsi[set];
+    ha.aux = c->aux[set];
+    ha.partials = c->partials;
+    HIPCHK(bec::launch_heval_epi(c->P, ha, c->nblk_pw, c->st));
+    STCHK(reduce_pw(c, bec::kHevalSums, 0));
+    STCHK(fetch(c, bec::kHevalSums));
+    const double* S = c->host;
+    std::memcpy(out->sums, S, sizeof(out->sums));
+    const double dV = c->dV;
+    bec_terms& t = out->t;
+    std::memset(&t, 0, sizeof(t));
+    const double snn[2][2] = {{S[4], S[5]}, {S[5], S[6]}};
+    for (int i = 0; i < 2; ++i) {
+        t.norm2[i] = dV * S[14 + i];
+        t.E_kin[i] = c->p.N[i] * dV * S[i];
+        t.E_trap[i] = c->p.N[i] * dV * S[2 + i];
+        double gdd_phi = 0.0;
+        for (int j = 0; j < 2; ++j) {
+            t.E_c[i][j] = 0.5 * c->p.N[i] * c->p.G[i][j] * dV * snn[i][j];
+            t.E_dd[i][j] = 0.5 * c->p.N[i] * c->p.Gdd[i][j] * dV * S[7 + 2 * i + j];
+            gdd_phi += c->p.Gdd[i][j] * S[7 + 2 * i + j];
+        }
+        t.mu[i] = S[12 + i] / S[14 + i];
+        t.shift[i] = (S[12 + i] - gdd_phi) / S[14 + i];
+        t.res[i] = NAN;
+    }
+    t.E_lhy = dV * S[11];
+    t.E = t.E_lhy;
+    for (int i = 0; i < 2; ++i) {
+        t.E += t.E_kin[i] + t.E_trap[i];
+        for (int j = 0; j < 2; ++j) t.E += t.E_c[i][j] + t.E_dd[i][j];
+    }
+    if (!std::isfinite(t.E) || !std::isfinite(t.mu[0]) || !std::isfinite(t.mu[1]))
+        return fail(BEC_ENONFINITE, "non-finite energy");
+    return BEC_OK;
+}
+
+bec::DirArgs dir_args(bec_ctx* c, int set, const Eval& ev, int zmode, double sigma)
+{
+    bec::DirArgs A{};
+    A.psi = c->psi[set];
+    A.hpsi = c->hpsi[set];
+    A.aux = c->aux[set];
+    A.zbuf = c->z;
+    A.r_old = c->r_old;
+    A.p = c->pdir;
+    A.r_out = c->r_old;
+    A.rho = c->rho;
+    for (int i = 0; i < 2; ++i) {
+        A.mu[i] = ev.t.mu[i];
+        A.diag_shift[i] = ev.t.shift[i];
+    }
+    A.sigma = sigma;
+    A.zmode = zmode;
+    A.zsign = -1.0;
+    A.beta = 0.0;
+    A.partials = c->partials;
+    return A;
+}
+
+// Direction reduce pass: returns the 12 sums (see kDirReduceSums).
+bec_status dir_reduce(bec_ctx* c, const bec::DirArgs& A, double* R)
+{
+    HIPCHK(bec::launch_dir_reduce(c->P, A, c->nblk_pw, c->st));
+    STCHK(reduce_pw(c, bec::kDirReduceSums, 0));
+    STCHK(fetch(c, bec::kDirReduceSums));
+    std::memcpy(R, c->host, bec::kDirReduceSums * sizeof(double));
+    return BEC_OK;
+}
+
+// z = P^-1 r into c->z for the kinetic / composite preconditioners.
+bec_status compute_z(bec_ctx* c, int set, const Eval& ev, const double2* rin, int apply_pv, double sigma)
+{
+    bec::MakeRArgs m{};
+    m.psi = c->psi[set];
+    m.hpsi = c->hpsi[set];
+    m.aux = c->aux[set];
+    m.rin = rin;
+    for (int i = 0; i < 2; ++i) {
+        m.mu[i] = ev.t.mu[i];
+        m.diag_shift[i] = ev.t.shift[i];
+    }
+    m.sigma = sigma;
+    m.apply_pv = apply_pv;
+    m.out = c->z;
+    HIPCHK(bec::launch_make_r(c->P, m, c->st));
+    const long long N = c->N;
+    const double2* src[2] = {c->z, c->z + N};
+    double2* dst[2] = {c->z, c->z + N};
+    const int ops[2] = {bec::kOpMulPrec, bec::kOpMulPrec};
+    const double pa[2] = {std::max(ev.t.shift[0], 0.0) + sigma, std::max(ev.t.shift[1], 0.0) + sigma};
+    return kspace_apply(c, src, dst, 2, ops, pa);
+}
+
+struct Model {
+    double D[bec::kDirWriteSums];
+    double LS[bec::kLsEpiSums];
+    double pars[2];
+    double pnorm[2], rp, E1, E2, psip[2];
+};
+
+// Direction write pass (p, r, rho) + Parseval FFT of p + dipolar FFT of rho +
+// model epilogue; one synchronisation for all the model scalars.
+bec_status direction_and_model(bec_ctx* c, const bec::DirArgs& A, const Eval& ev, Model* m)
+{
+    const long long N = c->N;
+    HIPCHK(bec::launch_dir_write(c->P, A, c->nblk_pw, c->st));
+    HIPCHK(bec::launch_reduce_final(c->partials, c->nblk_pw, bec::kDirWriteSums, c->scal, c->st));
+    const double2* src[3] = {c->pdir, c->pdir + N, c->rho};
+    double2* dst[3] = {c->W, c->W + N, c->W + 2 * N};
+    const int ops[3] = {bec::kOpParseval, bec::kOpParseval, bec::kOpMulDip};
+    STCHK(kspace_apply(c, src, dst, 3, ops, nullptr));
+    bec::LsEpiArgs la{};
+    la.rho = c->rho;
+    la.phr = c->W + 2 * N;
+    la.partials = c->partials;
+    HIPCHK(bec::launch_ls_epi(c->P, la, c->nblk_pw, c->st));
+    HIPCHK(bec::launch_reduce_final(c->partials, c->nblk_pw, bec::kLsEpiSums, c->scal + 20, c->st));
+    HIPCHK(bec::launch_reduce_final(c->fft_partials, c->nblk_x, 1, c->scal + 30, c->st));
+    HIPCHK(bec::launch_reduce_final(c->fft_partials + c->nblk_x, c->nblk_x, 1, c->scal + 31, c->st));
+    STCHK(fetch(c, 32));
+    const double* S = c->host;
+    std::memcpy(m->D, S, sizeof(m->D));
+    std::memcpy(m->LS, S + 20, sizeof(m->LS));
+    m->pars[0] = S[30];
+    m->pars[1] = S[31];
+    const double dV = c->dV;
+    const bec_params& p = c->p;
+    const double* D = m->D;
+    m->rp = 0.0;
+    double E1 = 0.0, E2 = 0.0;
+    for (int i = 0; i < 2; ++i) {
+        m->pnorm[i] = std::sqrt(dV * D[i]);
+        m->psip[i] = dV * D[16 + i];
+        m->rp += 2.0 * p.N[i] * dV * D[2 + i];
+        E1 += 2.0 * p.N[i] * dV * D[4 + i];                                   // E'_i
+        const double pTp = dV * m->pars[i] / (double)N;                       // <p_i, T p_i>
+        const double pn2 = m->pnorm[i] * m->pnorm[i];
+        E2 += 2.0 * p.N[i] * (pTp + dV * D[8 + i] - pn2 * dV * D[6 + i]);     // one-body part of E''_ii
+        for (int j = 0; j < 2; ++j) {
+            const double rr = (i == 0 && j == 0) ? m->LS[0] : (i == 1 && j == 1) ? m->LS[2] : m->LS[1];
+            E2 += 4.0 * p.N[i] * dV * (p.G[i][j] * rr + p.Gdd[i][j] * m->LS[3 + 2 * i + j]);
+        }
+        if (c->P.lhy_on) E2 += 2.0 * p.N[i] * dV * (D[10 + i] - pn2 * D[12 + i]);   // n'' part of E''_LHY
+    }
+    if (c->P.lhy_on) {
+        E1 += c->P.K3 * dV * D[14];
+        E2 += 2.0 * c->P.K3 * dV * D[15];
+    }
+    m->E1 = E1;
+    m->E2 = E2;
+    (void)ev;
+    return BEC_OK;
+}
+
+// trial coefficients along the geodesic: psi_i(alpha) = (cos th psi_i + sin th p_i/|p_i|)/norm
+void geodesic_coeffs(const Eval& ev, const Model& m, double alpha, double a[2], double b[2])
+{
+    for (int i = 0; i < 2; ++i) {
+        if (m.pnorm[i] > 0.0) {
+            const double th = alpha * m.pnorm[i];
+            const double ca = std::cos(th), sb = std::sin(th) / m.pnorm[i];
+            const double nrm2 = ca * ca * ev.t.norm2[i] + sb * sb * m.pnorm[i] * m.pnorm[i] + 2.0 * ca * sb * m.psip[i];
+            const double s = 1.0 / std::sqrt(nrm2);
+            a[i] = ca * s;
+            b[i] = sb * s;
+        } else {
+            a[i] = 1.0 / std::sqrt(ev.t.norm2[i]);
+            b[i] = 0.0;
+        }
+    }
+}
+
+bec_status normalise_into(bec_ctx* c, const double2* src, int set)
+{
+    HIPCHK(bec::launch_norm2(c->P, src, c->partials, c->nblk_pw, c->st));
+    STCHK(reduce_pw(c, 2, 0));
+    STCHK(fetch(c, 2));
+    const double n0 = c->dV * c->host[0], n1 = c->dV * c->host[1];
+    if (!(n0 > 0) || !(n1 > 0) || !std::isfinite(n0) || !std::isfinite(n1))
+        return fail(BEC_ENONFINITE, "initial state has zero or non-finite norm");
+    HIPCHK(bec::launch_scale2(c->P, src, c->psi[set], 1.0 / std::sqrt(n0), 1.0 / std::sqrt(n1), c->st));
+    return BEC_OK;
+}
+
+bec_status residual_norms(bec_ctx* c, int set, Eval* ev)
+{
+    bec::DirArgs A = dir_args(c, set, *ev, 0, 0.0);
+    double R[bec::kDirReduceSums];
+    STCHK(dir_reduce(c, A, R));
+    ev->t.res[0] = std::sqrt(c->dV * R[0]);
+    ev->t.res[1] = std::sqrt(c->dV * R[6]);
+    return BEC_OK;
+}
+
+const double kOne[2] = {1.0, 1.0};
+const double kZero[2] = {0.0, 0.0};
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* bec_last_error(void) { return g_err.c_str(); }
+
+bec_status bec_gauss_legendre(int32_t n, double* u, double* w)
+{
+    if (n < 1 || n > bec::kMaxNodes || !u || !w) return fail(BEC_EINVAL, "need 1 <= n <= %d and output arrays", bec::kMaxNodes);
+    std::vector<double> uu, ww;
+    gauss_legendre01(n, uu, ww);
+    std::memcpy(u, uu.data(), n * sizeof(double));
+    std::memcpy(w, ww.data(), n * sizeof(double));
+    return BEC_OK;
+}
+
+bec_status bec_workspace_size(const bec_grid* grid, const bec_params* params, size_t* bytes)
+{
+    STCHK(check_grid(grid));
+    if (params) STCHK(check_params(params));
+    if (!bytes) return fail(BEC_EINVAL, "bytes is null");
+    *bytes = ws_layout(grid->n, nullptr);
+    return BEC_OK;
+}
+
+bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_stream, void* workspace,
+                      size_t workspace_bytes, bec_ctx** out)
+{
+    try {
+        STCHK(check_grid(grid));
+        STCHK(check_params(params));
+        if (!out) return fail(BEC_EINVAL, "out is null");
+        if (!workspace) return fail(BEC_EINVAL, "workspace is null");
+        if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(BEC_EINVAL, "workspace must be 256-byte aligned");
+        size_t off[32];
+        const size_t need = ws_layout(grid->n, off);
+        if (workspace_bytes < need)
+            return fail(BEC_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+        bec_ctx* c = new bec_ctx();
+        c->g = *grid;
+        c->p = *params;
+        c->st = reinterpret_cast<hipStream_t>(hip_stream);
+        for (int d = 0; d < 3; ++d) {
+            c->n[d] = grid->n[d];
+            c->L[d] = grid->hi[d] - grid->lo[d];
+            c->h[d] = c->L[d] / grid->n[d];
+        }
+        c->N = (long long)c->n[0] * c->n[1] * c->n[2];
+        c->dV = c->h[0] * c->h[1] * c->h[2];
+        char* base = static_cast<char*>(workspace);
+        auto at = [&](int i) { return base + off[i]; };
+        c->psi[0] = (double2*)at(0);
+        c->psi[1] = (double2*)at(1);
+        c->hpsi[0] = (double2*)at(2);
+        c->hpsi[1] = (double2*)at(3);
+        c->aux[0] = (double2*)at(4);
+        c->aux[1] = (double2*)at(5);
+        c->pdir = (double2*)at(6);
+        c->r_old = (double2*)at(7);
+        c->z = (double2*)at(8);
+        c->rho = (double2*)at(9);
+        c->W = (double2*)at(10);
+        c->udtab = (double*)at(11);
+        for (int d = 0; d < 3; ++d) {
+            c->tw[d] = (double2*)at(12 + d);
+            c->kv[d] = (double*)at(15 + d);
+            c->vv[d] = (double*)at(18 + d);
+        }
+        c->nodes = (double*)at(21);
+        c->partials = (double*)at(22);
+        c->fft_partials = (double*)at(23);
+        c->scal = (double*)at(24);
+        c->nblk_pw = (int)std::min<long long>((c->N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwMaxBlocks);
+        c->nblk_x = bec::fft_blocks(c->n[0], (long long)c->n[1] * c->n[2]);
+        if (hipHostMalloc((void**)&c->host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            delete c;
+            return fail(BEC_EHIP, "hipHostMalloc of the scalar buffer failed");
+        }
+        // twiddles W_L^m and wavenumbers per axis
+        for (int d = 0; d < 3; ++d) {
+            const int L = c->n[d];
+            std::vector<double2> tw(L);
+            std::vector<double> kv(L);
+            for (int m = 0; m < L; ++m) {
+                const long double a = -2.0L * kPiL * (long double)m / (long double)L;
+                tw[m] = make_double2((double)cosl(a), (double)sinl(a));
+                const int jj = m < L / 2 ? m : m - L;
+                kv[m] = (double)(2.0L * kPiL * jj / (long double)c->L[d]);
+            }
+            if (hipMemcpyAsync(c->tw[d], tw.data(), L * sizeof(double2), hipMemcpyHostToDevice, c->st) != hipSuccess ||
+                hipMemcpyAsync(c->kv[d], kv.data(), L * sizeof(double), hipMemcpyHostToDevice, c->st) != hipSuccess ||
+                hipStreamSynchronize(c->st) != hipSuccess) {
+                (void)hipHostFree(c->host);
+                delete c;
+                return fail(BEC_EHIP, "upload of FFT tables failed");
+            }
+        }
+        bec_status st = upload_params(c, true);
+        if (st != BEC_OK) {
+            (void)hipHostFree(c->host);
+            delete c;
+            return st;
+        }
+        *out = c;
+        return BEC_OK;
+    } catch (...) {
+        return fail(BEC_EINVAL, "unexpected host exception in bec_create");
+    }
+}
+
+bec_status bec_destroy(bec_ctx* ctx)
+{
+    if (!ctx) return BEC_OK;
+    if (ctx->host) (void)hipHostFree(ctx->host);
+    delete ctx;
+    return BEC_OK;
+}
+
+bec_status bec_set_params(bec_ctx* c, const bec_params* params)
+{
+    if (!c) return fail(BEC_EINVAL, "ctx is null");
+    STCHK(check_params(params));
+    const bool dip = params->r_cut != c->p.r_cut;
+    c->p = *params;
+    return upload_params(c, dip);
+}
+
+bec_status bec_fft3d(bec_ctx* c, const double* in, double* out, int32_t nfield, int32_t sign)
+{
+    if (!c || !in || !out) return fail(BEC_EINVAL, "null argument");
+    if (nfield < 1 || nfield > 3) return fail(BEC_EINVAL, "nfield must be 1..3");
+    if (sign != -1 && sign != 1) return fail(BEC_EINVAL, "sign must be -1 or +1");
+    const double2* src[3];
+    double2* dst[3];
+    for (int f = 0; f < nfield; ++f) {
+        src[f] = reinterpret_cast<const double2*>(in) + f * c->N;
+        dst[f] = reinterpret_cast<double2*>(out) + f * c->N;
+    }
+    return fft3d_plain(c, src, dst, nfield, sign);
+}
+
+bec_status bec_energy(bec_ctx* c, const double* psi, bec_terms* out_h)
+{
+    if (!c || !psi || !out_h) return fail(BEC_EINVAL, "null argument");
+    Eval ev;
+    STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
+    STCHK(residual_norms(c, 0, &ev));
+    *out_h = ev.t;
+    return BEC_OK;
+}
+
+bec_status bec_hamiltonian(bec_ctx* c, const double* psi, double* hpsi, bec_terms* out_h)
+{
+    if (!c || !psi || !hpsi) return fail(BEC_EINVAL, "null argument");
+    Eval ev;
+    STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
+    STCHK(residual_norms(c, 0, &ev));
+    HIPCHK(hipMemcpyAsync(hpsi, c->hpsi[0], 2 * c->N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (out_h) *out_h = ev.t;
+    return BEC_OK;
+}
+
+bec_status bec_gradient(bec_ctx* c, const double* psi, double* grad, int32_t projected, bec_terms* out_h)
+{
+    if (!c || !psi || !grad) return fail(BEC_EINVAL, "null argument");
+    Eval ev;
+    STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
+    STCHK(residual_norms(c, 0, &ev));
+    HIPCHK(bec::launch_grad(c->P, c->psi[0], c->hpsi[0], reinterpret_cast<double2*>(grad), ev.t.mu[0], ev.t.mu[1],
+                            2.0 * c->p.N[0] * c->dV, 2.0 * c->p.N[1] * c->dV, projected ? 1 : 0, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (out_h) *out_h = ev.t;
+    return BEC_OK;
+}
+
+bec_status bec_precond_apply(bec_ctx* c, int32_t pc, double sigma, const double* psi, const double* r, double* z)
+{
+    if (!c || !psi || !r || !z) return fail(BEC_EINVAL, "null argument");
+    if (pc < 0 || pc > 3) return fail(BEC_EINVAL, "unknown preconditioner %d", pc);
+    if (!(sigma >= 0)) return fail(BEC_EINVAL, "sigma must be >= 0");
+    Eval ev;
+    STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
+    const double2* rin = reinterpret_cast<const double2*>(r);
+    double2* zout = reinterpret_cast<double2*>(z);
+    if (pc == BEC_PC_NONE) {
+        if (z != r) HIPCHK(hipMemcpyAsync(z, r, 2 * c->N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
+    } else if (pc == BEC_PC_V) {
+        bec::MakeRArgs m{};
+        m.psi = c->psi[0];
+        m.aux = c->aux[0];
+        m.rin = rin;
+        for (int i = 0; i < 2; ++i) m.diag_shift[i] = ev.t.shift[i];
+        m.sigma = sigma;
+        m.apply_pv = 1;
+        m.out = zout;
+        HIPCHK(bec::launch_make_r(c->P, m, c->st));
+    } else {
+        STCHK(compute_z(c, 0, ev, rin, pc == BEC_PC_COMPOSITE, sigma));
+        HIPCHK(hipMemcpyAsync(z, c->z, 2 * c->N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    return BEC_OK;
+}
+
+bec_status bec_linesearch(bec_ctx* c, const double* psi, const double* d, double* psi_out, const bec_opts* o,
+                          bec_ls_report* out_h)
+{
+    if (!c || !psi || !d || !psi_out || !o) return fail(BEC_EINVAL, "null argument");
+    if (psi_out == psi) return fail(BEC_EINVAL, "psi_out may not alias psi");
+    Eval ev;
+    STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
+    bec::DirArgs A = dir_args(c, 0, ev, 2, 0.0);
+    A.zbuf = reinterpret_cast<const double2*>(d);
+    double R[bec::kDirReduceSums];
+    STCHK(dir_reduce(c, A, R));
+    A.zsign = 1.0;
+    A.c[0] = c->dV * R[3];
+    A.c[1] = c->dV * R[9];
+    Model m;
+    STCHK(direction_and_model(c, A, ev, &m));
+    const double pmax = std::max(m.pnorm[0], m.pnorm[1]);
+    if (!(pmax > 0)) return fail(BEC_EINVAL, "direction has no tangent component");
+    double alpha = (m.E2 > 0 && std::isfinite(m.E2) && std::isfinite(m.E1) && -m.E1 / m.E2 > 0) ? -m.E1 / m.E2
+                                                                                                : 0.1 / pmax;
+    if (alpha * pmax > o->theta_max) alpha = o->theta_max / pmax;
+    const double tau = o->tau_rel * std::fabs(ev.t.E);
+    double a[2], b[2];
+    Eval tr;
+    int trials = 0, path = 0;
+    bool ok = false;
+    geodesic_coeffs(ev, m, alpha, a, b);
+    STCHK(heval(c, c->psi[0], c->pdir, a, b, 1, &tr));
+    ++trials;
+    if (tr.t.E <= ev.t.E + tau) ok = true;
+    for (int k = 0; !ok && k < o->max_backtrack; ++k) {
+        alpha *= 0.5;
+        geodesic_coeffs(ev, m, alpha, a, b);
+        STCHK(heval(c, c->psi[0], c->pdir, a, b, 1, &tr));
+        ++trials;
+        path |= 1;
+        if (tr.t.E <= ev.t.E + o->armijo_c1 * alpha * m.E1 + tau) ok = true;
+    }
+    HIPCHK(hipMemcpyAsync(psi_out, c->psi[1], 2 * c->N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (out_h) {
+        out_h->E0 = ev.t.E;
+        out_h->E1 = m.E1;
+        out_h->E2 = m.E2;
+        out_h->alpha = alpha;
+        out_h->theta[0] = alpha * m.pnorm[0];
+        out_h->theta[1] = alpha * m.pnorm[1];
+        out_h->E_new = tr.t.E;
+        out_h->pnorm[0] = m.pnorm[0];
+        out_h->pnorm[1] = m.pnorm[1];
+        out_h->n_trials = trials;
+        out_h->path = path;
+    }
+    return ok ? BEC_OK : fail(BEC_ESTAGNATED, "no decrease along the geodesic");
+}
+
+bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_report* out_h, bec_iter* log_h,
+                     int32_t log_cap)
+{
+    if (!c || !psi_inout || !o) return fail(BEC_EINVAL, "null argument");
+    if (o->pc < 0 || o->pc > 3 || o->beta < 0 || o->beta > 2) return fail(BEC_EINVAL, "bad options");
+    const auto t0 = std::chrono::steady_clock::now();
+    const double dV = c->dV;
+    const bec_params& p = c->p;
+    const double Ntot = p.N[0] + p.N[1];
+    const double wS[2] = {(p.N[0] / Ntot) * (p.N[0] / Ntot), (p.N[1] / Ntot) * (p.N[1] / Ntot)};
+    bec_report rep{};
+    int cur = 0;
+    STCHK(normalise_into(c, reinterpret_cast<const double2*>(psi_inout), 0));
+    Eval ev;
+    STCHK(heval(c, c->psi[0], nullptr, kOne, kZero, 0, &ev));
+
+    bool have_prev = false;
+    int n = 0;
+    bec_status status = BEC_ENOTCONV;
+    double E_prev = NAN, alpha_prev = 0.0, rz_old = 0.0;
+    const int zmode_pc = (o->pc == BEC_PC_V) ? 1 : (o->pc == BEC_PC_NONE ? 0 : 2);
+
+    for (;;) {
+        // 1. residual, preconditioned residual and the conjugacy sums
+        if (zmode_pc == 2) STCHK(compute_z(c, cur, ev, nullptr, o->pc == BEC_PC_COMPOSITE, o->sigma));
+        bec::DirArgs A = dir_args(c, cur, ev, zmode_pc, o->sigma);
+        A.have_prev = have_prev;
+        double R[bec::kDirReduceSums];
+        STCHK(dir_reduce(c, A, R));
+        ev.t.res[0] = std::sqrt(dV * R[0]);
+        ev.t.res[1] = std::sqrt(dV * R[6]);
+        const double res_max = std::max(ev.t.res[0], ev.t.res[1]);
+        if (!std::isfinite(res_max) || !std::isfinite(ev.t.E)) { status = BEC_ENONFINITE; break; }
+        if (res_max < o->tol_grad) { status = BEC_OK; break; }
+        if (o->tol_dE > 0 && n > 0 && std::fabs(ev.t.E - E_prev) < o->tol_dE) { status = BEC_OK; break; }
+        if (n >= o->max_iter) { status = BEC_ENOTCONV; break; }
+
+        // 2. beta (HS+ or PR+), restarts
+        const bool restart = !have_prev || o->beta == BEC_BETA_ZERO ||
+                             (o->restart_period > 0 && n % o->restart_period == 0);
+        double beta = 0.0;
+        if (!restart) {
+            double num = 0.0, den = 0.0;
+            for (int i = 0; i < 2; ++i) {
+                num += wS[i] * dV * R[6 * i + 1];
+                den += wS[i] * dV * R[6 * i + 2];
+            }
+            if (o->beta == BEC_BETA_PR_PLUS) den = rz_old;
+            beta = (den > 0 && std::isfinite(den) && std::isfinite(num)) ? num / den : 0.0;
+            if (beta < 0) beta = 0.0;
+        }
+        int level = beta > 0 ? 0 : 1, path = 0, trials = 0;
+        bool accepted = false, stagnated = false;
+        double alpha = 0.0, rz_now = 0.0;
+        Model m{};
+        Eval tr;
+        while (!accepted && !stagnated) {
+            // 3. direction d = -z + beta p_old, projected; restart when <r,p> >= 0
+            for (;;) {
+                const double b = level == 0 ? beta : 0.0;
+                if (level >= 2) {
+                    A = dir_args(c, cur, ev, level == 2 ? 1 : 0, o->sigma);
+                    A.have_prev = false;
+                    STCHK(dir_reduce(c, A, R));
+                }
+                A.beta = b;
+                A.zsign = -1.0;
+                for (int i = 0; i < 2; ++i) A.c[i] = -dV * R[6 * i + 3] + b * dV * R[6 * i + 4];
+                STCHK(direction_and_model(c, A, ev, &m));
+                if (m.rp < 0 && std::isfinite(m.rp)) break;
+                if (level == 0) { level = 1; rep.n_restarts++; continue; }
+                if (level == 1 && o->pc == BEC_PC_COMPOSITE) { level = 2; path |= 4; continue; }
+                if (level == 2) { level = 3; continue; }
+                stagnated = true;
+                break;
+            }
+            if (stagnated) break;
+            rz_now = wS[0] * dV * R[5] + wS[1] * dV * R[11];
+
+            // 4. closed-form step of the second-order model (Sec. V)
+            const double pmax = std::max(m.pnorm[0], m.pnorm[1]);
+            if (m.E2 > 0 && std::isfinite(m.E2) && std::isfinite(m.E1) && -m.E1 / m.E2 > 0)
+                alpha = -m.E1 / m.E2;
+            else
+                alpha = alpha_prev > 0 ? alpha_prev : 0.1 / pmax;
+            if (alpha * pmax > o->theta_max) alpha = o->theta_max / pmax;
+
+            // 5. validate along the exact geodesic, Armijo halving
+            const double tau = o->tau_rel * std::fabs(ev.t.E);
+            double a[2], bb[2];
+            geodesic_coeffs(ev, m, alpha, a, bb);
+            bec_status hs = heval(c, c->psi[cur], c->pdir, a, bb, 1 - cur, &tr);
+            if (hs != BEC_OK && hs != BEC_ENONFINITE) return hs;
+            ++trials;
+            if (hs == BEC_OK && tr.t.E <= ev.t.E + tau) {
+                accepted = true;
+            } else {
+                for (int k = 0; k < o->max_backtrack; ++k) {
+                    alpha *= 0.5;
+                    geodesic_coeffs(ev, m, alpha, a, bb);
+                    hs = heval(c, c->psi[cur], c->pdir, a, bb, 1 - cur, &tr);
+                    if (hs != BEC_OK && hs != BEC_ENONFINITE) return hs;
+                    ++trials;
+                    rep.n_backtracks++;
+                    if (hs == BEC_OK && tr.t.E <= ev.t.E + o->armijo_c1 * alpha * m.E1 + tau) {
+                        accepted = true;
+                        path |= 1;
+                        break;
+                    }
+                }
+            }
+            if (!accepted) {
+                if (level == 0) { level = 1; rep.n_restarts++; path |= 2; continue; }
+                stagnated = true;
+            }
+        }
+        if (stagnated) { status = BEC_ESTAGNATED; break; }
+
+        // 6. accept
+        if (log_h && n < log_cap) {
+            bec_iter& L = log_h[n];
+            L.iter = n;
+            L.n_trials = trials;
+            L.restarted = level >= 1;
+            L.path = path;
+            L.E = tr.t.E;
+            L.res_max = res_max;
+            L.E1 = m.E1;
+            L.E2 = m.E2;
+            L.alpha = alpha;
+            L.beta = level == 0 ? beta : 0.0;
+        }
+        E_prev = ev.t.E;
+        ev = tr;
+        cur = 1 - cur;
+        rz_old = rz_now;
+        alpha_prev = alpha;
+        have_prev = true;
+        ++n;
+    }
+    HIPCHK(hipMemcpyAsync(psi_inout, c->psi[cur], 2 * c->N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    rep.iters = n;
+    rep.status = status;
+    rep.final = ev.t;
+    rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (out_h) *out_h = rep;
+    if (status != BEC_OK && status != BEC_ENOTCONV)
+        fail(status, status == BEC_ESTAGNATED ? "no descent after a beta = 0 restart" : "non-finite state");
+    return status;
+}
+
+bec_status bec_param_grad(bec_ctx* c, const double* psi, double dG[2][2], double dGdd[2][2], double* dc_lhy)
+{
+    if (!c || !psi || !dG || !dGdd || !dc_lhy) return fail(BEC_EINVAL, "null argument");
+    Eval ev;
+    STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
+    bec::ParamGradArgs pa{};
+    pa.psi = c->psi[0];
+    pa.partials = c->partials;
+    HIPCHK(bec::launch_param_grad(c->P, pa, c->nblk_pw, c->st));
+    STCHK(reduce_pw(c, bec::kParamSums, 0));
+    STCHK(fetch(c, bec::kParamSums));
+    const double* S = c->host;
+    const double dV = c->dV;
+    const double K = std::sqrt(2.0) / (15.0 * M_PI * M_PI);
+    const double snn[2][2] = {{ev.sums[4], ev.sums[5]}, {ev.sums[5], ev.sums[6]}};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            dG[i][j] = 0.5 * c->p.N[i] * dV * snn[i][j] + c->p.c_lhy * K * dV * S[2 * i + j];
+            dGdd[i][j] = 0.5 * c->p.N[i] * dV * ev.sums[7 + 2 * i + j] + c->p.c_lhy * K * dV * S[4 + 2 * i + j];
+        }
+    *dc_lhy = K * dV * S[8];
+    return BEC_OK;
+}
+
+}  // extern "C"

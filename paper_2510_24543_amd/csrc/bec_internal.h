@@ -1,0 +1,162 @@
+// Internal declarations of the gfx950 library: kernel argument blocks and
+// launchers shared by the FFT, pointwise and host translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace bec {
+
+constexpr int kMaxNodes = 64;        // Gauss-Legendre nodes for the LHY u integral
+constexpr int kNodeStride = 8;       // doubles per node in the node table
+constexpr int kPwThreads = 256;      // threads per block of the pointwise kernels
+constexpr int kPwMaxBlocks = 2048;   // grid of the pointwise kernels (fixed per size)
+constexpr int kMaxSums = 32;         // reduced scalars per pass
+
+// Per-node table entry (kNodeStride doubles):
+//   [0] eta_11  [1] eta_22  [2] eta_12 eta_21  [3] w_q  [4] eta_12  [5] eta_21
+//   [6] 3u^2 - 1  [7] unused
+// eta_ij = G_ij + Gdd_ij (3 u_q^2 - 1); w_q are the weights on [0,1].
+
+// Physical and geometric constants used inside the pointwise kernels.
+struct PwParams {
+    int nx, ny, nz;
+    long long N;               // points per component
+    double G[2][2], Gdd[2][2];
+    double Nat[2];             // atom numbers N_i
+    double K5;                 // c_lhy sqrt(2)/(15 pi^2)   (energy density)
+    double K3;                 // c_lhy /(3 sqrt(2) pi^2)   (derivatives)
+    int n_u;
+    int lhy_on;                // c_lhy != 0
+    const double* nodes;       // n_u * kNodeStride
+    const double* vx;          // 1/2 omega_x^2 x^2 per x index
+    const double* vy;
+    const double* vz;
+};
+
+// ---------------------------------------------------------------- FFT passes
+enum FftOp : int {
+    kOpPlain = 0,       // one direction, store (optionally scaled)
+    kOpMulKin = 1,      // forward, times |k|^2/2 /N, inverse, store
+    kOpMulDip = 2,      // forward, times Ud(k)/N, inverse, store
+    kOpMulPrec = 3,     // forward, times 1/(a_f + |k|^2/2)/N, inverse, store
+    kOpParseval = 4     // forward, accumulate sum |k|^2/2 |v|^2, no store
+};
+
+struct FftPassArgs {
+    const double2* src[3];
+    double2* dst[3];
+    int op[3];             // per field (only the x pass uses ops other than Plain)
+    double prec_a[3];      // per field shift for kOpMulPrec
+    int nfield;
+    long long S;           // stride between successive pencil elements
+    long long npencil;     // pencils per field
+    const double2* tw;     // W_L^m = exp(-2 pi i m / L), m = 0..L-1
+    int sign;              // -1 forward, +1 inverse (kOpPlain)
+    double scale;          // applied at store (kOpPlain)
+    // x-pass multipliers
+    int nx, ny, nz;
+    const double* kx;      // wavenumbers per axis
+    const double* ky;
+    const double* kz;
+    const double* udtab;   // dipolar kernel on the k octant [nx/2+1][ny/2+1][nz/2+1]
+    double inv_n;          // 1/(nx ny nz)
+    double* partials;      // kOpParseval: [field][block]
+    int nblk_x;
+};
+
+// Launch one axis pass of length L over args.nfield fields. axis: 0 x, 1 y, 2 z.
+hipError_t fft_pass(int L, bool contiguous, const FftPassArgs& args, hipStream_t s);
+bool fft_supported(int L);
+int fft_blocks(int L, long long npencil);   // grid.x of a pass
+
+// ---------------------------------------------------------------- pointwise kernels
+struct TrialArgs {                // psi_dst = a_i psi_src + b_i p ; W2 = n1 + i n2
+    const double2* psi_src;
+    const double2* p;             // may be null (then psi_dst = a_i psi_src)
+    double a[2], b[2];
+    double2* psi_dst;
+    double2* dens;                // packed density n1 + i n2
+};
+
+struct HevalArgs {
+    const double2* psi;
+    const double2* Tpsi;          // 2N: -1/2 Lap psi_i
+    const double2* phi;           // N: Phi_1 + i Phi_2
+    double2* hpsi;                // 2N out
+    double2* aux;                 // 2N out: [0,N) Phi packed copy, [N,2N) muLHY_1 + i muLHY_2
+    double* partials;
+};
+constexpr int kHevalSums = 18;
+// sums: 0,1 Re<psi_i,Tpsi_i>; 2,3 V n_i; 4 n1n1; 5 n1n2; 6 n2n2; 7..10 n_i Phi_j (11,12,21,22);
+//       11 e_LHY; 12,13 Re<psi_i,Hpsi_i>; 14,15 n_i; 16,17 muLHY_i n_i
+
+struct DirArgs {
+    const double2* psi;
+    const double2* hpsi;
+    const double2* aux;           // Phi packed, muLHY packed
+    const double2* zbuf;          // z (when zmode == 2), 2N
+    const double2* r_old;         // 2N (read by the reduce pass)
+    double2* p;                   // 2N: p_old on input, p on output (write pass)
+    double2* r_out;               // 2N (write pass)
+    double2* rho;                 // N (write pass): rho_1 + i rho_2
+    double mu[2];
+    double diag_shift[2];         // shift_i for P_V
+    double sigma;
+    int zmode;                    // 0 identity, 1 P_V, 2 from zbuf
+    double zsign;                 // d = zsign z + beta p_old
+    double beta;
+    double c[2];                  // projection coefficients Re<d_i,psi_i>
+    int have_prev;
+    double* partials;
+};
+constexpr int kDirReduceSums = 12;
+// sums (per component i, index 6*i + k): 0 |r|^2, 1 Re<r - r_old, z>, 2 Re<r - r_old, p_old>,
+//   3 Re<z, psi>, 4 Re<p_old, psi>, 5 Re<r, z>
+constexpr int kDirWriteSums = 18;
+// sums: 0,1 |p_i|^2; 2,3 Re<p_i,r_i>; 4,5 Re<p_i,(H - muL)psi_i>; 6,7 Re<psi_i,(H - muL) psi_i>;
+//       8,9 U_MF,i |p_i|^2; 10,11 muL_i |p_i|^2; 12,13 muL_i n_i; 14 LHY V^1 sum; 15 LHY V^2 (n''=0) sum;
+//       16,17 Re<p_i, psi_i>
+
+struct LsEpiArgs {
+    const double2* rho;           // rho_1 + i rho_2
+    const double2* phr;           // Phi[rho_1] + i Phi[rho_2]
+    double* partials;
+};
+constexpr int kLsEpiSums = 7;
+// sums: 0 rho1 rho1; 1 rho1 rho2; 2 rho2 rho2; 3..6 rho_i Phi[rho_j] (11, 12, 21, 22)
+
+struct MakeRArgs {                // out = r or P_V^-1 r (for the kinetic preconditioners)
+    const double2* psi;
+    const double2* hpsi;
+    const double2* aux;
+    const double2* rin;           // if non-null: r given directly (ignores psi/hpsi/mu)
+    double mu[2];
+    double diag_shift[2];
+    double sigma;
+    int apply_pv;
+    double2* out;                 // 2N
+};
+
+struct ParamGradArgs {
+    const double2* psi;
+    double* partials;
+};
+constexpr int kParamSums = 9;     // 0..3 de/deta_ij (11,12,21,22); 4..7 same times (3u^2-1); 8 e (c = 1)
+
+hipError_t launch_trial(const PwParams& P, const TrialArgs& a, hipStream_t s);
+hipError_t launch_heval_epi(const PwParams& P, const HevalArgs& a, int nblk, hipStream_t s);
+hipError_t launch_dir_reduce(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s);
+hipError_t launch_dir_write(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s);
+hipError_t launch_ls_epi(const PwParams& P, const LsEpiArgs& a, int nblk, hipStream_t s);
+hipError_t launch_make_r(const PwParams& P, const MakeRArgs& a, hipStream_t s);
+hipError_t launch_param_grad(const PwParams& P, const ParamGradArgs& a, int nblk, hipStream_t s);
+hipError_t launch_norm2(const PwParams& P, const double2* f, double* partials, int nblk, hipStream_t s);
+hipError_t launch_scale2(const PwParams& P, const double2* in, double2* out, double s0, double s1,
+                         hipStream_t s);
+hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hpsi, double2* out,
+                       double mu0, double mu1, double s0, double s1, int projected, hipStream_t s);
+// out[m] = sum_b partials[m * nblk + b] for m < M (fixed order), one block
+hipError_t launch_reduce_final(const double* partials, int nblk, int M, double* out, hipStream_t s);
+
+}  // namespace bec

@@ -1,0 +1,405 @@
+// Batched 3D complex128 FFT passes for gfx950.
+//
+// A 3D transform is three axis passes (z, y, x forward; x, y, z inverse).  One
+// pass transforms every pencil along one axis, in place or out of place.  A
+// workgroup owns whole pencils: it loads them once from HBM into registers,
+// runs a self-sorting Stockham factorisation (radix 2/3/4/6/8/12/16 butterflies
+// in registers, one LDS exchange between stages), and stores them once.
+// Thread-to-element maps are chosen for coalescing: along the contiguous z
+// axis consecutive lanes read consecutive elements of a pencil; along the
+// strided y and x axes consecutive lanes take consecutive pencils, so each
+// load instruction reads whole 16-byte columns side by side.
+//
+// The x pass (last forward axis, first inverse axis) can fuse a diagonal
+// k-space operator: forward x, multiply, inverse x in registers -- the
+// kinetic term |k|^2/2, the dipolar kernel Ud(k), the kinetic preconditioner
+// 1/(a + |k|^2/2) -- or reduce the Parseval sum of |k|^2/2 |v|^2 without a
+// store.  The paper evaluates the kinetic term, the dipolar convolution and
+// the kinetic preconditioner with FFTs (Sec. IV.B, Sec. VI.B).
+#include "bec_internal.h"
+#include "dft_consts.h"
+
+namespace bec {
+namespace {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// v * W_R^m with W_R = exp(D 2 pi i / R); R divides 48; folds at compile time.
+template <int D>
+__device__ __forceinline__ double2 twmul(double2 v, int R, int m)
+{
+    const int idx = ((m * (48 / R)) % 48 + 48) % 48;
+    if (idx == 0) return v;
+    if (idx == 24) return make_double2(-v.x, -v.y);
+    if (idx == 12) return D < 0 ? make_double2(v.y, -v.x) : make_double2(-v.y, v.x);
+    if (idx == 36) return D < 0 ? make_double2(-v.y, v.x) : make_double2(v.y, -v.x);
+    const double2 w = make_double2(kCos48[idx], D < 0 ? -kSin48[idx] : kSin48[idx]);
+    return cmul(v, w);
+}
+
+template <int R, int D> struct Dft;
+
+template <int D> struct Dft<1, D> {
+    __device__ static void run(double2*) {}
+};
+
+template <int D> struct Dft<2, D> {
+    __device__ static void run(double2* v)
+    {
+        const double2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <int D> struct Dft<3, D> {
+    __device__ static void run(double2* v)
+    {
+        const double s3 = kSin48[16];                       // sin(2 pi / 3)
+        const double2 a = v[0], t = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+        const double2 m = make_double2(a.x - 0.5 * t.x, a.y - 0.5 * t.y);
+        const double2 isd = make_double2(-s3 * d.y, s3 * d.x);   // i sin(2pi/3) d
+        v[0] = cadd(a, t);
+        if (D < 0) { v[1] = csub(m, isd); v[2] = cadd(m, isd); }
+        else       { v[1] = cadd(m, isd); v[2] = csub(m, isd); }
+    }
+};
+
+template <int D> struct Dft<4, D> {
+    __device__ static void run(double2* v)
+    {
+        const double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        const double2 t2 = cadd(v[1], v[3]), d = csub(v[1], v[3]);
+        const double2 t3 = D < 0 ? make_double2(d.y, -d.x) : make_double2(-d.y, d.x);
+        v[0] = cadd(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[2] = csub(t0, t2);
+        v[3] = csub(t1, t3);
+    }
+};
+
+// Cooley-Tukey split R = R1 R2 inside registers:
+// X[k1 + R1 k2] = sum_n2 W_R2^(n2 k2) W_R^(n2 k1) sum_n1 x[n2 + R2 n1] W_R1^(n1 k1)
+template <int R1, int R2, int D>
+__device__ __forceinline__ void dft_split(double2* v)
+{
+    constexpr int R = R1 * R2;
+    double2 a[R];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+        double2 t[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[n2 + R2 * n1];
+        Dft<R1, D>::run(t);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) a[n2 * R1 + k1] = twmul<D>(t[k1], R, n2 * k1);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        double2 t[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) t[n2] = a[n2 * R1 + k1];
+        Dft<R2, D>::run(t);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+    }
+}
+
+template <int D> struct Dft<6, D> {
+    __device__ static void run(double2* v) { dft_split<2, 3, D>(v); }
+};
+template <int D> struct Dft<8, D> {
+    __device__ static void run(double2* v) { dft_split<2, 4, D>(v); }
+};
+template <int D> struct Dft<12, D> {
+    __device__ static void run(double2* v) { dft_split<4, 3, D>(v); }
+};
+template <int D> struct Dft<16, D> {
+    __device__ static void run(double2* v) { dft_split<4, 4, D>(v); }
+};
+
+// Stockham stage of radix R after a span NS of earlier radices.  Thread t owns
+// butterflies j = t + b T; butterfly j reads X[j + r L/R] (registers
+// v[b R + r]), applies W_L^(r k L/(NS R)), k = j mod NS, and a length-R DFT.
+template <int L, int T, int R, int NS, int D>
+__device__ __forceinline__ void stage(double2* v, int t, const double2* __restrict__ tw)
+{
+    constexpr int E = L / T, NB = E / R;
+    static_assert(E % R == 0, "radix must divide the elements per thread");
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (NS > 1) {
+            const int j = t + b * T;
+            const int k = j % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                double2 w = tw[r * k * (L / (NS * R))];
+                if (D > 0) w.y = -w.y;
+                v[b * R + r] = cmul(v[b * R + r], w);
+            }
+        }
+        Dft<R, D>::run(v + b * R);
+    }
+}
+
+// Output of stage (R, NS): v[b R + r] goes to Y[(j/NS) NS R + (j mod NS) + r NS].
+// The next stage (radix RN) reads X[t + b T + r L/RN].
+template <int L, int T, int R, int NS, int RN>
+__device__ __forceinline__ void exchange(double2* v, double2* row, int t)
+{
+    constexpr int E = L / T;
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+        const int j = t + b * T;
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) row[base + r * NS] = v[b * R + r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < E / RN; ++b)
+#pragma unroll
+        for (int r = 0; r < RN; ++r) v[b * RN + r] = row[t + b * T + r * (L / RN)];
+    __syncthreads();
+}
+
+// Full length-L transform of the registers, radices R0 R1 R2 (1 = absent).
+// Input in stage-0 layout of R0, output in natural layout of the last radix.
+template <int L, int T, int R0, int R1, int R2, int D>
+__device__ __forceinline__ void run_fft(double2* v, double2* row, int t, const double2* __restrict__ tw)
+{
+    stage<L, T, R0, 1, D>(v, t, tw);
+    if constexpr (R1 > 1) {
+        exchange<L, T, R0, 1, R1>(v, row, t);
+        stage<L, T, R1, R0, D>(v, t, tw);
+        if constexpr (R2 > 1) {
+            exchange<L, T, R1, R0, R2>(v, row, t);
+            stage<L, T, R2, R0 * R1, D>(v, t, tw);
+        }
+    }
+}
+
+template <int L, int T, int R0, int R1, int R2>
+struct Plan {
+    static constexpr int RL = R2 > 1 ? R2 : (R1 > 1 ? R1 : R0);   // last forward radix
+    static constexpr int E = L / T;
+    template <int D>
+    __device__ static void fwd_like(double2* v, double2* row, int t, const double2* tw)
+    {
+        run_fft<L, T, R0, R1, R2, D>(v, row, t, tw);
+    }
+    // inverse run with reversed radices: starts in the layout the forward ends in
+    __device__ static void inv_rev(double2* v, double2* row, int t, const double2* tw)
+    {
+        if constexpr (R2 > 1) run_fft<L, T, R2, R1, R0, +1>(v, row, t, tw);
+        else if constexpr (R1 > 1) run_fft<L, T, R1, R0, 1, +1>(v, row, t, tw);
+        else run_fft<L, T, R0, 1, 1, +1>(v, row, t, tw);
+    }
+};
+
+template <int NTHR>
+__device__ double block_sum(double v, double* sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NTHR / 64; ++i) r += sh[i];
+    return r;
+}
+
+// KMODE: 0 forward plain pass, 1 inverse plain pass, 2 x pass with per-field ops.
+template <int L, int T, int R0, int R1, int R2, int NTHR, bool CONTIG, int KMODE>
+__global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
+{
+    using PL = Plan<L, T, R0, R1, R2>;
+    constexpr int E = L / T, PB = NTHR / T, RS = L + 1;
+    __shared__ double2 lds[PB * RS];
+    const int f = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int pl = CONTIG ? tid / T : tid % PB;
+    const int t = CONTIG ? tid % T : tid / PB;
+    const long long pg = (long long)blockIdx.x * PB + pl;
+    const bool valid = pg < A.npencil;
+    const long long S = A.S;
+    long long base = 0, s = 0;
+    if (valid) {
+        const long long o = pg / S;
+        s = pg - o * S;
+        base = o * (long long)L * S + s;
+    }
+    const double2* __restrict__ src = A.src[f];
+    double2* __restrict__ dst = A.dst[f];
+    const double2* __restrict__ tw = A.tw;
+    const int op = KMODE == 2 ? A.op[f] : kOpPlain;
+    double2* row = lds + pl * RS;
+
+    double2 v[E];
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int j = t + b * T + r * (L / R0);
+            v[b * R0 + r] = valid ? src[base + (long long)j * S] : make_double2(0.0, 0.0);
+        }
+
+    constexpr int RL = PL::RL;
+    if (KMODE < 2) {
+        PL::template fwd_like<KMODE == 0 ? -1 : +1>(v, row, t, tw);
+        if (valid) {
+            const double sc = A.scale;
+#pragma unroll
+            for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+                for (int r = 0; r < RL; ++r) {
+                    const int j = t + b * T + r * (L / RL);
+                    dst[base + (long long)j * S] = sc == 1.0 ? v[b * RL + r] : cscale(v[b * RL + r], sc);
+                }
+        }
+        return;
+    }
+
+    // x pass with a diagonal k-space operator: forward, then op
+    PL::template fwd_like<-1>(v, row, t, tw);
+    double ky2 = 0.0, kz2 = 0.0;
+    int ay = 0, az = 0;
+    {
+        const int iy = (int)(s / A.nz), iz = (int)(s - (long long)iy * A.nz);
+        const double ky = A.ky[iy], kz = A.kz[iz];
+        ky2 = ky * ky;
+        kz2 = kz * kz;
+        ay = iy <= A.ny / 2 ? iy : A.ny - iy;
+        az = iz <= A.nz / 2 ? iz : A.nz - iz;
+    }
+    if (op == kOpParseval) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int j = t + b * T + r * (L / RL);
+                const double kx = A.kx[j];
+                const double2 w = v[b * RL + r];
+                acc += 0.5 * (kx * kx + ky2 + kz2) * (w.x * w.x + w.y * w.y);
+            }
+        if (!valid) acc = 0.0;
+        __syncthreads();
+        const double tot = block_sum<NTHR>(acc, reinterpret_cast<double*>(lds));
+        if (threadIdx.x == 0) A.partials[(long long)f * A.nblk_x + blockIdx.x] = tot;
+        return;
+    }
+    const double inv_n = A.inv_n;
+    const double pa = A.prec_a[f];
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const int j = t + b * T + r * (L / RL);
+            double m;
+            if (op == kOpMulKin) {
+                const double kx = A.kx[j];
+                m = 0.5 * (kx * kx + ky2 + kz2);
+            } else if (op == kOpMulDip) {
+                const int ax = j <= L / 2 ? j : L - j;
+                m = A.udtab[((long long)ax * (A.ny / 2 + 1) + ay) * (A.nz / 2 + 1) + az];
+            } else {
+                const double kx = A.kx[j];
+                m = 1.0 / (pa + 0.5 * (kx * kx + ky2 + kz2));
+            }
+            v[b * RL + r] = cscale(v[b * RL + r], m * inv_n);
+        }
+    PL::inv_rev(v, row, t, tw);
+    if (valid) {
+#pragma unroll
+        for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int j = t + b * T + r * (L / R0);
+                dst[base + (long long)j * S] = v[b * R0 + r];
+            }
+    }
+}
+
+template <int L, int T, int R0, int R1, int R2, int NTHR>
+hipError_t launch_cfg(bool contiguous, const FftPassArgs& A, hipStream_t st)
+{
+    constexpr int PB = NTHR / T;
+    dim3 grid((unsigned)((A.npencil + PB - 1) / PB), (unsigned)A.nfield);
+    bool plain = true;
+    for (int f = 0; f < A.nfield; ++f) plain = plain && A.op[f] == kOpPlain;
+    if (contiguous) {
+        // the contiguous (z) axis is never the fused x pass
+        if (!plain) return hipErrorInvalidValue;
+        if (A.sign < 0)
+            hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, true, 0>), grid, dim3(NTHR), 0, st, A);
+        else
+            hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, true, 1>), grid, dim3(NTHR), 0, st, A);
+    } else if (plain) {
+        if (A.sign < 0)
+            hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, false, 0>), grid, dim3(NTHR), 0, st, A);
+        else
+            hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, false, 1>), grid, dim3(NTHR), 0, st, A);
+    } else {
+        hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, false, 2>), grid, dim3(NTHR), 0, st, A);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Per-length plans: threads per pencil T, radices, threads per workgroup.
+bool fft_supported(int L)
+{
+    switch (L) {
+    case 8: case 16: case 32: case 48: case 64: case 96: case 128: case 256: return true;
+    default: return false;
+    }
+}
+
+static int pencils_per_block(int L)
+{
+    switch (L) {
+    case 8: return 128;      // T=1, 128 threads
+    case 16: return 64;      // T=4, 256
+    case 32: return 64;      // T=4, 256
+    case 48: return 64;      // T=4, 256
+    case 64: return 32;      // T=8, 256
+    case 96: return 32;      // T=4, 128
+    case 128: return 32;     // T=8, 256
+    case 256: return 16;     // T=16, 256
+    default: return 1;
+    }
+}
+
+int fft_blocks(int L, long long npencil)
+{
+    const int pb = pencils_per_block(L);
+    return (int)((npencil + pb - 1) / pb);
+}
+
+hipError_t fft_pass(int L, bool contiguous, const FftPassArgs& A, hipStream_t st)
+{
+    switch (L) {
+    case 8: return launch_cfg<8, 1, 8, 1, 1, 128>(contiguous, A, st);
+    case 16: return launch_cfg<16, 4, 4, 4, 1, 256>(contiguous, A, st);
+    case 32: return launch_cfg<32, 4, 8, 4, 1, 256>(contiguous, A, st);
+    case 48: return launch_cfg<48, 4, 12, 4, 1, 256>(contiguous, A, st);
+    case 64: return launch_cfg<64, 8, 8, 8, 1, 256>(contiguous, A, st);
+    case 96: return launch_cfg<96, 4, 12, 8, 1, 128>(contiguous, A, st);
+    case 128: return launch_cfg<128, 8, 16, 8, 1, 256>(contiguous, A, st);
+    case 256: return launch_cfg<256, 16, 16, 16, 1, 256>(contiguous, A, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace bec

@@ -1,0 +1,533 @@
+// Fused pointwise + reduction kernels for gfx950 (FP64 vector ALU, no MFMA:
+// nothing here is a dense contraction).
+//
+// Every kernel streams its operands once with 16-byte loads, does all per-point
+// algebra in registers, and reduces its scalars per thread, per wavefront
+// (lane shuffles) and per workgroup into a fixed slot of a partials array.  A
+// one-workgroup kernel then sums the partials in a fixed order, so every
+// reduced scalar is bitwise reproducible for a given grid size.
+//
+// Physics (arXiv:2510.24543):
+//   H_i psi_i = T psi_i + [V + sum_j (G_ij n_j + Gdd_ij Phi_j) + muLHY_i] psi_i   (Sec. II, Eq. (6))
+//   e_LHY = c sqrt(2)/(15 pi^2) int du sum_+- [V_+-]_+^(5/2)                      (Eq. (1), (3))
+//   muLHY_i = (1/N_i) de/dn_i                                                       (Eq. (5))
+//   residual r_i = H_i psi_i - mu_i psi_i                                           (Sec. III, Eq. (8))
+//   P_V diagonal [alpha_i + V + sum_j G_ij n_j + muLHY_i]_+ + sigma                  (Sec. IV.B)
+//   d = -z + beta p_old, p = d - Re<d,psi> psi                                      (Sec. IV.C, Sec. V)
+//   second-order energy model along the geodesic                                    (Sec. V)
+#include "bec_internal.h"
+
+namespace bec {
+namespace {
+
+__device__ __forceinline__ double sq2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double redot(double2 a, double2 b) { return a.x * b.x + a.y * b.y; }  // Re(conj(a) b)
+
+__device__ __forceinline__ double trap_at(const PwParams& P, long long i)
+{
+    const long long nyz = (long long)P.ny * P.nz;
+    const int ix = (int)(i / nyz);
+    const long long rem = i - (long long)ix * nyz;
+    const int iy = (int)(rem / P.nz);
+    const int iz = (int)(rem - (long long)iy * P.nz);
+    return P.vx[ix] + P.vy[iy] + P.vz[iz];
+}
+
+// LHY energy density and derivatives at one point.  Branches with V <= 0
+// contribute nothing ([V]_+ powers); ratio terms vanish when s = 0.
+__device__ __forceinline__ void lhy_point(const PwParams& P, double n1, double n2, double& e,
+                                          double& d1, double& d2)
+{
+    double ae = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int q = 0; q < P.n_u; ++q) {
+        const double* nd = P.nodes + q * kNodeStride;
+        const double e11 = nd[0], e22 = nd[1], p12 = nd[2], w = nd[3];
+        const double a = e11 * n1, b = e22 * n2, delta = a - b;
+        const double s = sqrt(delta * delta + 4.0 * p12 * n1 * n2);
+        const double inv = s > 0.0 ? 1.0 / s : 0.0;
+        const double r1 = (e11 * delta + 2.0 * p12 * n2) * inv;
+        const double r2 = (-e22 * delta + 2.0 * p12 * n1) * inv;
+        const double Vp = a + b + s, Vm = a + b - s;
+        if (Vp > 0.0) {
+            const double v32 = Vp * sqrt(Vp);
+            ae += w * Vp * v32;
+            a1 += w * v32 * (e11 + r1);
+            a2 += w * v32 * (e22 + r2);
+        }
+        if (Vm > 0.0) {
+            const double v32 = Vm * sqrt(Vm);
+            ae += w * Vm * v32;
+            a1 += w * v32 * (e11 - r1);
+            a2 += w * v32 * (e22 - r2);
+        }
+    }
+    e = P.K5 * ae;
+    d1 = P.K3 * a1;
+    d2 = P.K3 * a2;
+}
+
+// LHY part of the geodesic model with n'' = 0: sums of [V]_+^(3/2) V^1 and of
+// [V]_+^(3/2) V^2_0 + 3/4 [V]_+^(1/2) (V^1)^2.  The n'' part of V^2 is linear in
+// n''_i with coefficient dV/dn_i and is added from muLHY on the host.
+__device__ __forceinline__ void lhy_model(const PwParams& P, double n1, double n2, double n1p,
+                                          double n2p, double& L1, double& L2)
+{
+    double s1 = 0.0, s2acc = 0.0;
+    for (int q = 0; q < P.n_u; ++q) {
+        const double* nd = P.nodes + q * kNodeStride;
+        const double e11 = nd[0], e22 = nd[1], p12 = nd[2], w = nd[3];
+        const double delta = e11 * n1 - e22 * n2;
+        const double d1 = e11 * n1p - e22 * n2p;
+        const double ss = delta * delta + 4.0 * p12 * n1 * n2;
+        const double s = sqrt(ss);
+        const double A = delta * d1 + 2.0 * p12 * (n1 * n2p + n1p * n2);
+        const double B0 = d1 * d1 + 4.0 * p12 * n1p * n2p;
+        const double lin1 = e11 * n1p + e22 * n2p;
+        double ra = 0.0, rb = 0.0;
+        if (s > 0.0) {   // B/(2s) - A^2/(2s^3) as (B - (A/s)^2)/(2s): s^3 underflows at tiny densities
+            const double inv = 1.0 / s;
+            ra = A * inv;
+            rb = 0.5 * (B0 - ra * ra) * inv;
+        }
+        const double base = e11 * n1 + e22 * n2;
+        const double Vp = base + s, Vm = base - s;
+        if (Vp > 0.0) {
+            const double rv = sqrt(Vp), V1 = lin1 + ra, V2 = rb;
+            s1 += w * Vp * rv * V1;
+            s2acc += w * (Vp * rv * V2 + 0.75 * rv * V1 * V1);
+        }
+        if (Vm > 0.0) {
+            const double rv = sqrt(Vm), V1 = lin1 - ra, V2 = -rb;
+            s1 += w * Vm * rv * V1;
+            s2acc += w * (Vm * rv * V2 + 0.75 * rv * V1 * V1);
+        }
+    }
+    L1 = s1;
+    L2 = s2acc;
+}
+
+// Fixed-order workgroup reduction of M per-thread sums into partials[m * nblk + block].
+template <int M>
+__device__ __forceinline__ void block_reduce_store(const double (&acc)[M], double* partials, int nblk)
+{
+    __shared__ double sh[M][kPwThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        double v = acc[m];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) sh[m][w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < M) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kPwThreads / 64; ++k) s += sh[threadIdx.x][k];
+        partials[(long long)threadIdx.x * nblk + blockIdx.x] = s;
+    }
+}
+
+#define GRID_STRIDE(i, N)                                                                      \
+    for (long long i = (long long)blockIdx.x * kPwThreads + threadIdx.x; i < (N);             \
+         i += (long long)gridDim.x * kPwThreads)
+
+__global__ __launch_bounds__(kPwThreads) void trial_kernel(PwParams P, TrialArgs A)
+{
+    const long long N = P.N;
+    GRID_STRIDE(i, N)
+    {
+        double2 s1 = A.psi_src[i], s2 = A.psi_src[N + i];
+        double2 o1 = make_double2(A.a[0] * s1.x, A.a[0] * s1.y);
+        double2 o2 = make_double2(A.a[1] * s2.x, A.a[1] * s2.y);
+        if (A.p) {
+            const double2 p1 = A.p[i], p2 = A.p[N + i];
+            o1.x += A.b[0] * p1.x; o1.y += A.b[0] * p1.y;
+            o2.x += A.b[1] * p2.x; o2.y += A.b[1] * p2.y;
+        }
+        A.psi_dst[i] = o1;
+        A.psi_dst[N + i] = o2;
+        A.dens[i] = make_double2(sq2(o1), sq2(o2));
+    }
+}
+
+__global__ __launch_bounds__(kPwThreads) void heval_epi_kernel(PwParams P, HevalArgs A)
+{
+    const long long N = P.N;
+    double acc[kHevalSums];
+#pragma unroll
+    for (int m = 0; m < kHevalSums; ++m) acc[m] = 0.0;
+    GRID_STRIDE(i, N)
+    {
+        const double2 s1 = A.psi[i], s2 = A.psi[N + i];
+        const double2 t1 = A.Tpsi[i], t2 = A.Tpsi[N + i];
+        const double2 ph = A.phi[i];
+        const double n1 = sq2(s1), n2 = sq2(s2);
+        const double V = trap_at(P, i);
+        double e = 0.0, d1 = 0.0, d2 = 0.0;
+        if (P.lhy_on) lhy_point(P, n1, n2, e, d1, d2);
+        const double m1 = d1 / P.Nat[0], m2 = d2 / P.Nat[1];
+        const double U1 = V + P.G[0][0] * n1 + P.G[0][1] * n2 + P.Gdd[0][0] * ph.x + P.Gdd[0][1] * ph.y + m1;
+        const double U2 = V + P.G[1][0] * n1 + P.G[1][1] * n2 + P.Gdd[1][0] * ph.x + P.Gdd[1][1] * ph.y + m2;
+        const double2 h1 = make_double2(t1.x + U1 * s1.x, t1.y + U1 * s1.y);
+        const double2 h2 = make_double2(t2.x + U2 * s2.x, t2.y + U2 * s2.y);
+        A.hpsi[i] = h1;
+        A.hpsi[N + i] = h2;
+        A.aux[i] = ph;
+        A.aux[N + i] = make_double2(m1, m2);
+        acc[0] += redot(s1, t1);
+        acc[1] += redot(s2, t2);
+        acc[2] += V * n1;
+        acc[3] += V * n2;
+        acc[4] += n1 * n1;
+        acc[5] += n1 * n2;
+        acc[6] += n2 * n2;
+        acc[7] += n1 * ph.x;
+        acc[8] += n1 * ph.y;
+        acc[9] += n2 * ph.x;
+        acc[10] += n2 * ph.y;
+        acc[11] += e;
+        acc[12] += redot(s1, h1);
+        acc[13] += redot(s2, h2);
+        acc[14] += n1;
+        acc[15] += n2;
+        acc[16] += m1 * n1;
+        acc[17] += m2 * n2;
+    }
+    block_reduce_store<kHevalSums>(acc, A.partials, gridDim.x);
+}
+
+// residual and preconditioned residual at point i for both components
+struct RZ {
+    double2 r[2], z[2];
+};
+
+__device__ __forceinline__ RZ resid_precond(const PwParams& P, const DirArgs& A, long long i,
+                                            double2 s1, double2 s2)
+{
+    const long long N = P.N;
+    RZ o;
+    const double2 h1 = A.hpsi[i], h2 = A.hpsi[N + i];
+    o.r[0] = make_double2(h1.x - A.mu[0] * s1.x, h1.y - A.mu[0] * s1.y);
+    o.r[1] = make_double2(h2.x - A.mu[1] * s2.x, h2.y - A.mu[1] * s2.y);
+    if (A.zmode == 1) {
+        const double n1 = sq2(s1), n2 = sq2(s2);
+        const double V = trap_at(P, i);
+        const double2 ml = A.aux[N + i];
+        double g1 = A.diag_shift[0] + V + P.G[0][0] * n1 + P.G[0][1] * n2 + ml.x;
+        double g2 = A.diag_shift[1] + V + P.G[1][0] * n1 + P.G[1][1] * n2 + ml.y;
+        g1 = 1.0 / ((g1 > 0.0 ? g1 : 0.0) + A.sigma);
+        g2 = 1.0 / ((g2 > 0.0 ? g2 : 0.0) + A.sigma);
+        o.z[0] = make_double2(g1 * o.r[0].x, g1 * o.r[0].y);
+        o.z[1] = make_double2(g2 * o.r[1].x, g2 * o.r[1].y);
+    } else if (A.zmode == 2) {
+        o.z[0] = A.zbuf[i];
+        o.z[1] = A.zbuf[N + i];
+    } else {
+        o.z[0] = o.r[0];
+        o.z[1] = o.r[1];
+    }
+    return o;
+}
+
+__global__ __launch_bounds__(kPwThreads) void dir_reduce_kernel(PwParams P, DirArgs A)
+{
+    const long long N = P.N;
+    double acc[kDirReduceSums];
+#pragma unroll
+    for (int m = 0; m < kDirReduceSums; ++m) acc[m] = 0.0;
+    GRID_STRIDE(i, N)
+    {
+        const double2 s[2] = {A.psi[i], A.psi[N + i]};
+        const RZ q = resid_precond(P, A, i, s[0], s[1]);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            acc[6 * c + 0] += sq2(q.r[c]);
+            acc[6 * c + 3] += redot(q.z[c], s[c]);
+            acc[6 * c + 5] += redot(q.r[c], q.z[c]);
+            if (A.have_prev) {
+                const double2 ro = A.r_old[c * N + i], po = A.p[c * N + i];
+                const double2 y = make_double2(q.r[c].x - ro.x, q.r[c].y - ro.y);
+                acc[6 * c + 1] += redot(y, q.z[c]);
+                acc[6 * c + 2] += redot(y, po);
+                acc[6 * c + 4] += redot(po, s[c]);
+            }
+        }
+    }
+    block_reduce_store<kDirReduceSums>(acc, A.partials, gridDim.x);
+}
+
+__global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirArgs A)
+{
+    const long long N = P.N;
+    double acc[kDirWriteSums];
+#pragma unroll
+    for (int m = 0; m < kDirWriteSums; ++m) acc[m] = 0.0;
+    GRID_STRIDE(i, N)
+    {
+        const double2 s[2] = {A.psi[i], A.psi[N + i]};
+        const RZ q = resid_precond(P, A, i, s[0], s[1]);
+        const double2 h[2] = {A.hpsi[i], A.hpsi[N + i]};
+        const double2 ph = A.aux[i], ml = A.aux[N + i];
+        const double mlc[2] = {ml.x, ml.y};
+        const double n[2] = {sq2(s[0]), sq2(s[1])};
+        const double V = trap_at(P, i);
+        double2 p[2];
+        double rho[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            double2 d = make_double2(A.zsign * q.z[c].x, A.zsign * q.z[c].y);
+            if (A.beta != 0.0) {
+                const double2 po = A.p[c * N + i];
+                d.x += A.beta * po.x;
+                d.y += A.beta * po.y;
+            }
+            p[c] = make_double2(d.x - A.c[c] * s[c].x, d.y - A.c[c] * s[c].y);
+            A.p[c * N + i] = p[c];
+            A.r_out[c * N + i] = q.r[c];
+            rho[c] = redot(s[c], p[c]);
+            const double2 hmf = make_double2(h[c].x - mlc[c] * s[c].x, h[c].y - mlc[c] * s[c].y);
+            const double U = V + P.G[c][0] * n[0] + P.G[c][1] * n[1] + P.Gdd[c][0] * ph.x + P.Gdd[c][1] * ph.y;
+            const double pp = sq2(p[c]);
+            acc[0 + c] += pp;
+            acc[2 + c] += redot(p[c], q.r[c]);
+            acc[4 + c] += redot(p[c], hmf);
+            acc[6 + c] += redot(s[c], hmf);
+            acc[8 + c] += U * pp;
+            acc[10 + c] += mlc[c] * pp;
+            acc[12 + c] += mlc[c] * n[c];
+            acc[16 + c] += rho[c];
+        }
+        A.rho[i] = make_double2(rho[0], rho[1]);
+        if (P.lhy_on) {
+            double L1, L2;
+            lhy_model(P, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
+            acc[14] += L1;
+            acc[15] += L2;
+        }
+    }
+    block_reduce_store<kDirWriteSums>(acc, A.partials, gridDim.x);
+}
+
+__global__ __launch_bounds__(kPwThreads) void ls_epi_kernel(PwParams P, LsEpiArgs A)
+{
+    const long long N = P.N;
+    double acc[kLsEpiSums];
+#pragma unroll
+    for (int m = 0; m < kLsEpiSums; ++m) acc[m] = 0.0;
+    GRID_STRIDE(i, N)
+    {
+        const double2 r = A.rho[i], f = A.phr[i];
+        acc[0] += r.x * r.x;
+        acc[1] += r.x * r.y;
+        acc[2] += r.y * r.y;
+        acc[3] += r.x * f.x;
+        acc[4] += r.x * f.y;
+        acc[5] += r.y * f.x;
+        acc[6] += r.y * f.y;
+    }
+    block_reduce_store<kLsEpiSums>(acc, A.partials, gridDim.x);
+}
+
+__global__ __launch_bounds__(kPwThreads) void make_r_kernel(PwParams P, MakeRArgs A)
+{
+    const long long N = P.N;
+    GRID_STRIDE(i, N)
+    {
+        const double2 s1 = A.psi[i], s2 = A.psi[N + i];
+        double2 r1, r2;
+        if (A.rin) {
+            r1 = A.rin[i];
+            r2 = A.rin[N + i];
+        } else {
+            const double2 h1 = A.hpsi[i], h2 = A.hpsi[N + i];
+            r1 = make_double2(h1.x - A.mu[0] * s1.x, h1.y - A.mu[0] * s1.y);
+            r2 = make_double2(h2.x - A.mu[1] * s2.x, h2.y - A.mu[1] * s2.y);
+        }
+        if (A.apply_pv) {
+            const double n1 = sq2(s1), n2 = sq2(s2);
+            const double V = trap_at(P, i);
+            const double2 ml = A.aux[N + i];
+            double g1 = A.diag_shift[0] + V + P.G[0][0] * n1 + P.G[0][1] * n2 + ml.x;
+            double g2 = A.diag_shift[1] + V + P.G[1][0] * n1 + P.G[1][1] * n2 + ml.y;
+            g1 = 1.0 / ((g1 > 0.0 ? g1 : 0.0) + A.sigma);
+            g2 = 1.0 / ((g2 > 0.0 ? g2 : 0.0) + A.sigma);
+            r1 = make_double2(g1 * r1.x, g1 * r1.y);
+            r2 = make_double2(g2 * r2.x, g2 * r2.y);
+        }
+        A.out[i] = r1;
+        A.out[N + i] = r2;
+    }
+}
+
+__global__ __launch_bounds__(kPwThreads) void param_grad_kernel(PwParams P, ParamGradArgs A)
+{
+    const long long N = P.N;
+    double acc[kParamSums];
+#pragma unroll
+    for (int m = 0; m < kParamSums; ++m) acc[m] = 0.0;
+    GRID_STRIDE(i, N)
+    {
+        const double n1 = sq2(A.psi[i]), n2 = sq2(A.psi[N + i]);
+        for (int q = 0; q < P.n_u; ++q) {
+            const double* nd = P.nodes + q * kNodeStride;
+            const double e11 = nd[0], e22 = nd[1], p12 = nd[2], w = nd[3];
+            const double e12 = nd[4], e21 = nd[5], au = nd[6];
+            const double delta = e11 * n1 - e22 * n2;
+            const double s = sqrt(delta * delta + 4.0 * p12 * n1 * n2);
+            const double inv = s > 0.0 ? 1.0 / s : 0.0;
+            const double base = e11 * n1 + e22 * n2;
+            // dV_+-/d eta_11, eta_12, eta_21, eta_22 = (n1, 0, 0, n2) +- g
+            const double g0 = delta * n1 * inv, g1 = 2.0 * e21 * n1 * n2 * inv;
+            const double g2 = 2.0 * e12 * n1 * n2 * inv, g3 = -delta * n2 * inv;
+#pragma unroll
+            for (int br = 0; br < 2; ++br) {
+                const double sg = br == 0 ? 1.0 : -1.0;
+                const double V = base + sg * s;
+                if (V <= 0.0) continue;
+                const double v32 = V * sqrt(V);
+                const double f = 2.5 * w * v32;
+                const double dv[4] = {n1 + sg * g0, sg * g1, sg * g2, n2 + sg * g3};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    acc[c] += f * dv[c];
+                    acc[4 + c] += f * dv[c] * au;
+                }
+                acc[8] += w * V * v32;
+            }
+        }
+    }
+    block_reduce_store<kParamSums>(acc, A.partials, gridDim.x);
+}
+
+__global__ __launch_bounds__(kPwThreads) void norm2_kernel(PwParams P, const double2* f, double* partials)
+{
+    const long long N = P.N;
+    double acc[2] = {0.0, 0.0};
+    GRID_STRIDE(i, N)
+    {
+        acc[0] += sq2(f[i]);
+        acc[1] += sq2(f[N + i]);
+    }
+    block_reduce_store<2>(acc, partials, gridDim.x);
+}
+
+__global__ __launch_bounds__(kPwThreads) void scale2_kernel(PwParams P, const double2* in, double2* out,
+                                                            double s0, double s1)
+{
+    const long long N = P.N;
+    GRID_STRIDE(i, N)
+    {
+        const double2 a = in[i], b = in[N + i];
+        out[i] = make_double2(s0 * a.x, s0 * a.y);
+        out[N + i] = make_double2(s1 * b.x, s1 * b.y);
+    }
+}
+
+__global__ __launch_bounds__(kPwThreads) void grad_kernel(PwParams P, const double2* psi, const double2* hpsi,
+                                                          double2* out, double mu0, double mu1, double s0,
+                                                          double s1, int projected)
+{
+    const long long N = P.N;
+    GRID_STRIDE(i, N)
+    {
+        const double2 a = psi[i], b = psi[N + i], ha = hpsi[i], hb = hpsi[N + i];
+        const double m0 = projected ? mu0 : 0.0, m1 = projected ? mu1 : 0.0;
+        out[i] = make_double2(s0 * (ha.x - m0 * a.x), s0 * (ha.y - m0 * a.y));
+        out[N + i] = make_double2(s1 * (hb.x - m1 * b.x), s1 * (hb.y - m1 * b.y));
+    }
+}
+
+__global__ __launch_bounds__(256) void reduce_final_kernel(const double* partials, int nblk, int M, double* out)
+{
+    __shared__ double sh[4];
+    for (int m = 0; m < M; ++m) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += 256) s += partials[(long long)m * nblk + b];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) out[m] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    }
+}
+
+int pw_blocks(long long N)
+{
+    long long b = (N + kPwThreads - 1) / kPwThreads;
+    return (int)(b < kPwMaxBlocks ? b : kPwMaxBlocks);
+}
+
+}  // namespace
+
+hipError_t launch_trial(const PwParams& P, const TrialArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(trial_kernel, dim3(pw_blocks(P.N)), dim3(kPwThreads), 0, s, P, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_heval_epi(const PwParams& P, const HevalArgs& a, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(heval_epi_kernel, dim3(nblk), dim3(kPwThreads), 0, s, P, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dir_reduce(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(dir_reduce_kernel, dim3(nblk), dim3(kPwThreads), 0, s, P, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dir_write(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(dir_write_kernel, dim3(nblk), dim3(kPwThreads), 0, s, P, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ls_epi(const PwParams& P, const LsEpiArgs& a, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(ls_epi_kernel, dim3(nblk), dim3(kPwThreads), 0, s, P, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_r(const PwParams& P, const MakeRArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(make_r_kernel, dim3(pw_blocks(P.N)), dim3(kPwThreads), 0, s, P, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_param_grad(const PwParams& P, const ParamGradArgs& a, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(param_grad_kernel, dim3(nblk), dim3(kPwThreads), 0, s, P, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm2(const PwParams& P, const double2* f, double* partials, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(norm2_kernel, dim3(nblk), dim3(kPwThreads), 0, s, P, f, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale2(const PwParams& P, const double2* in, double2* out, double s0, double s1,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(scale2_kernel, dim3(pw_blocks(P.N)), dim3(kPwThreads), 0, s, P, in, out, s0, s1);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hpsi, double2* out,
+                       double mu0, double mu1, double s0, double s1, int projected, hipStream_t s)
+{
+    hipLaunchKernelGGL(grad_kernel, dim3(pw_blocks(P.N)), dim3(kPwThreads), 0, s, P, psi, hpsi, out, mu0,
+                       mu1, s0, s1, projected);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_final(const double* partials, int nblk, int M, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, s, partials, nblk, M, out);
+    return hipGetLastError();
+}
+
+}  // namespace bec

@@ -1,0 +1,310 @@
+"""Parity of the HIP path (called through the C ABI) against the FP64 CPU oracle.
+
+Same seeded inputs on both sides.  Bars (derived from FP64 arithmetic):
+energy terms relative 1e-12 at a given state, fields (H psi, gradients,
+preconditioned residuals) relative 1e-11 in max norm, FFT relative 1e-13; at
+convergence E* relative 1e-10, max |n_gpu - n_oracle| 1e-7, both |grad E| below
+the tolerance.
+"""
+import numpy as np
+import pytest
+
+from paper_2510_24543_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def solver():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2510_24543_amd import solver as s
+    return s
+
+
+def dvol(grid):
+    return float(np.prod([(grid["hi"][d] - grid["lo"][d]) / grid["n"][d] for d in range(3)]))
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+def small_params(**kw):
+    p = {"N": [1.0, 1.0], "omega": [1.0, 1.2, 2.6], "G": [[100.0, 50.0], [50.0, 90.0]],
+         "Gdd": [[60.0, 45.0], [45.0, 50.0]], "c_lhy": 5.0, "r_cut": 6.0, "n_u": 16}
+    p.update(kw)
+    return p
+
+
+# ---------------------------------------------------------------- FFT
+FFT_SHAPES = [(8, 8, 8), (16, 32, 8), (32, 32, 32), (48, 64, 96), (96, 48, 16), (128, 8, 16),
+              (8, 16, 256), (256, 16, 8), (64, 128, 32)]
+
+
+@pytest.mark.parametrize("shape", FFT_SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_fft3d_matches_numpy(solver, orc, shape):
+    grid = {"n": list(shape), "lo": [-1.0] * 3, "hi": [1.0] * 3}
+    ctx = solver.Context(grid, small_params())
+    rng = np.random.default_rng(sum(shape))
+    for nf in (1, 3):
+        a = rng.standard_normal((nf, *shape)) + 1j * rng.standard_normal((nf, *shape))
+        t = torch.from_numpy(a).cuda()
+        fwd = ctx.fft3d(t, -1).cpu().numpy()
+        ref = np.fft.fftn(a, axes=(1, 2, 3))
+        assert rel(fwd, ref) < 1e-13 * np.log2(np.prod(shape))
+        inv = ctx.fft3d(torch.from_numpy(ref).cuda(), +1).cpu().numpy()
+        assert rel(inv, a) < 1e-13 * np.log2(np.prod(shape))
+    if np.prod(shape) <= 8 * 8 * 8:
+        assert rel(fwd, orc.fft3d(a, -1)) < 1e-13
+
+
+def test_fft3d_in_place(solver):
+    grid = {"n": [32, 48, 64], "lo": [-1.0] * 3, "hi": [1.0] * 3}
+    ctx = solver.Context(grid, small_params())
+    a = inputs.random_field(grid, 3)
+    t = torch.from_numpy(a).cuda()
+    out = t.clone()
+    solver.B.check(solver.B.lib().bec_fft3d(ctx._ctx, solver._ptr(out), solver._ptr(out), 2, -1), "fft")
+    torch.cuda.synchronize()
+    assert rel(out.cpu().numpy(), np.fft.fftn(a, axes=(1, 2, 3))) < 1e-13 * 17
+
+
+# ---------------------------------------------------------------- energy / H psi / gradient
+CASES = {
+    "C1a": (inputs.CONFIGS["C1a"]["grid"], inputs.CONFIGS["C1a"]["params"]),
+    "C1b": (inputs.CONFIGS["C1b"]["grid"], inputs.CONFIGS["C1b"]["params"]),
+    "C2": (inputs.CONFIGS["C2"]["grid"], inputs.CONFIGS["C2"]["params"]),
+    "mixedN": ({"n": [16, 32, 48], "lo": [-6, -6, -6], "hi": [6, 6, 6]},
+               small_params(N=[1.0, 1.6], G=[[100.0, 50.0], [31.25, 90.0]], Gdd=[[60.0, 45.0], [28.125, 50.0]])),
+    "nu1_noLHY": ({"n": [32, 16, 8], "lo": [-6, -5, -4], "hi": [6, 5, 4]}, small_params(n_u=1, c_lhy=0.0)),
+    "decoupled": ({"n": [16, 16, 16], "lo": [-6, -6, -6], "hi": [6, 6, 6]},
+                  small_params(G=[[100.0, 0.0], [0.0, 90.0]], Gdd=[[0.0, 0.0], [0.0, 0.0]])),
+}
+
+
+def _state(grid, params, seed, phase):
+    return inputs.initial_state(grid, params["omega"], seed, phase=phase)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("phase", [False, True], ids=["real", "complex"])
+def test_energy_and_hamiltonian(solver, orc, case, phase):
+    grid, params = CASES[case]
+    psi = _state(grid, params, 11, phase)
+    ctx = solver.Context(grid, params)
+    h, t = ctx.hamiltonian(torch.from_numpy(psi))
+    to, ho, _, _ = orc.heval(grid, params, psi)
+    for k in ("E", "E_lhy"):
+        assert abs(t[k] - to[k]) <= 1e-12 * max(abs(to["E"]), 1e-300), k
+    for k in ("E_kin", "E_trap", "mu", "shift", "norm2", "res"):
+        for i in range(2):
+            assert abs(t[k][i] - to[k][i]) <= 1e-12 * max(abs(to[k][i]), 1e-12), (k, i)
+    for k in ("E_c", "E_dd"):
+        for i in range(2):
+            for j in range(2):
+                assert abs(t[k][i][j] - to[k][i][j]) <= 1e-12 * abs(to["E"]), (k, i, j)
+    assert rel(h.cpu().numpy(), ho) < 1e-11
+
+
+@pytest.mark.parametrize("case", ["C1b", "mixedN"])
+def test_gradient(solver, orc, case):
+    grid, params = CASES[case]
+    psi = _state(grid, params, 12, True)
+    ctx = solver.Context(grid, params)
+    to, ho, _, _ = orc.heval(grid, params, psi)
+    dV = dvol(grid)
+    for projected in (False, True):
+        g, _ = ctx.gradient(torch.from_numpy(psi), projected=projected)
+        ref = np.stack([2 * params["N"][i] * dV * (ho[i] - (to["mu"][i] * psi[i] if projected else 0))
+                        for i in range(2)])
+        assert rel(g.cpu().numpy(), ref) < 1e-11
+
+
+def test_energy_is_bitwise_repeatable(solver):
+    grid, params = CASES["C1b"]
+    psi = torch.from_numpy(_state(grid, params, 13, True)).cuda()
+    ctx = solver.Context(grid, params)
+    a = ctx.energy(psi)
+    b = ctx.energy(psi)
+    assert a == b
+
+
+# ---------------------------------------------------------------- preconditioners
+@pytest.mark.parametrize("pc", [0, 1, 2, 3])
+def test_preconditioners(solver, orc, pc):
+    grid, params = CASES["C1b"]
+    psi = _state(grid, params, 14, True)
+    r = inputs.random_field(grid, 15)
+    ctx = solver.Context(grid, params)
+    z = ctx.precond(pc, torch.from_numpy(psi), torch.from_numpy(r), sigma=1e-6).cpu().numpy()
+    zo = orc.precond(grid, params, pc, 1e-6, psi, r)
+    assert rel(z, zo) < 1e-12
+
+
+# ---------------------------------------------------------------- line search
+def _tangent(grid, d, psi):
+    dV = dvol(grid)
+    return np.array([d[i] - dV * np.sum(np.real(np.conj(d[i]) * psi[i])) * psi[i] for i in range(2)])
+
+
+@pytest.mark.parametrize("case", ["C1b", "C2", "mixedN"])
+@pytest.mark.parametrize("kind", ["random", "descent"])
+def test_linesearch_model_and_step(solver, orc, case, kind):
+    """random: a rough direction (model parity, including E1 > 0 / E2 < 0 and
+    the fallback step); descent: minus the residual plus a smooth perturbation."""
+    grid, params = CASES[case]
+    psi = _state(grid, params, 16, True)
+    psi_n = psi / np.sqrt(dvol(grid) * np.sum(np.abs(psi) ** 2, axis=(1, 2, 3)))[:, None, None, None]
+    X = np.meshgrid(*inputs.coords(grid), indexing="ij")
+    env = np.exp(-0.1 * (X[0] ** 2 + X[1] ** 2 + X[2] ** 2))
+    d = inputs.random_field(grid, 17) * env[None]
+    if kind == "random":
+        d = 0.3 * d
+    else:
+        to, ho, _, _ = orc.heval(grid, params, psi_n)
+        r = np.stack([ho[i] - to["mu"][i] * psi_n[i] for i in range(2)])
+        d = -r + 0.01 * d
+    ctx = solver.Context(grid, params)
+    out, rep = ctx.linesearch(torch.from_numpy(psi), torch.from_numpy(d),
+                              {"max_backtrack": 30, "tau_rel": 1e-14})
+    p = _tangent(grid, d, psi_n)
+    m = orc.model(grid, params, psi_n, p)
+    assert abs(rep["E1"] - m["E1"]) <= 1e-10 * abs(m["E1"])
+    assert abs(rep["E2"] - m["E2"]) <= 1e-10 * abs(m["E2"])
+    for i in range(2):
+        assert abs(rep["pnorm"][i] - m[f"pnorm_{i + 1}"]) <= 1e-12 * m[f"pnorm_{i + 1}"]
+    ref = orc.geodesic(grid, psi_n, p, rep["alpha"])
+    assert rel(out.cpu().numpy(), ref) < 1e-11
+    E_new = orc.heval(grid, params, ref)[0]["E"]
+    assert abs(rep["E_new"] - E_new) <= 1e-12 * abs(E_new)
+    if kind == "descent":
+        assert rep["status"] == "OK" and m["E1"] < 0 and rep["E_new"] < rep["E0"]
+
+
+# ---------------------------------------------------------------- parameter derivatives
+@pytest.mark.parametrize("case", ["C1b", "mixedN", "C2"])
+def test_param_grad(solver, orc, case):
+    grid, params = CASES[case]
+    psi = _state(grid, params, 18, True)
+    ctx = solver.Context(grid, params)
+    g = ctx.param_grad(torch.from_numpy(psi))
+    go = orc.param_grad(grid, params, psi)
+    for k in ("dG", "dGdd"):
+        assert np.max(np.abs(g[k] - go[k])) <= 1e-11 * np.max(np.abs(go[k])), k
+    assert abs(g["dc_lhy"] - go["dc_lhy"]) <= 1e-12 * abs(go["dc_lhy"])
+
+
+# ---------------------------------------------------------------- full solves
+SOLVE_CASES = [("C1a", 1), ("C1b", 1), ("C1b", 0), ("C1b", 2), ("C1b", 3)]
+
+
+@pytest.mark.parametrize("name,pc", SOLVE_CASES, ids=[f"{n}-pc{p}" for n, p in SOLVE_CASES])
+def test_solve_matches_oracle(solver, orc, name, pc):
+    c = inputs.CONFIGS[name]
+    grid, params = c["grid"], c["params"]
+    psi0 = inputs.config_state(name)
+    opts = {"tol_grad": 1e-10, "pc": pc, "max_iter": 3000}
+    ctx = solver.Context(grid, params)
+    psi, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=3000)
+    psio, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=3000)
+    assert rep["status"] == "OK" and repo["status"] == "OK"
+    assert max(rep["final"]["res"]) < 1e-10
+    assert abs(rep["final"]["E"] - repo["final"]["E"]) <= 1e-10 * abs(repo["final"]["E"])
+    n_g = np.abs(psi.cpu().numpy()) ** 2
+    n_o = np.abs(psio) ** 2
+    assert np.max(np.abs(n_g - n_o)) < 1e-7
+    # the trajectories agree step by step while round-off has not accumulated
+    for a, b in zip(log[:10], logo[:10]):
+        assert abs(a["E"] - b["E"]) <= 1e-11 * abs(b["E"])
+        assert abs(a["alpha"] - b["alpha"]) <= 1e-8 * abs(b["alpha"])
+    E = [l["E"] for l in log]
+    assert all(b <= a + 1e-14 * abs(a) for a, b in zip(E, E[1:]))
+
+
+def test_solve_c2_droplet(solver):
+    """64^3 droplet regime (eps_dd > 1: clipped LHY branches).  The oracle's
+    converged state is stored by tests/golden/make_golden.py (a full oracle
+    solve takes minutes); compared on the energy and on seeded density samples."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_solve.json")
+    ref = json.load(open(path))
+    c = inputs.CONFIGS["C2"]
+    grid, params = c["grid"], c["params"]
+    psi0 = inputs.config_state("C2")
+    opts = {"tol_grad": 1e-10, "pc": 1, "max_iter": 5000}
+    ctx = solver.Context(grid, params)
+    psi, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=5000)
+    assert rep["status"] == "OK" and ref["status"] == "OK"
+    assert max(rep["final"]["res"]) < 1e-10
+    assert abs(rep["final"]["E"] - ref["final"]["E"]) <= 1e-10 * abs(ref["final"]["E"])
+    n = np.abs(psi.cpu().numpy()) ** 2
+    idx = tuple(ref["sample_idx"])
+    for i in range(2):
+        assert np.max(np.abs(n[i][idx] - np.array(ref["n_samples"][i]))) < 1e-7
+        assert abs(n[i][tuple(ref["peak_idx"][i])] - ref["n_peak"][i]) < 1e-7
+    for a, b in zip(log[:10], ref["E_first10"]):
+        assert abs(a["E"] - b) <= 1e-11 * abs(b)
+
+
+# ---------------------------------------------------------------- full size, sampled
+@pytest.mark.timeout(900)
+def test_headline_grid_first_iterations(solver, orc):
+    """128^3 x 2 (the benchmark workload): energy terms of the seeded state and the
+    first three accepted steps against the oracle."""
+    c = inputs.CONFIGS["M"]
+    grid, params = c["grid"], c["params"]
+    psi0 = inputs.config_state("M")
+    ctx = solver.Context(grid, params)
+    t = ctx.energy(torch.from_numpy(psi0))
+    to = orc.heval(grid, params, psi0)[0]
+    assert abs(t["E"] - to["E"]) <= 1e-12 * abs(to["E"])
+    opts = {"tol_grad": 0.0, "max_iter": 3}
+    psi, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=3)
+    psio, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=3)
+    assert rep["iters"] == repo["iters"] == 3
+    for a, b in zip(log, logo):
+        assert abs(a["E"] - b["E"]) <= 1e-11 * abs(b["E"])
+    # sampled points of the state after three steps
+    rng = np.random.default_rng(5)
+    idx = tuple(rng.integers(0, n, 4096) for n in grid["n"])
+    g = psi.cpu().numpy()
+    for i in range(2):
+        assert np.max(np.abs(g[i][idx] - psio[i][idx])) <= 1e-10 * np.max(np.abs(psio[i]))
+
+
+# ---------------------------------------------------------------- errors and edge cases
+def test_errors_are_reported(solver):
+    B = solver.B
+    with pytest.raises(B.BecError, match="EUNSUPPORTED"):
+        solver.Context({"n": [30, 32, 32], "lo": [-1] * 3, "hi": [1] * 3}, small_params())
+    with pytest.raises(B.BecError, match="EINVAL"):
+        solver.Context({"n": [32, 32, 32], "lo": [1] * 3, "hi": [-1] * 3}, small_params())
+    with pytest.raises(B.BecError, match="EINVAL"):
+        solver.Context({"n": [32, 32, 32], "lo": [-1] * 3, "hi": [1] * 3}, small_params(n_u=0))
+    with pytest.raises(B.BecError, match="EINVAL"):
+        solver.Context({"n": [32, 32, 32], "lo": [-1] * 3, "hi": [1] * 3},
+                       small_params(G=[[1.0, 2.0], [3.0, 1.0]]))
+    grid, params = CASES["C1b"]
+    ctx = solver.Context(grid, params)
+    bad = torch.from_numpy(_state(grid, params, 19, False)).cuda()
+    bad[0, 3, 3, 3] = float("nan")
+    with pytest.raises(B.BecError, match="ENONFINITE"):
+        ctx.energy(bad)
+    with pytest.raises(ValueError):
+        ctx.energy(torch.zeros((2, 8, 8, 8), dtype=torch.complex128, device="cuda"))
+
+
+def test_workspace_too_small(solver):
+    import ctypes as C
+    B = solver.B
+    grid, params = CASES["C1b"]
+    g, p = B.make_grid(grid), B.make_params(params)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    out = C.c_void_p()
+    st = B.lib().bec_create(C.byref(g), C.byref(p), None, C.c_void_p(ws.data_ptr()), C.c_size_t(1 << 20),
+                            C.byref(out))
+    assert st == 2
