@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark of the preconditioned nonlinear CG hot path on one MI355X.
+
+Workload: 128^3 grid x 2 components (box [-8,8)^3, trap (1,1,2.6), g11 = g22 = 100,
+g12 = 50, gdd = 60 for all pairs, LHY coefficient 5, dipolar cutoff 8), FP64 /
+complex128, seeded Gaussian + noise start, P_V preconditioner, HS+ conjugacy.
+
+A step is one accepted PCG iteration (Hamiltonian at the trial point, residual,
+preconditioner, conjugacy, projected direction, line-search model with its
+FFTs, geodesic trial).  W warm-up steps run untimed, then exactly K steps are
+timed with HIP events on the library's stream, bracketed by device syncs.  The
+timed call is one bec_solve of K steps from the seeded start, so it includes
+one initial normalisation + Hamiltonian evaluation (about a third of a step).
+
+Also reported: time to max_i ||H_i psi_i - mu_i psi_i|| < 1e-8 from the seeded
+start, per-kernel event timings of a short profiled solve (the roofline entry
+is the kernel with the largest total time), and the CPU oracle timed on the
+host cores on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("PCG iter/s and time-to-|∇E|<1e-8 at 128³×2; HBM GB/s vs peak; "
+          "batched vs plain")
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "M"
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel calibration),
+    or None when no summary for this kernel exists."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_128cubed.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        return data["kernels"][kernel]["bytes_per_launch"]
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(grid, params, psi0, sample_iters: int):
+    """The oracle as it stands, on the host cores: rate = sample_iters / (t(1 + s) - t(1))."""
+    import oracle
+    opts = {"tol_grad": 0.0}
+    t0 = time.perf_counter()
+    oracle.solve(grid, params, psi0, dict(opts, max_iter=1))
+    t1 = time.perf_counter()
+    _, rep, _ = oracle.solve(grid, params, psi0, dict(opts, max_iter=1 + sample_iters))
+    t2 = time.perf_counter()
+    dt = (t2 - t1) - (t1 - t0)
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    return {"value": (rep["iters"] - 1) / dt, "unit": "iter/s", "cores": cores, "kind": "oracle",
+            "sample": f"{sample_iters} PCG iterations of the same 128^3 x 2 workload from the seeded "
+                      f"start (rate from the difference of a 1-step and a {1 + sample_iters}-step "
+                      f"oracle solve, {t2 - t0:.1f} s of CPU work)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=5, help="oracle iterations for the CPU baseline (0: skip)")
+    ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution solve")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU decomposition is a design note, "
+              "not code (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_24543_amd import inputs, solver
+
+    cfg = inputs.CONFIGS[WORKLOAD]
+    grid, params = cfg["grid"], cfg["params"]
+    psi0_np = inputs.config_state(WORKLOAD)
+    dev = torch.device("cuda:0")
+    ctx = solver.Context(grid, params, dev)
+    psi0 = torch.from_numpy(psi0_np).to(dev)
+    base_opts = {"pc": 1, "beta": 0, "restart_period": 50, "sigma": 1e-6}
+
+    # warm-up (untimed)
+    if args.warmup > 0:
+        ctx.solve(psi0, dict(base_opts, max_iter=args.warmup, tol_grad=0.0))
+    torch.cuda.synchronize()
+
+    # timed: exactly K steps
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(ctx.stream)
+    _, rep, _ = ctx.solve(psi0, dict(base_opts, max_iter=args.steps, tol_grad=0.0))
+    ev1.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    steps_done = rep["iters"]
+    ms_per_step = ms / max(steps_done, 1)
+    value = 1000.0 * steps_done / ms
+
+    # time to |grad E| < 1e-8 from the seeded start
+    tts = None
+    if not args.no_tts:
+        torch.cuda.synchronize()
+        ev0.record(ctx.stream)
+        _, trep, _ = ctx.solve(psi0, dict(base_opts, max_iter=5000, tol_grad=1e-8))
+        ev1.record(ctx.stream)
+        torch.cuda.synchronize()
+        tts = {"seconds": ev0.elapsed_time(ev1) / 1000.0, "iters": trep["iters"], "status": trep["status"],
+               "E_star": trep["final"]["E"], "res_max": max(trep["final"]["res"]),
+               "backtracks": trep["n_backtracks"], "restarts": trep["n_restarts"]}
+
+    # per-kernel timings (HIP events on the library stream) over a short solve
+    ctx.profile(True)
+    ctx.solve(psi0, dict(base_opts, max_iter=5, tol_grad=0.0))
+    stats = ctx.kernel_stats()
+    ctx.profile(False)
+    tot = sum(s["total_ms"] for s in stats)
+    kernels = sorted(({"name": s["name"], "launches": s["launches"],
+                       "avg_us": 1000.0 * s["total_ms"] / max(s["launches"], 1),
+                       "share": s["total_ms"] / tot if tot else 0.0,
+                       "GB_per_s": s["total_bytes"] / (s["total_ms"] * 1e6) if s["total_ms"] else 0.0,
+                       "bytes_per_launch": s["total_bytes"] / max(s["launches"], 1)} for s in stats),
+                     key=lambda k: -k["share"])
+    dom = kernels[0]
+    traffic = traffic_from_profiles(dom["name"])
+    roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(dom["GB_per_s"], 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["GB_per_s"] / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "avg_us": round(dom["avg_us"], 2),
+                "bytes_per_launch": dom["bytes_per_launch"]}
+
+    cpu = None
+    if args.cpu_sample > 0:
+        cpu = cpu_baseline(grid, params, psi0_np, args.cpu_sample)
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "iter/s", "n_gpus": 1,
+        "steps": steps_done, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "128^3 grid x 2 components, box [-8,8)^3, trap (1,1,2.6), g11=g22=100, "
+                               "g12=50, gdd=60 all pairs, LHY 5, cutoff 8, seeded Gaussian+noise start, "
+                               "P_V + HS+ (restart 50), FP64",
+                   "grid": grid["n"], "points": ctx.N, "components": 2},
+        "time_to_solution": tts,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in kk.items()} for kk in kernels],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -195,6 +195,25 @@ bec_status bec_solve(bec_ctx* ctx, double* psi_inout, const bec_opts* opts, bec_
 bec_status bec_param_grad(bec_ctx* ctx, const double* psi, double dG[2][2], double dGdd[2][2],
                           double* dc_lhy);
 
+/* Per-kernel timing statistics (see bec_profile_enable). */
+typedef struct {
+    char name[40];          /* kernel class, e.g. "fft_y_fwd", "heval_epilogue"  */
+    int64_t launches;
+    double total_ms;        /* sum of event-measured launch durations          */
+    double total_bytes;     /* algorithmic HBM bytes of those launches: every
+                               operand read once, every result written once   */
+} bec_kernel_stat;
+
+/* Start (on = 1, clearing earlier statistics) or stop (on = 0) per-kernel
+ * timing.  While on, every launch of the context is bracketed by HIP events
+ * recorded on the context stream; this adds a few microseconds per launch,
+ * so timed runs keep it off. */
+bec_status bec_profile_enable(bec_ctx* ctx, int32_t on);
+
+/* Copy up to cap kernel statistics into out_h (host) and their number into
+ * n_out.  Synchronises the context stream. */
+bec_status bec_profile_read(bec_ctx* ctx, bec_kernel_stat* out_h, int32_t cap, int32_t* n_out);
+
 /* Gauss-Legendre nodes u[0..n) and weights w[0..n) on [0,1] used for the LHY
  * u integral (host memory, caller-owned, n in 1..64).  Host-only: needs no GPU. */
 bec_status bec_gauss_legendre(int32_t n, double* u, double* w);

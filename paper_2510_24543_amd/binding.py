@@ -67,6 +67,11 @@ class Report(C.Structure):
                 ("status", C.c_int32), ("final", Terms), ("seconds", C.c_double)]
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("total_bytes", C.c_double)]
+
+
 # (name, restype, argtypes) of every entry point declared in include/bec.h
 _VP, _DP, _I32, _DBL = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_double
 _D22 = (C.c_double * 2) * 2
@@ -83,6 +88,8 @@ SIGNATURES = [
     ("bec_linesearch", C.c_int, [_VP, _VP, _VP, _VP, C.POINTER(Opts), C.POINTER(LsReport)]),
     ("bec_solve", C.c_int, [_VP, _VP, C.POINTER(Opts), C.POINTER(Report), C.POINTER(Iter), _I32]),
     ("bec_param_grad", C.c_int, [_VP, _VP, C.POINTER(_D22), C.POINTER(_D22), _DP]),
+    ("bec_profile_enable", C.c_int, [_VP, _I32]),
+    ("bec_profile_read", C.c_int, [_VP, C.POINTER(KernelStat), _I32, C.POINTER(_I32)]),
     ("bec_gauss_legendre", C.c_int, [_I32, _DP, _DP]),
     ("bec_last_error", C.c_char_p, []),
 ]

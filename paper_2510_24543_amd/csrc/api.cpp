@@ -146,6 +146,23 @@ long double cutoff_factor(long double q)
     return s;
 }
 
+// Optional per-kernel timing: HIP events recorded on the context stream around
+// every launch, resolved when the statistics are read.
+struct Prof {
+    bool on = false;
+    struct Rec {
+        int id;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<Rec> recs;
+    std::vector<std::string> names;
+    std::vector<long long> launches;
+    std::vector<double> total_ms, total_bytes;
+};
+
 }  // namespace
 
 struct bec_ctx {
@@ -164,10 +181,70 @@ struct bec_ctx {
     int nblk_pw = 0;
     int nblk_x = 0;
     PwParams P{};
-    double last_mLn[2] = {0, 0};
+    Prof prof;
 };
 
 namespace {
+
+hipEvent_t prof_event(bec_ctx* c)
+{
+    Prof& P = c->prof;
+    if (P.used == P.pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        P.pool.push_back(e);
+    }
+    return P.pool[P.used++];
+}
+
+int prof_id(bec_ctx* c, const char* name)
+{
+    Prof& P = c->prof;
+    for (size_t i = 0; i < P.names.size(); ++i)
+        if (P.names[i] == name) return (int)i;
+    P.names.emplace_back(name);
+    P.launches.push_back(0);
+    P.total_ms.push_back(0.0);
+    P.total_bytes.push_back(0.0);
+    return (int)P.names.size() - 1;
+}
+
+// resolve recorded event pairs into the per-kernel totals (synchronises)
+bec_status prof_flush(bec_ctx* c)
+{
+    Prof& P = c->prof;
+    if (P.recs.empty()) return BEC_OK;
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (const auto& r : P.recs) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        P.launches[r.id] += 1;
+        P.total_ms[r.id] += ms;
+        P.total_bytes[r.id] += r.bytes;
+    }
+    P.recs.clear();
+    P.used = 0;
+    return BEC_OK;
+}
+
+// launch `call` (a hipError_t expression); when profiling, bracket it with events
+#define LAUNCH(c, name, bytes, call)                                                   \
+    do {                                                                               \
+        hipEvent_t e0_ = nullptr;                                                      \
+        if ((c)->prof.on) {                                                            \
+            if ((c)->prof.used + 2 > 8192) STCHK(prof_flush(c));                       \
+            e0_ = prof_event(c);                                                       \
+            if (e0_) HIPCHK(hipEventRecord(e0_, (c)->st));                             \
+        }                                                                              \
+        HIPCHK(call);                                                                  \
+        if ((c)->prof.on && e0_) {                                                     \
+            hipEvent_t e1_ = prof_event(c);                                            \
+            if (e1_) {                                                                 \
+                HIPCHK(hipEventRecord(e1_, (c)->st));                                  \
+                (c)->prof.recs.push_back({prof_id(c, name), e0_, e1_, (double)(bytes)}); \
+            }                                                                          \
+        }                                                                              \
+    } while (0)
 
 size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
 {
@@ -349,7 +426,15 @@ bec_status run_pass(bec_ctx* c, int axis, const double2* const* src, double2* co
         if (ops) A.op[f] = ops[f];
         if (prec_a) A.prec_a[f] = prec_a[f];
     }
-    HIPCHK(bec::fft_pass(c->n[axis], axis == 2, A, c->st));
+    // algorithmic bytes: every field read once and (unless a Parseval field) written once
+    double bytes = 0.0;
+    const char* name = "fft";
+    for (int f = 0; f < nf; ++f) bytes += (double)c->N * ((ops && ops[f] == bec::kOpParseval) ? 16.0 : 32.0);
+    if (ops) name = "fft_x_kspace";
+    else if (axis == 2) name = sign < 0 ? "fft_z_fwd" : "fft_z_inv";
+    else if (axis == 1) name = sign < 0 ? "fft_y_fwd" : "fft_y_inv";
+    else name = sign < 0 ? "fft_x_fwd" : "fft_x_inv";
+    LAUNCH(c, name, bytes, bec::fft_pass(c->n[axis], axis == 2, A, c->st));
     return BEC_OK;
 }
 
@@ -396,7 +481,7 @@ bec_status fetch(bec_ctx* c, int M)
 
 bec_status reduce_pw(bec_ctx* c, int M, int out_off)
 {
-    HIPCHK(bec::launch_reduce_final(c->partials, c->nblk_pw, M, c->scal + out_off, c->st));
+    LAUNCH(c, "reduce_final", 8.0 * M * c->nblk_pw, bec::launch_reduce_final(c->partials, c->nblk_pw, M, c->scal + out_off, c->st));
     return BEC_OK;
 }
 
@@ -421,7 +506,7 @@ bec_status heval(bec_ctx* c, const double2* src, const double2* p, const double 
     }
     ta.psi_dst = c->psi[set];
     ta.dens = c->W + 2 * N;
-    HIPCHK(bec::launch_trial(c->P, ta, c->st));
+    LAUNCH(c, "trial_pack", (double)c->N * (p ? 112.0 : 80.0), bec::launch_trial(c->P, ta, c->st));
     const double2* fsrc[3] = {c->psi[set], c->psi[set] + N, c->W + 2 * N};
     double2* fdst[3] = {c->W, c->W + N, c->W + 2 * N};
     const int ops[3] = {bec::kOpMulKin, bec::kOpMulKin, bec::kOpMulDip};
@@ -433,7 +518,7 @@ bec_status heval(bec_ctx* c, const double2* src, const double2* p, const double 
     ha.hpsi = c->hpsi[set];
     ha.aux = c->aux[set];
     ha.partials = c->partials;
-    HIPCHK(bec::launch_heval_epi(c->P, ha, c->nblk_pw, c->st));
+    LAUNCH(c, "heval_epilogue", (double)c->N * 144.0, bec::launch_heval_epi(c->P, ha, c->nblk_pw, c->st));
     STCHK(reduce_pw(c, bec::kHevalSums, 0));
     STCHK(fetch(c, bec::kHevalSums));
     const double* S = c->host;
@@ -493,7 +578,8 @@ bec::DirArgs dir_args(bec_ctx* c, int set, const Eval& ev, int zmode, double sig
 // Direction reduce pass: returns the 12 sums (see kDirReduceSums).
 bec_status dir_reduce(bec_ctx* c, const bec::DirArgs& A, double* R)
 {
-    HIPCHK(bec::launch_dir_reduce(c->P, A, c->nblk_pw, c->st));
+    const double rb = 64.0 + (A.zmode == 1 ? 16.0 : 0.0) + (A.zmode == 2 ? 32.0 : 0.0) + (A.have_prev ? 64.0 : 0.0);
+    LAUNCH(c, "dir_reduce", (double)c->N * rb, bec::launch_dir_reduce(c->P, A, c->nblk_pw, c->st));
     STCHK(reduce_pw(c, bec::kDirReduceSums, 0));
     STCHK(fetch(c, bec::kDirReduceSums));
     std::memcpy(R, c->host, bec::kDirReduceSums * sizeof(double));
@@ -515,7 +601,7 @@ bec_status compute_z(bec_ctx* c, int set, const Eval& ev, const double2* rin, in
     m.sigma = sigma;
     m.apply_pv = apply_pv;
     m.out = c->z;
-    HIPCHK(bec::launch_make_r(c->P, m, c->st));
+    LAUNCH(c, "make_r", (double)c->N * 112.0, bec::launch_make_r(c->P, m, c->st));
     const long long N = c->N;
     const double2* src[2] = {c->z, c->z + N};
     double2* dst[2] = {c->z, c->z + N};
@@ -536,8 +622,10 @@ struct Model {
 bec_status direction_and_model(bec_ctx* c, const bec::DirArgs& A, const Eval& ev, Model* m)
 {
     const long long N = c->N;
-    HIPCHK(bec::launch_dir_write(c->P, A, c->nblk_pw, c->st));
-    HIPCHK(bec::launch_reduce_final(c->partials, c->nblk_pw, bec::kDirWriteSums, c->scal, c->st));
+    const double wb = 96.0 + (A.beta != 0.0 ? 32.0 : 0.0) + (A.zmode == 2 ? 32.0 : 0.0) + 80.0;
+    LAUNCH(c, "dir_write", (double)c->N * wb, bec::launch_dir_write(c->P, A, c->nblk_pw, c->st));
+    LAUNCH(c, "reduce_final", 8.0 * bec::kDirWriteSums * c->nblk_pw,
+           bec::launch_reduce_final(c->partials, c->nblk_pw, bec::kDirWriteSums, c->scal, c->st));
     const double2* src[3] = {c->pdir, c->pdir + N, c->rho};
     double2* dst[3] = {c->W, c->W + N, c->W + 2 * N};
     const int ops[3] = {bec::kOpParseval, bec::kOpParseval, bec::kOpMulDip};
@@ -546,10 +634,12 @@ bec_status direction_and_model(bec_ctx* c, const bec::DirArgs& A, const Eval& ev
     la.rho = c->rho;
     la.phr = c->W + 2 * N;
     la.partials = c->partials;
-    HIPCHK(bec::launch_ls_epi(c->P, la, c->nblk_pw, c->st));
-    HIPCHK(bec::launch_reduce_final(c->partials, c->nblk_pw, bec::kLsEpiSums, c->scal + 20, c->st));
-    HIPCHK(bec::launch_reduce_final(c->fft_partials, c->nblk_x, 1, c->scal + 30, c->st));
-    HIPCHK(bec::launch_reduce_final(c->fft_partials + c->nblk_x, c->nblk_x, 1, c->scal + 31, c->st));
+    LAUNCH(c, "ls_epilogue", (double)N * 32.0, bec::launch_ls_epi(c->P, la, c->nblk_pw, c->st));
+    LAUNCH(c, "reduce_final", 8.0 * bec::kLsEpiSums * c->nblk_pw,
+           bec::launch_reduce_final(c->partials, c->nblk_pw, bec::kLsEpiSums, c->scal + 20, c->st));
+    LAUNCH(c, "reduce_final", 8.0 * c->nblk_x, bec::launch_reduce_final(c->fft_partials, c->nblk_x, 1, c->scal + 30, c->st));
+    LAUNCH(c, "reduce_final", 8.0 * c->nblk_x,
+           bec::launch_reduce_final(c->fft_partials + c->nblk_x, c->nblk_x, 1, c->scal + 31, c->st));
     STCHK(fetch(c, 32));
     const double* S = c->host;
     std::memcpy(m->D, S, sizeof(m->D));
@@ -605,13 +695,14 @@ void geodesic_coeffs(const Eval& ev, const Model& m, double alpha, double a[2], 
 
 bec_status normalise_into(bec_ctx* c, const double2* src, int set)
 {
-    HIPCHK(bec::launch_norm2(c->P, src, c->partials, c->nblk_pw, c->st));
+    LAUNCH(c, "norm2", (double)c->N * 32.0, bec::launch_norm2(c->P, src, c->partials, c->nblk_pw, c->st));
     STCHK(reduce_pw(c, 2, 0));
     STCHK(fetch(c, 2));
     const double n0 = c->dV * c->host[0], n1 = c->dV * c->host[1];
     if (!(n0 > 0) || !(n1 > 0) || !std::isfinite(n0) || !std::isfinite(n1))
         return fail(BEC_ENONFINITE, "initial state has zero or non-finite norm");
-    HIPCHK(bec::launch_scale2(c->P, src, c->psi[set], 1.0 / std::sqrt(n0), 1.0 / std::sqrt(n1), c->st));
+    LAUNCH(c, "scale2", (double)c->N * 64.0,
+           bec::launch_scale2(c->P, src, c->psi[set], 1.0 / std::sqrt(n0), 1.0 / std::sqrt(n1), c->st));
     return BEC_OK;
 }
 
@@ -739,9 +830,42 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
     }
 }
 
+bec_status bec_profile_enable(bec_ctx* c, int32_t on)
+{
+    if (!c) return fail(BEC_EINVAL, "ctx is null");
+    STCHK(prof_flush(c));
+    if (on) {
+        c->prof.names.clear();
+        c->prof.launches.clear();
+        c->prof.total_ms.clear();
+        c->prof.total_bytes.clear();
+    }
+    c->prof.on = on != 0;
+    return BEC_OK;
+}
+
+bec_status bec_profile_read(bec_ctx* c, bec_kernel_stat* out_h, int32_t cap, int32_t* n_out)
+{
+    if (!c || !n_out || (cap > 0 && !out_h)) return fail(BEC_EINVAL, "null argument");
+    STCHK(prof_flush(c));
+    const Prof& P = c->prof;
+    const int n = (int)P.names.size();
+    for (int i = 0; i < n && i < cap; ++i) {
+        std::memset(out_h[i].name, 0, sizeof(out_h[i].name));
+        std::strncpy(out_h[i].name, P.names[i].c_str(), sizeof(out_h[i].name) - 1);
+        out_h[i].launches = P.launches[i];
+        out_h[i].total_ms = P.total_ms[i];
+        out_h[i].total_bytes = P.total_bytes[i];
+    }
+    *n_out = n;
+    return BEC_OK;
+}
+
 bec_status bec_destroy(bec_ctx* ctx)
 {
     if (!ctx) return BEC_OK;
+    (void)prof_flush(ctx);
+    for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
     if (ctx->host) (void)hipHostFree(ctx->host);
     delete ctx;
     return BEC_OK;

@@ -145,6 +145,17 @@ class Context:
         log = [{k: getattr(logs[i], k) for k, _ in B.Iter._fields_} for i in range(min(rep.iters, cap))]
         return psi, out, log
 
+    def profile(self, on: bool):
+        B.check(B.lib().bec_profile_enable(self._ctx, int(on)), "bec_profile_enable")
+
+    def kernel_stats(self) -> list:
+        cap = 64
+        arr = (B.KernelStat * cap)()
+        n = C.c_int32()
+        B.check(B.lib().bec_profile_read(self._ctx, arr, cap, C.byref(n)), "bec_profile_read")
+        return [{"name": arr[i].name.decode(), "launches": arr[i].launches, "total_ms": arr[i].total_ms,
+                 "total_bytes": arr[i].total_bytes} for i in range(min(n.value, cap))]
+
     def param_grad(self, psi) -> dict:
         psi = self.field(psi)
         dG = ((C.c_double * 2) * 2)()
