@@ -330,6 +330,10 @@ bec_status upload_params(bec_ctx* c, bool dipolar_table)
         nd[4] = e12;
         nd[5] = e21;
         nd[6] = a;
+        c->P.node4[q][0] = nd[0];
+        c->P.node4[q][1] = nd[1];
+        c->P.node4[q][2] = nd[2];
+        c->P.node4[q][3] = nd[3];
     }
     HIPCHK(hipMemcpyAsync(c->nodes, nodes.data(), nodes.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
     std::vector<double> vv[3];

@@ -28,7 +28,10 @@ struct PwParams {
     double K3;                 // c_lhy /(3 sqrt(2) pi^2)   (derivatives)
     int n_u;
     int lhy_on;                // c_lhy != 0
-    const double* nodes;       // n_u * kNodeStride
+    const double* nodes;       // n_u * kNodeStride (device copy, used by the non-hot kernels)
+    // hot-loop copy of (eta_11, eta_22, eta_12 eta_21, w_q) per node, passed in the
+    // kernel-argument block so the u loop reads it through scalar loads
+    double node4[kMaxNodes][4];
     const double* vx;          // 1/2 omega_x^2 x^2 per x index
     const double* vy;
     const double* vz;

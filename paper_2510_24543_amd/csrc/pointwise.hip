@@ -33,33 +33,45 @@ __device__ __forceinline__ double trap_at(const PwParams& P, long long i)
     return P.vx[ix] + P.vy[iy] + P.vz[iz];
 }
 
+// Reciprocal square root to full FP64 accuracy for x > kTiny: the hardware
+// estimate followed by two Newton steps r <- r (3 - x r^2) / 2.
+constexpr double kTiny = 1e-290;
+__device__ __forceinline__ double rsq_nr(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    r = r * fma(-h * r, r, 1.5);
+    r = r * fma(-h * r, r, 1.5);
+    return r;
+}
+
 // LHY energy density and derivatives at one point.  Branches with V <= 0
-// contribute nothing ([V]_+ powers); ratio terms vanish when s = 0.
+// contribute nothing ([V]_+ powers); ratio terms vanish when s = 0.  Values
+// below kTiny are treated as 0: their contributions (V^(3/2) < 1e-435) are
+// below FP64 resolution.  Branch-free: masks instead of divergent ifs.
 __device__ __forceinline__ void lhy_point(const PwParams& P, double n1, double n2, double& e,
                                           double& d1, double& d2)
 {
     double ae = 0.0, a1 = 0.0, a2 = 0.0;
+    const double n12x4 = 4.0 * n1 * n2, n1x2 = 2.0 * n1, n2x2 = 2.0 * n2;
     for (int q = 0; q < P.n_u; ++q) {
-        const double* nd = P.nodes + q * kNodeStride;
-        const double e11 = nd[0], e22 = nd[1], p12 = nd[2], w = nd[3];
-        const double a = e11 * n1, b = e22 * n2, delta = a - b;
-        const double s = sqrt(delta * delta + 4.0 * p12 * n1 * n2);
-        const double inv = s > 0.0 ? 1.0 / s : 0.0;
-        const double r1 = (e11 * delta + 2.0 * p12 * n2) * inv;
-        const double r2 = (-e22 * delta + 2.0 * p12 * n1) * inv;
-        const double Vp = a + b + s, Vm = a + b - s;
-        if (Vp > 0.0) {
-            const double v32 = Vp * sqrt(Vp);
-            ae += w * Vp * v32;
-            a1 += w * v32 * (e11 + r1);
-            a2 += w * v32 * (e22 + r2);
-        }
-        if (Vm > 0.0) {
-            const double v32 = Vm * sqrt(Vm);
-            ae += w * Vm * v32;
-            a1 += w * v32 * (e11 - r1);
-            a2 += w * v32 * (e22 - r2);
-        }
+        const double e11 = P.node4[q][0], e22 = P.node4[q][1], p12 = P.node4[q][2], w = P.node4[q][3];
+        const double a = e11 * n1, b = e22 * n2, delta = a - b, base = a + b;
+        const double ss = fma(delta, delta, p12 * n12x4);
+        const bool sp = ss > kTiny;
+        const double inv = sp ? rsq_nr(ss) : 0.0;          // 1/s
+        const double s = ss * inv;
+        const double r1 = fma(e11, delta, p12 * n2x2) * inv;
+        const double r2 = fma(-e22, delta, p12 * n1x2) * inv;
+        const double Vp = base + s, Vm = base - s;
+        const bool pp = Vp > kTiny, pm = Vm > kTiny;
+        const double xp = pp ? Vp : 1.0, xm = pm ? Vm : 1.0;
+        const double wp = pp ? w : 0.0, wm = pm ? w : 0.0;
+        const double v32p = xp * xp * rsq_nr(xp), v32m = xm * xm * rsq_nr(xm);   // V^(3/2)
+        const double cp = wp * v32p, cm = wm * v32m;
+        ae = fma(cp, xp, fma(cm, xm, ae));
+        a1 = fma(cp, e11 + r1, fma(cm, e11 - r1, a1));
+        a2 = fma(cp, e22 + r2, fma(cm, e22 - r2, a2));
     }
     e = P.K5 * ae;
     d1 = P.K3 * a1;
@@ -69,38 +81,35 @@ __device__ __forceinline__ void lhy_point(const PwParams& P, double n1, double n
 // LHY part of the geodesic model with n'' = 0: sums of [V]_+^(3/2) V^1 and of
 // [V]_+^(3/2) V^2_0 + 3/4 [V]_+^(1/2) (V^1)^2.  The n'' part of V^2 is linear in
 // n''_i with coefficient dV/dn_i and is added from muLHY on the host.
+// B/(2s) - A^2/(2s^3) is evaluated as (B - (A/s)^2)/(2s): s^3 underflows at
+// tiny densities.
 __device__ __forceinline__ void lhy_model(const PwParams& P, double n1, double n2, double n1p,
                                           double n2p, double& L1, double& L2)
 {
     double s1 = 0.0, s2acc = 0.0;
+    const double n12x4 = 4.0 * n1 * n2, cross = 2.0 * (n1 * n2p + n1p * n2), pp4 = 4.0 * n1p * n2p;
     for (int q = 0; q < P.n_u; ++q) {
-        const double* nd = P.nodes + q * kNodeStride;
-        const double e11 = nd[0], e22 = nd[1], p12 = nd[2], w = nd[3];
+        const double e11 = P.node4[q][0], e22 = P.node4[q][1], p12 = P.node4[q][2], w = P.node4[q][3];
         const double delta = e11 * n1 - e22 * n2;
         const double d1 = e11 * n1p - e22 * n2p;
-        const double ss = delta * delta + 4.0 * p12 * n1 * n2;
-        const double s = sqrt(ss);
-        const double A = delta * d1 + 2.0 * p12 * (n1 * n2p + n1p * n2);
-        const double B0 = d1 * d1 + 4.0 * p12 * n1p * n2p;
+        const double ss = fma(delta, delta, p12 * n12x4);
+        const bool sp = ss > kTiny;
+        const double inv = sp ? rsq_nr(ss) : 0.0;
+        const double s = ss * inv;
+        const double A = fma(delta, d1, p12 * cross);
+        const double B0 = fma(d1, d1, p12 * pp4);
         const double lin1 = e11 * n1p + e22 * n2p;
-        double ra = 0.0, rb = 0.0;
-        if (s > 0.0) {   // B/(2s) - A^2/(2s^3) as (B - (A/s)^2)/(2s): s^3 underflows at tiny densities
-            const double inv = 1.0 / s;
-            ra = A * inv;
-            rb = 0.5 * (B0 - ra * ra) * inv;
-        }
+        const double ra = A * inv;
+        const double rb = 0.5 * fma(-ra, ra, B0) * inv;
         const double base = e11 * n1 + e22 * n2;
         const double Vp = base + s, Vm = base - s;
-        if (Vp > 0.0) {
-            const double rv = sqrt(Vp), V1 = lin1 + ra, V2 = rb;
-            s1 += w * Vp * rv * V1;
-            s2acc += w * (Vp * rv * V2 + 0.75 * rv * V1 * V1);
-        }
-        if (Vm > 0.0) {
-            const double rv = sqrt(Vm), V1 = lin1 - ra, V2 = -rb;
-            s1 += w * Vm * rv * V1;
-            s2acc += w * (Vm * rv * V2 + 0.75 * rv * V1 * V1);
-        }
+        const bool pp = Vp > kTiny, pm = Vm > kTiny;
+        const double xp = pp ? Vp : 1.0, xm = pm ? Vm : 1.0;
+        const double wp = pp ? w : 0.0, wm = pm ? w : 0.0;
+        const double rvp = xp * rsq_nr(xp), rvm = xm * rsq_nr(xm);   // V^(1/2)
+        const double V1p = lin1 + ra, V1m = lin1 - ra;
+        s1 = fma(wp * xp * rvp, V1p, fma(wm * xm * rvm, V1m, s1));
+        s2acc = fma(wp * rvp, fma(xp, rb, 0.75 * V1p * V1p), fma(wm * rvm, fma(-xm, rb, 0.75 * V1m * V1m), s2acc));
     }
     L1 = s1;
     L2 = s2acc;
@@ -438,19 +447,18 @@ __global__ __launch_bounds__(kPwThreads) void grad_kernel(PwParams P, const doub
     }
 }
 
-__global__ __launch_bounds__(256) void reduce_final_kernel(const double* partials, int nblk, int M, double* out)
+// one workgroup per reduced scalar m: out[m] = sum_b partials[m * nblk + b]
+__global__ __launch_bounds__(256) void reduce_final_kernel(const double* partials, int nblk, double* out)
 {
     __shared__ double sh[4];
-    for (int m = 0; m < M; ++m) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += 256) s += partials[(long long)m * nblk + b];
+    const int m = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += partials[(long long)m * nblk + b];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) out[m] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
-    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[m] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
 int pw_blocks(long long N)
@@ -526,7 +534,7 @@ hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hps
 
 hipError_t launch_reduce_final(const double* partials, int nblk, int M, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, s, partials, nblk, M, out);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(M), dim3(256), 0, s, partials, nblk, out);
     return hipGetLastError();
 }
 
