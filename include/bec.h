@@ -195,6 +195,37 @@ bec_status bec_solve(bec_ctx* ctx, double* psi_inout, const bec_opts* opts, bec_
 bec_status bec_param_grad(bec_ctx* ctx, const double* psi, double dG[2][2], double dGdd[2][2],
                           double* dc_lhy);
 
+/* ---------------------------------------------------------------------------
+ * Batched scan: many independent instances (grids may differ; instances with
+ * the same grid shape are processed together by every kernel launch) solved by
+ * the same preconditioned CG as bec_solve, with the scalar decisions taken on
+ * the device so that a round of the iteration needs no host synchronisation.
+ * Supported preconditioners: BEC_PC_NONE and BEC_PC_V.
+ * ------------------------------------------------------------------------- */
+typedef struct bec_batch bec_batch;
+
+/* Device workspace for n_inst instances (grids[i], params[i]); about 330 bytes
+ * per grid point summed over the instances, plus per-instance tables. */
+bec_status bec_batch_workspace_size(int32_t n_inst, const bec_grid* grids, const bec_params* params,
+                                    size_t* bytes);
+
+/* Create a batch.  Same conventions as bec_create; the batch also owns one
+ * internal stream (default priority) used only to capture graphs. */
+bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_params* params, void* hip_stream,
+                            void* workspace, size_t workspace_bytes, bec_batch** out);
+
+bec_status bec_batch_destroy(bec_batch* b);
+
+/* Solve every instance.  psi_inout: host array of n_inst device pointers, each
+ * an initial state of its instance's grid (normalised on entry) that receives
+ * the final state.  rounds_per_sync: iteration rounds enqueued between two
+ * host checks of the instance states (0: 16).  use_graph: capture those rounds
+ * once in a hipGraph and replay it.  reports_h: host array of n_inst reports
+ * (seconds = wall time of the whole batch).  Returns BEC_OK when the call
+ * completed; per-instance outcomes are in reports_h[i].status. */
+bec_status bec_batch_solve(bec_batch* b, double* const* psi_inout, const bec_opts* opts, int32_t rounds_per_sync,
+                           int32_t use_graph, bec_report* reports_h);
+
 /* Per-kernel timing statistics (see bec_profile_enable). */
 typedef struct {
     char name[40];          /* kernel class, e.g. "fft_y_fwd", "heval_epilogue"  */

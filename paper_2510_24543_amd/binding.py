@@ -88,6 +88,11 @@ SIGNATURES = [
     ("bec_linesearch", C.c_int, [_VP, _VP, _VP, _VP, C.POINTER(Opts), C.POINTER(LsReport)]),
     ("bec_solve", C.c_int, [_VP, _VP, C.POINTER(Opts), C.POINTER(Report), C.POINTER(Iter), _I32]),
     ("bec_param_grad", C.c_int, [_VP, _VP, C.POINTER(_D22), C.POINTER(_D22), _DP]),
+    ("bec_batch_workspace_size", C.c_int, [_I32, C.POINTER(Grid), C.POINTER(Params), C.POINTER(C.c_size_t)]),
+    ("bec_batch_create", C.c_int, [_I32, C.POINTER(Grid), C.POINTER(Params), _VP, _VP, C.c_size_t,
+                                   C.POINTER(_VP)]),
+    ("bec_batch_destroy", C.c_int, [_VP]),
+    ("bec_batch_solve", C.c_int, [_VP, C.POINTER(_VP), C.POINTER(Opts), _I32, _I32, C.POINTER(Report)]),
     ("bec_profile_enable", C.c_int, [_VP, _I32]),
     ("bec_profile_read", C.c_int, [_VP, C.POINTER(KernelStat), _I32, C.POINTER(_I32)]),
     ("bec_gauss_legendre", C.c_int, [_I32, _DP, _DP]),

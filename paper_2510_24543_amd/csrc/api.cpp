@@ -403,6 +403,11 @@ FftPassArgs pass_args(bec_ctx* c, int axis)
     A.scale = 1.0;
     A.partials = c->fft_partials;
     A.nblk_x = c->nblk_x;
+    A.n_inst = 1;
+    for (int f = 0; f < 3; ++f) A.src_stride[f] = A.dst_stride[f] = A.src_sel_stride[f] = 0;
+    A.src_sel = nullptr;
+    A.active = nullptr;
+    A.per_inst_tab = 0;
     if (axis == 2) {
         A.S = 1;
         A.npencil = (long long)c->n[0] * c->n[1];
@@ -1191,6 +1196,610 @@ bec_status bec_param_grad(bec_ctx* c, const double* psi, double dG[2][2], double
             dGdd[i][j] = 0.5 * c->p.N[i] * dV * ev.sums[7 + 2 * i + j] + c->p.c_lhy * K * dV * S[4 + 2 * i + j];
         }
     *dc_lhy = K * dV * S[8];
+    return BEC_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== batched scan
+namespace {
+
+struct BatchGroup {
+    int n[3] = {0, 0, 0};
+    long long N = 0;
+    int first = 0, count = 0, nblk = 0, nblk_x = 0;
+    double2 *psi = nullptr, *hpsi = nullptr, *aux = nullptr, *p = nullptr, *r_old = nullptr, *rho = nullptr,
+            *W = nullptr;
+    double *partials = nullptr, *fft_partials = nullptr, *udtab = nullptr, *kv[3] = {}, *vv[3] = {};
+    double2* tw[3] = {};
+    long long udsize = 0;
+    bec::BGroup g{};
+};
+
+// host tables of one instance: wavenumbers, trap per axis, dipolar kernel on the k octant
+void instance_tables(const bec_grid& gr, const bec_params& p, std::vector<double> kv[3], std::vector<double> vv[3],
+                     std::vector<double>& ud)
+{
+    double L[3], h[3];
+    for (int d = 0; d < 3; ++d) {
+        L[d] = gr.hi[d] - gr.lo[d];
+        h[d] = L[d] / gr.n[d];
+        kv[d].resize(gr.n[d]);
+        vv[d].resize(gr.n[d]);
+        for (int j = 0; j < gr.n[d]; ++j) {
+            const int jj = j < gr.n[d] / 2 ? j : j - gr.n[d];
+            kv[d][j] = (double)(2.0L * kPiL * jj / (long double)L[d]);
+            const double x = gr.lo[d] + j * h[d];
+            vv[d][j] = 0.5 * p.omega[d] * p.omega[d] * x * x;
+        }
+    }
+    const int ax = gr.n[0] / 2 + 1, ay = gr.n[1] / 2 + 1, az = gr.n[2] / 2 + 1;
+    ud.assign((size_t)ax * ay * az, 0.0);
+    for (int i = 0; i < ax; ++i)
+        for (int j = 0; j < ay; ++j)
+            for (int k = 0; k < az; ++k) {
+                const long double kx = 2.0L * kPiL * i / L[0], ky = 2.0L * kPiL * j / L[1], kz = 2.0L * kPiL * k / L[2];
+                const long double k2 = kx * kx + ky * ky + kz * kz;
+                if (k2 > 0.0L)
+                    ud[((size_t)i * ay + j) * az + k] =
+                        (double)((3.0L * kz * kz / k2 - 1.0L) * cutoff_factor(sqrtl(k2) * (long double)p.r_cut));
+            }
+}
+
+void instance_params(const bec_grid& gr, const bec_params& p, bec::BInstParams& P)
+{
+    std::memset(&P, 0, sizeof(P));
+    double dV = 1.0;
+    long long npts = 1;
+    for (int d = 0; d < 3; ++d) {
+        dV *= (gr.hi[d] - gr.lo[d]) / gr.n[d];
+        npts *= gr.n[d];
+    }
+    for (int i = 0; i < 2; ++i) {
+        P.Nat[i] = p.N[i];
+        for (int j = 0; j < 2; ++j) {
+            P.G[i][j] = p.G[i][j];
+            P.Gdd[i][j] = p.Gdd[i][j];
+        }
+    }
+    const double Ntot = p.N[0] + p.N[1];
+    P.Ntot_w[0] = (p.N[0] / Ntot) * (p.N[0] / Ntot);
+    P.Ntot_w[1] = (p.N[1] / Ntot) * (p.N[1] / Ntot);
+    P.K5 = p.c_lhy * std::sqrt(2.0) / (15.0 * M_PI * M_PI);
+    P.K3 = p.c_lhy / (3.0 * std::sqrt(2.0) * M_PI * M_PI);
+    P.dV = dV;
+    P.inv_npts = 1.0 / (double)npts;
+    P.n_u = p.n_u;
+    P.lhy_on = p.c_lhy != 0.0;
+    std::vector<double> u, w;
+    gauss_legendre01(p.n_u, u, w);
+    for (int q = 0; q < p.n_u; ++q) {
+        const double a = 3.0 * u[q] * u[q] - 1.0;
+        const double e12 = p.G[0][1] + p.Gdd[0][1] * a, e21 = p.G[1][0] + p.Gdd[1][0] * a;
+        P.node4[q][0] = p.G[0][0] + p.Gdd[0][0] * a;
+        P.node4[q][1] = p.G[1][1] + p.Gdd[1][1] * a;
+        P.node4[q][2] = e12 * e21;
+        P.node4[q][3] = w[q];
+    }
+}
+
+bool same_shape(const bec_grid& a, const bec_grid& b) { return a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2]; }
+
+// instance order grouped by grid shape (stable), and the group boundaries
+void plan_groups(int n_inst, const bec_grid* grids, std::vector<int>& perm, std::vector<std::pair<int, int>>& ranges)
+{
+    perm.clear();
+    ranges.clear();
+    std::vector<bool> used(n_inst, false);
+    for (int i = 0; i < n_inst; ++i) {
+        if (used[i]) continue;
+        const int first = (int)perm.size();
+        for (int j = i; j < n_inst; ++j)
+            if (!used[j] && same_shape(grids[i], grids[j])) {
+                used[j] = true;
+                perm.push_back(j);
+            }
+        ranges.emplace_back(first, (int)perm.size() - first);
+    }
+}
+
+int group_nblk(long long N)
+{
+    long long b = N / (bec::kPwThreads * 4);
+    return (int)std::max<long long>(16, std::min<long long>(1024, b));
+}
+
+// sizes of the batch workspace in carve order; off receives the offsets
+size_t batch_layout(int n_inst, const bec_grid* grids, std::vector<size_t>* off)
+{
+    std::vector<int> perm;
+    std::vector<std::pair<int, int>> ranges;
+    plan_groups(n_inst, grids, perm, ranges);
+    std::vector<size_t> sizes;
+    sizes.push_back(n_inst * sizeof(bec::BInstParams));
+    sizes.push_back(n_inst * sizeof(bec::BInstState));
+    sizes.push_back((size_t)n_inst * bec::kBSumStride * sizeof(double));
+    sizes.push_back(3 * (size_t)n_inst * sizeof(int));          // act_dir, act_trial, tsel
+    sizes.push_back(n_inst * sizeof(double*));                  // user pointers
+    const size_t c2 = sizeof(double2);
+    for (auto& r : ranges) {
+        const bec_grid& g = grids[perm[r.first]];
+        const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
+        const long long cnt = r.second;
+        const int nblk = group_nblk(N);
+        const int nbx = bec::fft_blocks(g.n[0], (long long)g.n[1] * g.n[2]);
+        const size_t ud = (size_t)(g.n[0] / 2 + 1) * (g.n[1] / 2 + 1) * (g.n[2] / 2 + 1);
+        size_t gs[] = {cnt * 4 * N * c2, cnt * 4 * N * c2, cnt * 4 * N * c2,  // psi, hpsi, aux (2 buffers)
+                       cnt * 2 * N * c2, cnt * 2 * N * c2, cnt * N * c2,      // p, r_old, rho
+                       cnt * 3 * N * c2,                                      // W
+                       (size_t)cnt * bec::kMaxSums * nblk * sizeof(double),   // partials
+                       (size_t)cnt * 3 * nbx * sizeof(double),                // fft partials
+                       cnt * ud * sizeof(double),                             // dipolar tables
+                       cnt * g.n[0] * sizeof(double), cnt * g.n[1] * sizeof(double), cnt * g.n[2] * sizeof(double),
+                       cnt * g.n[0] * sizeof(double), cnt * g.n[1] * sizeof(double), cnt * g.n[2] * sizeof(double),
+                       g.n[0] * c2, g.n[1] * c2, g.n[2] * c2};
+        for (size_t s : gs) sizes.push_back(s);
+    }
+    size_t total = 0;
+    if (off) off->clear();
+    for (size_t s : sizes) {
+        if (off) off->push_back(total);
+        total += align256(s);
+    }
+    return total;
+}
+
+}  // namespace
+
+struct bec_batch {
+    int n_inst = 0;
+    hipStream_t st = nullptr;
+    hipStream_t cap = nullptr;     // capture stream
+    std::vector<bec_grid> grids;
+    std::vector<bec_params> params;
+    std::vector<int> perm;         // internal index -> caller index
+    std::vector<BatchGroup> groups;
+    bec::BInstParams* ip = nullptr;
+    bec::BInstState* state = nullptr;
+    double* sums = nullptr;
+    int *act_dir = nullptr, *act_trial = nullptr, *tsel = nullptr;
+    double** psi_user = nullptr;
+    bec::BInstState* host_state = nullptr;   // pinned
+    double** host_ptrs = nullptr;            // pinned
+    hipGraphExec_t exec = nullptr;
+    int graph_rounds = 0;
+    bec::BOpts graph_opts{};
+};
+
+namespace {
+
+bec_status check_batch_args(int32_t n_inst, const bec_grid* grids, const bec_params* params)
+{
+    if (n_inst < 1 || !grids || !params) return fail(BEC_EINVAL, "need n_inst >= 1 and grid/param arrays");
+    for (int i = 0; i < n_inst; ++i) {
+        STCHK(check_grid(&grids[i]));
+        STCHK(check_params(&params[i]));
+    }
+    return BEC_OK;
+}
+
+FftPassArgs batch_pass_args(const BatchGroup& G, int axis, const int* active)
+{
+    FftPassArgs A{};
+    A.nx = G.n[0];
+    A.ny = G.n[1];
+    A.nz = G.n[2];
+    A.kx = G.kv[0];
+    A.ky = G.kv[1];
+    A.kz = G.kv[2];
+    A.udtab = G.udtab;
+    A.udsize = G.udsize;
+    A.per_inst_tab = 1;
+    A.inv_n = 1.0 / (double)G.N;
+    A.tw = G.tw[axis];
+    A.scale = 1.0;
+    A.partials = G.fft_partials;
+    A.nblk_x = G.nblk_x;
+    A.n_inst = G.count;
+    A.active = active + G.first;
+    A.src_sel = nullptr;
+    if (axis == 2) {
+        A.S = 1;
+        A.npencil = (long long)G.n[0] * G.n[1];
+    } else if (axis == 1) {
+        A.S = G.n[2];
+        A.npencil = (long long)G.n[0] * G.n[2];
+    } else {
+        A.S = (long long)G.n[1] * G.n[2];
+        A.npencil = A.S;
+    }
+    for (int f = 0; f < 3; ++f) {
+        A.op[f] = bec::kOpPlain;
+        A.src_stride[f] = A.dst_stride[f] = 3 * G.N;
+        A.src_sel_stride[f] = 0;
+    }
+    return A;
+}
+
+bec_status bpass(bec_batch* b, const BatchGroup& G, FftPassArgs A, int axis, int nf, int sign)
+{
+    A.nfield = nf;
+    A.sign = sign;
+    HIPCHK(bec::fft_pass(G.n[axis], axis == 2, A, b->st));
+    return BEC_OK;
+}
+
+// Hamiltonian FFTs of the trial state of every active instance of the group
+bec_status batch_heval_fft(bec_batch* b, const BatchGroup& G, hipStream_t s)
+{
+    (void)s;
+    const long long N = G.N;
+    FftPassArgs A = batch_pass_args(G, 2, b->act_trial);
+    A.src[0] = G.psi;
+    A.src[1] = G.psi + N;
+    A.src[2] = G.W + 2 * N;
+    A.src_stride[0] = A.src_stride[1] = 4 * N;
+    A.src_sel = b->tsel + G.first;
+    A.src_sel_stride[0] = A.src_sel_stride[1] = 2 * N;
+    for (int f = 0; f < 3; ++f) A.dst[f] = G.W + f * N;
+    STCHK(bpass(b, G, A, 2, 3, -1));
+    A = batch_pass_args(G, 1, b->act_trial);
+    for (int f = 0; f < 3; ++f) A.src[f] = A.dst[f] = G.W + f * N;
+    STCHK(bpass(b, G, A, 1, 3, -1));
+    A = batch_pass_args(G, 0, b->act_trial);
+    for (int f = 0; f < 3; ++f) A.src[f] = A.dst[f] = G.W + f * N;
+    A.op[0] = A.op[1] = bec::kOpMulKin;
+    A.op[2] = bec::kOpMulDip;
+    STCHK(bpass(b, G, A, 0, 3, -1));
+    A = batch_pass_args(G, 1, b->act_trial);
+    for (int f = 0; f < 3; ++f) A.src[f] = A.dst[f] = G.W + f * N;
+    STCHK(bpass(b, G, A, 1, 3, +1));
+    A = batch_pass_args(G, 2, b->act_trial);
+    for (int f = 0; f < 3; ++f) A.src[f] = A.dst[f] = G.W + f * N;
+    return bpass(b, G, A, 2, 3, +1);
+}
+
+// line-search FFTs: Parseval of p_1, p_2; packed dipolar convolution of rho
+bec_status batch_ls_fft(bec_batch* b, const BatchGroup& G)
+{
+    const long long N = G.N;
+    FftPassArgs A = batch_pass_args(G, 2, b->act_dir);
+    A.src[0] = G.p;
+    A.src[1] = G.p + N;
+    A.src[2] = G.rho;
+    A.src_stride[0] = A.src_stride[1] = 2 * N;
+    A.src_stride[2] = N;
+    for (int f = 0; f < 3; ++f) A.dst[f] = G.W + f * N;
+    STCHK(bpass(b, G, A, 2, 3, -1));
+    A = batch_pass_args(G, 1, b->act_dir);
+    for (int f = 0; f < 3; ++f) A.src[f] = A.dst[f] = G.W + f * N;
+    STCHK(bpass(b, G, A, 1, 3, -1));
+    A = batch_pass_args(G, 0, b->act_dir);
+    for (int f = 0; f < 3; ++f) A.src[f] = A.dst[f] = G.W + f * N;
+    A.op[0] = A.op[1] = bec::kOpParseval;
+    A.op[2] = bec::kOpMulDip;
+    STCHK(bpass(b, G, A, 0, 3, -1));
+    A = batch_pass_args(G, 1, b->act_dir);
+    A.src[0] = A.dst[0] = G.W + 2 * N;
+    STCHK(bpass(b, G, A, 1, 1, +1));
+    A = batch_pass_args(G, 2, b->act_dir);
+    A.src[0] = A.dst[0] = G.W + 2 * N;
+    return bpass(b, G, A, 2, 1, +1);
+}
+
+bec_status breduce(bec_batch* b, const BatchGroup& G, int M, int off)
+{
+    HIPCHK(bec::launch_b_reduce(G.partials, (long long)bec::kMaxSums * G.nblk, G.nblk, G.nblk, M, G.count,
+                                b->sums + (long long)G.first * bec::kBSumStride, off, b->st));
+    return BEC_OK;
+}
+
+bec_status batch_trial_and_accept(bec_batch* b, const bec::BOpts& o)
+{
+    for (auto& G : b->groups) {
+        HIPCHK(bec::launch_b_trial(G.g, b->st));
+        STCHK(batch_heval_fft(b, G, b->st));
+        HIPCHK(bec::launch_b_heval_epi(G.g, b->st));
+        STCHK(breduce(b, G, bec::kHevalSums, bec::kSH));
+    }
+    HIPCHK(bec::launch_b_decide_accept(b->n_inst, o, b->ip, b->state, b->sums, b->act_trial, b->st));
+    return BEC_OK;
+}
+
+// one round of the iteration for every instance (no host synchronisation)
+bec_status batch_round(bec_batch* b, const bec::BOpts& o)
+{
+    for (auto& G : b->groups) {
+        HIPCHK(bec::launch_b_dir_reduce(G.g, b->st));
+        STCHK(breduce(b, G, bec::kDirReduceSums, bec::kSR));
+    }
+    HIPCHK(bec::launch_b_decide_dir(b->n_inst, o, b->ip, b->state, b->sums, b->act_dir, b->st));
+    for (auto& G : b->groups) {
+        HIPCHK(bec::launch_b_dir_write(G.g, b->st));
+        STCHK(breduce(b, G, bec::kDirWriteSums, bec::kSW));
+        STCHK(batch_ls_fft(b, G));
+        HIPCHK(bec::launch_b_ls_epi(G.g, b->st));
+        STCHK(breduce(b, G, bec::kLsEpiSums, bec::kSL));
+        HIPCHK(bec::launch_b_reduce(G.fft_partials, 3LL * G.nblk_x, G.nblk_x, G.nblk_x, 2, G.count,
+                                    b->sums + (long long)G.first * bec::kBSumStride, bec::kSP, b->st));
+    }
+    HIPCHK(bec::launch_b_decide_step(b->n_inst, o, b->ip, b->state, b->sums, b->act_dir, b->act_trial, b->tsel,
+                                     b->st));
+    return batch_trial_and_accept(b, o);
+}
+
+bec::BOpts to_bopts(const bec_opts* o)
+{
+    bec::BOpts b{};
+    b.beta_mode = o->beta;
+    b.max_iter = o->max_iter;
+    b.restart_period = o->restart_period;
+    b.max_backtrack = o->max_backtrack;
+    b.tol_grad = o->tol_grad;
+    b.tol_dE = o->tol_dE;
+    b.sigma = o->sigma;
+    b.armijo_c1 = o->armijo_c1;
+    b.theta_max = o->theta_max;
+    b.tau_rel = o->tau_rel;
+    return b;
+}
+
+bool same_bopts(const bec::BOpts& a, const bec::BOpts& b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+bec_status bec_batch_workspace_size(int32_t n_inst, const bec_grid* grids, const bec_params* params, size_t* bytes)
+{
+    STCHK(check_batch_args(n_inst, grids, params));
+    if (!bytes) return fail(BEC_EINVAL, "bytes is null");
+    *bytes = batch_layout(n_inst, grids, nullptr);
+    return BEC_OK;
+}
+
+bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_params* params, void* hip_stream,
+                            void* workspace, size_t workspace_bytes, bec_batch** out)
+{
+    try {
+        STCHK(check_batch_args(n_inst, grids, params));
+        if (!out || !workspace) return fail(BEC_EINVAL, "null argument");
+        if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(BEC_EINVAL, "workspace must be 256-byte aligned");
+        std::vector<size_t> off;
+        const size_t need = batch_layout(n_inst, grids, &off);
+        if (workspace_bytes < need) return fail(BEC_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+        bec_batch* b = new bec_batch();
+        b->n_inst = n_inst;
+        b->st = reinterpret_cast<hipStream_t>(hip_stream);
+        b->grids.assign(grids, grids + n_inst);
+        b->params.assign(params, params + n_inst);
+        std::vector<std::pair<int, int>> ranges;
+        plan_groups(n_inst, grids, b->perm, ranges);
+        char* base = static_cast<char*>(workspace);
+        size_t k = 0;
+        b->ip = (bec::BInstParams*)(base + off[k++]);
+        b->state = (bec::BInstState*)(base + off[k++]);
+        b->sums = (double*)(base + off[k++]);
+        b->act_dir = (int*)(base + off[k++]);
+        b->act_trial = b->act_dir + n_inst;
+        b->tsel = b->act_dir + 2 * n_inst;
+        b->psi_user = (double**)(base + off[k++]);
+        auto cleanup = [&](bec_status s) {
+            if (b->host_state) (void)hipHostFree(b->host_state);
+            if (b->host_ptrs) (void)hipHostFree(b->host_ptrs);
+            if (b->cap) (void)hipStreamDestroy(b->cap);
+            delete b;
+            return s;
+        };
+        if (hipHostMalloc((void**)&b->host_state, n_inst * sizeof(bec::BInstState), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&b->host_ptrs, n_inst * sizeof(double*), hipHostMallocDefault) != hipSuccess ||
+            hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+            return cleanup(fail(BEC_EHIP, "host buffers / capture stream"));
+        std::vector<bec::BInstParams> hip_params(n_inst);
+        for (int i = 0; i < n_inst; ++i) instance_params(grids[b->perm[i]], params[b->perm[i]], hip_params[i]);
+        if (hipMemcpyAsync(b->ip, hip_params.data(), n_inst * sizeof(bec::BInstParams), hipMemcpyHostToDevice, b->st) !=
+            hipSuccess)
+            return cleanup(fail(BEC_EHIP, "upload of instance parameters"));
+        for (auto& r : ranges) {
+            BatchGroup G;
+            const bec_grid& g0 = grids[b->perm[r.first]];
+            for (int d = 0; d < 3; ++d) G.n[d] = g0.n[d];
+            G.N = (long long)G.n[0] * G.n[1] * G.n[2];
+            G.first = r.first;
+            G.count = r.second;
+            G.nblk = group_nblk(G.N);
+            G.nblk_x = bec::fft_blocks(G.n[0], (long long)G.n[1] * G.n[2]);
+            G.udsize = (long long)(G.n[0] / 2 + 1) * (G.n[1] / 2 + 1) * (G.n[2] / 2 + 1);
+            G.psi = (double2*)(base + off[k++]);
+            G.hpsi = (double2*)(base + off[k++]);
+            G.aux = (double2*)(base + off[k++]);
+            G.p = (double2*)(base + off[k++]);
+            G.r_old = (double2*)(base + off[k++]);
+            G.rho = (double2*)(base + off[k++]);
+            G.W = (double2*)(base + off[k++]);
+            G.partials = (double*)(base + off[k++]);
+            G.fft_partials = (double*)(base + off[k++]);
+            G.udtab = (double*)(base + off[k++]);
+            for (int d = 0; d < 3; ++d) G.kv[d] = (double*)(base + off[k++]);
+            for (int d = 0; d < 3; ++d) G.vv[d] = (double*)(base + off[k++]);
+            for (int d = 0; d < 3; ++d) G.tw[d] = (double2*)(base + off[k++]);
+            // per-instance tables
+            std::vector<double> ud_all, kv_all[3], vv_all[3];
+            for (int l = 0; l < G.count; ++l) {
+                std::vector<double> kv[3], vv[3], ud;
+                instance_tables(grids[b->perm[G.first + l]], params[b->perm[G.first + l]], kv, vv, ud);
+                ud_all.insert(ud_all.end(), ud.begin(), ud.end());
+                for (int d = 0; d < 3; ++d) {
+                    kv_all[d].insert(kv_all[d].end(), kv[d].begin(), kv[d].end());
+                    vv_all[d].insert(vv_all[d].end(), vv[d].begin(), vv[d].end());
+                }
+            }
+            bool ok = hipMemcpyAsync(G.udtab, ud_all.data(), ud_all.size() * sizeof(double), hipMemcpyHostToDevice,
+                                     b->st) == hipSuccess;
+            for (int d = 0; d < 3 && ok; ++d) {
+                ok = hipMemcpyAsync(G.kv[d], kv_all[d].data(), kv_all[d].size() * sizeof(double),
+                                    hipMemcpyHostToDevice, b->st) == hipSuccess &&
+                     hipMemcpyAsync(G.vv[d], vv_all[d].data(), vv_all[d].size() * sizeof(double),
+                                    hipMemcpyHostToDevice, b->st) == hipSuccess;
+                std::vector<double2> tw(G.n[d]);
+                for (int m = 0; m < G.n[d]; ++m) {
+                    const long double a = -2.0L * kPiL * (long double)m / (long double)G.n[d];
+                    tw[m] = make_double2((double)cosl(a), (double)sinl(a));
+                }
+                ok = ok && hipMemcpyAsync(G.tw[d], tw.data(), G.n[d] * sizeof(double2), hipMemcpyHostToDevice,
+                                          b->st) == hipSuccess &&
+                     hipStreamSynchronize(b->st) == hipSuccess;
+            }
+            if (!ok || hipStreamSynchronize(b->st) != hipSuccess) return cleanup(fail(BEC_EHIP, "upload of tables"));
+            bec::BGroup& g = G.g;
+            g.first = G.first;
+            g.count = G.count;
+            g.nx = G.n[0];
+            g.ny = G.n[1];
+            g.nz = G.n[2];
+            g.N = G.N;
+            g.nblk = G.nblk;
+            g.ip = b->ip;
+            g.st = b->state;
+            g.sums = b->sums;
+            g.act_dir = b->act_dir;
+            g.act_trial = b->act_trial;
+            g.psi_user = b->psi_user;
+            g.vx = G.vv[0];
+            g.vy = G.vv[1];
+            g.vz = G.vv[2];
+            g.psi = G.psi;
+            g.hpsi = G.hpsi;
+            g.aux = G.aux;
+            g.p = G.p;
+            g.r_old = G.r_old;
+            g.rho = G.rho;
+            g.W = G.W;
+            g.partials = G.partials;
+            b->groups.push_back(G);
+        }
+        if (hipStreamSynchronize(b->st) != hipSuccess) return cleanup(fail(BEC_EHIP, "synchronise"));
+        *out = b;
+        return BEC_OK;
+    } catch (...) {
+        return fail(BEC_EINVAL, "unexpected host exception in bec_batch_create");
+    }
+}
+
+bec_status bec_batch_destroy(bec_batch* b)
+{
+    if (!b) return BEC_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->host_state) (void)hipHostFree(b->host_state);
+    if (b->host_ptrs) (void)hipHostFree(b->host_ptrs);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return BEC_OK;
+}
+
+bec_status bec_batch_solve(bec_batch* b, double* const* psi_inout, const bec_opts* o, int32_t rounds_per_sync,
+                           int32_t use_graph, bec_report* reports_h)
+{
+    if (!b || !psi_inout || !o || !reports_h) return fail(BEC_EINVAL, "null argument");
+    if (o->pc != BEC_PC_NONE && o->pc != BEC_PC_V)
+        return fail(BEC_EUNSUPPORTED, "the batched solver supports the identity and P_V preconditioners");
+    if (o->beta < 0 || o->beta > 2) return fail(BEC_EINVAL, "bad beta mode");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int K = rounds_per_sync > 0 ? rounds_per_sync : 16;
+    const bec::BOpts bo = to_bopts(o);
+    for (auto& G : b->groups) {
+        G.g.zmode = o->pc == BEC_PC_V ? 1 : 0;
+        G.g.sigma = o->sigma;
+    }
+    for (int i = 0; i < b->n_inst; ++i) {
+        if (!psi_inout[b->perm[i]]) return fail(BEC_EINVAL, "psi_inout[%d] is null", b->perm[i]);
+        b->host_ptrs[i] = psi_inout[b->perm[i]];
+    }
+    HIPCHK(hipMemcpyAsync(b->psi_user, b->host_ptrs, b->n_inst * sizeof(double*), hipMemcpyHostToDevice, b->st));
+    // initial state: normalise and evaluate
+    for (auto& G : b->groups) {
+        HIPCHK(bec::launch_b_norm2(G.g, b->st));
+        STCHK(breduce(b, G, 2, bec::kSR));
+    }
+    HIPCHK(bec::launch_b_decide_init(b->n_inst, b->ip, b->state, b->sums, b->act_dir, b->act_trial, b->tsel, b->st));
+    STCHK(batch_trial_and_accept(b, bo));
+
+    if (use_graph && (!b->exec || b->graph_rounds != K || !same_bopts(b->graph_opts, bo))) {
+        if (b->exec) {
+            HIPCHK(hipGraphExecDestroy(b->exec));
+            b->exec = nullptr;
+        }
+        hipStream_t user = b->st;
+        b->st = b->cap;
+        HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        bec_status cs = BEC_OK;
+        for (int r = 0; r < K && cs == BEC_OK; ++r) cs = batch_round(b, bo);
+        hipGraph_t graph = nullptr;
+        const hipError_t ce = hipStreamEndCapture(b->cap, &graph);
+        b->st = user;
+        if (cs != BEC_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return cs;
+        }
+        if (ce != hipSuccess) return fail(BEC_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
+        const hipError_t ie = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return fail(BEC_EHIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+        b->graph_rounds = K;
+        b->graph_opts = bo;
+    }
+    const long long max_rounds = (long long)(o->max_iter + 1) * (o->max_backtrack + 3) + 8;
+    long long rounds = 0;
+    for (;;) {
+        if (use_graph) {
+            HIPCHK(hipGraphLaunch(b->exec, b->st));
+        } else {
+            for (int r = 0; r < K; ++r) STCHK(batch_round(b, bo));
+        }
+        rounds += K;
+        HIPCHK(hipMemcpyAsync(b->host_state, b->state, b->n_inst * sizeof(bec::BInstState), hipMemcpyDeviceToHost,
+                              b->st));
+        HIPCHK(hipStreamSynchronize(b->st));
+        bool running = false;
+        for (int i = 0; i < b->n_inst; ++i) running = running || b->host_state[i].status == bec::kBRunning;
+        if (!running || rounds >= max_rounds) break;
+    }
+    for (auto& G : b->groups) HIPCHK(bec::launch_b_copy_out(G.g, b->st));
+    HIPCHK(hipStreamSynchronize(b->st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < b->n_inst; ++i) {
+        const bec::BInstState& S = b->host_state[i];
+        const bec_params& p = b->params[b->perm[i]];
+        bec_report& R = reports_h[b->perm[i]];
+        std::memset(&R, 0, sizeof(R));
+        R.iters = S.iter;
+        R.n_restarts = S.n_restarts;
+        R.n_backtracks = S.n_backtracks;
+        R.status = S.status == bec::kBConverged ? BEC_OK
+                   : S.status == bec::kBRunning || S.status == bec::kBNotConv ? BEC_ENOTCONV
+                   : S.status == bec::kBStagnated ? BEC_ESTAGNATED : BEC_ENONFINITE;
+        bec::BInstParams P;
+        instance_params(b->grids[b->perm[i]], p, P);
+        const double* H = S.hsum;
+        const double dV = P.dV;
+        bec_terms& t = R.final;
+        const double snn[2][2] = {{H[4], H[5]}, {H[5], H[6]}};
+        for (int c = 0; c < 2; ++c) {
+            t.norm2[c] = dV * H[14 + c];
+            t.E_kin[c] = p.N[c] * dV * H[c];
+            t.E_trap[c] = p.N[c] * dV * H[2 + c];
+            for (int j = 0; j < 2; ++j) {
+                t.E_c[c][j] = 0.5 * p.N[c] * p.G[c][j] * dV * snn[c][j];
+                t.E_dd[c][j] = 0.5 * p.N[c] * p.Gdd[c][j] * dV * H[7 + 2 * c + j];
+            }
+            t.mu[c] = S.mu[c];
+            t.shift[c] = S.shift[c];
+            t.res[c] = S.res[c];
+        }
+        t.E_lhy = dV * H[11];
+        t.E = S.E;
+        R.seconds = secs;
+    }
     return BEC_OK;
 }
 

@@ -64,8 +64,19 @@ struct FftPassArgs {
     const double* kz;
     const double* udtab;   // dipolar kernel on the k octant [nx/2+1][ny/2+1][nz/2+1]
     double inv_n;          // 1/(nx ny nz)
-    double* partials;      // kOpParseval: [field][block]
+    double* partials;      // kOpParseval: [instance][field][block]
     int nblk_x;
+    // batched passes: grid.z = instance; field f of instance i starts at
+    // src[f] + i * src_stride[f] (+ src_sel[i] * src_sel_stride[f]) and
+    // dst[f] + i * dst_stride[f]; per-instance k / dipolar tables when
+    // per_inst_tab; instances with active[i] == 0 are skipped
+    int n_inst;
+    long long src_stride[3], dst_stride[3];   // per-field instance strides (elements)
+    const int* src_sel;                       // optional: buffer index per instance
+    long long src_sel_stride[3];              // src offset += src_sel[i] * src_sel_stride[f]
+    const int* active;
+    int per_inst_tab;
+    long long udsize;      // doubles per instance in udtab
 };
 
 // Launch one axis pass of length L over args.nfield fields. axis: 0 x, 1 y, 2 z.
@@ -161,5 +172,87 @@ hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hps
                        double mu0, double mu1, double s0, double s1, int projected, hipStream_t s);
 // out[m] = sum_b partials[m * nblk + b] for m < M (fixed order), one block
 hipError_t launch_reduce_final(const double* partials, int nblk, int M, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------- batched scan
+// Instances with the same grid shape form a group; every batched kernel covers
+// one group (grid.y or grid.z = instance within the group).  The scalar
+// decisions of the CG loop run on the device, one thread per instance, so a
+// round needs no host synchronisation and can be captured in a graph.
+constexpr int kBSumStride = 64;   // reduced scalars per instance
+constexpr int kSH = 0;            // 18 Hamiltonian-epilogue sums
+constexpr int kSR = 18;           // 12 direction-reduce sums
+constexpr int kSW = 30;           // 18 direction-write sums
+constexpr int kSL = 48;           // 7 line-search epilogue sums
+constexpr int kSP = 55;           // 2 Parseval sums
+
+struct BInstParams {
+    double G[2][2], Gdd[2][2], Nat[2], K5, K3, dV;
+    double Ntot_w[2];             // stacked inner-product weights (N_i/N)^2
+    double inv_npts;              // 1 / (nx ny nz)
+    int n_u, lhy_on;
+    double node4[kMaxNodes][4];
+};
+
+enum : int { kBRunning = 0, kBConverged = 1, kBNotConv = 2, kBStagnated = 3, kBNonFinite = 4 };
+enum : int { kBInit = 0, kBNewDir = 1, kBBacktrack = 2, kBRedo = 3 };
+
+struct BInstState {
+    int status, phase, cur, iter, have_prev, level, path, nbt, n_restarts, n_backtracks, rounds, pad;
+    double E, E_prev, mu[2], shift[2], norm2[2], res[2];
+    double beta, c[2], zpsi[2], ppsi[2], rz[2], rz_old, rz_now, alpha, alpha_prev, E1, E2, rp;
+    double pnorm[2], psip[2], a[2], b[2];
+    double hsum[kHevalSums];      // Hamiltonian sums of the accepted state
+};
+
+struct BOpts {                    // the bec_opts fields the device decisions use
+    int beta_mode, max_iter, restart_period, max_backtrack;
+    double tol_grad, tol_dE, sigma, armijo_c1, theta_max, tau_rel;
+};
+
+struct BGroup {
+    int first, count;             // global index of the first instance, instances in the group
+    int nx, ny, nz;
+    long long N;
+    int nblk;                     // pointwise blocks per instance
+    int zmode;                    // 0 identity, 1 P_V
+    double sigma;
+    const BInstParams* ip;        // [n_inst] (global index)
+    BInstState* st;               // [n_inst]
+    double* sums;                 // [n_inst][kBSumStride]
+    const int* act_dir;           // [n_inst]
+    const int* act_trial;         // [n_inst]
+    double* const* psi_user;      // [n_inst] caller's device fields
+    const double* vx;             // [count][nx], trap per axis
+    const double* vy;
+    const double* vz;
+    double2* psi;                 // [count][2 buffers][2N]
+    double2* hpsi;                // [count][2][2N]
+    double2* aux;                 // [count][2][2N]
+    double2* p;                   // [count][2N]
+    double2* r_old;               // [count][2N]
+    double2* rho;                 // [count][N]
+    double2* W;                   // [count][3N]
+    double* partials;             // [count][kMaxSums][nblk]
+};
+
+hipError_t launch_b_norm2(const BGroup& g, hipStream_t s);
+hipError_t launch_b_trial(const BGroup& g, hipStream_t s);
+hipError_t launch_b_heval_epi(const BGroup& g, hipStream_t s);
+hipError_t launch_b_dir_reduce(const BGroup& g, hipStream_t s);
+hipError_t launch_b_dir_write(const BGroup& g, hipStream_t s);
+hipError_t launch_b_ls_epi(const BGroup& g, hipStream_t s);
+hipError_t launch_b_copy_out(const BGroup& g, hipStream_t s);
+// sums[first + l][off + m] = sum_b partials[l * inst_stride + m * row_stride + b], m < M
+hipError_t launch_b_reduce(const double* partials, long long inst_stride, long long row_stride, int nblk, int M,
+                           int count, double* sums_first, int off, hipStream_t s);
+// decision kernels over all n_inst instances
+hipError_t launch_b_decide_init(int n_inst, const BInstParams* ip, BInstState* st, const double* sums,
+                                int* act_dir, int* act_trial, int* tsel, hipStream_t s);
+hipError_t launch_b_decide_dir(int n_inst, BOpts o, const BInstParams* ip, BInstState* st, const double* sums,
+                               int* act_dir, hipStream_t s);
+hipError_t launch_b_decide_step(int n_inst, BOpts o, const BInstParams* ip, BInstState* st, const double* sums,
+                                const int* act_dir, int* act_trial, int* tsel, hipStream_t s);
+hipError_t launch_b_decide_accept(int n_inst, BOpts o, const BInstParams* ip, BInstState* st, const double* sums,
+                                  int* act_trial, hipStream_t s);
 
 }  // namespace bec

@@ -226,6 +226,11 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
     constexpr int E = L / T, PB = NTHR / T, RS = L + 1;
     __shared__ double2 lds[PB * RS];
     const int f = blockIdx.y;
+    const int inst = blockIdx.z;
+    if (A.active && A.active[inst] == 0) return;   // uniform per block
+    const long long soff = (long long)inst * A.src_stride[f] +
+                           (A.src_sel ? (long long)A.src_sel[inst] * A.src_sel_stride[f] : 0);
+    const long long doff = (long long)inst * A.dst_stride[f];
     const int tid = threadIdx.x;
     const int pl = CONTIG ? tid / T : tid % PB;
     const int t = CONTIG ? tid % T : tid / PB;
@@ -238,8 +243,8 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
         s = pg - o * S;
         base = o * (long long)L * S + s;
     }
-    const double2* __restrict__ src = A.src[f];
-    double2* __restrict__ dst = A.dst[f];
+    const double2* __restrict__ src = A.src[f] + soff;
+    double2* __restrict__ dst = A.dst[f] + doff;
     const double2* __restrict__ tw = A.tw;
     const int op = KMODE == 2 ? A.op[f] : kOpPlain;
     double2* row = lds + pl * RS;
@@ -271,11 +276,14 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
 
     // x pass with a diagonal k-space operator: forward, then op
     PL::template fwd_like<-1>(v, row, t, tw);
+    const double* __restrict__ kxt = A.kx + (A.per_inst_tab ? (long long)inst * A.nx : 0);
+    const double* __restrict__ udt = A.udtab + (A.per_inst_tab ? (long long)inst * A.udsize : 0);
     double ky2 = 0.0, kz2 = 0.0;
     int ay = 0, az = 0;
     {
         const int iy = (int)(s / A.nz), iz = (int)(s - (long long)iy * A.nz);
-        const double ky = A.ky[iy], kz = A.kz[iz];
+        const double ky = A.ky[iy + (A.per_inst_tab ? (long long)inst * A.ny : 0)];
+        const double kz = A.kz[iz + (A.per_inst_tab ? (long long)inst * A.nz : 0)];
         ky2 = ky * ky;
         kz2 = kz * kz;
         ay = iy <= A.ny / 2 ? iy : A.ny - iy;
@@ -288,14 +296,14 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const int j = t + b * T + r * (L / RL);
-                const double kx = A.kx[j];
+                const double kx = kxt[j];
                 const double2 w = v[b * RL + r];
                 acc += 0.5 * (kx * kx + ky2 + kz2) * (w.x * w.x + w.y * w.y);
             }
         if (!valid) acc = 0.0;
         __syncthreads();
         const double tot = block_sum<NTHR>(acc, reinterpret_cast<double*>(lds));
-        if (threadIdx.x == 0) A.partials[(long long)f * A.nblk_x + blockIdx.x] = tot;
+        if (threadIdx.x == 0) A.partials[((long long)inst * A.nfield + f) * A.nblk_x + blockIdx.x] = tot;
         return;
     }
     const double inv_n = A.inv_n;
@@ -307,13 +315,13 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
             const int j = t + b * T + r * (L / RL);
             double m;
             if (op == kOpMulKin) {
-                const double kx = A.kx[j];
+                const double kx = kxt[j];
                 m = 0.5 * (kx * kx + ky2 + kz2);
             } else if (op == kOpMulDip) {
                 const int ax = j <= L / 2 ? j : L - j;
-                m = A.udtab[((long long)ax * (A.ny / 2 + 1) + ay) * (A.nz / 2 + 1) + az];
+                m = udt[((long long)ax * (A.ny / 2 + 1) + ay) * (A.nz / 2 + 1) + az];
             } else {
-                const double kx = A.kx[j];
+                const double kx = kxt[j];
                 m = 1.0 / (pa + 0.5 * (kx * kx + ky2 + kz2));
             }
             v[b * RL + r] = cscale(v[b * RL + r], m * inv_n);
@@ -334,7 +342,7 @@ template <int L, int T, int R0, int R1, int R2, int NTHR>
 hipError_t launch_cfg(bool contiguous, const FftPassArgs& A, hipStream_t st)
 {
     constexpr int PB = NTHR / T;
-    dim3 grid((unsigned)((A.npencil + PB - 1) / PB), (unsigned)A.nfield);
+    dim3 grid((unsigned)((A.npencil + PB - 1) / PB), (unsigned)A.nfield, (unsigned)(A.n_inst > 0 ? A.n_inst : 1));
     bool plain = true;
     for (int f = 0; f < A.nfield; ++f) plain = plain && A.op[f] == kOpPlain;
     if (contiguous) {

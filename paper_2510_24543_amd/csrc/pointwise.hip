@@ -16,12 +16,10 @@
 //   d = -z + beta p_old, p = d - Re<d,psi> psi                                      (Sec. IV.C, Sec. V)
 //   second-order energy model along the geodesic                                    (Sec. V)
 #include "bec_internal.h"
+#include "pw_math.h"
 
 namespace bec {
 namespace {
-
-__device__ __forceinline__ double sq2(double2 a) { return a.x * a.x + a.y * a.y; }
-__device__ __forceinline__ double redot(double2 a, double2 b) { return a.x * b.x + a.y * b.y; }  // Re(conj(a) b)
 
 __device__ __forceinline__ double trap_at(const PwParams& P, long long i)
 {
@@ -33,87 +31,11 @@ __device__ __forceinline__ double trap_at(const PwParams& P, long long i)
     return P.vx[ix] + P.vy[iy] + P.vz[iz];
 }
 
-// Reciprocal square root to full FP64 accuracy for x > kTiny: the hardware
-// estimate followed by two Newton steps r <- r (3 - x r^2) / 2.
-constexpr double kTiny = 1e-290;
-__device__ __forceinline__ double rsq_nr(double x)
-{
-    double r = __builtin_amdgcn_rsq(x);
-    const double h = 0.5 * x;
-    r = r * fma(-h * r, r, 1.5);
-    r = r * fma(-h * r, r, 1.5);
-    return r;
-}
-
-// LHY energy density and derivatives at one point.  Branches with V <= 0
-// contribute nothing ([V]_+ powers); ratio terms vanish when s = 0.  Values
-// below kTiny are treated as 0: their contributions (V^(3/2) < 1e-435) are
-// below FP64 resolution.  Branch-free: masks instead of divergent ifs.
-__device__ __forceinline__ void lhy_point(const PwParams& P, double n1, double n2, double& e,
-                                          double& d1, double& d2)
-{
-    double ae = 0.0, a1 = 0.0, a2 = 0.0;
-    const double n12x4 = 4.0 * n1 * n2, n1x2 = 2.0 * n1, n2x2 = 2.0 * n2;
-    for (int q = 0; q < P.n_u; ++q) {
-        const double e11 = P.node4[q][0], e22 = P.node4[q][1], p12 = P.node4[q][2], w = P.node4[q][3];
-        const double a = e11 * n1, b = e22 * n2, delta = a - b, base = a + b;
-        const double ss = fma(delta, delta, p12 * n12x4);
-        const bool sp = ss > kTiny;
-        const double inv = sp ? rsq_nr(ss) : 0.0;          // 1/s
-        const double s = ss * inv;
-        const double r1 = fma(e11, delta, p12 * n2x2) * inv;
-        const double r2 = fma(-e22, delta, p12 * n1x2) * inv;
-        const double Vp = base + s, Vm = base - s;
-        const bool pp = Vp > kTiny, pm = Vm > kTiny;
-        const double xp = pp ? Vp : 1.0, xm = pm ? Vm : 1.0;
-        const double wp = pp ? w : 0.0, wm = pm ? w : 0.0;
-        const double v32p = xp * xp * rsq_nr(xp), v32m = xm * xm * rsq_nr(xm);   // V^(3/2)
-        const double cp = wp * v32p, cm = wm * v32m;
-        ae = fma(cp, xp, fma(cm, xm, ae));
-        a1 = fma(cp, e11 + r1, fma(cm, e11 - r1, a1));
-        a2 = fma(cp, e22 + r2, fma(cm, e22 - r2, a2));
-    }
-    e = P.K5 * ae;
-    d1 = P.K3 * a1;
-    d2 = P.K3 * a2;
-}
-
-// LHY part of the geodesic model with n'' = 0: sums of [V]_+^(3/2) V^1 and of
-// [V]_+^(3/2) V^2_0 + 3/4 [V]_+^(1/2) (V^1)^2.  The n'' part of V^2 is linear in
-// n''_i with coefficient dV/dn_i and is added from muLHY on the host.
-// B/(2s) - A^2/(2s^3) is evaluated as (B - (A/s)^2)/(2s): s^3 underflows at
-// tiny densities.
-__device__ __forceinline__ void lhy_model(const PwParams& P, double n1, double n2, double n1p,
-                                          double n2p, double& L1, double& L2)
-{
-    double s1 = 0.0, s2acc = 0.0;
-    const double n12x4 = 4.0 * n1 * n2, cross = 2.0 * (n1 * n2p + n1p * n2), pp4 = 4.0 * n1p * n2p;
-    for (int q = 0; q < P.n_u; ++q) {
-        const double e11 = P.node4[q][0], e22 = P.node4[q][1], p12 = P.node4[q][2], w = P.node4[q][3];
-        const double delta = e11 * n1 - e22 * n2;
-        const double d1 = e11 * n1p - e22 * n2p;
-        const double ss = fma(delta, delta, p12 * n12x4);
-        const bool sp = ss > kTiny;
-        const double inv = sp ? rsq_nr(ss) : 0.0;
-        const double s = ss * inv;
-        const double A = fma(delta, d1, p12 * cross);
-        const double B0 = fma(d1, d1, p12 * pp4);
-        const double lin1 = e11 * n1p + e22 * n2p;
-        const double ra = A * inv;
-        const double rb = 0.5 * fma(-ra, ra, B0) * inv;
-        const double base = e11 * n1 + e22 * n2;
-        const double Vp = base + s, Vm = base - s;
-        const bool pp = Vp > kTiny, pm = Vm > kTiny;
-        const double xp = pp ? Vp : 1.0, xm = pm ? Vm : 1.0;
-        const double wp = pp ? w : 0.0, wm = pm ? w : 0.0;
-        const double rvp = xp * rsq_nr(xp), rvm = xm * rsq_nr(xm);   // V^(1/2)
-        const double V1p = lin1 + ra, V1m = lin1 - ra;
-        s1 = fma(wp * xp * rvp, V1p, fma(wm * xm * rvm, V1m, s1));
-        s2acc = fma(wp * rvp, fma(xp, rb, 0.75 * V1p * V1p), fma(wm * rvm, fma(-xm, rb, 0.75 * V1m * V1m), s2acc));
-    }
-    L1 = s1;
-    L2 = s2acc;
-}
+// node constants read from the kernel-argument block (scalar loads)
+struct KernargNodes {
+    const PwParams& P;
+    __device__ double operator()(int q, int k) const { return P.node4[q][k]; }
+};
 
 // Fixed-order workgroup reduction of M per-thread sums into partials[m * nblk + block].
 template <int M>
@@ -174,7 +96,7 @@ __global__ __launch_bounds__(kPwThreads) void heval_epi_kernel(PwParams P, Heval
         const double n1 = sq2(s1), n2 = sq2(s2);
         const double V = trap_at(P, i);
         double e = 0.0, d1 = 0.0, d2 = 0.0;
-        if (P.lhy_on) lhy_point(P, n1, n2, e, d1, d2);
+        if (P.lhy_on) lhy_point(KernargNodes{P}, P.n_u, P.K5, P.K3, n1, n2, e, d1, d2);
         const double m1 = d1 / P.Nat[0], m2 = d2 / P.Nat[1];
         const double U1 = V + P.G[0][0] * n1 + P.G[0][1] * n2 + P.Gdd[0][0] * ph.x + P.Gdd[0][1] * ph.y + m1;
         const double U2 = V + P.G[1][0] * n1 + P.G[1][1] * n2 + P.Gdd[1][0] * ph.x + P.Gdd[1][1] * ph.y + m2;
@@ -310,7 +232,7 @@ __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirAr
         A.rho[i] = make_double2(rho[0], rho[1]);
         if (P.lhy_on) {
             double L1, L2;
-            lhy_model(P, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
+            lhy_model(KernargNodes{P}, P.n_u, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
             acc[14] += L1;
             acc[15] += L2;
         }

@@ -168,6 +168,66 @@ class Context:
                 "dc_lhy": dc.value}
 
 
+class Batch:
+    """Many independent instances solved together (bec_batch_*).
+
+    Instances with the same grid shape share every kernel launch; the CG
+    decisions run on the device; ``use_graph`` replays a captured hipGraph of
+    ``rounds_per_sync`` rounds between host checks."""
+
+    def __init__(self, grids: list, params: list, device: str | torch.device = "cuda:0", stream=None):
+        if len(grids) != len(params) or not grids:
+            raise ValueError("need one params dict per grid")
+        self.n = len(grids)
+        self.device = torch.device(device)
+        self.shapes = [(2, *[int(v) for v in g["n"]]) for g in grids]
+        L = B.lib()
+        self._g = (B.Grid * self.n)(*[B.make_grid(g) for g in grids])
+        self._p = (B.Params * self.n)(*[B.make_params(p) for p in params])
+        nbytes = C.c_size_t()
+        B.check(L.bec_batch_workspace_size(self.n, self._g, self._p, C.byref(nbytes)), "bec_batch_workspace_size")
+        self.workspace_bytes = int(nbytes.value)
+        with torch.cuda.device(self.device):
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            self._ws_ptr = (self._ws.data_ptr() + 255) // 256 * 256
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._b = C.c_void_p()
+        B.check(L.bec_batch_create(self.n, self._g, self._p, C.c_void_p(self.stream.cuda_stream),
+                                   C.c_void_p(self._ws_ptr), C.c_size_t(self.workspace_bytes), C.byref(self._b)),
+                "bec_batch_create")
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            B.lib().bec_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, psi0: list, opts: dict | None = None, rounds_per_sync: int = 16, use_graph: bool = True):
+        """Returns (list of final states, list of reports)."""
+        if len(psi0) != self.n:
+            raise ValueError(f"need {self.n} initial states")
+        psi = []
+        for k, x in enumerate(psi0):
+            if not isinstance(x, torch.Tensor):
+                x = torch.as_tensor(np.asarray(x))
+            x = x.to(device=self.device, dtype=torch.complex128).contiguous().clone()
+            if tuple(x.shape) != self.shapes[k]:
+                raise ValueError(f"instance {k}: expected shape {self.shapes[k]}, got {tuple(x.shape)}")
+            psi.append(x)
+        ptrs = (C.c_void_p * self.n)(*[t.data_ptr() for t in psi])
+        reps = (B.Report * self.n)()
+        B.check(B.lib().bec_batch_solve(self._b, ptrs, C.byref(B.make_opts(opts)), int(rounds_per_sync),
+                                        int(bool(use_graph)), reps), "bec_batch_solve")
+        out = [{"iters": r.iters, "n_restarts": r.n_restarts, "n_backtracks": r.n_backtracks,
+                "status": B.STATUS[r.status], "final": r.final.to_dict(), "seconds": r.seconds} for r in reps]
+        return psi, out
+
+
 def theta_of(params: dict) -> torch.Tensor:
     """Coupling vector (G11, G12, G21, G22, Gdd11, Gdd12, Gdd21, Gdd22, c_lhy) in float64."""
     G, D = params["G"], params["Gdd"]

@@ -1,0 +1,97 @@
+"""The batched multi-instance solver against individual solves, the oracle,
+graph replay against eager launches, and a host-forced stagnation."""
+import numpy as np
+import pytest
+
+from paper_2510_24543_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def solver():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2510_24543_amd import solver as s
+    return s
+
+
+def small_scan(n_inst=6, seed=77):
+    """Uneven grids (16^3, 32^3, 16x32x32 cycling) and seeded couplings."""
+    shapes = [(16, 16, 16), (32, 32, 32), (16, 32, 32)]
+    out = []
+    for k in range(n_inst):
+        u = inputs.unit_stream(seed, np.arange(3 * k + 1, 3 * k + 4, dtype=np.uint64))
+        g12, gdd, c = 20 + 70 * u[0], 30 + 60 * u[1], 1 + 5 * u[2]
+        grid = {"n": list(shapes[k % 3]), "lo": [-6.0] * 3, "hi": [6.0] * 3}
+        params = {"N": [1.0, 1.0], "omega": [1.0, 1.0, 2.0], "G": [[80.0, g12], [g12, 80.0]],
+                  "Gdd": [[gdd, gdd], [gdd, gdd]], "c_lhy": c, "r_cut": 6.0, "n_u": 16}
+        out.append((grid, params, inputs.initial_state(grid, params["omega"], 500 + k)))
+    return out
+
+
+OPTS = {"tol_grad": 1e-10, "max_iter": 4000, "pc": 1}
+
+
+def test_batch_matches_individual_solves(solver):
+    scan = small_scan()
+    b = solver.Batch([s[0] for s in scan], [s[1] for s in scan])
+    psis, reps = b.solve([s[2] for s in scan], OPTS, rounds_per_sync=8, use_graph=True)
+    for (grid, params, psi0), psi_b, rb in zip(scan, psis, reps):
+        ctx = solver.Context(grid, params)
+        psi_s, rs, _ = ctx.solve(torch.from_numpy(psi0), OPTS)
+        assert rb["status"] == "OK" and rs["status"] == "OK", (rb["status"], rs["status"])
+        assert max(rb["final"]["res"]) < 1e-10
+        assert abs(rb["final"]["E"] - rs["final"]["E"]) <= 1e-10 * abs(rs["final"]["E"])
+        nb = np.abs(psi_b.cpu().numpy()) ** 2
+        ns = np.abs(psi_s.cpu().numpy()) ** 2
+        assert np.max(np.abs(nb - ns)) < 1e-7
+        assert abs(rb["iters"] - rs["iters"]) <= max(5, rs["iters"] // 10)
+
+
+def test_batch_matches_oracle(solver, orc):
+    grid, params, psi0 = small_scan(2)[1]
+    b = solver.Batch([grid], [params])
+    psis, reps = b.solve([psi0], OPTS)
+    psio, repo, _ = orc.solve(grid, params, psi0, OPTS)
+    assert reps[0]["status"] == "OK" and repo["status"] == "OK"
+    assert abs(reps[0]["final"]["E"] - repo["final"]["E"]) <= 1e-10 * abs(repo["final"]["E"])
+    assert np.max(np.abs(np.abs(psis[0].cpu().numpy()) ** 2 - np.abs(psio) ** 2)) < 1e-7
+
+
+def test_graph_replay_equals_eager_launches(solver):
+    scan = small_scan(4, seed=91)
+    grids, params, psi0 = [s[0] for s in scan], [s[1] for s in scan], [s[2] for s in scan]
+    b = solver.Batch(grids, params)
+    eager, re = b.solve(psi0, OPTS, rounds_per_sync=4, use_graph=False)
+    torch.cuda.synchronize()
+    g1, r1 = b.solve(psi0, OPTS, rounds_per_sync=4, use_graph=True)
+    torch.cuda.synchronize()
+    g2, r2 = b.solve(psi0, OPTS, rounds_per_sync=4, use_graph=True)     # the same graph replayed again
+    for k in range(len(scan)):
+        for other, ro in ((g1, r1), (g2, r2)):
+            assert torch.equal(eager[k], other[k]), k
+            assert re[k]["final"]["E"] == ro[k]["final"]["E"] and re[k]["iters"] == ro[k]["iters"]
+
+
+def test_batch_reports_stagnation_forced_from_the_host(solver):
+    """A negative acceptance band makes every trial fail: Armijo halvings, the
+    beta = 0 restart, then a stagnation report -- the same outcome as bec_solve."""
+    grid, params, psi0 = small_scan(1)[0]
+    opts = dict(OPTS, tau_rel=-1.0, max_backtrack=3)
+    b = solver.Batch([grid], [params])
+    _, reps = b.solve([psi0], opts, rounds_per_sync=4)
+    ctx = solver.Context(grid, params)
+    _, rs, _ = ctx.solve(torch.from_numpy(psi0), opts)
+    assert reps[0]["status"] == "ESTAGNATED" and rs["status"] == "ESTAGNATED"
+    assert reps[0]["iters"] == rs["iters"] == 0
+    assert reps[0]["n_backtracks"] == rs["n_backtracks"]
+
+
+def test_batch_rejects_kinetic_preconditioner(solver):
+    grid, params, psi0 = small_scan(1)[0]
+    b = solver.Batch([grid], [params])
+    with pytest.raises(solver.B.BecError, match="EUNSUPPORTED"):
+        b.solve([psi0], dict(OPTS, pc=2))
