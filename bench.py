@@ -67,6 +67,57 @@ def cpu_baseline(grid, params, psi0, sample_iters: int):
                       f"oracle solve, {t2 - t0:.1f} s of CPU work)"}
 
 
+def scan_comparison(n_inst: int, use_graph: bool = True):
+    """Parameter scan of n_inst instances (grids cycling 48^3, 64^3, 96^3; seeded
+    g12, gdd, LHY): one batched solve against the same instances solved one after
+    another with the plain solver, both to |grad E| < 1e-10 from the same seeded
+    starts.  Times are HIP-event times of the solve calls only."""
+    import torch
+    from paper_2510_24543_amd import inputs, solver
+
+    scan = inputs.scan_instances(n_inst)
+    grids = [s["grid"] for s in scan]
+    params = [s["params"] for s in scan]
+    psi0 = [torch.from_numpy(inputs.initial_state(s["grid"], s["params"]["omega"], s["seed"])).cuda()
+            for s in scan]
+    opts = {"pc": 1, "beta": 0, "restart_period": 50, "tol_grad": 1e-10, "max_iter": 5000}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    b = solver.Batch(grids, params)
+    b.solve(psi0, dict(opts, max_iter=2), use_graph=use_graph)   # warm-up (graph build)
+    torch.cuda.synchronize()
+    ev0.record(b.stream)
+    _, brep = b.solve(psi0, opts, use_graph=use_graph)
+    ev1.record(b.stream)
+    torch.cuda.synchronize()
+    t_batch = ev0.elapsed_time(ev1) / 1000.0
+    b.close()
+    del b
+
+    t_seq = 0.0
+    max_rel = 0.0
+    seq_iters = []
+    for k, s in enumerate(scan):
+        ctx = solver.Context(s["grid"], s["params"])
+        torch.cuda.synchronize()
+        ev0.record(ctx.stream)
+        _, rep, _ = ctx.solve(psi0[k], opts)
+        ev1.record(ctx.stream)
+        torch.cuda.synchronize()
+        t_seq += ev0.elapsed_time(ev1) / 1000.0
+        seq_iters.append(rep["iters"])
+        if rep["status"] == "OK" and brep[k]["status"] == "OK":
+            max_rel = max(max_rel, abs(rep["final"]["E"] - brep[k]["final"]["E"]) / abs(rep["final"]["E"]))
+        ctx.close()
+        del ctx
+    return {"instances": n_inst, "grids": "48^3/64^3/96^3 cycling", "tol_grad": 1e-10,
+            "batched_s": round(t_batch, 4), "sequential_plain_s": round(t_seq, 4),
+            "speedup": round(t_seq / t_batch, 3), "graph": use_graph,
+            "batched_converged": sum(r["status"] == "OK" for r in brep),
+            "max_rel_dE_vs_plain": max_rel,
+            "iters_batched_total": sum(r["iters"] for r in brep), "iters_plain_total": sum(seq_iters)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +125,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=5, help="oracle iterations for the CPU baseline (0: skip)")
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution solve")
+    ap.add_argument("--scan", type=int, default=96, help="instances of the batched-vs-plain scan (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU decomposition is a design note, "
@@ -139,6 +191,8 @@ def main():
                 "traffic": traffic, "avg_us": round(dom["avg_us"], 2),
                 "bytes_per_launch": dom["bytes_per_launch"]}
 
+    scan = scan_comparison(args.scan) if args.scan > 0 else None
+
     cpu = None
     if args.cpu_sample > 0:
         cpu = cpu_baseline(grid, params, psi0_np, args.cpu_sample)
@@ -153,6 +207,7 @@ def main():
                                "P_V + HS+ (restart 50), FP64",
                    "grid": grid["n"], "points": ctx.N, "components": 2},
         "time_to_solution": tts,
+        "batched_vs_plain": scan,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in kk.items()} for kk in kernels],

@@ -404,6 +404,7 @@ FftPassArgs pass_args(bec_ctx* c, int axis)
     A.partials = c->fft_partials;
     A.nblk_x = c->nblk_x;
     A.n_inst = 1;
+    A.inst_ids = nullptr;
     for (int f = 0; f < 3; ++f) A.src_stride[f] = A.dst_stride[f] = A.src_sel_stride[f] = 0;
     A.src_sel = nullptr;
     A.active = nullptr;
@@ -1213,6 +1214,9 @@ struct BatchGroup {
     double *partials = nullptr, *fft_partials = nullptr, *udtab = nullptr, *kv[3] = {}, *vv[3] = {};
     double2* tw[3] = {};
     long long udsize = 0;
+    int* ids_all = nullptr;        // device: 0..count-1
+    int* ids_act = nullptr;        // device: running instances (compacted launches)
+    std::vector<int> act;          // host copy of the running list
     bec::BGroup g{};
 };
 
@@ -1337,7 +1341,8 @@ size_t batch_layout(int n_inst, const bec_grid* grids, std::vector<size_t>* off)
                        cnt * ud * sizeof(double),                             // dipolar tables
                        cnt * g.n[0] * sizeof(double), cnt * g.n[1] * sizeof(double), cnt * g.n[2] * sizeof(double),
                        cnt * g.n[0] * sizeof(double), cnt * g.n[1] * sizeof(double), cnt * g.n[2] * sizeof(double),
-                       g.n[0] * c2, g.n[1] * c2, g.n[2] * c2};
+                       g.n[0] * c2, g.n[1] * c2, g.n[2] * c2,
+                       2 * (size_t)cnt * sizeof(int)};                          // instance id lists
         for (size_t s : gs) sizes.push_back(s);
     }
     size_t total = 0;
@@ -1400,7 +1405,8 @@ FftPassArgs batch_pass_args(const BatchGroup& G, int axis, const int* active)
     A.scale = 1.0;
     A.partials = G.fft_partials;
     A.nblk_x = G.nblk_x;
-    A.n_inst = G.count;
+    A.n_inst = G.g.n_ids;
+    A.inst_ids = G.g.ids;
     A.active = active + G.first;
     A.src_sel = nullptr;
     if (axis == 2) {
@@ -1489,14 +1495,15 @@ bec_status batch_ls_fft(bec_batch* b, const BatchGroup& G)
 
 bec_status breduce(bec_batch* b, const BatchGroup& G, int M, int off)
 {
-    HIPCHK(bec::launch_b_reduce(G.partials, (long long)bec::kMaxSums * G.nblk, G.nblk, G.nblk, M, G.count,
-                                b->sums + (long long)G.first * bec::kBSumStride, off, b->st));
+    HIPCHK(bec::launch_b_reduce(G.partials, (long long)bec::kMaxSums * G.nblk, G.nblk, G.nblk, M, G.g.ids,
+                                G.g.n_ids, b->sums + (long long)G.first * bec::kBSumStride, off, b->st));
     return BEC_OK;
 }
 
 bec_status batch_trial_and_accept(bec_batch* b, const bec::BOpts& o)
 {
     for (auto& G : b->groups) {
+        if (G.g.n_ids == 0) continue;
         HIPCHK(bec::launch_b_trial(G.g, b->st));
         STCHK(batch_heval_fft(b, G, b->st));
         HIPCHK(bec::launch_b_heval_epi(G.g, b->st));
@@ -1510,17 +1517,19 @@ bec_status batch_trial_and_accept(bec_batch* b, const bec::BOpts& o)
 bec_status batch_round(bec_batch* b, const bec::BOpts& o)
 {
     for (auto& G : b->groups) {
+        if (G.g.n_ids == 0) continue;
         HIPCHK(bec::launch_b_dir_reduce(G.g, b->st));
         STCHK(breduce(b, G, bec::kDirReduceSums, bec::kSR));
     }
     HIPCHK(bec::launch_b_decide_dir(b->n_inst, o, b->ip, b->state, b->sums, b->act_dir, b->st));
     for (auto& G : b->groups) {
+        if (G.g.n_ids == 0) continue;
         HIPCHK(bec::launch_b_dir_write(G.g, b->st));
         STCHK(breduce(b, G, bec::kDirWriteSums, bec::kSW));
         STCHK(batch_ls_fft(b, G));
         HIPCHK(bec::launch_b_ls_epi(G.g, b->st));
         STCHK(breduce(b, G, bec::kLsEpiSums, bec::kSL));
-        HIPCHK(bec::launch_b_reduce(G.fft_partials, 3LL * G.nblk_x, G.nblk_x, G.nblk_x, 2, G.count,
+        HIPCHK(bec::launch_b_reduce(G.fft_partials, 3LL * G.nblk_x, G.nblk_x, G.nblk_x, 2, G.g.ids, G.g.n_ids,
                                     b->sums + (long long)G.first * bec::kBSumStride, bec::kSP, b->st));
     }
     HIPCHK(bec::launch_b_decide_step(b->n_inst, o, b->ip, b->state, b->sums, b->act_dir, b->act_trial, b->tsel,
@@ -1623,6 +1632,16 @@ bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_par
             for (int d = 0; d < 3; ++d) G.kv[d] = (double*)(base + off[k++]);
             for (int d = 0; d < 3; ++d) G.vv[d] = (double*)(base + off[k++]);
             for (int d = 0; d < 3; ++d) G.tw[d] = (double2*)(base + off[k++]);
+            G.ids_all = (int*)(base + off[k++]);
+            G.ids_act = G.ids_all + G.count;
+            {
+                std::vector<int> iota(G.count);
+                for (int l = 0; l < G.count; ++l) iota[l] = l;
+                if (hipMemcpyAsync(G.ids_all, iota.data(), G.count * sizeof(int), hipMemcpyHostToDevice, b->st) !=
+                        hipSuccess ||
+                    hipStreamSynchronize(b->st) != hipSuccess)
+                    return cleanup(fail(BEC_EHIP, "upload of instance lists"));
+            }
             // per-instance tables
             std::vector<double> ud_all, kv_all[3], vv_all[3];
             for (int l = 0; l < G.count; ++l) {
@@ -1676,6 +1695,8 @@ bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_par
             g.rho = G.rho;
             g.W = G.W;
             g.partials = G.partials;
+            g.ids = G.ids_all;
+            g.n_ids = G.count;
             b->groups.push_back(G);
         }
         if (hipStreamSynchronize(b->st) != hipSuccess) return cleanup(fail(BEC_EHIP, "synchronise"));
@@ -1716,6 +1737,12 @@ bec_status bec_batch_solve(bec_batch* b, double* const* psi_inout, const bec_opt
         b->host_ptrs[i] = psi_inout[b->perm[i]];
     }
     HIPCHK(hipMemcpyAsync(b->psi_user, b->host_ptrs, b->n_inst * sizeof(double*), hipMemcpyHostToDevice, b->st));
+    for (auto& G : b->groups) {
+        G.g.ids = G.ids_all;
+        G.g.n_ids = G.count;
+        G.act.assign(G.count, 0);
+        for (int l = 0; l < G.count; ++l) G.act[l] = l;
+    }
     // initial state: normalise and evaluate
     for (auto& G : b->groups) {
         HIPCHK(bec::launch_b_norm2(G.g, b->st));
@@ -1724,34 +1751,38 @@ bec_status bec_batch_solve(bec_batch* b, double* const* psi_inout, const bec_opt
     HIPCHK(bec::launch_b_decide_init(b->n_inst, b->ip, b->state, b->sums, b->act_dir, b->act_trial, b->tsel, b->st));
     STCHK(batch_trial_and_accept(b, bo));
 
-    if (use_graph && (!b->exec || b->graph_rounds != K || !same_bopts(b->graph_opts, bo))) {
-        if (b->exec) {
-            HIPCHK(hipGraphExecDestroy(b->exec));
-            b->exec = nullptr;
-        }
-        hipStream_t user = b->st;
-        b->st = b->cap;
-        HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-        bec_status cs = BEC_OK;
-        for (int r = 0; r < K && cs == BEC_OK; ++r) cs = batch_round(b, bo);
-        hipGraph_t graph = nullptr;
-        const hipError_t ce = hipStreamEndCapture(b->cap, &graph);
-        b->st = user;
-        if (cs != BEC_OK) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return cs;
-        }
-        if (ce != hipSuccess) return fail(BEC_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
-        const hipError_t ie = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ie != hipSuccess) return fail(BEC_EHIP, "graph instantiation failed: %s", hipGetErrorString(ie));
-        b->graph_rounds = K;
-        b->graph_opts = bo;
-    }
+    // Rounds are launched in chunks of K; between chunks the host reads the
+    // instance states and compacts every launch to the instances still running
+    // (the graph is re-captured when that set changes).
+    bool dirty = true;
     const long long max_rounds = (long long)(o->max_iter + 1) * (o->max_backtrack + 3) + 8;
     long long rounds = 0;
     for (;;) {
         if (use_graph) {
+            if (dirty || !b->exec || b->graph_rounds != K || !same_bopts(b->graph_opts, bo)) {
+                if (b->exec) {
+                    HIPCHK(hipGraphExecDestroy(b->exec));
+                    b->exec = nullptr;
+                }
+                hipStream_t user = b->st;
+                b->st = b->cap;
+                HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+                bec_status cs = BEC_OK;
+                for (int r = 0; r < K && cs == BEC_OK; ++r) cs = batch_round(b, bo);
+                hipGraph_t graph = nullptr;
+                const hipError_t ce = hipStreamEndCapture(b->cap, &graph);
+                b->st = user;
+                if (cs != BEC_OK) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return cs;
+                }
+                if (ce != hipSuccess) return fail(BEC_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
+                const hipError_t ie = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (ie != hipSuccess) return fail(BEC_EHIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+                b->graph_rounds = K;
+                b->graph_opts = bo;
+            }
             HIPCHK(hipGraphLaunch(b->exec, b->st));
         } else {
             for (int r = 0; r < K; ++r) STCHK(batch_round(b, bo));
@@ -1761,8 +1792,32 @@ bec_status bec_batch_solve(bec_batch* b, double* const* psi_inout, const bec_opt
                               b->st));
         HIPCHK(hipStreamSynchronize(b->st));
         bool running = false;
-        for (int i = 0; i < b->n_inst; ++i) running = running || b->host_state[i].status == bec::kBRunning;
+        dirty = false;
+        for (auto& G : b->groups) {
+            std::vector<int> act;
+            for (int l = 0; l < G.count; ++l)
+                if (b->host_state[G.first + l].status == bec::kBRunning) act.push_back(l);
+            running = running || !act.empty();
+            if (act != G.act) {
+                G.act = act;
+                dirty = true;
+                if (!act.empty())
+                    HIPCHK(hipMemcpyAsync(G.ids_act, G.act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice,
+                                          b->st));
+                G.g.ids = G.ids_act;
+                G.g.n_ids = (int)act.size();
+            }
+        }
+        if (dirty) HIPCHK(hipStreamSynchronize(b->st));   // the host list is reused on the next change
         if (!running || rounds >= max_rounds) break;
+    }
+    for (auto& G : b->groups) {
+        G.g.ids = G.ids_all;
+        G.g.n_ids = G.count;
+    }
+    if (b->exec) {
+        HIPCHK(hipGraphExecDestroy(b->exec));
+        b->exec = nullptr;
     }
     for (auto& G : b->groups) HIPCHK(bec::launch_b_copy_out(G.g, b->st));
     HIPCHK(hipStreamSynchronize(b->st));

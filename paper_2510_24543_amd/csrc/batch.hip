@@ -61,7 +61,7 @@ __device__ __forceinline__ void bblock_store(const double (&acc)[M], double* par
 
 __global__ __launch_bounds__(kPwThreads) void b_norm2_kernel(BGroup g)
 {
-    const int l = blockIdx.y, inst = g.first + l;
+    const int l = g.ids[blockIdx.y], inst = g.first + l;
     const long long N = g.N;
     const double2* f = reinterpret_cast<const double2*>(g.psi_user[inst]);
     double acc[2] = {0.0, 0.0};
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kPwThreads) void b_norm2_kernel(BGroup g)
 
 __global__ __launch_bounds__(kPwThreads) void b_trial_kernel(BGroup g)
 {
-    const int l = blockIdx.y, inst = g.first + l;
+    const int l = g.ids[blockIdx.y], inst = g.first + l;
     if (!g.act_trial[inst]) return;
     const BInstState& S = g.st[inst];
     const long long N = g.N;
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kPwThreads) void b_trial_kernel(BGroup g)
 
 __global__ __launch_bounds__(kPwThreads) void b_heval_epi_kernel(BGroup g)
 {
-    const int l = blockIdx.y, inst = g.first + l;
+    const int l = g.ids[blockIdx.y], inst = g.first + l;
     if (!g.act_trial[inst]) return;
     __shared__ double nd[kMaxNodes][4];
     const BInstParams& P = g.ip[inst];
@@ -193,7 +193,7 @@ __device__ __forceinline__ BRZ b_resid(const BGroup& g, const BInstParams& P, co
 
 __global__ __launch_bounds__(kPwThreads) void b_dir_reduce_kernel(BGroup g)
 {
-    const int l = blockIdx.y, inst = g.first + l;
+    const int l = g.ids[blockIdx.y], inst = g.first + l;
     const BInstState& S = g.st[inst];
     if (S.status != kBRunning || S.phase != kBNewDir) return;
     const BInstParams& P = g.ip[inst];
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kPwThreads) void b_dir_reduce_kernel(BGroup g)
 
 __global__ __launch_bounds__(kPwThreads) void b_dir_write_kernel(BGroup g)
 {
-    const int l = blockIdx.y, inst = g.first + l;
+    const int l = g.ids[blockIdx.y], inst = g.first + l;
     if (!g.act_dir[inst]) return;
     __shared__ double nd[kMaxNodes][4];
     const BInstParams& P = g.ip[inst];
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kPwThreads) void b_dir_write_kernel(BGroup g)
 
 __global__ __launch_bounds__(kPwThreads) void b_ls_epi_kernel(BGroup g)
 {
-    const int l = blockIdx.y, inst = g.first + l;
+    const int l = g.ids[blockIdx.y], inst = g.first + l;
     if (!g.act_dir[inst]) return;
     const long long N = g.N;
     const double2* rho = g.rho + (long long)l * N;
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kPwThreads) void b_ls_epi_kernel(BGroup g)
 
 __global__ __launch_bounds__(kPwThreads) void b_copy_out_kernel(BGroup g)
 {
-    const int l = blockIdx.y, inst = g.first + l;
+    const int l = g.ids[blockIdx.y], inst = g.first + l;
     const long long N = g.N;
     const double2* src = g.psi + ((long long)l * 2 + g.st[inst].cur) * 2 * N;
     double2* dst = reinterpret_cast<double2*>(g.psi_user[inst]);
@@ -331,10 +331,11 @@ __global__ __launch_bounds__(kPwThreads) void b_copy_out_kernel(BGroup g)
 }
 
 __global__ __launch_bounds__(256) void b_reduce_kernel(const double* partials, long long inst_stride,
-                                                       long long row_stride, int nblk, double* sums_first, int off)
+                                                       long long row_stride, int nblk, const int* ids,
+                                                       double* sums_first, int off)
 {
     __shared__ double sh[4];
-    const int m = blockIdx.x, l = blockIdx.y;
+    const int m = blockIdx.x, l = ids[blockIdx.y];
     const double* row = partials + (long long)l * inst_stride + (long long)m * row_stride;
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256) s += row[b];
@@ -581,7 +582,7 @@ __global__ void b_decide_accept_kernel(int n, BOpts o, const BInstParams* ip, BI
     }
 }
 
-dim3 bgrid(const BGroup& g) { return dim3((unsigned)g.nblk, (unsigned)g.count); }
+dim3 bgrid(const BGroup& g) { return dim3((unsigned)g.nblk, (unsigned)g.n_ids); }
 dim3 dgrid(int n) { return dim3((unsigned)((n + 63) / 64)); }
 
 }  // namespace
@@ -622,10 +623,10 @@ hipError_t launch_b_copy_out(const BGroup& g, hipStream_t s)
     return hipGetLastError();
 }
 hipError_t launch_b_reduce(const double* partials, long long inst_stride, long long row_stride, int nblk, int M,
-                           int count, double* sums_first, int off, hipStream_t s)
+                           const int* ids, int n_ids, double* sums_first, int off, hipStream_t s)
 {
-    hipLaunchKernelGGL(b_reduce_kernel, dim3((unsigned)M, (unsigned)count), dim3(256), 0, s, partials, inst_stride,
-                       row_stride, nblk, sums_first, off);
+    hipLaunchKernelGGL(b_reduce_kernel, dim3((unsigned)M, (unsigned)n_ids), dim3(256), 0, s, partials, inst_stride,
+                       row_stride, nblk, ids, sums_first, off);
     return hipGetLastError();
 }
 hipError_t launch_b_decide_init(int n, const BInstParams* ip, BInstState* st, const double* sums, int* act_dir,

@@ -72,6 +72,7 @@ struct FftPassArgs {
     // per_inst_tab; instances with active[i] == 0 are skipped
     int n_inst;
     long long src_stride[3], dst_stride[3];   // per-field instance strides (elements)
+    const int* inst_ids;                      // optional: instance of blockIdx.z (compacted launch)
     const int* src_sel;                       // optional: buffer index per instance
     long long src_sel_stride[3];              // src offset += src_sel[i] * src_sel_stride[f]
     const int* active;
@@ -211,6 +212,8 @@ struct BOpts {                    // the bec_opts fields the device decisions us
 
 struct BGroup {
     int first, count;             // global index of the first instance, instances in the group
+    const int* ids;               // [n_ids] local indices this launch covers (grid.y = n_ids)
+    int n_ids;
     int nx, ny, nz;
     long long N;
     int nblk;                     // pointwise blocks per instance
@@ -242,9 +245,9 @@ hipError_t launch_b_dir_reduce(const BGroup& g, hipStream_t s);
 hipError_t launch_b_dir_write(const BGroup& g, hipStream_t s);
 hipError_t launch_b_ls_epi(const BGroup& g, hipStream_t s);
 hipError_t launch_b_copy_out(const BGroup& g, hipStream_t s);
-// sums[first + l][off + m] = sum_b partials[l * inst_stride + m * row_stride + b], m < M
+// for l = ids[y], y < n_ids: sums[first + l][off + m] = sum_b partials[l * inst_stride + m * row_stride + b]
 hipError_t launch_b_reduce(const double* partials, long long inst_stride, long long row_stride, int nblk, int M,
-                           int count, double* sums_first, int off, hipStream_t s);
+                           const int* ids, int n_ids, double* sums_first, int off, hipStream_t s);
 // decision kernels over all n_inst instances
 hipError_t launch_b_decide_init(int n_inst, const BInstParams* ip, BInstState* st, const double* sums,
                                 int* act_dir, int* act_trial, int* tsel, hipStream_t s);

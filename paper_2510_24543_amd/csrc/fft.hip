@@ -226,7 +226,7 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
     constexpr int E = L / T, PB = NTHR / T, RS = L + 1;
     __shared__ double2 lds[PB * RS];
     const int f = blockIdx.y;
-    const int inst = blockIdx.z;
+    const int inst = A.inst_ids ? A.inst_ids[blockIdx.z] : (int)blockIdx.z;
     if (A.active && A.active[inst] == 0) return;   // uniform per block
     const long long soff = (long long)inst * A.src_stride[f] +
                            (A.src_sel ? (long long)A.src_sel[inst] * A.src_sel_stride[f] : 0);
