@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=5, help="oracle iterations for the CPU baseline (0: skip)")
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution solve")
     ap.add_argument("--scan", type=int, default=96, help="instances of the batched-vs-plain scan (0: skip)")
+    ap.add_argument("--tuning", choices=("auto", "cache", "default"), default="auto",
+                    help="launch plans: autotune now, read the committed cache, or the defaults")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU decomposition is a design note, "
@@ -142,6 +144,17 @@ def main():
     ctx = solver.Context(grid, params, dev)
     psi0 = torch.from_numpy(psi0_np).to(dev)
     base_opts = {"pc": 1, "beta": 0, "restart_period": 50, "sigma": 1e-6}
+
+    from paper_2510_24543_amd import autotune
+    tuning = {"mode": args.tuning, "plan": ctx.get_tuning()}
+    if args.tuning == "auto":
+        res = autotune.tune(ctx, psi0=psi0, opts=base_opts)
+        tuning.update(plan=res["tuning"], seconds=res["seconds"], iter_ms=res["iter_ms"])
+    elif args.tuning == "cache":
+        cached = autotune.load_cached(grid)
+        if cached:
+            ctx.set_tuning(cached)
+            tuning["plan"] = cached
 
     # warm-up (untimed)
     if args.warmup > 0:
@@ -207,6 +220,7 @@ def main():
                                "P_V + HS+ (restart 50), FP64",
                    "grid": grid["n"], "points": ctx.N, "components": 2},
         "time_to_solution": tts,
+        "tuning": tuning,
         "batched_vs_plain": scan,
         "roofline": roofline,
         "cpu_baseline": cpu,

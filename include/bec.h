@@ -226,6 +226,33 @@ bec_status bec_batch_destroy(bec_batch* b);
 bec_status bec_batch_solve(bec_batch* b, double* const* psi_inout, const bec_opts* opts, int32_t rounds_per_sync,
                            int32_t use_graph, bec_report* reports_h);
 
+/* ---------------------------------------------------------------------------
+ * Launch tuning.  Every 3D FFT axis pass has several plan variants (threads per
+ * pencil, radix order, workgroup size); the pointwise kernels have a grid size.
+ * The autotuner (paper_2510_24543_amd/autotune.py) times the choices with
+ * bec_time_fft_pass / full iterations and sets the fastest with
+ * bec_set_tuning.  Results are identical up to rounding order for every choice.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t fft_variant[3][2];  /* per axis (x, y, z): [0] plain passes, [1] the x pass with the fused
+                                   k-space operator (only [0][1] is used); 0 = default plan */
+    int32_t pw_blocks;          /* workgroups of the pointwise kernels (64 .. 4096) */
+} bec_tuning;
+
+bec_status bec_get_tuning(bec_ctx* ctx, bec_tuning* out_h);
+bec_status bec_set_tuning(bec_ctx* ctx, const bec_tuning* t);
+
+/* Number of plan variants for an axis of length L (host-only). */
+bec_status bec_fft_variant_count(int32_t L, int32_t* count);
+
+/* Average duration in milliseconds of `reps` launches of one axis pass over the
+ * three fields of the context's work area, with plan `variant`: kind 0 forward,
+ * 1 inverse, 2 the x pass with the fused kinetic / dipolar operators (axis 0
+ * only).  HIP events on the context stream; overwrites the work area (not
+ * the caller's fields).  Synchronises. */
+bec_status bec_time_fft_pass(bec_ctx* ctx, int32_t axis, int32_t kind, int32_t variant, int32_t reps,
+                             double* ms_out);
+
 /* Per-kernel timing statistics (see bec_profile_enable). */
 typedef struct {
     char name[40];          /* kernel class, e.g. "fft_y_fwd", "heval_epilogue"  */

@@ -1,0 +1,112 @@
+"""Autotuner for the launch plans of the library.
+
+For every axis of a grid it times each FFT plan variant of the plain passes
+(forward + inverse) and, for the x axis, of the pass with the fused k-space
+operators (bec_time_fft_pass, HIP events); then it times whole PCG iterations
+(bec_solve) for each candidate grid size of the pointwise kernels.  The
+fastest choices are set on the context and can be stored in a JSON cache keyed
+by device architecture and grid shape.  Every choice computes the same result
+up to rounding order.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+import time
+
+from . import binding as B
+
+CACHE_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
+PW_CHOICES = (256, 512, 1024, 2048, 4096)
+
+
+def variant_count(L: int) -> int:
+    n = C.c_int32()
+    B.check(B.lib().bec_fft_variant_count(int(L), C.byref(n)), "bec_fft_variant_count")
+    return n.value
+
+
+def grid_key(grid: dict) -> str:
+    return "x".join(str(int(n)) for n in grid["n"])
+
+
+def arch() -> str:
+    import torch
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "gfx950"
+
+
+def cache_path(arch_name: str | None = None) -> str:
+    return os.path.join(CACHE_DIR, f"{arch_name or arch()}.json")
+
+
+def load_cached(grid: dict, path: str | None = None):
+    path = path or cache_path()
+    if not os.path.exists(path):
+        return None
+    try:
+        return json.load(open(path)).get(grid_key(grid), {}).get("tuning")
+    except ValueError:
+        return None
+
+
+def store(grid: dict, result: dict, path: str | None = None):
+    path = path or cache_path()
+    data = {}
+    if os.path.exists(path):
+        try:
+            data = json.load(open(path))
+        except ValueError:
+            data = {}
+    data[grid_key(grid)] = result
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+
+
+def tune(ctx, reps: int = 20, iters: int = 4, psi0=None, opts: dict | None = None) -> dict:
+    """Tune ctx in place; returns {"tuning": ..., "fft_ms": ..., "iter_ms": ..., "seconds": ...}."""
+    import torch
+    t0 = time.time()
+    best = ctx.get_tuning()
+    fft_ms = {}
+    for axis in range(3):
+        L = ctx.grid["n"][axis]
+        times = []
+        for v in range(variant_count(L)):
+            times.append(ctx.time_fft_pass(axis, 0, v, reps) + ctx.time_fft_pass(axis, 1, v, reps))
+        best["fft_variant"][axis][0] = int(min(range(len(times)), key=times.__getitem__))
+        fft_ms[f"axis{axis}_plain_fwd+inv"] = [round(x, 5) for x in times]
+        if axis == 0:
+            kt = [ctx.time_fft_pass(0, 2, v, reps) for v in range(variant_count(L))]
+            best["fft_variant"][0][1] = int(min(range(len(kt)), key=kt.__getitem__))
+            fft_ms["axis0_kspace"] = [round(x, 5) for x in kt]
+    ctx.set_tuning(best)
+    # grid of the pointwise kernels: whole PCG iterations
+    if psi0 is None:
+        from . import inputs
+        psi0 = inputs.initial_state(ctx.grid, ctx.params["omega"], 12345)
+    psi0 = ctx.field(psi0)
+    o = dict(opts or {}, tol_grad=0.0, max_iter=iters)
+    cap = min(PW_CHOICES[-1], (ctx.N + 255) // 256)
+    iter_ms = {}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for b in PW_CHOICES:
+        if b > cap:
+            continue
+        best["pw_blocks"] = b
+        ctx.set_tuning(best)
+        ctx.solve(psi0, dict(o, max_iter=1))
+        torch.cuda.synchronize()
+        ev0.record(ctx.stream)
+        ctx.solve(psi0, o)
+        ev1.record(ctx.stream)
+        torch.cuda.synchronize()
+        iter_ms[b] = ev0.elapsed_time(ev1) / iters
+    best["pw_blocks"] = int(min(iter_ms, key=iter_ms.get))
+    ctx.set_tuning(best)
+    return {"tuning": best, "fft_ms": fft_ms, "iter_ms": {str(k): round(v, 5) for k, v in iter_ms.items()},
+            "seconds": round(time.time() - t0, 3)}

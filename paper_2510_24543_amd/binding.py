@@ -67,6 +67,10 @@ class Report(C.Structure):
                 ("status", C.c_int32), ("final", Terms), ("seconds", C.c_double)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("fft_variant", (C.c_int32 * 2) * 3), ("pw_blocks", C.c_int32)]
+
+
 class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("total_ms", C.c_double),
                 ("total_bytes", C.c_double)]
@@ -93,6 +97,10 @@ SIGNATURES = [
                                    C.POINTER(_VP)]),
     ("bec_batch_destroy", C.c_int, [_VP]),
     ("bec_batch_solve", C.c_int, [_VP, C.POINTER(_VP), C.POINTER(Opts), _I32, _I32, C.POINTER(Report)]),
+    ("bec_get_tuning", C.c_int, [_VP, C.POINTER(Tuning)]),
+    ("bec_set_tuning", C.c_int, [_VP, C.POINTER(Tuning)]),
+    ("bec_fft_variant_count", C.c_int, [_I32, C.POINTER(_I32)]),
+    ("bec_time_fft_pass", C.c_int, [_VP, _I32, _I32, _I32, _I32, _DP]),
     ("bec_profile_enable", C.c_int, [_VP, _I32]),
     ("bec_profile_read", C.c_int, [_VP, C.POINTER(KernelStat), _I32, C.POINTER(_I32)]),
     ("bec_gauss_legendre", C.c_int, [_I32, _DP, _DP]),

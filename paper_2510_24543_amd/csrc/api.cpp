@@ -180,6 +180,7 @@ struct bec_ctx {
     double* host = nullptr;   // pinned scalars
     int nblk_pw = 0;
     int nblk_x = 0;
+    int fft_var[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // plan variant per axis: [plain, fused k-space]
     PwParams P{};
     Prof prof;
 };
@@ -251,7 +252,7 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
     const long long N = (long long)n[0] * n[1] * n[2];
     const size_t c2 = sizeof(double2);
     const long long nb_pw = std::min<long long>((N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwMaxBlocks);
-    const long long nb_x = bec::fft_blocks(n[0], (long long)n[1] * n[2]);
+    const long long nb_x = bec::fft_max_blocks(n[0], (long long)n[1] * n[2]);
     size_t sizes[] = {
         2 * N * c2, 2 * N * c2,                    // psi[0], psi[1]
         2 * N * c2, 2 * N * c2,                    // hpsi[0], hpsi[1]
@@ -384,6 +385,7 @@ bec_status upload_params(bec_ctx* c, bool dipolar_table)
     P.vx = c->vv[0];
     P.vy = c->vv[1];
     P.vz = c->vv[2];
+    P.nblk_pw = c->nblk_pw;
     return BEC_OK;
 }
 
@@ -444,7 +446,7 @@ bec_status run_pass(bec_ctx* c, int axis, const double2* const* src, double2* co
     else if (axis == 2) name = sign < 0 ? "fft_z_fwd" : "fft_z_inv";
     else if (axis == 1) name = sign < 0 ? "fft_y_fwd" : "fft_y_inv";
     else name = sign < 0 ? "fft_x_fwd" : "fft_x_inv";
-    LAUNCH(c, name, bytes, bec::fft_pass(c->n[axis], axis == 2, A, c->st));
+    LAUNCH(c, name, bytes, bec::fft_pass(c->n[axis], c->fft_var[axis][ops ? 1 : 0], axis == 2, A, c->st));
     return BEC_OK;
 }
 
@@ -802,8 +804,8 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
         c->partials = (double*)at(22);
         c->fft_partials = (double*)at(23);
         c->scal = (double*)at(24);
-        c->nblk_pw = (int)std::min<long long>((c->N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwMaxBlocks);
-        c->nblk_x = bec::fft_blocks(c->n[0], (long long)c->n[1] * c->n[2]);
+        c->nblk_pw = (int)std::min<long long>((c->N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwDefaultBlocks);
+        c->nblk_x = bec::fft_blocks(c->n[0], c->fft_var[0][1], (long long)c->n[1] * c->n[2]);
         if (hipHostMalloc((void**)&c->host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             delete c;
             return fail(BEC_EHIP, "hipHostMalloc of the scalar buffer failed");
@@ -838,6 +840,72 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
     } catch (...) {
         return fail(BEC_EINVAL, "unexpected host exception in bec_create");
     }
+}
+
+bec_status bec_get_tuning(bec_ctx* c, bec_tuning* t)
+{
+    if (!c || !t) return fail(BEC_EINVAL, "null argument");
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 2; ++k) t->fft_variant[a][k] = c->fft_var[a][k];
+    t->pw_blocks = c->nblk_pw;
+    return BEC_OK;
+}
+
+bec_status bec_set_tuning(bec_ctx* c, const bec_tuning* t)
+{
+    if (!c || !t) return fail(BEC_EINVAL, "null argument");
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 2; ++k)
+            if (t->fft_variant[a][k] < 0 || t->fft_variant[a][k] >= bec::fft_num_variants(c->n[a]))
+                return fail(BEC_EINVAL, "axis %d has no plan variant %d", a, t->fft_variant[a][k]);
+    const long long cap = std::min<long long>((c->N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwMaxBlocks);
+    if (t->pw_blocks < 1 || t->pw_blocks > cap) return fail(BEC_EINVAL, "pw_blocks must be in 1..%lld", cap);
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 2; ++k) c->fft_var[a][k] = t->fft_variant[a][k];
+    c->nblk_pw = t->pw_blocks;
+    c->P.nblk_pw = c->nblk_pw;
+    c->nblk_x = bec::fft_blocks(c->n[0], c->fft_var[0][1], (long long)c->n[1] * c->n[2]);
+    return BEC_OK;
+}
+
+bec_status bec_fft_variant_count(int32_t L, int32_t* count)
+{
+    if (!count) return fail(BEC_EINVAL, "null argument");
+    *count = bec::fft_num_variants(L);
+    return *count > 0 ? BEC_OK : fail(BEC_EUNSUPPORTED, "length %d not supported", L);
+}
+
+bec_status bec_time_fft_pass(bec_ctx* c, int32_t axis, int32_t kind, int32_t variant, int32_t reps, double* ms_out)
+{
+    if (!c || !ms_out) return fail(BEC_EINVAL, "null argument");
+    if (axis < 0 || axis > 2 || kind < 0 || kind > 2 || (kind == 2 && axis != 0) || reps < 1)
+        return fail(BEC_EINVAL, "bad axis / kind / reps");
+    if (variant < 0 || variant >= bec::fft_num_variants(c->n[axis]))
+        return fail(BEC_EINVAL, "axis %d has no plan variant %d", axis, variant);
+    const long long N = c->N;
+    const double2* src[3] = {c->W, c->W + N, c->W + 2 * N};
+    double2* dst[3] = {c->W, c->W + N, c->W + 2 * N};
+    const int ops[3] = {bec::kOpMulKin, bec::kOpMulKin, bec::kOpMulDip};
+    const int saved = c->fft_var[axis][kind == 2 ? 1 : 0];
+    c->fft_var[axis][kind == 2 ? 1 : 0] = variant;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    bec_status st = BEC_OK;
+    const int sign = kind == 1 ? +1 : -1;
+    st = run_pass(c, axis, src, dst, 3, sign, 1.0, kind == 2 ? ops : nullptr, nullptr);   // warm-up
+    if (st == BEC_OK && hipEventRecord(e0, c->st) != hipSuccess) st = fail(BEC_EHIP, "event record");
+    for (int r = 0; r < reps && st == BEC_OK; ++r)
+        st = run_pass(c, axis, src, dst, 3, sign, 1.0, kind == 2 ? ops : nullptr, nullptr);
+    float ms = 0.f;
+    if (st == BEC_OK && (hipEventRecord(e1, c->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = fail(BEC_EHIP, "event timing");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->fft_var[axis][kind == 2 ? 1 : 0] = saved;
+    if (st == BEC_OK) *ms_out = ms / reps;
+    return st;
 }
 
 bec_status bec_profile_enable(bec_ctx* c, int32_t on)
@@ -1331,7 +1399,7 @@ size_t batch_layout(int n_inst, const bec_grid* grids, std::vector<size_t>* off)
         const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
         const long long cnt = r.second;
         const int nblk = group_nblk(N);
-        const int nbx = bec::fft_blocks(g.n[0], (long long)g.n[1] * g.n[2]);
+        const int nbx = bec::fft_blocks(g.n[0], 0, (long long)g.n[1] * g.n[2]);
         const size_t ud = (size_t)(g.n[0] / 2 + 1) * (g.n[1] / 2 + 1) * (g.n[2] / 2 + 1);
         size_t gs[] = {cnt * 4 * N * c2, cnt * 4 * N * c2, cnt * 4 * N * c2,  // psi, hpsi, aux (2 buffers)
                        cnt * 2 * N * c2, cnt * 2 * N * c2, cnt * N * c2,      // p, r_old, rho
@@ -1431,7 +1499,7 @@ bec_status bpass(bec_batch* b, const BatchGroup& G, FftPassArgs A, int axis, int
 {
     A.nfield = nf;
     A.sign = sign;
-    HIPCHK(bec::fft_pass(G.n[axis], axis == 2, A, b->st));
+    HIPCHK(bec::fft_pass(G.n[axis], 0, axis == 2, A, b->st));
     return BEC_OK;
 }
 
@@ -1617,7 +1685,7 @@ bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_par
             G.first = r.first;
             G.count = r.second;
             G.nblk = group_nblk(G.N);
-            G.nblk_x = bec::fft_blocks(G.n[0], (long long)G.n[1] * G.n[2]);
+            G.nblk_x = bec::fft_blocks(G.n[0], 0, (long long)G.n[1] * G.n[2]);
             G.udsize = (long long)(G.n[0] / 2 + 1) * (G.n[1] / 2 + 1) * (G.n[2] / 2 + 1);
             G.psi = (double2*)(base + off[k++]);
             G.hpsi = (double2*)(base + off[k++]);

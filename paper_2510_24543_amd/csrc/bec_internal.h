@@ -10,7 +10,8 @@ namespace bec {
 constexpr int kMaxNodes = 64;        // Gauss-Legendre nodes for the LHY u integral
 constexpr int kNodeStride = 8;       // doubles per node in the node table
 constexpr int kPwThreads = 256;      // threads per block of the pointwise kernels
-constexpr int kPwMaxBlocks = 2048;   // grid of the pointwise kernels (fixed per size)
+constexpr int kPwMaxBlocks = 4096;   // largest grid of the pointwise kernels
+constexpr int kPwDefaultBlocks = 1024;
 constexpr int kMaxSums = 32;         // reduced scalars per pass
 
 // Per-node table entry (kNodeStride doubles):
@@ -35,6 +36,7 @@ struct PwParams {
     const double* vx;          // 1/2 omega_x^2 x^2 per x index
     const double* vy;
     const double* vz;
+    int nblk_pw;               // grid of the pointwise kernels
 };
 
 // ---------------------------------------------------------------- FFT passes
@@ -80,10 +82,13 @@ struct FftPassArgs {
     long long udsize;      // doubles per instance in udtab
 };
 
-// Launch one axis pass of length L over args.nfield fields. axis: 0 x, 1 y, 2 z.
-hipError_t fft_pass(int L, bool contiguous, const FftPassArgs& args, hipStream_t s);
+// Launch one axis pass of length L over args.nfield fields with plan variant
+// `variant` (0 = default); `contiguous` for the z axis.
+hipError_t fft_pass(int L, int variant, bool contiguous, const FftPassArgs& args, hipStream_t s);
 bool fft_supported(int L);
-int fft_blocks(int L, long long npencil);   // grid.x of a pass
+int fft_num_variants(int L);
+int fft_blocks(int L, int variant, long long npencil);   // grid.x of a pass
+int fft_max_blocks(int L, long long npencil);            // over all variants
 
 // ---------------------------------------------------------------- pointwise kernels
 struct TrialArgs {                // psi_dst = a_i psi_src + b_i p ; W2 = n1 + i n2

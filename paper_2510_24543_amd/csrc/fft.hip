@@ -19,6 +19,8 @@
 #include "bec_internal.h"
 #include "dft_consts.h"
 
+#include <algorithm>
+
 namespace bec {
 namespace {
 
@@ -365,49 +367,75 @@ hipError_t launch_cfg(bool contiguous, const FftPassArgs& A, hipStream_t st)
 
 }  // namespace
 
-// Per-length plans: threads per pencil T, radices, threads per workgroup.
+// Plan variants per length: threads per pencil T, radices (R0, R1, R2), threads
+// per workgroup.  Variant 0 is the default; the autotuner picks among them.
+struct Variant {
+    int T, R0, R1, R2, nthr;
+};
+
+#define BEC_FFT_VARIANTS(X)                                                                          \
+    X(8, 0, 1, 8, 1, 1, 128) X(8, 1, 1, 8, 1, 1, 64) X(8, 2, 1, 8, 1, 1, 256)                        \
+    X(16, 0, 4, 4, 4, 1, 256) X(16, 1, 2, 8, 2, 1, 256) X(16, 2, 4, 4, 4, 1, 128)                    \
+    X(32, 0, 4, 8, 4, 1, 256) X(32, 1, 4, 4, 8, 1, 256) X(32, 2, 4, 8, 4, 1, 128)                    \
+    X(32, 3, 8, 4, 4, 2, 256)                                                                        \
+    X(48, 0, 4, 12, 4, 1, 256) X(48, 1, 4, 4, 12, 1, 256) X(48, 2, 4, 12, 4, 1, 128)                 \
+    X(64, 0, 8, 8, 8, 1, 256) X(64, 1, 4, 16, 4, 1, 256) X(64, 2, 8, 8, 8, 1, 128)                   \
+    X(64, 3, 8, 8, 8, 1, 512) X(64, 4, 16, 4, 4, 4, 256)                                             \
+    X(96, 0, 4, 12, 8, 1, 128) X(96, 1, 4, 12, 8, 1, 256) X(96, 2, 8, 6, 4, 4, 256)                  \
+    X(96, 3, 8, 12, 4, 2, 256)                                                                       \
+    X(128, 0, 8, 16, 8, 1, 256) X(128, 1, 8, 8, 16, 1, 256) X(128, 2, 8, 16, 8, 1, 128)              \
+    X(128, 3, 8, 16, 8, 1, 512) X(128, 4, 16, 8, 4, 4, 256)                                          \
+    X(256, 0, 16, 16, 16, 1, 256) X(256, 1, 16, 16, 16, 1, 128) X(256, 2, 16, 16, 16, 1, 512)        \
+    X(256, 3, 32, 8, 8, 4, 256)
+
+static bool find_variant(int L, int v, Variant* out)
+{
+#define BEC_FIND(LL, VV, T, R0, R1, R2, NT)         \
+    if (L == LL && v == VV) {                       \
+        *out = Variant{T, R0, R1, R2, NT};          \
+        return true;                                \
+    }
+    BEC_FFT_VARIANTS(BEC_FIND)
+#undef BEC_FIND
+    return false;
+}
+
 bool fft_supported(int L)
 {
-    switch (L) {
-    case 8: case 16: case 32: case 48: case 64: case 96: case 128: case 256: return true;
-    default: return false;
-    }
+    Variant v;
+    return find_variant(L, 0, &v);
 }
 
-static int pencils_per_block(int L)
+int fft_num_variants(int L)
 {
-    switch (L) {
-    case 8: return 128;      // T=1, 128 threads
-    case 16: return 64;      // T=4, 256
-    case 32: return 64;      // T=4, 256
-    case 48: return 64;      // T=4, 256
-    case 64: return 32;      // T=8, 256
-    case 96: return 32;      // T=4, 128
-    case 128: return 32;     // T=8, 256
-    case 256: return 16;     // T=16, 256
-    default: return 1;
-    }
+    int n = 0;
+    Variant v;
+    while (find_variant(L, n, &v)) ++n;
+    return n;
 }
 
-int fft_blocks(int L, long long npencil)
+int fft_blocks(int L, int variant, long long npencil)
 {
-    const int pb = pencils_per_block(L);
+    Variant v;
+    if (!find_variant(L, variant, &v)) return 0;
+    const int pb = v.nthr / v.T;
     return (int)((npencil + pb - 1) / pb);
 }
 
-hipError_t fft_pass(int L, bool contiguous, const FftPassArgs& A, hipStream_t st)
+int fft_max_blocks(int L, long long npencil)
 {
-    switch (L) {
-    case 8: return launch_cfg<8, 1, 8, 1, 1, 128>(contiguous, A, st);
-    case 16: return launch_cfg<16, 4, 4, 4, 1, 256>(contiguous, A, st);
-    case 32: return launch_cfg<32, 4, 8, 4, 1, 256>(contiguous, A, st);
-    case 48: return launch_cfg<48, 4, 12, 4, 1, 256>(contiguous, A, st);
-    case 64: return launch_cfg<64, 8, 8, 8, 1, 256>(contiguous, A, st);
-    case 96: return launch_cfg<96, 4, 12, 8, 1, 128>(contiguous, A, st);
-    case 128: return launch_cfg<128, 8, 16, 8, 1, 256>(contiguous, A, st);
-    case 256: return launch_cfg<256, 16, 16, 16, 1, 256>(contiguous, A, st);
-    default: return hipErrorInvalidValue;
-    }
+    int m = 0;
+    for (int k = 0; k < fft_num_variants(L); ++k) m = std::max(m, fft_blocks(L, k, npencil));
+    return m;
+}
+
+hipError_t fft_pass(int L, int variant, bool contiguous, const FftPassArgs& A, hipStream_t st)
+{
+#define BEC_CASE(LL, VV, T, R0, R1, R2, NT) \
+    if (L == LL && variant == VV) return launch_cfg<LL, T, R0, R1, R2, NT>(contiguous, A, st);
+    BEC_FFT_VARIANTS(BEC_CASE)
+#undef BEC_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace bec

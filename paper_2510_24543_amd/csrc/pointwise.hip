@@ -383,17 +383,13 @@ __global__ __launch_bounds__(256) void reduce_final_kernel(const double* partial
     if (threadIdx.x == 0) out[m] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
-int pw_blocks(long long N)
-{
-    long long b = (N + kPwThreads - 1) / kPwThreads;
-    return (int)(b < kPwMaxBlocks ? b : kPwMaxBlocks);
-}
+int pw_blocks(const PwParams& P) { return P.nblk_pw; }
 
 }  // namespace
 
 hipError_t launch_trial(const PwParams& P, const TrialArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(trial_kernel, dim3(pw_blocks(P.N)), dim3(kPwThreads), 0, s, P, a);
+    hipLaunchKernelGGL(trial_kernel, dim3(pw_blocks(P)), dim3(kPwThreads), 0, s, P, a);
     return hipGetLastError();
 }
 
@@ -423,7 +419,7 @@ hipError_t launch_ls_epi(const PwParams& P, const LsEpiArgs& a, int nblk, hipStr
 
 hipError_t launch_make_r(const PwParams& P, const MakeRArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(make_r_kernel, dim3(pw_blocks(P.N)), dim3(kPwThreads), 0, s, P, a);
+    hipLaunchKernelGGL(make_r_kernel, dim3(pw_blocks(P)), dim3(kPwThreads), 0, s, P, a);
     return hipGetLastError();
 }
 
@@ -442,14 +438,14 @@ hipError_t launch_norm2(const PwParams& P, const double2* f, double* partials, i
 hipError_t launch_scale2(const PwParams& P, const double2* in, double2* out, double s0, double s1,
                          hipStream_t s)
 {
-    hipLaunchKernelGGL(scale2_kernel, dim3(pw_blocks(P.N)), dim3(kPwThreads), 0, s, P, in, out, s0, s1);
+    hipLaunchKernelGGL(scale2_kernel, dim3(pw_blocks(P)), dim3(kPwThreads), 0, s, P, in, out, s0, s1);
     return hipGetLastError();
 }
 
 hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hpsi, double2* out,
                        double mu0, double mu1, double s0, double s1, int projected, hipStream_t s)
 {
-    hipLaunchKernelGGL(grad_kernel, dim3(pw_blocks(P.N)), dim3(kPwThreads), 0, s, P, psi, hpsi, out, mu0,
+    hipLaunchKernelGGL(grad_kernel, dim3(pw_blocks(P)), dim3(kPwThreads), 0, s, P, psi, hpsi, out, mu0,
                        mu1, s0, s1, projected);
     return hipGetLastError();
 }

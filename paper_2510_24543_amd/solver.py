@@ -145,6 +145,26 @@ class Context:
         log = [{k: getattr(logs[i], k) for k, _ in B.Iter._fields_} for i in range(min(rep.iters, cap))]
         return psi, out, log
 
+    # ------------------------------------------------------------------ tuning
+    def get_tuning(self) -> dict:
+        t = B.Tuning()
+        B.check(B.lib().bec_get_tuning(self._ctx, C.byref(t)), "bec_get_tuning")
+        return {"fft_variant": [[t.fft_variant[a][k] for k in range(2)] for a in range(3)],
+                "pw_blocks": t.pw_blocks}
+
+    def set_tuning(self, tuning: dict):
+        t = B.Tuning()
+        for a in range(3):
+            for k in range(2):
+                t.fft_variant[a][k] = int(tuning["fft_variant"][a][k])
+        t.pw_blocks = int(tuning["pw_blocks"])
+        B.check(B.lib().bec_set_tuning(self._ctx, C.byref(t)), "bec_set_tuning")
+
+    def time_fft_pass(self, axis: int, kind: int, variant: int, reps: int = 20) -> float:
+        ms = C.c_double()
+        B.check(B.lib().bec_time_fft_pass(self._ctx, axis, kind, variant, reps, C.byref(ms)), "bec_time_fft_pass")
+        return ms.value
+
     def profile(self, on: bool):
         B.check(B.lib().bec_profile_enable(self._ctx, int(on)), "bec_profile_enable")
 

@@ -33,7 +33,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     import subprocess
     structs = {"bec_grid": B.Grid, "bec_params": B.Params, "bec_opts": B.Opts, "bec_terms": B.Terms,
                "bec_ls_report": B.LsReport, "bec_iter": B.Iter, "bec_report": B.Report,
-               "bec_kernel_stat": B.KernelStat}
+               "bec_kernel_stat": B.KernelStat, "bec_tuning": B.Tuning}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bec.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -88,3 +88,11 @@ def test_library_quadrature_is_exact_for_polynomials(n):
     for k in range(2 * n):
         assert abs(np.sum(w * u ** k) - 1.0 / (k + 1)) < 1e-15
     assert L.bec_gauss_legendre(65, u.ctypes.data_as(dp), w.ctypes.data_as(dp)) == 1
+
+
+def test_fft_variant_counts():
+    L = B.lib()
+    n = C.c_int32()
+    for length in (8, 16, 32, 48, 64, 96, 128, 256):
+        assert L.bec_fft_variant_count(length, C.byref(n)) == 0 and n.value >= 3
+    assert L.bec_fft_variant_count(30, C.byref(n)) == 7 and n.value == 0

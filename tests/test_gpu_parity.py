@@ -61,6 +61,44 @@ def test_fft3d_matches_numpy(solver, orc, shape):
         assert rel(fwd, orc.fft3d(a, -1)) < 1e-13
 
 
+@pytest.mark.parametrize("n", [8, 16, 32, 48, 64, 96, 128, 256])
+def test_fft3d_every_plan_variant(solver, n):
+    """Every plan variant of every axis length computes the same transform."""
+    from paper_2510_24543_amd import autotune
+    shape = (n, 16, 8) if n >= 128 else (n, n, 8) if n >= 48 else (n, n, n)
+    grid = {"n": list(shape), "lo": [-1.0] * 3, "hi": [1.0] * 3}
+    ctx = solver.Context(grid, small_params())
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal((3, *shape)) + 1j * rng.standard_normal((3, *shape))
+    ref = np.fft.fftn(a, axes=(1, 2, 3))
+    base = ctx.get_tuning()
+    for axis in range(3):
+        for v in range(autotune.variant_count(shape[axis])):
+            t = {"fft_variant": [r[:] for r in base["fft_variant"]], "pw_blocks": base["pw_blocks"]}
+            t["fft_variant"][axis][0] = v
+            ctx.set_tuning(t)
+            fwd = ctx.fft3d(torch.from_numpy(a).cuda(), -1).cpu().numpy()
+            assert rel(fwd, ref) < 1e-13 * np.log2(np.prod(shape)), (axis, v)
+            inv = ctx.fft3d(torch.from_numpy(ref).cuda(), +1).cpu().numpy()
+            assert rel(inv, a) < 1e-13 * np.log2(np.prod(shape)), (axis, v)
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_energy_with_other_plans(solver, orc, variant):
+    """The fused k-space x pass and the pointwise grid under non-default plans."""
+    grid, params = inputs.CONFIGS["C2"]["grid"], inputs.CONFIGS["C2"]["params"]
+    psi = inputs.initial_state(grid, params["omega"], 41, phase=True)
+    ctx = solver.Context(grid, params)
+    ctx.set_tuning({"fft_variant": [[variant, variant], [variant, 0], [variant, 0]], "pw_blocks": 256 * variant})
+    h, t = ctx.hamiltonian(torch.from_numpy(psi))
+    to, ho, _, _ = orc.heval(grid, params, psi)
+    assert abs(t["E"] - to["E"]) <= 1e-12 * abs(to["E"])
+    assert rel(h.cpu().numpy(), ho) < 1e-11
+    p = inputs.random_field(grid, 42) * 1e-2
+    z = ctx.precond(2, torch.from_numpy(psi), torch.from_numpy(p)).cpu().numpy()
+    assert rel(z, orc.precond(grid, params, 2, 1e-6, psi, p)) < 1e-12
+
+
 def test_fft3d_in_place(solver):
     grid = {"n": [32, 48, 64], "lo": [-1.0] * 3, "hi": [1.0] * 3}
     ctx = solver.Context(grid, small_params())
