@@ -331,10 +331,12 @@ bec_status upload_params(bec_ctx* c, bool dipolar_table)
         nd[4] = e12;
         nd[5] = e21;
         nd[6] = a;
-        c->P.node4[q][0] = nd[0];
-        c->P.node4[q][1] = nd[1];
-        c->P.node4[q][2] = nd[2];
-        c->P.node4[q][3] = nd[3];
+        c->P.node5[q][0] = nd[0];
+        c->P.node5[q][1] = nd[1];
+        c->P.node5[q][2] = nd[2];
+        c->P.node5[q][3] = nd[3];
+        const double det = nd[0] * nd[1] - nd[2];
+        c->P.node5[q][4] = det >= 0.0 ? std::sqrt(det) : -1.0;
     }
     HIPCHK(hipMemcpyAsync(c->nodes, nodes.data(), nodes.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
     std::vector<double> vv[3];
@@ -1348,10 +1350,12 @@ void instance_params(const bec_grid& gr, const bec_params& p, bec::BInstParams& 
     for (int q = 0; q < p.n_u; ++q) {
         const double a = 3.0 * u[q] * u[q] - 1.0;
         const double e12 = p.G[0][1] + p.Gdd[0][1] * a, e21 = p.G[1][0] + p.Gdd[1][0] * a;
-        P.node4[q][0] = p.G[0][0] + p.Gdd[0][0] * a;
-        P.node4[q][1] = p.G[1][1] + p.Gdd[1][1] * a;
-        P.node4[q][2] = e12 * e21;
-        P.node4[q][3] = w[q];
+        P.node5[q][0] = p.G[0][0] + p.Gdd[0][0] * a;
+        P.node5[q][1] = p.G[1][1] + p.Gdd[1][1] * a;
+        P.node5[q][2] = e12 * e21;
+        P.node5[q][3] = w[q];
+        const double det = P.node5[q][0] * P.node5[q][1] - P.node5[q][2];
+        P.node5[q][4] = det >= 0.0 ? std::sqrt(det) : -1.0;
     }
 }
 

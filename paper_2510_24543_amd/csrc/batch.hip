@@ -14,13 +14,14 @@ namespace bec {
 namespace {
 
 struct LdsNodes {
-    const double (*nd)[4];
+    const double (*nd)[kNodeVals];
     __device__ double operator()(int q, int k) const { return nd[q][k]; }
 };
 
-__device__ __forceinline__ void load_nodes(const BInstParams& P, double (*nd)[4])
+__device__ __forceinline__ void load_nodes(const BInstParams& P, double (*nd)[kNodeVals])
 {
-    for (int t = threadIdx.x; t < P.n_u * 4; t += blockDim.x) nd[t >> 2][t & 3] = P.node4[t >> 2][t & 3];
+    for (int t = threadIdx.x; t < P.n_u * kNodeVals; t += blockDim.x)
+        nd[t / kNodeVals][t % kNodeVals] = P.node5[t / kNodeVals][t % kNodeVals];
     __syncthreads();
 }
 
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kPwThreads) void b_heval_epi_kernel(BGroup g)
 {
     const int l = g.ids[blockIdx.y], inst = g.first + l;
     if (!g.act_trial[inst]) return;
-    __shared__ double nd[kMaxNodes][4];
+    __shared__ double nd[kMaxNodes][kNodeVals];
     const BInstParams& P = g.ip[inst];
     load_nodes(P, nd);
     const LdsNodes nodes{nd};
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(kPwThreads) void b_dir_write_kernel(BGroup g)
 {
     const int l = g.ids[blockIdx.y], inst = g.first + l;
     if (!g.act_dir[inst]) return;
-    __shared__ double nd[kMaxNodes][4];
+    __shared__ double nd[kMaxNodes][kNodeVals];
     const BInstParams& P = g.ip[inst];
     load_nodes(P, nd);
     const LdsNodes nodes{nd};

@@ -30,9 +30,10 @@ struct PwParams {
     int n_u;
     int lhy_on;                // c_lhy != 0
     const double* nodes;       // n_u * kNodeStride (device copy, used by the non-hot kernels)
-    // hot-loop copy of (eta_11, eta_22, eta_12 eta_21, w_q) per node, passed in the
-    // kernel-argument block so the u loop reads it through scalar loads
-    double node4[kMaxNodes][4];
+    // hot-loop copy of (eta_11, eta_22, eta_12 eta_21, w_q, r_q) per node (see
+    // pw_math.h), passed in the kernel-argument block so the u loop reads it
+    // through scalar loads
+    double node5[kMaxNodes][5];
     const double* vx;          // 1/2 omega_x^2 x^2 per x index
     const double* vy;
     const double* vz;
@@ -196,7 +197,7 @@ struct BInstParams {
     double Ntot_w[2];             // stacked inner-product weights (N_i/N)^2
     double inv_npts;              // 1 / (nx ny nz)
     int n_u, lhy_on;
-    double node4[kMaxNodes][4];
+    double node5[kMaxNodes][5];
 };
 
 enum : int { kBRunning = 0, kBConverged = 1, kBNotConv = 2, kBStagnated = 3, kBNonFinite = 4 };

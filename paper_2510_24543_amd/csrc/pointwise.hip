@@ -34,7 +34,7 @@ __device__ __forceinline__ double trap_at(const PwParams& P, long long i)
 // node constants read from the kernel-argument block (scalar loads)
 struct KernargNodes {
     const PwParams& P;
-    __device__ double operator()(int q, int k) const { return P.node4[q][k]; }
+    __device__ double operator()(int q, int k) const { return P.node5[q][k]; }
 };
 
 // Fixed-order workgroup reduction of M per-thread sums into partials[m * nblk + block].
@@ -82,17 +82,37 @@ __global__ __launch_bounds__(kPwThreads) void trial_kernel(PwParams P, TrialArgs
     }
 }
 
+struct HevalIn {
+    double2 s1, s2, t1, t2, ph;
+};
+
+__device__ __forceinline__ HevalIn heval_load(const HevalArgs& A, long long N, long long i)
+{
+    HevalIn v;
+    v.s1 = A.psi[i];
+    v.s2 = A.psi[N + i];
+    v.t1 = A.Tpsi[i];
+    v.t2 = A.Tpsi[N + i];
+    v.ph = A.phi[i];
+    return v;
+}
+
+// The operands of the next grid-stride point are loaded before the LHY loop of
+// the current one, so the loads overlap the FP64 arithmetic.
 __global__ __launch_bounds__(kPwThreads) void heval_epi_kernel(PwParams P, HevalArgs A)
 {
     const long long N = P.N;
+    const long long stride = (long long)gridDim.x * kPwThreads;
     double acc[kHevalSums];
 #pragma unroll
     for (int m = 0; m < kHevalSums; ++m) acc[m] = 0.0;
-    GRID_STRIDE(i, N)
-    {
-        const double2 s1 = A.psi[i], s2 = A.psi[N + i];
-        const double2 t1 = A.Tpsi[i], t2 = A.Tpsi[N + i];
-        const double2 ph = A.phi[i];
+    long long i = (long long)blockIdx.x * kPwThreads + threadIdx.x;
+    HevalIn cur{};
+    if (i < N) cur = heval_load(A, N, i);
+    for (; i < N; i += stride) {
+        HevalIn nxt{};
+        if (i + stride < N) nxt = heval_load(A, N, i + stride);
+        const double2 s1 = cur.s1, s2 = cur.s2, t1 = cur.t1, t2 = cur.t2, ph = cur.ph;
         const double n1 = sq2(s1), n2 = sq2(s2);
         const double V = trap_at(P, i);
         double e = 0.0, d1 = 0.0, d2 = 0.0;
@@ -124,6 +144,7 @@ __global__ __launch_bounds__(kPwThreads) void heval_epi_kernel(PwParams P, Heval
         acc[15] += n2;
         acc[16] += m1 * n1;
         acc[17] += m2 * n2;
+        cur = nxt;
     }
     block_reduce_store<kHevalSums>(acc, A.partials, gridDim.x);
 }
@@ -188,40 +209,87 @@ __global__ __launch_bounds__(kPwThreads) void dir_reduce_kernel(PwParams P, DirA
     block_reduce_store<kDirReduceSums>(acc, A.partials, gridDim.x);
 }
 
+struct DirIn {
+    double2 s[2], h[2], ph, ml, po[2], zb[2];
+};
+
+__device__ __forceinline__ DirIn dir_load(const DirArgs& A, long long N, long long i)
+{
+    DirIn v;
+    v.s[0] = A.psi[i];
+    v.s[1] = A.psi[N + i];
+    v.h[0] = A.hpsi[i];
+    v.h[1] = A.hpsi[N + i];
+    v.ph = A.aux[i];
+    v.ml = A.aux[N + i];
+    if (A.beta != 0.0) {
+        v.po[0] = A.p[i];
+        v.po[1] = A.p[N + i];
+    } else {
+        v.po[0] = v.po[1] = make_double2(0.0, 0.0);
+    }
+    if (A.zmode == 2) {
+        v.zb[0] = A.zbuf[i];
+        v.zb[1] = A.zbuf[N + i];
+    } else {
+        v.zb[0] = v.zb[1] = make_double2(0.0, 0.0);
+    }
+    return v;
+}
+
+// Direction write pass with the LHY part of the line-search model; operands of
+// the next grid-stride point are prefetched before the LHY loop.
 __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirArgs A)
 {
     const long long N = P.N;
+    const long long stride = (long long)gridDim.x * kPwThreads;
     double acc[kDirWriteSums];
 #pragma unroll
     for (int m = 0; m < kDirWriteSums; ++m) acc[m] = 0.0;
-    GRID_STRIDE(i, N)
-    {
-        const double2 s[2] = {A.psi[i], A.psi[N + i]};
-        const RZ q = resid_precond(P, A, i, s[0], s[1]);
-        const double2 h[2] = {A.hpsi[i], A.hpsi[N + i]};
-        const double2 ph = A.aux[i], ml = A.aux[N + i];
-        const double mlc[2] = {ml.x, ml.y};
+    long long i = (long long)blockIdx.x * kPwThreads + threadIdx.x;
+    DirIn cur{};
+    if (i < N) cur = dir_load(A, N, i);
+    for (; i < N; i += stride) {
+        DirIn nxt{};
+        if (i + stride < N) nxt = dir_load(A, N, i + stride);
+        const double2* s = cur.s;
+        double2 r[2], z[2];
+        for (int c = 0; c < 2; ++c) r[c] = make_double2(cur.h[c].x - A.mu[c] * s[c].x, cur.h[c].y - A.mu[c] * s[c].y);
         const double n[2] = {sq2(s[0]), sq2(s[1])};
         const double V = trap_at(P, i);
+        const double mlc[2] = {cur.ml.x, cur.ml.y};
+        if (A.zmode == 1) {
+            for (int c = 0; c < 2; ++c) {
+                double g = A.diag_shift[c] + V + P.G[c][0] * n[0] + P.G[c][1] * n[1] + mlc[c];
+                g = 1.0 / ((g > 0.0 ? g : 0.0) + A.sigma);
+                z[c] = make_double2(g * r[c].x, g * r[c].y);
+            }
+        } else if (A.zmode == 2) {
+            z[0] = cur.zb[0];
+            z[1] = cur.zb[1];
+        } else {
+            z[0] = r[0];
+            z[1] = r[1];
+        }
+        const double2 ph = cur.ph;
         double2 p[2];
         double rho[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            double2 d = make_double2(A.zsign * q.z[c].x, A.zsign * q.z[c].y);
+            double2 d = make_double2(A.zsign * z[c].x, A.zsign * z[c].y);
             if (A.beta != 0.0) {
-                const double2 po = A.p[c * N + i];
-                d.x += A.beta * po.x;
-                d.y += A.beta * po.y;
+                d.x += A.beta * cur.po[c].x;
+                d.y += A.beta * cur.po[c].y;
             }
             p[c] = make_double2(d.x - A.c[c] * s[c].x, d.y - A.c[c] * s[c].y);
             A.p[c * N + i] = p[c];
-            A.r_out[c * N + i] = q.r[c];
+            A.r_out[c * N + i] = r[c];
             rho[c] = redot(s[c], p[c]);
-            const double2 hmf = make_double2(h[c].x - mlc[c] * s[c].x, h[c].y - mlc[c] * s[c].y);
+            const double2 hmf = make_double2(cur.h[c].x - mlc[c] * s[c].x, cur.h[c].y - mlc[c] * s[c].y);
             const double U = V + P.G[c][0] * n[0] + P.G[c][1] * n[1] + P.Gdd[c][0] * ph.x + P.Gdd[c][1] * ph.y;
             const double pp = sq2(p[c]);
             acc[0 + c] += pp;
-            acc[2 + c] += redot(p[c], q.r[c]);
+            acc[2 + c] += redot(p[c], r[c]);
             acc[4 + c] += redot(p[c], hmf);
             acc[6 + c] += redot(s[c], hmf);
             acc[8 + c] += U * pp;
@@ -236,6 +304,7 @@ __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirAr
             acc[14] += L1;
             acc[15] += L2;
         }
+        cur = nxt;
     }
     block_reduce_store<kDirWriteSums>(acc, A.partials, gridDim.x);
 }
