@@ -13,11 +13,14 @@ timed call is one bec_solve of K steps from the seeded start, so it includes
 one initial normalisation + Hamiltonian evaluation (about a third of a step).
 
 Also reported: time to max_i ||H_i psi_i - mu_i psi_i|| < 1e-8 from the seeded
-start, per-kernel event timings of a short profiled solve (the roofline entry
-is the kernel with the largest total time), and the CPU oracle timed on the
+start; per-kernel HIP-event timings over a second, profiled run of the same K
+steps (events around every launch on the library's stream; the roofline entry
+is the kernel with the largest total time); and the CPU oracle timed on the
 host cores on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --copy-probe MIB       (plain device copy, for counter calibration)
+       python bench.py --pmc-summary FETCH.csv WRITE.csv COPY_FETCH.csv COPY_WRITE.csv COPY_MIB
 """
 from __future__ import annotations
 
@@ -36,18 +39,105 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = "M"
 
 
-def traffic_from_profiles(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel calibration),
-    or None when no summary for this kernel exists."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_128cubed.json")
-    if not os.path.exists(path):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_128cubed.json")
+# library profiler labels -> kernel function names as rocprofv3 reports them
+LABEL_KERNEL = {"dir_write": "dir_write_kernel", "heval_epilogue": "heval_epi_kernel",
+                "dir_reduce": "dir_reduce_kernel", "trial_pack": "trial_kernel",
+                "ls_epilogue": "ls_epi_kernel", "reduce_final": "reduce_final_kernel",
+                "scale2": "scale2_kernel", "norm2": "norm2_kernel"}
+# sources whose change invalidates the stored counter figures of the pointwise kernels
+KERNEL_SOURCES = ["paper_2510_24543_amd/csrc/pointwise.hip", "paper_2510_24543_amd/csrc/pw_math.h",
+                  "paper_2510_24543_amd/csrc/bec_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(label: str):
+    """HBM bytes per launch of the kernel behind `label` from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    copy-kernel calibration); None when there is no summary for it or the
+    kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE) or label not in LABEL_KERNEL:
         return None
     try:
-        data = json.load(open(path))
-        return data["kernels"][kernel]["bytes_per_launch"]
+        data = json.load(open(TRAFFIC_FILE))
+        if data.get("source_hash") != kernel_source_hash():
+            return None
+        return data["kernels"][LABEL_KERNEL[label]]["bytes_per_launch"]
     except (KeyError, ValueError):
         return None
+
+
+def copy_probe(mib: int, reps: int = 5):
+    """A plain device-to-device copy of `mib` MiB, `reps` times: under
+    rocprofv3 --pmc its FETCH_SIZE / WRITE_SIZE per dispatch calibrate the
+    counters against a known byte count."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.arange(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    print(json.dumps({"copy_mib": mib, "bytes_read": 8 * n, "bytes_written": 8 * n,
+                      "ms": round(ms, 4), "GB_per_s": round(16 * n / (ms * 1e6), 1)}), flush=True)
+
+
+def _pmc_table(path: str, counter: str):
+    """mean counter value per dispatch, by kernel name, from a rocprofv3
+    counter_collection.csv"""
+    import csv
+    sums, counts = {}, {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = row["Kernel_Name"]
+            sums[name] = sums.get(name, 0.0) + float(row["Counter_Value"])
+            counts[name] = counts.get(name, 0) + 1
+    return {k: (sums[k] / counts[k], counts[k]) for k in sums}
+
+
+def pmc_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib):
+    """Write the HBM-traffic summary: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) of each kernel, scaled by known_bytes / counter_bytes of the
+    plain copy kernel."""
+    known = copy_mib * (1 << 20)
+
+    def copy_factor(path, counter):
+        t = _pmc_table(path, counter)
+        name, (kib, _) = max(t.items(), key=lambda kv: kv[1][0])
+        return known / (kib * 1024.0), name
+
+    f_fac, copy_name = copy_factor(copy_fetch_csv, "FETCH_SIZE")
+    w_fac, _ = copy_factor(copy_write_csv, "WRITE_SIZE")
+    fetch, write = _pmc_table(fetch_csv, "FETCH_SIZE"), _pmc_table(write_csv, "WRITE_SIZE")
+    kernels = {}
+    for full in sorted(set(fetch) & set(write)):
+        base = full[:full.rfind("(")] if full.endswith(")") else full
+        short = base.split("::")[-1]
+        fb = fetch[full][0] * 1024.0 * f_fac
+        wb = write[full][0] * 1024.0 * w_fac
+        kernels[short] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+                          "dispatches": fetch[full][1]}
+    out = {"workload": "128^3 x 2", "copy_kernel": copy_name, "copy_bytes_each_way": known,
+           "fetch_factor": f_fac, "write_factor": w_fac, "source_hash": kernel_source_hash(),
+           "kernels": kernels}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps({k: round(v["bytes_per_launch"] / 2**20, 2) for k, v in kernels.items()}))
 
 
 def cpu_baseline(grid, params, psi0, sample_iters: int):
@@ -128,7 +218,19 @@ def main():
     ap.add_argument("--scan", type=int, default=96, help="instances of the batched-vs-plain scan (0: skip)")
     ap.add_argument("--tuning", choices=("auto", "cache", "default"), default="auto",
                     help="launch plans: autotune now, read the committed cache, or the defaults")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=5, default=None,
+                    metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "COPY_MIB"),
+                    help="only turn rocprofv3 counter CSVs into the committed traffic summary")
     args = ap.parse_args()
+    if args.pmc_summary:
+        a = args.pmc_summary
+        pmc_summary(a[0], a[1], a[2], a[3], int(a[4]))
+        return
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU decomposition is a design note, "
               "not code (use --gpus 1)", file=sys.stderr)
@@ -185,9 +287,15 @@ def main():
                "E_star": trep["final"]["E"], "res_max": max(trep["final"]["res"]),
                "backtracks": trep["n_backtracks"], "restarts": trep["n_restarts"]}
 
-    # per-kernel timings (HIP events on the library stream) over a short solve
+    # per-kernel timings: HIP events around every launch on the library stream,
+    # over a second run of the same K steps
     ctx.profile(True)
-    ctx.solve(psi0, dict(base_opts, max_iter=5, tol_grad=0.0))
+    torch.cuda.synchronize()
+    ev0.record(ctx.stream)
+    _, prep, _ = ctx.solve(psi0, dict(base_opts, max_iter=args.steps, tol_grad=0.0))
+    ev1.record(ctx.stream)
+    torch.cuda.synchronize()
+    prof_ms = ev0.elapsed_time(ev1)
     stats = ctx.kernel_stats()
     ctx.profile(False)
     tot = sum(s["total_ms"] for s in stats)
@@ -202,7 +310,8 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(dom["GB_per_s"], 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["GB_per_s"] / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "avg_us": round(dom["avg_us"], 2),
-                "bytes_per_launch": dom["bytes_per_launch"]}
+                "bytes_per_launch": dom["bytes_per_launch"],
+                "profiled_ms_per_step": round(prof_ms / max(prep["iters"], 1), 4)}
 
     scan = scan_comparison(args.scan) if args.scan > 0 else None
 

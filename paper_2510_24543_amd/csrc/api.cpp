@@ -11,12 +11,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <array>
 #include <vector>
 
 using bec::FftPassArgs;
@@ -312,6 +314,32 @@ bec_status check_params(const bec_params* p)
     return BEC_OK;
 }
 
+// Node table of the LHY loops (Sec. II Eq. (3) with Gauss-Legendre nodes u_q):
+// eta_ij = G_ij + Gdd_ij (3 u_q^2 - 1); class-A nodes (det >= 0, eta_11 or
+// eta_22 > 0; both branch potentials >= 0) first, then class-B nodes (det < 0;
+// V_- clipped); nodes with both branches clipped everywhere are left out.
+void hot_nodes(const bec_params& p, const std::vector<double>& u, const std::vector<double>& w,
+               double node5[][5], int* n_a, int* n_b)
+{
+    std::vector<std::array<double, 5>> A, B;
+    for (int q = 0; q < p.n_u; ++q) {
+        const double a = 3.0 * u[q] * u[q] - 1.0;
+        const double e11 = p.G[0][0] + p.Gdd[0][0] * a, e22 = p.G[1][1] + p.Gdd[1][1] * a;
+        const double p12 = (p.G[0][1] + p.Gdd[0][1] * a) * (p.G[1][0] + p.Gdd[1][0] * a);
+        const double det = e11 * e22 - p12;
+        if (det < 0.0)
+            B.push_back({e11, e22, p12, w[q], 0.0});
+        else if (e11 > 0.0 || e22 > 0.0)
+            A.push_back({e11, e22, p12, w[q], std::sqrt(det)});
+    }
+    int k = 0;
+    for (const auto& v : A) { for (int j = 0; j < 5; ++j) node5[k][j] = v[j]; ++k; }
+    for (const auto& v : B) { for (int j = 0; j < 5; ++j) node5[k][j] = v[j]; ++k; }
+    for (; k < bec::kMaxNodes; ++k) for (int j = 0; j < 5; ++j) node5[k][j] = 0.0;
+    *n_a = (int)A.size();
+    *n_b = (int)B.size();
+}
+
 // Host tables that depend on the parameters: quadrature nodes, couplings,
 // trap, dipolar kernel.  Uploads asynchronously, then synchronises.
 bec_status upload_params(bec_ctx* c, bool dipolar_table)
@@ -331,13 +359,8 @@ bec_status upload_params(bec_ctx* c, bool dipolar_table)
         nd[4] = e12;
         nd[5] = e21;
         nd[6] = a;
-        c->P.node5[q][0] = nd[0];
-        c->P.node5[q][1] = nd[1];
-        c->P.node5[q][2] = nd[2];
-        c->P.node5[q][3] = nd[3];
-        const double det = nd[0] * nd[1] - nd[2];
-        c->P.node5[q][4] = det >= 0.0 ? std::sqrt(det) : -1.0;
     }
+    hot_nodes(p, u, w, c->P.node5, &c->P.n_a, &c->P.n_b);
     HIPCHK(hipMemcpyAsync(c->nodes, nodes.data(), nodes.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
     std::vector<double> vv[3];
     for (int d = 0; d < 3; ++d) {
@@ -1347,16 +1370,7 @@ void instance_params(const bec_grid& gr, const bec_params& p, bec::BInstParams& 
     P.lhy_on = p.c_lhy != 0.0;
     std::vector<double> u, w;
     gauss_legendre01(p.n_u, u, w);
-    for (int q = 0; q < p.n_u; ++q) {
-        const double a = 3.0 * u[q] * u[q] - 1.0;
-        const double e12 = p.G[0][1] + p.Gdd[0][1] * a, e21 = p.G[1][0] + p.Gdd[1][0] * a;
-        P.node5[q][0] = p.G[0][0] + p.Gdd[0][0] * a;
-        P.node5[q][1] = p.G[1][1] + p.Gdd[1][1] * a;
-        P.node5[q][2] = e12 * e21;
-        P.node5[q][3] = w[q];
-        const double det = P.node5[q][0] * P.node5[q][1] - P.node5[q][2];
-        P.node5[q][4] = det >= 0.0 ? std::sqrt(det) : -1.0;
-    }
+    hot_nodes(p, u, w, P.node5, &P.n_a, &P.n_b);
 }
 
 bool same_shape(const bec_grid& a, const bec_grid& b) { return a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2]; }

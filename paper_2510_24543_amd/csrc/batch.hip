@@ -20,7 +20,7 @@ struct LdsNodes {
 
 __device__ __forceinline__ void load_nodes(const BInstParams& P, double (*nd)[kNodeVals])
 {
-    for (int t = threadIdx.x; t < P.n_u * kNodeVals; t += blockDim.x)
+    for (int t = threadIdx.x; t < (P.n_a + P.n_b) * kNodeVals; t += blockDim.x)
         nd[t / kNodeVals][t % kNodeVals] = P.node5[t / kNodeVals][t % kNodeVals];
     __syncthreads();
 }
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kPwThreads) void b_heval_epi_kernel(BGroup g)
     const double2* phi = Tpsi + 2 * N;
     double2* hpsi = g.hpsi + ((long long)l * 2 + tb) * 2 * N;
     double2* aux = g.aux + ((long long)l * 2 + tb) * 2 * N;
-    const int n_u = P.n_u, lhy = P.lhy_on;
+    const int n_a = P.n_a, n_b = P.n_b, lhy = P.lhy_on;
     const double K5 = P.K5, K3 = P.K3;
     double acc[kHevalSums];
 #pragma unroll
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kPwThreads) void b_heval_epi_kernel(BGroup g)
         const double n1 = sq2(s1), n2 = sq2(s2);
         const double V = btrap(g, l, i);
         double e = 0.0, d1 = 0.0, d2 = 0.0;
-        if (lhy) lhy_point(nodes, n_u, K5, K3, n1, n2, e, d1, d2);
+        if (lhy) lhy_point(nodes, n_a, n_b, K5, K3, n1, n2, e, d1, d2);
         const double m1 = d1 / P.Nat[0], m2 = d2 / P.Nat[1];
         const double U1 = V + P.G[0][0] * n1 + P.G[0][1] * n2 + P.Gdd[0][0] * ph.x + P.Gdd[0][1] * ph.y + m1;
         const double U2 = V + P.G[1][0] * n1 + P.G[1][1] * n2 + P.Gdd[1][0] * ph.x + P.Gdd[1][1] * ph.y + m2;
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kPwThreads) void b_dir_write_kernel(BGroup g)
     double2* p = g.p + (long long)l * 2 * N;
     double2* r_out = g.r_old + (long long)l * 2 * N;
     double2* rho_o = g.rho + (long long)l * N;
-    const int n_u = P.n_u, lhy = P.lhy_on;
+    const int n_a = P.n_a, n_b = P.n_b, lhy = P.lhy_on;
     double acc[kDirWriteSums];
 #pragma unroll
     for (int m = 0; m < kDirWriteSums; ++m) acc[m] = 0.0;
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kPwThreads) void b_dir_write_kernel(BGroup g)
         rho_o[i] = make_double2(rho[0], rho[1]);
         if (lhy) {
             double L1, L2;
-            lhy_model(nodes, n_u, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
+            lhy_model(nodes, n_a, n_b, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
             acc[14] += L1;
             acc[15] += L2;
         }

@@ -30,9 +30,11 @@ struct PwParams {
     int n_u;
     int lhy_on;                // c_lhy != 0
     const double* nodes;       // n_u * kNodeStride (device copy, used by the non-hot kernels)
-    // hot-loop copy of (eta_11, eta_22, eta_12 eta_21, w_q, r_q) per node (see
+    // hot-loop copy of (eta_11, eta_22, eta_12 eta_21, w_q, sqrt(det_q)) per
+    // node, class-A nodes first (n_a), then class-B nodes (n_b) (see
     // pw_math.h), passed in the kernel-argument block so the u loop reads it
     // through scalar loads
+    int n_a, n_b;
     double node5[kMaxNodes][5];
     const double* vx;          // 1/2 omega_x^2 x^2 per x index
     const double* vy;
@@ -197,6 +199,7 @@ struct BInstParams {
     double Ntot_w[2];             // stacked inner-product weights (N_i/N)^2
     double inv_npts;              // 1 / (nx ny nz)
     int n_u, lhy_on;
+    int n_a, n_b;                 // class-A / class-B node counts of node5
     double node5[kMaxNodes][5];
 };
 

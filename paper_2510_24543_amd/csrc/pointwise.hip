@@ -97,8 +97,6 @@ __device__ __forceinline__ HevalIn heval_load(const HevalArgs& A, long long N, l
     return v;
 }
 
-// The operands of the next grid-stride point are loaded before the LHY loop of
-// the current one, so the loads overlap the FP64 arithmetic.
 __global__ __launch_bounds__(kPwThreads) void heval_epi_kernel(PwParams P, HevalArgs A)
 {
     const long long N = P.N;
@@ -107,16 +105,13 @@ __global__ __launch_bounds__(kPwThreads) void heval_epi_kernel(PwParams P, Heval
 #pragma unroll
     for (int m = 0; m < kHevalSums; ++m) acc[m] = 0.0;
     long long i = (long long)blockIdx.x * kPwThreads + threadIdx.x;
-    HevalIn cur{};
-    if (i < N) cur = heval_load(A, N, i);
     for (; i < N; i += stride) {
-        HevalIn nxt{};
-        if (i + stride < N) nxt = heval_load(A, N, i + stride);
+        const HevalIn cur = heval_load(A, N, i);
         const double2 s1 = cur.s1, s2 = cur.s2, t1 = cur.t1, t2 = cur.t2, ph = cur.ph;
         const double n1 = sq2(s1), n2 = sq2(s2);
         const double V = trap_at(P, i);
         double e = 0.0, d1 = 0.0, d2 = 0.0;
-        if (P.lhy_on) lhy_point(KernargNodes{P}, P.n_u, P.K5, P.K3, n1, n2, e, d1, d2);
+        if (P.lhy_on) lhy_point(KernargNodes{P}, P.n_a, P.n_b, P.K5, P.K3, n1, n2, e, d1, d2);
         const double m1 = d1 / P.Nat[0], m2 = d2 / P.Nat[1];
         const double U1 = V + P.G[0][0] * n1 + P.G[0][1] * n2 + P.Gdd[0][0] * ph.x + P.Gdd[0][1] * ph.y + m1;
         const double U2 = V + P.G[1][0] * n1 + P.G[1][1] * n2 + P.Gdd[1][0] * ph.x + P.Gdd[1][1] * ph.y + m2;
@@ -144,7 +139,6 @@ __global__ __launch_bounds__(kPwThreads) void heval_epi_kernel(PwParams P, Heval
         acc[15] += n2;
         acc[16] += m1 * n1;
         acc[17] += m2 * n2;
-        cur = nxt;
     }
     block_reduce_store<kHevalSums>(acc, A.partials, gridDim.x);
 }
@@ -237,8 +231,7 @@ __device__ __forceinline__ DirIn dir_load(const DirArgs& A, long long N, long lo
     return v;
 }
 
-// Direction write pass with the LHY part of the line-search model; operands of
-// the next grid-stride point are prefetched before the LHY loop.
+// Direction write pass with the LHY part of the line-search model.
 __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirArgs A)
 {
     const long long N = P.N;
@@ -247,11 +240,8 @@ __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirAr
 #pragma unroll
     for (int m = 0; m < kDirWriteSums; ++m) acc[m] = 0.0;
     long long i = (long long)blockIdx.x * kPwThreads + threadIdx.x;
-    DirIn cur{};
-    if (i < N) cur = dir_load(A, N, i);
     for (; i < N; i += stride) {
-        DirIn nxt{};
-        if (i + stride < N) nxt = dir_load(A, N, i + stride);
+        const DirIn cur = dir_load(A, N, i);
         const double2* s = cur.s;
         double2 r[2], z[2];
         for (int c = 0; c < 2; ++c) r[c] = make_double2(cur.h[c].x - A.mu[c] * s[c].x, cur.h[c].y - A.mu[c] * s[c].y);
@@ -300,11 +290,10 @@ __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirAr
         A.rho[i] = make_double2(rho[0], rho[1]);
         if (P.lhy_on) {
             double L1, L2;
-            lhy_model(KernargNodes{P}, P.n_u, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
+            lhy_model(KernargNodes{P}, P.n_a, P.n_b, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
             acc[14] += L1;
             acc[15] += L2;
         }
-        cur = nxt;
     }
     block_reduce_store<kDirWriteSums>(acc, A.partials, gridDim.x);
 }

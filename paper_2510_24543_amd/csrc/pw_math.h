@@ -21,89 +21,139 @@ __device__ __forceinline__ double rsq_nr(double x)
     return r;
 }
 
-// Per node q the tables hold (eta_11, eta_22, eta_12 eta_21, w_q, r_q) with
-// r_q = sqrt(eta_11 eta_22 - eta_12 eta_21) when that is >= 0, else -1.
-// Since V_+ V_- = 4 n1 n2 (eta_11 eta_22 - eta_12 eta_21), sqrt(V_-) follows from
-// 1/sqrt(V_+) as 2 sqrt(n1 n2) r_q / sqrt(V_+): two reciprocal square roots per
-// node (s and V_+) instead of three.  A negative product means V_- < 0, whose
-// branch is clipped away ([V]_+).
+// Node classes.  With det_q = eta_11 eta_22 - eta_12 eta_21 (eta_12 eta_21 >= 0
+// because N_i G_ij and N_i Gdd_ij are symmetric) the two branch potentials
+// satisfy V_+ + V_- = 2 (eta_11 n1 + eta_22 n2) and V_+ V_- = 4 n1 n2 det_q, so
+// for n1 n2 > 0 the signs of V_+- are fixed per node, independent of the point:
+//   class A: det_q >= 0 and eta_11, eta_22 >= 0 (not both 0): V_+, V_- >= 0;
+//   class B: det_q < 0: V_+ > 0 > V_-, the V_- branch is clipped ([V]_+);
+//   otherwise (det_q >= 0, eta_11, eta_22 <= 0) both branches are clipped and
+//   the node contributes nothing.
+// The host stores the class-A nodes first, then the class-B nodes; per node the
+// table holds (eta_11, eta_22, eta_12 eta_21, w_q, sqrt(det_q) or 0).
+//
+// Class A uses a = sqrt(V_+), b = sqrt(V_-) through sigma = a + b and pi = a b:
+// sigma^2 = 2 (eta_11 n1 + eta_22 n2) + 2 pi, pi = 2 sqrt(n1 n2 det_q), and
+//   a^5 + b^5 = sigma (sigma^4 - 5 sigma^2 pi + 5 pi^2),
+//   a^3 + b^3 = sigma (sigma^2 - 3 pi),
+//   a^3 - b^3 = (2 s / sigma) (sigma^2 - pi),
+// so every sum over the two branches needs one reciprocal square root (of
+// sigma^2) and no square root of s^2.  Class B needs s and sqrt(V_+).
+// As in the definition of the ratio terms, terms carrying 1/s are dropped
+// where s^2 <= kTiny.
 constexpr int kNodeVals = 5;
 
-// LHY energy density and derivatives at one point.  Branches with V <= 0
-// contribute nothing ([V]_+ powers); ratio terms vanish when s = 0.  Values
-// below kTiny are treated as 0: their contributions (V^(3/2) < 1e-435) are
-// below FP64 resolution.  Branch-free: masks instead of divergent ifs.
+// LHY energy density e and de/dn_i at one point.  Values below kTiny are
+// treated as 0: their contributions (V^(3/2) < 1e-435) are below FP64
+// resolution.  Branch-free: masks instead of divergent ifs.
 // Nodes: any type with operator()(q, k) giving the k-th table value of node q.
 template <class Nodes>
-__device__ __forceinline__ void lhy_point(const Nodes& nodes, int n_u, double K5, double K3, double n1,
+__device__ __forceinline__ void lhy_point(const Nodes& nodes, int n_a, int n_b, double K5, double K3, double n1,
                                           double n2, double& e, double& d1, double& d2)
 {
     double ae = 0.0, a1 = 0.0, a2 = 0.0;
-    const double n12x4 = 4.0 * n1 * n2, n1x2 = 2.0 * n1, n2x2 = 2.0 * n2;
+    const double n12x4 = 4.0 * n1 * n2;
     const double nn = n1 * n2;
     const double sqnn2 = nn > kTiny ? 2.0 * nn * rsq_nr(nn) : 0.0;      // 2 sqrt(n1 n2)
-    for (int q = 0; q < n_u; ++q) {
+    for (int q = 0; q < n_a; ++q) {
         const double e11 = nodes(q, 0), e22 = nodes(q, 1), p12 = nodes(q, 2), w = nodes(q, 3), rq = nodes(q, 4);
-        const double a = e11 * n1, b = e22 * n2, delta = a - b, base = a + b;
+        const double a = e11 * n1, b = e22 * n2, delta = a - b;
+        const double pi = sqnn2 * rq;
+        const double x = 2.0 * (a + b + pi);                            // sigma^2
+        const bool ok = x > kTiny;
+        const double r = rsq_nr(ok ? x : 1.0);                         // 1/sigma
+        const double sg = x * r;
+        const double wq = ok ? w : 0.0;
+        const double ss = fma(delta, delta, p12 * n12x4);
+        const double t1 = ss > kTiny ? 2.0 * (x - pi) * r : 0.0;       // 2 (sigma^2 - pi)/sigma
+        const double t3 = sg * (x - 3.0 * pi);                          // a^3 + b^3
+        const double e5 = sg * fma(x, x - 5.0 * pi, 5.0 * pi * pi);     // a^5 + b^5
+        const double u1 = fma(e11, delta, 2.0 * p12 * n2);              // s ds/dn1
+        const double u2 = fma(-e22, delta, 2.0 * p12 * n1);             // s ds/dn2
+        ae = fma(wq, e5, ae);
+        a1 = fma(wq, fma(e11, t3, u1 * t1), a1);
+        a2 = fma(wq, fma(e22, t3, u2 * t1), a2);
+    }
+    for (int q = n_a; q < n_a + n_b; ++q) {
+        const double e11 = nodes(q, 0), e22 = nodes(q, 1), p12 = nodes(q, 2), w = nodes(q, 3);
+        const double a = e11 * n1, b = e22 * n2, delta = a - b;
         const double ss = fma(delta, delta, p12 * n12x4);
         const double inv = ss > kTiny ? rsq_nr(ss) : 0.0;              // 1/s
-        const double s = ss * inv;
-        const double r1 = fma(e11, delta, p12 * n2x2) * inv;
-        const double r2 = fma(-e22, delta, p12 * n1x2) * inv;
-        const double Vp = base + s;
+        const double Vp = fma(ss, inv, a + b);
         const bool pp = Vp > kTiny;
         const double xp = pp ? Vp : 1.0;
-        const double rp = rsq_nr(xp);                                  // 1/sqrt(V_+)
-        const double sqp = xp * rp;                                    // sqrt(V_+)
-        const double sqm = rq >= 0.0 ? sqnn2 * rq * rp : 0.0;          // sqrt(V_-) (0 when clipped)
-        const double Vm = sqm * sqm;
-        const double cp = (pp ? w : 0.0) * xp * sqp;                   // w V_+^(3/2)
-        const double cm = (pp ? w : 0.0) * Vm * sqm;                   // w V_-^(3/2)
-        ae = fma(cp, xp, fma(cm, Vm, ae));
-        a1 = fma(cp, e11 + r1, fma(cm, e11 - r1, a1));
-        a2 = fma(cp, e22 + r2, fma(cm, e22 - r2, a2));
+        const double cp = (pp ? w : 0.0) * xp * (xp * rsq_nr(xp));     // w V_+^(3/2)
+        const double r1 = fma(e11, delta, 2.0 * p12 * n2) * inv;
+        const double r2 = fma(-e22, delta, 2.0 * p12 * n1) * inv;
+        ae = fma(cp, xp, ae);
+        a1 = fma(cp, e11 + r1, a1);
+        a2 = fma(cp, e22 + r2, a2);
     }
     e = K5 * ae;
     d1 = K3 * a1;
     d2 = K3 * a2;
 }
 
-// LHY part of the geodesic model with n'' = 0: sums of [V]_+^(3/2) V^1 and of
-// [V]_+^(3/2) V^2_0 + 3/4 [V]_+^(1/2) (V^1)^2.  The n'' part of V^2 is linear in
-// n''_i with coefficient dV/dn_i and is added from muLHY on the host.
-// B/(2s) - A^2/(2s^3) is evaluated as (B - (A/s)^2)/(2s): s^3 underflows at
-// tiny densities.
+// LHY part of the geodesic model with n'' = 0: sums over nodes and branches of
+// [V]_+^(3/2) V^1 and of [V]_+^(3/2) V^2_0 + 3/4 [V]_+^(1/2) (V^1)^2, with
+// V^1 = lin +- A/s and V^2_0 = +-(B - (A/s)^2)/(2s) along (n1', n2').  The n''
+// part of V^2 is linear in n''_i with coefficient dV/dn_i and is added from
+// muLHY on the host.  For class A the branch sums reduce to
+//   sum a^3 V^1      = lin (a^3 + b^3) + 2 A (sigma^2 - pi)/sigma,
+//   sum a^3 V^2_0    = (B - A^2/s^2) (sigma^2 - pi)/sigma,
+//   sum a (V^1)^2    = sigma (lin^2 + A^2/s^2) + 4 lin A / sigma,
+// and since s^2 = sigma^2 (a - b)^2 / 4 the A^2/s^2 parts combine to
+//   sum [a^3 V^2_0 + 3/4 a (V^1)^2] = B (sigma^2 - pi)/sigma - A^2/sigma^3
+//                                     + 3/4 sigma lin^2 + 3 lin A / sigma,
+// free of 1/s (and of the cancellation it carries where s is small).
 template <class Nodes>
-__device__ __forceinline__ void lhy_model(const Nodes& nodes, int n_u, double n1, double n2, double n1p,
+__device__ __forceinline__ void lhy_model(const Nodes& nodes, int n_a, int n_b, double n1, double n2, double n1p,
                                           double n2p, double& L1, double& L2)
 {
     double s1 = 0.0, s2acc = 0.0;
     const double n12x4 = 4.0 * n1 * n2, cross = 2.0 * (n1 * n2p + n1p * n2), pp4 = 4.0 * n1p * n2p;
     const double nn = n1 * n2;
     const double sqnn2 = nn > kTiny ? 2.0 * nn * rsq_nr(nn) : 0.0;
-    for (int q = 0; q < n_u; ++q) {
+    for (int q = 0; q < n_a; ++q) {
         const double e11 = nodes(q, 0), e22 = nodes(q, 1), p12 = nodes(q, 2), w = nodes(q, 3), rq = nodes(q, 4);
+        const double a = e11 * n1, b = e22 * n2, delta = a - b;
+        const double d1 = e11 * n1p - e22 * n2p;
+        const double lin = fma(e11, n1p, e22 * n2p);
+        const double pi = sqnn2 * rq;
+        const double x = 2.0 * (a + b + pi);
+        const bool ok = x > kTiny;
+        const double r = rsq_nr(ok ? x : 1.0);
+        const double sg = x * r;
+        const double wq = ok ? w : 0.0;
+        const double ss = fma(delta, delta, p12 * n12x4);
+        const bool sp = ss > kTiny;
+        const double A = sp ? fma(delta, d1, p12 * cross) : 0.0;
+        const double B0 = fma(d1, d1, p12 * pp4);
+        const double t1 = (x - pi) * r;                                 // (sigma^2 - pi)/sigma
+        const double t3 = sg * (x - 3.0 * pi);
+        s1 = fma(wq, fma(lin, t3, 2.0 * A * t1), s1);
+        const double v2 = sp ? fma(B0, t1, -A * A * (r * r * r)) : 0.0;
+        s2acc = fma(wq, v2 + fma(0.75 * sg * lin, lin, 3.0 * lin * A * r), s2acc);
+    }
+    for (int q = n_a; q < n_a + n_b; ++q) {
+        const double e11 = nodes(q, 0), e22 = nodes(q, 1), p12 = nodes(q, 2), w = nodes(q, 3);
         const double delta = e11 * n1 - e22 * n2;
         const double d1 = e11 * n1p - e22 * n2p;
         const double ss = fma(delta, delta, p12 * n12x4);
         const double inv = ss > kTiny ? rsq_nr(ss) : 0.0;
-        const double s = ss * inv;
         const double A = fma(delta, d1, p12 * cross);
         const double B0 = fma(d1, d1, p12 * pp4);
-        const double lin1 = e11 * n1p + e22 * n2p;
+        const double lin = fma(e11, n1p, e22 * n2p);
         const double ra = A * inv;
         const double rb = 0.5 * fma(-ra, ra, B0) * inv;
-        const double Vp = e11 * n1 + e22 * n2 + s;
+        const double Vp = fma(ss, inv, fma(e11, n1, e22 * n2));
         const bool pp = Vp > kTiny;
         const double xp = pp ? Vp : 1.0;
-        const double rp = rsq_nr(xp);
-        const double rvp = xp * rp;                                    // sqrt(V_+)
-        const double rvm = rq >= 0.0 ? sqnn2 * rq * rp : 0.0;          // sqrt(V_-)
-        const double xm = rvm * rvm;
+        const double rvp = xp * rsq_nr(xp);                              // sqrt(V_+)
         const double wp = pp ? w : 0.0;
-        const double V1p = lin1 + ra, V1m = lin1 - ra;
-        s1 = fma(wp * xp * rvp, V1p, fma(wp * xm * rvm, V1m, s1));
-        s2acc = fma(wp * rvp, fma(xp, rb, 0.75 * V1p * V1p), fma(wp * rvm, fma(-xm, rb, 0.75 * V1m * V1m), s2acc));
+        const double V1 = lin + ra;
+        s1 = fma(wp * xp * rvp, V1, s1);
+        s2acc = fma(wp * rvp, fma(xp, rb, 0.75 * V1 * V1), s2acc);
     }
     L1 = s1;
     L2 = s2acc;
