@@ -177,7 +177,8 @@ struct bec_ctx {
     double2 *psi[2] = {}, *hpsi[2] = {}, *aux[2] = {};
     double2 *pdir = nullptr, *r_old = nullptr, *z = nullptr, *rho = nullptr, *W = nullptr;
     double *udtab = nullptr, *kv[3] = {}, *vv[3] = {}, *nodes = nullptr;
-    double *partials = nullptr, *fft_partials = nullptr, *scal = nullptr;
+    double *partials = nullptr, *fft_partials = nullptr;
+    double* scal = nullptr;    // device address of `host` (reduced scalars)
     double2* tw[3] = {};
     double* host = nullptr;   // pinned scalars
     int nblk_pw = 0;
@@ -271,7 +272,7 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
         bec::kMaxNodes * bec::kNodeStride * sizeof(double),                         // nodes
         (size_t)bec::kMaxSums * nb_pw * sizeof(double),                             // partials
         (size_t)3 * nb_x * sizeof(double),                                          // fft partials
-        64 * sizeof(double),                                                        // scal
+        64 * sizeof(double),                                                        // reserved
     };
     size_t total = 0;
     for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); ++i) {
@@ -509,9 +510,10 @@ bec_status kspace_apply(bec_ctx* c, const double2* const* src, double2* const* d
 }
 
 // ------------------------------------------------------------------ reductions
+// c->scal is the device address of the pinned host buffer c->host
 bec_status fetch(bec_ctx* c, int M)
 {
-    HIPCHK(hipMemcpyAsync(c->host, c->scal, M * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    (void)M;
     HIPCHK(hipStreamSynchronize(c->st));
     return BEC_OK;
 }
@@ -544,18 +546,20 @@ bec_status heval(bec_ctx* c, const double2* src, const double2* p, const double 
     ta.psi_dst = c->psi[set];
     ta.dens = c->W + 2 * N;
     LAUNCH(c, "trial_pack", (double)c->N * (p ? 112.0 : 80.0), bec::launch_trial(c->P, ta, c->st));
+    // the dipolar potentials Phi_1 + i Phi_2 land directly in aux[set] (its first
+    // half), where the later passes read them
     const double2* fsrc[3] = {c->psi[set], c->psi[set] + N, c->W + 2 * N};
-    double2* fdst[3] = {c->W, c->W + N, c->W + 2 * N};
+    double2* fdst[3] = {c->W, c->W + N, c->aux[set]};
     const int ops[3] = {bec::kOpMulKin, bec::kOpMulKin, bec::kOpMulDip};
     STCHK(kspace_apply(c, fsrc, fdst, 3, ops, nullptr));
     bec::HevalArgs ha{};
     ha.psi = c->psi[set];
     ha.Tpsi = c->W;
-    ha.phi = c->W + 2 * N;
+    ha.phi = c->aux[set];
     ha.hpsi = c->hpsi[set];
     ha.aux = c->aux[set];
     ha.partials = c->partials;
-    LAUNCH(c, "heval_epilogue", (double)c->N * 144.0, bec::launch_heval_epi(c->P, ha, c->nblk_pw, c->st));
+    LAUNCH(c, "heval_epilogue", (double)c->N * 128.0, bec::launch_heval_epi(c->P, ha, c->nblk_pw, c->st));
     STCHK(reduce_pw(c, bec::kHevalSums, 0));
     STCHK(fetch(c, bec::kHevalSums));
     const double* S = c->host;
@@ -828,12 +832,18 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
         c->nodes = (double*)at(21);
         c->partials = (double*)at(22);
         c->fft_partials = (double*)at(23);
-        c->scal = (double*)at(24);
         c->nblk_pw = (int)std::min<long long>((c->N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwDefaultBlocks);
         c->nblk_x = bec::fft_blocks(c->n[0], c->fft_var[0][1], (long long)c->n[1] * c->n[2]);
+        // reduced scalars: the final-reduction kernels write straight into pinned
+        // host memory, so reading them back needs a stream synchronisation only
         if (hipHostMalloc((void**)&c->host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             delete c;
             return fail(BEC_EHIP, "hipHostMalloc of the scalar buffer failed");
+        }
+        if (hipHostGetDevicePointer((void**)&c->scal, c->host, 0) != hipSuccess) {
+            (void)hipHostFree(c->host);
+            delete c;
+            return fail(BEC_EHIP, "hipHostGetDevicePointer of the scalar buffer failed");
         }
         // twiddles W_L^m and wavenumbers per axis
         for (int d = 0; d < 3; ++d) {

@@ -107,7 +107,7 @@ struct HevalArgs {
     const double2* Tpsi;          // 2N: -1/2 Lap psi_i
     const double2* phi;           // N: Phi_1 + i Phi_2
     double2* hpsi;                // 2N out
-    double2* aux;                 // 2N out: [0,N) Phi packed copy, [N,2N) muLHY_1 + i muLHY_2
+    double2* aux;                 // 2N out: [0,N) Phi packed (copied unless phi == aux), [N,2N) muLHY_1 + i muLHY_2
     double* partials;
 };
 constexpr int kHevalSums = 18;

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kPwThreads) void heval_epi_kernel(PwParams P, Heval
         const double2 h2 = make_double2(t2.x + U2 * s2.x, t2.y + U2 * s2.y);
         A.hpsi[i] = h1;
         A.hpsi[N + i] = h2;
-        A.aux[i] = ph;
+        if (A.phi != A.aux) A.aux[i] = ph;      // uniform: Phi already in place otherwise
         A.aux[N + i] = make_double2(m1, m2);
         acc[0] += redot(s1, t1);
         acc[1] += redot(s2, t2);
