@@ -658,6 +658,9 @@ struct Model {
     double pnorm[2], rp, E1, E2, psip[2];
 };
 
+static_assert(bec::kDirWriteSums + bec::kLsEpiSums <= 30, "model scalars overlap the Parseval slots");
+static_assert(bec::kDirWriteSums + bec::kLsEpiSums <= bec::kMaxSums, "model partials exceed the partials area");
+
 // Direction write pass (p, r, rho) + Parseval FFT of p + dipolar FFT of rho +
 // model epilogue; one synchronisation for all the model scalars.
 bec_status direction_and_model(bec_ctx* c, const bec::DirArgs& A, const Eval& ev, Model* m)
@@ -665,8 +668,6 @@ bec_status direction_and_model(bec_ctx* c, const bec::DirArgs& A, const Eval& ev
     const long long N = c->N;
     const double wb = 96.0 + (A.beta != 0.0 ? 32.0 : 0.0) + (A.zmode == 2 ? 32.0 : 0.0) + 80.0;
     LAUNCH(c, "dir_write", (double)c->N * wb, bec::launch_dir_write(c->P, A, c->nblk_pw, c->st));
-    LAUNCH(c, "reduce_final", 8.0 * bec::kDirWriteSums * c->nblk_pw,
-           bec::launch_reduce_final(c->partials, c->nblk_pw, bec::kDirWriteSums, c->scal, c->st));
     const double2* src[3] = {c->pdir, c->pdir + N, c->rho};
     double2* dst[3] = {c->W, c->W + N, c->W + 2 * N};
     const int ops[3] = {bec::kOpParseval, bec::kOpParseval, bec::kOpMulDip};
@@ -674,17 +675,17 @@ bec_status direction_and_model(bec_ctx* c, const bec::DirArgs& A, const Eval& ev
     bec::LsEpiArgs la{};
     la.rho = c->rho;
     la.phr = c->W + 2 * N;
-    la.partials = c->partials;
+    // the epilogue's partials follow the direction-write rows, so one launch
+    // reduces both together with the two Parseval sums of the x pass
+    la.partials = c->partials + (long long)bec::kDirWriteSums * c->nblk_pw;
     LAUNCH(c, "ls_epilogue", (double)N * 32.0, bec::launch_ls_epi(c->P, la, c->nblk_pw, c->st));
-    LAUNCH(c, "reduce_final", 8.0 * bec::kLsEpiSums * c->nblk_pw,
-           bec::launch_reduce_final(c->partials, c->nblk_pw, bec::kLsEpiSums, c->scal + 20, c->st));
-    LAUNCH(c, "reduce_final", 8.0 * c->nblk_x, bec::launch_reduce_final(c->fft_partials, c->nblk_x, 1, c->scal + 30, c->st));
-    LAUNCH(c, "reduce_final", 8.0 * c->nblk_x,
-           bec::launch_reduce_final(c->fft_partials + c->nblk_x, c->nblk_x, 1, c->scal + 31, c->st));
+    LAUNCH(c, "reduce_final", 8.0 * ((bec::kDirWriteSums + bec::kLsEpiSums) * c->nblk_pw + 2 * c->nblk_x),
+           bec::launch_reduce_final2(c->partials, c->nblk_pw, bec::kDirWriteSums + bec::kLsEpiSums, c->scal,
+                                     c->fft_partials, c->nblk_x, 2, c->scal + 30, c->st));
     STCHK(fetch(c, 32));
     const double* S = c->host;
     std::memcpy(m->D, S, sizeof(m->D));
-    std::memcpy(m->LS, S + 20, sizeof(m->LS));
+    std::memcpy(m->LS, S + bec::kDirWriteSums, sizeof(m->LS));
     m->pars[0] = S[30];
     m->pars[1] = S[31];
     const double dV = c->dV;

@@ -181,6 +181,9 @@ hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hps
                        double mu0, double mu1, double s0, double s1, int projected, hipStream_t s);
 // out[m] = sum_b partials[m * nblk + b] for m < M (fixed order), one block
 hipError_t launch_reduce_final(const double* partials, int nblk, int M, double* out, hipStream_t s);
+// two partial arrays in one launch (M1 rows of nblk1, then M2 rows of nblk2)
+hipError_t launch_reduce_final2(const double* partials1, int nblk1, int M1, double* out1, const double* partials2,
+                                int nblk2, int M2, double* out2, hipStream_t s);
 
 // ---------------------------------------------------------------- batched scan
 // Instances with the same grid shape form a group; every batched kernel covers

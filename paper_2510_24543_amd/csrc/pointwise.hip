@@ -428,10 +428,17 @@ __global__ __launch_bounds__(kPwThreads) void grad_kernel(PwParams P, const doub
 }
 
 // one workgroup per reduced scalar m: out[m] = sum_b partials[m * nblk + b]
-__global__ __launch_bounds__(256) void reduce_final_kernel(const double* partials, int nblk, double* out)
+// One block per scalar: blocks [0, M1) reduce rows of partials1 (nblk1 per row)
+// into out1, blocks [M1, M1 + M2) rows of partials2 into out2.
+__global__ __launch_bounds__(256) void reduce_final_kernel(const double* partials1, int nblk1, int M1, double* out1,
+                                                           const double* partials2, int nblk2, double* out2)
 {
     __shared__ double sh[4];
-    const int m = blockIdx.x;
+    const bool first = (int)blockIdx.x < M1;
+    const int m = first ? (int)blockIdx.x : (int)blockIdx.x - M1;
+    const double* partials = first ? partials1 : partials2;
+    const int nblk = first ? nblk1 : nblk2;
+    double* out = first ? out1 : out2;
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256) s += partials[(long long)m * nblk + b];
 #pragma unroll
@@ -510,7 +517,16 @@ hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hps
 
 hipError_t launch_reduce_final(const double* partials, int nblk, int M, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(M), dim3(256), 0, s, partials, nblk, out);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(M), dim3(256), 0, s, partials, nblk, M, out,
+                       (const double*)nullptr, 0, (double*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_final2(const double* partials1, int nblk1, int M1, double* out1, const double* partials2,
+                                int nblk2, int M2, double* out2, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(M1 + M2), dim3(256), 0, s, partials1, nblk1, M1, out1, partials2,
+                       nblk2, out2);
     return hipGetLastError();
 }
 
