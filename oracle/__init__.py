@@ -71,6 +71,10 @@ class Iter(C.Structure):
                 ("beta", C.c_double)]
 
 
+class IteOpts(C.Structure):
+    _fields_ = [("dt", C.c_double), ("tol_dE", C.c_double), ("max_iter", C.c_int32), ("pad", C.c_int32)]
+
+
 class Report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_restarts", C.c_int32), ("n_backtracks", C.c_int32),
                 ("status", C.c_int32), ("final", Terms)]
@@ -97,6 +101,8 @@ def lib():
         L.orc_param_grad.argtypes = [C.POINTER(Grid), C.POINTER(Params), dp, dp]
         L.orc_solve.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.POINTER(Opts), dp,
                                 C.POINTER(Report), C.POINTER(Iter), C.c_int32]
+        L.orc_ite.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.POINTER(IteOpts), dp,
+                              C.POINTER(Report), dp, C.c_int32]
         _lib = L
     return _lib
 
@@ -242,3 +248,20 @@ def solve(grid: dict, params: dict, psi0: np.ndarray, opts: dict | None = None, 
     n_log = min(rep.iters, log_cap)
     log = [{k: getattr(logs[i], k) for k, _ in Iter._fields_} for i in range(n_log)]
     return psi, out, log
+
+
+def ite(grid: dict, params: dict, psi0: np.ndarray, dt: float, tol_dE: float = 1e-6, max_iter: int = 100000,
+        log_cap: int = 0):
+    """Imaginary-time evolution (normalised first-order time splitting) from
+    psi0; returns (psi, report, energies of the iterates psi^0, psi^1, ...)."""
+    g = make_grid(grid["n"], grid["lo"], grid["hi"])
+    psi = _field(psi0, grid["n"]).copy()
+    rep = Report()
+    logE = np.zeros(max(log_cap, 1))
+    st = lib().orc_ite(C.byref(g), C.byref(make_params(params)),
+                       C.byref(IteOpts(dt=dt, tol_dE=tol_dE, max_iter=max_iter, pad=0)), _dp(psi),
+                       C.byref(rep), _dp(logE), log_cap)
+    if st == 1:
+        raise RuntimeError("oracle ite: invalid input")
+    out = {"iters": rep.iters, "status": STATUS.get(rep.status, rep.status), "final": rep.final.to_dict()}
+    return psi, out, logE[:min(rep.iters + 1, log_cap)]

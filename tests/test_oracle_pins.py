@@ -550,3 +550,69 @@ def test_envelope_theorem_for_converged_states(orc):
         Es.append(r2["final"]["E"])
     fd = (Es[0] - Es[1]) / (2 * h)
     assert abs(fd - dE) < 1e-6 * abs(dE)
+
+
+# ---------------------------------------------------------------- ITE baseline
+def split_step_top_vector(n, lo, hi, omega, dt):
+    """Dominant eigenvector of the 1D split-step map diag(exp(-dt V)) F^-1 diag(exp(-dt k^2/2)) F
+    (dense matrices; the 3D map of a separable linear problem is the tensor product)."""
+    L = hi - lo
+    x = lo + L / n * np.arange(n)
+    F = dft_matrix(n)
+    C = (np.linalg.inv(F) @ np.diag(np.exp(-dt * 0.5 * kvec(n, L) ** 2)) @ F).real
+    A = np.diag(np.exp(-dt * 0.5 * omega ** 2 * x ** 2)) @ C
+    w, v = np.linalg.eig(A)
+    top = np.argmax(w.real)
+    u = np.abs(v[:, top].real)
+    return u / np.linalg.norm(u)
+
+
+@pytest.mark.parametrize("dt", [0.05, 0.2])
+def test_ite_linear_fixed_point_is_tensor_product_of_1d_eigenvectors(orc, dt):
+    grid = make_grid((12, 16, 20), (-6, -6, -6), (6, 6, 6))
+    om = (1.0, 1.3, 2.0)
+    P = params(N=(1.0, 1.6), omega=om)
+    psi0 = inputs.initial_state(grid, om, 81, phase=True)
+    psi, rep, logE = orc.ite(grid, P, psi0, dt, tol_dE=0.0, max_iter=int(60 / dt), log_cap=0)
+    assert rep["status"] == "ENOTCONV"         # tol 0: runs the full max_iter steps
+    vs = [split_step_top_vector(grid["n"][d], grid["lo"][d], grid["hi"][d], om[d], dt) for d in range(3)]
+    ref = np.einsum("i,j,k->ijk", vs[0] ** 2, vs[1] ** 2, vs[2] ** 2)
+    ref /= ref.sum() * dvol(grid)
+    for i in range(2):
+        n_i = np.abs(psi[i]) ** 2
+        assert np.max(np.abs(n_i - ref)) < 1e-11 * np.max(ref)
+
+
+P_ITE = {"N": [1.0, 1.6], "omega": [2.0, 2.0, 3.0], "G": [[10.0, 4.0], [2.5, 8.0]],
+         "Gdd": [[5.0, 3.0], [1.875, 4.0]], "c_lhy": 2.0, "r_cut": 4.0, "n_u": 16}
+GRID_ITE = {"n": [12, 12, 16], "lo": [-4, -4, -4], "hi": [4, 4, 4]}
+
+
+def test_ite_energy_decreases_and_stops_on_energy_change(orc):
+    psi0 = inputs.initial_state(GRID_ITE, P_ITE["omega"], 5)
+    psi, rep, logE = orc.ite(GRID_ITE, P_ITE, psi0, 0.01, tol_dE=1e-9, max_iter=20000, log_cap=20001)
+    assert rep["status"] == "OK"
+    n = rep["iters"]
+    assert len(logE) == n + 1
+    assert np.all(np.diff(logE) <= 1e-13 * abs(logE[0]))
+    assert abs(logE[-1] - logE[-2]) < 1e-9 <= abs(logE[-2] - logE[-3])
+    # the returned state is normalised and its energy is the last logged one
+    t, _, _, _ = orc.heval(GRID_ITE, P_ITE, psi)
+    assert abs(t["E"] - logE[-1]) < 1e-13 * abs(logE[-1])
+    assert abs(rep["final"]["E"] - logE[-1]) < 1e-13 * abs(logE[-1])
+    assert max(abs(x - 1.0) for x in t["norm2"]) < 1e-13
+
+
+def test_ite_fixed_point_energy_converges_to_cg_minimum_at_second_order(orc):
+    """The splitting's fixed point differs from the minimiser by O(dt) in the
+    state, so its energy exceeds the CG minimum by O(dt^2)."""
+    psi0 = inputs.initial_state(GRID_ITE, P_ITE["omega"], 5)
+    _, rc, _ = orc.solve(GRID_ITE, P_ITE, psi0, {"tol_grad": 1e-11, "max_iter": 5000})
+    assert rc["status"] == "OK"
+    gaps = []
+    for dt in (0.02, 0.01):
+        _, r, _ = orc.ite(GRID_ITE, P_ITE, psi0, dt, tol_dE=1e-11, max_iter=40000)
+        assert r["status"] == "OK"
+        gaps.append(r["final"]["E"] - rc["final"]["E"])
+    assert gaps[0] > 0 and gaps[1] > 0
+    assert 3.8 < gaps[0] / gaps[1] < 4.2
