@@ -187,6 +187,30 @@ bec_status bec_linesearch(bec_ctx* ctx, const double* psi, const double* d, doub
 bec_status bec_solve(bec_ctx* ctx, double* psi_inout, const bec_opts* opts, bec_report* out_h,
                      bec_iter* log_h, int32_t log_cap);
 
+/* Options of the imaginary-time baseline. */
+typedef struct {
+    double dt;          /* imaginary-time step > 0                              */
+    double tol_dE;      /* stop when |E(psi^n) - E(psi^(n-1))| < tol_dE        */
+    int32_t max_iter;   /* steps before BEC_ENOTCONV                            */
+    int32_t pad;
+} bec_ite_opts;
+
+/* Imaginary-time evolution, the method the paper compares against (Sec. VI;
+ * its stopping rule |Delta E| < 1e-6 is Sec. VI.B).  One step is the
+ * normalised first-order splitting of d psi_i/d tau = -H_i psi_i:
+ *   psi_i <- N[ exp(-dt U_i(psi)) F^-1 exp(-dt |k|^2/2) F psi_i ],
+ * U_i = V + sum_j (G_ij n_j + Gdd_ij Phi_j) + muLHY_i at the current iterate,
+ * N normalising each component.  The energy of every iterate is evaluated (its
+ * kinetic part by Parseval inside the same transforms); the run stops at the
+ * first n >= 1 with |E(psi^n) - E(psi^(n-1))| < tol_dE and returns psi^n.
+ * psi_inout (device) holds the initial state (normalised on entry) and
+ * receives the final one; log_h optionally receives E(psi^0..) (host, log_cap
+ * doubles); out_h->final holds the energy terms and residual norms of the
+ * returned state, out_h->iters the steps taken.  Returns BEC_OK, BEC_ENOTCONV
+ * (max_iter steps), BEC_EINVAL or BEC_ENONFINITE.  Synchronises every step. */
+bec_status bec_ite_solve(bec_ctx* ctx, double* psi_inout, const bec_ite_opts* opts, bec_report* out_h,
+                         double* log_h, int32_t log_cap);
+
 /* Derivatives of E with respect to the couplings at fixed psi, each matrix
  * entry treated as independent: dG[i][j] = dE/dG_ij, dGdd[i][j] = dE/dGdd_ij,
  * dc_lhy = dE/dc_lhy.  At a converged state these are the derivatives of the

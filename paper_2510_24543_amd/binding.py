@@ -62,6 +62,10 @@ class Iter(C.Structure):
                 ("E1", C.c_double), ("E2", C.c_double), ("alpha", C.c_double), ("beta", C.c_double)]
 
 
+class IteOpts(C.Structure):
+    _fields_ = [("dt", C.c_double), ("tol_dE", C.c_double), ("max_iter", C.c_int32), ("pad", C.c_int32)]
+
+
 class Report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_restarts", C.c_int32), ("n_backtracks", C.c_int32),
                 ("status", C.c_int32), ("final", Terms), ("seconds", C.c_double)]
@@ -92,6 +96,7 @@ SIGNATURES = [
     ("bec_linesearch", C.c_int, [_VP, _VP, _VP, _VP, C.POINTER(Opts), C.POINTER(LsReport)]),
     ("bec_solve", C.c_int, [_VP, _VP, C.POINTER(Opts), C.POINTER(Report), C.POINTER(Iter), _I32]),
     ("bec_param_grad", C.c_int, [_VP, _VP, C.POINTER(_D22), C.POINTER(_D22), _DP]),
+    ("bec_ite_solve", C.c_int, [_VP, _VP, C.POINTER(IteOpts), C.POINTER(Report), _DP, _I32]),
     ("bec_batch_workspace_size", C.c_int, [_I32, C.POINTER(Grid), C.POINTER(Params), C.POINTER(C.c_size_t)]),
     ("bec_batch_create", C.c_int, [_I32, C.POINTER(Grid), C.POINTER(Params), _VP, _VP, C.c_size_t,
                                    C.POINTER(_VP)]),

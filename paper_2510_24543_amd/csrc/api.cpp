@@ -510,6 +510,8 @@ bec_status kspace_apply(bec_ctx* c, const double2* const* src, double2* const* d
 }
 
 // ------------------------------------------------------------------ reductions
+constexpr int kParsevalOut = 30;    // scal slots of the two Parseval sums of an x pass
+
 // c->scal is the device address of the pinned host buffer c->host
 bec_status fetch(bec_ctx* c, int M)
 {
@@ -658,7 +660,8 @@ struct Model {
     double pnorm[2], rp, E1, E2, psip[2];
 };
 
-static_assert(bec::kDirWriteSums + bec::kLsEpiSums <= 30, "model scalars overlap the Parseval slots");
+static_assert(bec::kDirWriteSums + bec::kLsEpiSums <= kParsevalOut, "model scalars overlap the Parseval slots");
+static_assert(bec::kIteSums <= kParsevalOut, "imaginary-time sums overlap the Parseval slots");
 static_assert(bec::kDirWriteSums + bec::kLsEpiSums <= bec::kMaxSums, "model partials exceed the partials area");
 
 // Direction write pass (p, r, rho) + Parseval FFT of p + dipolar FFT of rho +
@@ -681,13 +684,13 @@ bec_status direction_and_model(bec_ctx* c, const bec::DirArgs& A, const Eval& ev
     LAUNCH(c, "ls_epilogue", (double)N * 32.0, bec::launch_ls_epi(c->P, la, c->nblk_pw, c->st));
     LAUNCH(c, "reduce_final", 8.0 * ((bec::kDirWriteSums + bec::kLsEpiSums) * c->nblk_pw + 2 * c->nblk_x),
            bec::launch_reduce_final2(c->partials, c->nblk_pw, bec::kDirWriteSums + bec::kLsEpiSums, c->scal,
-                                     c->fft_partials, c->nblk_x, 2, c->scal + 30, c->st));
+                                     c->fft_partials, c->nblk_x, 2, c->scal + kParsevalOut, c->st));
     STCHK(fetch(c, 32));
     const double* S = c->host;
     std::memcpy(m->D, S, sizeof(m->D));
     std::memcpy(m->LS, S + bec::kDirWriteSums, sizeof(m->LS));
-    m->pars[0] = S[30];
-    m->pars[1] = S[31];
+    m->pars[0] = S[kParsevalOut];
+    m->pars[1] = S[kParsevalOut + 1];
     const double dV = c->dV;
     const bec_params& p = c->p;
     const double* D = m->D;
@@ -1277,6 +1280,88 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
     if (out_h) *out_h = rep;
     if (status != BEC_OK && status != BEC_ENOTCONV)
         fail(status, status == BEC_ESTAGNATED ? "no descent after a beta = 0 restart" : "non-finite state");
+    return status;
+}
+
+bec_status bec_ite_solve(bec_ctx* c, double* psi_inout, const bec_ite_opts* o, bec_report* out_h, double* log_E,
+                         int32_t log_cap)
+{
+    if (!c || !psi_inout || !o) return fail(BEC_EINVAL, "null argument");
+    if (!(o->dt > 0.0) || !std::isfinite(o->dt) || o->max_iter < 0 || !(o->tol_dE >= 0.0))
+        return fail(BEC_EINVAL, "need dt > 0, tol_dE >= 0, max_iter >= 0");
+    const auto t0 = std::chrono::steady_clock::now();
+    const long long N = c->N;
+    const double dV = c->dV;
+    const bec_params& p = c->p;
+    bec_report rep{};
+    STCHK(normalise_into(c, reinterpret_cast<const double2*>(psi_inout), 0));
+    // psi[0]: the iterate psi^n; psi[1]: exp(-dt U) F^-1 exp(-dt T) F psi^n (not normalised)
+    const double2* src = c->psi[0];
+    double a[2] = {1.0, 1.0};
+    int n = 0;
+    bec_status status = BEC_ENOTCONV;
+    double E_prev = NAN;
+    for (;;) {
+        bec::TrialArgs ta{};
+        ta.psi_src = src;
+        ta.p = nullptr;
+        ta.a[0] = a[0];
+        ta.a[1] = a[1];
+        ta.psi_dst = c->psi[0];
+        ta.dens = c->W + 2 * N;
+        LAUNCH(c, "trial_pack", (double)N * 80.0, bec::launch_trial(c->P, ta, c->st));
+        const double2* fsrc[3] = {c->psi[0], c->psi[0] + N, c->W + 2 * N};
+        double2* fdst[3] = {c->W, c->W + N, c->aux[0]};
+        const int ops[3] = {bec::kOpExpKin, bec::kOpExpKin, bec::kOpMulDip};
+        const double dts[3] = {o->dt, o->dt, 0.0};
+        STCHK(kspace_apply(c, fsrc, fdst, 3, ops, dts));
+        bec::IteArgs ia{};
+        ia.psi = c->psi[0];
+        ia.hat = c->W;
+        ia.phi = c->aux[0];
+        ia.out = c->psi[1];
+        ia.dt = o->dt;
+        ia.partials = c->partials;
+        LAUNCH(c, "ite_epilogue", (double)N * 112.0, bec::launch_ite_epi(c->P, ia, c->nblk_pw, c->st));
+        LAUNCH(c, "reduce_final", 8.0 * (bec::kIteSums * c->nblk_pw + 2 * c->nblk_x),
+               bec::launch_reduce_final2(c->partials, c->nblk_pw, bec::kIteSums, c->scal, c->fft_partials,
+                                         c->nblk_x, 2, c->scal + kParsevalOut, c->st));
+        STCHK(fetch(c, 32));
+        const double* S = c->host;
+        // energy of psi^n (Sec. II, Eq. (1)); kinetic part by Parseval of F psi^n
+        double E = dV * S[9];
+        for (int i = 0; i < 2; ++i) {
+            E += p.N[i] * dV * (S[kParsevalOut + i] / (double)N + S[i]);
+            const double nn[2] = {i == 0 ? S[2] : S[3], i == 0 ? S[3] : S[4]};
+            for (int j = 0; j < 2; ++j)
+                E += 0.5 * p.N[i] * dV * (p.G[i][j] * nn[j] + p.Gdd[i][j] * S[5 + 2 * i + j]);
+        }
+        if (log_E && n < log_cap) log_E[n] = E;
+        if (!std::isfinite(E)) { status = BEC_ENONFINITE; break; }
+        if (n >= 1 && std::fabs(E - E_prev) < o->tol_dE) { status = BEC_OK; break; }
+        if (n >= o->max_iter) { status = BEC_ENOTCONV; break; }
+        E_prev = E;
+        for (int i = 0; i < 2; ++i) {
+            const double nrm2 = dV * S[12 + i];
+            if (!(nrm2 > 0.0) || !std::isfinite(nrm2)) return fail(BEC_ENONFINITE, "imaginary-time step lost the norm");
+            a[i] = 1.0 / std::sqrt(nrm2);
+        }
+        src = c->psi[1];
+        ++n;
+    }
+    Eval ev;
+    if (status != BEC_ENONFINITE) {
+        STCHK(heval(c, c->psi[0], nullptr, kOne, kZero, 1, &ev));
+        STCHK(residual_norms(c, 1, &ev));
+        rep.final = ev.t;
+    }
+    HIPCHK(hipMemcpyAsync(psi_inout, c->psi[0], 2 * N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    rep.iters = n;
+    rep.status = status;
+    rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (out_h) *out_h = rep;
+    if (status == BEC_ENONFINITE) fail(status, "non-finite energy");
     return status;
 }
 

@@ -48,7 +48,8 @@ enum FftOp : int {
     kOpMulKin = 1,      // forward, times |k|^2/2 /N, inverse, store
     kOpMulDip = 2,      // forward, times Ud(k)/N, inverse, store
     kOpMulPrec = 3,     // forward, times 1/(a_f + |k|^2/2)/N, inverse, store
-    kOpParseval = 4     // forward, accumulate sum |k|^2/2 |v|^2, no store
+    kOpParseval = 4,    // forward, accumulate sum |k|^2/2 |v|^2, no store
+    kOpExpKin = 5       // forward, accumulate as kOpParseval, times exp(-a_f |k|^2/2)/N, inverse, store
 };
 
 struct FftPassArgs {
@@ -101,6 +102,20 @@ struct TrialArgs {                // psi_dst = a_i psi_src + b_i p ; W2 = n1 + i
     double2* psi_dst;
     double2* dens;                // packed density n1 + i n2
 };
+
+// Imaginary-time step epilogue: out_i = exp(-dt U_i) hat_i with U_i the
+// potential part of H_i at psi; sums see kIteSums.
+struct IteArgs {
+    const double2* psi;           // 2N: the current iterate
+    const double2* hat;           // 2N: F^-1 exp(-dt |k|^2/2) F psi_i
+    const double2* phi;           // N: Phi_1 + i Phi_2 of psi
+    double2* out;                 // 2N
+    double dt;
+    double* partials;
+};
+constexpr int kIteSums = 14;
+// sums: 0,1 V n_i; 2 n1n1; 3 n1n2; 4 n2n2; 5..8 n_i Phi_j (11,12,21,22); 9 e_LHY;
+//       10,11 n_i; 12,13 |out_i|^2
 
 struct HevalArgs {
     const double2* psi;
@@ -169,6 +184,7 @@ constexpr int kParamSums = 9;     // 0..3 de/deta_ij (11,12,21,22); 4..7 same ti
 
 hipError_t launch_trial(const PwParams& P, const TrialArgs& a, hipStream_t s);
 hipError_t launch_heval_epi(const PwParams& P, const HevalArgs& a, int nblk, hipStream_t s);
+hipError_t launch_ite_epi(const PwParams& P, const IteArgs& a, int nblk, hipStream_t s);
 hipError_t launch_dir_reduce(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s);
 hipError_t launch_dir_write(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s);
 hipError_t launch_ls_epi(const PwParams& P, const LsEpiArgs& a, int nblk, hipStream_t s);

@@ -291,7 +291,7 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
         ay = iy <= A.ny / 2 ? iy : A.ny - iy;
         az = iz <= A.nz / 2 ? iz : A.nz - iz;
     }
-    if (op == kOpParseval) {
+    if (op == kOpParseval || op == kOpExpKin) {
         double acc = 0.0;
 #pragma unroll
         for (int b = 0; b < E / RL; ++b)
@@ -306,7 +306,8 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
         __syncthreads();
         const double tot = block_sum<NTHR>(acc, reinterpret_cast<double*>(lds));
         if (threadIdx.x == 0) A.partials[((long long)inst * A.nfield + f) * A.nblk_x + blockIdx.x] = tot;
-        return;
+        if (op == kOpParseval) return;
+        __syncthreads();                               // lds is reused by the inverse transform
     }
     const double inv_n = A.inv_n;
     const double pa = A.prec_a[f];
@@ -319,6 +320,9 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
             if (op == kOpMulKin) {
                 const double kx = kxt[j];
                 m = 0.5 * (kx * kx + ky2 + kz2);
+            } else if (op == kOpExpKin) {
+                const double kx = kxt[j];
+                m = exp(-pa * 0.5 * (kx * kx + ky2 + kz2));
             } else if (op == kOpMulDip) {
                 const int ax = j <= L / 2 ? j : L - j;
                 m = udt[((long long)ax * (A.ny / 2 + 1) + ay) * (A.nz / 2 + 1) + az];

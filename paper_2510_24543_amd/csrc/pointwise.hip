@@ -143,6 +143,47 @@ __global__ __launch_bounds__(kPwThreads) void heval_epi_kernel(PwParams P, Heval
     block_reduce_store<kHevalSums>(acc, A.partials, gridDim.x);
 }
 
+// One imaginary-time step at point i (the potential factor of the splitting)
+// with the energy sums of the current iterate.
+__global__ __launch_bounds__(kPwThreads) void ite_epi_kernel(PwParams P, IteArgs A)
+{
+    const long long N = P.N;
+    double acc[kIteSums];
+#pragma unroll
+    for (int m = 0; m < kIteSums; ++m) acc[m] = 0.0;
+    for (long long i = (long long)blockIdx.x * kPwThreads + threadIdx.x; i < N;
+         i += (long long)gridDim.x * kPwThreads) {
+        const double2 s1 = A.psi[i], s2 = A.psi[N + i];
+        const double2 h1 = A.hat[i], h2 = A.hat[N + i];
+        const double2 ph = A.phi[i];
+        const double n1 = sq2(s1), n2 = sq2(s2);
+        const double V = trap_at(P, i);
+        double e = 0.0, d1 = 0.0, d2 = 0.0;
+        if (P.lhy_on) lhy_point(KernargNodes{P}, P.n_a, P.n_b, P.K5, P.K3, n1, n2, e, d1, d2);
+        const double U1 = V + P.G[0][0] * n1 + P.G[0][1] * n2 + P.Gdd[0][0] * ph.x + P.Gdd[0][1] * ph.y + d1 / P.Nat[0];
+        const double U2 = V + P.G[1][0] * n1 + P.G[1][1] * n2 + P.Gdd[1][0] * ph.x + P.Gdd[1][1] * ph.y + d2 / P.Nat[1];
+        const double f1 = exp(-A.dt * U1), f2 = exp(-A.dt * U2);
+        const double2 o1 = make_double2(f1 * h1.x, f1 * h1.y), o2 = make_double2(f2 * h2.x, f2 * h2.y);
+        A.out[i] = o1;
+        A.out[N + i] = o2;
+        acc[0] += V * n1;
+        acc[1] += V * n2;
+        acc[2] += n1 * n1;
+        acc[3] += n1 * n2;
+        acc[4] += n2 * n2;
+        acc[5] += n1 * ph.x;
+        acc[6] += n1 * ph.y;
+        acc[7] += n2 * ph.x;
+        acc[8] += n2 * ph.y;
+        acc[9] += e;
+        acc[10] += n1;
+        acc[11] += n2;
+        acc[12] += sq2(o1);
+        acc[13] += sq2(o2);
+    }
+    block_reduce_store<kIteSums>(acc, A.partials, gridDim.x);
+}
+
 // residual and preconditioned residual at point i for both components
 struct RZ {
     double2 r[2], z[2];
@@ -455,6 +496,12 @@ int pw_blocks(const PwParams& P) { return P.nblk_pw; }
 hipError_t launch_trial(const PwParams& P, const TrialArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(trial_kernel, dim3(pw_blocks(P)), dim3(kPwThreads), 0, s, P, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ite_epi(const PwParams& P, const IteArgs& a, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(ite_epi_kernel, dim3(nblk), dim3(kPwThreads), 0, s, P, a);
     return hipGetLastError();
 }
 
