@@ -494,10 +494,35 @@ bec_status fft3d_plain(bec_ctx* c, const double2* const* src, double2* const* ds
 // Diagonal k-space operators on nf fields: forward z, y, then the fused x pass
 // (ops per field), then inverse y, z for the fields that are stored.
 // Parseval fields come first in the list (they end at the x pass).
+bec_status kspace_after_z(bec_ctx* c, double2* const* dst, int nf, const int* ops, const double* prec_a);
+
 bec_status kspace_apply(bec_ctx* c, const double2* const* src, double2* const* dst, int nf, const int* ops,
                         const double* prec_a)
 {
     STCHK(run_pass(c, 2, src, dst, nf, -1, 1.0, nullptr, nullptr));
+    return kspace_after_z(c, dst, nf, ops, prec_a);
+}
+
+// The same for the three fields (psi_1, psi_2, packed density) of the trial
+// point psi_dst = a_i psi_src + b_i p: the trial update rides in the loads of
+// the forward z pass, which also stores psi_dst.
+bec_status kspace_apply_trial(bec_ctx* c, const bec::TrialZArgs& Z, double2* const* dst, const int* ops,
+                              const double* prec_a)
+{
+    bec::FftPassArgs A = pass_args(c, 2);
+    A.nfield = 3;
+    A.sign = -1;
+    for (int f = 0; f < 3; ++f) {
+        A.src[f] = dst[f];
+        A.dst[f] = dst[f];
+    }
+    const double bytes = (double)c->N * ((Z.p ? 64.0 : 32.0) + 32.0 + 48.0);
+    LAUNCH(c, "fft_z_trial", bytes, bec::fft_trial_z_pass(c->n[2], c->fft_var[2][0], A, Z, c->st));
+    return kspace_after_z(c, dst, 3, ops, prec_a);
+}
+
+bec_status kspace_after_z(bec_ctx* c, double2* const* dst, int nf, const int* ops, const double* prec_a)
+{
     STCHK(run_pass(c, 1, dst, dst, nf, -1, 1.0, nullptr, nullptr));
     STCHK(run_pass(c, 0, dst, dst, nf, -1, 1.0, ops, prec_a));
     int first = 0;
@@ -538,22 +563,20 @@ bec_status heval(bec_ctx* c, const double2* src, const double2* p, const double 
                  Eval* out)
 {
     const long long N = c->N;
-    bec::TrialArgs ta{};
-    ta.psi_src = src;
-    ta.p = p;
+    bec::TrialZArgs z{};
+    z.psi_src = src;
+    z.p = p;
     for (int i = 0; i < 2; ++i) {
-        ta.a[i] = a[i];
-        ta.b[i] = b[i];
+        z.a[i] = a[i];
+        z.b[i] = b[i];
     }
-    ta.psi_dst = c->psi[set];
-    ta.dens = c->W + 2 * N;
-    LAUNCH(c, "trial_pack", (double)c->N * (p ? 112.0 : 80.0), bec::launch_trial(c->P, ta, c->st));
+    z.psi_dst = c->psi[set];
+    z.N = N;
     // the dipolar potentials Phi_1 + i Phi_2 land directly in aux[set] (its first
     // half), where the later passes read them
-    const double2* fsrc[3] = {c->psi[set], c->psi[set] + N, c->W + 2 * N};
     double2* fdst[3] = {c->W, c->W + N, c->aux[set]};
     const int ops[3] = {bec::kOpMulKin, bec::kOpMulKin, bec::kOpMulDip};
-    STCHK(kspace_apply(c, fsrc, fdst, 3, ops, nullptr));
+    STCHK(kspace_apply_trial(c, z, fdst, ops, nullptr));
     bec::HevalArgs ha{};
     ha.psi = c->psi[set];
     ha.Tpsi = c->W;
@@ -1302,19 +1325,17 @@ bec_status bec_ite_solve(bec_ctx* c, double* psi_inout, const bec_ite_opts* o, b
     bec_status status = BEC_ENOTCONV;
     double E_prev = NAN;
     for (;;) {
-        bec::TrialArgs ta{};
-        ta.psi_src = src;
-        ta.p = nullptr;
-        ta.a[0] = a[0];
-        ta.a[1] = a[1];
-        ta.psi_dst = c->psi[0];
-        ta.dens = c->W + 2 * N;
-        LAUNCH(c, "trial_pack", (double)N * 80.0, bec::launch_trial(c->P, ta, c->st));
-        const double2* fsrc[3] = {c->psi[0], c->psi[0] + N, c->W + 2 * N};
+        bec::TrialZArgs z{};
+        z.psi_src = src;
+        z.p = nullptr;
+        z.a[0] = a[0];
+        z.a[1] = a[1];
+        z.psi_dst = c->psi[0];
+        z.N = N;
         double2* fdst[3] = {c->W, c->W + N, c->aux[0]};
         const int ops[3] = {bec::kOpExpKin, bec::kOpExpKin, bec::kOpMulDip};
         const double dts[3] = {o->dt, o->dt, 0.0};
-        STCHK(kspace_apply(c, fsrc, fdst, 3, ops, dts));
+        STCHK(kspace_apply_trial(c, z, fdst, ops, dts));
         bec::IteArgs ia{};
         ia.psi = c->psi[0];
         ia.hat = c->W;

@@ -86,6 +86,19 @@ struct FftPassArgs {
     long long udsize;      // doubles per instance in udtab
 };
 
+// Forward z pass fused with the geodesic trial update: psi_dst = a_i psi_src +
+// b_i p (p may be null) is stored, and the forward z transforms of psi_dst_1,
+// psi_dst_2 and of the packed density |psi_dst_1|^2 + i |psi_dst_2|^2 go to
+// args.dst[0..2].  args is a z-axis pass (S = 1).
+struct TrialZArgs {
+    const double2* psi_src;       // 2N
+    const double2* p;             // 2N or null
+    double a[2], b[2];
+    double2* psi_dst;             // 2N (may equal psi_src)
+    long long N;                  // points per component
+};
+hipError_t fft_trial_z_pass(int L, int variant, const FftPassArgs& args, const TrialZArgs& z, hipStream_t s);
+
 // Launch one axis pass of length L over args.nfield fields with plan variant
 // `variant` (0 = default); `contiguous` for the z axis.
 hipError_t fft_pass(int L, int variant, bool contiguous, const FftPassArgs& args, hipStream_t s);
@@ -95,13 +108,6 @@ int fft_blocks(int L, int variant, long long npencil);   // grid.x of a pass
 int fft_max_blocks(int L, long long npencil);            // over all variants
 
 // ---------------------------------------------------------------- pointwise kernels
-struct TrialArgs {                // psi_dst = a_i psi_src + b_i p ; W2 = n1 + i n2
-    const double2* psi_src;
-    const double2* p;             // may be null (then psi_dst = a_i psi_src)
-    double a[2], b[2];
-    double2* psi_dst;
-    double2* dens;                // packed density n1 + i n2
-};
 
 // Imaginary-time step epilogue: out_i = exp(-dt U_i) hat_i with U_i the
 // potential part of H_i at psi; sums see kIteSums.
@@ -182,7 +188,6 @@ struct ParamGradArgs {
 };
 constexpr int kParamSums = 9;     // 0..3 de/deta_ij (11,12,21,22); 4..7 same times (3u^2-1); 8 e (c = 1)
 
-hipError_t launch_trial(const PwParams& P, const TrialArgs& a, hipStream_t s);
 hipError_t launch_heval_epi(const PwParams& P, const HevalArgs& a, int nblk, hipStream_t s);
 hipError_t launch_ite_epi(const PwParams& P, const IteArgs& a, int nblk, hipStream_t s);
 hipError_t launch_dir_reduce(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s);

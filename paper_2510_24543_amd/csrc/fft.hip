@@ -344,6 +344,83 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
     }
 }
 
+// Forward z pass with the trial update fused into its loads (see TrialZArgs):
+// all loads of both components are issued first, then the two components are
+// transformed one after the other, then the packed density kept from them.
+template <int L, int T, int R0, int R1, int R2, int NTHR>
+__global__ __launch_bounds__(NTHR) void fft_trial_z_kernel(FftPassArgs A, TrialZArgs Z)
+{
+    using PL = Plan<L, T, R0, R1, R2>;
+    constexpr int E = L / T, PB = NTHR / T, RS = L + 1, RL = PL::RL;
+    __shared__ double2 lds[PB * RS];
+    const int tid = threadIdx.x;
+    const int pl = tid / T, t = tid % T;
+    const long long pg = (long long)blockIdx.x * PB + pl;
+    const bool valid = pg < A.npencil;
+    const long long base = valid ? pg * (long long)L : 0;
+    const long long N = Z.N;
+    double2* row = lds + pl * RS;
+    double2 w0[E], w1[E];
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = b * R0 + r;
+            const long long j = base + t + b * T + r * (L / R0);
+            w0[k] = make_double2(0.0, 0.0);
+            w1[k] = make_double2(0.0, 0.0);
+            if (valid) {
+                const double2 x0 = Z.psi_src[j], x1 = Z.psi_src[N + j];
+                w0[k] = make_double2(Z.a[0] * x0.x, Z.a[0] * x0.y);
+                w1[k] = make_double2(Z.a[1] * x1.x, Z.a[1] * x1.y);
+                if (Z.p) {
+                    const double2 q0 = Z.p[j], q1 = Z.p[N + j];
+                    w0[k].x += Z.b[0] * q0.x;
+                    w0[k].y += Z.b[0] * q0.y;
+                    w1[k].x += Z.b[1] * q1.x;
+                    w1[k].y += Z.b[1] * q1.y;
+                }
+            }
+        }
+    double dn0[E];
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = b * R0 + r;
+            const long long j = base + t + b * T + r * (L / R0);
+            if (valid) {
+                Z.psi_dst[j] = w0[k];
+                Z.psi_dst[N + j] = w1[k];
+            }
+            dn0[k] = w0[k].x * w0[k].x + w0[k].y * w0[k].y;
+        }
+    PL::template fwd_like<-1>(w0, row, t, A.tw);
+    if (valid) {
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) A.dst[0][base + t + b * T + r * (L / RL)] = w0[b * RL + r];
+    }
+    // w0 is free now: it takes the packed density of the loaded points
+#pragma unroll
+    for (int k = 0; k < E; ++k) w0[k] = make_double2(dn0[k], w1[k].x * w1[k].x + w1[k].y * w1[k].y);
+    PL::template fwd_like<-1>(w1, row, t, A.tw);
+    if (valid) {
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) A.dst[1][base + t + b * T + r * (L / RL)] = w1[b * RL + r];
+    }
+    PL::template fwd_like<-1>(w0, row, t, A.tw);
+    if (valid) {
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) A.dst[2][base + t + b * T + r * (L / RL)] = w0[b * RL + r];
+    }
+}
+
 template <int L, int T, int R0, int R1, int R2, int NTHR>
 hipError_t launch_cfg(bool contiguous, const FftPassArgs& A, hipStream_t st)
 {
@@ -431,6 +508,20 @@ int fft_max_blocks(int L, long long npencil)
     int m = 0;
     for (int k = 0; k < fft_num_variants(L); ++k) m = std::max(m, fft_blocks(L, k, npencil));
     return m;
+}
+
+hipError_t fft_trial_z_pass(int L, int variant, const FftPassArgs& A, const TrialZArgs& Z, hipStream_t st)
+{
+    if (A.S != 1) return hipErrorInvalidValue;
+#define BEC_TCASE(LL, VV, T, R0, R1, R2, NT)                                                            \
+    if (L == LL && variant == VV) {                                                                      \
+        const dim3 grid((unsigned)((A.npencil + NT / T - 1) / (NT / T)));                                \
+        hipLaunchKernelGGL((fft_trial_z_kernel<LL, T, R0, R1, R2, NT>), grid, dim3(NT), 0, st, A, Z);    \
+        return hipGetLastError();                                                                        \
+    }
+    BEC_FFT_VARIANTS(BEC_TCASE)
+#undef BEC_TCASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t fft_pass(int L, int variant, bool contiguous, const FftPassArgs& A, hipStream_t st)

@@ -63,25 +63,6 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[M], doubl
     for (long long i = (long long)blockIdx.x * kPwThreads + threadIdx.x; i < (N);             \
          i += (long long)gridDim.x * kPwThreads)
 
-__global__ __launch_bounds__(kPwThreads) void trial_kernel(PwParams P, TrialArgs A)
-{
-    const long long N = P.N;
-    GRID_STRIDE(i, N)
-    {
-        double2 s1 = A.psi_src[i], s2 = A.psi_src[N + i];
-        double2 o1 = make_double2(A.a[0] * s1.x, A.a[0] * s1.y);
-        double2 o2 = make_double2(A.a[1] * s2.x, A.a[1] * s2.y);
-        if (A.p) {
-            const double2 p1 = A.p[i], p2 = A.p[N + i];
-            o1.x += A.b[0] * p1.x; o1.y += A.b[0] * p1.y;
-            o2.x += A.b[1] * p2.x; o2.y += A.b[1] * p2.y;
-        }
-        A.psi_dst[i] = o1;
-        A.psi_dst[N + i] = o2;
-        A.dens[i] = make_double2(sq2(o1), sq2(o2));
-    }
-}
-
 struct HevalIn {
     double2 s1, s2, t1, t2, ph;
 };
@@ -492,12 +473,6 @@ __global__ __launch_bounds__(256) void reduce_final_kernel(const double* partial
 int pw_blocks(const PwParams& P) { return P.nblk_pw; }
 
 }  // namespace
-
-hipError_t launch_trial(const PwParams& P, const TrialArgs& a, hipStream_t s)
-{
-    hipLaunchKernelGGL(trial_kernel, dim3(pw_blocks(P)), dim3(kPwThreads), 0, s, P, a);
-    return hipGetLastError();
-}
 
 hipError_t launch_ite_epi(const PwParams& P, const IteArgs& a, int nblk, hipStream_t s)
 {
