@@ -158,7 +158,7 @@ def cpu_baseline(grid, params, psi0, sample_iters: int):
                       f"oracle solve, {t2 - t0:.1f} s of CPU work)"}
 
 
-def pcg_vs_ite(ctx, psi0, base_opts: dict, dt: float, tol_dE: float = 1e-6, E_ref=None):
+def pcg_vs_ite(ctx, psi0, base_opts: dict, dt: float, tol_dE: float = 1e-6, E_ref=None, progress=None):
     """The paper's comparison (Sec. VI.B): PCG and imaginary-time evolution from
     the same start, both stopped by |E_n - E_(n-1)| < tol_dE; HIP-event times.
     E_ref (the PCG energy at |grad E| < 1e-8) measures how far each stopped
@@ -173,8 +173,10 @@ def pcg_vs_ite(ctx, psi0, base_opts: dict, dt: float, tol_dE: float = 1e-6, E_re
     torch.cuda.synchronize()
     out["pcg"] = {"iters": rep["iters"], "seconds": round(ev0.elapsed_time(ev1) / 1000.0, 4),
                   "E": rep["final"]["E"], "res_max": max(rep["final"]["res"]), "status": rep["status"]}
+    if progress:
+        print(f"{progress}: PCG under the dE rule done ({rep['iters']} iterations)", file=sys.stderr, flush=True)
     ev0.record(ctx.stream)
-    _, rep, _ = ctx.ite(psi0, dt, tol_dE=tol_dE, max_iter=200000)
+    _, rep, _ = ctx.ite(psi0, dt, tol_dE=tol_dE, max_iter=100000)
     ev1.record(ctx.stream)
     torch.cuda.synchronize()
     t = ev0.elapsed_time(ev1) / 1000.0
@@ -217,7 +219,8 @@ def ite_workload(name: str, dt: float):
     _, ref, _ = ctx.solve(psi0, dict(opts, tol_grad=1e-8, max_iter=20000))
     ev1.record(ctx.stream)
     torch.cuda.synchronize()
-    out = pcg_vs_ite(ctx, psi0, opts, dt, E_ref=ref["final"]["E"])
+    print(f"{name}: reference PCG solve done ({ref['iters']} iterations, {ref['status']})", file=sys.stderr, flush=True)
+    out = pcg_vs_ite(ctx, psi0, opts, dt, E_ref=ref["final"]["E"], progress=name)
     out["workload"] = name
     out["grid"] = cfg["grid"]["n"]
     out["pcg_to_1e-8"] = {"iters": ref["iters"], "status": ref["status"], "seconds": round(ev0.elapsed_time(ev1) / 1000, 4),
