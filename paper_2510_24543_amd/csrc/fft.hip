@@ -150,6 +150,13 @@ __device__ __forceinline__ void stage(double2* v, int t, const double2* __restri
     }
 }
 
+// LDS rows are padded by one element after every 8: the stride-R writes of
+// the first stages (R = 4..16, with the lanes of one pencil adjacent in the
+// contiguous z pass) then fall on different banks.
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
+template <int L>
+constexpr int lds_row() { return L + L / 8 + 1; }
+
 // Output of stage (R, NS): v[b R + r] goes to Y[(j/NS) NS R + (j mod NS) + r NS].
 // The next stage (radix RN) reads X[t + b T + r L/RN].
 template <int L, int T, int R, int NS, int RN>
@@ -161,13 +168,13 @@ __device__ __forceinline__ void exchange(double2* v, double2* row, int t)
         const int j = t + b * T;
         const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-        for (int r = 0; r < R; ++r) row[base + r * NS] = v[b * R + r];
+        for (int r = 0; r < R; ++r) row[lds_pad(base + r * NS)] = v[b * R + r];
     }
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < E / RN; ++b)
 #pragma unroll
-        for (int r = 0; r < RN; ++r) v[b * RN + r] = row[t + b * T + r * (L / RN)];
+        for (int r = 0; r < RN; ++r) v[b * RN + r] = row[lds_pad(t + b * T + r * (L / RN))];
     __syncthreads();
 }
 
@@ -225,7 +232,7 @@ template <int L, int T, int R0, int R1, int R2, int NTHR, bool CONTIG, int KMODE
 __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
 {
     using PL = Plan<L, T, R0, R1, R2>;
-    constexpr int E = L / T, PB = NTHR / T, RS = L + 1;
+    constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>();
     __shared__ double2 lds[PB * RS];
     const int f = blockIdx.y;
     const int inst = A.inst_ids ? A.inst_ids[blockIdx.z] : (int)blockIdx.z;
@@ -351,7 +358,7 @@ template <int L, int T, int R0, int R1, int R2, int NTHR>
 __global__ __launch_bounds__(NTHR) void fft_trial_z_kernel(FftPassArgs A, TrialZArgs Z)
 {
     using PL = Plan<L, T, R0, R1, R2>;
-    constexpr int E = L / T, PB = NTHR / T, RS = L + 1, RL = PL::RL;
+    constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>(), RL = PL::RL;
     __shared__ double2 lds[PB * RS];
     const int tid = threadIdx.x;
     const int pl = tid / T, t = tid % T;

@@ -120,6 +120,14 @@ CASES = {
     "nu1_noLHY": ({"n": [32, 16, 8], "lo": [-6, -5, -4], "hi": [6, 5, 4]}, small_params(n_u=1, c_lhy=0.0)),
     "decoupled": ({"n": [16, 16, 16], "lo": [-6, -6, -6], "hi": [6, 6, 6]},
                   small_params(G=[[100.0, 0.0], [0.0, 90.0]], Gdd=[[0.0, 0.0], [0.0, 0.0]])),
+    # LHY quadrature nodes of all three kinds: both branches open, V_- clipped,
+    # and both clipped (eta_11, eta_22 < 0 with eta_11 eta_22 >= eta_12 eta_21 near u = 0)
+    "allclasses": ({"n": [16, 16, 32], "lo": [-6, -6, -6], "hi": [6, 6, 6]},
+                   small_params(G=[[10.0, 2.0], [2.0, 12.0]], Gdd=[[30.0, 5.0], [5.0, 30.0]])),
+    "nu5": ({"n": [16, 32, 16], "lo": [-6, -6, -6], "hi": [6, 6, 6]}, small_params(n_u=5)),
+    "nu24_mixedN": ({"n": [32, 16, 16], "lo": [-6, -6, -6], "hi": [6, 6, 6]},
+                    small_params(n_u=24, N=[1.0, 1.6], G=[[100.0, 50.0], [31.25, 90.0]],
+                                 Gdd=[[60.0, 45.0], [28.125, 50.0]])),
 }
 
 
@@ -188,7 +196,7 @@ def _tangent(grid, d, psi):
     return np.array([d[i] - dV * np.sum(np.real(np.conj(d[i]) * psi[i])) * psi[i] for i in range(2)])
 
 
-@pytest.mark.parametrize("case", ["C1b", "C2", "mixedN"])
+@pytest.mark.parametrize("case", ["C1b", "C2", "mixedN", "allclasses", "nu5"])
 @pytest.mark.parametrize("kind", ["random", "descent"])
 def test_linesearch_model_and_step(solver, orc, case, kind):
     """random: a rough direction (model parity, including E1 > 0 / E2 < 0 and
