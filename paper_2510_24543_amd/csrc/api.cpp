@@ -177,7 +177,7 @@ struct bec_ctx {
     double2 *psi[2] = {}, *hpsi[2] = {}, *aux[2] = {};
     double2 *pdir = nullptr, *r_old = nullptr, *z = nullptr, *rho = nullptr, *W = nullptr;
     double *udtab = nullptr, *kv[3] = {}, *vv[3] = {}, *nodes = nullptr;
-    double *partials = nullptr, *fft_partials = nullptr;
+    double *partials = nullptr, *fft_partials = nullptr, *ls_partials = nullptr;
     double* scal = nullptr;    // device address of `host` (reduced scalars)
     double2* tw[3] = {};
     double* host = nullptr;   // pinned scalars
@@ -256,6 +256,7 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
     const size_t c2 = sizeof(double2);
     const long long nb_pw = std::min<long long>((N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwMaxBlocks);
     const long long nb_x = bec::fft_max_blocks(n[0], (long long)n[1] * n[2]);
+    const long long nb_z = bec::fft_max_blocks(n[2], (long long)n[0] * n[1]);
     size_t sizes[] = {
         2 * N * c2, 2 * N * c2,                    // psi[0], psi[1]
         2 * N * c2, 2 * N * c2,                    // hpsi[0], hpsi[1]
@@ -273,6 +274,7 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
         (size_t)bec::kMaxSums * nb_pw * sizeof(double),                             // partials
         (size_t)3 * nb_x * sizeof(double),                                          // fft partials
         64 * sizeof(double),                                                        // reserved
+        (size_t)bec::kLsEpiSums * nb_z * sizeof(double),                            // line-search partials
     };
     size_t total = 0;
     for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); ++i) {
@@ -694,20 +696,28 @@ bec_status direction_and_model(bec_ctx* c, const bec::DirArgs& A, const Eval& ev
     const long long N = c->N;
     const double wb = 96.0 + (A.beta != 0.0 ? 32.0 : 0.0) + (A.zmode == 2 ? 32.0 : 0.0) + 80.0;
     LAUNCH(c, "dir_write", (double)c->N * wb, bec::launch_dir_write(c->P, A, c->nblk_pw, c->st));
+    // Parseval sums <p_i, T p_i> from the forward transforms of p; the packed
+    // rho_1 + i rho_2 through the dipolar kernel, its last inverse pass fused
+    // with the model epilogue (K*rho is never stored); one launch reduces the
+    // direction-write, Parseval and epilogue partials
     const double2* src[3] = {c->pdir, c->pdir + N, c->rho};
     double2* dst[3] = {c->W, c->W + N, c->W + 2 * N};
     const int ops[3] = {bec::kOpParseval, bec::kOpParseval, bec::kOpMulDip};
-    STCHK(kspace_apply(c, src, dst, 3, ops, nullptr));
-    bec::LsEpiArgs la{};
-    la.rho = c->rho;
-    la.phr = c->W + 2 * N;
-    // the epilogue's partials follow the direction-write rows, so one launch
-    // reduces both together with the two Parseval sums of the x pass
-    la.partials = c->partials + (long long)bec::kDirWriteSums * c->nblk_pw;
-    LAUNCH(c, "ls_epilogue", (double)N * 32.0, bec::launch_ls_epi(c->P, la, c->nblk_pw, c->st));
-    LAUNCH(c, "reduce_final", 8.0 * ((bec::kDirWriteSums + bec::kLsEpiSums) * c->nblk_pw + 2 * c->nblk_x),
-           bec::launch_reduce_final2(c->partials, c->nblk_pw, bec::kDirWriteSums + bec::kLsEpiSums, c->scal,
-                                     c->fft_partials, c->nblk_x, 2, c->scal + kParsevalOut, c->st));
+    STCHK(run_pass(c, 2, src, dst, 3, -1, 1.0, nullptr, nullptr));
+    STCHK(run_pass(c, 1, dst, dst, 3, -1, 1.0, nullptr, nullptr));
+    STCHK(run_pass(c, 0, dst, dst, 3, -1, 1.0, ops, nullptr));
+    STCHK(run_pass(c, 1, dst + 2, dst + 2, 1, +1, 1.0, nullptr, nullptr));
+    bec::FftPassArgs zA = pass_args(c, 2);
+    zA.nfield = 1;
+    zA.sign = +1;
+    zA.src[0] = zA.dst[0] = dst[2];
+    const int nblk_z = bec::fft_blocks(c->n[2], c->fft_var[2][0], zA.npencil);
+    LAUNCH(c, "fft_z_inv_ls", (double)N * 32.0,
+           bec::fft_zinv_ls_pass(c->n[2], c->fft_var[2][0], zA, c->rho, c->ls_partials, c->st));
+    LAUNCH(c, "reduce_final", 8.0 * (bec::kDirWriteSums * c->nblk_pw + 2 * c->nblk_x + bec::kLsEpiSums * nblk_z),
+           bec::launch_reduce_final3(c->partials, c->nblk_pw, bec::kDirWriteSums, c->scal, c->fft_partials,
+                                     c->nblk_x, 2, c->scal + kParsevalOut, c->ls_partials, nblk_z,
+                                     bec::kLsEpiSums, c->scal + bec::kDirWriteSums, c->st));
     STCHK(fetch(c, 32));
     const double* S = c->host;
     std::memcpy(m->D, S, sizeof(m->D));
@@ -859,6 +869,7 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
         c->nodes = (double*)at(21);
         c->partials = (double*)at(22);
         c->fft_partials = (double*)at(23);
+        c->ls_partials = (double*)at(25);
         c->nblk_pw = (int)std::min<long long>((c->N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwDefaultBlocks);
         c->nblk_x = bec::fft_blocks(c->n[0], c->fft_var[0][1], (long long)c->n[1] * c->n[2]);
         // reduced scalars: the final-reduction kernels write straight into pinned

@@ -99,6 +99,15 @@ struct TrialZArgs {
 };
 hipError_t fft_trial_z_pass(int L, int variant, const FftPassArgs& args, const TrialZArgs& z, hipStream_t s);
 
+// Last inverse pass (z) of the packed line-search density transform fused with
+// the model epilogue: transforms field 0 of args (args.src[0], in place), and
+// instead of storing K*rho accumulates the kLsEpiSums sums (0 rho1 rho1,
+// 1 rho1 rho2, 2 rho2 rho2, 3..6 rho_i (K*rho)_j for ij = 11, 12, 21, 22) into
+// partials[m * grid + block]; grid = fft_blocks(L, variant, args.npencil).
+// args is a z-axis pass (S = 1).
+hipError_t fft_zinv_ls_pass(int L, int variant, const FftPassArgs& args, const double2* rho, double* partials,
+                            hipStream_t s);
+
 // Launch one axis pass of length L over args.nfield fields with plan variant
 // `variant` (0 = default); `contiguous` for the z axis.
 hipError_t fft_pass(int L, int variant, bool contiguous, const FftPassArgs& args, hipStream_t s);
@@ -162,12 +171,7 @@ constexpr int kDirWriteSums = 18;
 //       8,9 U_MF,i |p_i|^2; 10,11 muL_i |p_i|^2; 12,13 muL_i n_i; 14 LHY V^1 sum; 15 LHY V^2 (n''=0) sum;
 //       16,17 Re<p_i, psi_i>
 
-struct LsEpiArgs {
-    const double2* rho;           // rho_1 + i rho_2
-    const double2* phr;           // Phi[rho_1] + i Phi[rho_2]
-    double* partials;
-};
-constexpr int kLsEpiSums = 7;
+constexpr int kLsEpiSums = 7;    // line-search model epilogue (rho_1 + i rho_2 against K*rho)
 // sums: 0 rho1 rho1; 1 rho1 rho2; 2 rho2 rho2; 3..6 rho_i Phi[rho_j] (11, 12, 21, 22)
 
 struct MakeRArgs {                // out = r or P_V^-1 r (for the kinetic preconditioners)
@@ -192,7 +196,6 @@ hipError_t launch_heval_epi(const PwParams& P, const HevalArgs& a, int nblk, hip
 hipError_t launch_ite_epi(const PwParams& P, const IteArgs& a, int nblk, hipStream_t s);
 hipError_t launch_dir_reduce(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s);
 hipError_t launch_dir_write(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s);
-hipError_t launch_ls_epi(const PwParams& P, const LsEpiArgs& a, int nblk, hipStream_t s);
 hipError_t launch_make_r(const PwParams& P, const MakeRArgs& a, hipStream_t s);
 hipError_t launch_param_grad(const PwParams& P, const ParamGradArgs& a, int nblk, hipStream_t s);
 hipError_t launch_norm2(const PwParams& P, const double2* f, double* partials, int nblk, hipStream_t s);
@@ -202,9 +205,13 @@ hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hps
                        double mu0, double mu1, double s0, double s1, int projected, hipStream_t s);
 // out[m] = sum_b partials[m * nblk + b] for m < M (fixed order), one block
 hipError_t launch_reduce_final(const double* partials, int nblk, int M, double* out, hipStream_t s);
-// two partial arrays in one launch (M1 rows of nblk1, then M2 rows of nblk2)
+// two or three partial arrays in one launch (M1 rows of nblk1, then M2 rows of
+// nblk2, then M3 rows of nblk3)
 hipError_t launch_reduce_final2(const double* partials1, int nblk1, int M1, double* out1, const double* partials2,
                                 int nblk2, int M2, double* out2, hipStream_t s);
+hipError_t launch_reduce_final3(const double* partials1, int nblk1, int M1, double* out1, const double* partials2,
+                                int nblk2, int M2, double* out2, const double* partials3, int nblk3, int M3,
+                                double* out3, hipStream_t s);
 
 // ---------------------------------------------------------------- batched scan
 // Instances with the same grid shape form a group; every batched kernel covers

@@ -428,6 +428,67 @@ __global__ __launch_bounds__(NTHR) void fft_trial_z_kernel(FftPassArgs A, TrialZ
     }
 }
 
+// Inverse z pass of the packed density rho_1 + i rho_2 of the line search with
+// the model epilogue: K*rho stays in registers; per block the sums
+// rho_i rho_j (11, 12, 22) and rho_i (K*rho)_j (11, 12, 21, 22).
+template <int L, int T, int R0, int R1, int R2, int NTHR>
+__global__ __launch_bounds__(NTHR) void fft_zinv_ls_kernel(FftPassArgs A, const double2* __restrict__ rho,
+                                                            double* __restrict__ partials)
+{
+    using PL = Plan<L, T, R0, R1, R2>;
+    constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>(), RL = PL::RL, M = kLsEpiSums;
+    __shared__ double2 lds[PB * RS];
+    const int tid = threadIdx.x;
+    const int pl = tid / T, t = tid % T;
+    const long long pg = (long long)blockIdx.x * PB + pl;
+    const bool valid = pg < A.npencil;
+    const long long base = valid ? pg * (long long)L : 0;
+    const double2* __restrict__ src = A.src[0];
+    double2* row = lds + pl * RS;
+    double2 v[E];
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r)
+            v[b * R0 + r] = valid ? src[base + t + b * T + r * (L / R0)] : make_double2(0.0, 0.0);
+    PL::template fwd_like<+1>(v, row, t, A.tw);
+    double acc[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = 0.0;
+    if (valid) {
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const double2 q = rho[base + t + b * T + r * (L / RL)], f = v[b * RL + r];
+                acc[0] += q.x * q.x;
+                acc[1] += q.x * q.y;
+                acc[2] += q.y * q.y;
+                acc[3] += q.x * f.x;
+                acc[4] += q.x * f.y;
+                acc[5] += q.y * f.x;
+                acc[6] += q.y * f.y;
+            }
+    }
+    // fixed-order block reduction of the M sums
+    double* sh = reinterpret_cast<double*>(lds);
+    const int lane = tid & 63, w = tid >> 6;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        double x = acc[m];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) sh[m * (NTHR / 64) + w] = x;
+    }
+    __syncthreads();
+    if (tid < M) {
+        double s = 0.0;
+        for (int k = 0; k < NTHR / 64; ++k) s += sh[tid * (NTHR / 64) + k];
+        partials[(long long)tid * gridDim.x + blockIdx.x] = s;
+    }
+}
+
 template <int L, int T, int R0, int R1, int R2, int NTHR>
 hipError_t launch_cfg(bool contiguous, const FftPassArgs& A, hipStream_t st)
 {
@@ -528,6 +589,21 @@ hipError_t fft_trial_z_pass(int L, int variant, const FftPassArgs& A, const Tria
     }
     BEC_FFT_VARIANTS(BEC_TCASE)
 #undef BEC_TCASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t fft_zinv_ls_pass(int L, int variant, const FftPassArgs& A, const double2* rho, double* partials,
+                            hipStream_t st)
+{
+    if (A.S != 1) return hipErrorInvalidValue;
+#define BEC_LCASE(LL, VV, T, R0, R1, R2, NT)                                                                 \
+    if (L == LL && variant == VV) {                                                                           \
+        const dim3 grid((unsigned)((A.npencil + NT / T - 1) / (NT / T)));                                     \
+        hipLaunchKernelGGL((fft_zinv_ls_kernel<LL, T, R0, R1, R2, NT>), grid, dim3(NT), 0, st, A, rho, partials); \
+        return hipGetLastError();                                                                             \
+    }
+    BEC_FFT_VARIANTS(BEC_LCASE)
+#undef BEC_LCASE
     return hipErrorInvalidValue;
 }
 

@@ -320,26 +320,6 @@ __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirAr
     block_reduce_store<kDirWriteSums>(acc, A.partials, gridDim.x);
 }
 
-__global__ __launch_bounds__(kPwThreads) void ls_epi_kernel(PwParams P, LsEpiArgs A)
-{
-    const long long N = P.N;
-    double acc[kLsEpiSums];
-#pragma unroll
-    for (int m = 0; m < kLsEpiSums; ++m) acc[m] = 0.0;
-    GRID_STRIDE(i, N)
-    {
-        const double2 r = A.rho[i], f = A.phr[i];
-        acc[0] += r.x * r.x;
-        acc[1] += r.x * r.y;
-        acc[2] += r.y * r.y;
-        acc[3] += r.x * f.x;
-        acc[4] += r.x * f.y;
-        acc[5] += r.y * f.x;
-        acc[6] += r.y * f.y;
-    }
-    block_reduce_store<kLsEpiSums>(acc, A.partials, gridDim.x);
-}
-
 __global__ __launch_bounds__(kPwThreads) void make_r_kernel(PwParams P, MakeRArgs A)
 {
     const long long N = P.N;
@@ -451,16 +431,30 @@ __global__ __launch_bounds__(kPwThreads) void grad_kernel(PwParams P, const doub
 
 // one workgroup per reduced scalar m: out[m] = sum_b partials[m * nblk + b]
 // One block per scalar: blocks [0, M1) reduce rows of partials1 (nblk1 per row)
-// into out1, blocks [M1, M1 + M2) rows of partials2 into out2.
-__global__ __launch_bounds__(256) void reduce_final_kernel(const double* partials1, int nblk1, int M1, double* out1,
-                                                           const double* partials2, int nblk2, double* out2)
+// into out1, the next M2 blocks rows of partials2 into out2, the rest rows of
+// partials3 into out3.
+struct RedSeg {
+    const double* partials;
+    int nblk, M;
+    double* out;
+};
+
+__global__ __launch_bounds__(256) void reduce_final_kernel(RedSeg s1, RedSeg s2, RedSeg s3)
 {
     __shared__ double sh[4];
-    const bool first = (int)blockIdx.x < M1;
-    const int m = first ? (int)blockIdx.x : (int)blockIdx.x - M1;
-    const double* partials = first ? partials1 : partials2;
-    const int nblk = first ? nblk1 : nblk2;
-    double* out = first ? out1 : out2;
+    int m = (int)blockIdx.x;
+    RedSeg g = s1;
+    if (m >= s1.M) {
+        m -= s1.M;
+        g = s2;
+        if (m >= s2.M) {
+            m -= s2.M;
+            g = s3;
+        }
+    }
+    const double* partials = g.partials;
+    const int nblk = g.nblk;
+    double* out = g.out;
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256) s += partials[(long long)m * nblk + b];
 #pragma unroll
@@ -498,12 +492,6 @@ hipError_t launch_dir_write(const PwParams& P, const DirArgs& a, int nblk, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_ls_epi(const PwParams& P, const LsEpiArgs& a, int nblk, hipStream_t s)
-{
-    hipLaunchKernelGGL(ls_epi_kernel, dim3(nblk), dim3(kPwThreads), 0, s, P, a);
-    return hipGetLastError();
-}
-
 hipError_t launch_make_r(const PwParams& P, const MakeRArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(make_r_kernel, dim3(pw_blocks(P)), dim3(kPwThreads), 0, s, P, a);
@@ -537,19 +525,24 @@ hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hps
     return hipGetLastError();
 }
 
+hipError_t launch_reduce_final3(const double* partials1, int nblk1, int M1, double* out1, const double* partials2,
+                                int nblk2, int M2, double* out2, const double* partials3, int nblk3, int M3,
+                                double* out3, hipStream_t s)
+{
+    const RedSeg a{partials1, nblk1, M1, out1}, b{partials2, nblk2, M2, out2}, c{partials3, nblk3, M3, out3};
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(M1 + M2 + M3), dim3(256), 0, s, a, b, c);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce_final(const double* partials, int nblk, int M, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(M), dim3(256), 0, s, partials, nblk, M, out,
-                       (const double*)nullptr, 0, (double*)nullptr);
-    return hipGetLastError();
+    return launch_reduce_final3(partials, nblk, M, out, nullptr, 0, 0, nullptr, nullptr, 0, 0, nullptr, s);
 }
 
 hipError_t launch_reduce_final2(const double* partials1, int nblk1, int M1, double* out1, const double* partials2,
                                 int nblk2, int M2, double* out2, hipStream_t s)
 {
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(M1 + M2), dim3(256), 0, s, partials1, nblk1, M1, out1, partials2,
-                       nblk2, out2);
-    return hipGetLastError();
+    return launch_reduce_final3(partials1, nblk1, M1, out1, partials2, nblk2, M2, out2, nullptr, 0, 0, nullptr, s);
 }
 
 }  // namespace bec
