@@ -96,6 +96,27 @@ def copy_probe(mib: int, reps: int = 5):
                       "ms": round(ms, 4), "GB_per_s": round(16 * n / (ms * 1e6), 1)}), flush=True)
 
 
+def kernel_short_name(full: str) -> str:
+    """'ns::(anonymous namespace)::name<args>(params)' -> 'name<args>'"""
+    end = len(full)
+    if full.endswith(")"):
+        depth = 0
+        for i in range(len(full) - 1, -1, -1):
+            depth += {")": 1, "(": -1}.get(full[i], 0)
+            if depth == 0:
+                end = i
+                break
+    head, depth, cut = full[:end], 0, 0
+    for i, ch in enumerate(head):            # last '::' outside <...> and (...)
+        if ch in "<(":
+            depth += 1
+        elif ch in ">)":
+            depth -= 1
+        elif ch == ":" and depth == 0 and head[i:i + 2] == "::":
+            cut = i + 2
+    return head[cut:]
+
+
 def _pmc_table(path: str, counter: str):
     """mean counter value per dispatch, by kernel name, from a rocprofv3
     counter_collection.csv"""
@@ -127,8 +148,7 @@ def pmc_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib):
     fetch, write = _pmc_table(fetch_csv, "FETCH_SIZE"), _pmc_table(write_csv, "WRITE_SIZE")
     kernels = {}
     for full in sorted(set(fetch) & set(write)):
-        base = full[:full.rfind("(")] if full.endswith(")") else full
-        short = base.split("::")[-1]
+        short = kernel_short_name(full)
         fb = fetch[full][0] * 1024.0 * f_fac
         wb = write[full][0] * 1024.0 * w_fac
         kernels[short] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
@@ -385,6 +405,10 @@ def main():
                        "bytes_per_launch": s["total_bytes"] / max(s["launches"], 1)} for s in stats),
                      key=lambda k: -k["share"])
     dom = kernels[0]
+    # the whole step: algorithmic bytes of all launches per step over the unprofiled step time
+    step_bytes = sum(s["total_bytes"] for s in stats) / max(prep["iters"], 1)
+    step_bw = {"bytes_per_step": step_bytes, "GB_per_s": round(step_bytes / (ms_per_step * 1e6), 1),
+               "frac_of_peak": round(step_bytes / (ms_per_step * 1e6) / HBM_PEAK_GBS, 4)}
     traffic = traffic_from_profiles(dom["name"])
     roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(dom["GB_per_s"], 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["GB_per_s"] / HBM_PEAK_GBS, 4),
@@ -415,6 +439,7 @@ def main():
         "pcg_vs_ite": ite_cmp,
         "batched_vs_plain": scan,
         "roofline": roofline,
+        "step_bandwidth": step_bw,
         "cpu_baseline": cpu,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in kk.items()} for kk in kernels],
     }
