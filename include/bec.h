@@ -240,6 +240,7 @@ bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_par
 
 bec_status bec_batch_destroy(bec_batch* b);
 
+
 /* Solve every instance.  psi_inout: host array of n_inst device pointers, each
  * an initial state of its instance's grid (normalised on entry) that receives
  * the final state.  rounds_per_sync: iteration rounds enqueued between two
@@ -265,6 +266,14 @@ typedef struct {
 
 bec_status bec_get_tuning(bec_ctx* ctx, bec_tuning* out_h);
 bec_status bec_set_tuning(bec_ctx* ctx, const bec_tuning* t);
+
+/* FFT plans for the instances of one grid shape (as chosen for that grid by
+ * bec_get_tuning after tuning a single-instance context): per axis the
+ * variant of bec_tuning.fft_variant (x: the k-space pass entry [0][1]; y, z:
+ * the plain entries); pw_blocks is not used.  Returns BEC_EINVAL if no
+ * instance has that grid or a variant does not exist.  Takes effect from the
+ * next bec_batch_solve (a captured graph is rebuilt). */
+bec_status bec_batch_set_tuning(bec_batch* b, const bec_grid* grid, const bec_tuning* t);
 
 /* Number of plan variants for an axis of length L (host-only). */
 bec_status bec_fft_variant_count(int32_t L, int32_t* count);

@@ -97,6 +97,7 @@ SIGNATURES = [
     ("bec_solve", C.c_int, [_VP, _VP, C.POINTER(Opts), C.POINTER(Report), C.POINTER(Iter), _I32]),
     ("bec_param_grad", C.c_int, [_VP, _VP, C.POINTER(_D22), C.POINTER(_D22), _DP]),
     ("bec_ite_solve", C.c_int, [_VP, _VP, C.POINTER(IteOpts), C.POINTER(Report), _DP, _I32]),
+    ("bec_batch_set_tuning", C.c_int, [_VP, C.POINTER(Grid), C.POINTER(Tuning)]),
     ("bec_batch_workspace_size", C.c_int, [_I32, C.POINTER(Grid), C.POINTER(Params), C.POINTER(C.c_size_t)]),
     ("bec_batch_create", C.c_int, [_I32, C.POINTER(Grid), C.POINTER(Params), _VP, _VP, C.c_size_t,
                                    C.POINTER(_VP)]),

@@ -1430,6 +1430,7 @@ struct BatchGroup {
     int n[3] = {0, 0, 0};
     long long N = 0;
     int first = 0, count = 0, nblk = 0, nblk_x = 0;
+    int var[3] = {0, 0, 0};        // FFT plan variant per axis (the x pass is always the k-space pass)
     double2 *psi = nullptr, *hpsi = nullptr, *aux = nullptr, *p = nullptr, *r_old = nullptr, *rho = nullptr,
             *W = nullptr;
     double *partials = nullptr, *fft_partials = nullptr, *udtab = nullptr, *kv[3] = {}, *vv[3] = {};
@@ -1545,7 +1546,7 @@ size_t batch_layout(int n_inst, const bec_grid* grids, std::vector<size_t>* off)
         const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
         const long long cnt = r.second;
         const int nblk = group_nblk(N);
-        const int nbx = bec::fft_blocks(g.n[0], 0, (long long)g.n[1] * g.n[2]);
+        const int nbx = bec::fft_max_blocks(g.n[0], (long long)g.n[1] * g.n[2]);   // any plan variant
         const size_t ud = (size_t)(g.n[0] / 2 + 1) * (g.n[1] / 2 + 1) * (g.n[2] / 2 + 1);
         size_t gs[] = {cnt * 4 * N * c2, cnt * 4 * N * c2, cnt * 4 * N * c2,  // psi, hpsi, aux (2 buffers)
                        cnt * 2 * N * c2, cnt * 2 * N * c2, cnt * N * c2,      // p, r_old, rho
@@ -1645,24 +1646,18 @@ bec_status bpass(bec_batch* b, const BatchGroup& G, FftPassArgs A, int axis, int
 {
     A.nfield = nf;
     A.sign = sign;
-    HIPCHK(bec::fft_pass(G.n[axis], 0, axis == 2, A, b->st));
+    HIPCHK(bec::fft_pass(G.n[axis], G.var[axis], axis == 2, A, b->st));
     return BEC_OK;
 }
 
-// Hamiltonian FFTs of the trial state of every active instance of the group
+// Trial points and Hamiltonian FFTs of every active instance of the group: the
+// trial update rides in the loads of the first (z) pass
 bec_status batch_heval_fft(bec_batch* b, const BatchGroup& G, hipStream_t s)
 {
     (void)s;
     const long long N = G.N;
     FftPassArgs A = batch_pass_args(G, 2, b->act_trial);
-    A.src[0] = G.psi;
-    A.src[1] = G.psi + N;
-    A.src[2] = G.W + 2 * N;
-    A.src_stride[0] = A.src_stride[1] = 4 * N;
-    A.src_sel = b->tsel + G.first;
-    A.src_sel_stride[0] = A.src_sel_stride[1] = 2 * N;
-    for (int f = 0; f < 3; ++f) A.dst[f] = G.W + f * N;
-    STCHK(bpass(b, G, A, 2, 3, -1));
+    HIPCHK(bec::fft_btrial_z_pass(G.n[2], G.var[2], A, G.g, b->st));
     A = batch_pass_args(G, 1, b->act_trial);
     for (int f = 0; f < 3; ++f) A.src[f] = A.dst[f] = G.W + f * N;
     STCHK(bpass(b, G, A, 1, 3, -1));
@@ -1718,7 +1713,6 @@ bec_status batch_trial_and_accept(bec_batch* b, const bec::BOpts& o)
 {
     for (auto& G : b->groups) {
         if (G.g.n_ids == 0) continue;
-        HIPCHK(bec::launch_b_trial(G.g, b->st));
         STCHK(batch_heval_fft(b, G, b->st));
         HIPCHK(bec::launch_b_heval_epi(G.g, b->st));
         STCHK(breduce(b, G, bec::kHevalSums, bec::kSH));
@@ -1929,6 +1923,28 @@ bec_status bec_batch_destroy(bec_batch* b)
     if (b->host_ptrs) (void)hipHostFree(b->host_ptrs);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
+    return BEC_OK;
+}
+
+bec_status bec_batch_set_tuning(bec_batch* b, const bec_grid* grid, const bec_tuning* t)
+{
+    if (!b || !grid || !t) return fail(BEC_EINVAL, "null argument");
+    const int v[3] = {t->fft_variant[0][1], t->fft_variant[1][0], t->fft_variant[2][0]};
+    int matched = 0;
+    for (auto& G : b->groups) {
+        if (G.n[0] != grid->n[0] || G.n[1] != grid->n[1] || G.n[2] != grid->n[2]) continue;
+        for (int d = 0; d < 3; ++d)
+            if (v[d] < 0 || v[d] >= bec::fft_num_variants(G.n[d]))
+                return fail(BEC_EINVAL, "axis %d: plan variant %d of length %d does not exist", d, v[d], G.n[d]);
+        for (int d = 0; d < 3; ++d) G.var[d] = v[d];
+        G.nblk_x = bec::fft_blocks(G.n[0], G.var[0], (long long)G.n[1] * G.n[2]);
+        ++matched;
+    }
+    if (!matched) return fail(BEC_EINVAL, "no instance has the grid %dx%dx%d", grid->n[0], grid->n[1], grid->n[2]);
+    if (b->exec) {   // a captured round holds the old plans
+        HIPCHK(hipGraphExecDestroy(b->exec));
+        b->exec = nullptr;
+    }
     return BEC_OK;
 }
 

@@ -74,35 +74,6 @@ __global__ __launch_bounds__(kPwThreads) void b_norm2_kernel(BGroup g)
     bblock_store<2>(acc, g.partials + (long long)l * kMaxSums * g.nblk, g.nblk);
 }
 
-__global__ __launch_bounds__(kPwThreads) void b_trial_kernel(BGroup g)
-{
-    const int l = g.ids[blockIdx.y], inst = g.first + l;
-    if (!g.act_trial[inst]) return;
-    const BInstState& S = g.st[inst];
-    const long long N = g.N;
-    const int cur = S.cur;
-    const bool init = S.phase == kBInit;
-    const double2* src = init ? reinterpret_cast<const double2*>(g.psi_user[inst]) : g.psi + ((long long)l * 2 + cur) * 2 * N;
-    const double2* p = init ? nullptr : g.p + (long long)l * 2 * N;
-    double2* dst = g.psi + ((long long)l * 2 + (1 - cur)) * 2 * N;
-    double2* dens = g.W + (long long)l * 3 * N + 2 * N;
-    const double a0 = S.a[0], a1 = S.a[1], b0 = S.b[0], b1 = S.b[1];
-    BSTRIDE(i, N)
-    {
-        const double2 s1 = src[i], s2 = src[N + i];
-        double2 o1 = make_double2(a0 * s1.x, a0 * s1.y);
-        double2 o2 = make_double2(a1 * s2.x, a1 * s2.y);
-        if (p) {
-            const double2 p1 = p[i], p2 = p[N + i];
-            o1.x += b0 * p1.x; o1.y += b0 * p1.y;
-            o2.x += b1 * p2.x; o2.y += b1 * p2.y;
-        }
-        dst[i] = o1;
-        dst[N + i] = o2;
-        dens[i] = make_double2(sq2(o1), sq2(o2));
-    }
-}
-
 __global__ __launch_bounds__(kPwThreads) void b_heval_epi_kernel(BGroup g)
 {
     const int l = g.ids[blockIdx.y], inst = g.first + l;
@@ -591,11 +562,6 @@ dim3 dgrid(int n) { return dim3((unsigned)((n + 63) / 64)); }
 hipError_t launch_b_norm2(const BGroup& g, hipStream_t s)
 {
     hipLaunchKernelGGL(b_norm2_kernel, bgrid(g), dim3(kPwThreads), 0, s, g);
-    return hipGetLastError();
-}
-hipError_t launch_b_trial(const BGroup& g, hipStream_t s)
-{
-    hipLaunchKernelGGL(b_trial_kernel, bgrid(g), dim3(kPwThreads), 0, s, g);
     return hipGetLastError();
 }
 hipError_t launch_b_heval_epi(const BGroup& g, hipStream_t s)

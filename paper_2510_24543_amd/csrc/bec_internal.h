@@ -278,8 +278,11 @@ struct BGroup {
     double* partials;             // [count][kMaxSums][nblk]
 };
 
+// Batched form of fft_trial_z_pass over the running instances of a group
+// (args: a z-axis pass of the group's grid; grid.z = g.n_ids).
+hipError_t fft_btrial_z_pass(int L, int variant, const FftPassArgs& args, const BGroup& g, hipStream_t s);
+
 hipError_t launch_b_norm2(const BGroup& g, hipStream_t s);
-hipError_t launch_b_trial(const BGroup& g, hipStream_t s);
 hipError_t launch_b_heval_epi(const BGroup& g, hipStream_t s);
 hipError_t launch_b_dir_reduce(const BGroup& g, hipStream_t s);
 hipError_t launch_b_dir_write(const BGroup& g, hipStream_t s);

@@ -355,11 +355,12 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
 // all loads of both components are issued first, then the two components are
 // transformed one after the other, then the packed density kept from them.
 template <int L, int T, int R0, int R1, int R2, int NTHR>
-__global__ __launch_bounds__(NTHR) void fft_trial_z_kernel(FftPassArgs A, TrialZArgs Z)
+__device__ __forceinline__ void trial_z_body(const FftPassArgs& A, const TrialZArgs& Z, double2* d0, double2* d1,
+                                             double2* d2, double2* lds)
 {
     using PL = Plan<L, T, R0, R1, R2>;
-    constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>(), RL = PL::RL;
-    __shared__ double2 lds[PB * RS];
+    constexpr int E = L / T, RS = lds_row<L>(), RL = PL::RL;
+    constexpr int PB = NTHR / T;
     const int tid = threadIdx.x;
     const int pl = tid / T, t = tid % T;
     const long long pg = (long long)blockIdx.x * PB + pl;
@@ -407,7 +408,7 @@ __global__ __launch_bounds__(NTHR) void fft_trial_z_kernel(FftPassArgs A, TrialZ
 #pragma unroll
         for (int b = 0; b < E / RL; ++b)
 #pragma unroll
-            for (int r = 0; r < RL; ++r) A.dst[0][base + t + b * T + r * (L / RL)] = w0[b * RL + r];
+            for (int r = 0; r < RL; ++r) d0[base + t + b * T + r * (L / RL)] = w0[b * RL + r];
     }
     // w0 is free now: it takes the packed density of the loaded points
 #pragma unroll
@@ -417,20 +418,54 @@ __global__ __launch_bounds__(NTHR) void fft_trial_z_kernel(FftPassArgs A, TrialZ
 #pragma unroll
         for (int b = 0; b < E / RL; ++b)
 #pragma unroll
-            for (int r = 0; r < RL; ++r) A.dst[1][base + t + b * T + r * (L / RL)] = w1[b * RL + r];
+            for (int r = 0; r < RL; ++r) d1[base + t + b * T + r * (L / RL)] = w1[b * RL + r];
     }
     PL::template fwd_like<-1>(w0, row, t, A.tw);
     if (valid) {
 #pragma unroll
         for (int b = 0; b < E / RL; ++b)
 #pragma unroll
-            for (int r = 0; r < RL; ++r) A.dst[2][base + t + b * T + r * (L / RL)] = w0[b * RL + r];
+            for (int r = 0; r < RL; ++r) d2[base + t + b * T + r * (L / RL)] = w0[b * RL + r];
     }
 }
 
 // Inverse z pass of the packed density rho_1 + i rho_2 of the line search with
 // the model epilogue: K*rho stays in registers; per block the sums
 // rho_i rho_j (11, 12, 22) and rho_i (K*rho)_j (11, 12, 21, 22).
+
+template <int L, int T, int R0, int R1, int R2, int NTHR>
+__global__ __launch_bounds__(NTHR) void fft_trial_z_kernel(FftPassArgs A, TrialZArgs Z)
+{
+    __shared__ double2 lds[(NTHR / T) * lds_row<L>()];
+    trial_z_body<L, T, R0, R1, R2, NTHR>(A, Z, A.dst[0], A.dst[1], A.dst[2], lds);
+}
+
+// The same for every running instance of a batch group (grid.z = instance):
+// the trial point of instance l from its current state and search direction
+// (or the caller's field on its first evaluation), transformed into its slice
+// of the group's work fields.
+template <int L, int T, int R0, int R1, int R2, int NTHR>
+__global__ __launch_bounds__(NTHR) void fft_btrial_z_kernel(FftPassArgs A, BGroup g)
+{
+    __shared__ double2 lds[(NTHR / T) * lds_row<L>()];
+    const int l = g.ids[blockIdx.z], inst = g.first + l;
+    if (!g.act_trial[inst]) return;                 // uniform per block
+    const BInstState& S = g.st[inst];
+    const long long N = g.N;
+    const bool init = S.phase == kBInit;
+    TrialZArgs Z;
+    Z.psi_src = init ? reinterpret_cast<const double2*>(g.psi_user[inst]) : g.psi + ((long long)l * 2 + S.cur) * 2 * N;
+    Z.p = init ? nullptr : g.p + (long long)l * 2 * N;
+    Z.a[0] = S.a[0];
+    Z.a[1] = S.a[1];
+    Z.b[0] = S.b[0];
+    Z.b[1] = S.b[1];
+    Z.psi_dst = g.psi + ((long long)l * 2 + (1 - S.cur)) * 2 * N;
+    Z.N = N;
+    double2* w = g.W + (long long)l * 3 * N;
+    trial_z_body<L, T, R0, R1, R2, NTHR>(A, Z, w, w + N, w + 2 * N, lds);
+}
+
 template <int L, int T, int R0, int R1, int R2, int NTHR>
 __global__ __launch_bounds__(NTHR) void fft_zinv_ls_kernel(FftPassArgs A, const double2* __restrict__ rho,
                                                             double* __restrict__ partials)
@@ -589,6 +624,20 @@ hipError_t fft_trial_z_pass(int L, int variant, const FftPassArgs& A, const Tria
     }
     BEC_FFT_VARIANTS(BEC_TCASE)
 #undef BEC_TCASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t fft_btrial_z_pass(int L, int variant, const FftPassArgs& A, const BGroup& g, hipStream_t st)
+{
+    if (A.S != 1) return hipErrorInvalidValue;
+#define BEC_BCASE(LL, VV, T, R0, R1, R2, NT)                                                             \
+    if (L == LL && variant == VV) {                                                                       \
+        const dim3 grid((unsigned)((A.npencil + NT / T - 1) / (NT / T)), 1u, (unsigned)g.n_ids);          \
+        hipLaunchKernelGGL((fft_btrial_z_kernel<LL, T, R0, R1, R2, NT>), grid, dim3(NT), 0, st, A, g);    \
+        return hipGetLastError();                                                                         \
+    }
+    BEC_FFT_VARIANTS(BEC_BCASE)
+#undef BEC_BCASE
     return hipErrorInvalidValue;
 }
 

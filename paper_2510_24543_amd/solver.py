@@ -241,6 +241,16 @@ class Batch:
         except Exception:
             pass
 
+    def set_tuning(self, grid: dict, tuning: dict):
+        """FFT plans (a Context.get_tuning() dict) for the instances on `grid`."""
+        t = B.Tuning()
+        for a in range(3):
+            for k in range(2):
+                t.fft_variant[a][k] = int(tuning["fft_variant"][a][k])
+        t.pw_blocks = int(tuning.get("pw_blocks", 0))
+        B.check(B.lib().bec_batch_set_tuning(self._b, C.byref(B.make_grid(grid)), C.byref(t)),
+                "bec_batch_set_tuning")
+
     def solve(self, psi0: list, opts: dict | None = None, rounds_per_sync: int = 16, use_graph: bool = True):
         """Returns (list of final states, list of reports)."""
         if len(psi0) != self.n:

@@ -95,3 +95,28 @@ def test_batch_rejects_kinetic_preconditioner(solver):
     b = solver.Batch([grid], [params])
     with pytest.raises(solver.B.BecError, match="EUNSUPPORTED"):
         b.solve([psi0], dict(OPTS, pc=2))
+
+
+def test_batch_with_other_fft_plans_matches_default_plans(solver):
+    """Per-grid FFT plan variants (bec_batch_set_tuning) change only the
+    rounding: the same iterates to 1e-12 in E after a fixed number of rounds."""
+    scan = small_scan(6)
+    opts = dict(OPTS, max_iter=40, tol_grad=0.0)
+    grids, params = [s[0] for s in scan], [s[1] for s in scan]
+    b0 = solver.Batch(grids, params)
+    _, r0 = b0.solve([s[2] for s in scan], opts, rounds_per_sync=8, use_graph=True)
+    b1 = solver.Batch(grids, params)
+    from paper_2510_24543_amd import autotune
+    for g in ({"n": [16, 16, 16]}, {"n": [32, 32, 32]}, {"n": [16, 32, 32]}):
+        g = dict(g, lo=[-6.0] * 3, hi=[6.0] * 3)
+        last = [[autotune.variant_count(g["n"][a]) - 1] * 2 for a in range(3)]
+        b1.set_tuning(g, {"fft_variant": last, "pw_blocks": 0})
+    _, r1 = b1.solve([s[2] for s in scan], opts, rounds_per_sync=8, use_graph=True)
+    for a, c in zip(r0, r1):
+        assert a["iters"] == c["iters"] == 40
+        assert abs(a["final"]["E"] - c["final"]["E"]) <= 1e-12 * abs(a["final"]["E"])
+    with pytest.raises(Exception):
+        b1.set_tuning({"n": [48, 48, 48], "lo": [-6.0] * 3, "hi": [6.0] * 3},
+                      {"fft_variant": [[0, 0]] * 3, "pw_blocks": 0})
+    with pytest.raises(Exception):
+        b1.set_tuning(grids[0], {"fft_variant": [[0, 99], [0, 0], [0, 0]], "pw_blocks": 0})
