@@ -249,6 +249,36 @@ def ite_workload(name: str, dt: float):
     return out
 
 
+def precond_study(name: str, tol: float = 1e-8, max_iter: int = 20000):
+    """The paper's first comparison (Sec. VI.B): the four preconditioners with
+    both conjugacy rules, each from the same seeded start to max_i ||r_i|| < tol;
+    HIP-event times."""
+    import torch
+    from paper_2510_24543_amd import inputs, solver, autotune
+    cfg = inputs.CONFIGS[name]
+    ctx = solver.Context(cfg["grid"], cfg["params"])
+    cached = autotune.load_cached(cfg["grid"])
+    if cached:
+        ctx.set_tuning(cached)
+    psi0 = torch.from_numpy(inputs.config_state(name)).cuda()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows = []
+    for pc, pname in ((0, "none"), (1, "P_V"), (2, "P_Delta"), (3, "P_Delta P_V")):
+        for beta, bname in ((0, "HS+"), (1, "PR+")):
+            opts = {"pc": pc, "beta": beta, "restart_period": 50, "sigma": 1e-6, "tol_grad": tol, "max_iter": max_iter}
+            torch.cuda.synchronize()
+            ev0.record(ctx.stream)
+            _, rep, _ = ctx.solve(psi0, opts)
+            ev1.record(ctx.stream)
+            torch.cuda.synchronize()
+            rows.append({"precond": pname, "beta": bname, "iters": rep["iters"], "status": rep["status"],
+                         "seconds": round(ev0.elapsed_time(ev1) / 1000.0, 4), "E": rep["final"]["E"],
+                         "res_max": max(rep["final"]["res"]), "restarts": rep["n_restarts"],
+                         "backtracks": rep["n_backtracks"]})
+            print(f"{name}: {pname} {bname} {rep['iters']} iterations {rep['status']}", file=sys.stderr, flush=True)
+    return {"workload": name, "grid": cfg["grid"]["n"], "tol_grad": tol, "runs": rows}
+
+
 def scan_comparison(n_inst: int, use_graph: bool = True):
     """Parameter scan of n_inst instances (grids cycling 48^3, 64^3, 96^3; seeded
     g12, gdd, LHY): one batched solve against the same instances solved one after
@@ -327,6 +357,8 @@ def main():
     ap.add_argument("--scan", type=int, default=96, help="instances of the batched-vs-plain scan (0: skip)")
     ap.add_argument("--ite-dt", type=float, default=0.01,
                     help="imaginary-time step of the PCG-vs-ITE comparison (0: skip it)")
+    ap.add_argument("--precond-study", default=None, metavar="WORKLOAD",
+                    help="only run the preconditioner x conjugacy-rule study on this workload and print it")
     ap.add_argument("--ite-only", default=None, metavar="WORKLOAD",
                     help="only run the PCG-vs-ITE comparison on this workload (e.g. C2, C3, C5) and print it")
     ap.add_argument("--tuning", choices=("auto", "cache", "default"), default="auto",
@@ -352,6 +384,9 @@ def main():
     import torch
     from paper_2510_24543_amd import inputs, solver
 
+    if args.precond_study:
+        print(json.dumps(precond_study(args.precond_study)), flush=True)
+        return
     if args.ite_only:
         print(json.dumps(ite_workload(args.ite_only, args.ite_dt)), flush=True)
         return

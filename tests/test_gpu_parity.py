@@ -322,6 +322,33 @@ def test_headline_grid_first_iterations(solver, orc):
         assert np.max(np.abs(g[i][idx] - psio[i][idx])) <= 1e-10 * np.max(np.abs(psio[i]))
 
 
+@pytest.mark.timeout(900)
+def test_largest_grid_energy_hamiltonian_and_first_step(solver, orc):
+    """256 x 256 x 128 (the largest workload): energy terms, H psi at 4096
+    sampled points, and the first accepted step against the oracle."""
+    c = inputs.CONFIGS["C5"]
+    grid, params = c["grid"], c["params"]
+    psi0 = inputs.config_state("C5")
+    ctx = solver.Context(grid, params)
+    t = ctx.energy(torch.from_numpy(psi0))
+    h, _ = ctx.hamiltonian(torch.from_numpy(psi0))
+    to, ho, _, _ = orc.heval(grid, params, psi0)
+    for k in ("E", "E_lhy"):
+        assert abs(t[k] - to[k]) <= 1e-12 * abs(to[k]), k
+    for i in range(2):
+        assert abs(t["mu"][i] - to["mu"][i]) <= 1e-12 * abs(to["mu"][i])
+    rng = np.random.default_rng(11)
+    idx = tuple(rng.integers(0, n, 4096) for n in grid["n"])
+    hg = h.cpu().numpy()
+    for i in range(2):
+        assert np.max(np.abs(hg[i][idx] - ho[i][idx])) <= 1e-11 * np.max(np.abs(ho[i]))
+    opts = {"tol_grad": 0.0, "max_iter": 1}
+    _, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=1)
+    _, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=1)
+    assert abs(log[0]["E"] - logo[0]["E"]) <= 1e-11 * abs(logo[0]["E"])
+    assert abs(log[0]["alpha"] - logo[0]["alpha"]) <= 1e-8 * abs(logo[0]["alpha"])
+
+
 # ---------------------------------------------------------------- errors and edge cases
 def test_errors_are_reported(solver):
     B = solver.B
