@@ -439,6 +439,18 @@ def main():
                "E_star": trep["final"]["E"], "res_max": max(trep["final"]["res"]),
                "backtracks": trep["n_backtracks"], "restarts": trep["n_restarts"]}
 
+    # the same with the composite preconditioner P_Delta^-1 P_V^-1 (fewest iterations on this grid)
+    tts_comp = None
+    if not args.no_tts:
+        torch.cuda.synchronize()
+        ev0.record(ctx.stream)
+        _, crep, _ = ctx.solve(psi0, dict(base_opts, pc=3, max_iter=5000, tol_grad=1e-8))
+        ev1.record(ctx.stream)
+        torch.cuda.synchronize()
+        tts_comp = {"precond": "P_Delta^-1 P_V^-1", "seconds": ev0.elapsed_time(ev1) / 1000.0,
+                    "iters": crep["iters"], "status": crep["status"], "E_star": crep["final"]["E"],
+                    "res_max": max(crep["final"]["res"])}
+
     # per-kernel timings: HIP events around every launch on the library stream,
     # over a second run of the same K steps
     ctx.profile(True)
@@ -488,6 +500,7 @@ def main():
                                "P_V + HS+ (restart 50), FP64",
                    "grid": grid["n"], "points": ctx.N, "components": 2},
         "time_to_solution": tts,
+        "time_to_solution_composite_precond": tts_comp,
         "tuning": tuning,
         "pcg_vs_ite": ite_cmp,
         "batched_vs_plain": scan,
