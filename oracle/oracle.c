@@ -598,7 +598,32 @@ static void precond_K(const geom *g, const hstate *s, double sigma, const cplx *
     }
 }
 
-/* z = P^-1 r for mode 0 (identity), 1 (P_V), 2 (P_Delta), 3 (P_Delta P_V) */
+/* Symmetrised composite (an extension beyond Sec. IV.B, where the composite of
+ * Eq. (18) is P_Delta^-1 P_V^-1, which is not symmetric): with D the P_V
+ * diagonal, z = D^(-1/2) P_Delta^-1 D^(-1/2) r, symmetric and positive
+ * definite because both factors are. */
+static void precond_S(const geom *g, const orc_params *P, const hstate *s, double sigma,
+                      const cplx *r, cplx *z)
+{
+    long N = g->N;
+    double *dh = (double *)malloc(sizeof(double) * 2 * (size_t)N);   /* D^(-1/2) */
+    for (int i = 0; i < 2; ++i) {
+        #pragma omp parallel for schedule(static)
+        for (long x = 0; x < N; ++x) {
+            double diag = s->t.shift[i] + g->V[x] + s->muL[i * N + x];
+            for (int j = 0; j < 2; ++j) diag += P->G[i][j] * s->n[j * N + x];
+            if (diag < 0.0) diag = 0.0;
+            dh[i * N + x] = 1.0 / sqrt(diag + sigma);
+        }
+    }
+    for (long x = 0; x < 2 * N; ++x) z[x] = dh[x] * r[x];
+    precond_K(g, s, sigma, z, z);
+    for (long x = 0; x < 2 * N; ++x) z[x] *= dh[x];
+    free(dh);
+}
+
+/* z = P^-1 r for mode 0 (identity), 1 (P_V), 2 (P_Delta), 3 (P_Delta P_V),
+ * 4 (symmetrised composite) */
 static void precond_apply(const geom *g, const orc_params *P, const hstate *s, int mode,
                           double sigma, const cplx *r, cplx *z)
 {
@@ -607,6 +632,7 @@ static void precond_apply(const geom *g, const orc_params *P, const hstate *s, i
     case 1: precond_V(g, P, s, sigma, r, z); break;
     case 2: precond_K(g, s, sigma, r, z); break;
     case 3: precond_V(g, P, s, sigma, r, z); precond_K(g, s, sigma, z, z); break;
+    case 4: precond_S(g, P, s, sigma, r, z); break;
     default: memcpy(z, r, sizeof(cplx) * 2 * (size_t)N); break;
     }
 }
@@ -980,7 +1006,7 @@ int orc_solve(const orc_grid *gr, const orc_params *P, const orc_opts *o, double
                 }
                 if (rp < 0.0 && isfinite(rp)) break;
                 if (level == 0) { level = 1; rep->n_restarts++; continue; }
-                if (level == 1 && o->pc == 3) { level = 2; path |= 4; continue; }
+                if (level == 1 && o->pc >= 3) { level = 2; path |= 4; continue; }
                 if (level == 2) { level = 3; continue; }
                 stagnated = 1;
                 break;

@@ -455,6 +455,55 @@ def test_potential_preconditioner_diagonal(orc):
     assert np.array_equal(orc.precond(grid, P, 0, sigma, psi, r), r)
 
 
+def test_symmetrised_composite_is_symmetric_positive_and_factorises(orc):
+    """z = D^-1/2 P_Delta^-1 D^-1/2 r with D the P_V diagonal: symmetric and
+    positive in the real inner product (unlike the composite of Eq. (18)), and
+    equal to D^-1/2 applied around the kinetic preconditioner."""
+    grid = make_grid((12, 12, 16), (-6, -6, -6), (6, 6, 6))
+    psi = smooth_state(grid, 4)
+    om = (1.0, 1.3, 2.0)
+    G = ((10.0, 4.0), (4.0, 8.0))
+    P = params(omega=om, G=G, Gdd=((5.0, 2.0), (2.0, 3.0)))
+    t = orc.heval(grid, P, psi)[0]
+    sigma = 1e-6
+    u, v = smooth_direction(grid, 21), smooth_direction(grid, 22)
+
+    def ip(a, b):
+        return float(np.sum((np.conj(a) * b).real))
+
+    Pu, Pv = orc.precond(grid, P, 4, sigma, psi, u), orc.precond(grid, P, 4, sigma, psi, v)
+    assert abs(ip(u, Pv) - ip(Pu, v)) < 1e-13 * abs(ip(u, Pv))
+    assert ip(u, Pu) > 0 and ip(v, Pv) > 0
+    Cu, Cv = orc.precond(grid, P, 3, sigma, psi, u), orc.precond(grid, P, 3, sigma, psi, v)
+    assert abs(ip(u, Cv) - ip(Cu, v)) > 1e-6 * abs(ip(u, Cv))      # Eq. (18) is not symmetric
+    X, Y, Z = mesh(grid)
+    V = 0.5 * (om[0] ** 2 * X ** 2 + om[1] ** 2 * Y ** 2 + om[2] ** 2 * Z ** 2)
+    n = np.abs(psi) ** 2
+    dh = np.array([1.0 / np.sqrt(np.maximum(t["shift"][i] + V + G[i][0] * n[0] + G[i][1] * n[1], 0.0) + sigma)
+                   for i in range(2)])
+    ref = dh * orc.precond(grid, P, 2, sigma, psi, dh * u)
+    assert np.max(np.abs(Pu - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_symmetrised_composite_with_constant_diagonal_on_plane_waves(orc):
+    """No trap, no interactions: D = alpha_i + sigma everywhere, so a plane wave
+    is scaled by 1/((alpha_i + sigma)(alpha_i + sigma + |k|^2/2))."""
+    grid = make_grid((8, 12, 16), (-3, -4, -5), (3, 4, 5))
+    X, Y, Z = mesh(grid)
+    L = [6.0, 8.0, 10.0]
+    psi = smooth_state(grid, 3, phase=False)
+    P = params()
+    t = orc.heval(grid, P, psi)[0]
+    sigma = 1e-3
+    m = [(1, -2, 3), (0, 4, -1)]
+    r = np.array([np.exp(1j * sum(2 * np.pi * mm[d] / L[d] * c for d, c in enumerate((X, Y, Z)))) for mm in m])
+    z = orc.precond(grid, P, 4, sigma, psi, r)
+    for i in range(2):
+        a = t["shift"][i] + sigma
+        k2h = 0.5 * sum((2 * np.pi * m[i][d] / L[d]) ** 2 for d in range(3))
+        assert np.max(np.abs(z[i] - r[i] / (a * (a + k2h)))) < 1e-13 / (a * a)
+
+
 # ---------------------------------------------------------------- P10: manifold
 def test_geodesic_stays_on_the_product_of_spheres(orc):
     psi = smooth_state(SMALL, 13)
@@ -496,7 +545,7 @@ def test_solver_restart_period_one_is_steepest_descent(orc):
 
 def test_all_preconditioners_reach_the_same_ground_state(orc):
     Es = []
-    for pc in (0, 1, 2, 3):
+    for pc in (0, 1, 2, 3, 4):
         _, rep, _ = solve_c1(orc, "C1b", pc=pc)
         assert rep["status"] == "OK"
         Es.append(rep["final"]["E"])
