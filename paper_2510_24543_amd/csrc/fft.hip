@@ -564,13 +564,14 @@ struct Variant {
     X(32, 3, 8, 4, 4, 2, 256)                                                                        \
     X(48, 0, 4, 12, 4, 1, 256) X(48, 1, 4, 4, 12, 1, 256) X(48, 2, 4, 12, 4, 1, 128)                 \
     X(64, 0, 8, 8, 8, 1, 256) X(64, 1, 4, 16, 4, 1, 256) X(64, 2, 8, 8, 8, 1, 128)                   \
-    X(64, 3, 8, 8, 8, 1, 512) X(64, 4, 16, 4, 4, 4, 256)                                             \
+    X(64, 3, 8, 8, 8, 1, 512) X(64, 4, 16, 4, 4, 4, 256) X(64, 5, 16, 4, 4, 4, 128)                  \
     X(96, 0, 4, 12, 8, 1, 128) X(96, 1, 4, 12, 8, 1, 256) X(96, 2, 8, 6, 4, 4, 256)                  \
     X(96, 3, 8, 12, 4, 2, 256)                                                                       \
     X(128, 0, 8, 16, 8, 1, 256) X(128, 1, 8, 8, 16, 1, 256) X(128, 2, 8, 16, 8, 1, 128)              \
-    X(128, 3, 8, 16, 8, 1, 512) X(128, 4, 16, 8, 4, 4, 256)                                          \
+    X(128, 3, 8, 16, 8, 1, 512) X(128, 4, 16, 8, 4, 4, 256) X(128, 5, 16, 8, 4, 4, 512)              \
+    X(128, 6, 16, 8, 4, 4, 128) X(128, 7, 16, 4, 4, 8, 256)                                          \
     X(256, 0, 16, 16, 16, 1, 256) X(256, 1, 16, 16, 16, 1, 128) X(256, 2, 16, 16, 16, 1, 512)        \
-    X(256, 3, 32, 8, 8, 4, 256)
+    X(256, 3, 32, 8, 8, 4, 256) X(256, 4, 16, 16, 4, 4, 256) X(256, 5, 32, 8, 8, 4, 512)
 
 static bool find_variant(int L, int v, Variant* out)
 {
