@@ -263,7 +263,7 @@ def precond_study(name: str, tol: float = 1e-8, max_iter: int = 20000):
     psi0 = torch.from_numpy(inputs.config_state(name)).cuda()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     rows = []
-    for pc, pname in ((0, "none"), (1, "P_V"), (2, "P_Delta"), (3, "P_Delta P_V")):
+    for pc, pname in ((0, "none"), (1, "P_V"), (2, "P_Delta"), (3, "P_Delta P_V"), (4, "symmetrised")):
         for beta, bname in ((0, "HS+"), (1, "PR+")):
             opts = {"pc": pc, "beta": beta, "restart_period": 50, "sigma": 1e-6, "tol_grad": tol, "max_iter": max_iter}
             torch.cuda.synchronize()

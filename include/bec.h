@@ -76,8 +76,10 @@ typedef struct {
 } bec_params;
 
 /* Preconditioners of Sec. IV.B: identity, real-space diagonal P_V, kinetic
- * P_Delta (Fourier diagonal), and the composite P_Delta^-1 P_V^-1 (Eq. (18)). */
-typedef enum { BEC_PC_NONE = 0, BEC_PC_V = 1, BEC_PC_KIN = 2, BEC_PC_COMPOSITE = 3 } bec_precond;
+ * P_Delta (Fourier diagonal), and the composite P_Delta^-1 P_V^-1 (Eq. (18));
+ * and, beyond the paper, the symmetrised composite D^-1/2 P_Delta^-1 D^-1/2
+ * with D the P_V diagonal (symmetric and positive definite, unlike Eq. (18)). */
+typedef enum { BEC_PC_NONE = 0, BEC_PC_V = 1, BEC_PC_KIN = 2, BEC_PC_COMPOSITE = 3, BEC_PC_SYMMETRIC = 4 } bec_precond;
 
 /* Conjugacy parameter of Sec. IV.C: Hestenes-Stiefel+, Polak-Ribiere+, or 0. */
 typedef enum { BEC_BETA_HS_PLUS = 0, BEC_BETA_PR_PLUS = 1, BEC_BETA_ZERO = 2 } bec_beta;

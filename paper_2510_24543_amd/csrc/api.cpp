@@ -1083,7 +1083,7 @@ bec_status bec_gradient(bec_ctx* c, const double* psi, double* grad, int32_t pro
 bec_status bec_precond_apply(bec_ctx* c, int32_t pc, double sigma, const double* psi, const double* r, double* z)
 {
     if (!c || !psi || !r || !z) return fail(BEC_EINVAL, "null argument");
-    if (pc < 0 || pc > 3) return fail(BEC_EINVAL, "unknown preconditioner %d", pc);
+    if (pc < 0 || pc > 4) return fail(BEC_EINVAL, "unknown preconditioner %d", pc);
     if (!(sigma >= 0)) return fail(BEC_EINVAL, "sigma must be >= 0");
     Eval ev;
     STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
@@ -1102,8 +1102,21 @@ bec_status bec_precond_apply(bec_ctx* c, int32_t pc, double sigma, const double*
         m.out = zout;
         HIPCHK(bec::launch_make_r(c->P, m, c->st));
     } else {
-        STCHK(compute_z(c, 0, ev, rin, pc == BEC_PC_COMPOSITE, sigma));
-        HIPCHK(hipMemcpyAsync(z, c->z, 2 * c->N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
+        const int pv = pc == BEC_PC_COMPOSITE ? 1 : (pc == BEC_PC_SYMMETRIC ? 2 : 0);
+        STCHK(compute_z(c, 0, ev, rin, pv, sigma));
+        if (pc == BEC_PC_SYMMETRIC) {   // the outer D^-1/2
+            bec::MakeRArgs m{};
+            m.psi = c->psi[0];
+            m.aux = c->aux[0];
+            m.rin = c->z;
+            for (int i = 0; i < 2; ++i) m.diag_shift[i] = ev.t.shift[i];
+            m.sigma = sigma;
+            m.apply_pv = 2;
+            m.out = zout;
+            HIPCHK(bec::launch_make_r(c->P, m, c->st));
+        } else {
+            HIPCHK(hipMemcpyAsync(z, c->z, 2 * c->N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
+        }
     }
     HIPCHK(hipStreamSynchronize(c->st));
     return BEC_OK;
@@ -1169,7 +1182,7 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
                      int32_t log_cap)
 {
     if (!c || !psi_inout || !o) return fail(BEC_EINVAL, "null argument");
-    if (o->pc < 0 || o->pc > 3 || o->beta < 0 || o->beta > 2) return fail(BEC_EINVAL, "bad options");
+    if (o->pc < 0 || o->pc > 4 || o->beta < 0 || o->beta > 2) return fail(BEC_EINVAL, "bad options");
     const auto t0 = std::chrono::steady_clock::now();
     const double dV = c->dV;
     const bec_params& p = c->p;
@@ -1185,11 +1198,13 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
     int n = 0;
     bec_status status = BEC_ENOTCONV;
     double E_prev = NAN, alpha_prev = 0.0, rz_old = 0.0;
-    const int zmode_pc = (o->pc == BEC_PC_V) ? 1 : (o->pc == BEC_PC_NONE ? 0 : 2);
+    const int zmode_pc = (o->pc == BEC_PC_V) ? 1 : (o->pc == BEC_PC_NONE ? 0 : (o->pc == BEC_PC_SYMMETRIC ? 3 : 2));
 
     for (;;) {
         // 1. residual, preconditioned residual and the conjugacy sums
-        if (zmode_pc == 2) STCHK(compute_z(c, cur, ev, nullptr, o->pc == BEC_PC_COMPOSITE, o->sigma));
+        if (zmode_pc >= 2)
+            STCHK(compute_z(c, cur, ev, nullptr,
+                            o->pc == BEC_PC_COMPOSITE ? 1 : (o->pc == BEC_PC_SYMMETRIC ? 2 : 0), o->sigma));
         bec::DirArgs A = dir_args(c, cur, ev, zmode_pc, o->sigma);
         A.have_prev = have_prev;
         double R[bec::kDirReduceSums];
@@ -1236,7 +1251,7 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
                 STCHK(direction_and_model(c, A, ev, &m));
                 if (m.rp < 0 && std::isfinite(m.rp)) break;
                 if (level == 0) { level = 1; rep.n_restarts++; continue; }
-                if (level == 1 && o->pc == BEC_PC_COMPOSITE) { level = 2; path |= 4; continue; }
+                if (level == 1 && o->pc >= BEC_PC_COMPOSITE) { level = 2; path |= 4; continue; }
                 if (level == 2) { level = 3; continue; }
                 stagnated = true;
                 break;

@@ -156,7 +156,7 @@ struct DirArgs {
     double mu[2];
     double diag_shift[2];         // shift_i for P_V
     double sigma;
-    int zmode;                    // 0 identity, 1 P_V, 2 from zbuf
+    int zmode;                    // 0 identity, 1 P_V, 2 from zbuf, 3 D^-1/2 zbuf (symmetrised composite)
     double zsign;                 // d = zsign z + beta p_old
     double beta;
     double c[2];                  // projection coefficients Re<d_i,psi_i>
@@ -174,7 +174,7 @@ constexpr int kDirWriteSums = 18;
 constexpr int kLsEpiSums = 7;    // line-search model epilogue (rho_1 + i rho_2 against K*rho)
 // sums: 0 rho1 rho1; 1 rho1 rho2; 2 rho2 rho2; 3..6 rho_i Phi[rho_j] (11, 12, 21, 22)
 
-struct MakeRArgs {                // out = r or P_V^-1 r (for the kinetic preconditioners)
+struct MakeRArgs {                // out = r, P_V^-1 r (apply_pv 1) or D^-1/2 r (apply_pv 2; D the P_V diagonal)
     const double2* psi;
     const double2* hpsi;
     const double2* aux;

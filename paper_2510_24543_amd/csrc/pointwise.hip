@@ -170,6 +170,14 @@ struct RZ {
     double2 r[2], z[2];
 };
 
+// 1 / ([shift + V + sum_j G_cj n_j + muLHY_c]_+ + sigma): the inverse P_V diagonal
+__device__ __forceinline__ double pv_inv(const PwParams& P, int c, double shift, double sigma, double V, double n1,
+                                         double n2, double ml)
+{
+    const double g = shift + V + P.G[c][0] * n1 + P.G[c][1] * n2 + ml;
+    return 1.0 / ((g > 0.0 ? g : 0.0) + sigma);
+}
+
 __device__ __forceinline__ RZ resid_precond(const PwParams& P, const DirArgs& A, long long i,
                                             double2 s1, double2 s2)
 {
@@ -191,6 +199,15 @@ __device__ __forceinline__ RZ resid_precond(const PwParams& P, const DirArgs& A,
     } else if (A.zmode == 2) {
         o.z[0] = A.zbuf[i];
         o.z[1] = A.zbuf[N + i];
+    } else if (A.zmode == 3) {
+        const double n1 = sq2(s1), n2 = sq2(s2);
+        const double V = trap_at(P, i);
+        const double2 ml = A.aux[N + i];
+        const double q1 = sqrt(pv_inv(P, 0, A.diag_shift[0], A.sigma, V, n1, n2, ml.x));
+        const double q2 = sqrt(pv_inv(P, 1, A.diag_shift[1], A.sigma, V, n1, n2, ml.y));
+        const double2 w1 = A.zbuf[i], w2 = A.zbuf[N + i];
+        o.z[0] = make_double2(q1 * w1.x, q1 * w1.y);
+        o.z[1] = make_double2(q2 * w2.x, q2 * w2.y);
     } else {
         o.z[0] = o.r[0];
         o.z[1] = o.r[1];
@@ -244,7 +261,7 @@ __device__ __forceinline__ DirIn dir_load(const DirArgs& A, long long N, long lo
     } else {
         v.po[0] = v.po[1] = make_double2(0.0, 0.0);
     }
-    if (A.zmode == 2) {
+    if (A.zmode >= 2) {
         v.zb[0] = A.zbuf[i];
         v.zb[1] = A.zbuf[N + i];
     } else {
@@ -279,6 +296,11 @@ __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirAr
         } else if (A.zmode == 2) {
             z[0] = cur.zb[0];
             z[1] = cur.zb[1];
+        } else if (A.zmode == 3) {
+            for (int c = 0; c < 2; ++c) {
+                const double q = sqrt(pv_inv(P, c, A.diag_shift[c], A.sigma, V, n[0], n[1], mlc[c]));
+                z[c] = make_double2(q * cur.zb[c].x, q * cur.zb[c].y);
+            }
         } else {
             z[0] = r[0];
             z[1] = r[1];
@@ -339,10 +361,12 @@ __global__ __launch_bounds__(kPwThreads) void make_r_kernel(PwParams P, MakeRArg
             const double n1 = sq2(s1), n2 = sq2(s2);
             const double V = trap_at(P, i);
             const double2 ml = A.aux[N + i];
-            double g1 = A.diag_shift[0] + V + P.G[0][0] * n1 + P.G[0][1] * n2 + ml.x;
-            double g2 = A.diag_shift[1] + V + P.G[1][0] * n1 + P.G[1][1] * n2 + ml.y;
-            g1 = 1.0 / ((g1 > 0.0 ? g1 : 0.0) + A.sigma);
-            g2 = 1.0 / ((g2 > 0.0 ? g2 : 0.0) + A.sigma);
+            double g1 = pv_inv(P, 0, A.diag_shift[0], A.sigma, V, n1, n2, ml.x);
+            double g2 = pv_inv(P, 1, A.diag_shift[1], A.sigma, V, n1, n2, ml.y);
+            if (A.apply_pv == 2) {
+                g1 = sqrt(g1);
+                g2 = sqrt(g2);
+            }
             r1 = make_double2(g1 * r1.x, g1 * r1.y);
             r2 = make_double2(g2 * r2.x, g2 * r2.y);
         }

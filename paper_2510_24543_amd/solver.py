@@ -16,7 +16,7 @@ import torch
 
 from . import binding as B
 
-PC = {"none": 0, "V": 1, "kin": 2, "composite": 3}
+PC = {"none": 0, "V": 1, "kin": 2, "composite": 3, "symmetric": 4}
 BETA = {"HS+": 0, "PR+": 1, "zero": 2}
 
 

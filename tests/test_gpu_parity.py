@@ -179,7 +179,7 @@ def test_energy_is_bitwise_repeatable(solver):
 
 
 # ---------------------------------------------------------------- preconditioners
-@pytest.mark.parametrize("pc", [0, 1, 2, 3])
+@pytest.mark.parametrize("pc", [0, 1, 2, 3, 4])
 def test_preconditioners(solver, orc, pc):
     grid, params = CASES["C1b"]
     psi = _state(grid, params, 14, True)
@@ -244,7 +244,7 @@ def test_param_grad(solver, orc, case):
 
 
 # ---------------------------------------------------------------- full solves
-SOLVE_CASES = [("C1a", 1), ("C1b", 1), ("C1b", 0), ("C1b", 2), ("C1b", 3)]
+SOLVE_CASES = [("C1a", 1), ("C1b", 1), ("C1b", 0), ("C1b", 2), ("C1b", 3), ("C1b", 4)]
 
 
 @pytest.mark.parametrize("name,pc", SOLVE_CASES, ids=[f"{n}-pc{p}" for n, p in SOLVE_CASES])
