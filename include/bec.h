@@ -84,13 +84,23 @@ typedef enum { BEC_PC_NONE = 0, BEC_PC_V = 1, BEC_PC_KIN = 2, BEC_PC_COMPOSITE =
 /* Conjugacy parameter of Sec. IV.C: Hestenes-Stiefel+, Polak-Ribiere+, or 0. */
 typedef enum { BEC_BETA_HS_PLUS = 0, BEC_BETA_PR_PLUS = 1, BEC_BETA_ZERO = 2 } bec_beta;
 
+/* bec_opts.flags.  BEC_SOLVE_SYNCHRONOUS: the host reads every reduced scalar
+ * before it enqueues the launches that depend on it.  By default bec_solve
+ * pipelines each iteration with P_V or no preconditioner: the device decides
+ * the step, the trial, the next residual sums and the next direction write
+ * from the reduced sums it has just produced, and the host waits once per
+ * iteration and checks every decision against the same rules; restarts and
+ * backtracking fall back to synchronous launches.  Both give the same iterates
+ * bit for bit. */
+#define BEC_SOLVE_SYNCHRONOUS 1
+
 typedef struct {
     int32_t pc;             /* bec_precond                                     */
     int32_t beta;           /* bec_beta                                        */
     int32_t max_iter;       /* accepted steps before BEC_ENOTCONV              */
     int32_t restart_period; /* beta = 0 when iter mod restart_period == 0; 0 off */
     int32_t max_backtrack;  /* Armijo halvings per step                        */
-    int32_t pad;
+    int32_t flags;          /* BEC_SOLVE_* bits; 0 = default                   */
     double tol_grad;        /* stop when max_i ||H_i psi_i - mu_i psi_i|| < tol */
     double tol_dE;          /* stop when |E_n - E_(n-1)| < tol_dE (0: off)     */
     double sigma;           /* regularising shift of P_V and P_Delta           */

@@ -32,7 +32,7 @@ class Params(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("pc", C.c_int32), ("beta", C.c_int32), ("max_iter", C.c_int32),
-                ("restart_period", C.c_int32), ("max_backtrack", C.c_int32), ("pad", C.c_int32),
+                ("restart_period", C.c_int32), ("max_backtrack", C.c_int32), ("flags", C.c_int32),
                 ("tol_grad", C.c_double), ("tol_dE", C.c_double), ("sigma", C.c_double),
                 ("armijo_c1", C.c_double), ("theta_max", C.c_double), ("tau_rel", C.c_double)]
 
@@ -158,7 +158,7 @@ def make_params(p: dict) -> Params:
     return P
 
 
-DEFAULT_OPTS = dict(pc=1, beta=0, max_iter=2000, restart_period=50, max_backtrack=30,
+DEFAULT_OPTS = dict(pc=1, beta=0, max_iter=2000, restart_period=50, max_backtrack=30, flags=0,
                     tol_grad=1e-10, tol_dE=0.0, sigma=1e-6, armijo_c1=1e-4,
                     theta_max=1.5707963267948966, tau_rel=1e-14)
 

@@ -175,12 +175,19 @@ struct bec_ctx {
     long long N = 0;
     double h[3] = {0, 0, 0}, L[3] = {0, 0, 0}, dV = 0;
     double2 *psi[2] = {}, *hpsi[2] = {}, *aux[2] = {};
-    double2 *pdir = nullptr, *r_old = nullptr, *z = nullptr, *rho = nullptr, *W = nullptr;
+    // search directions and residuals in pairs: a direction write reads p_old
+    // (pold) and r_old and writes p (pdir) and r (r_new); an accepted step swaps
+    // each pair, so a write enqueued ahead of the acceptance test leaves the
+    // state that a rejected step falls back to intact
+    double2 *pdir = nullptr, *pold = nullptr, *r_old = nullptr, *r_new = nullptr;
+    double2 *z = nullptr, *rho = nullptr, *W = nullptr;
     double *udtab = nullptr, *kv[3] = {}, *vv[3] = {}, *nodes = nullptr;
     double *partials = nullptr, *fft_partials = nullptr, *ls_partials = nullptr;
     double* scal = nullptr;    // device address of `host` (reduced scalars)
+    double* dscal = nullptr;   // device copies of the scalars that later launches read (same offsets)
     double2* tw[3] = {};
     double* host = nullptr;   // pinned scalars
+    hipEvent_t mark = nullptr; // end of the part of a pipelined iteration the host waits for
     int nblk_pw = 0;
     int nblk_x = 0;
     int fft_var[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // plan variant per axis: [plain, fused k-space]
@@ -250,6 +257,17 @@ bec_status prof_flush(bec_ctx* c)
         }                                                                              \
     } while (0)
 
+// Scalar slots (pinned host buffer and its device copy): each reduction of a
+// pipelined iteration has its own range, so one synchronisation reads them all.
+constexpr int kScalSlots = 128;
+constexpr int kScalModel = 0;     // direction-write sums [0,18), line-search sums [18,25), Parseval [30,32)
+constexpr int kScalHeval = 32;    // energy sums (kHevalSums)
+constexpr int kScalDir = 56;      // direction-reduce sums (kDirReduceSums)
+constexpr int kScalStep = 72;     // device step decision (kStepOut)
+static_assert(kScalHeval >= 32 && kScalHeval + bec::kHevalSums <= kScalDir, "scalar ranges overlap");
+static_assert(kScalDir + bec::kDirReduceSums <= kScalStep && kScalStep + bec::kStepOut <= kScalSlots,
+              "scalar ranges overlap");
+
 size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
 {
     const long long N = (long long)n[0] * n[1] * n[2];
@@ -273,8 +291,10 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
         bec::kMaxNodes * bec::kNodeStride * sizeof(double),                         // nodes
         (size_t)bec::kMaxSums * nb_pw * sizeof(double),                             // partials
         (size_t)3 * nb_x * sizeof(double),                                          // fft partials
-        64 * sizeof(double),                                                        // reserved
+        kScalSlots * sizeof(double),                                                // device scalar copies
         (size_t)bec::kLsEpiSums * nb_z * sizeof(double),                            // line-search partials
+        2 * N * c2,                                                                 // pold
+        2 * N * c2,                                                                 // r_new
     };
     size_t total = 0;
     for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); ++i) {
@@ -553,25 +573,36 @@ bec_status reduce_pw(bec_ctx* c, int M, int out_off)
     return BEC_OK;
 }
 
+// the same, with a device copy of the results at the same offset of c->dscal
+bec_status reduce_pw_copy(bec_ctx* c, int M, int out_off)
+{
+    const bec::RedSeg a{c->partials, c->nblk_pw, M, c->scal + out_off, c->dscal + out_off};
+    const bec::RedSeg none{nullptr, 0, 0, nullptr, nullptr};
+    LAUNCH(c, "reduce_final", 8.0 * M * c->nblk_pw, bec::launch_reduce_segs(a, none, none, c->st));
+    return BEC_OK;
+}
+
 // ------------------------------------------------------------------ H evaluation
 struct Eval {
     bec_terms t{};
     double sums[bec::kHevalSums]{};
 };
 
-// psi[set] = a_i src + b_i p (p may be null), then H psi, Phi, muLHY and the
-// energy sums for that state.
-bec_status heval(bec_ctx* c, const double2* src, const double2* p, const double a[2], const double b[2], int set,
-                 Eval* out)
+// psi[set] = a_i src + b_i p (p may be null; a, b from the device step
+// decision at `coef` when that is set), then H psi, Phi, muLHY and the energy
+// sums for that state (scalar range kScalHeval, host and device copy).
+bec_status heval_launch(bec_ctx* c, const double2* src, const double2* p, const double a[2], const double b[2],
+                        const double* coef, int set)
 {
     const long long N = c->N;
     bec::TrialZArgs z{};
     z.psi_src = src;
     z.p = p;
     for (int i = 0; i < 2; ++i) {
-        z.a[i] = a[i];
-        z.b[i] = b[i];
+        z.a[i] = coef ? 0.0 : a[i];
+        z.b[i] = coef ? 0.0 : b[i];
     }
+    z.coef = coef;
     z.psi_dst = c->psi[set];
     z.N = N;
     // the dipolar potentials Phi_1 + i Phi_2 land directly in aux[set] (its first
@@ -587,26 +618,29 @@ bec_status heval(bec_ctx* c, const double2* src, const double2* p, const double 
     ha.aux = c->aux[set];
     ha.partials = c->partials;
     LAUNCH(c, "heval_epilogue", (double)c->N * 128.0, bec::launch_heval_epi(c->P, ha, c->nblk_pw, c->st));
-    STCHK(reduce_pw(c, bec::kHevalSums, 0));
-    STCHK(fetch(c, bec::kHevalSums));
-    const double* S = c->host;
+    return reduce_pw_copy(c, bec::kHevalSums, kScalHeval);
+}
+
+// energy terms, chemical potentials and shifts from the energy sums of the last
+// heval_launch (after a synchronisation)
+bec_status heval_read(bec_ctx* c, Eval* out)
+{
+    const double* S = c->host + kScalHeval;
     std::memcpy(out->sums, S, sizeof(out->sums));
     const double dV = c->dV;
     bec_terms& t = out->t;
     std::memset(&t, 0, sizeof(t));
     const double snn[2][2] = {{S[4], S[5]}, {S[5], S[6]}};
+    // the rule that pipelined launches apply on the device to the same sums
+    bec::rule_mu_shift(S, c->P.Gdd, t.mu, t.shift);
     for (int i = 0; i < 2; ++i) {
         t.norm2[i] = dV * S[14 + i];
         t.E_kin[i] = c->p.N[i] * dV * S[i];
         t.E_trap[i] = c->p.N[i] * dV * S[2 + i];
-        double gdd_phi = 0.0;
         for (int j = 0; j < 2; ++j) {
             t.E_c[i][j] = 0.5 * c->p.N[i] * c->p.G[i][j] * dV * snn[i][j];
             t.E_dd[i][j] = 0.5 * c->p.N[i] * c->p.Gdd[i][j] * dV * S[7 + 2 * i + j];
-            gdd_phi += c->p.Gdd[i][j] * S[7 + 2 * i + j];
         }
-        t.mu[i] = S[12 + i] / S[14 + i];
-        t.shift[i] = (S[12 + i] - gdd_phi) / S[14 + i];
         t.res[i] = NAN;
     }
     t.E_lhy = dV * S[11];
@@ -620,6 +654,14 @@ bec_status heval(bec_ctx* c, const double2* src, const double2* p, const double 
     return BEC_OK;
 }
 
+bec_status heval(bec_ctx* c, const double2* src, const double2* p, const double a[2], const double b[2], int set,
+                 Eval* out)
+{
+    STCHK(heval_launch(c, src, p, a, b, nullptr, set));
+    STCHK(fetch(c, 0));
+    return heval_read(c, out);
+}
+
 bec::DirArgs dir_args(bec_ctx* c, int set, const Eval& ev, int zmode, double sigma)
 {
     bec::DirArgs A{};
@@ -628,8 +670,9 @@ bec::DirArgs dir_args(bec_ctx* c, int set, const Eval& ev, int zmode, double sig
     A.aux = c->aux[set];
     A.zbuf = c->z;
     A.r_old = c->r_old;
-    A.p = c->pdir;
-    A.r_out = c->r_old;
+    A.p = c->pold;
+    A.p_out = c->pdir;
+    A.r_out = c->r_new;
     A.rho = c->rho;
     for (int i = 0; i < 2; ++i) {
         A.mu[i] = ev.t.mu[i];
@@ -643,14 +686,20 @@ bec::DirArgs dir_args(bec_ctx* c, int set, const Eval& ev, int zmode, double sig
     return A;
 }
 
-// Direction reduce pass: returns the 12 sums (see kDirReduceSums).
-bec_status dir_reduce(bec_ctx* c, const bec::DirArgs& A, double* R)
+// Direction reduce pass into the scalar range kScalDir (host and device copy).
+bec_status dir_reduce_launch(bec_ctx* c, const bec::DirArgs& A)
 {
     const double rb = 64.0 + (A.zmode == 1 ? 16.0 : 0.0) + (A.zmode == 2 ? 32.0 : 0.0) + (A.have_prev ? 64.0 : 0.0);
     LAUNCH(c, "dir_reduce", (double)c->N * rb, bec::launch_dir_reduce(c->P, A, c->nblk_pw, c->st));
-    STCHK(reduce_pw(c, bec::kDirReduceSums, 0));
+    return reduce_pw_copy(c, bec::kDirReduceSums, kScalDir);
+}
+
+// Direction reduce pass: returns the 12 sums (see kDirReduceSums).
+bec_status dir_reduce(bec_ctx* c, const bec::DirArgs& A, double* R)
+{
+    STCHK(dir_reduce_launch(c, A));
     STCHK(fetch(c, bec::kDirReduceSums));
-    std::memcpy(R, c->host, bec::kDirReduceSums * sizeof(double));
+    std::memcpy(R, c->host + kScalDir, bec::kDirReduceSums * sizeof(double));
     return BEC_OK;
 }
 
@@ -683,23 +732,32 @@ struct Model {
     double LS[bec::kLsEpiSums];
     double pars[2];
     double pnorm[2], rp, E1, E2, psip[2];
+    double alpha, a[2], b[2];     // the device step decision and its trial coefficients
 };
 
 static_assert(bec::kDirWriteSums + bec::kLsEpiSums <= kParsevalOut, "model scalars overlap the Parseval slots");
 static_assert(bec::kIteSums <= kParsevalOut, "imaginary-time sums overlap the Parseval slots");
 static_assert(bec::kDirWriteSums + bec::kLsEpiSums <= bec::kMaxSums, "model partials exceed the partials area");
+static_assert(kParsevalOut + 2 <= kScalHeval, "Parseval slots overlap the energy sums");
 
-// Direction write pass (p, r, rho) + Parseval FFT of p + dipolar FFT of rho +
-// model epilogue; one synchronisation for all the model scalars.
-bec_status direction_and_model(bec_ctx* c, const bec::DirArgs& A, const Eval& ev, Model* m)
+// Direction write pass (p, r, rho).
+bec_status dir_write_launch(bec_ctx* c, const bec::DirArgs& A)
+{
+    const double wb = 96.0 + (A.beta != 0.0 || A.dev_dir ? 32.0 : 0.0) + (A.zmode == 2 ? 32.0 : 0.0) + 80.0;
+    LAUNCH(c, "dir_write", (double)c->N * wb, bec::launch_dir_write(c->P, A, c->nblk_pw, c->st));
+    return BEC_OK;
+}
+
+// Parseval FFT of p, dipolar FFT of rho with the model epilogue, one reduction
+// of the direction-write, Parseval and epilogue partials (host and device
+// copies), then the step decision on the device (kScalStep) from the state's
+// norms, the previous step and the angle cap.
+bec_status model_launch(bec_ctx* c, const double norm2[2], double alpha_prev, double theta_max)
 {
     const long long N = c->N;
-    const double wb = 96.0 + (A.beta != 0.0 ? 32.0 : 0.0) + (A.zmode == 2 ? 32.0 : 0.0) + 80.0;
-    LAUNCH(c, "dir_write", (double)c->N * wb, bec::launch_dir_write(c->P, A, c->nblk_pw, c->st));
     // Parseval sums <p_i, T p_i> from the forward transforms of p; the packed
     // rho_1 + i rho_2 through the dipolar kernel, its last inverse pass fused
-    // with the model epilogue (K*rho is never stored); one launch reduces the
-    // direction-write, Parseval and epilogue partials
+    // with the model epilogue (K*rho is never stored)
     const double2* src[3] = {c->pdir, c->pdir + N, c->rho};
     double2* dst[3] = {c->W, c->W + N, c->W + 2 * N};
     const int ops[3] = {bec::kOpParseval, bec::kOpParseval, bec::kOpMulDip};
@@ -714,42 +772,58 @@ bec_status direction_and_model(bec_ctx* c, const bec::DirArgs& A, const Eval& ev
     const int nblk_z = bec::fft_blocks(c->n[2], c->fft_var[2][0], zA.npencil);
     LAUNCH(c, "fft_z_inv_ls", (double)N * 32.0,
            bec::fft_zinv_ls_pass(c->n[2], c->fft_var[2][0], zA, c->rho, c->ls_partials, c->st));
+    const int o = kScalModel;
+    const bec::RedSeg s1{c->partials, c->nblk_pw, bec::kDirWriteSums, c->scal + o, c->dscal + o};
+    const bec::RedSeg s2{c->fft_partials, c->nblk_x, 2, c->scal + o + kParsevalOut, c->dscal + o + kParsevalOut};
+    const bec::RedSeg s3{c->ls_partials, nblk_z, bec::kLsEpiSums, c->scal + o + bec::kDirWriteSums,
+                         c->dscal + o + bec::kDirWriteSums};
     LAUNCH(c, "reduce_final", 8.0 * (bec::kDirWriteSums * c->nblk_pw + 2 * c->nblk_x + bec::kLsEpiSums * nblk_z),
-           bec::launch_reduce_final3(c->partials, c->nblk_pw, bec::kDirWriteSums, c->scal, c->fft_partials,
-                                     c->nblk_x, 2, c->scal + kParsevalOut, c->ls_partials, nblk_z,
-                                     bec::kLsEpiSums, c->scal + bec::kDirWriteSums, c->st));
-    STCHK(fetch(c, 32));
-    const double* S = c->host;
+           bec::launch_reduce_segs(s1, s2, s3, c->st));
+    bec::StepArgs st{};
+    st.D = c->dscal + o;
+    st.LS = c->dscal + o + bec::kDirWriteSums;
+    st.pars = c->dscal + o + kParsevalOut;
+    st.dV = c->dV;
+    st.inv_n = 1.0 / (double)N;
+    st.norm2[0] = norm2[0];
+    st.norm2[1] = norm2[1];
+    st.alpha_prev = alpha_prev;
+    st.theta_max = theta_max;
+    st.out = c->dscal + kScalStep;
+    st.out_host = c->scal + kScalStep;
+    LAUNCH(c, "ls_step", 8.0 * 32, bec::launch_ls_step(c->P, st, c->st));
+    return BEC_OK;
+}
+
+// model sums and the step decision of the last model_launch (after a synchronisation)
+void model_read(bec_ctx* c, Model* m)
+{
+    const double* S = c->host + kScalModel;
     std::memcpy(m->D, S, sizeof(m->D));
     std::memcpy(m->LS, S + bec::kDirWriteSums, sizeof(m->LS));
     m->pars[0] = S[kParsevalOut];
     m->pars[1] = S[kParsevalOut + 1];
-    const double dV = c->dV;
-    const bec_params& p = c->p;
-    const double* D = m->D;
-    m->rp = 0.0;
-    double E1 = 0.0, E2 = 0.0;
+    const double* T = c->host + kScalStep;
     for (int i = 0; i < 2; ++i) {
-        m->pnorm[i] = std::sqrt(dV * D[i]);
-        m->psip[i] = dV * D[16 + i];
-        m->rp += 2.0 * p.N[i] * dV * D[2 + i];
-        E1 += 2.0 * p.N[i] * dV * D[4 + i];                                   // E'_i
-        const double pTp = dV * m->pars[i] / (double)N;                       // <p_i, T p_i>
-        const double pn2 = m->pnorm[i] * m->pnorm[i];
-        E2 += 2.0 * p.N[i] * (pTp + dV * D[8 + i] - pn2 * dV * D[6 + i]);     // one-body part of E''_ii
-        for (int j = 0; j < 2; ++j) {
-            const double rr = (i == 0 && j == 0) ? m->LS[0] : (i == 1 && j == 1) ? m->LS[2] : m->LS[1];
-            E2 += 4.0 * p.N[i] * dV * (p.G[i][j] * rr + p.Gdd[i][j] * m->LS[3 + 2 * i + j]);
-        }
-        if (c->P.lhy_on) E2 += 2.0 * p.N[i] * dV * (D[10 + i] - pn2 * D[12 + i]);   // n'' part of E''_LHY
+        m->a[i] = T[i];
+        m->b[i] = T[2 + i];
+        m->pnorm[i] = T[8 + i];
+        m->psip[i] = T[10 + i];
     }
-    if (c->P.lhy_on) {
-        E1 += c->P.K3 * dV * D[14];
-        E2 += 2.0 * c->P.K3 * dV * D[15];
-    }
-    m->E1 = E1;
-    m->E2 = E2;
-    (void)ev;
+    m->alpha = T[4];
+    m->rp = T[5];
+    m->E1 = T[6];
+    m->E2 = T[7];
+}
+
+// Direction write + model + step decision; one synchronisation.
+bec_status direction_and_model(bec_ctx* c, const bec::DirArgs& A, const Eval& ev, double alpha_prev,
+                               double theta_max, Model* m)
+{
+    STCHK(dir_write_launch(c, A));
+    STCHK(model_launch(c, ev.t.norm2, alpha_prev, theta_max));
+    STCHK(fetch(c, 0));
+    model_read(c, m);
     return BEC_OK;
 }
 
@@ -857,6 +931,9 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
         c->aux[1] = (double2*)at(5);
         c->pdir = (double2*)at(6);
         c->r_old = (double2*)at(7);
+        c->pold = (double2*)at(26);
+        c->r_new = (double2*)at(27);
+        c->dscal = (double*)at(24);
         c->z = (double2*)at(8);
         c->rho = (double2*)at(9);
         c->W = (double2*)at(10);
@@ -874,11 +951,17 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
         c->nblk_x = bec::fft_blocks(c->n[0], c->fft_var[0][1], (long long)c->n[1] * c->n[2]);
         // reduced scalars: the final-reduction kernels write straight into pinned
         // host memory, so reading them back needs a stream synchronisation only
-        if (hipHostMalloc((void**)&c->host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void**)&c->host, kScalSlots * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             delete c;
             return fail(BEC_EHIP, "hipHostMalloc of the scalar buffer failed");
         }
+        if (hipEventCreateWithFlags(&c->mark, hipEventDisableTiming) != hipSuccess) {
+            (void)hipHostFree(c->host);
+            delete c;
+            return fail(BEC_EHIP, "hipEventCreate failed");
+        }
         if (hipHostGetDevicePointer((void**)&c->scal, c->host, 0) != hipSuccess) {
+            (void)hipEventDestroy(c->mark);
             (void)hipHostFree(c->host);
             delete c;
             return fail(BEC_EHIP, "hipHostGetDevicePointer of the scalar buffer failed");
@@ -897,6 +980,7 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
             if (hipMemcpyAsync(c->tw[d], tw.data(), L * sizeof(double2), hipMemcpyHostToDevice, c->st) != hipSuccess ||
                 hipMemcpyAsync(c->kv[d], kv.data(), L * sizeof(double), hipMemcpyHostToDevice, c->st) != hipSuccess ||
                 hipStreamSynchronize(c->st) != hipSuccess) {
+                (void)hipEventDestroy(c->mark);
                 (void)hipHostFree(c->host);
                 delete c;
                 return fail(BEC_EHIP, "upload of FFT tables failed");
@@ -904,6 +988,7 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
         }
         bec_status st = upload_params(c, true);
         if (st != BEC_OK) {
+            (void)hipEventDestroy(c->mark);
             (void)hipHostFree(c->host);
             delete c;
             return st;
@@ -1017,6 +1102,7 @@ bec_status bec_destroy(bec_ctx* ctx)
     if (!ctx) return BEC_OK;
     (void)prof_flush(ctx);
     for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
+    if (ctx->mark) (void)hipEventDestroy(ctx->mark);
     if (ctx->host) (void)hipHostFree(ctx->host);
     delete ctx;
     return BEC_OK;
@@ -1137,19 +1223,17 @@ bec_status bec_linesearch(bec_ctx* c, const double* psi, const double* d, double
     A.c[0] = c->dV * R[3];
     A.c[1] = c->dV * R[9];
     Model m;
-    STCHK(direction_and_model(c, A, ev, &m));
+    // step of the model: -E'/E'' when it has a minimum, else 0.1 / max|p_i|, capped at theta_max
+    STCHK(direction_and_model(c, A, ev, 0.0, o->theta_max, &m));
     const double pmax = std::max(m.pnorm[0], m.pnorm[1]);
     if (!(pmax > 0)) return fail(BEC_EINVAL, "direction has no tangent component");
-    double alpha = (m.E2 > 0 && std::isfinite(m.E2) && std::isfinite(m.E1) && -m.E1 / m.E2 > 0) ? -m.E1 / m.E2
-                                                                                                : 0.1 / pmax;
-    if (alpha * pmax > o->theta_max) alpha = o->theta_max / pmax;
+    double alpha = m.alpha;
     const double tau = o->tau_rel * std::fabs(ev.t.E);
     double a[2], b[2];
     Eval tr;
     int trials = 0, path = 0;
     bool ok = false;
-    geodesic_coeffs(ev, m, alpha, a, b);
-    STCHK(heval(c, c->psi[0], c->pdir, a, b, 1, &tr));
+    STCHK(heval(c, c->psi[0], c->pdir, m.a, m.b, 1, &tr));
     ++trials;
     if (tr.t.E <= ev.t.E + tau) ok = true;
     for (int k = 0; !ok && k < o->max_backtrack; ++k) {
@@ -1199,6 +1283,27 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
     bec_status status = BEC_ENOTCONV;
     double E_prev = NAN, alpha_prev = 0.0, rz_old = 0.0;
     const int zmode_pc = (o->pc == BEC_PC_V) ? 1 : (o->pc == BEC_PC_NONE ? 0 : (o->pc == BEC_PC_SYMMETRIC ? 3 : 2));
+    // Pipelined iterations (P_V or no preconditioner): the first trial of a step
+    // is enqueued at the step the device decides from the model sums, followed
+    // by the direction reduce of the trial state and, from there, the next
+    // direction write with the device's beta; the host waits once, for the part
+    // before that write, and checks every decision afterwards.  A step that
+    // needs a restart or a backtrack falls back to host-synchronised launches;
+    // the speculative write then only touched buffers the fallback rewrites.
+    const bool pipe = !(o->flags & BEC_SOLVE_SYNCHRONOUS) && zmode_pc <= 1;
+    auto beta_rule = [&](int iter, bool prev, double rz_prev) {
+        bec::BetaRule br{};
+        br.restart = !prev || o->beta == BEC_BETA_ZERO || (o->restart_period > 0 && iter % o->restart_period == 0);
+        br.mode = o->beta == BEC_BETA_PR_PLUS ? 1 : 0;
+        br.rz_old = rz_prev;
+        br.w[0] = wS[0];
+        br.w[1] = wS[1];
+        br.dV = dV;
+        return br;
+    };
+    double R[bec::kDirReduceSums];
+    bool R_ready = false;      // R holds the direction-reduce sums of the current state
+    bool spec_write = false;   // the current state's direction write (device beta) is already enqueued
 
     for (;;) {
         // 1. residual, preconditioned residual and the conjugacy sums
@@ -1207,8 +1312,8 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
                             o->pc == BEC_PC_COMPOSITE ? 1 : (o->pc == BEC_PC_SYMMETRIC ? 2 : 0), o->sigma));
         bec::DirArgs A = dir_args(c, cur, ev, zmode_pc, o->sigma);
         A.have_prev = have_prev;
-        double R[bec::kDirReduceSums];
-        STCHK(dir_reduce(c, A, R));
+        if (!R_ready) STCHK(dir_reduce(c, A, R));
+        R_ready = false;
         ev.t.res[0] = std::sqrt(dV * R[0]);
         ev.t.res[1] = std::sqrt(dV * R[6]);
         const double res_max = std::max(ev.t.res[0], ev.t.res[1]);
@@ -1217,25 +1322,16 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
         if (o->tol_dE > 0 && n > 0 && std::fabs(ev.t.E - E_prev) < o->tol_dE) { status = BEC_OK; break; }
         if (n >= o->max_iter) { status = BEC_ENOTCONV; break; }
 
-        // 2. beta (HS+ or PR+), restarts
-        const bool restart = !have_prev || o->beta == BEC_BETA_ZERO ||
-                             (o->restart_period > 0 && n % o->restart_period == 0);
-        double beta = 0.0;
-        if (!restart) {
-            double num = 0.0, den = 0.0;
-            for (int i = 0; i < 2; ++i) {
-                num += wS[i] * dV * R[6 * i + 1];
-                den += wS[i] * dV * R[6 * i + 2];
-            }
-            if (o->beta == BEC_BETA_PR_PLUS) den = rz_old;
-            beta = (den > 0 && std::isfinite(den) && std::isfinite(num)) ? num / den : 0.0;
-            if (beta < 0) beta = 0.0;
-        }
+        // 2. beta (HS+ or PR+), restarts (Sec. IV.C)
+        const double beta = bec::rule_beta(R, beta_rule(n, have_prev, rz_old));
+        double rz_now = wS[0] * dV * R[5] + wS[1] * dV * R[11];
         int level = beta > 0 ? 0 : 1, path = 0, trials = 0;
-        bool accepted = false, stagnated = false;
-        double alpha = 0.0, rz_now = 0.0;
+        bool accepted = false, stagnated = false, first = true, tried = false, next_ready = false;
+        double alpha = 0.0;
+        double Rn[bec::kDirReduceSums];
         Model m{};
         Eval tr;
+        bec_status hs = BEC_OK;
         while (!accepted && !stagnated) {
             // 3. direction d = -z + beta p_old, projected; restart when <r,p> >= 0
             for (;;) {
@@ -1247,9 +1343,40 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
                 }
                 A.beta = b;
                 A.zsign = -1.0;
-                for (int i = 0; i < 2; ++i) A.c[i] = -dV * R[6 * i + 3] + b * dV * R[6 * i + 4];
-                STCHK(direction_and_model(c, A, ev, &m));
+                bec::rule_proj(R, b, dV, A.c);
+                if (!(first && spec_write)) STCHK(dir_write_launch(c, A));
+                // 4. the closed-form step of the second-order model (Sec. V), decided on the device
+                STCHK(model_launch(c, ev.t.norm2, alpha_prev, o->theta_max));
+                if (first && pipe) {
+                    // 5a. the trial at the device's step, the reduce of the state it
+                    // reaches and the next direction write, then one wait
+                    const int nxt = 1 - cur;
+                    STCHK(heval_launch(c, c->psi[cur], c->pdir, nullptr, nullptr, c->dscal + kScalStep, nxt));
+                    bec::DirArgs An = dir_args(c, nxt, ev, zmode_pc, o->sigma);
+                    An.dev_state = c->dscal + kScalHeval;
+                    An.have_prev = 1;
+                    An.r_old = c->r_new;      // r and p of this step: the pair after the swap
+                    An.p = c->pdir;
+                    An.p_out = c->pold;
+                    An.r_out = c->r_old;
+                    STCHK(dir_reduce_launch(c, An));
+                    HIPCHK(hipEventRecord(c->mark, c->st));
+                    An.rule = beta_rule(n + 1, true, rz_now);
+                    An.dev_dir = c->dscal + kScalDir;
+                    An.zsign = -1.0;
+                    STCHK(dir_write_launch(c, An));
+                    HIPCHK(hipEventSynchronize(c->mark));
+                    model_read(c, &m);
+                    hs = heval_read(c, &tr);
+                    std::memcpy(Rn, c->host + kScalDir, sizeof(Rn));
+                    tried = true;
+                } else {
+                    STCHK(fetch(c, 0));
+                    model_read(c, &m);
+                }
+                first = false;
                 if (m.rp < 0 && std::isfinite(m.rp)) break;
+                tried = false;
                 if (level == 0) { level = 1; rep.n_restarts++; continue; }
                 if (level == 1 && o->pc >= BEC_PC_COMPOSITE) { level = 2; path |= 4; continue; }
                 if (level == 2) { level = 3; continue; }
@@ -1259,24 +1386,21 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
             if (stagnated) break;
             rz_now = wS[0] * dV * R[5] + wS[1] * dV * R[11];
 
-            // 4. closed-form step of the second-order model (Sec. V)
-            const double pmax = std::max(m.pnorm[0], m.pnorm[1]);
-            if (m.E2 > 0 && std::isfinite(m.E2) && std::isfinite(m.E1) && -m.E1 / m.E2 > 0)
-                alpha = -m.E1 / m.E2;
-            else
-                alpha = alpha_prev > 0 ? alpha_prev : 0.1 / pmax;
-            if (alpha * pmax > o->theta_max) alpha = o->theta_max / pmax;
-
             // 5. validate along the exact geodesic, Armijo halving
+            alpha = m.alpha;
             const double tau = o->tau_rel * std::fabs(ev.t.E);
-            double a[2], bb[2];
-            geodesic_coeffs(ev, m, alpha, a, bb);
-            bec_status hs = heval(c, c->psi[cur], c->pdir, a, bb, 1 - cur, &tr);
+            if (!tried) {
+                STCHK(heval_launch(c, c->psi[cur], c->pdir, nullptr, nullptr, c->dscal + kScalStep, 1 - cur));
+                STCHK(fetch(c, 0));
+                hs = heval_read(c, &tr);
+            }
             if (hs != BEC_OK && hs != BEC_ENONFINITE) return hs;
             ++trials;
             if (hs == BEC_OK && tr.t.E <= ev.t.E + tau) {
                 accepted = true;
+                next_ready = tried;
             } else {
+                double a[2], bb[2];
                 for (int k = 0; k < o->max_backtrack; ++k) {
                     alpha *= 0.5;
                     geodesic_coeffs(ev, m, alpha, a, bb);
@@ -1291,6 +1415,7 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
                     }
                 }
             }
+            tried = false;
             if (!accepted) {
                 if (level == 0) { level = 1; rep.n_restarts++; path |= 2; continue; }
                 stagnated = true;
@@ -1315,10 +1440,15 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
         E_prev = ev.t.E;
         ev = tr;
         cur = 1 - cur;
+        std::swap(c->pdir, c->pold);
+        std::swap(c->r_old, c->r_new);
         rz_old = rz_now;
         alpha_prev = alpha;
         have_prev = true;
         ++n;
+        // the speculative reduce and write were made for exactly this state
+        R_ready = spec_write = next_ready;
+        if (next_ready) std::memcpy(R, Rn, sizeof(R));
     }
     HIPCHK(hipMemcpyAsync(psi_inout, c->psi[cur], 2 * c->N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
     HIPCHK(hipStreamSynchronize(c->st));

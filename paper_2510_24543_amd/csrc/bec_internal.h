@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "pcg_rules.h"
+
 namespace bec {
 
 constexpr int kMaxNodes = 64;        // Gauss-Legendre nodes for the LHY u integral
@@ -94,6 +96,7 @@ struct TrialZArgs {
     const double2* psi_src;       // 2N
     const double2* p;             // 2N or null
     double a[2], b[2];
+    const double* coef;           // non-null: a and b from device memory (a_1, a_2, b_1, b_2) instead
     double2* psi_dst;             // 2N (may equal psi_src)
     long long N;                  // points per component
 };
@@ -150,7 +153,8 @@ struct DirArgs {
     const double2* aux;           // Phi packed, muLHY packed
     const double2* zbuf;          // z (when zmode == 2), 2N
     const double2* r_old;         // 2N (read by the reduce pass)
-    double2* p;                   // 2N: p_old on input, p on output (write pass)
+    double2* p;                   // 2N: p_old
+    double2* p_out;               // 2N: p (write pass; may equal p)
     double2* r_out;               // 2N (write pass)
     double2* rho;                 // N (write pass): rho_1 + i rho_2
     double mu[2];
@@ -162,6 +166,14 @@ struct DirArgs {
     double c[2];                  // projection coefficients Re<d_i,psi_i>
     int have_prev;
     double* partials;
+    // Pipelined launches, enqueued before the host has read the sums they
+    // depend on: when dev_state is set, mu and diag_shift come from the energy
+    // sums there (rule_mu_shift); when dev_dir is set (write pass), beta and c
+    // come from the direction-reduce sums there (rule_beta with `rule`, then
+    // rule_proj).  Both point to device memory written by an earlier launch.
+    const double* dev_state;
+    const double* dev_dir;
+    BetaRule rule;
 };
 constexpr int kDirReduceSums = 12;
 // sums (per component i, index 6*i + k): 0 |r|^2, 1 Re<r - r_old, z>, 2 Re<r - r_old, p_old>,
@@ -203,6 +215,26 @@ hipError_t launch_scale2(const PwParams& P, const double2* in, double2* out, dou
                          hipStream_t s);
 hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hpsi, double2* out,
                        double mu0, double mu1, double s0, double s1, int projected, hipStream_t s);
+// Closed-form step of the second-order model (Sec. V) from the reduced model
+// sums, on the device, so the trial point can be enqueued before the host has
+// read them.  One thread; writes kStepOut values to out (device) and, when
+// non-null, out_host (host-mapped).
+struct StepArgs {
+    const double* D;              // kDirWriteSums direction-write sums
+    const double* LS;             // kLsEpiSums line-search epilogue sums
+    const double* pars;           // 2 Parseval sums sum_k |k|^2/2 |FFT(p_i)|^2
+    double dV, inv_n;             // cell volume, 1 / points
+    double norm2[2];              // |psi_i|^2 of the current state
+    double alpha_prev;            // previous accepted step (fallback when the model has no minimum)
+    double theta_max;             // largest geodesic angle
+    double* out;
+    double* out_host;
+};
+constexpr int kStepOut = 12;
+// out: 0,1 a_i; 2,3 b_i (trial psi_i = a_i psi_i + b_i p_i); 4 alpha; 5 <r,p> sum; 6 E';
+//      7 E''; 8,9 |p_i|; 10,11 Re<p_i, psi_i> dV
+hipError_t launch_ls_step(const PwParams& P, const StepArgs& a, hipStream_t s);
+
 // out[m] = sum_b partials[m * nblk + b] for m < M (fixed order), one block
 hipError_t launch_reduce_final(const double* partials, int nblk, int M, double* out, hipStream_t s);
 // two or three partial arrays in one launch (M1 rows of nblk1, then M2 rows of
@@ -212,6 +244,15 @@ hipError_t launch_reduce_final2(const double* partials1, int nblk1, int M1, doub
 hipError_t launch_reduce_final3(const double* partials1, int nblk1, int M1, double* out1, const double* partials2,
                                 int nblk2, int M2, double* out2, const double* partials3, int nblk3, int M3,
                                 double* out3, hipStream_t s);
+// Reduction segment with an optional second destination: out[m] and, when
+// copy is non-null, copy[m] (a device copy of host-mapped results).
+struct RedSeg {
+    const double* partials;
+    int nblk, M;
+    double* out;
+    double* copy;
+};
+hipError_t launch_reduce_segs(const RedSeg& s1, const RedSeg& s2, const RedSeg& s3, hipStream_t s);
 
 // ---------------------------------------------------------------- batched scan
 // Instances with the same grid shape form a group; every batched kernel covers

@@ -437,6 +437,12 @@ template <int L, int T, int R0, int R1, int R2, int NTHR>
 __global__ __launch_bounds__(NTHR) void fft_trial_z_kernel(FftPassArgs A, TrialZArgs Z)
 {
     __shared__ double2 lds[(NTHR / T) * lds_row<L>()];
+    if (Z.coef) {   // coefficients decided on the device by the step kernel
+        Z.a[0] = Z.coef[0];
+        Z.a[1] = Z.coef[1];
+        Z.b[0] = Z.coef[2];
+        Z.b[1] = Z.coef[3];
+    }
     trial_z_body<L, T, R0, R1, R2, NTHR>(A, Z, A.dst[0], A.dst[1], A.dst[2], lds);
 }
 
@@ -460,6 +466,7 @@ __global__ __launch_bounds__(NTHR) void fft_btrial_z_kernel(FftPassArgs A, BGrou
     Z.a[1] = S.a[1];
     Z.b[0] = S.b[0];
     Z.b[1] = S.b[1];
+    Z.coef = nullptr;
     Z.psi_dst = g.psi + ((long long)l * 2 + (1 - S.cur)) * 2 * N;
     Z.N = N;
     double2* w = g.W + (long long)l * 3 * N;

@@ -217,6 +217,7 @@ __device__ __forceinline__ RZ resid_precond(const PwParams& P, const DirArgs& A,
 
 __global__ __launch_bounds__(kPwThreads) void dir_reduce_kernel(PwParams P, DirArgs A)
 {
+    if (A.dev_state) rule_mu_shift(A.dev_state, P.Gdd, A.mu, A.diag_shift);
     const long long N = P.N;
     double acc[kDirReduceSums];
 #pragma unroll
@@ -273,6 +274,11 @@ __device__ __forceinline__ DirIn dir_load(const DirArgs& A, long long N, long lo
 // Direction write pass with the LHY part of the line-search model.
 __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirArgs A)
 {
+    if (A.dev_state) rule_mu_shift(A.dev_state, P.Gdd, A.mu, A.diag_shift);
+    if (A.dev_dir) {
+        A.beta = rule_beta(A.dev_dir, A.rule);
+        rule_proj(A.dev_dir, A.beta, A.rule.dV, A.c);
+    }
     const long long N = P.N;
     const long long stride = (long long)gridDim.x * kPwThreads;
     double acc[kDirWriteSums];
@@ -316,7 +322,7 @@ __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirAr
                 d.y += A.beta * cur.po[c].y;
             }
             p[c] = make_double2(d.x - A.c[c] * s[c].x, d.y - A.c[c] * s[c].y);
-            A.p[c * N + i] = p[c];
+            A.p_out[c * N + i] = p[c];
             A.r_out[c * N + i] = r[c];
             rho[c] = redot(s[c], p[c]);
             const double2 hmf = make_double2(cur.h[c].x - mlc[c] * s[c].x, cur.h[c].y - mlc[c] * s[c].y);
@@ -453,16 +459,9 @@ __global__ __launch_bounds__(kPwThreads) void grad_kernel(PwParams P, const doub
     }
 }
 
-// one workgroup per reduced scalar m: out[m] = sum_b partials[m * nblk + b]
-// One block per scalar: blocks [0, M1) reduce rows of partials1 (nblk1 per row)
-// into out1, the next M2 blocks rows of partials2 into out2, the rest rows of
-// partials3 into out3.
-struct RedSeg {
-    const double* partials;
-    int nblk, M;
-    double* out;
-};
-
+// One block per scalar: blocks [0, M1) reduce rows of s1.partials (s1.nblk per
+// row) into s1.out, the next M2 blocks rows of s2 into s2.out, the rest rows of
+// s3 into s3.out (and each into its copy when that is set).
 __global__ __launch_bounds__(256) void reduce_final_kernel(RedSeg s1, RedSeg s2, RedSeg s3)
 {
     __shared__ double sh[4];
@@ -478,14 +477,79 @@ __global__ __launch_bounds__(256) void reduce_final_kernel(RedSeg s1, RedSeg s2,
     }
     const double* partials = g.partials;
     const int nblk = g.nblk;
-    double* out = g.out;
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256) s += partials[(long long)m * nblk + b];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) out[m] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    if (threadIdx.x == 0) {
+        const double v = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+        g.out[m] = v;
+        if (g.copy) g.copy[m] = v;
+    }
+}
+
+// Closed-form step of the second-order model along the geodesic (Sec. V):
+// E'(0) and E''(0) from the model sums, alpha* = -E'/E'' when the model has a
+// minimum (else the previous step, else 0.1 / max|p_i|), capped at theta_max,
+// then the trial coefficients psi_i(alpha) = (cos th_i psi_i + sin th_i p_i/|p_i|)
+// / norm with th_i = alpha |p_i|.
+__global__ void ls_step_kernel(PwParams P, StepArgs A)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double dV = A.dV;
+    const double* D = A.D;
+    const double* LS = A.LS;
+    double o[kStepOut];
+    double rp = 0.0, E1 = 0.0, E2 = 0.0, pnorm[2], psip[2];
+    for (int i = 0; i < 2; ++i) {
+        pnorm[i] = sqrt(dV * D[i]);
+        psip[i] = dV * D[16 + i];
+        rp += 2.0 * P.Nat[i] * dV * D[2 + i];
+        E1 += 2.0 * P.Nat[i] * dV * D[4 + i];                                  // E'_i
+        const double pTp = dV * A.pars[i] * A.inv_n;                           // <p_i, T p_i> (Parseval)
+        const double pn2 = pnorm[i] * pnorm[i];
+        E2 += 2.0 * P.Nat[i] * (pTp + dV * D[8 + i] - pn2 * dV * D[6 + i]);    // one-body part of E''_ii
+        for (int j = 0; j < 2; ++j) {
+            const double rr = (i == 0 && j == 0) ? LS[0] : (i == 1 && j == 1) ? LS[2] : LS[1];
+            E2 += 4.0 * P.Nat[i] * dV * (P.G[i][j] * rr + P.Gdd[i][j] * LS[3 + 2 * i + j]);
+        }
+        if (P.lhy_on) E2 += 2.0 * P.Nat[i] * dV * (D[10 + i] - pn2 * D[12 + i]);   // n'' part of E''_LHY
+    }
+    if (P.lhy_on) {
+        E1 += P.K3 * dV * D[14];
+        E2 += 2.0 * P.K3 * dV * D[15];
+    }
+    const double pmax = fmax(pnorm[0], pnorm[1]);
+    double alpha;
+    if (E2 > 0.0 && isfinite(E2) && isfinite(E1) && -E1 / E2 > 0.0) alpha = -E1 / E2;
+    else alpha = A.alpha_prev > 0.0 ? A.alpha_prev : 0.1 / pmax;
+    if (alpha * pmax > A.theta_max) alpha = A.theta_max / pmax;
+    for (int i = 0; i < 2; ++i) {
+        if (pnorm[i] > 0.0) {
+            const double th = alpha * pnorm[i];
+            const double ca = cos(th), sb = sin(th) / pnorm[i];
+            const double nrm2 = ca * ca * A.norm2[i] + sb * sb * pnorm[i] * pnorm[i] + 2.0 * ca * sb * psip[i];
+            const double s = 1.0 / sqrt(nrm2);
+            o[i] = ca * s;
+            o[2 + i] = sb * s;
+        } else {
+            o[i] = 1.0 / sqrt(A.norm2[i]);
+            o[2 + i] = 0.0;
+        }
+    }
+    o[4] = alpha;
+    o[5] = rp;
+    o[6] = E1;
+    o[7] = E2;
+    o[8] = pnorm[0];
+    o[9] = pnorm[1];
+    o[10] = psip[0];
+    o[11] = psip[1];
+    for (int m = 0; m < kStepOut; ++m) A.out[m] = o[m];
+    if (A.out_host)
+        for (int m = 0; m < kStepOut; ++m) A.out_host[m] = o[m];
 }
 
 int pw_blocks(const PwParams& P) { return P.nblk_pw; }
@@ -549,12 +613,24 @@ hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hps
     return hipGetLastError();
 }
 
+hipError_t launch_reduce_segs(const RedSeg& s1, const RedSeg& s2, const RedSeg& s3, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(s1.M + s2.M + s3.M), dim3(256), 0, s, s1, s2, s3);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce_final3(const double* partials1, int nblk1, int M1, double* out1, const double* partials2,
                                 int nblk2, int M2, double* out2, const double* partials3, int nblk3, int M3,
                                 double* out3, hipStream_t s)
 {
-    const RedSeg a{partials1, nblk1, M1, out1}, b{partials2, nblk2, M2, out2}, c{partials3, nblk3, M3, out3};
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(M1 + M2 + M3), dim3(256), 0, s, a, b, c);
+    const RedSeg a{partials1, nblk1, M1, out1, nullptr}, b{partials2, nblk2, M2, out2, nullptr},
+        c{partials3, nblk3, M3, out3, nullptr};
+    return launch_reduce_segs(a, b, c, s);
+}
+
+hipError_t launch_ls_step(const PwParams& P, const StepArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(ls_step_kernel, dim3(1), dim3(64), 0, s, P, a);
     return hipGetLastError();
 }
 

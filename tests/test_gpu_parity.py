@@ -296,6 +296,46 @@ def test_solve_c2_droplet(solver):
         assert abs(a["E"] - b) <= 1e-11 * abs(b)
 
 
+# ---------------------------------------------------------------- pipelined iterations
+# bec_solve pipelines each P_V / unpreconditioned iteration (the device decides
+# the step, the trial, the next residual sums and the next direction write; the
+# host checks afterwards) unless BEC_SOLVE_SYNCHRONOUS is set.  Both apply the
+# same rules to the same reduced sums, so the iterates agree bit for bit,
+# including the fallbacks for restarts, backtracking and stagnation.
+PIPE_CASES = [
+    ("C1b", {"pc": 1, "beta": 0}),
+    ("C1b", {"pc": 1, "beta": 1, "restart_period": 3}),
+    ("C1b", {"pc": 0, "beta": 0, "max_iter": 25}),
+    ("mixedN", {"pc": 1, "beta": 0}),
+    ("allclasses", {"pc": 1, "beta": 2}),
+    # a negative acceptance margin rejects trials: backtracks, beta = 0 retries, stagnation
+    ("C1b", {"pc": 1, "tau_rel": -2e-6, "max_backtrack": 2}),
+    ("C2", {"pc": 1, "max_iter": 40}),
+]
+
+
+@pytest.mark.parametrize("name,extra", PIPE_CASES, ids=[f"{n}-{i}" for i, (n, _) in enumerate(PIPE_CASES)])
+def test_pipelined_solve_is_bitwise_the_synchronous_one(solver, name, extra):
+    if name in CASES:
+        grid, params = CASES[name]
+        psi0 = _state(grid, params, 71, True)
+    else:
+        grid, params = inputs.CONFIGS[name]["grid"], inputs.CONFIGS[name]["params"]
+        psi0 = inputs.config_state(name)
+    ctx = solver.Context(grid, params)
+    opts = dict({"tol_grad": 1e-10, "max_iter": 60}, **extra)
+    pa, ra, la = ctx.solve(torch.from_numpy(psi0), dict(opts, flags=0), log_cap=200)
+    pb, rb, lb = ctx.solve(torch.from_numpy(psi0), dict(opts, flags=1), log_cap=200)
+    assert ra["iters"] > 0
+    for k in ("iters", "n_restarts", "n_backtracks", "status"):
+        assert ra[k] == rb[k], k
+    assert ra["final"] == rb["final"]
+    assert la == lb
+    assert torch.equal(pa, pb)
+    if extra.get("tau_rel", 0.0) < 0:
+        assert ra["n_backtracks"] > 0
+
+
 # ---------------------------------------------------------------- full size, sampled
 @pytest.mark.timeout(900)
 def test_headline_grid_first_iterations(solver, orc):
