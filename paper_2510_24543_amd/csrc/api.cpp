@@ -187,7 +187,6 @@ struct bec_ctx {
     double* dscal = nullptr;   // device copies of the scalars that later launches read (same offsets)
     double2* tw[3] = {};
     double* host = nullptr;   // pinned scalars
-    hipEvent_t mark = nullptr; // end of the part of a pipelined iteration the host waits for
     int nblk_pw = 0;
     int nblk_x = 0;
     int fft_var[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // plan variant per axis: [plain, fused k-space]
@@ -267,6 +266,39 @@ constexpr int kScalStep = 72;     // device step decision (kStepOut)
 static_assert(kScalHeval >= 32 && kScalHeval + bec::kHevalSums <= kScalDir, "scalar ranges overlap");
 static_assert(kScalDir + bec::kDirReduceSums <= kScalStep && kScalStep + bec::kStepOut <= kScalSlots,
               "scalar ranges overlap");
+
+// The host waits for the scalars of a pipelined iteration by watching the
+// pinned slots themselves: before the launches that write them it stores a
+// marker there, a signalling-NaN bit pattern, which no arithmetic result can
+// be (IEEE operations return quiet NaNs), and it reads a slot once the marker
+// is gone.  Each slot is one aligned 8-byte store, so no ordering between slots
+// is needed and no stream event is placed between the kernels.
+constexpr uint64_t kScalMarker = 0x7ff4dead5e7f11edull;
+struct ScalRange {
+    int lo, n;
+};
+
+void arm_scalars(double* host, const ScalRange* r, int nr)
+{
+    for (int k = 0; k < nr; ++k)
+        for (int i = r[k].lo; i < r[k].lo + r[k].n; ++i)
+            __atomic_store_n(reinterpret_cast<uint64_t*>(host + i), kScalMarker, __ATOMIC_RELAXED);
+    __atomic_thread_fence(__ATOMIC_SEQ_CST);
+}
+
+bool await_scalars(const double* host, const ScalRange* r, int nr, double timeout_s)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int k = 0; k < nr; ++k)
+        for (int i = r[k].lo; i < r[k].lo + r[k].n; ++i) {
+            const uint64_t* q = reinterpret_cast<const uint64_t*>(host + i);
+            for (unsigned spin = 1; __atomic_load_n(q, __ATOMIC_ACQUIRE) == kScalMarker; ++spin)
+                if ((spin & 0xfffu) == 0 &&
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > timeout_s)
+                    return false;
+        }
+    return true;
+}
 
 size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
 {
@@ -955,13 +987,7 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
             delete c;
             return fail(BEC_EHIP, "hipHostMalloc of the scalar buffer failed");
         }
-        if (hipEventCreateWithFlags(&c->mark, hipEventDisableTiming) != hipSuccess) {
-            (void)hipHostFree(c->host);
-            delete c;
-            return fail(BEC_EHIP, "hipEventCreate failed");
-        }
         if (hipHostGetDevicePointer((void**)&c->scal, c->host, 0) != hipSuccess) {
-            (void)hipEventDestroy(c->mark);
             (void)hipHostFree(c->host);
             delete c;
             return fail(BEC_EHIP, "hipHostGetDevicePointer of the scalar buffer failed");
@@ -980,15 +1006,13 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
             if (hipMemcpyAsync(c->tw[d], tw.data(), L * sizeof(double2), hipMemcpyHostToDevice, c->st) != hipSuccess ||
                 hipMemcpyAsync(c->kv[d], kv.data(), L * sizeof(double), hipMemcpyHostToDevice, c->st) != hipSuccess ||
                 hipStreamSynchronize(c->st) != hipSuccess) {
-                (void)hipEventDestroy(c->mark);
-                (void)hipHostFree(c->host);
+                    (void)hipHostFree(c->host);
                 delete c;
                 return fail(BEC_EHIP, "upload of FFT tables failed");
             }
         }
         bec_status st = upload_params(c, true);
         if (st != BEC_OK) {
-            (void)hipEventDestroy(c->mark);
             (void)hipHostFree(c->host);
             delete c;
             return st;
@@ -1102,7 +1126,6 @@ bec_status bec_destroy(bec_ctx* ctx)
     if (!ctx) return BEC_OK;
     (void)prof_flush(ctx);
     for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
-    if (ctx->mark) (void)hipEventDestroy(ctx->mark);
     if (ctx->host) (void)hipHostFree(ctx->host);
     delete ctx;
     return BEC_OK;
@@ -1345,6 +1368,13 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
                 A.zsign = -1.0;
                 bec::rule_proj(R, b, dV, A.c);
                 if (!(first && spec_write)) STCHK(dir_write_launch(c, A));
+                // the scalar slots the pipelined part writes: model, Parseval, energy, reduce, step
+                const ScalRange waits[] = {{kScalModel, bec::kDirWriteSums + bec::kLsEpiSums},
+                                           {kScalModel + kParsevalOut, 2},
+                                           {kScalHeval, bec::kHevalSums},
+                                           {kScalDir, bec::kDirReduceSums},
+                                           {kScalStep, bec::kStepOut}};
+                if (first && pipe) arm_scalars(c->host, waits, 5);
                 // 4. the closed-form step of the second-order model (Sec. V), decided on the device
                 STCHK(model_launch(c, ev.t.norm2, alpha_prev, o->theta_max));
                 if (first && pipe) {
@@ -1360,12 +1390,15 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
                     An.p_out = c->pold;
                     An.r_out = c->r_old;
                     STCHK(dir_reduce_launch(c, An));
-                    HIPCHK(hipEventRecord(c->mark, c->st));
                     An.rule = beta_rule(n + 1, true, rz_now);
                     An.dev_dir = c->dscal + kScalDir;
                     An.zsign = -1.0;
                     STCHK(dir_write_launch(c, An));
-                    HIPCHK(hipEventSynchronize(c->mark));
+                    if (!await_scalars(c->host, waits, 5, 120.0)) {
+                        HIPCHK(hipStreamSynchronize(c->st));   // reports a device error if there is one
+                        if (!await_scalars(c->host, waits, 5, 0.0))
+                            return fail(BEC_EHIP, "reduced scalars did not arrive");
+                    }
                     model_read(c, &m);
                     hs = heval_read(c, &tr);
                     std::memcpy(Rn, c->host + kScalDir, sizeof(Rn));

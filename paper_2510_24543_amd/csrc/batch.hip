@@ -40,13 +40,13 @@ __device__ __forceinline__ void bblock_store(const double (&acc)[M], double* par
 {
     __shared__ double sh[M][kPwThreads / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double v[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        double v = acc[m];
+    for (int m = 0; m < M; ++m) v[m] = acc[m];
+    wave_sum_down(v);
+    if (lane == 0)
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) sh[m][w] = v;
-    }
+        for (int m = 0; m < M; ++m) sh[m][w] = v[m];
     __syncthreads();
     if (threadIdx.x < M) {
         double s = 0.0;

@@ -16,6 +16,20 @@ constexpr int kPwMaxBlocks = 4096;   // largest grid of the pointwise kernels
 constexpr int kPwDefaultBlocks = 1024;
 constexpr int kMaxSums = 32;         // reduced scalars per pass
 
+// Butterfly sums over the 64 lanes of a wavefront for M values at once; lane 0
+// ends with the wavefront totals (the per-value order of additions is that of
+// M separate butterflies).  All M values step through the butterfly together,
+// so the lane exchanges of different values are in flight at the same time
+// instead of M dependent chains one after another.
+template <int M>
+__device__ __forceinline__ void wave_sum_down(double (&v)[M])
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] += __shfl_down(v[m], off, 64);
+}
+
 // Per-node table entry (kNodeStride doubles):
 //   [0] eta_11  [1] eta_22  [2] eta_12 eta_21  [3] w_q  [4] eta_12  [5] eta_21
 //   [6] 3u^2 - 1  [7] unused
@@ -217,10 +231,10 @@ hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hps
                        double mu0, double mu1, double s0, double s1, int projected, hipStream_t s);
 // Closed-form step of the second-order model (Sec. V) from the reduced model
 // sums, on the device, so the trial point can be enqueued before the host has
-// read them.  One thread; writes kStepOut values to out (device) and, when
-// non-null, out_host (host-mapped).
+// read them.  One thread; writes kStepOut values to out (device) and out_host
+// (host-mapped).
 struct StepArgs {
-    const double* D;              // kDirWriteSums direction-write sums
+    const double* D;              // kDirWriteSums direction-write sums (device)
     const double* LS;             // kLsEpiSums line-search epilogue sums
     const double* pars;           // 2 Parseval sums sum_k |k|^2/2 |FFT(p_i)|^2
     double dV, inv_n;             // cell volume, 1 / points

@@ -516,13 +516,10 @@ __global__ __launch_bounds__(NTHR) void fft_zinv_ls_kernel(FftPassArgs A, const 
     double* sh = reinterpret_cast<double*>(lds);
     const int lane = tid & 63, w = tid >> 6;
     __syncthreads();
+    wave_sum_down(acc);
+    if (lane == 0)
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        double x = acc[m];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-        if (lane == 0) sh[m * (NTHR / 64) + w] = x;
-    }
+        for (int m = 0; m < M; ++m) sh[m * (NTHR / 64) + w] = acc[m];
     __syncthreads();
     if (tid < M) {
         double s = 0.0;

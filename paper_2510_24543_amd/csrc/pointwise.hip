@@ -43,13 +43,13 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[M], doubl
 {
     __shared__ double sh[M][kPwThreads / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double v[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        double v = acc[m];
+    for (int m = 0; m < M; ++m) v[m] = acc[m];
+    wave_sum_down(v);
+    if (lane == 0)
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) sh[m][w] = v;
-    }
+        for (int m = 0; m < M; ++m) sh[m][w] = v[m];
     __syncthreads();
     if (threadIdx.x < M) {
         double s = 0.0;
@@ -490,16 +490,17 @@ __global__ __launch_bounds__(256) void reduce_final_kernel(RedSeg s1, RedSeg s2,
     }
 }
 
-// Closed-form step of the second-order model along the geodesic (Sec. V):
-// E'(0) and E''(0) from the model sums, alpha* = -E'/E'' when the model has a
-// minimum (else the previous step, else 0.1 / max|p_i|), capped at theta_max,
-// then the trial coefficients psi_i(alpha) = (cos th_i psi_i + sin th_i p_i/|p_i|)
-// / norm with th_i = alpha |p_i|.
+// Closed-form step of the second-order model along the geodesic (Sec. V), one
+// thread, from the reduced model sums: E'(0) and E''(0), alpha* = -E'/E'' when
+// the model has a minimum (else the previous step, else 0.1 / max|p_i|), capped
+// at theta_max, and the trial coefficients psi_i(alpha) = (cos th_i psi_i +
+// sin th_i p_i/|p_i|) / norm with th_i = alpha |p_i|.
 __global__ void ls_step_kernel(PwParams P, StepArgs A)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double dV = A.dV;
     const double* D = A.D;
+    const double* pars = A.pars;
     const double* LS = A.LS;
     double o[kStepOut];
     double rp = 0.0, E1 = 0.0, E2 = 0.0, pnorm[2], psip[2];
@@ -508,7 +509,7 @@ __global__ void ls_step_kernel(PwParams P, StepArgs A)
         psip[i] = dV * D[16 + i];
         rp += 2.0 * P.Nat[i] * dV * D[2 + i];
         E1 += 2.0 * P.Nat[i] * dV * D[4 + i];                                  // E'_i
-        const double pTp = dV * A.pars[i] * A.inv_n;                           // <p_i, T p_i> (Parseval)
+        const double pTp = dV * pars[i] * A.inv_n;                             // <p_i, T p_i> (Parseval)
         const double pn2 = pnorm[i] * pnorm[i];
         E2 += 2.0 * P.Nat[i] * (pTp + dV * D[8 + i] - pn2 * dV * D[6 + i]);    // one-body part of E''_ii
         for (int j = 0; j < 2; ++j) {
@@ -528,11 +529,12 @@ __global__ void ls_step_kernel(PwParams P, StepArgs A)
     if (alpha * pmax > A.theta_max) alpha = A.theta_max / pmax;
     for (int i = 0; i < 2; ++i) {
         if (pnorm[i] > 0.0) {
-            const double th = alpha * pnorm[i];
-            const double ca = cos(th), sb = sin(th) / pnorm[i];
-            const double nrm2 = ca * ca * A.norm2[i] + sb * sb * pnorm[i] * pnorm[i] + 2.0 * ca * sb * psip[i];
+            double sn, cs;
+            sincos(alpha * pnorm[i], &sn, &cs);
+            const double sb = sn / pnorm[i];
+            const double nrm2 = cs * cs * A.norm2[i] + sb * sb * pnorm[i] * pnorm[i] + 2.0 * cs * sb * psip[i];
             const double s = 1.0 / sqrt(nrm2);
-            o[i] = ca * s;
+            o[i] = cs * s;
             o[2 + i] = sb * s;
         } else {
             o[i] = 1.0 / sqrt(A.norm2[i]);
@@ -547,9 +549,10 @@ __global__ void ls_step_kernel(PwParams P, StepArgs A)
     o[9] = pnorm[1];
     o[10] = psip[0];
     o[11] = psip[1];
-    for (int m = 0; m < kStepOut; ++m) A.out[m] = o[m];
-    if (A.out_host)
-        for (int m = 0; m < kStepOut; ++m) A.out_host[m] = o[m];
+    for (int m = 0; m < kStepOut; ++m) {
+        A.out[m] = o[m];
+        A.out_host[m] = o[m];
+    }
 }
 
 int pw_blocks(const PwParams& P) { return P.nblk_pw; }
