@@ -86,8 +86,8 @@ typedef enum { BEC_BETA_HS_PLUS = 0, BEC_BETA_PR_PLUS = 1, BEC_BETA_ZERO = 2 } b
 
 /* bec_opts.flags.  BEC_SOLVE_SYNCHRONOUS: the host reads every reduced scalar
  * before it enqueues the launches that depend on it.  By default bec_solve
- * pipelines each iteration with P_V or no preconditioner: the device decides
- * the step, the trial, the next residual sums and the next direction write
+ * pipelines each iteration: the device decides the step, the trial, the next
+ * preconditioned residual, its reduce sums and the next direction write
  * from the reduced sums it has just produced, and the host waits once per
  * iteration and checks every decision against the same rules; restarts and
  * backtracking fall back to synchronous launches.  Both give the same iterates

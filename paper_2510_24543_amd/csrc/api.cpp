@@ -180,7 +180,7 @@ struct bec_ctx {
     // each pair, so a write enqueued ahead of the acceptance test leaves the
     // state that a rejected step falls back to intact
     double2 *pdir = nullptr, *pold = nullptr, *r_old = nullptr, *r_new = nullptr;
-    double2 *z = nullptr, *rho = nullptr, *W = nullptr;
+    double2 *z = nullptr, *z_next = nullptr, *rho = nullptr, *W = nullptr;   // z_next: a pipelined lookahead
     double *udtab = nullptr, *kv[3] = {}, *vv[3] = {}, *nodes = nullptr;
     double *partials = nullptr, *fft_partials = nullptr, *ls_partials = nullptr;
     double* scal = nullptr;    // device address of `host` (reduced scalars)
@@ -327,6 +327,7 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
         (size_t)bec::kLsEpiSums * nb_z * sizeof(double),                            // line-search partials
         2 * N * c2,                                                                 // pold
         2 * N * c2,                                                                 // r_new
+        2 * N * c2,                                                                 // z_next
     };
     size_t total = 0;
     for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); ++i) {
@@ -506,12 +507,17 @@ FftPassArgs pass_args(bec_ctx* c, int axis)
 }
 
 bec_status run_pass(bec_ctx* c, int axis, const double2* const* src, double2* const* dst, int nf, int sign,
-                    double scale, const int* ops, const double* prec_a)
+                    double scale, const int* ops, const double* prec_a, const double* prec_state = nullptr,
+                    double prec_sigma = 0.0)
 {
     FftPassArgs A = pass_args(c, axis);
     A.nfield = nf;
     A.sign = sign;
     A.scale = scale;
+    A.prec_state = prec_state;
+    A.prec_sigma = prec_sigma;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) A.prec_Gdd[i][j] = c->P.Gdd[i][j];
     for (int f = 0; f < nf; ++f) {
         A.src[f] = src[f];
         A.dst[f] = dst[f];
@@ -548,13 +554,15 @@ bec_status fft3d_plain(bec_ctx* c, const double2* const* src, double2* const* ds
 // Diagonal k-space operators on nf fields: forward z, y, then the fused x pass
 // (ops per field), then inverse y, z for the fields that are stored.
 // Parseval fields come first in the list (they end at the x pass).
-bec_status kspace_after_z(bec_ctx* c, double2* const* dst, int nf, const int* ops, const double* prec_a);
+bec_status kspace_after_z(bec_ctx* c, double2* const* dst, int nf, const int* ops, const double* prec_a,
+                          const double* prec_state = nullptr, double prec_sigma = 0.0);
 
+// prec_state / prec_sigma: kOpMulPrec shifts decided on the device (see FftPassArgs)
 bec_status kspace_apply(bec_ctx* c, const double2* const* src, double2* const* dst, int nf, const int* ops,
-                        const double* prec_a)
+                        const double* prec_a, const double* prec_state = nullptr, double prec_sigma = 0.0)
 {
     STCHK(run_pass(c, 2, src, dst, nf, -1, 1.0, nullptr, nullptr));
-    return kspace_after_z(c, dst, nf, ops, prec_a);
+    return kspace_after_z(c, dst, nf, ops, prec_a, prec_state, prec_sigma);
 }
 
 // The same for the three fields (psi_1, psi_2, packed density) of the trial
@@ -575,10 +583,11 @@ bec_status kspace_apply_trial(bec_ctx* c, const bec::TrialZArgs& Z, double2* con
     return kspace_after_z(c, dst, 3, ops, prec_a);
 }
 
-bec_status kspace_after_z(bec_ctx* c, double2* const* dst, int nf, const int* ops, const double* prec_a)
+bec_status kspace_after_z(bec_ctx* c, double2* const* dst, int nf, const int* ops, const double* prec_a,
+                          const double* prec_state, double prec_sigma)
 {
     STCHK(run_pass(c, 1, dst, dst, nf, -1, 1.0, nullptr, nullptr));
-    STCHK(run_pass(c, 0, dst, dst, nf, -1, 1.0, ops, prec_a));
+    STCHK(run_pass(c, 0, dst, dst, nf, -1, 1.0, ops, prec_a, prec_state, prec_sigma));
     int first = 0;
     while (first < nf && ops[first] == bec::kOpParseval) ++first;
     if (first < nf) {
@@ -735,9 +744,13 @@ bec_status dir_reduce(bec_ctx* c, const bec::DirArgs& A, double* R)
     return BEC_OK;
 }
 
-// z = P^-1 r into c->z for the kinetic / composite preconditioners.
-bec_status compute_z(bec_ctx* c, int set, const Eval& ev, const double2* rin, int apply_pv, double sigma)
+// z = P^-1 r into out (default c->z) for the kinetic / composite preconditioners;
+// with dev_state the chemical potentials and shifts come from those device
+// energy sums (a pipelined launch) instead of ev.
+bec_status compute_z(bec_ctx* c, int set, const Eval& ev, const double2* rin, int apply_pv, double sigma,
+                     double2* out = nullptr, const double* dev_state = nullptr)
 {
+    if (!out) out = c->z;
     bec::MakeRArgs m{};
     m.psi = c->psi[set];
     m.hpsi = c->hpsi[set];
@@ -749,14 +762,15 @@ bec_status compute_z(bec_ctx* c, int set, const Eval& ev, const double2* rin, in
     }
     m.sigma = sigma;
     m.apply_pv = apply_pv;
-    m.out = c->z;
+    m.out = out;
+    m.dev_state = dev_state;
     LAUNCH(c, "make_r", (double)c->N * 112.0, bec::launch_make_r(c->P, m, c->st));
     const long long N = c->N;
-    const double2* src[2] = {c->z, c->z + N};
-    double2* dst[2] = {c->z, c->z + N};
+    const double2* src[2] = {out, out + N};
+    double2* dst[2] = {out, out + N};
     const int ops[2] = {bec::kOpMulPrec, bec::kOpMulPrec};
     const double pa[2] = {std::max(ev.t.shift[0], 0.0) + sigma, std::max(ev.t.shift[1], 0.0) + sigma};
-    return kspace_apply(c, src, dst, 2, ops, pa);
+    return kspace_apply(c, src, dst, 2, ops, pa, dev_state, sigma);
 }
 
 struct Model {
@@ -965,6 +979,7 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
         c->r_old = (double2*)at(7);
         c->pold = (double2*)at(26);
         c->r_new = (double2*)at(27);
+        c->z_next = (double2*)at(28);
         c->dscal = (double*)at(24);
         c->z = (double2*)at(8);
         c->rho = (double2*)at(9);
@@ -1306,14 +1321,16 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
     bec_status status = BEC_ENOTCONV;
     double E_prev = NAN, alpha_prev = 0.0, rz_old = 0.0;
     const int zmode_pc = (o->pc == BEC_PC_V) ? 1 : (o->pc == BEC_PC_NONE ? 0 : (o->pc == BEC_PC_SYMMETRIC ? 3 : 2));
-    // Pipelined iterations (P_V or no preconditioner): the first trial of a step
-    // is enqueued at the step the device decides from the model sums, followed
-    // by the direction reduce of the trial state and, from there, the next
-    // direction write with the device's beta; the host waits once, for the part
-    // before that write, and checks every decision afterwards.  A step that
-    // needs a restart or a backtrack falls back to host-synchronised launches;
-    // the speculative write then only touched buffers the fallback rewrites.
-    const bool pipe = !(o->flags & BEC_SOLVE_SYNCHRONOUS) && zmode_pc <= 1;
+    // Pipelined iterations: the first trial of a step is enqueued at the step
+    // the device decides from the model sums, followed by the preconditioned
+    // residual (Fourier / composite preconditioners, into z_next) and the
+    // direction reduce of the trial state and, from there, the next direction
+    // write with the device's beta; the host waits once, for the part before
+    // that write, and checks every decision afterwards.  A step that needs a
+    // restart or a backtrack falls back to host-synchronised launches; the
+    // speculative work then only touched buffers the fallback rewrites.
+    const bool pipe = !(o->flags & BEC_SOLVE_SYNCHRONOUS);
+    const int pv_mode = o->pc == BEC_PC_COMPOSITE ? 1 : (o->pc == BEC_PC_SYMMETRIC ? 2 : 0);
     auto beta_rule = [&](int iter, bool prev, double rz_prev) {
         bec::BetaRule br{};
         br.restart = !prev || o->beta == BEC_BETA_ZERO || (o->restart_period > 0 && iter % o->restart_period == 0);
@@ -1330,9 +1347,7 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
 
     for (;;) {
         // 1. residual, preconditioned residual and the conjugacy sums
-        if (zmode_pc >= 2)
-            STCHK(compute_z(c, cur, ev, nullptr,
-                            o->pc == BEC_PC_COMPOSITE ? 1 : (o->pc == BEC_PC_SYMMETRIC ? 2 : 0), o->sigma));
+        if (zmode_pc >= 2 && !R_ready) STCHK(compute_z(c, cur, ev, nullptr, pv_mode, o->sigma));
         bec::DirArgs A = dir_args(c, cur, ev, zmode_pc, o->sigma);
         A.have_prev = have_prev;
         if (!R_ready) STCHK(dir_reduce(c, A, R));
@@ -1389,6 +1404,10 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
                     An.p = c->pdir;
                     An.p_out = c->pold;
                     An.r_out = c->r_old;
+                    if (zmode_pc >= 2) {   // z of the trial state into the spare buffer
+                        STCHK(compute_z(c, nxt, ev, nullptr, pv_mode, o->sigma, c->z_next, c->dscal + kScalHeval));
+                        An.zbuf = c->z_next;
+                    }
                     STCHK(dir_reduce_launch(c, An));
                     An.rule = beta_rule(n + 1, true, rz_now);
                     An.dev_dir = c->dscal + kScalDir;
@@ -1481,7 +1500,10 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
         ++n;
         // the speculative reduce and write were made for exactly this state
         R_ready = spec_write = next_ready;
-        if (next_ready) std::memcpy(R, Rn, sizeof(R));
+        if (next_ready) {
+            std::memcpy(R, Rn, sizeof(R));
+            std::swap(c->z, c->z_next);
+        }
     }
     HIPCHK(hipMemcpyAsync(psi_inout, c->psi[cur], 2 * c->N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
     HIPCHK(hipStreamSynchronize(c->st));

@@ -100,6 +100,12 @@ struct FftPassArgs {
     const int* active;
     int per_inst_tab;
     long long udsize;      // doubles per instance in udtab
+    // kOpMulPrec shift from device memory (pipelined launches): when
+    // prec_state is set, field f < 2 uses [shift_f]_+ + prec_sigma with
+    // shift_f = rule_mu_shift(prec_state, prec_Gdd) instead of prec_a[f]
+    const double* prec_state;
+    double prec_sigma;
+    double prec_Gdd[2][2];
 };
 
 // Forward z pass fused with the geodesic trial update: psi_dst = a_i psi_src +
@@ -210,6 +216,7 @@ struct MakeRArgs {                // out = r, P_V^-1 r (apply_pv 1) or D^-1/2 r 
     double sigma;
     int apply_pv;
     double2* out;                 // 2N
+    const double* dev_state;      // non-null: mu and diag_shift from these energy sums (rule_mu_shift)
 };
 
 struct ParamGradArgs {

@@ -317,7 +317,12 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
         __syncthreads();                               // lds is reused by the inverse transform
     }
     const double inv_n = A.inv_n;
-    const double pa = A.prec_a[f];
+    double pa = A.prec_a[f];
+    if (A.prec_state && op == kOpMulPrec && f < 2) {   // shift decided from device sums
+        double mu[2], sh[2];
+        rule_mu_shift(A.prec_state, A.prec_Gdd, mu, sh);
+        pa = (sh[f] < 0.0 ? 0.0 : sh[f]) + A.prec_sigma;
+    }
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll

@@ -350,6 +350,7 @@ __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirAr
 
 __global__ __launch_bounds__(kPwThreads) void make_r_kernel(PwParams P, MakeRArgs A)
 {
+    if (A.dev_state) rule_mu_shift(A.dev_state, P.Gdd, A.mu, A.diag_shift);
     const long long N = P.N;
     GRID_STRIDE(i, N)
     {

@@ -65,7 +65,7 @@ def test_workspace_size_and_validation():
     sz = C.c_size_t()
     p = B.make_params(PARAMS)
     assert L.bec_workspace_size(C.byref(grid()), C.byref(p), C.byref(sz)) == 0
-    assert 416 * 32 ** 3 < sz.value < 450 * 32 ** 3     # 26 complex fields of N points + tables
+    assert 448 * 32 ** 3 < sz.value < 480 * 32 ** 3     # 28 complex fields of N points + tables
     assert L.bec_workspace_size(C.byref(grid((30, 32, 32))), C.byref(p), C.byref(sz)) == 7
     assert b"not supported" in L.bec_last_error()
     bad = B.make_params(dict(PARAMS, n_u=0))

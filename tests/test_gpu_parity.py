@@ -297,7 +297,7 @@ def test_solve_c2_droplet(solver):
 
 
 # ---------------------------------------------------------------- pipelined iterations
-# bec_solve pipelines each P_V / unpreconditioned iteration (the device decides
+# bec_solve pipelines each iteration (the device decides
 # the step, the trial, the next residual sums and the next direction write; the
 # host checks afterwards) unless BEC_SOLVE_SYNCHRONOUS is set.  Both apply the
 # same rules to the same reduced sums, so the iterates agree bit for bit,
@@ -311,6 +311,11 @@ PIPE_CASES = [
     # a negative acceptance margin rejects trials: backtracks, beta = 0 retries, stagnation
     ("C1b", {"pc": 1, "tau_rel": -2e-6, "max_backtrack": 2}),
     ("C2", {"pc": 1, "max_iter": 40}),
+    ("C1b", {"pc": 2, "beta": 0}),
+    ("C1b", {"pc": 3, "beta": 1}),
+    ("C1b", {"pc": 4, "beta": 0}),
+    ("C2", {"pc": 3, "beta": 0, "max_iter": 80}),
+    ("C1b", {"pc": 3, "tau_rel": -2e-6, "max_backtrack": 2}),
 ]
 
 
