@@ -91,7 +91,7 @@ typedef enum { BEC_BETA_HS_PLUS = 0, BEC_BETA_PR_PLUS = 1, BEC_BETA_ZERO = 2 } b
  * from the reduced sums it has just produced, and the host waits once per
  * iteration and checks every decision against the same rules; restarts and
  * backtracking fall back to synchronous launches.  Both give the same iterates
- * bit for bit. */
+ * bit for bit.  Other bits are rejected (BEC_EINVAL). */
 #define BEC_SOLVE_SYNCHRONOUS 1
 
 typedef struct {

@@ -1305,6 +1305,7 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
 {
     if (!c || !psi_inout || !o) return fail(BEC_EINVAL, "null argument");
     if (o->pc < 0 || o->pc > 4 || o->beta < 0 || o->beta > 2) return fail(BEC_EINVAL, "bad options");
+    if (o->flags & ~BEC_SOLVE_SYNCHRONOUS) return fail(BEC_EINVAL, "unknown bits in opts.flags: 0x%x", o->flags);
     const auto t0 = std::chrono::steady_clock::now();
     const double dV = c->dV;
     const bec_params& p = c->p;

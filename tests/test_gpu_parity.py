@@ -412,6 +412,11 @@ def test_errors_are_reported(solver):
     bad[0, 3, 3, 3] = float("nan")
     with pytest.raises(B.BecError, match="ENONFINITE"):
         ctx.energy(bad)
+    with pytest.raises(B.BecError, match="ENONFINITE"):
+        ctx.solve(bad, {"max_iter": 5})
+    good = torch.from_numpy(_state(grid, params, 19, False)).cuda()
+    with pytest.raises(B.BecError, match="EINVAL"):
+        ctx.solve(good, {"max_iter": 5, "flags": 4})
     with pytest.raises(ValueError):
         ctx.energy(torch.zeros((2, 8, 8, 8), dtype=torch.complex128, device="cuda"))
 
