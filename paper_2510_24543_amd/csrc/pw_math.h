@@ -55,24 +55,26 @@ __device__ __forceinline__ void lhy_point(const Nodes& nodes, int n_a, int n_b, 
     const double n12x4 = 4.0 * n1 * n2;
     const double nn = n1 * n2;
     const double sqnn2 = nn > kTiny ? 2.0 * nn * rsq_nr(nn) : 0.0;      // 2 sqrt(n1 n2)
+    const double tn1 = 2.0 * n1, tn2 = 2.0 * n2;
+    // Class A without per-node guards: where sigma^2 <= kTiny every term of the
+    // node is below 1e-140 (r is taken at kTiny, so nothing overflows), and where
+    // s^2 <= kTiny the ratio term u t1 carries a factor u = s ds/dn of size
+    // sqrt(kTiny); both are below FP64 resolution against the other terms.
     for (int q = 0; q < n_a; ++q) {
         const double e11 = nodes(q, 0), e22 = nodes(q, 1), p12 = nodes(q, 2), w = nodes(q, 3), rq = nodes(q, 4);
         const double a = e11 * n1, b = e22 * n2, delta = a - b;
         const double pi = sqnn2 * rq;
         const double x = 2.0 * (a + b + pi);                            // sigma^2
-        const bool ok = x > kTiny;
-        const double r = rsq_nr(ok ? x : 1.0);                         // 1/sigma
+        const double r = rsq_nr(fmax(x, kTiny));                       // 1/sigma
         const double sg = x * r;
-        const double wq = ok ? w : 0.0;
-        const double ss = fma(delta, delta, p12 * n12x4);
-        const double t1 = ss > kTiny ? 2.0 * (x - pi) * r : 0.0;       // 2 (sigma^2 - pi)/sigma
-        const double t3 = sg * (x - 3.0 * pi);                          // a^3 + b^3
-        const double e5 = sg * fma(x, x - 5.0 * pi, 5.0 * pi * pi);     // a^5 + b^5
-        const double u1 = fma(e11, delta, 2.0 * p12 * n2);              // s ds/dn1
-        const double u2 = fma(-e22, delta, 2.0 * p12 * n1);             // s ds/dn2
-        ae = fma(wq, e5, ae);
-        a1 = fma(wq, fma(e11, t3, u1 * t1), a1);
-        a2 = fma(wq, fma(e22, t3, u2 * t1), a2);
+        const double t1 = (x - pi) * (r + r);                           // 2 (sigma^2 - pi)/sigma
+        const double t3 = sg * fma(-3.0, pi, x);                        // a^3 + b^3
+        const double e5 = sg * fma(x, fma(-5.0, pi, x), 5.0 * pi * pi); // a^5 + b^5
+        const double u1 = fma(e11, delta, p12 * tn2);                   // s ds/dn1
+        const double u2 = fma(-e22, delta, p12 * tn1);                  // s ds/dn2
+        ae = fma(w, e5, ae);
+        a1 = fma(w, fma(e11, t3, u1 * t1), a1);
+        a2 = fma(w, fma(e22, t3, u2 * t1), a2);
     }
     for (int q = n_a; q < n_a + n_b; ++q) {
         const double e11 = nodes(q, 0), e22 = nodes(q, 1), p12 = nodes(q, 2), w = nodes(q, 3);
@@ -121,19 +123,20 @@ __device__ __forceinline__ void lhy_model(const Nodes& nodes, int n_a, int n_b, 
         const double lin = fma(e11, n1p, e22 * n2p);
         const double pi = sqnn2 * rq;
         const double x = 2.0 * (a + b + pi);
-        const bool ok = x > kTiny;
-        const double r = rsq_nr(ok ? x : 1.0);
+        // no guard on sigma^2 <= kTiny (see lhy_point); the s^2 <= kTiny rule
+        // stays, since B t1 is not small there
+        const double r = rsq_nr(fmax(x, kTiny));
         const double sg = x * r;
-        const double wq = ok ? w : 0.0;
         const double ss = fma(delta, delta, p12 * n12x4);
         const bool sp = ss > kTiny;
         const double A = sp ? fma(delta, d1, p12 * cross) : 0.0;
-        const double B0 = fma(d1, d1, p12 * pp4);
+        const double B0 = sp ? fma(d1, d1, p12 * pp4) : 0.0;
         const double t1 = (x - pi) * r;                                 // (sigma^2 - pi)/sigma
-        const double t3 = sg * (x - 3.0 * pi);
-        s1 = fma(wq, fma(lin, t3, 2.0 * A * t1), s1);
-        const double v2 = sp ? fma(B0, t1, -A * A * (r * r * r)) : 0.0;
-        s2acc = fma(wq, v2 + fma(0.75 * sg * lin, lin, 3.0 * lin * A * r), s2acc);
+        const double t3 = sg * fma(-3.0, pi, x);
+        const double Ar = A * r;
+        s1 = fma(w, fma(lin, t3, (A + A) * t1), s1);
+        const double v2 = fma(B0, t1, -Ar * Ar * r);
+        s2acc = fma(w, v2 + lin * fma(0.75 * sg, lin, 3.0 * Ar), s2acc);
     }
     for (int q = n_a; q < n_a + n_b; ++q) {
         const double e11 = nodes(q, 0), e22 = nodes(q, 1), p12 = nodes(q, 2), w = nodes(q, 3);
