@@ -268,12 +268,19 @@ bec_status bec_batch_solve(bec_batch* b, double* const* psi_inout, const bec_opt
  * pencil, radix order, workgroup size); the pointwise kernels have a grid size.
  * The autotuner (paper_2510_24543_amd/autotune.py) times the choices with
  * bec_time_fft_pass / full iterations and sets the fastest with
- * bec_set_tuning.  Results are identical up to rounding order for every choice.
+ * bec_set_tuning.  Results are identical up to rounding order for every FFT
+ * variant and grid size; the LHY table agrees with the node loop to about 1e-14
+ * of the LHY terms.
  * ------------------------------------------------------------------------- */
 typedef struct {
     int32_t fft_variant[3][2];  /* per axis (x, y, z): [0] plain passes, [1] the x pass with the fused
                                    k-space operator (only [0][1] is used); 0 = default plan */
     int32_t pw_blocks;          /* workgroups of the pointwise kernels (64 .. 4096) */
+    int32_t lhy_table;          /* 1 (default): the class-A part of the LHY node sum from Chebyshev
+                                   series of its restriction to n1 + n2 = 1 (it is homogeneous of
+                                   degree 5/2), when those series match the node sum to 2e-14 of
+                                   its range at creation; 0: the node loop */
+    int32_t lhy_terms;          /* out: terms per series in use (0: node loop); ignored on set */
 } bec_tuning;
 
 bec_status bec_get_tuning(bec_ctx* ctx, bec_tuning* out_h);

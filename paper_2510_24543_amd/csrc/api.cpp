@@ -187,6 +187,10 @@ struct bec_ctx {
     double* dscal = nullptr;   // device copies of the scalars that later launches read (same offsets)
     double2* tw[3] = {};
     double* host = nullptr;   // pinned scalars
+    double* lhytab = nullptr;  // class-A LHY Chebyshev series (device, 3 * kLhyTabMax)
+    std::vector<double> lhy_host = std::vector<double>(3 * bec::kLhyTabMax, 0.0);
+    int lhy_K_built = 0;       // terms per series of the built table (0: none met the bar)
+    int lhy_table_on = 1;      // tuning: use the table when built
     int nblk_pw = 0;
     int nblk_x = 0;
     int fft_var[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // plan variant per axis: [plain, fused k-space]
@@ -328,6 +332,7 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
         2 * N * c2,                                                                 // pold
         2 * N * c2,                                                                 // r_new
         2 * N * c2,                                                                 // z_next
+        3 * bec::kLhyTabMax * sizeof(double),                                       // LHY table
     };
     size_t total = 0;
     for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); ++i) {
@@ -396,6 +401,106 @@ void hot_nodes(const bec_params& p, const std::vector<double>& u, const std::vec
     *n_b = (int)B.size();
 }
 
+// Class-A sums at (n1, n2) = (x, 1 - x) in long double: f = F, f' = dF/dx along
+// (1, -1) = (5/2)(a1 - a2), f'' = 5 times the model sum along n' = (1, -1), from
+// the node formulas of the device loops (pw_math.h), without their guards.
+struct ClassAVals {
+    long double f, f1, f2;
+};
+ClassAVals class_a_sums(const double node5[][5], int n_a, long double n1, long double n2)
+{
+    ClassAVals o{0.0L, 0.0L, 0.0L};
+    long double A1 = 0.0L, A2 = 0.0L, S2 = 0.0L;
+    const long double sq = 2.0L * sqrtl(n1 * n2);
+    for (int q = 0; q < n_a; ++q) {
+        const long double e11 = node5[q][0], e22 = node5[q][1], p12 = node5[q][2], w = node5[q][3], rq = node5[q][4];
+        const long double a = e11 * n1, b = e22 * n2, delta = a - b, pi = sq * rq;
+        const long double X = 2.0L * (a + b + pi);
+        if (!(X > 1e-300L)) continue;   // the node vanishes there with its derivatives
+        const long double r = 1.0L / sqrtl(X), sg = X * r;
+        const long double t1 = 2.0L * (X - pi) * r, t3 = sg * (X - 3.0L * pi);
+        o.f += w * sg * (X * (X - 5.0L * pi) + 5.0L * pi * pi);
+        A1 += w * (e11 * t3 + (e11 * delta + 2.0L * p12 * n2) * t1);
+        A2 += w * (e22 * t3 + (-e22 * delta + 2.0L * p12 * n1) * t1);
+        const long double d1 = e11 + e22, lin = e11 - e22, cross = 2.0L * (n2 - n1);
+        const long double A = delta * d1 + p12 * cross, B0 = d1 * d1 - 4.0L * p12;
+        S2 += w * (B0 * (X - pi) * r - A * A * r * r * r + 0.75L * sg * lin * lin + 3.0L * lin * A * r);
+    }
+    o.f1 = 2.5L * (A1 - A2);
+    o.f2 = 5.0L * S2;
+    return o;
+}
+
+// Chebyshev series of f, f', f'' in y = (sqrt x - sqrt(1-x))/(sqrt x + sqrt(1-x))
+// (x = (1+y)^2 / (2 (1+y^2))): the smallest K in 24, 32, ..., kLhyTabMax whose
+// series, summed in double as on the device, stay within 2e-14 of the long-double
+// sums (relative to each function's largest value) at 257 points of [-1, 1].
+// Returns K, or 0 when no K meets that bar (the device keeps the node loop).
+int build_lhy_table(const double node5[][5], int n_a, double* coef /* 3 * kLhyTabMax */)
+{
+    std::fill(coef, coef + 3 * bec::kLhyTabMax, 0.0);
+    if (n_a == 0) return 0;
+    auto x_of = [](long double y, long double* x1, long double* x2) {
+        const long double d = 2.0L * (1.0L + y * y);
+        *x1 = (1.0L + y) * (1.0L + y) / d;
+        *x2 = (1.0L - y) * (1.0L - y) / d;
+    };
+    constexpr int M = 257;
+    std::vector<ClassAVals> ref(M);
+    long double fmax[3] = {0.0L, 0.0L, 0.0L};
+    for (int m = 0; m < M; ++m) {
+        long double x1, x2;
+        x_of(cosl(kPiL * m / (M - 1)), &x1, &x2);
+        ref[m] = class_a_sums(node5, n_a, x1, x2);
+        fmax[0] = std::max(fmax[0], fabsl(ref[m].f));
+        fmax[1] = std::max(fmax[1], fabsl(ref[m].f1));
+        fmax[2] = std::max(fmax[2], fabsl(ref[m].f2));
+    }
+    for (int K = 24; K <= bec::kLhyTabMax; K += 8) {
+        std::vector<ClassAVals> v(K);
+        for (int k = 0; k < K; ++k) {
+            long double x1, x2;
+            x_of(cosl(kPiL * (k + 0.5L) / K), &x1, &x2);
+            v[k] = class_a_sums(node5, n_a, x1, x2);
+        }
+        std::vector<double> c(3 * bec::kLhyTabMax, 0.0);
+        for (int j = 0; j < K; ++j) {
+            long double s0 = 0.0L, s1 = 0.0L, s2 = 0.0L;
+            for (int k = 0; k < K; ++k) {
+                const long double t = cosl(kPiL * j * (k + 0.5L) / K);
+                s0 += v[k].f * t;
+                s1 += v[k].f1 * t;
+                s2 += v[k].f2 * t;
+            }
+            const long double sc = (j == 0 ? 1.0L : 2.0L) / K;
+            c[j] = (double)(sc * s0);
+            c[bec::kLhyTabMax + j] = (double)(sc * s1);
+            c[2 * bec::kLhyTabMax + j] = (double)(sc * s2);
+        }
+        bool ok = true;
+        for (int m = 0; m < M && ok; ++m) {
+            const double y = (double)cosl(kPiL * m / (M - 1));
+            const long double want[3] = {ref[m].f, ref[m].f1, ref[m].f2};
+            for (int sidx = 0; sidx < 3 && ok; ++sidx) {
+                const double* cs = c.data() + sidx * bec::kLhyTabMax;
+                double pp = 0.0, qq = 0.0;   // the device's order (lhy_cheb in pw_math.h)
+                for (int k = K - 1; k >= 2; k -= 2) {
+                    qq = std::fma(y + y, pp, cs[k] - qq);
+                    pp = std::fma(y + y, qq, cs[k - 1] - pp);
+                }
+                const double b1 = std::fma(y + y, pp, cs[1] - qq);
+                const double got = std::fma(y, b1, cs[0] - pp);
+                if (!(fabsl((long double)got - want[sidx]) <= 2e-14L * fmax[sidx])) ok = false;
+            }
+        }
+        if (ok) {
+            std::copy(c.begin(), c.end(), coef);
+            return K;
+        }
+    }
+    return 0;
+}
+
 // Host tables that depend on the parameters: quadrature nodes, couplings,
 // trap, dipolar kernel.  Uploads asynchronously, then synchronises.
 bec_status upload_params(bec_ctx* c, bool dipolar_table)
@@ -418,6 +523,10 @@ bec_status upload_params(bec_ctx* c, bool dipolar_table)
     }
     hot_nodes(p, u, w, c->P.node5, &c->P.n_a, &c->P.n_b);
     HIPCHK(hipMemcpyAsync(c->nodes, nodes.data(), nodes.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+    // the host copy outlives the upload: the function synchronises below
+    c->lhy_K_built = p.c_lhy != 0.0 ? build_lhy_table(c->P.node5, c->P.n_a, c->lhy_host.data()) : 0;
+    HIPCHK(hipMemcpyAsync(c->lhytab, c->lhy_host.data(), c->lhy_host.size() * sizeof(double), hipMemcpyHostToDevice,
+                          c->st));
     std::vector<double> vv[3];
     for (int d = 0; d < 3; ++d) {
         vv[d].resize(c->n[d]);
@@ -462,6 +571,8 @@ bec_status upload_params(bec_ctx* c, bool dipolar_table)
     P.K3 = p.c_lhy / (3.0 * std::sqrt(2.0) * M_PI * M_PI);
     P.n_u = p.n_u;
     P.lhy_on = p.c_lhy != 0.0;
+    P.lhy_tab = c->lhytab;
+    P.lhy_K = c->lhy_table_on ? c->lhy_K_built : 0;
     P.nodes = c->nodes;
     P.vx = c->vv[0];
     P.vy = c->vv[1];
@@ -980,6 +1091,7 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
         c->pold = (double2*)at(26);
         c->r_new = (double2*)at(27);
         c->z_next = (double2*)at(28);
+        c->lhytab = (double*)at(29);
         c->dscal = (double*)at(24);
         c->z = (double2*)at(8);
         c->rho = (double2*)at(9);
@@ -1045,6 +1157,8 @@ bec_status bec_get_tuning(bec_ctx* c, bec_tuning* t)
     for (int a = 0; a < 3; ++a)
         for (int k = 0; k < 2; ++k) t->fft_variant[a][k] = c->fft_var[a][k];
     t->pw_blocks = c->nblk_pw;
+    t->lhy_table = c->lhy_table_on;
+    t->lhy_terms = c->P.lhy_K;
     return BEC_OK;
 }
 
@@ -1061,6 +1175,8 @@ bec_status bec_set_tuning(bec_ctx* c, const bec_tuning* t)
         for (int k = 0; k < 2; ++k) c->fft_var[a][k] = t->fft_variant[a][k];
     c->nblk_pw = t->pw_blocks;
     c->P.nblk_pw = c->nblk_pw;
+    c->lhy_table_on = t->lhy_table != 0;
+    c->P.lhy_K = c->lhy_table_on ? c->lhy_K_built : 0;
     c->nblk_x = bec::fft_blocks(c->n[0], c->fft_var[0][1], (long long)c->n[1] * c->n[2]);
     return BEC_OK;
 }

@@ -15,6 +15,7 @@ constexpr int kPwThreads = 256;      // threads per block of the pointwise kerne
 constexpr int kPwMaxBlocks = 4096;   // largest grid of the pointwise kernels
 constexpr int kPwDefaultBlocks = 1024;
 constexpr int kMaxSums = 32;         // reduced scalars per pass
+constexpr int kLhyTabMax = 64;       // terms per Chebyshev series of the class-A LHY table
 
 // Butterfly sums over the 64 lanes of a wavefront for M values at once; lane 0
 // ends with the wavefront totals (the per-value order of additions is that of
@@ -45,6 +46,8 @@ struct PwParams {
     double K3;                 // c_lhy /(3 sqrt(2) pi^2)   (derivatives)
     int n_u;
     int lhy_on;                // c_lhy != 0
+    const double* lhy_tab;     // class-A Chebyshev series (see pw_math.h), lhy_K terms each; lhy_K = 0: node loop
+    int lhy_K;
     const double* nodes;       // n_u * kNodeStride (device copy, used by the non-hot kernels)
     // hot-loop copy of (eta_11, eta_22, eta_12 eta_21, w_q, sqrt(det_q)) per
     // node, class-A nodes first (n_a), then class-B nodes (n_b) (see

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kPwThreads) void heval_epi_kernel(PwParams P, Heval
         const double n1 = sq2(s1), n2 = sq2(s2);
         const double V = trap_at(P, i);
         double e = 0.0, d1 = 0.0, d2 = 0.0;
-        if (P.lhy_on) lhy_point(KernargNodes{P}, P.n_a, P.n_b, P.K5, P.K3, n1, n2, e, d1, d2);
+        if (P.lhy_on) lhy_point(KernargNodes{P}, LhyTab{P.lhy_tab, P.lhy_K}, P.n_a, P.n_b, P.K5, P.K3, n1, n2, e, d1, d2);
         const double m1 = d1 / P.Nat[0], m2 = d2 / P.Nat[1];
         const double U1 = V + P.G[0][0] * n1 + P.G[0][1] * n2 + P.Gdd[0][0] * ph.x + P.Gdd[0][1] * ph.y + m1;
         const double U2 = V + P.G[1][0] * n1 + P.G[1][1] * n2 + P.Gdd[1][0] * ph.x + P.Gdd[1][1] * ph.y + m2;
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kPwThreads) void ite_epi_kernel(PwParams P, IteArgs
         const double n1 = sq2(s1), n2 = sq2(s2);
         const double V = trap_at(P, i);
         double e = 0.0, d1 = 0.0, d2 = 0.0;
-        if (P.lhy_on) lhy_point(KernargNodes{P}, P.n_a, P.n_b, P.K5, P.K3, n1, n2, e, d1, d2);
+        if (P.lhy_on) lhy_point(KernargNodes{P}, LhyTab{P.lhy_tab, P.lhy_K}, P.n_a, P.n_b, P.K5, P.K3, n1, n2, e, d1, d2);
         const double U1 = V + P.G[0][0] * n1 + P.G[0][1] * n2 + P.Gdd[0][0] * ph.x + P.Gdd[0][1] * ph.y + d1 / P.Nat[0];
         const double U2 = V + P.G[1][0] * n1 + P.G[1][1] * n2 + P.Gdd[1][0] * ph.x + P.Gdd[1][1] * ph.y + d2 / P.Nat[1];
         const double f1 = exp(-A.dt * U1), f2 = exp(-A.dt * U2);
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirAr
         A.rho[i] = make_double2(rho[0], rho[1]);
         if (P.lhy_on) {
             double L1, L2;
-            lhy_model(KernargNodes{P}, P.n_a, P.n_b, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
+            lhy_model(KernargNodes{P}, LhyTab{P.lhy_tab, P.lhy_K}, P.n_a, P.n_b, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
             acc[14] += L1;
             acc[15] += L2;
         }

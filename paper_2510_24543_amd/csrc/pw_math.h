@@ -43,24 +43,78 @@ __device__ __forceinline__ double rsq_nr(double x)
 // where s^2 <= kTiny.
 constexpr int kNodeVals = 5;
 
+// The class-A part of the node sum, F(n1, n2) = sum_q w_q sum_+- V_+-^(5/2) over
+// the class-A nodes, is homogeneous of degree 5/2 (V is linear in n), so
+// F = R^(5/2) f(x) with R = n1 + n2 and x = n1 / R.  The host can tabulate f, f'
+// and f'' as Chebyshev series in y = (sqrt n1 - sqrt n2)/(sqrt n1 + sqrt n2) =
+// (n1 - n2)/(R + 2 sqrt(n1 n2)), in which they are analytic on [-1, 1] (the
+// V_-^(5/2) endpoint terms become polynomial), and checks the series against the
+// node sum; then the point evaluations below replace the class-A loop (3 series
+// of K <= kLhyTabMax terms instead of n_a nodes).  The class-B loop is unchanged.
+struct LhyTab {
+    const double* c;   // series s at c[s * kLhyTabMax + k], s = 0 f, 1 f', 2 f''
+    int K;             // terms per series; 0: no table (class-A loop)
+};
+
+// Clenshaw sums of the first NS series at y; the coefficients are uniform across
+// the wavefront and read through the scalar cache (constant address space).
+template <int NS>
+__device__ __forceinline__ void lhy_cheb(const LhyTab& T, double y, double (&g)[NS])
+{
+    using cptr = const __attribute__((address_space(4))) double*;
+    const cptr c = (cptr)T.c;
+    // b_k = c_k + 2y b_(k+1) - b_(k+2), two terms per trip with the roles of the
+    // two registers alternating (no copies); K is even, so K - 2 terms run in
+    // pairs and b_1 is the last step before f = c_0 + y b_1 - b_2
+    double p[NS], q[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) p[s] = q[s] = 0.0;
+    const double y2 = y + y;
+    for (int k = T.K - 1; k >= 2; k -= 2)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            q[s] = fma(y2, p[s], c[s * kLhyTabMax + k] - q[s]);        // b_k
+            p[s] = fma(y2, q[s], c[s * kLhyTabMax + k - 1] - p[s]);    // b_(k-1)
+        }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const double b1 = fma(y2, p[s], c[s * kLhyTabMax + 1] - q[s]);  // p = b_2 here
+        g[s] = fma(y, b1, c[s * kLhyTabMax] - p[s]);
+    }
+}
+
 // LHY energy density e and de/dn_i at one point.  Values below kTiny are
 // treated as 0: their contributions (V^(3/2) < 1e-435) are below FP64
 // resolution.  Branch-free: masks instead of divergent ifs.
 // Nodes: any type with operator()(q, k) giving the k-th table value of node q.
 template <class Nodes>
-__device__ __forceinline__ void lhy_point(const Nodes& nodes, int n_a, int n_b, double K5, double K3, double n1,
-                                          double n2, double& e, double& d1, double& d2)
+__device__ __forceinline__ void lhy_point(const Nodes& nodes, const LhyTab& tab, int n_a, int n_b, double K5,
+                                          double K3, double n1, double n2, double& e, double& d1, double& d2)
 {
     double ae = 0.0, a1 = 0.0, a2 = 0.0;
     const double n12x4 = 4.0 * n1 * n2;
     const double nn = n1 * n2;
     const double sqnn2 = nn > kTiny ? 2.0 * nn * rsq_nr(nn) : 0.0;      // 2 sqrt(n1 n2)
     const double tn1 = 2.0 * n1, tn2 = 2.0 * n2;
+    if (tab.K > 0) {   // class A from the table: F, and dF/dn_i = R^(3/2) (5/2 f + (1 - x) f', 5/2 f - x f')
+        const double R = n1 + n2;
+        if (R > kTiny) {
+            const double rr = rsq_nr(R), sR = R * rr, iR = rr * rr, R32 = R * sR;
+            const double y = (n1 - n2) / (R + sqnn2);
+            const double x1 = n1 * iR, x2 = n2 * iR;
+            double g[2];
+            lhy_cheb<2>(tab, y, g);
+            ae = R * R32 * g[0];
+            a1 = 0.4 * R32 * fma(2.5, g[0], x2 * g[1]);      // the loop's sums are (2/5) dF/dn_i
+            a2 = 0.4 * R32 * fma(2.5, g[0], -x1 * g[1]);
+        }
+    }
     // Class A without per-node guards: where sigma^2 <= kTiny every term of the
     // node is below 1e-140 (r is taken at kTiny, so nothing overflows), and where
     // s^2 <= kTiny the ratio term u t1 carries a factor u = s ds/dn of size
     // sqrt(kTiny); both are below FP64 resolution against the other terms.
-    for (int q = 0; q < n_a; ++q) {
+    const int na_loop = tab.K > 0 ? 0 : n_a;
+    for (int q = 0; q < na_loop; ++q) {
         const double e11 = nodes(q, 0), e22 = nodes(q, 1), p12 = nodes(q, 2), w = nodes(q, 3), rq = nodes(q, 4);
         const double a = e11 * n1, b = e22 * n2, delta = a - b;
         const double pi = sqnn2 * rq;
@@ -109,14 +163,31 @@ __device__ __forceinline__ void lhy_point(const Nodes& nodes, int n_a, int n_b, 
 //                                     + 3/4 sigma lin^2 + 3 lin A / sigma,
 // free of 1/s (and of the cancellation it carries where s is small).
 template <class Nodes>
-__device__ __forceinline__ void lhy_model(const Nodes& nodes, int n_a, int n_b, double n1, double n2, double n1p,
-                                          double n2p, double& L1, double& L2)
+__device__ __forceinline__ void lhy_model(const Nodes& nodes, const LhyTab& tab, int n_a, int n_b, double n1,
+                                          double n2, double n1p, double n2p, double& L1, double& L2)
 {
     double s1 = 0.0, s2acc = 0.0;
     const double n12x4 = 4.0 * n1 * n2, cross = 2.0 * (n1 * n2p + n1p * n2), pp4 = 4.0 * n1p * n2p;
     const double nn = n1 * n2;
     const double sqnn2 = nn > kTiny ? 2.0 * nn * rsq_nr(nn) : 0.0;
-    for (int q = 0; q < n_a; ++q) {
+    if (tab.K > 0) {   // class A from the table: (2/5) dF/ds and (1/5) d^2F/ds^2 along (n1', n2')
+        const double R = n1 + n2;
+        if (R > kTiny) {
+            const double rr = rsq_nr(R), sR = R * rr, iR = rr * rr, R32 = R * sR;
+            const double y = (n1 - n2) / (R + sqnn2);
+            const double x1 = n1 * iR, x2 = n2 * iR;
+            double g[3];
+            lhy_cheb<3>(tab, y, g);
+            // F_1 = R^(3/2) h1, F_2 = R^(3/2) h2; Hessian R^(1/2) (H11, H12, H22)
+            const double h1 = fma(2.5, g[0], x2 * g[1]), h2 = fma(2.5, g[0], -x1 * g[1]);
+            const double q1 = fma(1.5, g[1], x2 * g[2]), q2 = fma(1.5, g[1], -x1 * g[2]);
+            const double H11 = fma(1.5, h1, x2 * q1), H12 = fma(1.5, h1, -x1 * q1), H22 = fma(1.5, h2, -x1 * q2);
+            s1 = 0.4 * R32 * fma(h1, n1p, h2 * n2p);
+            s2acc = 0.2 * sR * fma(H11 * n1p, n1p, n2p * fma(2.0 * H12, n1p, H22 * n2p));
+        }
+    }
+    const int na_loop = tab.K > 0 ? 0 : n_a;
+    for (int q = 0; q < na_loop; ++q) {
         const double e11 = nodes(q, 0), e22 = nodes(q, 1), p12 = nodes(q, 2), w = nodes(q, 3), rq = nodes(q, 4);
         const double a = e11 * n1, b = e22 * n2, delta = a - b;
         const double d1 = e11 * n1p - e22 * n2p;

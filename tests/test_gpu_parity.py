@@ -178,6 +178,36 @@ def test_energy_is_bitwise_repeatable(solver):
     assert a == b
 
 
+# ---------------------------------------------------------------- LHY table
+# The class-A part of the LHY node sum can come from Chebyshev series of its
+# restriction to n1 + n2 = 1 (tuning lhy_table, on by default where the series
+# meet their 2e-14 bar at creation).  Table and node loop agree to ~1e-14 of the
+# LHY terms; the oracle parity tests above run with the table on.
+@pytest.mark.parametrize("case", ["C1b", "mixedN", "allclasses", "nu24_mixedN", "C2"])
+def test_lhy_table_matches_node_loop(solver, case):
+    grid, params = CASES[case]
+    psi = torch.from_numpy(_state(grid, params, 23, True)).cuda()
+    ctx = solver.Context(grid, params)
+    t = ctx.get_tuning()
+    assert t["lhy_table"] == 1 and t["lhy_terms"] in (24, 32, 40, 48, 56, 64)
+    h_tab, e_tab = ctx.hamiltonian(psi)
+    d = torch.from_numpy(_state(grid, params, 29, True)).cuda()
+    _, ls_tab = ctx.linesearch(psi, d)
+    ctx.set_tuning(dict(t, lhy_table=0))
+    assert ctx.get_tuning()["lhy_terms"] == 0
+    h_loop, e_loop = ctx.hamiltonian(psi)
+    _, ls_loop = ctx.linesearch(psi, d)
+    assert abs(e_tab["E_lhy"] - e_loop["E_lhy"]) <= 5e-14 * abs(e_loop["E_lhy"])
+    assert abs(e_tab["E"] - e_loop["E"]) <= 1e-14 * abs(e_loop["E"])
+    for i in range(2):
+        assert abs(e_tab["mu"][i] - e_loop["mu"][i]) <= 1e-13 * abs(e_loop["mu"][i])
+    assert rel(h_tab.cpu().numpy(), h_loop.cpu().numpy()) < 1e-13
+    for k in ("E1", "E2", "alpha"):
+        assert abs(ls_tab[k] - ls_loop[k]) <= 1e-12 * abs(ls_loop[k]), k
+    ctx.set_tuning(dict(t, lhy_table=1))
+    assert ctx.get_tuning()["lhy_terms"] == t["lhy_terms"]
+
+
 # ---------------------------------------------------------------- preconditioners
 @pytest.mark.parametrize("pc", [0, 1, 2, 3, 4])
 def test_preconditioners(solver, orc, pc):
