@@ -352,6 +352,8 @@ bec_status check_grid(const bec_grid* g)
         if (!(g->hi[d] > g->lo[d]) || !std::isfinite(g->lo[d]) || !std::isfinite(g->hi[d]))
             return fail(BEC_EINVAL, "axis %d: need finite lo < hi", d);
     }
+    if ((long long)g->n[0] * g->n[1] * g->n[2] >= (1LL << 31))   // 32-bit point indices in the kernels
+        return fail(BEC_EUNSUPPORTED, "more than 2^31 - 1 points per component");
     return BEC_OK;
 }
 
@@ -560,6 +562,8 @@ bec_status upload_params(bec_ctx* c, bool dipolar_table)
     P.ny = c->n[1];
     P.nz = c->n[2];
     P.N = c->N;
+    bec::div_magic((uint32_t)(c->n[1] * c->n[2]), &P.m_nyz, &P.s_nyz);
+    bec::div_magic((uint32_t)c->n[2], &P.m_nz, &P.s_nz);
     for (int i = 0; i < 2; ++i) {
         P.Nat[i] = p.N[i];
         for (int j = 0; j < 2; ++j) {

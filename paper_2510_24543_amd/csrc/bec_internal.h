@@ -17,6 +17,15 @@ constexpr int kPwDefaultBlocks = 1024;
 constexpr int kMaxSums = 32;         // reduced scalars per pass
 constexpr int kLhyTabMax = 64;       // terms per Chebyshev series of the class-A LHY table
 
+// multiplier and shift of the division by d of indices below 2^31 (see PwParams)
+inline void div_magic(uint32_t d, uint32_t* m, int* s)
+{
+    int l = 0;
+    while ((1ull << l) < d) ++l;
+    *s = 31 + l;
+    *m = (uint32_t)(((1ull << (31 + l)) + d - 1) / d);
+}
+
 // Butterfly sums over the 64 lanes of a wavefront for M values at once; lane 0
 // ends with the wavefront totals (the per-value order of additions is that of
 // M separate butterflies).  All M values step through the butterfly together,
@@ -55,6 +64,11 @@ struct PwParams {
     // through scalar loads
     int n_a, n_b;
     double node5[kMaxNodes][5];
+    // i / (ny nz) and r / nz for linear indices below 2^31 by multiply and shift:
+    // q = (i * m) >> s with m = ceil(2^(31 + l) / d), s = 31 + l, 2^l >= d (exact
+    // for every i < 2^31), set by div_magic on the host
+    uint32_t m_nyz, m_nz;
+    int s_nyz, s_nz;
     const double* vx;          // 1/2 omega_x^2 x^2 per x index
     const double* vy;
     const double* vz;

@@ -23,11 +23,11 @@ namespace {
 
 __device__ __forceinline__ double trap_at(const PwParams& P, long long i)
 {
-    const long long nyz = (long long)P.ny * P.nz;
-    const int ix = (int)(i / nyz);
-    const long long rem = i - (long long)ix * nyz;
-    const int iy = (int)(rem / P.nz);
-    const int iz = (int)(rem - (long long)iy * P.nz);
+    const uint32_t ii = (uint32_t)i;   // N < 2^31 (checked at creation)
+    const uint32_t ix = (uint32_t)(((uint64_t)ii * P.m_nyz) >> P.s_nyz);
+    const uint32_t rem = ii - ix * (uint32_t)(P.ny * P.nz);
+    const uint32_t iy = (uint32_t)(((uint64_t)rem * P.m_nz) >> P.s_nz);
+    const uint32_t iz = rem - iy * (uint32_t)P.nz;
     return P.vx[ix] + P.vy[iy] + P.vz[iz];
 }
 
