@@ -1821,6 +1821,7 @@ void instance_params(const bec_grid& gr, const bec_params& p, bec::BInstParams& 
     std::vector<double> u, w;
     gauss_legendre01(p.n_u, u, w);
     hot_nodes(p, u, w, P.node5, &P.n_a, &P.n_b);
+    P.lhy_K = P.lhy_on ? build_lhy_table(P.node5, P.n_a, P.lhytab) : 0;
 }
 
 bool same_shape(const bec_grid& a, const bec_grid& b) { return a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2]; }
@@ -2205,6 +2206,8 @@ bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_par
             g.nx = G.n[0];
             g.ny = G.n[1];
             g.nz = G.n[2];
+            bec::div_magic((uint32_t)(G.n[1] * G.n[2]), &g.m_nyz, &g.s_nyz);
+            bec::div_magic((uint32_t)G.n[2], &g.m_nz, &g.s_nz);
             g.N = G.N;
             g.nblk = G.nblk;
             g.ip = b->ip;

@@ -27,11 +27,11 @@ __device__ __forceinline__ void load_nodes(const BInstParams& P, double (*nd)[kN
 
 __device__ __forceinline__ double btrap(const BGroup& g, int l, long long i)
 {
-    const long long nyz = (long long)g.ny * g.nz;
-    const int ix = (int)(i / nyz);
-    const long long rem = i - (long long)ix * nyz;
-    const int iy = (int)(rem / g.nz);
-    const int iz = (int)(rem - (long long)iy * g.nz);
+    const uint32_t ii = (uint32_t)i;   // points per instance < 2^31 (checked at creation)
+    const uint32_t ix = (uint32_t)(((uint64_t)ii * g.m_nyz) >> g.s_nyz);
+    const uint32_t rem = ii - ix * (uint32_t)(g.ny * g.nz);
+    const uint32_t iy = (uint32_t)(((uint64_t)rem * g.m_nz) >> g.s_nz);
+    const uint32_t iz = rem - iy * (uint32_t)g.nz;
     return g.vx[(long long)l * g.nx + ix] + g.vy[(long long)l * g.ny + iy] + g.vz[(long long)l * g.nz + iz];
 }
 
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kPwThreads) void b_heval_epi_kernel(BGroup g)
         const double n1 = sq2(s1), n2 = sq2(s2);
         const double V = btrap(g, l, i);
         double e = 0.0, d1 = 0.0, d2 = 0.0;
-        if (lhy) lhy_point(nodes, LhyTab{nullptr, 0}, n_a, n_b, K5, K3, n1, n2, e, d1, d2);
+        if (lhy) lhy_point(nodes, LhyTab{P.lhytab, P.lhy_K}, n_a, n_b, K5, K3, n1, n2, e, d1, d2);
         const double m1 = d1 / P.Nat[0], m2 = d2 / P.Nat[1];
         const double U1 = V + P.G[0][0] * n1 + P.G[0][1] * n2 + P.Gdd[0][0] * ph.x + P.Gdd[0][1] * ph.y + m1;
         const double U2 = V + P.G[1][0] * n1 + P.G[1][1] * n2 + P.Gdd[1][0] * ph.x + P.Gdd[1][1] * ph.y + m2;
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kPwThreads) void b_dir_write_kernel(BGroup g)
         rho_o[i] = make_double2(rho[0], rho[1]);
         if (lhy) {
             double L1, L2;
-            lhy_model(nodes, LhyTab{nullptr, 0}, n_a, n_b, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
+            lhy_model(nodes, LhyTab{P.lhytab, P.lhy_K}, n_a, n_b, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
             acc[14] += L1;
             acc[15] += L2;
         }

@@ -311,6 +311,8 @@ struct BInstParams {
     int n_u, lhy_on;
     int n_a, n_b;                 // class-A / class-B node counts of node5
     double node5[kMaxNodes][5];
+    int lhy_K;                    // class-A LHY table terms per series (0: node loop), see pw_math.h
+    double lhytab[3 * kLhyTabMax];
 };
 
 enum : int { kBRunning = 0, kBConverged = 1, kBNotConv = 2, kBStagnated = 3, kBNonFinite = 4 };
@@ -334,6 +336,8 @@ struct BGroup {
     const int* ids;               // [n_ids] local indices this launch covers (grid.y = n_ids)
     int n_ids;
     int nx, ny, nz;
+    uint32_t m_nyz, m_nz;         // index division by multiply and shift (div_magic)
+    int s_nyz, s_nz;
     long long N;
     int nblk;                     // pointwise blocks per instance
     int zmode;                    // 0 identity, 1 P_V
