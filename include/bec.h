@@ -204,7 +204,7 @@ typedef struct {
     double dt;          /* imaginary-time step > 0                              */
     double tol_dE;      /* stop when |E(psi^n) - E(psi^(n-1))| < tol_dE        */
     int32_t max_iter;   /* steps before BEC_ENOTCONV                            */
-    int32_t pad;
+    int32_t flags;      /* BEC_SOLVE_SYNCHRONOUS or 0 (default: pipelined steps) */
 } bec_ite_opts;
 
 /* Imaginary-time evolution, the method the paper compares against (Sec. VI;
@@ -219,7 +219,11 @@ typedef struct {
  * receives the final one; log_h optionally receives E(psi^0..) (host, log_cap
  * doubles); out_h->final holds the energy terms and residual norms of the
  * returned state, out_h->iters the steps taken.  Returns BEC_OK, BEC_ENOTCONV
- * (max_iter steps), BEC_EINVAL or BEC_ENONFINITE.  Synchronises every step. */
+ * (max_iter steps), BEC_EINVAL or BEC_ENONFINITE.  By default step n + 1 is
+ * enqueued (its normalisation taken on the device from step n's sums) before
+ * the host reads step n's energy, so the host waits once per step without
+ * leaving the GPU idle; the iterates and energies are bit-identical to the
+ * BEC_SOLVE_SYNCHRONOUS schedule. */
 bec_status bec_ite_solve(bec_ctx* ctx, double* psi_inout, const bec_ite_opts* opts, bec_report* out_h,
                          double* log_h, int32_t log_cap);
 

@@ -63,7 +63,7 @@ class Iter(C.Structure):
 
 
 class IteOpts(C.Structure):
-    _fields_ = [("dt", C.c_double), ("tol_dE", C.c_double), ("max_iter", C.c_int32), ("pad", C.c_int32)]
+    _fields_ = [("dt", C.c_double), ("tol_dE", C.c_double), ("max_iter", C.c_int32), ("flags", C.c_int32)]
 
 
 class Report(C.Structure):

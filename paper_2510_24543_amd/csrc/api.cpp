@@ -267,6 +267,8 @@ constexpr int kScalModel = 0;     // direction-write sums [0,18), line-search su
 constexpr int kScalHeval = 32;    // energy sums (kHevalSums)
 constexpr int kScalDir = 56;      // direction-reduce sums (kDirReduceSums)
 constexpr int kScalStep = 72;     // device step decision (kStepOut)
+constexpr int kScalIte0 = 0;      // imaginary-time sums of even steps (kIteSums + 2 Parseval)
+constexpr int kScalIte1 = 96;     // and of odd steps
 static_assert(kScalHeval >= 32 && kScalHeval + bec::kHevalSums <= kScalDir, "scalar ranges overlap");
 static_assert(kScalDir + bec::kDirReduceSums <= kScalStep && kScalStep + bec::kStepOut <= kScalSlots,
               "scalar ranges overlap");
@@ -1649,42 +1651,83 @@ bec_status bec_ite_solve(bec_ctx* c, double* psi_inout, const bec_ite_opts* o, b
     const double dV = c->dV;
     const bec_params& p = c->p;
     bec_report rep{};
+    if (o->flags & ~BEC_SOLVE_SYNCHRONOUS) return fail(BEC_EINVAL, "unknown bits in opts.flags: 0x%x", o->flags);
+    const bool pipe = !(o->flags & BEC_SOLVE_SYNCHRONOUS);
     STCHK(normalise_into(c, reinterpret_cast<const double2*>(psi_inout), 0));
-    // psi[0]: the iterate psi^n; psi[1]: exp(-dt U) F^-1 exp(-dt T) F psi^n (not normalised)
-    const double2* src = c->psi[0];
-    double a[2] = {1.0, 1.0};
-    int n = 0;
-    bec_status status = BEC_ENOTCONV;
-    double E_prev = NAN;
-    for (;;) {
+    // Step n reads the unnormalised output of step n - 1 (or the normalised
+    // start), stores the normalised iterate psi^n in slot A(n) and
+    // exp(-dt U) F^-1 exp(-dt T) F psi^n in slot B(n); the slots alternate
+    // between (psi[0], psi[1]) and (hpsi[0], hpsi[1]), so a step enqueued ahead
+    // of the host's convergence test never overwrites the iterate it returns.
+    // Its sums go to scalar range R(n % 2) (host and device copies).
+    auto slotA = [&](int k) { return (k & 1) ? c->hpsi[0] : c->psi[0]; };
+    auto slotB = [&](int k) { return (k & 1) ? c->hpsi[1] : c->psi[1]; };
+    auto region = [](int k) { return (k & 1) ? kScalIte1 : kScalIte0; };
+    auto enqueue_step = [&](int k, const double a_host[2]) -> bec_status {
         bec::TrialZArgs z{};
-        z.psi_src = src;
+        z.psi_src = k == 0 ? c->psi[0] : slotB(k - 1);
         z.p = nullptr;
-        z.a[0] = a[0];
-        z.a[1] = a[1];
-        z.psi_dst = c->psi[0];
+        z.a[0] = a_host ? a_host[0] : 0.0;
+        z.a[1] = a_host ? a_host[1] : 0.0;
+        if (!a_host) {   // normalisation of step k - 1's output, decided on the device
+            z.norm_sums = c->dscal + region(k - 1) + 12;
+            z.norm_dV = dV;
+        }
+        z.psi_dst = slotA(k);
         z.N = N;
         double2* fdst[3] = {c->W, c->W + N, c->aux[0]};
         const int ops[3] = {bec::kOpExpKin, bec::kOpExpKin, bec::kOpMulDip};
         const double dts[3] = {o->dt, o->dt, 0.0};
         STCHK(kspace_apply_trial(c, z, fdst, ops, dts));
         bec::IteArgs ia{};
-        ia.psi = c->psi[0];
+        ia.psi = slotA(k);
         ia.hat = c->W;
         ia.phi = c->aux[0];
-        ia.out = c->psi[1];
+        ia.out = slotB(k);
         ia.dt = o->dt;
         ia.partials = c->partials;
         LAUNCH(c, "ite_epilogue", (double)N * 112.0, bec::launch_ite_epi(c->P, ia, c->nblk_pw, c->st));
+        const int rb = region(k);
+        const bec::RedSeg s1{c->partials, c->nblk_pw, bec::kIteSums, c->scal + rb, c->dscal + rb};
+        const bec::RedSeg s2{c->fft_partials, c->nblk_x, 2, c->scal + rb + bec::kIteSums,
+                             c->dscal + rb + bec::kIteSums};
+        const bec::RedSeg none{nullptr, 0, 0, nullptr, nullptr};
         LAUNCH(c, "reduce_final", 8.0 * (bec::kIteSums * c->nblk_pw + 2 * c->nblk_x),
-               bec::launch_reduce_final2(c->partials, c->nblk_pw, bec::kIteSums, c->scal, c->fft_partials,
-                                         c->nblk_x, 2, c->scal + kParsevalOut, c->st));
-        STCHK(fetch(c, 32));
-        const double* S = c->host;
+               bec::launch_reduce_segs(s1, s2, none, c->st));
+        return BEC_OK;
+    };
+    const double one[2] = {1.0, 1.0};
+    int n = 0;
+    bec_status status = BEC_ENOTCONV;
+    double E_prev = NAN;
+    double a[2] = {1.0, 1.0};
+    {
+        const ScalRange w0[] = {{region(0), bec::kIteSums + 2}};
+        if (pipe) arm_scalars(c->host, w0, 1);
+        STCHK(enqueue_step(0, one));
+    }
+    for (;;) {
+        // step n + 1 goes ahead of the host's test of step n (unless step n is the last allowed)
+        const bool ahead = pipe && n < o->max_iter;
+        const ScalRange wn[] = {{region(n), bec::kIteSums + 2}};
+        if (ahead) {
+            const ScalRange wn1[] = {{region(n + 1), bec::kIteSums + 2}};
+            arm_scalars(c->host, wn1, 1);
+            STCHK(enqueue_step(n + 1, nullptr));
+        }
+        if (pipe) {
+            if (!await_scalars(c->host, wn, 1, 120.0)) {
+                HIPCHK(hipStreamSynchronize(c->st));
+                if (!await_scalars(c->host, wn, 1, 0.0)) return fail(BEC_EHIP, "reduced scalars did not arrive");
+            }
+        } else {
+            STCHK(fetch(c, 0));
+        }
+        const double* S = c->host + region(n);
         // energy of psi^n (Sec. II, Eq. (1)); kinetic part by Parseval of F psi^n
         double E = dV * S[9];
         for (int i = 0; i < 2; ++i) {
-            E += p.N[i] * dV * (S[kParsevalOut + i] / (double)N + S[i]);
+            E += p.N[i] * dV * (S[bec::kIteSums + i] / (double)N + S[i]);
             const double nn[2] = {i == 0 ? S[2] : S[3], i == 0 ? S[3] : S[4]};
             for (int j = 0; j < 2; ++j)
                 E += 0.5 * p.N[i] * dV * (p.G[i][j] * nn[j] + p.Gdd[i][j] * S[5 + 2 * i + j]);
@@ -1696,19 +1739,23 @@ bec_status bec_ite_solve(bec_ctx* c, double* psi_inout, const bec_ite_opts* o, b
         E_prev = E;
         for (int i = 0; i < 2; ++i) {
             const double nrm2 = dV * S[12 + i];
-            if (!(nrm2 > 0.0) || !std::isfinite(nrm2)) return fail(BEC_ENONFINITE, "imaginary-time step lost the norm");
-            a[i] = 1.0 / std::sqrt(nrm2);
+            if (!(nrm2 > 0.0) || !std::isfinite(nrm2)) {
+                (void)hipStreamSynchronize(c->st);
+                return fail(BEC_ENONFINITE, "imaginary-time step lost the norm");
+            }
+            a[i] = 1.0 / std::sqrt(nrm2);   // the trial pass's own formula, for the synchronous schedule
         }
-        src = c->psi[1];
         ++n;
+        if (!pipe) STCHK(enqueue_step(n, a));
     }
+    double2* const result = slotA(n);
     Eval ev;
     if (status != BEC_ENONFINITE) {
-        STCHK(heval(c, c->psi[0], nullptr, kOne, kZero, 1, &ev));
+        STCHK(heval(c, result, nullptr, kOne, kZero, 1, &ev));
         STCHK(residual_norms(c, 1, &ev));
         rep.final = ev.t;
     }
-    HIPCHK(hipMemcpyAsync(psi_inout, c->psi[0], 2 * N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(psi_inout, result, 2 * N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     rep.iters = n;
     rep.status = status;

@@ -134,6 +134,8 @@ struct TrialZArgs {
     const double2* p;             // 2N or null
     double a[2], b[2];
     const double* coef;           // non-null: a and b from device memory (a_1, a_2, b_1, b_2) instead
+    const double* norm_sums;      // non-null: a_i = 1 / sqrt(norm_dV norm_sums[i]), b = 0 (imaginary time)
+    double norm_dV;
     double2* psi_dst;             // 2N (may equal psi_src)
     long long N;                  // points per component
 };

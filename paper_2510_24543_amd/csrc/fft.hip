@@ -448,6 +448,11 @@ __global__ __launch_bounds__(NTHR) void fft_trial_z_kernel(FftPassArgs A, TrialZ
         Z.b[0] = Z.coef[2];
         Z.b[1] = Z.coef[3];
     }
+    if (Z.norm_sums) {   // normalisation from the previous step's device sums (the host's formula)
+        Z.a[0] = 1.0 / sqrt(Z.norm_dV * Z.norm_sums[0]);
+        Z.a[1] = 1.0 / sqrt(Z.norm_dV * Z.norm_sums[1]);
+        Z.b[0] = Z.b[1] = 0.0;
+    }
     trial_z_body<L, T, R0, R1, R2, NTHR>(A, Z, A.dst[0], A.dst[1], A.dst[2], lds);
 }
 
@@ -472,6 +477,7 @@ __global__ __launch_bounds__(NTHR) void fft_btrial_z_kernel(FftPassArgs A, BGrou
     Z.b[0] = S.b[0];
     Z.b[1] = S.b[1];
     Z.coef = nullptr;
+    Z.norm_sums = nullptr;
     Z.psi_dst = g.psi + ((long long)l * 2 + (1 - S.cur)) * 2 * N;
     Z.N = N;
     double2* w = g.W + (long long)l * 3 * N;

@@ -145,14 +145,15 @@ class Context:
         log = [{k: getattr(logs[i], k) for k, _ in B.Iter._fields_} for i in range(min(rep.iters, cap))]
         return psi, out, log
 
-    def ite(self, psi0, dt: float, tol_dE: float = 1e-6, max_iter: int = 100000, log_cap: int = 0):
+    def ite(self, psi0, dt: float, tol_dE: float = 1e-6, max_iter: int = 100000, log_cap: int = 0,
+            flags: int = 0):
         """Imaginary-time evolution baseline (normalised first-order splitting);
         returns (psi, report, energies of the iterates psi^0, psi^1, ...)."""
         psi = self.field(psi0).clone()
         rep = B.Report()
         cap = max(int(log_cap), 0)
         logE = (C.c_double * max(cap, 1))()
-        o = B.IteOpts(dt=float(dt), tol_dE=float(tol_dE), max_iter=int(max_iter), pad=0)
+        o = B.IteOpts(dt=float(dt), tol_dE=float(tol_dE), max_iter=int(max_iter), flags=int(flags))
         st = B.lib().bec_ite_solve(self._ctx, _ptr(psi), C.byref(o), C.byref(rep), logE, cap)
         B.check(st, "bec_ite_solve", ok=(0, 4))
         out = {"iters": rep.iters, "status": B.STATUS[rep.status], "final": rep.final.to_dict(),

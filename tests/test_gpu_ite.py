@@ -114,3 +114,22 @@ def test_ite_rejects_bad_options(solver):
     for dt in (0.0, -0.1, float("nan")):
         with pytest.raises(Exception):
             ctx.ite(psi0, dt)
+
+
+@pytest.mark.parametrize("case,tol,max_iter", [("C1b", 1e-6, 5000), ("C2", 1e-6, 300), ("mixedN", 0.0, 7),
+                                               ("noLHY", 1e-5, 5000)])
+def test_ite_pipelined_is_bitwise_the_synchronous_one(solver, case, tol, max_iter):
+    """Step n + 1 is enqueued before the host tests step n (its normalisation from
+    the device copy of step n's sums): iterates, energies and reports equal the
+    host-synchronised schedule bit for bit, through convergence and max_iter."""
+    grid, params, dt = CASES[case]
+    psi0 = torch.from_numpy(inputs.initial_state(grid, params["omega"], 47, phase=True))
+    ctx = solver.Context(grid, params)
+    pa, ra, la = ctx.ite(psi0, dt, tol_dE=tol, max_iter=max_iter, log_cap=max_iter + 1, flags=0)
+    pb, rb, lb = ctx.ite(psi0, dt, tol_dE=tol, max_iter=max_iter, log_cap=max_iter + 1, flags=1)
+    assert ra["iters"] == rb["iters"] and ra["status"] == rb["status"]
+    assert ra["final"] == rb["final"]
+    assert np.array_equal(la, lb)
+    assert torch.equal(pa, pb)
+    with pytest.raises(Exception):
+        ctx.ite(psi0, dt, max_iter=3, flags=4)
