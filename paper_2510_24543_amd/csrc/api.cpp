@@ -135,13 +135,14 @@ void gauss_legendre01(int n, std::vector<double>& u, std::vector<double>& w)
 
 // Spherical cutoff of the dipolar kernel (radius R in real space):
 // c(q) = 1 + 3 cos q / q^2 - 3 sin q / q^3, q = |k| R; below q = 1 its series
-// sum_{m>=1} (-1)^(m+1) 6 m q^(2m) / (2m+3)!, in long double.
+// sum_{m>=1} (-1)^(m+1) 6 (m+1) q^(2m) / (2m+3)! = q^2/10 - q^4/280 + ...,
+// in long double.
 long double cutoff_factor(long double q)
 {
     if (q >= 1.0L) return 1.0L + 3.0L * cosl(q) / (q * q) - 3.0L * sinl(q) / (q * q * q);
     long double q2 = q * q, term = q2, fact = 120.0L, s = 0.0L;   // (2m+3)! at m = 1 is 5! = 120
     for (int m = 1; m <= 14; ++m) {
-        s += ((m % 2) ? 1.0L : -1.0L) * 6.0L * m * term / fact;
+        s += ((m % 2) ? 1.0L : -1.0L) * 6.0L * (m + 1) * term / fact;
         term *= q2;
         fact *= (2.0L * m + 4.0L) * (2.0L * m + 5.0L);
     }

@@ -61,6 +61,25 @@ def test_batch_matches_oracle(solver, orc):
     assert np.max(np.abs(np.abs(psis[0].cpu().numpy()) ** 2 - np.abs(psio) ** 2)) < 1e-7
 
 
+def test_batch_small_cutoff_matches_oracle(solver, orc):
+    """Cutoff radii far below the box, so that the per-instance dipolar tables
+    take the cutoff factor from its series for the low modes (q = |k| R_c < 1)."""
+    cases = []
+    for k, (n, rc) in enumerate((((16, 16, 32), 1.0), ((32, 16, 16), 2.0))):
+        grid = {"n": list(n), "lo": [-6.0] * 3, "hi": [6.0] * 3}
+        params = {"N": [1.0, 1.0], "omega": [1.0, 1.0, 2.0], "G": [[80.0, 40.0], [40.0, 80.0]],
+                  "Gdd": [[60.0, 50.0], [50.0, 60.0]], "c_lhy": 3.0, "r_cut": rc, "n_u": 16}
+        cases.append((grid, params, inputs.initial_state(grid, params["omega"], 610 + k)))
+    b = solver.Batch([c[0] for c in cases], [c[1] for c in cases])
+    psis, reps = b.solve([c[2] for c in cases], OPTS)
+    for (grid, params, psi0), psi_b, rb in zip(cases, psis, reps):
+        print(f"grid {grid['n']} r_cut {params['r_cut']}", flush=True)
+        psio, repo, _ = orc.solve(grid, params, psi0, OPTS)
+        assert rb["status"] == "OK" and repo["status"] == "OK"
+        assert abs(rb["final"]["E"] - repo["final"]["E"]) <= 1e-10 * abs(repo["final"]["E"])
+        assert np.max(np.abs(np.abs(psi_b.cpu().numpy()) ** 2 - np.abs(psio) ** 2)) < 1e-7
+
+
 def test_graph_replay_equals_eager_launches(solver):
     scan = small_scan(4, seed=91)
     grids, params, psi0 = [s[0] for s in scan], [s[1] for s in scan], [s[2] for s in scan]

@@ -128,6 +128,12 @@ CASES = {
     "nu24_mixedN": ({"n": [32, 16, 16], "lo": [-6, -6, -6], "hi": [6, 6, 6]},
                     small_params(n_u=24, N=[1.0, 1.6], G=[[100.0, 50.0], [31.25, 90.0]],
                                  Gdd=[[60.0, 45.0], [28.125, 50.0]])),
+    # cutoff radius small against the box: the low modes have q = |k| R_c < 1, where
+    # the kernel's cutoff factor c(q) is taken from its series
+    "smallcut": ({"n": [32, 32, 32], "lo": [-8, -8, -8], "hi": [8, 8, 8]}, small_params(r_cut=1.0)),
+    "smallcut_aniso": ({"n": [32, 32, 16], "lo": [-16, -12, -4], "hi": [16, 12, 4]},
+                       small_params(r_cut=2.5, N=[1.0, 1.6], G=[[100.0, 50.0], [31.25, 90.0]],
+                                    Gdd=[[60.0, -45.0], [-28.125, 50.0]])),
 }
 
 

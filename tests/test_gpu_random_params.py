@@ -3,7 +3,9 @@
 Random grids (supported axis lengths up to 48), boxes, atom numbers, traps,
 contact and dipolar couplings of either sign (symmetric N_i G_ij), LHY on or off
 and 1 to 24 quadrature nodes, so that the LHY nodes fall into every class and the
-class-A Chebyshev table is built on some sets and refused or empty on others.
+class-A Chebyshev table is built on some sets and refused or empty on others;
+cutoff radii from 0.5 to 10, so that on some sets the lowest modes take the
+dipolar cutoff factor c(q) from its series (q = |k| R_c < 1).
 Bars as in test_gpu_parity: energy terms 1e-12 of the energy scale, H psi 1e-11
 in max norm, line-search model 1e-10.
 """
@@ -33,7 +35,7 @@ def random_case(seed):
         "Gdd": [[float(rng.uniform(-50.0, 200.0)), float(Gdd12)],
                 [float(N[0] * Gdd12 / N[1]), float(rng.uniform(-50.0, 200.0))]],
         "c_lhy": 0.0 if rng.uniform() < 0.2 else float(rng.uniform(0.5, 10.0)),
-        "r_cut": float(rng.uniform(3.0, 10.0)),
+        "r_cut": float(rng.uniform(0.5, 10.0)),
         "n_u": int(rng.choice([1, 5, 16, 24])),
     }
     grid = {"n": n, "lo": [float(-h) for h in half], "hi": [float(h) for h in half]}
