@@ -332,6 +332,39 @@ bec_status bec_profile_read(bec_ctx* ctx, bec_kernel_stat* out_h, int32_t cap, i
  * u integral (host memory, caller-owned, n in 1..64).  Host-only: needs no GPU. */
 bec_status bec_gauss_legendre(int32_t n, double* u, double* w);
 
+/* A two-component dipolar mixture in laboratory units.  The energy functional
+ * of Sec. II has one kinetic term -1/2 nabla^2 for both components, so a single
+ * atomic mass m fixes the oscillator length l = sqrt(hbar / (m omega_0)). */
+typedef struct {
+    double mass_amu;        /* atomic mass m in unified atomic mass units, > 0           */
+    double a_bohr[2][2];    /* s-wave scattering lengths a_ij in Bohr radii, symmetric   */
+    double mu_bohr[2];      /* magnetic moments along the field in Bohr magnetons;
+                               opposite signs make counter-polarised components          */
+    double N[2];            /* atom numbers N_i > 0                                      */
+    double f0_hz;           /* unit frequency omega_0 / 2 pi in Hz, > 0                  */
+    double trap_hz[3];      /* trap frequencies omega_d / 2 pi in Hz, >= 0               */
+    double c_lhy;           /* multiplier of the LHY term (1 = the paper's model)        */
+    double r_cut_um;        /* dipolar cutoff radius in micrometres, > 0                 */
+    int32_t n_u;            /* Gauss-Legendre nodes for the u integral, 1..64            */
+    int32_t contact_2pi;    /* 0: G_ij = 4 pi a_ij N_j / l, the contact coupling
+                               4 pi hbar^2 a / m that the LHY prefactor of Eq. (1)
+                               assumes; 1: the prefactor 2 pi as printed in Sec. II       */
+} bec_physical;
+
+/* Convert laboratory units into the oscillator units of Sec. II (host-only:
+ * needs no GPU).  lambda_d = omega_d / omega_0; G_ij = 4 pi a_ij N_j / l;
+ * Gdd_ij = mu_0 mu_i mu_j N_j / (3 l^3 hbar omega_0), the k-space amplitude,
+ * which is (4 pi / 3) times the real-space coefficient D_ij of Sec. II because
+ * the Fourier transform of (1 - 3 cos^2 theta) / r^3 is (4 pi / 3)(3 cos^2 alpha - 1);
+ * r_cut = r_cut_um / l; c_lhy and n_u are copied.  Constants: CODATA 2018.
+ * in_h and out_h are caller-owned host structs; length_m_h (host, may be null)
+ * receives l in metres, by which lengths such as the box edges are divided.
+ * BEC_EINVAL on a null in_h/out_h, a mass, unit frequency, atom number or
+ * cutoff that is not finite and positive, a negative or non-finite trap
+ * frequency, a non-finite or asymmetric a_ij, a non-finite mu_i or c_lhy,
+ * n_u outside 1..64, or contact_2pi other than 0 and 1. */
+bec_status bec_params_from_physical(const bec_physical* in_h, bec_params* out_h, double* length_m_h);
+
 /* Thread-local message of the last failing call on this thread. */
 const char* bec_last_error(void);
 

@@ -29,6 +29,10 @@ class Params(C.Structure):
                 ("G", (C.c_double * 2) * 2), ("Gdd", (C.c_double * 2) * 2),
                 ("c_lhy", C.c_double), ("r_cut", C.c_double), ("n_u", C.c_int32)]
 
+    def to_dict(self) -> dict:
+        return {"N": list(self.N), "omega": list(self.omega), "G": [list(r) for r in self.G],
+                "Gdd": [list(r) for r in self.Gdd], "c_lhy": self.c_lhy, "r_cut": self.r_cut, "n_u": self.n_u}
+
 
 class Opts(C.Structure):
     _fields_ = [("pc", C.c_int32), ("beta", C.c_int32), ("max_iter", C.c_int32),
@@ -76,6 +80,12 @@ class Tuning(C.Structure):
                 ("lhy_terms", C.c_int32)]
 
 
+class Physical(C.Structure):
+    _fields_ = [("mass_amu", C.c_double), ("a_bohr", (C.c_double * 2) * 2), ("mu_bohr", C.c_double * 2),
+                ("N", C.c_double * 2), ("f0_hz", C.c_double), ("trap_hz", C.c_double * 3),
+                ("c_lhy", C.c_double), ("r_cut_um", C.c_double), ("n_u", C.c_int32), ("contact_2pi", C.c_int32)]
+
+
 class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("total_ms", C.c_double),
                 ("total_bytes", C.c_double)]
@@ -111,6 +121,7 @@ SIGNATURES = [
     ("bec_profile_enable", C.c_int, [_VP, _I32]),
     ("bec_profile_read", C.c_int, [_VP, C.POINTER(KernelStat), _I32, C.POINTER(_I32)]),
     ("bec_gauss_legendre", C.c_int, [_I32, _DP, _DP]),
+    ("bec_params_from_physical", C.c_int, [C.POINTER(Physical), C.POINTER(Params), _DP]),
     ("bec_last_error", C.c_char_p, []),
 ]
 

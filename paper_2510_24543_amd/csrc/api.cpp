@@ -1052,6 +1052,49 @@ bec_status bec_gauss_legendre(int32_t n, double* u, double* w)
     return BEC_OK;
 }
 
+bec_status bec_params_from_physical(const bec_physical* in, bec_params* out, double* length_m)
+{
+    // CODATA 2018: hbar (exact h / 2 pi), mu_0, Bohr magneton, Bohr radius, atomic mass unit
+    constexpr double kHbar = 1.054571817e-34, kMu0 = 1.25663706212e-6, kMuB = 9.2740100783e-24;
+    constexpr double kA0 = 5.29177210903e-11, kAmu = 1.66053906660e-27, kPi = 3.14159265358979323846;
+    if (!in || !out) return fail(BEC_EINVAL, "in and out must not be null");
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    if (!pos(in->mass_amu) || !pos(in->f0_hz) || !pos(in->N[0]) || !pos(in->N[1]) || !pos(in->r_cut_um))
+        return fail(BEC_EINVAL, "mass, unit frequency, atom numbers and cutoff must be finite and positive");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(in->trap_hz[d]) || in->trap_hz[d] < 0.0)
+            return fail(BEC_EINVAL, "trap frequencies must be finite and >= 0");
+    for (int i = 0; i < 2; ++i) {
+        if (!std::isfinite(in->mu_bohr[i])) return fail(BEC_EINVAL, "non-finite magnetic moment");
+        for (int j = 0; j < 2; ++j)
+            if (!std::isfinite(in->a_bohr[i][j])) return fail(BEC_EINVAL, "non-finite scattering length");
+    }
+    if (in->a_bohr[0][1] != in->a_bohr[1][0]) return fail(BEC_EINVAL, "a_12 and a_21 must be equal");
+    if (!std::isfinite(in->c_lhy)) return fail(BEC_EINVAL, "non-finite c_lhy");
+    if (in->contact_2pi != 0 && in->contact_2pi != 1) return fail(BEC_EINVAL, "contact_2pi must be 0 or 1");
+
+    const double m = in->mass_amu * kAmu, w0 = 2.0 * kPi * in->f0_hz;
+    const double l = std::sqrt(kHbar / (m * w0));
+    const double cg = (in->contact_2pi ? 2.0 : 4.0) * kPi;
+    const double dd = kMu0 * kMuB * kMuB / (3.0 * l * l * l * kHbar * w0);
+    bec_params p{};
+    for (int i = 0; i < 2; ++i) {
+        p.N[i] = in->N[i];
+        for (int j = 0; j < 2; ++j) {
+            p.G[i][j] = cg * (in->a_bohr[i][j] * kA0 / l) * in->N[j];
+            p.Gdd[i][j] = dd * in->mu_bohr[i] * in->mu_bohr[j] * in->N[j];
+        }
+    }
+    for (int d = 0; d < 3; ++d) p.omega[d] = in->trap_hz[d] / in->f0_hz;
+    p.c_lhy = in->c_lhy;
+    p.r_cut = in->r_cut_um * 1e-6 / l;
+    p.n_u = in->n_u;
+    STCHK(check_params(&p));
+    *out = p;
+    if (length_m) *length_m = l;
+    return BEC_OK;
+}
+
 bec_status bec_workspace_size(const bec_grid* grid, const bec_params* params, size_t* bytes)
 {
     STCHK(check_grid(grid));

@@ -33,7 +33,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     import subprocess
     structs = {"bec_grid": B.Grid, "bec_params": B.Params, "bec_opts": B.Opts, "bec_terms": B.Terms,
                "bec_ls_report": B.LsReport, "bec_iter": B.Iter, "bec_report": B.Report,
-               "bec_kernel_stat": B.KernelStat, "bec_tuning": B.Tuning, "bec_ite_opts": B.IteOpts}
+               "bec_kernel_stat": B.KernelStat, "bec_tuning": B.Tuning, "bec_ite_opts": B.IteOpts,
+               "bec_physical": B.Physical}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bec.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -1,0 +1,104 @@
+"""Parity of the HIP path with the oracle on the laboratory setups of Sec. VI,
+converted by bec_params_from_physical.
+
+These are the paper's own regimes: counter-polarised components (negative
+cross dipolar amplitude), eps_dd well above 1 with clipped LHY branches, and
+couplings of 1e3 to 1e5 in oscillator units.  Unstated inputs are read as:
+52Cr scattering lengths 100 a_0 for every pair (Sec. VI.A gives none); the
+162Dy radial trap 2 pi x 50 Hz (Sec. VI.C gives only omega_z); the Dy-Er mixture
+with one atomic mass (164 u), no radial trap (periodic xy), omega_0 = 2 pi x 900 Hz
+and lambda_z = 0.08, in a 40 x 40 periodic xy box (N / (L_x L_y) = 625).  Grids are
+small so that the oracle finishes in seconds.  Bars as in test_gpu_parity:
+energy terms 1e-12 of the energy scale, H psi 1e-11 in max norm, model 1e-10,
+and the first ten iterates of the solve 1e-11 in energy.
+"""
+import numpy as np
+import pytest
+
+from paper_2510_24543_amd import inputs, units
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+NAMES = ["Cr52_VI.A", "Dy162_VI.C", "DyEr_VI.C"]
+
+
+def setup(name):
+    """(grid, params, initial-state width parameters) of one setup; the conversion
+    runs in the test, not at collection."""
+    out = {}
+    P, l = units.physical_params(51.9405075, [[100.0, 100.0], [100.0, 100.0]], [6.0, -6.0], [5e5, 2.5e5],
+                                 100.0, [100.0, 100.0, 800.0], r_cut_um=4.0 * 1.3949, n_u=16)
+    out["Cr52_VI.A"] = ({"n": [32, 32, 16], "lo": [-16.0, -16.0, -4.0], "hi": [16.0, 16.0, 4.0]}, P,
+                        [0.05, 0.05, 2.0])
+    P, l = units.physical_params(161.9268056, [[50.0, 150.0], [150.0, 70.0]], [10.0, -10.0], [3e4, 3e4],
+                                 100.0, [50.0, 50.0, 250.0], r_cut_um=5.0, n_u=24)
+    out["Dy162_VI.C"] = ({"n": [32, 32, 16], "lo": [-10.0, -10.0, -5.0], "hi": [10.0, 10.0, 5.0]}, P,
+                         [0.2, 0.2, 1.0])
+    P, l = units.physical_params(164.0, [[118.5, 57.65], [57.65, 58.95]], [10.0, 7.07], [1e6, 1e6],
+                                 900.0, [0.0, 0.0, 72.0], r_cut_um=8.0 * 0.26, n_u=16)
+    out["DyEr_VI.C"] = ({"n": [32, 32, 32], "lo": [-20.0, -20.0, -16.0], "hi": [20.0, 20.0, 16.0]}, P,
+                        [0.01, 0.01, 0.02])
+    return out[name]
+
+
+@pytest.fixture(scope="module")
+def solver():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2510_24543_amd import solver as s
+    return s
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_physical_setup_energy_hamiltonian_model(solver, orc, name):
+    grid, params, width = setup(name)
+    print(f"{name}: grid {grid['n']} G11 {params['G'][0][0]:.4g} Gdd12 {params['Gdd'][0][1]:.4g}", flush=True)
+    psi = inputs.initial_state(grid, width, 71, phase=True)
+    ctx = solver.Context(grid, params)
+    h, t = ctx.hamiltonian(torch.from_numpy(psi))
+    to, ho, _, _ = orc.heval(grid, params, psi)
+    scale = abs(to["E_kin"][0]) + abs(to["E_kin"][1]) + abs(to["E_trap"][0]) + abs(to["E_trap"][1]) + \
+        sum(abs(to[k][i][j]) for k in ("E_c", "E_dd") for i in range(2) for j in range(2)) + abs(to["E_lhy"])
+    for k in ("E", "E_lhy"):
+        assert abs(t[k] - to[k]) <= 1e-12 * scale, k
+    for k in ("E_c", "E_dd"):
+        for i in range(2):
+            for j in range(2):
+                assert abs(t[k][i][j] - to[k][i][j]) <= 1e-12 * scale, (k, i, j)
+    for k in ("mu", "shift"):
+        for i in range(2):
+            assert abs(t[k][i] - to[k][i]) <= 1e-11 * scale / params["N"][i], (k, i)
+    assert _rel(h.cpu().numpy(), ho) < 1e-11
+    dV = float(np.prod([(grid["hi"][a] - grid["lo"][a]) / grid["n"][a] for a in range(3)]))
+    r = np.stack([ho[i] - to["mu"][i] * psi[i] for i in range(2)])
+    d = -r + 0.01 * np.max(np.abs(r)) * inputs.random_field(grid, 72)
+    _, rep = ctx.linesearch(torch.from_numpy(psi), torch.from_numpy(d), {"max_backtrack": 30})
+    p = np.stack([d[i] - dV * np.sum(np.real(np.conj(d[i]) * psi[i])) * psi[i] for i in range(2)])
+    m = orc.model(grid, params, psi, p)
+    assert abs(rep["E1"] - m["E1"]) <= 1e-10 * abs(m["E1"])
+    assert abs(rep["E2"] - m["E2"]) <= 1e-10 * max(abs(m["E2"]), 1e-10 * abs(m["E1"]))
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_physical_setup_first_iterations(solver, orc, name):
+    grid, params, width = setup(name)
+    print(f"{name}: 10 iterations", flush=True)
+    psi0 = inputs.initial_state(grid, width, 73)
+    opts = {"tol_grad": 1e-10, "pc": 1, "max_iter": 10}
+    ctx = solver.Context(grid, params)
+    _, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=16)
+    _, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=16)
+    assert rep["status"] == repo["status"] and rep["iters"] == repo["iters"] == 10
+    assert len(log) == len(logo) == 10
+    E0 = abs(logo[0]["E"])          # the 162Dy energy passes through zero on its way down
+    for a, b in zip(log, logo):
+        assert abs(a["E"] - b["E"]) <= 1e-11 * max(abs(b["E"]), E0)
+    E = [l["E"] for l in log]
+    assert all(b <= a + 1e-14 * abs(a) for a, b in zip(E, E[1:]))
