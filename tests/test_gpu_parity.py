@@ -131,6 +131,10 @@ CASES = {
     # cutoff radius small against the box: the low modes have q = |k| R_c < 1, where
     # the kernel's cutoff factor c(q) is taken from its series
     "smallcut": ({"n": [32, 32, 32], "lo": [-8, -8, -8], "hi": [8, 8, 8]}, small_params(r_cut=1.0)),
+    # the largest quadrature (64 nodes) and a 10:1 atom-number ratio (Sec. VI.A sweeps N_1/N_2 up to 10)
+    "nu64": ({"n": [16, 16, 32], "lo": [-6, -6, -6], "hi": [6, 6, 6]}, small_params(n_u=64)),
+    "Nratio10": ({"n": [16, 32, 16], "lo": [-6, -6, -6], "hi": [6, 6, 6]},
+                 small_params(N=[10.0, 1.0], G=[[100.0, 5.0], [50.0, 90.0]], Gdd=[[60.0, 4.5], [45.0, 50.0]])),
     "smallcut_aniso": ({"n": [32, 32, 16], "lo": [-16, -12, -4], "hi": [16, 12, 4]},
                        small_params(r_cut=2.5, N=[1.0, 1.6], G=[[100.0, 50.0], [31.25, 90.0]],
                                     Gdd=[[60.0, -45.0], [-28.125, 50.0]])),
