@@ -279,6 +279,60 @@ def precond_study(name: str, tol: float = 1e-8, max_iter: int = 20000):
     return {"workload": name, "grid": cfg["grid"]["n"], "tol_grad": tol, "runs": rows}
 
 
+CR52_SWEEP = {
+    # Sec. VI.A: 52Cr, counter-polarised moments (6, -6) mu_B, trap 2 pi (100, 100, 800) Hz,
+    # 256 x 256 x 32 grid, N_1 in {2, 5, 8, 10} x 1e5, N_1 / N_2 in {1, 2, 5, 10}, tol 1e-10.
+    # Not stated there and taken here: omega_0 = 2 pi x 100 Hz, a_11 = a_22 = 100 a_0,
+    # a_12 = 70 a_0, the box [-20, 20)^2 x [-6, 6) in units of l and the cutoff radius 6 l.
+    "mass_amu": 51.9405075, "a_bohr": [[100.0, 70.0], [70.0, 100.0]], "mu_bohr": [6.0, -6.0],
+    "f0_hz": 100.0, "trap_hz": [100.0, 100.0, 800.0],
+    "grid": {"n": [256, 256, 32], "lo": [-20.0, -20.0, -6.0], "hi": [20.0, 20.0, 6.0]}, "r_cut_l": 6.0,
+    "N1": [2e5, 5e5, 8e5, 1e6], "ratio": [1, 2, 5, 10],
+}
+
+
+def cr52_sweep(tol: float = 1e-10, max_iter: int = 20000):
+    """The preconditioner sweep of Sec. VI.A on its 52Cr setup, converted from
+    laboratory units: P_V against P_Delta (HS+, restart period 50) from the same
+    seeded Gaussian + noise start for every (N_1, N_1 / N_2); iterations to
+    max_i ||r_i|| < tol and HIP-event seconds."""
+    import torch
+    from paper_2510_24543_amd import inputs, solver, units, autotune
+    S = CR52_SWEEP
+    grid = S["grid"]
+    _, l = units.physical_params(S["mass_amu"], S["a_bohr"], S["mu_bohr"], [1.0, 1.0], S["f0_hz"],
+                                 S["trap_hz"], r_cut_um=1.0)
+    rows, plan = [], None
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for N1 in S["N1"]:
+        for ratio in S["ratio"]:
+            params, _ = units.physical_params(S["mass_amu"], S["a_bohr"], S["mu_bohr"], [N1, N1 / ratio],
+                                              S["f0_hz"], S["trap_hz"], r_cut_um=S["r_cut_l"] * l * 1e6)
+            ctx = solver.Context(grid, params)
+            if plan is None:
+                plan = autotune.tune(ctx)["tuning"]
+            ctx.set_tuning(plan)
+            psi0 = torch.from_numpy(inputs.initial_state(grid, [0.02, 0.02, 1.0], 4242)).cuda()
+            for pc, pname in ((1, "P_V"), (2, "P_Delta")):
+                opts = {"pc": pc, "beta": 0, "restart_period": 50, "sigma": 1e-6, "tol_grad": tol,
+                        "max_iter": max_iter}
+                torch.cuda.synchronize()
+                ev0.record(ctx.stream)
+                _, rep, _ = ctx.solve(psi0, opts)
+                ev1.record(ctx.stream)
+                torch.cuda.synchronize()
+                rows.append({"N1": N1, "N1/N2": ratio, "precond": pname, "iters": rep["iters"],
+                             "status": rep["status"], "seconds": round(ev0.elapsed_time(ev1) / 1000.0, 4),
+                             "E": rep["final"]["E"], "res_max": max(rep["final"]["res"]),
+                             "G11": params["G"][0][0], "Gdd11": params["Gdd"][0][0]})
+                print(f"Cr52 N1 {N1:.0e} ratio {ratio}: {pname} {rep['iters']} iterations {rep['status']} "
+                      f"{rows[-1]['seconds']} s", file=sys.stderr, flush=True)
+            ctx.close()
+            del ctx
+    return {"setup": "52Cr, Sec. VI.A", "length_unit_m": l, "grid": grid, "tol_grad": tol,
+            "assumed": {k: S[k] for k in ("a_bohr", "f0_hz", "r_cut_l")}, "plan": plan, "runs": rows}
+
+
 def scan_comparison(n_inst: int, use_graph: bool = True):
     """Parameter scan of n_inst instances (grids cycling 48^3, 64^3, 96^3; seeded
     g12, gdd, LHY): one batched solve against the same instances solved one after
@@ -359,6 +413,8 @@ def main():
                     help="imaginary-time step of the PCG-vs-ITE comparison (0: skip it)")
     ap.add_argument("--precond-study", default=None, metavar="WORKLOAD",
                     help="only run the preconditioner x conjugacy-rule study on this workload and print it")
+    ap.add_argument("--cr52-sweep", action="store_true",
+                    help="only run the P_V vs P_Delta sweep on the 52Cr laboratory setup and print it")
     ap.add_argument("--ite-only", default=None, metavar="WORKLOAD",
                     help="only run the PCG-vs-ITE comparison on this workload (e.g. C2, C3, C5) and print it")
     ap.add_argument("--tuning", choices=("auto", "cache", "default"), default="auto",
@@ -389,6 +445,9 @@ def main():
         return
     if args.ite_only:
         print(json.dumps(ite_workload(args.ite_only, args.ite_dt)), flush=True)
+        return
+    if args.cr52_sweep:
+        print(json.dumps(cr52_sweep()), flush=True)
         return
 
     cfg = inputs.CONFIGS[WORKLOAD]
