@@ -230,6 +230,43 @@ def test_preconditioners(solver, orc, pc):
     assert rel(z, zo) < 1e-12
 
 
+@pytest.mark.parametrize("n", [8, 16, 32, 48, 64, 96, 128, 256])
+def test_every_variant_of_the_fused_passes(solver, orc, n):
+    """Every plan variant of the passes with fused work: the x pass with the
+    k-space operators (slot [0][1]) and the z passes that carry the trial update
+    and the line-search epilogue (slot [2][0]), on a grid that is n long along
+    that axis; energy, H psi and the line-search model and trial against the oracle."""
+    from paper_2510_24543_amd import autotune
+    params = small_params()
+    for axis, slot in ((0, (0, 1)), (2, (2, 0))):
+        shape = [8, 16, 8]
+        shape[axis] = n
+        grid = {"n": shape, "lo": [-6.0] * 3, "hi": [6.0] * 3}
+        psi = inputs.initial_state(grid, params["omega"], 43, phase=True)
+        to, ho, _, _ = orc.heval(grid, params, psi)
+        r = np.stack([ho[i] - to["mu"][i] * psi[i] for i in range(2)])
+        d = -r + 0.01 * np.max(np.abs(r)) * inputs.random_field(grid, 44)
+        p = _tangent(grid, d, psi)
+        m = orc.model(grid, params, psi, p)
+        ctx = solver.Context(grid, params)
+        base = ctx.get_tuning()
+        for v in range(autotune.variant_count(n)):
+            print(f"n {n} axis {axis} variant {v}", flush=True)
+            t = {"fft_variant": [r_[:] for r_ in base["fft_variant"]], "pw_blocks": base["pw_blocks"]}
+            t["fft_variant"][slot[0]][slot[1]] = v
+            ctx.set_tuning(t)
+            h, tg = ctx.hamiltonian(torch.from_numpy(psi))
+            assert abs(tg["E"] - to["E"]) <= 1e-12 * abs(to["E"]), (axis, v)
+            assert rel(h.cpu().numpy(), ho) < 1e-11, (axis, v)
+            out, rep = ctx.linesearch(torch.from_numpy(psi), torch.from_numpy(d), {"max_backtrack": 30})
+            assert abs(rep["E1"] - m["E1"]) <= 1e-10 * abs(m["E1"]), (axis, v)
+            assert abs(rep["E2"] - m["E2"]) <= 1e-10 * abs(m["E2"]), (axis, v)
+            ref = orc.geodesic(grid, psi, p, rep["alpha"])
+            assert rel(out.cpu().numpy(), ref) < 1e-11, (axis, v)
+            E_new = orc.heval(grid, params, ref)[0]["E"]
+            assert abs(rep["E_new"] - E_new) <= 1e-12 * abs(E_new), (axis, v)
+
+
 # ---------------------------------------------------------------- line search
 def _tangent(grid, d, psi):
     dV = dvol(grid)
