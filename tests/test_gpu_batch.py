@@ -80,6 +80,37 @@ def test_batch_small_cutoff_matches_oracle(solver, orc):
         assert np.max(np.abs(np.abs(psi_b.cpu().numpy()) ** 2 - np.abs(psio) ** 2)) < 1e-7
 
 
+@pytest.mark.parametrize("n", [8, 16, 32, 48, 64, 96, 128, 256])
+def test_batch_every_variant_of_the_fused_passes(solver, orc, n):
+    """Every plan variant of the batched x pass with the k-space operators and of
+    the batched z passes with the trial update, set per grid with
+    bec_batch_set_tuning: two instances, five iterations, against the oracle."""
+    from paper_2510_24543_amd import autotune
+    opts = {"tol_grad": 1e-10, "max_iter": 5, "pc": 1}
+    for axis, slot in ((0, (0, 1)), (2, (2, 0))):
+        shape = [8, 16, 8]
+        shape[axis] = n
+        grid = {"n": shape, "lo": [-6.0] * 3, "hi": [6.0] * 3}
+        inst = []
+        for k in range(2):
+            params = {"N": [1.0, 1.0], "omega": [1.0, 1.0, 2.0], "G": [[80.0, 30.0 + 20 * k], [30.0 + 20 * k, 80.0]],
+                      "Gdd": [[50.0, 40.0], [40.0, 50.0]], "c_lhy": 2.0 + k, "r_cut": 5.0, "n_u": 16}
+            psi0 = inputs.initial_state(grid, params["omega"], 700 + k)
+            _, repo, _ = orc.solve(grid, params, psi0, opts)
+            inst.append((params, psi0, repo))
+        b = solver.Batch([grid, grid], [x[0] for x in inst])
+        base = {"fft_variant": [[0, 0], [0, 0], [0, 0]], "pw_blocks": 0}
+        for v in range(autotune.variant_count(n)):
+            print(f"n {n} axis {axis} variant {v}", flush=True)
+            t = {"fft_variant": [r[:] for r in base["fft_variant"]], "pw_blocks": 0}
+            t["fft_variant"][slot[0]][slot[1]] = v
+            b.set_tuning(grid, t)
+            _, reps = b.solve([x[1] for x in inst], opts, rounds_per_sync=2)
+            for (params, psi0, repo), rb in zip(inst, reps):
+                assert rb["iters"] == repo["iters"] and rb["status"] == repo["status"], (axis, v)
+                assert abs(rb["final"]["E"] - repo["final"]["E"]) <= 1e-11 * abs(repo["final"]["E"]), (axis, v)
+
+
 def test_graph_replay_equals_eager_launches(solver):
     scan = small_scan(4, seed=91)
     grids, params, psi0 = [s[0] for s in scan], [s[1] for s in scan], [s[2] for s in scan]
