@@ -76,6 +76,34 @@ def test_ite_energies_of_successive_iterates_match_oracle(solver, orc, case):
     assert np.all(np.diff(logE) <= 1e-13 * abs(logE[0]))
 
 
+@pytest.mark.parametrize("n", [8, 16, 32, 48, 64, 96, 128, 256])
+def test_ite_every_variant_of_the_fused_passes(solver, orc, n):
+    """Every plan variant of the x pass with exp(-dt k^2/2) and of the z pass with
+    the normalisation and packing, at every supported axis length: four steps'
+    energies against the oracle."""
+    from paper_2510_24543_amd import autotune
+    params = {"N": [1.0, 1.0], "omega": [1.0, 1.2, 2.0], "G": [[100.0, 50.0], [50.0, 90.0]],
+              "Gdd": [[60.0, 45.0], [45.0, 50.0]], "c_lhy": 5.0, "r_cut": 6.0, "n_u": 16}
+    K, dt = 4, 0.005
+    for axis, slot in ((0, (0, 1)), (2, (2, 0))):
+        shape = [8, 16, 8]
+        shape[axis] = n
+        grid = {"n": shape, "lo": [-6.0] * 3, "hi": [6.0] * 3}
+        psi0 = inputs.initial_state(grid, params["omega"], 45)
+        _, repo, logo = orc.ite(grid, params, psi0, dt, tol_dE=0.0, max_iter=K, log_cap=K + 1)
+        ctx = solver.Context(grid, params)
+        base = ctx.get_tuning()
+        for v in range(autotune.variant_count(n)):
+            print(f"n {n} axis {axis} variant {v}", flush=True)
+            t = {"fft_variant": [r[:] for r in base["fft_variant"]], "pw_blocks": base["pw_blocks"]}
+            t["fft_variant"][slot[0]][slot[1]] = v
+            ctx.set_tuning(t)
+            _, rep, logE = ctx.ite(torch.from_numpy(psi0), dt, tol_dE=0.0, max_iter=K, log_cap=K + 1)
+            assert rep["iters"] == repo["iters"] == K and len(logE) == len(logo), (axis, v)
+            for a, b in zip(logE, logo):
+                assert abs(a - b) <= 1e-12 * abs(b), (axis, v)
+
+
 def test_ite_stop_rule_matches_oracle(solver, orc):
     c = inputs.CONFIGS["C1b"]
     grid, params = c["grid"], c["params"]
