@@ -314,6 +314,7 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
     const long long nb_pw = std::min<long long>((N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwMaxBlocks);
     const long long nb_x = bec::fft_max_blocks(n[0], (long long)n[1] * n[2]);
     const long long nb_z = bec::fft_max_blocks(n[2], (long long)n[0] * n[1]);
+    const long long nb_y = bec::fft_max_blocks(n[1], (long long)n[0] * n[2]);
     size_t sizes[] = {
         2 * N * c2, 2 * N * c2,                    // psi[0], psi[1]
         2 * N * c2, 2 * N * c2,                    // hpsi[0], hpsi[1]
@@ -329,7 +330,7 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
         n[0] * sizeof(double), n[1] * sizeof(double), n[2] * sizeof(double),        // V per axis
         bec::kMaxNodes * bec::kNodeStride * sizeof(double),                         // nodes
         (size_t)bec::kMaxSums * nb_pw * sizeof(double),                             // partials
-        (size_t)3 * nb_x * sizeof(double),                                          // fft partials
+        (size_t)3 * (nb_x + nb_y + nb_z) * sizeof(double),                          // fft partials
         kScalSlots * sizeof(double),                                                // device scalar copies
         (size_t)bec::kLsEpiSums * nb_z * sizeof(double),                            // line-search partials
         2 * N * c2,                                                                 // pold
@@ -604,6 +605,8 @@ FftPassArgs pass_args(bec_ctx* c, int axis)
     A.scale = 1.0;
     A.partials = c->fft_partials;
     A.nblk_x = c->nblk_x;
+    A.kaxis = c->kv[axis];
+    A.pscale = 1.0;
     A.n_inst = 1;
     A.inst_ids = nullptr;
     for (int f = 0; f < 3; ++f) A.src_stride[f] = A.dst_stride[f] = A.src_sel_stride[f] = 0;
@@ -624,11 +627,24 @@ FftPassArgs pass_args(bec_ctx* c, int axis)
     return A;
 }
 
+// Where a pass with kOpParsevalAxis fields writes its block sums: `partials`
+// with block stride `stride`, each sum times `pscale` (N / n_axis).
+struct ParsevalOut {
+    double* partials;
+    int stride;
+    double pscale;
+};
+
 bec_status run_pass(bec_ctx* c, int axis, const double2* const* src, double2* const* dst, int nf, int sign,
                     double scale, const int* ops, const double* prec_a, const double* prec_state = nullptr,
-                    double prec_sigma = 0.0)
+                    double prec_sigma = 0.0, const ParsevalOut* po = nullptr)
 {
     FftPassArgs A = pass_args(c, axis);
+    if (po) {
+        A.partials = po->partials;
+        A.nblk_x = po->stride;
+        A.pscale = po->pscale;
+    }
     A.nfield = nf;
     A.sign = sign;
     A.scale = scale;
@@ -645,12 +661,14 @@ bec_status run_pass(bec_ctx* c, int axis, const double2* const* src, double2* co
     // algorithmic bytes: every field read once and (unless a Parseval field) written once
     double bytes = 0.0;
     const char* name = "fft";
-    for (int f = 0; f < nf; ++f) bytes += (double)c->N * ((ops && ops[f] == bec::kOpParseval) ? 16.0 : 32.0);
-    if (ops) name = "fft_x_kspace";
-    else if (axis == 2) name = sign < 0 ? "fft_z_fwd" : "fft_z_inv";
-    else if (axis == 1) name = sign < 0 ? "fft_y_fwd" : "fft_y_inv";
+    for (int f = 0; f < nf; ++f)
+        bytes += (double)c->N * ((ops && (ops[f] == bec::kOpParseval || ops[f] == bec::kOpParsevalAxis)) ? 16.0 : 32.0);
+    const bool kspace = ops && axis == 0;    // the x pass with per-field operators; other passes: forward plain
+    if (kspace) name = "fft_x_kspace";
+    else if (axis == 2) name = sign < 0 ? (ops ? "fft_z_fwd_ls" : "fft_z_fwd") : "fft_z_inv";
+    else if (axis == 1) name = sign < 0 ? (ops ? "fft_y_fwd_ls" : "fft_y_fwd") : "fft_y_inv";
     else name = sign < 0 ? "fft_x_fwd" : "fft_x_inv";
-    LAUNCH(c, name, bytes, bec::fft_pass(c->n[axis], c->fft_var[axis][ops ? 1 : 0], axis == 2, A, c->st));
+    LAUNCH(c, name, bytes, bec::fft_pass(c->n[axis], c->fft_var[axis][kspace ? 1 : 0], axis == 2, A, c->st));
     return BEC_OK;
 }
 
@@ -919,15 +937,26 @@ bec_status dir_write_launch(bec_ctx* c, const bec::DirArgs& A)
 bec_status model_launch(bec_ctx* c, const double norm2[2], double alpha_prev, double theta_max)
 {
     const long long N = c->N;
-    // Parseval sums <p_i, T p_i> from the forward transforms of p; the packed
-    // rho_1 + i rho_2 through the dipolar kernel, its last inverse pass fused
-    // with the model epilogue (K*rho is never stored)
+    // <p_i, T p_i> = sum over the axes a of <p_i, T_a p_i> (T is separable), each
+    // from the one-dimensional transform of p itself along a: read-only fields
+    // (kOpParsevalAxis) of the z, y and x passes that carry the packed
+    // rho_1 + i rho_2 through the dipolar kernel; its last inverse pass is fused
+    // with the model epilogue (K*rho is never stored).  The three passes write
+    // their block sums side by side, summed by one reduction.
     const double2* src[3] = {c->pdir, c->pdir + N, c->rho};
-    double2* dst[3] = {c->W, c->W + N, c->W + 2 * N};
-    const int ops[3] = {bec::kOpParseval, bec::kOpParseval, bec::kOpMulDip};
-    STCHK(run_pass(c, 2, src, dst, 3, -1, 1.0, nullptr, nullptr));
-    STCHK(run_pass(c, 1, dst, dst, 3, -1, 1.0, nullptr, nullptr));
-    STCHK(run_pass(c, 0, dst, dst, 3, -1, 1.0, ops, nullptr));
+    const double2* src_p[3] = {c->pdir, c->pdir + N, c->W + 2 * N};
+    double2* dst[3] = {c->W, c->W + N, c->W + 2 * N};    // dst[0..1]: not written
+    const int ops_a[3] = {bec::kOpParsevalAxis, bec::kOpParsevalAxis, bec::kOpPlain};
+    const int ops[3] = {bec::kOpParsevalAxis, bec::kOpParsevalAxis, bec::kOpMulDip};
+    const int nbz = bec::fft_blocks(c->n[2], c->fft_var[2][0], (long long)c->n[0] * c->n[1]);
+    const int nby = bec::fft_blocks(c->n[1], c->fft_var[1][0], (long long)c->n[0] * c->n[2]);
+    const int nbp = nbz + nby + c->nblk_x;
+    const ParsevalOut pz{c->fft_partials, nbp, (double)c->n[0] * c->n[1]};
+    const ParsevalOut py{c->fft_partials + nbz, nbp, (double)c->n[0] * c->n[2]};
+    const ParsevalOut px{c->fft_partials + nbz + nby, nbp, (double)c->n[1] * c->n[2]};
+    STCHK(run_pass(c, 2, src, dst, 3, -1, 1.0, ops_a, nullptr, nullptr, 0.0, &pz));
+    STCHK(run_pass(c, 1, src_p, dst, 3, -1, 1.0, ops_a, nullptr, nullptr, 0.0, &py));
+    STCHK(run_pass(c, 0, src_p, dst, 3, -1, 1.0, ops, nullptr, nullptr, 0.0, &px));
     STCHK(run_pass(c, 1, dst + 2, dst + 2, 1, +1, 1.0, nullptr, nullptr));
     bec::FftPassArgs zA = pass_args(c, 2);
     zA.nfield = 1;
@@ -938,10 +967,10 @@ bec_status model_launch(bec_ctx* c, const double norm2[2], double alpha_prev, do
            bec::fft_zinv_ls_pass(c->n[2], c->fft_var[2][0], zA, c->rho, c->ls_partials, c->st));
     const int o = kScalModel;
     const bec::RedSeg s1{c->partials, c->nblk_pw, bec::kDirWriteSums, c->scal + o, c->dscal + o};
-    const bec::RedSeg s2{c->fft_partials, c->nblk_x, 2, c->scal + o + kParsevalOut, c->dscal + o + kParsevalOut};
+    const bec::RedSeg s2{c->fft_partials, nbp, 2, c->scal + o + kParsevalOut, c->dscal + o + kParsevalOut};
     const bec::RedSeg s3{c->ls_partials, nblk_z, bec::kLsEpiSums, c->scal + o + bec::kDirWriteSums,
                          c->dscal + o + bec::kDirWriteSums};
-    LAUNCH(c, "reduce_final", 8.0 * (bec::kDirWriteSums * c->nblk_pw + 2 * c->nblk_x + bec::kLsEpiSums * nblk_z),
+    LAUNCH(c, "reduce_final", 8.0 * (bec::kDirWriteSums * c->nblk_pw + 2 * nbp + bec::kLsEpiSums * nblk_z),
            bec::launch_reduce_segs(s1, s2, s3, c->st));
     bec::StepArgs st{};
     st.D = c->dscal + o;

@@ -82,13 +82,18 @@ enum FftOp : int {
     kOpMulDip = 2,      // forward, times Ud(k)/N, inverse, store
     kOpMulPrec = 3,     // forward, times 1/(a_f + |k|^2/2)/N, inverse, store
     kOpParseval = 4,    // forward, accumulate sum |k|^2/2 |v|^2, no store
-    kOpExpKin = 5       // forward, accumulate as kOpParseval, times exp(-a_f |k|^2/2)/N, inverse, store
+    kOpExpKin = 5,      // forward, accumulate as kOpParseval, times exp(-a_f |k|^2/2)/N, inverse, store
+    // forward along the pass axis only (any pass), accumulate pscale * sum k_a^2/2 |v|^2
+    // (k_a the wavenumber of that axis), no store.  T is separable, so the three axis
+    // terms of <p, T p>, each from a one-dimensional transform of p itself, add up to
+    // the kOpParseval sum when pscale = N / n_a
+    kOpParsevalAxis = 6
 };
 
 struct FftPassArgs {
     const double2* src[3];
     double2* dst[3];
-    int op[3];             // per field (only the x pass uses ops other than Plain)
+    int op[3];             // per field (the x pass; the other forward passes: Plain or ParsevalAxis)
     double prec_a[3];      // per field shift for kOpMulPrec
     int nfield;
     long long S;           // stride between successive pencil elements
@@ -103,8 +108,10 @@ struct FftPassArgs {
     const double* kz;
     const double* udtab;   // dipolar kernel on the k octant [nx/2+1][ny/2+1][nz/2+1]
     double inv_n;          // 1/(nx ny nz)
-    double* partials;      // kOpParseval: [instance][field][block]
-    int nblk_x;
+    double* partials;      // kOpParseval / kOpParsevalAxis: [instance][field][block]
+    int nblk_x;            // block stride of `partials`
+    const double* kaxis;   // kOpParsevalAxis: wavenumbers of the pass axis
+    double pscale;         // kOpParsevalAxis: factor of the block sums
     // batched passes: grid.z = instance; field f of instance i starts at
     // src[f] + i * src_stride[f] (+ src_sel[i] * src_sel_stride[f]) and
     // dst[f] + i * dst_stride[f]; per-instance k / dipolar tables when

@@ -270,6 +270,24 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
     constexpr int RL = PL::RL;
     if (KMODE < 2) {
         PL::template fwd_like<KMODE == 0 ? -1 : +1>(v, row, t, tw);
+        if (KMODE == 0 && A.op[f] == kOpParsevalAxis) {      // uniform per block (f = blockIdx.y)
+            double acc = 0.0;
+#pragma unroll
+            for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+                for (int r = 0; r < RL; ++r) {
+                    const int j = t + b * T + r * (L / RL);
+                    const double k = A.kaxis[j];
+                    const double2 w = v[b * RL + r];
+                    acc += 0.5 * (k * k) * (w.x * w.x + w.y * w.y);
+                }
+            if (!valid) acc = 0.0;
+            __syncthreads();
+            const double tot = block_sum<NTHR>(acc, reinterpret_cast<double*>(lds));
+            if (threadIdx.x == 0)
+                A.partials[((long long)inst * A.nfield + f) * A.nblk_x + blockIdx.x] = tot * A.pscale;
+            return;
+        }
         if (valid) {
             const double sc = A.scale;
 #pragma unroll
@@ -298,7 +316,7 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
         ay = iy <= A.ny / 2 ? iy : A.ny - iy;
         az = iz <= A.nz / 2 ? iz : A.nz - iz;
     }
-    if (op == kOpParseval || op == kOpExpKin) {
+    if (op == kOpParseval || op == kOpExpKin || op == kOpParsevalAxis) {
         double acc = 0.0;
 #pragma unroll
         for (int b = 0; b < E / RL; ++b)
@@ -307,13 +325,16 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
                 const int j = t + b * T + r * (L / RL);
                 const double kx = kxt[j];
                 const double2 w = v[b * RL + r];
-                acc += 0.5 * (kx * kx + ky2 + kz2) * (w.x * w.x + w.y * w.y);
+                const double kk = op == kOpParsevalAxis ? kx * kx : kx * kx + ky2 + kz2;
+                acc += 0.5 * kk * (w.x * w.x + w.y * w.y);
             }
         if (!valid) acc = 0.0;
         __syncthreads();
         const double tot = block_sum<NTHR>(acc, reinterpret_cast<double*>(lds));
-        if (threadIdx.x == 0) A.partials[((long long)inst * A.nfield + f) * A.nblk_x + blockIdx.x] = tot;
-        if (op == kOpParseval) return;
+        if (threadIdx.x == 0)
+            A.partials[((long long)inst * A.nfield + f) * A.nblk_x + blockIdx.x] =
+                op == kOpParsevalAxis ? tot * A.pscale : tot;
+        if (op == kOpParseval || op == kOpParsevalAxis) return;
         __syncthreads();                               // lds is reused by the inverse transform
     }
     const double inv_n = A.inv_n;
@@ -544,8 +565,14 @@ hipError_t launch_cfg(bool contiguous, const FftPassArgs& A, hipStream_t st)
 {
     constexpr int PB = NTHR / T;
     dim3 grid((unsigned)((A.npencil + PB - 1) / PB), (unsigned)A.nfield, (unsigned)(A.n_inst > 0 ? A.n_inst : 1));
-    bool plain = true;
-    for (int f = 0; f < A.nfield; ++f) plain = plain && A.op[f] == kOpPlain;
+    // plain: every field Plain or ParsevalAxis (a one-axis pass; ParsevalAxis
+    // fields only in a forward pass); otherwise the fused x pass
+    bool plain = true, axis_sums = false;
+    for (int f = 0; f < A.nfield; ++f) {
+        plain = plain && (A.op[f] == kOpPlain || A.op[f] == kOpParsevalAxis);
+        axis_sums = axis_sums || A.op[f] == kOpParsevalAxis;
+    }
+    if (plain && axis_sums && A.sign >= 0) return hipErrorInvalidValue;
     if (contiguous) {
         // the contiguous (z) axis is never the fused x pass
         if (!plain) return hipErrorInvalidValue;
