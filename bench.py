@@ -462,7 +462,8 @@ def main():
     tuning = {"mode": args.tuning, "plan": ctx.get_tuning()}
     if args.tuning == "auto":
         res = autotune.tune(ctx, psi0=psi0, opts=base_opts)
-        tuning.update(plan=res["tuning"], seconds=res["seconds"], iter_ms=res["iter_ms"])
+        tuning.update(plan=res["tuning"], seconds=res["seconds"], iter_ms=res["iter_ms"],
+                      iter_ms_variants=res["iter_ms_variants"])
     elif args.tuning == "cache":
         cached = autotune.load_cached(grid)
         if cached:

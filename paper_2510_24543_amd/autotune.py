@@ -67,7 +67,7 @@ def store(grid: dict, result: dict, path: str | None = None):
         json.dump(data, f, indent=1, sort_keys=True)
 
 
-def tune(ctx, reps: int = 20, iters: int = 4, psi0=None, opts: dict | None = None) -> dict:
+def tune(ctx, reps: int = 20, iters: int = 8, psi0=None, opts: dict | None = None) -> dict:
     """Tune ctx in place; returns {"tuning": ..., "fft_ms": ..., "iter_ms": ..., "seconds": ...}."""
     import torch
     t0 = time.time()
@@ -92,21 +92,39 @@ def tune(ctx, reps: int = 20, iters: int = 4, psi0=None, opts: dict | None = Non
     psi0 = ctx.field(psi0)
     o = dict(opts or {}, tol_grad=0.0, max_iter=iters)
     cap = min(PW_CHOICES[-1], (ctx.N + 255) // 256)
-    iter_ms = {}
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for b in PW_CHOICES:
-        if b > cap:
-            continue
-        best["pw_blocks"] = b
-        ctx.set_tuning(best)
+
+    def per_iter(plan):
+        ctx.set_tuning(plan)
         ctx.solve(psi0, dict(o, max_iter=1))
         torch.cuda.synchronize()
         ev0.record(ctx.stream)
         ctx.solve(psi0, o)
         ev1.record(ctx.stream)
         torch.cuda.synchronize()
-        iter_ms[b] = ev0.elapsed_time(ev1) / iters
+        return ev0.elapsed_time(ev1) / iters
+
+    iter_ms = {}
+    for b in PW_CHOICES:
+        if b > cap:
+            continue
+        best["pw_blocks"] = b
+        iter_ms[b] = per_iter(best)
     best["pw_blocks"] = int(min(iter_ms, key=iter_ms.get))
+    # the z, y and k-space x variants also run the passes with fused work (the trial
+    # update and the kinetic axis terms, the Parseval axis sums), which the single-pass
+    # timings above do not see: choose them over whole PCG iterations too
+    axis_ms = {}
+    for axis, slot in ((2, 0), (1, 0), (0, 1)):
+        L = ctx.grid["n"][axis]
+        if variant_count(L) < 2:
+            continue
+        t = []
+        for v in range(variant_count(L)):
+            best["fft_variant"][axis][slot] = v
+            t.append(per_iter(best))
+        best["fft_variant"][axis][slot] = int(min(range(len(t)), key=t.__getitem__))
+        axis_ms[f"axis{axis}" + ("_kspace" if slot else "")] = [round(x, 5) for x in t]
     ctx.set_tuning(best)
     return {"tuning": best, "fft_ms": fft_ms, "iter_ms": {str(k): round(v, 5) for k, v in iter_ms.items()},
-            "seconds": round(time.time() - t0, 3)}
+            "iter_ms_variants": axis_ms, "seconds": round(time.time() - t0, 3)}

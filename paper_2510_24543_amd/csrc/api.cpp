@@ -607,6 +607,8 @@ FftPassArgs pass_args(bec_ctx* c, int axis)
     A.nblk_x = c->nblk_x;
     A.kaxis = c->kv[axis];
     A.pscale = 1.0;
+    A.inv_na = 1.0 / (double)c->n[axis];
+    for (int f = 0; f < 3; ++f) A.acc[f] = nullptr;
     A.n_inst = 1;
     A.inst_ids = nullptr;
     for (int f = 0; f < 3; ++f) A.src_stride[f] = A.dst_stride[f] = A.src_sel_stride[f] = 0;
@@ -637,9 +639,11 @@ struct ParsevalOut {
 
 bec_status run_pass(bec_ctx* c, int axis, const double2* const* src, double2* const* dst, int nf, int sign,
                     double scale, const int* ops, const double* prec_a, const double* prec_state = nullptr,
-                    double prec_sigma = 0.0, const ParsevalOut* po = nullptr)
+                    double prec_sigma = 0.0, const ParsevalOut* po = nullptr, const double2* const* acc = nullptr)
 {
     FftPassArgs A = pass_args(c, axis);
+    if (acc)
+        for (int f = 0; f < nf; ++f) A.acc[f] = acc[f];
     if (po) {
         A.partials = po->partials;
         A.nblk_x = po->stride;
@@ -661,12 +665,21 @@ bec_status run_pass(bec_ctx* c, int axis, const double2* const* src, double2* co
     // algorithmic bytes: every field read once and (unless a Parseval field) written once
     double bytes = 0.0;
     const char* name = "fft";
-    for (int f = 0; f < nf; ++f)
-        bytes += (double)c->N * ((ops && (ops[f] == bec::kOpParseval || ops[f] == bec::kOpParsevalAxis)) ? 16.0 : 32.0);
-    const bool kspace = ops && axis == 0;    // the x pass with per-field operators; other passes: forward plain
-    if (kspace) name = "fft_x_kspace";
+    bool kin = false, axis_sums = false;
+    for (int f = 0; f < nf; ++f) {
+        const int op = ops ? ops[f] : bec::kOpPlain;
+        kin = kin || op == bec::kOpKinAxis;
+        axis_sums = axis_sums || op == bec::kOpParsevalAxis;
+        bytes += (double)c->N * ((op == bec::kOpParseval || op == bec::kOpParsevalAxis) ? 16.0
+                                 : (op == bec::kOpKinAxis && acc && acc[f]) ? 48.0 : 32.0);
+    }
+    const bool kspace = ops && axis == 0;    // the x pass with per-field operators
+    // one label per kind of launch: the energy evaluation's x pass (kinetic axis
+    // term + dipolar multiply), the line search's (Parseval axis sums + dipolar
+    // multiply), and the other k-space x passes (preconditioner, imaginary time)
+    if (kspace) name = kin ? "fft_x_kin" : axis_sums ? "fft_x_ls" : "fft_x_kspace";
     else if (axis == 2) name = sign < 0 ? (ops ? "fft_z_fwd_ls" : "fft_z_fwd") : "fft_z_inv";
-    else if (axis == 1) name = sign < 0 ? (ops ? "fft_y_fwd_ls" : "fft_y_fwd") : "fft_y_inv";
+    else if (axis == 1) name = sign < 0 ? (kin ? "fft_y_kin" : ops ? "fft_y_fwd_ls" : "fft_y_fwd") : "fft_y_inv";
     else name = sign < 0 ? "fft_x_fwd" : "fft_x_inv";
     LAUNCH(c, name, bytes, bec::fft_pass(c->n[axis], c->fft_var[axis][kspace ? 1 : 0], axis == 2, A, c->st));
     return BEC_OK;
@@ -704,9 +717,16 @@ bec_status kspace_apply(bec_ctx* c, const double2* const* src, double2* const* d
 // The same for the three fields (psi_1, psi_2, packed density) of the trial
 // point psi_dst = a_i psi_src + b_i p: the trial update rides in the loads of
 // the forward z pass, which also stores psi_dst.
+//
+// With the kinetic multiply on psi_1, psi_2 (ops MulKin, MulKin, MulDip) the
+// kinetic term uses T = T_x + T_y + T_z: the trial pass stores T_z psi_i, the
+// y and x passes that carry the density's forward transforms add T_y psi_i and
+// T_x psi_i from one-dimensional transforms of the stored trial point, and the
+// inverse y and z passes carry the density alone.
 bec_status kspace_apply_trial(bec_ctx* c, const bec::TrialZArgs& Z, double2* const* dst, const int* ops,
                               const double* prec_a)
 {
+    const bool kin_axes = ops[0] == bec::kOpMulKin && ops[1] == bec::kOpMulKin && ops[2] == bec::kOpMulDip;
     bec::FftPassArgs A = pass_args(c, 2);
     A.nfield = 3;
     A.sign = -1;
@@ -714,9 +734,21 @@ bec_status kspace_apply_trial(bec_ctx* c, const bec::TrialZArgs& Z, double2* con
         A.src[f] = dst[f];
         A.dst[f] = dst[f];
     }
+    bec::TrialZArgs Zk = Z;
+    Zk.kin_z = kin_axes ? 1 : 0;
     const double bytes = (double)c->N * ((Z.p ? 64.0 : 32.0) + 32.0 + 48.0);
-    LAUNCH(c, "fft_z_trial", bytes, bec::fft_trial_z_pass(c->n[2], c->fft_var[2][0], A, Z, c->st));
-    return kspace_after_z(c, dst, 3, ops, prec_a);
+    LAUNCH(c, "fft_z_trial", bytes, bec::fft_trial_z_pass(c->n[2], c->fft_var[2][0], A, Zk, c->st));
+    if (!kin_axes) return kspace_after_z(c, dst, 3, ops, prec_a);
+    const long long N = c->N;
+    const double2* src[3] = {Z.psi_dst, Z.psi_dst + N, dst[2]};
+    const double2* acc[3] = {dst[0], dst[1], nullptr};
+    const int ops_y[3] = {bec::kOpKinAxis, bec::kOpKinAxis, bec::kOpPlain};
+    const int ops_x[3] = {bec::kOpKinAxis, bec::kOpKinAxis, bec::kOpMulDip};
+    STCHK(run_pass(c, 1, src, dst, 3, -1, 1.0, ops_y, prec_a, nullptr, 0.0, nullptr, acc));
+    STCHK(run_pass(c, 0, src, dst, 3, -1, 1.0, ops_x, prec_a, nullptr, 0.0, nullptr, acc));
+    STCHK(run_pass(c, 1, dst + 2, dst + 2, 1, +1, 1.0, nullptr, nullptr));
+    STCHK(run_pass(c, 2, dst + 2, dst + 2, 1, +1, 1.0, nullptr, nullptr));
+    return BEC_OK;
 }
 
 bec_status kspace_after_z(bec_ctx* c, double2* const* dst, int nf, const int* ops, const double* prec_a,

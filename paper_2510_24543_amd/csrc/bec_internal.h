@@ -87,7 +87,10 @@ enum FftOp : int {
     // (k_a the wavenumber of that axis), no store.  T is separable, so the three axis
     // terms of <p, T p>, each from a one-dimensional transform of p itself, add up to
     // the kOpParseval sum when pscale = N / n_a
-    kOpParsevalAxis = 6
+    kOpParsevalAxis = 6,
+    // forward along the pass axis, times k_a^2/2 / n_a, inverse, plus acc[f] (if set), store:
+    // the axis term T_a of the separable kinetic operator, accumulated over the passes
+    kOpKinAxis = 7
 };
 
 struct FftPassArgs {
@@ -110,8 +113,10 @@ struct FftPassArgs {
     double inv_n;          // 1/(nx ny nz)
     double* partials;      // kOpParseval / kOpParsevalAxis: [instance][field][block]
     int nblk_x;            // block stride of `partials`
-    const double* kaxis;   // kOpParsevalAxis: wavenumbers of the pass axis
+    const double* kaxis;   // kOpParsevalAxis, kOpKinAxis: wavenumbers of the pass axis
     double pscale;         // kOpParsevalAxis: factor of the block sums
+    double inv_na;         // kOpKinAxis: 1 / (length of the pass axis)
+    const double2* acc[3]; // kOpKinAxis: field added to the result (may be the destination itself)
     // batched passes: grid.z = instance; field f of instance i starts at
     // src[f] + i * src_stride[f] (+ src_sel[i] * src_sel_stride[f]) and
     // dst[f] + i * dst_stride[f]; per-instance k / dipolar tables when
@@ -145,6 +150,8 @@ struct TrialZArgs {
     double norm_dV;
     double2* psi_dst;             // 2N (may equal psi_src)
     long long N;                  // points per component
+    int kin_z;                    // 1: store T_z psi_i (forward, times k_z^2/2 / n_z, inverse) for
+                                  // i = 1, 2 instead of their forward z transforms
 };
 hipError_t fft_trial_z_pass(int L, int variant, const FftPassArgs& args, const TrialZArgs& z, hipStream_t s);
 

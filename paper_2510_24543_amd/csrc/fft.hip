@@ -303,6 +303,19 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
 
     // x pass with a diagonal k-space operator: forward, then op
     PL::template fwd_like<-1>(v, row, t, tw);
+    if (op == kOpPlain) {                              // a forward-only field of a mixed pass
+        if (valid) {
+            const double sc = A.scale;
+#pragma unroll
+            for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+                for (int r = 0; r < RL; ++r) {
+                    const int j = t + b * T + r * (L / RL);
+                    dst[base + (long long)j * S] = sc == 1.0 ? v[b * RL + r] : cscale(v[b * RL + r], sc);
+                }
+        }
+        return;
+    }
     const double* __restrict__ kxt = A.kx + (A.per_inst_tab ? (long long)inst * A.nx : 0);
     const double* __restrict__ udt = A.udtab + (A.per_inst_tab ? (long long)inst * A.udsize : 0);
     double ky2 = 0.0, kz2 = 0.0;
@@ -359,14 +372,37 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
             } else if (op == kOpMulDip) {
                 const int ax = j <= L / 2 ? j : L - j;
                 m = udt[((long long)ax * (A.ny / 2 + 1) + ay) * (A.nz / 2 + 1) + az];
+            } else if (op == kOpKinAxis) {
+                const double k = A.kaxis[j];
+                m = 0.5 * (k * k);
             } else {
                 const double kx = kxt[j];
                 m = 1.0 / (pa + 0.5 * (kx * kx + ky2 + kz2));
             }
-            v[b * RL + r] = cscale(v[b * RL + r], m * inv_n);
+            v[b * RL + r] = cscale(v[b * RL + r], m * (op == kOpKinAxis ? A.inv_na : inv_n));
         }
     PL::inv_rev(v, row, t, tw);
     if (valid) {
+        if (op == kOpKinAxis && A.acc[f]) {
+            // acc may be the destination: every value is read before it is stored, through
+            // pointers without the restrict qualifier
+            const double2* acc = A.acc[f] + doff;
+            double2* out = A.dst[f] + doff;
+            double2 q[E];
+#pragma unroll
+            for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+                for (int r = 0; r < R0; ++r) q[b * R0 + r] = acc[base + (long long)(t + b * T + r * (L / R0)) * S];
+#pragma unroll
+            for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+                for (int r = 0; r < R0; ++r) {
+                    const int j = t + b * T + r * (L / R0);
+                    const double2 o = v[b * R0 + r], a = q[b * R0 + r];
+                    out[base + (long long)j * S] = make_double2(o.x + a.x, o.y + a.y);
+                }
+            return;
+        }
 #pragma unroll
         for (int b = 0; b < E / R0; ++b)
 #pragma unroll
@@ -374,6 +410,30 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
                 const int j = t + b * T + r * (L / R0);
                 dst[base + (long long)j * S] = v[b * R0 + r];
             }
+    }
+}
+
+// T_z of one component held in registers after its forward z transform: times
+// k_z^2/2 / n_z, inverse z transform, stored in natural order.
+template <int L, int T, int R0, int R1, int R2>
+__device__ __forceinline__ void kin_z_store(double2* w, double2* row, int t, const FftPassArgs& A, double2* d,
+                                            long long base, bool valid)
+{
+    using PL = Plan<L, T, R0, R1, R2>;
+    constexpr int E = L / T, RL = PL::RL;
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const double k = A.kaxis[t + b * T + r * (L / RL)];
+            w[b * RL + r] = cscale(w[b * RL + r], 0.5 * (k * k) * A.inv_na);
+        }
+    PL::inv_rev(w, row, t, A.tw);
+    if (valid) {
+#pragma unroll
+        for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) d[base + t + b * T + r * (L / R0)] = w[b * R0 + r];
     }
 }
 
@@ -430,7 +490,9 @@ __device__ __forceinline__ void trial_z_body(const FftPassArgs& A, const TrialZA
             dn0[k] = w0[k].x * w0[k].x + w0[k].y * w0[k].y;
         }
     PL::template fwd_like<-1>(w0, row, t, A.tw);
-    if (valid) {
+    if (Z.kin_z) {
+        kin_z_store<L, T, R0, R1, R2>(w0, row, t, A, d0, base, valid);
+    } else if (valid) {
 #pragma unroll
         for (int b = 0; b < E / RL; ++b)
 #pragma unroll
@@ -440,7 +502,9 @@ __device__ __forceinline__ void trial_z_body(const FftPassArgs& A, const TrialZA
 #pragma unroll
     for (int k = 0; k < E; ++k) w0[k] = make_double2(dn0[k], w1[k].x * w1[k].x + w1[k].y * w1[k].y);
     PL::template fwd_like<-1>(w1, row, t, A.tw);
-    if (valid) {
+    if (Z.kin_z) {
+        kin_z_store<L, T, R0, R1, R2>(w1, row, t, A, d1, base, valid);
+    } else if (valid) {
 #pragma unroll
         for (int b = 0; b < E / RL; ++b)
 #pragma unroll
@@ -501,6 +565,7 @@ __global__ __launch_bounds__(NTHR) void fft_btrial_z_kernel(FftPassArgs A, BGrou
     Z.norm_sums = nullptr;
     Z.psi_dst = g.psi + ((long long)l * 2 + (1 - S.cur)) * 2 * N;
     Z.N = N;
+    Z.kin_z = 0;
     double2* w = g.W + (long long)l * 3 * N;
     trial_z_body<L, T, R0, R1, R2, NTHR>(A, Z, w, w + N, w + 2 * N, lds);
 }
