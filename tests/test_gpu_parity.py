@@ -233,12 +233,14 @@ def test_preconditioners(solver, orc, pc):
 @pytest.mark.parametrize("n", [8, 16, 32, 48, 64, 96, 128, 256])
 def test_every_variant_of_the_fused_passes(solver, orc, n):
     """Every plan variant of the passes with fused work: the x pass with the
-    k-space operators (slot [0][1]) and the z passes that carry the trial update
-    and the line-search epilogue (slot [2][0]), on a grid that is n long along
-    that axis; energy, H psi and the line-search model and trial against the oracle."""
+    k-space operators (slot [0][1]), the y passes that add the kinetic axis term
+    and the Parseval axis sums (slot [1][0]) and the z passes that carry the
+    trial update, the kinetic axis term and the line-search epilogue (slot
+    [2][0]), on a grid that is n long along that axis; energy, H psi and the
+    line-search model and trial against the oracle."""
     from paper_2510_24543_amd import autotune
     params = small_params()
-    for axis, slot in ((0, (0, 1)), (2, (2, 0))):
+    for axis, slot in ((0, (0, 1)), (1, (1, 0)), (2, (2, 0))):
         shape = [8, 16, 8]
         shape[axis] = n
         grid = {"n": shape, "lo": [-6.0] * 3, "hi": [6.0] * 3}
