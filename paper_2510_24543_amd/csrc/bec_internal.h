@@ -96,7 +96,7 @@ enum FftOp : int {
 struct FftPassArgs {
     const double2* src[3];
     double2* dst[3];
-    int op[3];             // per field (the x pass; the other forward passes: Plain or ParsevalAxis)
+    int op[3];             // per field: any op in a fused (mode 2) pass; Plain or ParsevalAxis otherwise
     double prec_a[3];      // per field shift for kOpMulPrec
     int nfield;
     long long S;           // stride between successive pencil elements

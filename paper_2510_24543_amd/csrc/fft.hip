@@ -227,7 +227,9 @@ __device__ double block_sum(double v, double* sh)
     return r;
 }
 
-// KMODE: 0 forward plain pass, 1 inverse plain pass, 2 x pass with per-field ops.
+// KMODE: 0 forward plain pass (fields Plain or ParsevalAxis), 1 inverse plain pass, 2 fused pass with
+// per-field ops: forward, operator, inverse (the x pass; the y pass with kinetic axis terms); its
+// Plain fields are forward only.
 template <int L, int T, int R0, int R1, int R2, int NTHR, bool CONTIG, int KMODE>
 __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
 {
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
         return;
     }
 
-    // x pass with a diagonal k-space operator: forward, then op
+    // fused pass: forward, then the per-field operator
     PL::template fwd_like<-1>(v, row, t, tw);
     if (op == kOpPlain) {                              // a forward-only field of a mixed pass
         if (valid) {
@@ -631,7 +633,7 @@ hipError_t launch_cfg(bool contiguous, const FftPassArgs& A, hipStream_t st)
     constexpr int PB = NTHR / T;
     dim3 grid((unsigned)((A.npencil + PB - 1) / PB), (unsigned)A.nfield, (unsigned)(A.n_inst > 0 ? A.n_inst : 1));
     // plain: every field Plain or ParsevalAxis (a one-axis pass; ParsevalAxis
-    // fields only in a forward pass); otherwise the fused x pass
+    // fields only in a forward pass); otherwise the fused pass (mode 2)
     bool plain = true, axis_sums = false;
     for (int f = 0; f < A.nfield; ++f) {
         plain = plain && (A.op[f] == kOpPlain || A.op[f] == kOpParsevalAxis);
@@ -639,7 +641,7 @@ hipError_t launch_cfg(bool contiguous, const FftPassArgs& A, hipStream_t st)
     }
     if (plain && axis_sums && A.sign >= 0) return hipErrorInvalidValue;
     if (contiguous) {
-        // the contiguous (z) axis is never the fused x pass
+        // the contiguous (z) axis never runs the fused mode
         if (!plain) return hipErrorInvalidValue;
         if (A.sign < 0)
             hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, true, 0>), grid, dim3(NTHR), 0, st, A);
