@@ -1903,6 +1903,7 @@ struct BatchGroup {
     int n[3] = {0, 0, 0};
     long long N = 0;
     int first = 0, count = 0, nblk = 0, nblk_x = 0;
+    int nblk_pz = 0, nblk_py = 0;  // blocks of the z and y passes (Parseval axis sums of the line search)
     int var[3] = {0, 0, 0};        // FFT plan variant per axis (the x pass is always the k-space pass)
     double2 *psi = nullptr, *hpsi = nullptr, *aux = nullptr, *p = nullptr, *r_old = nullptr, *rho = nullptr,
             *W = nullptr;
@@ -2021,12 +2022,14 @@ size_t batch_layout(int n_inst, const bec_grid* grids, std::vector<size_t>* off)
         const long long cnt = r.second;
         const int nblk = group_nblk(N);
         const int nbx = bec::fft_max_blocks(g.n[0], (long long)g.n[1] * g.n[2]);   // any plan variant
+        const int nby = bec::fft_max_blocks(g.n[1], (long long)g.n[0] * g.n[2]);
+        const int nbz = bec::fft_max_blocks(g.n[2], (long long)g.n[0] * g.n[1]);
         const size_t ud = (size_t)(g.n[0] / 2 + 1) * (g.n[1] / 2 + 1) * (g.n[2] / 2 + 1);
         size_t gs[] = {cnt * 4 * N * c2, cnt * 4 * N * c2, cnt * 4 * N * c2,  // psi, hpsi, aux (2 buffers)
                        cnt * 2 * N * c2, cnt * 2 * N * c2, cnt * N * c2,      // p, r_old, rho
                        cnt * 3 * N * c2,                                      // W
                        (size_t)cnt * bec::kMaxSums * nblk * sizeof(double),   // partials
-                       (size_t)cnt * 3 * nbx * sizeof(double),                // fft partials
+                       (size_t)cnt * 3 * (nbx + nby + nbz) * sizeof(double),  // fft partials
                        cnt * ud * sizeof(double),                             // dipolar tables
                        cnt * g.n[0] * sizeof(double), cnt * g.n[1] * sizeof(double), cnt * g.n[2] * sizeof(double),
                        cnt * g.n[0] * sizeof(double), cnt * g.n[1] * sizeof(double), cnt * g.n[2] * sizeof(double),
@@ -2094,6 +2097,8 @@ FftPassArgs batch_pass_args(const BatchGroup& G, int axis, const int* active)
     A.scale = 1.0;
     A.partials = G.fft_partials;
     A.nblk_x = G.nblk_x;
+    A.kaxis = G.kv[axis];
+    A.inv_na = 1.0 / (double)G.n[axis];
     A.n_inst = G.g.n_ids;
     A.inst_ids = G.g.ids;
     A.active = active + G.first;
@@ -2148,27 +2153,34 @@ bec_status batch_heval_fft(bec_batch* b, const BatchGroup& G, hipStream_t s)
     return bpass(b, G, A, 2, 3, +1);
 }
 
-// line-search FFTs: Parseval of p_1, p_2; packed dipolar convolution of rho
+// Block stride of a group's Parseval partials: the z, y and x passes of the
+// line search write theirs side by side.
+int batch_parseval_stride(const BatchGroup& G) { return G.nblk_pz + G.nblk_py + G.nblk_x; }
+
+// line-search FFTs: <p_i, T p_i> as the sum of its one-axis terms (kOpParsevalAxis:
+// p_1, p_2 read by each forward pass, nothing stored) while the passes carry the
+// packed dipolar convolution of rho
 bec_status batch_ls_fft(bec_batch* b, const BatchGroup& G)
 {
     const long long N = G.N;
-    FftPassArgs A = batch_pass_args(G, 2, b->act_dir);
-    A.src[0] = G.p;
-    A.src[1] = G.p + N;
-    A.src[2] = G.rho;
-    A.src_stride[0] = A.src_stride[1] = 2 * N;
-    A.src_stride[2] = N;
-    for (int f = 0; f < 3; ++f) A.dst[f] = G.W + f * N;
-    STCHK(bpass(b, G, A, 2, 3, -1));
-    A = batch_pass_args(G, 1, b->act_dir);
-    for (int f = 0; f < 3; ++f) A.src[f] = A.dst[f] = G.W + f * N;
-    STCHK(bpass(b, G, A, 1, 3, -1));
-    A = batch_pass_args(G, 0, b->act_dir);
-    for (int f = 0; f < 3; ++f) A.src[f] = A.dst[f] = G.W + f * N;
-    A.op[0] = A.op[1] = bec::kOpParseval;
-    A.op[2] = bec::kOpMulDip;
-    STCHK(bpass(b, G, A, 0, 3, -1));
-    A = batch_pass_args(G, 1, b->act_dir);
+    const int T = batch_parseval_stride(G);
+    const long long off[3] = {G.nblk_pz + G.nblk_py, G.nblk_pz, 0};   // per axis x, y, z
+    for (int axis = 2; axis >= 0; --axis) {
+        FftPassArgs A = batch_pass_args(G, axis, b->act_dir);
+        A.src[0] = G.p;
+        A.src[1] = G.p + N;
+        A.src_stride[0] = A.src_stride[1] = 2 * N;
+        A.src[2] = axis == 2 ? G.rho : G.W + 2 * N;
+        A.src_stride[2] = axis == 2 ? N : 3 * N;
+        for (int f = 0; f < 3; ++f) A.dst[f] = G.W + f * N;
+        A.op[0] = A.op[1] = bec::kOpParsevalAxis;
+        A.op[2] = axis == 0 ? bec::kOpMulDip : bec::kOpPlain;
+        A.partials = G.fft_partials + off[axis];
+        A.nblk_x = T;
+        A.pscale = (double)(N / G.n[axis]);
+        STCHK(bpass(b, G, A, axis, 3, -1));
+    }
+    FftPassArgs A = batch_pass_args(G, 1, b->act_dir);
     A.src[0] = A.dst[0] = G.W + 2 * N;
     STCHK(bpass(b, G, A, 1, 1, +1));
     A = batch_pass_args(G, 2, b->act_dir);
@@ -2211,7 +2223,8 @@ bec_status batch_round(bec_batch* b, const bec::BOpts& o)
         STCHK(batch_ls_fft(b, G));
         HIPCHK(bec::launch_b_ls_epi(G.g, b->st));
         STCHK(breduce(b, G, bec::kLsEpiSums, bec::kSL));
-        HIPCHK(bec::launch_b_reduce(G.fft_partials, 3LL * G.nblk_x, G.nblk_x, G.nblk_x, 2, G.g.ids, G.g.n_ids,
+        const int T = batch_parseval_stride(G);
+        HIPCHK(bec::launch_b_reduce(G.fft_partials, 3LL * T, T, T, 2, G.g.ids, G.g.n_ids,
                                     b->sums + (long long)G.first * bec::kBSumStride, bec::kSP, b->st));
     }
     HIPCHK(bec::launch_b_decide_step(b->n_inst, o, b->ip, b->state, b->sums, b->act_dir, b->act_trial, b->tsel,
@@ -2300,6 +2313,8 @@ bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_par
             G.count = r.second;
             G.nblk = group_nblk(G.N);
             G.nblk_x = bec::fft_blocks(G.n[0], 0, (long long)G.n[1] * G.n[2]);
+            G.nblk_py = bec::fft_blocks(G.n[1], 0, (long long)G.n[0] * G.n[2]);
+            G.nblk_pz = bec::fft_blocks(G.n[2], 0, (long long)G.n[0] * G.n[1]);
             G.udsize = (long long)(G.n[0] / 2 + 1) * (G.n[1] / 2 + 1) * (G.n[2] / 2 + 1);
             G.psi = (double2*)(base + off[k++]);
             G.hpsi = (double2*)(base + off[k++]);
@@ -2414,6 +2429,8 @@ bec_status bec_batch_set_tuning(bec_batch* b, const bec_grid* grid, const bec_tu
                 return fail(BEC_EINVAL, "axis %d: plan variant %d of length %d does not exist", d, v[d], G.n[d]);
         for (int d = 0; d < 3; ++d) G.var[d] = v[d];
         G.nblk_x = bec::fft_blocks(G.n[0], G.var[0], (long long)G.n[1] * G.n[2]);
+        G.nblk_py = bec::fft_blocks(G.n[1], G.var[1], (long long)G.n[0] * G.n[2]);
+        G.nblk_pz = bec::fft_blocks(G.n[2], G.var[2], (long long)G.n[0] * G.n[1]);
         ++matched;
     }
     if (!matched) return fail(BEC_EINVAL, "no instance has the grid %dx%dx%d", grid->n[0], grid->n[1], grid->n[2]);

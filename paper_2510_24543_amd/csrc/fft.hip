@@ -279,7 +279,7 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
 #pragma unroll
                 for (int r = 0; r < RL; ++r) {
                     const int j = t + b * T + r * (L / RL);
-                    const double k = A.kaxis[j];
+                    const double k = A.kaxis[(A.per_inst_tab ? (long long)inst * L : 0) + j];
                     const double2 w = v[b * RL + r];
                     acc += 0.5 * (k * k) * (w.x * w.x + w.y * w.y);
                 }
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
                 const int ax = j <= L / 2 ? j : L - j;
                 m = udt[((long long)ax * (A.ny / 2 + 1) + ay) * (A.nz / 2 + 1) + az];
             } else if (op == kOpKinAxis) {
-                const double k = A.kaxis[j];
+                const double k = A.kaxis[(A.per_inst_tab ? (long long)inst * L : 0) + j];
                 m = 0.5 * (k * k);
             } else {
                 const double kx = kxt[j];
