@@ -285,6 +285,11 @@ typedef struct {
                                    degree 5/2), when those series match the node sum to 2e-14 of
                                    its range at creation; 0: the node loop */
     int32_t lhy_terms;          /* out: terms per series in use (0: node loop); ignored on set */
+    int32_t kin_axes;           /* 1 (default): the kinetic term of the energy evaluation as
+                                   T_x + T_y + T_z from one-dimensional transforms inside the trial,
+                                   y and x passes; 0: the 3D multiply in the x pass (fewer
+                                   transforms per pencil: faster on small, launch-bound grids).
+                                   Not used by bec_batch_set_tuning */
 } bec_tuning;
 
 bec_status bec_get_tuning(bec_ctx* ctx, bec_tuning* out_h);

@@ -105,9 +105,7 @@ def tune(ctx, reps: int = 20, iters: int = 8, psi0=None, opts: dict | None = Non
         return ev0.elapsed_time(ev1) / iters
 
     iter_ms = {}
-    for b in PW_CHOICES:
-        if b > cap:
-            continue
+    for b in [c for c in PW_CHOICES if c <= cap] or [cap]:   # small grids: one block per 256 points
         best["pw_blocks"] = b
         iter_ms[b] = per_iter(best)
     best["pw_blocks"] = int(min(iter_ms, key=iter_ms.get))
@@ -125,6 +123,14 @@ def tune(ctx, reps: int = 20, iters: int = 8, psi0=None, opts: dict | None = Non
             t.append(per_iter(best))
         best["fft_variant"][axis][slot] = int(min(range(len(t)), key=t.__getitem__))
         axis_ms[f"axis{axis}" + ("_kspace" if slot else "")] = [round(x, 5) for x in t]
+    # the kinetic term from one-axis transforms (less traffic, more transforms per pencil in
+    # the trial pass) against the 3D multiply (pays off on launch-bound small grids)
+    t = []
+    for k in (0, 1):
+        best["kin_axes"] = k
+        t.append(per_iter(best))
+    best["kin_axes"] = int(t[1] <= t[0])
+    axis_ms["kin_axes"] = [round(x, 5) for x in t]
     ctx.set_tuning(best)
     return {"tuning": best, "fft_ms": fft_ms, "iter_ms": {str(k): round(v, 5) for k, v in iter_ms.items()},
             "iter_ms_variants": axis_ms, "seconds": round(time.time() - t0, 3)}

@@ -192,6 +192,7 @@ struct bec_ctx {
     std::vector<double> lhy_host = std::vector<double>(3 * bec::kLhyTabMax, 0.0);
     int lhy_K_built = 0;       // terms per series of the built table (0: none met the bar)
     int lhy_table_on = 1;      // tuning: use the table when built
+    int kin_axes_on = 1;       // tuning: kinetic term of the energy evaluation from one-axis transforms
     int nblk_pw = 0;
     int nblk_x = 0;
     int fft_var[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // plan variant per axis: [plain, fused k-space]
@@ -726,7 +727,8 @@ bec_status kspace_apply(bec_ctx* c, const double2* const* src, double2* const* d
 bec_status kspace_apply_trial(bec_ctx* c, const bec::TrialZArgs& Z, double2* const* dst, const int* ops,
                               const double* prec_a)
 {
-    const bool kin_axes = ops[0] == bec::kOpMulKin && ops[1] == bec::kOpMulKin && ops[2] == bec::kOpMulDip;
+    const bool kin_axes =
+        c->kin_axes_on && ops[0] == bec::kOpMulKin && ops[1] == bec::kOpMulKin && ops[2] == bec::kOpMulDip;
     bec::FftPassArgs A = pass_args(c, 2);
     A.nfield = 3;
     A.sign = -1;
@@ -1270,6 +1272,7 @@ bec_status bec_get_tuning(bec_ctx* c, bec_tuning* t)
     t->pw_blocks = c->nblk_pw;
     t->lhy_table = c->lhy_table_on;
     t->lhy_terms = c->P.lhy_K;
+    t->kin_axes = c->kin_axes_on;
     return BEC_OK;
 }
 
@@ -1288,6 +1291,7 @@ bec_status bec_set_tuning(bec_ctx* c, const bec_tuning* t)
     c->P.nblk_pw = c->nblk_pw;
     c->lhy_table_on = t->lhy_table != 0;
     c->P.lhy_K = c->lhy_table_on ? c->lhy_K_built : 0;
+    c->kin_axes_on = t->kin_axes != 0;
     c->nblk_x = bec::fft_blocks(c->n[0], c->fft_var[0][1], (long long)c->n[1] * c->n[2]);
     return BEC_OK;
 }

@@ -165,7 +165,8 @@ class Context:
         t = B.Tuning()
         B.check(B.lib().bec_get_tuning(self._ctx, C.byref(t)), "bec_get_tuning")
         return {"fft_variant": [[t.fft_variant[a][k] for k in range(2)] for a in range(3)],
-                "pw_blocks": t.pw_blocks, "lhy_table": t.lhy_table, "lhy_terms": t.lhy_terms}
+                "pw_blocks": t.pw_blocks, "lhy_table": t.lhy_table, "lhy_terms": t.lhy_terms,
+                "kin_axes": t.kin_axes}
 
     def set_tuning(self, tuning: dict):
         t = B.Tuning()
@@ -174,6 +175,7 @@ class Context:
                 t.fft_variant[a][k] = int(tuning["fft_variant"][a][k])
         t.pw_blocks = int(tuning["pw_blocks"])
         t.lhy_table = int(tuning.get("lhy_table", 1))
+        t.kin_axes = int(tuning.get("kin_axes", 1))
         B.check(B.lib().bec_set_tuning(self._ctx, C.byref(t)), "bec_set_tuning")
 
     def time_fft_pass(self, axis: int, kind: int, variant: int, reps: int = 20) -> float:

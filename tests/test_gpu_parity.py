@@ -165,6 +165,33 @@ def test_energy_and_hamiltonian(solver, orc, case, phase):
     assert rel(h.cpu().numpy(), ho) < 1e-11
 
 
+@pytest.mark.parametrize("case", ["C1b", "mixedN", "smallcut_aniso"])
+def test_kinetic_3d_multiply_path(solver, orc, case):
+    """kin_axes = 0 (the autotuner's choice on small grids): the kinetic term of
+    the energy evaluation from the 3D multiply in the x pass, against the oracle
+    and against the one-axis path, including ten solver iterations."""
+    grid, params = CASES[case]
+    psi = _state(grid, params, 19, True)
+    ctx = solver.Context(grid, params)
+    t1 = ctx.get_tuning()
+    assert t1["kin_axes"] == 1
+    h1, e1 = ctx.hamiltonian(torch.from_numpy(psi))
+    ctx.set_tuning(dict(t1, kin_axes=0))
+    assert ctx.get_tuning()["kin_axes"] == 0
+    h0, e0 = ctx.hamiltonian(torch.from_numpy(psi))
+    to, ho, _, _ = orc.heval(grid, params, psi)
+    assert abs(e0["E"] - to["E"]) <= 1e-12 * abs(to["E"])
+    assert abs(e0["E"] - e1["E"]) <= 1e-12 * abs(to["E"])
+    assert rel(h0.cpu().numpy(), ho) < 1e-11 and rel(h0.cpu().numpy(), h1.cpu().numpy()) < 1e-11
+    psi0 = _state(grid, params, 20, False)
+    opts = {"tol_grad": 1e-10, "pc": 1, "max_iter": 10}
+    _, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=16)
+    _, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=16)
+    assert rep["iters"] == repo["iters"]
+    for a, b in zip(log, logo):
+        assert abs(a["E"] - b["E"]) <= 1e-11 * abs(b["E"])
+
+
 @pytest.mark.parametrize("case", ["C1b", "mixedN"])
 def test_gradient(solver, orc, case):
     grid, params = CASES[case]
