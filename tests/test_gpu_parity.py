@@ -165,6 +165,26 @@ def test_energy_and_hamiltonian(solver, orc, case, phase):
     assert rel(h.cpu().numpy(), ho) < 1e-11
 
 
+@pytest.mark.parametrize("shape", [(16, 16, 16), (32, 32, 32)])
+def test_autotune_small_grids(solver, orc, shape):
+    """The autotuner on grids below 256 points per pointwise block of its smallest
+    grid choice: it takes one block per 256 points, picks every switch over whole
+    iterations, and the tuned context still matches the oracle."""
+    from paper_2510_24543_amd import autotune
+    grid = {"n": list(shape), "lo": [-6.0] * 3, "hi": [6.0] * 3}
+    params = small_params()
+    ctx = solver.Context(grid, params)
+    res = autotune.tune(ctx, iters=2)
+    t = ctx.get_tuning()
+    assert t["pw_blocks"] == res["tuning"]["pw_blocks"] <= (int(np.prod(shape)) + 255) // 256
+    assert t["kin_axes"] in (0, 1) and len(res["iter_ms_variants"]["kin_axes"]) == 2
+    psi = _state(grid, params, 21, True)
+    h, e = ctx.hamiltonian(torch.from_numpy(psi))
+    to, ho, _, _ = orc.heval(grid, params, psi)
+    assert abs(e["E"] - to["E"]) <= 1e-12 * abs(to["E"])
+    assert rel(h.cpu().numpy(), ho) < 1e-11
+
+
 @pytest.mark.parametrize("case", ["C1b", "mixedN", "smallcut_aniso"])
 def test_kinetic_3d_multiply_path(solver, orc, case):
     """kin_axes = 0 (the autotuner's choice on small grids): the kinetic term of
