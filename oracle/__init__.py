@@ -17,7 +17,9 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB_PATH loads another build of oracle.c instead (the mutation test of
+# tests/test_oracle_mutations.py builds copies with planted mistakes).
+_LIB_PATH = os.environ.get("ORACLE_LIB_PATH") or os.path.join(_HERE, "liboracle.so")
 _SRC_PATH = os.path.join(_HERE, "oracle.c")
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 4: "ENOTCONV", 5: "ESTAGNATED", 6: "ENONFINITE"}
@@ -68,7 +70,10 @@ class Iter(C.Structure):
     _fields_ = [("iter", C.c_int32), ("n_trials", C.c_int32), ("restarted", C.c_int32),
                 ("path", C.c_int32), ("E", C.c_double), ("res_max", C.c_double),
                 ("E1", C.c_double), ("E2", C.c_double), ("alpha", C.c_double),
-                ("beta", C.c_double)]
+                ("beta", C.c_double), ("level", C.c_int32), ("halvings", C.c_int32),
+                ("beta_num", C.c_double), ("beta_den", C.c_double), ("rp", C.c_double),
+                ("alpha_model", C.c_double), ("pmax", C.c_double), ("E0", C.c_double),
+                ("tau", C.c_double)]
 
 
 class IteOpts(C.Structure):
@@ -101,6 +106,8 @@ def lib():
         L.orc_param_grad.argtypes = [C.POINTER(Grid), C.POINTER(Params), dp, dp]
         L.orc_solve.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.POINTER(Opts), dp,
                                 C.POINTER(Report), C.POINTER(Iter), C.c_int32]
+        L.orc_solve_trace.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.POINTER(Opts), dp,
+                                      C.POINTER(Report), C.POINTER(Iter), C.c_int32, dp, C.c_int32]
         L.orc_ite.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.POINTER(IteOpts), dp,
                               C.POINTER(Report), dp, C.c_int32]
         _lib = L
@@ -248,6 +255,33 @@ def solve(grid: dict, params: dict, psi0: np.ndarray, opts: dict | None = None, 
     n_log = min(rep.iters, log_cap)
     log = [{k: getattr(logs[i], k) for k, _ in Iter._fields_} for i in range(n_log)]
     return psi, out, log
+
+
+TRACE_FIELDS = ("psi", "r", "z", "p_old", "d", "p")
+
+
+def solve_traced(grid: dict, params: dict, psi0: np.ndarray, opts: dict | None = None,
+                 n_steps: int = 20):
+    """solve() that also returns, for each of the first n_steps accepted steps,
+    the fields psi (start of the step), r, z (the preconditioned residual the
+    accepted direction used), p_old, d (unprojected direction) and p (projected),
+    each of shape (2, nx, ny, nz): trace[k][name]."""
+    o = dict(DEFAULT_OPTS)
+    o.update(opts or {})
+    g = make_grid(grid["n"], grid["lo"], grid["hi"])
+    psi = _field(psi0, grid["n"]).copy()
+    n = grid["n"]
+    tr = np.zeros((max(n_steps, 1), len(TRACE_FIELDS), 2, n[0], n[1], n[2]), dtype=np.complex128)
+    rep = Report()
+    logs = (Iter * max(n_steps, 1))()
+    lib().orc_solve_trace(C.byref(g), C.byref(make_params(params)), C.byref(make_opts(o)), _dp(psi),
+                          C.byref(rep), logs, n_steps, _dp(tr), n_steps)
+    out = {"iters": rep.iters, "n_restarts": rep.n_restarts, "n_backtracks": rep.n_backtracks,
+           "status": STATUS.get(rep.status, rep.status), "final": rep.final.to_dict()}
+    n_log = min(rep.iters, n_steps)
+    log = [{k: getattr(logs[i], k) for k, _ in Iter._fields_} for i in range(n_log)]
+    trace = [{name: tr[k, f] for f, name in enumerate(TRACE_FIELDS)} for k in range(n_log)]
+    return psi, out, log, trace
 
 
 def ite(grid: dict, params: dict, psi0: np.ndarray, dt: float, tol_dE: float = 1e-6, max_iter: int = 100000,

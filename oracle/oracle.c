@@ -92,10 +92,21 @@ typedef struct {
     int32_t iter;       /* index of the accepted step                           */
     int32_t n_trials;   /* energy evaluations spent on this step               */
     int32_t restarted;  /* 1 if beta was forced to zero                        */
-    int32_t path;       /* 0 model step, 1 Armijo, 2 beta=0 retry, 3 fallback z */
+    int32_t path;       /* bits: 1 Armijo, 2 beta=0 retry, 4 fallback z       */
     double E;           /* energy after the step                               */
     double res_max;     /* max_i ||r_i|| before the step                       */
     double E1, E2, alpha, beta;
+    int32_t level;      /* direction of the accepted step: 0 the computed beta,
+                           1 beta = 0, 2 z = P_V^-1 r, 3 z = r                 */
+    int32_t halvings;   /* Armijo halvings of the accepted trial               */
+    double beta_num;    /* sum_i w_i Re<r_i - r_old_i, z_i> (0 on restarts)     */
+    double beta_den;    /* HS+: sum_i w_i Re<r_i - r_old_i, p_old_i>;
+                           PR+: sum_i w_i Re<r_old_i, z_old_i> (0 on restarts) */
+    double rp;          /* sum_i 2 N_i Re<p_i, r_i> of the accepted direction   */
+    double alpha_model; /* step before halving: -E1/E2 or the fallback, clamped */
+    double pmax;        /* max_i ||p_i||                                        */
+    double E0;          /* energy at the start of the step                      */
+    double tau;         /* acceptance band tau_rel |E0|                          */
 } orc_iter;
 
 typedef struct {
@@ -914,8 +925,15 @@ int orc_param_grad(const orc_grid *gr, const orc_params *P, const double *psi_d,
 /* ------------------------------------------------------------------------- */
 static int finite2(double a, double b) { return isfinite(a) && isfinite(b); }
 
-int orc_solve(const orc_grid *gr, const orc_params *P, const orc_opts *o, double *psi_d,
-              orc_report *rep, orc_iter *log, int32_t log_cap)
+/* Optional trace of the first trace_cap accepted steps (test instrumentation):
+ * per step n, six fields of 2 N complex values in this order: psi^(n) at the
+ * start of the step, r^(n), the preconditioned residual z that the accepted
+ * direction used, p^(n-1) (zero at n = 0), the unprojected direction d and the
+ * projected direction p^(n). */
+enum { TR_PSI = 0, TR_R, TR_Z, TR_POLD, TR_D, TR_P, TR_FIELDS };
+
+int orc_solve_trace(const orc_grid *gr, const orc_params *P, const orc_opts *o, double *psi_d,
+                    orc_report *rep, orc_iter *log, int32_t log_cap, double *trace, int32_t trace_cap)
 {
     int st = check_inputs(gr, P);
     if (st) return st;
@@ -930,6 +948,7 @@ int orc_solve(const orc_grid *gr, const orc_params *P, const orc_opts *o, double
     size_t vb = sizeof(cplx) * 2 * (size_t)N;
     cplx *r = (cplx *)malloc(vb), *z = (cplx *)malloc(vb), *p = (cplx *)malloc(vb);
     cplx *r_old = (cplx *)malloc(vb), *p_old = (cplx *)malloc(vb), *ptr = (cplx *)malloc(vb);
+    cplx *d_last = trace ? (cplx *)malloc(vb) : NULL;   /* unprojected d, for the trace */
     memset(rep, 0, sizeof(*rep));
 
     /* the iterate lives on the manifold: normalise each component */
@@ -963,7 +982,7 @@ int orc_solve(const orc_grid *gr, const orc_params *P, const orc_opts *o, double
         /* 3. conjugacy parameter: HS+ (default) or PR+ (Sec. IV.C) */
         int restart = !have_prev || o->beta == 2 ||
                       (o->restart_period > 0 && n % o->restart_period == 0);
-        double beta = 0.0;
+        double beta = 0.0, beta_num = 0.0, beta_den = 0.0;
         if (!restart) {
             double num = 0.0, den = 0.0;
             for (int i = 0; i < 2; ++i) {
@@ -979,13 +998,15 @@ int orc_solve(const orc_grid *gr, const orc_params *P, const orc_opts *o, double
             if (o->beta == 1) den = rz_old;
             beta = (den > 0.0 && isfinite(den) && isfinite(num)) ? num / den : 0.0;
             if (beta < 0.0) beta = 0.0;
+            beta_num = num;
+            beta_den = den;
         }
         /* level 0: computed beta; 1: beta = 0; 2: z = P_V^-1 r; 3: z = r.
          * path bits: 1 Armijo backtracking, 2 beta = 0 retry after a failed
          * line search, 4 fallback preconditioner (composite only).         */
         int level = (beta > 0.0) ? 0 : 1;
-        int path = 0, accepted = 0, trials = 0, stagnated = 0;
-        double rz_now = 0.0, alpha = 0.0, Et = NAN;
+        int path = 0, accepted = 0, trials = 0, stagnated = 0, halvings = 0;
+        double rz_now = 0.0, alpha = 0.0, alpha_model = 0.0, pmax = 0.0, rp_acc = 0.0, Et = NAN;
         model_t m;
         memset(&m, 0, sizeof(m));
         while (!accepted && !stagnated) {
@@ -1000,6 +1021,7 @@ int orc_solve(const orc_grid *gr, const orc_params *P, const orc_opts *o, double
                 for (int i = 0; i < 2; ++i) {
                     for (long x = 0; x < N; ++x)
                         p[i * N + x] = -z[i * N + x] + (b > 0.0 ? b * p_old[i * N + x] : 0.0);
+                    if (d_last) memcpy(d_last + i * N, p + i * N, sizeof(cplx) * (size_t)N);
                     double c = dV * re_dot(p + i * N, psi + i * N, N);   /* Re<d_i,psi_i> */
                     for (long x = 0; x < N; ++x) p[i * N + x] -= c * psi[i * N + x];
                     rp += 2.0 * P->N[i] * dV * re_dot(p + i * N, r + i * N, N);
@@ -1018,12 +1040,15 @@ int orc_solve(const orc_grid *gr, const orc_params *P, const orc_opts *o, double
             /* 5. second-order model and closed-form step (Sec. V) */
             model_coeffs(&g, P, psi, &cur, p, &m);
             m.rp = rp;
-            double pmax = m.pnorm[0] > m.pnorm[1] ? m.pnorm[0] : m.pnorm[1];
+            rp_acc = rp;
+            pmax = m.pnorm[0] > m.pnorm[1] ? m.pnorm[0] : m.pnorm[1];
             if (m.E2 > 0.0 && isfinite(m.E2) && isfinite(m.E1) && -m.E1 / m.E2 > 0.0)
                 alpha = -m.E1 / m.E2;
             else
                 alpha = alpha_prev > 0.0 ? alpha_prev : 0.1 / pmax;
             if (alpha * pmax > o->theta_max) alpha = o->theta_max / pmax;
+            alpha_model = alpha;
+            halvings = 0;
 
             /* 6. validate along the exact geodesic; Armijo backtracking */
             double tau = o->tau_rel * fabs(cur.t.E);
@@ -1039,6 +1064,7 @@ int orc_solve(const orc_grid *gr, const orc_params *P, const orc_opts *o, double
                     geodesic(&g, psi, p, m.pnorm, alpha, ptr);
                     heval(&g, P, ptr, &tri);
                     trials++;
+                    halvings++;
                     rep->n_backtracks++;
                     Et = tri.t.E;
                     if (isfinite(Et) && Et <= cur.t.E + o->armijo_c1 * alpha * m.E1 + tau) {
@@ -1061,6 +1087,20 @@ int orc_solve(const orc_grid *gr, const orc_params *P, const orc_opts *o, double
             L->iter = n; L->n_trials = trials; L->restarted = (level >= 1);
             L->path = path; L->E = Et; L->res_max = res_max;
             L->E1 = m.E1; L->E2 = m.E2; L->alpha = alpha; L->beta = (level == 0) ? beta : 0.0;
+            L->level = level; L->halvings = halvings;
+            L->beta_num = beta_num; L->beta_den = beta_den; L->rp = rp_acc;
+            L->alpha_model = alpha_model; L->pmax = pmax; L->E0 = cur.t.E;
+            L->tau = o->tau_rel * fabs(cur.t.E);
+        }
+        if (trace && n < trace_cap) {
+            cplx *T = (cplx *)trace + (size_t)n * TR_FIELDS * 2 * (size_t)N;
+            memcpy(T + TR_PSI * 2 * N, psi, vb);
+            memcpy(T + TR_R * 2 * N, r, vb);
+            memcpy(T + TR_Z * 2 * N, z, vb);
+            if (have_prev) memcpy(T + TR_POLD * 2 * N, p_old, vb);
+            else memset(T + TR_POLD * 2 * N, 0, vb);
+            memcpy(T + TR_D * 2 * N, d_last, vb);
+            memcpy(T + TR_P * 2 * N, p, vb);
         }
         E_prev = cur.t.E;
         memcpy(psi, ptr, vb);
@@ -1075,10 +1115,16 @@ int orc_solve(const orc_grid *gr, const orc_params *P, const orc_opts *o, double
     rep->iters = n;
     rep->status = status;
     rep->final = cur.t;
-    free(r); free(z); free(p); free(r_old); free(p_old); free(ptr);
+    free(r); free(z); free(p); free(r_old); free(p_old); free(ptr); free(d_last);
     hstate_free(&cur); hstate_free(&tri);
     geom_free(&g);
     return status;
+}
+
+int orc_solve(const orc_grid *gr, const orc_params *P, const orc_opts *o, double *psi_d,
+              orc_report *rep, orc_iter *log, int32_t log_cap)
+{
+    return orc_solve_trace(gr, P, o, psi_d, rep, log, log_cap, NULL, 0);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -252,8 +252,9 @@ def test_dipolar_small_cutoff_exercises_the_series_branch(orc):
 K5 = np.sqrt(2) / (15 * np.pi ** 2)
 
 
-def test_lhy_without_dipoles_is_u_independent_closed_form(orc):
-    G = ((7.0, 3.0), (3.0, 5.0))
+@pytest.mark.parametrize("G", [((7.0, 3.0), (3.0, 5.0)), ((7.0, 3.0), (2.0, 5.0))], ids=["sym", "mixedN"])
+def test_lhy_without_dipoles_is_u_independent_closed_form(orc, G):
+    # G_12 != G_21 where N_1 != N_2 (N_i G_ij symmetric): only the product eta_12 eta_21 enters
     n1, n2 = 0.37, 0.21
     d = G[0][0] * n1 - G[1][1] * n2
     s = np.sqrt(d * d + 4 * G[0][1] * G[1][0] * n1 * n2)
