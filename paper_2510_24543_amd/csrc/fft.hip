@@ -227,10 +227,18 @@ __device__ double block_sum(double v, double* sh)
     return r;
 }
 
+// Launch kinds.  The kernel body is the same for all of them; the kind only
+// names the instantiation, so that a kernel trace times the passes of the
+// energy evaluation (kinetic axis terms), of the line search (Parseval axis
+// sums) and the other passes separately.
+struct GenericPass {};
+struct EnergyPass {};
+struct LineSearchPass {};
+
 // KMODE: 0 forward plain pass (fields Plain or ParsevalAxis), 1 inverse plain pass, 2 fused pass with
 // per-field ops: forward, operator, inverse (the x pass; the y pass with kinetic axis terms); its
 // Plain fields are forward only.
-template <int L, int T, int R0, int R1, int R2, int NTHR, bool CONTIG, int KMODE>
+template <int L, int T, int R0, int R1, int R2, int NTHR, bool CONTIG, int KMODE, typename KIND>
 __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
 {
     using PL = Plan<L, T, R0, R1, R2>;
@@ -634,27 +642,33 @@ hipError_t launch_cfg(bool contiguous, const FftPassArgs& A, hipStream_t st)
     dim3 grid((unsigned)((A.npencil + PB - 1) / PB), (unsigned)A.nfield, (unsigned)(A.n_inst > 0 ? A.n_inst : 1));
     // plain: every field Plain or ParsevalAxis (a one-axis pass; ParsevalAxis
     // fields only in a forward pass); otherwise the fused pass (mode 2)
-    bool plain = true, axis_sums = false;
+    bool plain = true, axis_sums = false, kin = false;
     for (int f = 0; f < A.nfield; ++f) {
         plain = plain && (A.op[f] == kOpPlain || A.op[f] == kOpParsevalAxis);
         axis_sums = axis_sums || A.op[f] == kOpParsevalAxis;
+        kin = kin || A.op[f] == kOpKinAxis;
     }
     if (plain && axis_sums && A.sign >= 0) return hipErrorInvalidValue;
+#define BEC_LAUNCH_PASS(C, K, KIND) \
+    hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, C, K, KIND>), grid, dim3(NTHR), 0, st, A)
     if (contiguous) {
         // the contiguous (z) axis never runs the fused mode
         if (!plain) return hipErrorInvalidValue;
-        if (A.sign < 0)
-            hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, true, 0>), grid, dim3(NTHR), 0, st, A);
-        else
-            hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, true, 1>), grid, dim3(NTHR), 0, st, A);
+        if (A.sign >= 0) BEC_LAUNCH_PASS(true, 1, GenericPass);
+        else if (axis_sums) BEC_LAUNCH_PASS(true, 0, LineSearchPass);
+        else BEC_LAUNCH_PASS(true, 0, GenericPass);
     } else if (plain) {
-        if (A.sign < 0)
-            hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, false, 0>), grid, dim3(NTHR), 0, st, A);
-        else
-            hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, false, 1>), grid, dim3(NTHR), 0, st, A);
+        if (A.sign >= 0) BEC_LAUNCH_PASS(false, 1, GenericPass);
+        else if (axis_sums) BEC_LAUNCH_PASS(false, 0, LineSearchPass);
+        else BEC_LAUNCH_PASS(false, 0, GenericPass);
+    } else if (kin) {
+        BEC_LAUNCH_PASS(false, 2, EnergyPass);
+    } else if (axis_sums) {
+        BEC_LAUNCH_PASS(false, 2, LineSearchPass);
     } else {
-        hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, false, 2>), grid, dim3(NTHR), 0, st, A);
+        BEC_LAUNCH_PASS(false, 2, GenericPass);
     }
+#undef BEC_LAUNCH_PASS
     return hipGetLastError();
 }
 

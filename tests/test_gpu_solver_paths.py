@@ -1,0 +1,223 @@
+"""GPU-vs-oracle parity, step by step, of the solver's less common paths and of
+the larger workloads (Sec. III Algorithm 1; Sec. IV.C conjugacy rules and
+restarts; Sec. V step, Armijo fallback, beta = 0 retry, stagnation):
+
+* PR+ with P_V and with the composite preconditioner (Eq. (18)), full solves;
+* Armijo halving, beta = 0 retries after failed line searches and stagnation in a
+  strongly interacting (compressed) cloud where the quadratic model overshoots;
+* the composite's fallback directions z = P_V^-1 r and z = r (path bit 4),
+  reached with a negative regularising shift;
+* the stripe workload (128 x 128 x 96): energy terms, H psi at sampled points and
+  the first three steps;
+* one scan instance per grid size of the 96-instance scan (48^3, 64^3, 96^3) at
+  its own parameters, one of them past the miscibility edge (g12 > sqrt(g11 g22)),
+  through the batched solver for five rounds.
+
+Each logged step is compared: the same iteration index, trials, restart flag
+and path bits (decisions, at every compared step), E relative 1e-11, alpha,
+beta and the model coefficients E1, E2 relative 1e-8 (ratios of reduced sums,
+each about 1e-13 on its own) over the first ten steps, and 100x those bars over
+the next ten.  Differences of 1e-15 grow along a trajectory, by about 1.7x per
+step in the strongly interacting runs (the quadratic model overshoots there, the
+regime that engages the Armijo fallback); the decisions stay identical.
+"""
+import numpy as np
+import pytest
+
+from paper_2510_24543_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def solver():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2510_24543_amd import solver as s
+    return s
+
+
+GRID16 = {"n": [16, 16, 16], "lo": [-6.0, -6.0, -6.0], "hi": [6.0, 6.0, 6.0]}
+
+
+def mixed_params(scale=1.0):
+    s = float(scale)
+    return {"N": [1.0, 1.6], "omega": [1.0, 1.2, 2.6],
+            "G": [[100.0 * s, 50.0 * s], [31.25 * s, 90.0 * s]],
+            "Gdd": [[60.0 * s, 45.0 * s], [28.125 * s, 50.0 * s]],
+            "c_lhy": 5.0, "r_cut": 6.0, "n_u": 16}
+
+
+def close(a, b, tol):
+    return abs(a - b) <= tol * max(abs(b), 1e-300)
+
+
+def compare_logs(log, logo, n=None, n_val=20, tol_E=1e-11, tol_v=1e-8):
+    """Decisions equal at the first n steps (all logged ones by default); values
+    to the bars over the first ten steps, 100x looser up to step n_val."""
+    n = len(logo) if n is None else n
+    assert len(log) >= n and len(logo) >= n
+    worst = {}
+    for k in range(min(n, n_val)):
+        a, b = log[k], logo[k]
+        for key in ("E", "alpha", "beta", "E1", "E2"):
+            d = abs(a[key] - b[key]) / max(abs(b[key]), 1e-300)
+            worst[key] = max(worst.get(key, (0.0, 0)), (d, k))
+    print("max relative deviation (value, step):", {k: (f"{v[0]:.1e}", v[1]) for k, v in worst.items()}, flush=True)
+    for k in range(n):
+        a, b = log[k], logo[k]
+        for key in ("iter", "n_trials", "restarted", "path"):
+            assert a[key] == b[key], (k, key, a[key], b[key])
+        if k >= n_val:
+            continue
+        f = 1.0 if k < 10 else 100.0
+        assert close(a["E"], b["E"], f * tol_E), (k, a["E"], b["E"])
+        for key in ("alpha", "beta", "E1", "E2"):
+            assert close(a[key], b[key], f * tol_v), (k, key, a[key], b[key])
+
+
+def run_both(solver, orc, grid, params, psi0, opts, cap):
+    print(f"grid {grid['n']} opts {opts}", flush=True)
+    ctx = solver.Context(grid, params)
+    psi, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=cap)
+    psio, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=cap)
+    return psi.cpu().numpy(), rep, log, psio, repo, logo
+
+
+# ---------------------------------------------------------------- PR+
+PR_CASES = [("C1b", 1), ("C1b", 3), ("mixedN", 1), ("mixedN", 3)]
+
+
+@pytest.mark.parametrize("name,pc", PR_CASES, ids=[f"{n}-pc{p}" for n, p in PR_CASES])
+def test_polak_ribiere_plus_solves(solver, orc, name, pc):
+    if name == "mixedN":
+        grid, params = GRID16, mixed_params()
+        psi0 = inputs.initial_state(grid, params["omega"], 71, phase=True)
+    else:
+        c = inputs.CONFIGS[name]
+        grid, params, psi0 = c["grid"], c["params"], inputs.config_state(name)
+    opts = {"tol_grad": 1e-10, "pc": pc, "beta": 1, "max_iter": 3000}
+    psi, rep, log, psio, repo, logo = run_both(solver, orc, grid, params, psi0, opts, 3000)
+    assert rep["status"] == "OK" and repo["status"] == "OK"
+    assert max(rep["final"]["res"]) < 1e-10
+    assert abs(rep["final"]["E"] - repo["final"]["E"]) <= 1e-10 * abs(repo["final"]["E"])
+    assert np.max(np.abs(np.abs(psi) ** 2 - np.abs(psio) ** 2)) < 1e-7
+    compare_logs(log, logo, n=min(20, len(logo)))
+    assert sum(1 for L in logo[:20] if L["beta"] > 0) >= 10
+    assert abs(rep["iters"] - repo["iters"]) <= max(2, repo["iters"] // 20)
+
+
+# ---------------------------------------------------------------- line-search fallbacks
+BT_CASES = {
+    # Armijo halving accepted (the quadratic model overshoots)
+    "armijo-hs": dict(pc=1, beta=0, max_backtrack=4, armijo_c1=0.3),
+    "armijo-pr": dict(pc=1, beta=1, max_backtrack=4, armijo_c1=0.3),
+    "armijo-none": dict(pc=0, beta=0, max_backtrack=4, armijo_c1=0.3),
+    # one halving only: failed searches retried with beta = 0 (path bit 2), then stagnation
+    "retry": dict(pc=1, beta=0, max_backtrack=1, armijo_c1=0.3),
+    # a negative acceptance band: stagnation after a beta = 0 retry (at step 42)
+    "stagnation": dict(pc=1, beta=0, max_backtrack=2, tau_rel=-1e-3, max_iter=60),
+}
+
+
+@pytest.mark.parametrize("case", list(BT_CASES))
+def test_line_search_fallbacks_step_by_step(solver, orc, case):
+    params = mixed_params(10.0)
+    psi0 = inputs.initial_state(GRID16, params["omega"], 71, phase=True)
+    opts = dict({"tol_grad": 1e-10, "max_iter": 40}, **BT_CASES[case])
+    psi, rep, log, psio, repo, logo = run_both(solver, orc, GRID16, params, psi0, opts, opts["max_iter"])
+    for k in ("status", "iters", "n_restarts", "n_backtracks"):
+        assert rep[k] == repo[k], (k, rep[k], repo[k])
+    compare_logs(log, logo)
+    paths = [L["path"] for L in logo]
+    if case.startswith("armijo"):
+        assert sum(1 for p in paths if p & 1) >= 3
+    if case == "retry":
+        assert sum(1 for p in paths if p & 2) >= 2
+    if case in ("retry", "stagnation"):
+        assert repo["status"] == "ESTAGNATED"
+
+
+def test_composite_fallback_directions(solver, orc):
+    """sigma < 0 makes the P_V diagonal indefinite near the centre, so the
+    composite direction of Eq. (18) stops descending and the solver falls back
+    to z = P_V^-1 r (level 2) and z = r (level 3), path bit 4.  Such input is
+    ill-conditioned by construction: the indefinite P_V diagonal passes within
+    1e-5 of zero (relative to its range) at some grid point, and once the shift
+    falls below |sigma| the P_Delta multiplier 1/([shift]_+ + sigma + |k|^2/2)
+    passes within 0.05 of a pole, so round-off is amplified by up to 1e5.  The
+    decisions of the first twelve steps (levels 2 and 3 both occur in them) are
+    compared exactly, the values to 1e-9 in E and 1e-4 in the rest."""
+    params = mixed_params()
+    psi0 = inputs.initial_state(GRID16, params["omega"], 71, phase=False)
+    opts = {"tol_grad": 1e-10, "max_iter": 12, "pc": 3, "beta": 0, "sigma": -60.0}
+    psi, rep, log, psio, repo, logo = run_both(solver, orc, GRID16, params, psi0, opts, 12)
+    assert rep["iters"] == repo["iters"] == 12
+    assert sum(1 for L in logo if L["path"] & 4) >= 4
+    levels = [L["level"] for L in logo]
+    assert 2 in levels and 3 in levels
+    compare_logs(log, logo, n_val=12, tol_E=1e-9, tol_v=1e-4)
+
+
+# ---------------------------------------------------------------- stripe workload at full size
+@pytest.mark.timeout(900)
+def test_stripe_grid_energy_hamiltonian_and_first_steps(solver, orc):
+    """128 x 128 x 96, elongated trap, eps_dd = 1.3 (clipped LHY branches): energy
+    terms, H psi at 4096 sampled points and the first three accepted steps."""
+    c = inputs.CONFIGS["C3"]
+    grid, params = c["grid"], c["params"]
+    psi0 = inputs.config_state("C3")
+    ctx = solver.Context(grid, params)
+    h, t = ctx.hamiltonian(torch.from_numpy(psi0))
+    to, ho, _, _ = orc.heval(grid, params, psi0)
+    for k in ("E", "E_lhy"):
+        assert abs(t[k] - to[k]) <= 1e-12 * abs(to["E"]), k
+    for k in ("E_kin", "E_trap", "mu", "shift", "res"):
+        for i in range(2):
+            assert abs(t[k][i] - to[k][i]) <= 1e-12 * abs(to[k][i]), (k, i)
+    for k in ("E_c", "E_dd"):
+        for i in range(2):
+            for j in range(2):
+                assert abs(t[k][i][j] - to[k][i][j]) <= 1e-12 * abs(to["E"]), (k, i, j)
+    rng = np.random.default_rng(13)
+    idx = tuple(rng.integers(0, n, 4096) for n in grid["n"])
+    hg = h.cpu().numpy()
+    for i in range(2):
+        assert np.max(np.abs(hg[i][idx] - ho[i][idx])) <= 1e-11 * np.max(np.abs(ho[i]))
+    opts = {"tol_grad": 0.0, "max_iter": 3}
+    psi, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=3)
+    psio, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=3)
+    assert rep["iters"] == repo["iters"] == 3
+    compare_logs(log, logo)
+    g = psi.cpu().numpy()
+    for i in range(2):
+        assert np.max(np.abs(g[i][idx] - psio[i][idx])) <= 1e-10 * np.max(np.abs(psio[i]))
+
+
+# ---------------------------------------------------------------- scan instances
+SCAN_PICK = [6, 1, 2]     # 48^3 with g12 = 88.6 (> 80 = sqrt(g11 g22)), 64^3, 96^3
+
+
+@pytest.mark.timeout(900)
+def test_scan_instances_batched_against_oracle(solver, orc):
+    inst = [inputs.scan_instances()[k] for k in SCAN_PICK]
+    assert [s["grid"]["n"][0] for s in inst] == [48, 64, 96] and inst[0]["params"]["G"][0][1] > 80.0
+    psi0 = [inputs.initial_state(s["grid"], s["params"]["omega"], s["seed"]) for s in inst]
+    opts = {"tol_grad": 1e-10, "max_iter": 5, "pc": 1}
+    b = solver.Batch([s["grid"] for s in inst], [s["params"] for s in inst])
+    psis, reps = b.solve(psi0, opts, rounds_per_sync=2, use_graph=True)
+    rng = np.random.default_rng(17)
+    for s, p0, pb, rb in zip(inst, psi0, psis, reps):
+        print(f"scan grid {s['grid']['n']} g12 {s['params']['G'][0][1]:.2f}", flush=True)
+        psio, repo, logo = orc.solve(s["grid"], s["params"], p0, opts, log_cap=5)
+        assert rb["iters"] == repo["iters"] == 5 and rb["status"] == repo["status"]
+        assert rb["n_restarts"] == repo["n_restarts"] and rb["n_backtracks"] == repo["n_backtracks"]
+        assert abs(rb["final"]["E"] - repo["final"]["E"]) <= 1e-11 * abs(repo["final"]["E"])
+        for i in range(2):
+            assert abs(rb["final"]["res"][i] - repo["final"]["res"][i]) <= 1e-9 * repo["final"]["res"][i]
+        idx = tuple(rng.integers(0, n, 4096) for n in s["grid"]["n"])
+        g = pb.cpu().numpy()
+        for i in range(2):
+            assert np.max(np.abs(g[i][idx] - psio[i][idx])) <= 1e-10 * np.max(np.abs(psio[i]))
