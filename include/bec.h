@@ -140,7 +140,7 @@ typedef struct {
 
 typedef struct bec_ctx bec_ctx;
 
-/* Bytes of device workspace bec_create needs for this grid (about 370 bytes per
+/* Bytes of device workspace bec_create needs for this grid (about 450 bytes per
  * grid point).  Returns BEC_EINVAL / BEC_EUNSUPPORTED for a bad grid. */
 bec_status bec_workspace_size(const bec_grid* grid, const bec_params* params, size_t* bytes);
 
@@ -176,6 +176,25 @@ bec_status bec_hamiltonian(bec_ctx* ctx, const double* psi, double* hpsi, bec_te
  * Synchronises. */
 bec_status bec_gradient(bec_ctx* ctx, const double* psi, double* grad, int32_t projected,
                         bec_terms* out_h);
+
+/* The gradient of bec_gradient without a context and without allocating:
+ * for callers that cannot allocate device or pinned host memory at call time
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and results as bec_gradient (grad must not be
+ * null, out_h may be) plus the grid, the parameters and the HIP stream (NULL =
+ * the null stream) that bec_create would take.  The workspace of a context
+ * (bec_workspace_size bytes) and the reduced scalars live in a fixed device
+ * array of BEC_NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds
+ * until the process ends; a grid whose workspace does not fit (above about
+ * 147,000 points: 48^3 and 64 x 64 x 32 fit, 64 x 64 x 48 does not) returns
+ * BEC_ENOMEM before any device work.  The call rebuilds its tables each time
+ * (host work growing with the grid), runs on default launch plans, and
+ * synchronises the stream before returning.  Calls on one device are
+ * serialised by a lock inside the library; the array keeps the last call's
+ * contents.  Calls no hipMalloc / hipFree / hipHostMalloc. */
+#define BEC_NOALLOC_SCRATCH_BYTES (64u << 20)
+bec_status bec_gradient_noalloc(const bec_grid* grid, const bec_params* params, void* hip_stream, const double* psi,
+                                double* grad, int32_t projected, bec_terms* out_h);
 
 /* z = P^-1 r for the preconditioner pc evaluated at psi (Sec. IV.B; shift
  * alpha_i = <psi_i,(T + V + sum_j G_ij n_j + muLHY_i) psi_i>, regularised by

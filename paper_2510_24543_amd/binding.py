@@ -103,6 +103,8 @@ SIGNATURES = [
     ("bec_energy", C.c_int, [_VP, _VP, C.POINTER(Terms)]),
     ("bec_hamiltonian", C.c_int, [_VP, _VP, _VP, C.POINTER(Terms)]),
     ("bec_gradient", C.c_int, [_VP, _VP, _VP, _I32, C.POINTER(Terms)]),
+    ("bec_gradient_noalloc", C.c_int, [C.POINTER(Grid), C.POINTER(Params), _VP, _VP, _VP, _I32,
+                                       C.POINTER(Terms)]),
     ("bec_precond_apply", C.c_int, [_VP, _I32, _DBL, _VP, _VP, _VP]),
     ("bec_linesearch", C.c_int, [_VP, _VP, _VP, _VP, C.POINTER(Opts), C.POINTER(LsReport)]),
     ("bec_solve", C.c_int, [_VP, _VP, C.POINTER(Opts), C.POINTER(Report), C.POINTER(Iter), _I32]),

@@ -17,8 +17,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
-#include <array>
 #include <vector>
 
 using bec::FftPassArgs;
@@ -184,7 +184,8 @@ struct bec_ctx {
     double2 *z = nullptr, *z_next = nullptr, *rho = nullptr, *W = nullptr;   // z_next: a pipelined lookahead
     double *udtab = nullptr, *kv[3] = {}, *vv[3] = {}, *nodes = nullptr;
     double *partials = nullptr, *fft_partials = nullptr, *ls_partials = nullptr;
-    double* scal = nullptr;    // device address of `host` (reduced scalars)
+    double* scal = nullptr;    // device address of `host` (reduced scalars), or device memory (scal_on_device)
+    bool scal_on_device = false;   // scal is plain device memory: fetch() copies it into `host`
     double* dscal = nullptr;   // device copies of the scalars that later launches read (same offsets)
     double2* tw[3] = {};
     double* host = nullptr;   // pinned scalars
@@ -770,10 +771,13 @@ bec_status kspace_after_z(bec_ctx* c, double2* const* dst, int nf, const int* op
 // ------------------------------------------------------------------ reductions
 constexpr int kParsevalOut = 30;    // scal slots of the two Parseval sums of an x pass
 
-// c->scal is the device address of the pinned host buffer c->host
+// c->scal is the device address of the pinned host buffer c->host (or, for a
+// context without pinned memory, device memory that is copied back here)
 bec_status fetch(bec_ctx* c, int M)
 {
     (void)M;
+    if (c->scal_on_device)
+        HIPCHK(hipMemcpyAsync(c->host, c->scal, kScalSlots * sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     return BEC_OK;
 }
@@ -1098,6 +1102,73 @@ bec_status residual_norms(bec_ctx* c, int set, Eval* ev)
 const double kOne[2] = {1.0, 1.0};
 const double kZero[2] = {0.0, 0.0};
 
+// Grid geometry and workspace pointers of a context (layout `off` of ws_layout
+// inside `base`); no device work.
+void ctx_attach(bec_ctx* c, const bec_grid* grid, const bec_params* params, void* hip_stream, char* base,
+                const size_t* off)
+{
+    c->g = *grid;
+    c->p = *params;
+    c->st = reinterpret_cast<hipStream_t>(hip_stream);
+    for (int d = 0; d < 3; ++d) {
+        c->n[d] = grid->n[d];
+        c->L[d] = grid->hi[d] - grid->lo[d];
+        c->h[d] = c->L[d] / grid->n[d];
+    }
+    c->N = (long long)c->n[0] * c->n[1] * c->n[2];
+    c->dV = c->h[0] * c->h[1] * c->h[2];
+    auto at = [&](int i) { return base + off[i]; };
+    c->psi[0] = (double2*)at(0);
+    c->psi[1] = (double2*)at(1);
+    c->hpsi[0] = (double2*)at(2);
+    c->hpsi[1] = (double2*)at(3);
+    c->aux[0] = (double2*)at(4);
+    c->aux[1] = (double2*)at(5);
+    c->pdir = (double2*)at(6);
+    c->r_old = (double2*)at(7);
+    c->pold = (double2*)at(26);
+    c->r_new = (double2*)at(27);
+    c->z_next = (double2*)at(28);
+    c->lhytab = (double*)at(29);
+    c->dscal = (double*)at(24);
+    c->z = (double2*)at(8);
+    c->rho = (double2*)at(9);
+    c->W = (double2*)at(10);
+    c->udtab = (double*)at(11);
+    for (int d = 0; d < 3; ++d) {
+        c->tw[d] = (double2*)at(12 + d);
+        c->kv[d] = (double*)at(15 + d);
+        c->vv[d] = (double*)at(18 + d);
+    }
+    c->nodes = (double*)at(21);
+    c->partials = (double*)at(22);
+    c->fft_partials = (double*)at(23);
+    c->ls_partials = (double*)at(25);
+    c->nblk_pw = (int)std::min<long long>((c->N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwDefaultBlocks);
+    c->nblk_x = bec::fft_blocks(c->n[0], c->fft_var[0][1], (long long)c->n[1] * c->n[2]);
+}
+
+// Twiddles W_L^m and wavenumbers per axis, then the parameter tables
+// (synchronises the context stream).
+bec_status ctx_tables(bec_ctx* c)
+{
+    for (int d = 0; d < 3; ++d) {
+        const int L = c->n[d];
+        std::vector<double2> tw(L);
+        std::vector<double> kv(L);
+        for (int m = 0; m < L; ++m) {
+            const long double a = -2.0L * kPiL * (long double)m / (long double)L;
+            tw[m] = make_double2((double)cosl(a), (double)sinl(a));
+            const int jj = m < L / 2 ? m : m - L;
+            kv[m] = (double)(2.0L * kPiL * jj / (long double)c->L[d]);
+        }
+        HIPCHK(hipMemcpyAsync(c->tw[d], tw.data(), L * sizeof(double2), hipMemcpyHostToDevice, c->st));
+        HIPCHK(hipMemcpyAsync(c->kv[d], kv.data(), L * sizeof(double), hipMemcpyHostToDevice, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+    }
+    return upload_params(c, true);
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1181,46 +1252,7 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
         if (workspace_bytes < need)
             return fail(BEC_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
         bec_ctx* c = new bec_ctx();
-        c->g = *grid;
-        c->p = *params;
-        c->st = reinterpret_cast<hipStream_t>(hip_stream);
-        for (int d = 0; d < 3; ++d) {
-            c->n[d] = grid->n[d];
-            c->L[d] = grid->hi[d] - grid->lo[d];
-            c->h[d] = c->L[d] / grid->n[d];
-        }
-        c->N = (long long)c->n[0] * c->n[1] * c->n[2];
-        c->dV = c->h[0] * c->h[1] * c->h[2];
-        char* base = static_cast<char*>(workspace);
-        auto at = [&](int i) { return base + off[i]; };
-        c->psi[0] = (double2*)at(0);
-        c->psi[1] = (double2*)at(1);
-        c->hpsi[0] = (double2*)at(2);
-        c->hpsi[1] = (double2*)at(3);
-        c->aux[0] = (double2*)at(4);
-        c->aux[1] = (double2*)at(5);
-        c->pdir = (double2*)at(6);
-        c->r_old = (double2*)at(7);
-        c->pold = (double2*)at(26);
-        c->r_new = (double2*)at(27);
-        c->z_next = (double2*)at(28);
-        c->lhytab = (double*)at(29);
-        c->dscal = (double*)at(24);
-        c->z = (double2*)at(8);
-        c->rho = (double2*)at(9);
-        c->W = (double2*)at(10);
-        c->udtab = (double*)at(11);
-        for (int d = 0; d < 3; ++d) {
-            c->tw[d] = (double2*)at(12 + d);
-            c->kv[d] = (double*)at(15 + d);
-            c->vv[d] = (double*)at(18 + d);
-        }
-        c->nodes = (double*)at(21);
-        c->partials = (double*)at(22);
-        c->fft_partials = (double*)at(23);
-        c->ls_partials = (double*)at(25);
-        c->nblk_pw = (int)std::min<long long>((c->N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwDefaultBlocks);
-        c->nblk_x = bec::fft_blocks(c->n[0], c->fft_var[0][1], (long long)c->n[1] * c->n[2]);
+        ctx_attach(c, grid, params, hip_stream, static_cast<char*>(workspace), off);
         // reduced scalars: the final-reduction kernels write straight into pinned
         // host memory, so reading them back needs a stream synchronisation only
         if (hipHostMalloc((void**)&c->host, kScalSlots * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -1232,26 +1264,7 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
             delete c;
             return fail(BEC_EHIP, "hipHostGetDevicePointer of the scalar buffer failed");
         }
-        // twiddles W_L^m and wavenumbers per axis
-        for (int d = 0; d < 3; ++d) {
-            const int L = c->n[d];
-            std::vector<double2> tw(L);
-            std::vector<double> kv(L);
-            for (int m = 0; m < L; ++m) {
-                const long double a = -2.0L * kPiL * (long double)m / (long double)L;
-                tw[m] = make_double2((double)cosl(a), (double)sinl(a));
-                const int jj = m < L / 2 ? m : m - L;
-                kv[m] = (double)(2.0L * kPiL * jj / (long double)c->L[d]);
-            }
-            if (hipMemcpyAsync(c->tw[d], tw.data(), L * sizeof(double2), hipMemcpyHostToDevice, c->st) != hipSuccess ||
-                hipMemcpyAsync(c->kv[d], kv.data(), L * sizeof(double), hipMemcpyHostToDevice, c->st) != hipSuccess ||
-                hipStreamSynchronize(c->st) != hipSuccess) {
-                    (void)hipHostFree(c->host);
-                delete c;
-                return fail(BEC_EHIP, "upload of FFT tables failed");
-            }
-        }
-        bec_status st = upload_params(c, true);
+        bec_status st = ctx_tables(c);
         if (st != BEC_OK) {
             (void)hipHostFree(c->host);
             delete c;
@@ -1433,6 +1446,76 @@ bec_status bec_gradient(bec_ctx* c, const double* psi, double* grad, int32_t pro
     HIPCHK(hipStreamSynchronize(c->st));
     if (out_h) *out_h = ev.t;
     return BEC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// bec_gradient_noalloc: the workspace of a context (fields, FFT work area,
+// tables, partial sums) and the reduced scalars live in this array instead of
+// caller or pinned host memory.  Every GPU the library runs on holds its own
+// copy from module load until the process ends.  In host code `scratch` names a
+// host-side stand-in: its device address on the current device comes from
+// hipGetSymbolAddress and only that address is handed to kernels and copies.
+static __device__ __align__(256) char scratch[BEC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+struct NoAllocDevice {
+    std::mutex lock;          // calls on one device run one at a time
+    char* ptr = nullptr;      // device address of `scratch` on this device
+};
+NoAllocDevice g_noalloc[kMaxDevices];
+
+}  // namespace
+
+extern "C" {
+
+bec_status bec_gradient_noalloc(const bec_grid* grid, const bec_params* params, void* hip_stream, const double* psi,
+                                double* grad, int32_t projected, bec_terms* out_h)
+{
+    try {
+        STCHK(check_grid(grid));
+        STCHK(check_params(params));
+        if (!psi || !grad) return fail(BEC_EINVAL, "null argument");
+        size_t off[32];
+        const size_t ws = ws_layout(grid->n, off);
+        const size_t need = ws + align256(kScalSlots * sizeof(double));
+        if (need > sizeof(scratch))
+            return fail(BEC_ENOMEM, "grid %dx%dx%d needs %zu bytes, the static scratch of bec_gradient_noalloc has %zu",
+                        grid->n[0], grid->n[1], grid->n[2], need, sizeof(scratch));
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        if (dev < 0 || dev >= kMaxDevices) return fail(BEC_EUNSUPPORTED, "device index %d beyond %d", dev, kMaxDevices);
+        NoAllocDevice& D = g_noalloc[dev];
+        std::lock_guard<std::mutex> guard(D.lock);
+        if (!D.ptr) {   // once per device, with that device current
+            void* p = nullptr;
+            HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+            D.ptr = static_cast<char*>(p);
+        }
+        // a context on the host stack whose workspace is the device's scratch;
+        // every table it needs is rebuilt here, no buffer has to start at zero
+        bec_ctx c;
+        double host[kScalSlots];
+        ctx_attach(&c, grid, params, hip_stream, D.ptr, off);
+        c.scal = reinterpret_cast<double*>(D.ptr + ws);
+        c.host = host;
+        c.scal_on_device = true;
+        STCHK(ctx_tables(&c));
+        Eval ev;
+        STCHK(heval(&c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
+        STCHK(residual_norms(&c, 0, &ev));
+        HIPCHK(bec::launch_grad(c.P, c.psi[0], c.hpsi[0], reinterpret_cast<double2*>(grad), ev.t.mu[0], ev.t.mu[1],
+                                2.0 * c.p.N[0] * c.dV, 2.0 * c.p.N[1] * c.dV, projected ? 1 : 0, c.st));
+        HIPCHK(hipStreamSynchronize(c.st));
+        c.host = nullptr;   // not owned
+        if (out_h) *out_h = ev.t;
+        return BEC_OK;
+    } catch (...) {
+        return fail(BEC_EINVAL, "unexpected host exception in bec_gradient_noalloc");
+    }
 }
 
 bec_status bec_precond_apply(bec_ctx* c, int32_t pc, double sigma, const double* psi, const double* r, double* z)

@@ -24,6 +24,23 @@ def _ptr(t: torch.Tensor) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
+def gradient_noalloc(grid: dict, params: dict, psi: torch.Tensor, projected: bool = False, stream=None):
+    """bec_gradient_noalloc: the gradient of bec_gradient without a context, its
+    workspace in the library's fixed device array (no allocation by the library;
+    the output tensor is allocated here).  psi: complex128 (2, nx, ny, nz) on the
+    current device; stream: a torch stream (default: the current one)."""
+    if psi.dtype != torch.complex128 or not psi.is_cuda or tuple(psi.shape) != (2, *grid["n"]):
+        raise ValueError(f"psi must be a complex128 CUDA tensor of shape (2, {grid['n']})")
+    psi = psi.contiguous()
+    st = stream if stream is not None else torch.cuda.current_stream(psi.device)
+    g = torch.empty_like(psi)
+    t = B.Terms()
+    B.check(B.lib().bec_gradient_noalloc(C.byref(B.make_grid(grid)), C.byref(B.make_params(params)),
+                                         C.c_void_p(st.cuda_stream), _ptr(psi), _ptr(g), int(projected),
+                                         C.byref(t)), "bec_gradient_noalloc")
+    return g, t.to_dict()
+
+
 class Context:
     """One grid + parameter set on one device and stream (bec_create / bec_destroy)."""
 
