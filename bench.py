@@ -162,21 +162,64 @@ def pmc_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib, 
     return out
 
 
-def cpu_baseline(grid, params, psi0, sample_iters: int):
-    """The oracle as it stands, on the host cores: rate = sample_iters / (t(1 + s) - t(1))."""
+def cpu_leg(sample_iters: int, repeats: int):
+    """Child-process part of the CPU baseline: the oracle on the 128^3 x 2
+    workload at the OpenMP thread count of this process; per repeat the rate
+    sample_iters / (t(1 + sample_iters) - t(1)) from a 1-step and a longer
+    oracle solve of the same seeded start; prints the rates as JSON."""
     import oracle
+    from paper_2510_24543_amd import inputs
+    cfg = inputs.CONFIGS[WORKLOAD]
+    psi0 = inputs.config_state(WORKLOAD)
     opts = {"tol_grad": 0.0}
-    t0 = time.perf_counter()
-    oracle.solve(grid, params, psi0, dict(opts, max_iter=1))
-    t1 = time.perf_counter()
-    _, rep, _ = oracle.solve(grid, params, psi0, dict(opts, max_iter=1 + sample_iters))
-    t2 = time.perf_counter()
-    dt = (t2 - t1) - (t1 - t0)
+    rates, t_all = [], time.perf_counter()
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        oracle.solve(cfg["grid"], cfg["params"], psi0, dict(opts, max_iter=1))
+        t1 = time.perf_counter()
+        _, rep, _ = oracle.solve(cfg["grid"], cfg["params"], psi0, dict(opts, max_iter=1 + sample_iters))
+        t2 = time.perf_counter()
+        rates.append((rep["iters"] - 1) / ((t2 - t1) - (t1 - t0)))
+    print(json.dumps({"rates": rates, "seconds": time.perf_counter() - t_all}), flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sample_iters: int, repeats: int = 3):
+    """The oracle as it stands, on the host cores, in child processes (the
+    OpenMP thread count is fixed per process): all host threads (the harness's
+    OMP_NUM_THREADS, else every core) with the median of `repeats` rates, then
+    one thread with a one-iteration sample."""
+    import statistics
+    import subprocess
+
+    def leg(threads, sample):
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+        p = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", str(sample), str(repeats)],
+                           env=env, capture_output=True, text=True, check=True)
+        return json.loads(p.stdout.strip().splitlines()[-1])
+
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    return {"value": (rep["iters"] - 1) / dt, "unit": "iter/s", "cores": cores, "kind": "oracle",
-            "sample": f"{sample_iters} PCG iterations of the same 128^3 x 2 workload from the seeded "
-                      f"start (rate from the difference of a 1-step and a {1 + sample_iters}-step "
-                      f"oracle solve, {t2 - t0:.1f} s of CPU work)"}
+    multi = leg(cores, sample_iters)
+    single = leg(1, 1)
+    sample = (f"PCG iterations of the same 128^3 x 2 workload from the seeded start; each rate from the "
+              f"difference of a 1-step and a (1 + s)-step oracle solve, median of {repeats}")
+    return {"value": round(statistics.median(multi["rates"]), 4), "unit": "iter/s", "cores": cores,
+            "kind": "oracle", "sample": f"s = {sample_iters} {sample} ({multi['seconds']:.1f} s of CPU work)",
+            "rates": [round(r, 4) for r in multi["rates"]],
+            "single_thread": {"value": round(statistics.median(single["rates"]), 4), "unit": "iter/s", "cores": 1,
+                              "rates": [round(r, 4) for r in single["rates"]],
+                              "sample": f"s = 1 {sample} ({single['seconds']:.1f} s of CPU work)"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
 def pcg_vs_ite(ctx, psi0, base_opts: dict, dt: float, tol_dE: float = 1e-6, E_ref=None, progress=None):
@@ -279,65 +322,14 @@ def precond_study(name: str, tol: float = 1e-8, max_iter: int = 20000):
     return {"workload": name, "grid": cfg["grid"]["n"], "tol_grad": tol, "runs": rows}
 
 
-CR52_SWEEP = {
-    # Sec. VI.A: 52Cr, counter-polarised moments (6, -6) mu_B, trap 2 pi (100, 100, 800) Hz,
-    # 256 x 256 x 32 grid, N_1 in {2, 5, 8, 10} x 1e5, N_1 / N_2 in {1, 2, 5, 10}, tol 1e-10.
-    # Not stated there and taken here: omega_0 = 2 pi x 100 Hz, a_11 = a_22 = 100 a_0,
-    # a_12 = 70 a_0, the box [-20, 20)^2 x [-6, 6) in units of l and the cutoff radius 6 l.
-    "mass_amu": 51.9405075, "a_bohr": [[100.0, 70.0], [70.0, 100.0]], "mu_bohr": [6.0, -6.0],
-    "f0_hz": 100.0, "trap_hz": [100.0, 100.0, 800.0],
-    "grid": {"n": [256, 256, 32], "lo": [-20.0, -20.0, -6.0], "hi": [20.0, 20.0, 6.0]}, "r_cut_l": 6.0,
-    "N1": [2e5, 5e5, 8e5, 1e6], "ratio": [1, 2, 5, 10],
-}
-
-
-def cr52_sweep(tol: float = 1e-10, max_iter: int = 20000):
-    """The preconditioner sweep of Sec. VI.A on its 52Cr setup, converted from
-    laboratory units: P_V against P_Delta (HS+, restart period 50) from the same
-    seeded Gaussian + noise start for every (N_1, N_1 / N_2); iterations to
-    max_i ||r_i|| < tol and HIP-event seconds."""
-    import torch
-    from paper_2510_24543_amd import inputs, solver, units, autotune
-    S = CR52_SWEEP
-    grid = S["grid"]
-    _, l = units.physical_params(S["mass_amu"], S["a_bohr"], S["mu_bohr"], [1.0, 1.0], S["f0_hz"],
-                                 S["trap_hz"], r_cut_um=1.0)
-    rows, plan = [], None
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for N1 in S["N1"]:
-        for ratio in S["ratio"]:
-            params, _ = units.physical_params(S["mass_amu"], S["a_bohr"], S["mu_bohr"], [N1, N1 / ratio],
-                                              S["f0_hz"], S["trap_hz"], r_cut_um=S["r_cut_l"] * l * 1e6)
-            ctx = solver.Context(grid, params)
-            if plan is None:
-                plan = autotune.tune(ctx)["tuning"]
-            ctx.set_tuning(plan)
-            psi0 = torch.from_numpy(inputs.initial_state(grid, [0.02, 0.02, 1.0], 4242)).cuda()
-            for pc, pname in ((1, "P_V"), (2, "P_Delta")):
-                opts = {"pc": pc, "beta": 0, "restart_period": 50, "sigma": 1e-6, "tol_grad": tol,
-                        "max_iter": max_iter}
-                torch.cuda.synchronize()
-                ev0.record(ctx.stream)
-                _, rep, _ = ctx.solve(psi0, opts)
-                ev1.record(ctx.stream)
-                torch.cuda.synchronize()
-                rows.append({"N1": N1, "N1/N2": ratio, "precond": pname, "iters": rep["iters"],
-                             "status": rep["status"], "seconds": round(ev0.elapsed_time(ev1) / 1000.0, 4),
-                             "E": rep["final"]["E"], "res_max": max(rep["final"]["res"]),
-                             "G11": params["G"][0][0], "Gdd11": params["Gdd"][0][0]})
-                print(f"Cr52 N1 {N1:.0e} ratio {ratio}: {pname} {rep['iters']} iterations {rep['status']} "
-                      f"{rows[-1]['seconds']} s", file=sys.stderr, flush=True)
-            ctx.close()
-            del ctx
-    return {"setup": "52Cr, Sec. VI.A", "length_unit_m": l, "grid": grid, "tol_grad": tol,
-            "assumed": {k: S[k] for k in ("a_bohr", "f0_hz", "r_cut_l")}, "plan": plan, "runs": rows}
-
-
 def scan_comparison(n_inst: int, use_graph: bool = True):
     """Parameter scan of n_inst instances (grids cycling 48^3, 64^3, 96^3; seeded
     g12, gdd, LHY): one batched solve against the same instances solved one after
     another with the plain solver, both to |grad E| < 1e-10 from the same seeded
-    starts.  Times are HIP-event times of the solve calls only."""
+    starts, with the same stall stop (the residual must halve within 1000 steps:
+    past the miscibility edge, g12 > 80, the separated components can turn about
+    the trap's symmetry axis at almost no cost, and the iteration creeps along that
+    soft mode).  Times are HIP-event times of the solve calls only."""
     import torch
     from paper_2510_24543_amd import inputs, solver
 
@@ -347,7 +339,7 @@ def scan_comparison(n_inst: int, use_graph: bool = True):
     params = [s["params"] for s in scan]
     psi0 = [torch.from_numpy(inputs.initial_state(s["grid"], s["params"]["omega"], s["seed"])).cuda()
             for s in scan]
-    opts = {"pc": 1, "beta": 0, "restart_period": 50, "tol_grad": 1e-10, "max_iter": 5000}
+    opts = {"pc": 1, "beta": 0, "restart_period": 50, "tol_grad": 1e-10, "max_iter": 5000, "stall_window": 1000}
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     # FFT plans tuned once per grid shape on a single-instance context; both
@@ -377,7 +369,7 @@ def scan_comparison(n_inst: int, use_graph: bool = True):
 
     t_seq = 0.0
     max_rel = 0.0
-    seq_iters = []
+    seq_iters, seq_s, seq_ok, seq_status = [], [], [], []
     for k, s in enumerate(scan):
         ctx = solver.Context(s["grid"], s["params"])
         ctx.set_tuning(plans[tuple(s["grid"]["n"])])
@@ -386,19 +378,53 @@ def scan_comparison(n_inst: int, use_graph: bool = True):
         _, rep, _ = ctx.solve(psi0[k], opts)
         ev1.record(ctx.stream)
         torch.cuda.synchronize()
-        t_seq += ev0.elapsed_time(ev1) / 1000.0
+        seq_s.append(ev0.elapsed_time(ev1) / 1000.0)
+        t_seq += seq_s[-1]
         seq_iters.append(rep["iters"])
+        seq_ok.append(rep["status"] == "OK")
+        seq_status.append(rep["status"])
         if rep["status"] == "OK" and brep[k]["status"] == "OK":
             max_rel = max(max_rel, abs(rep["final"]["E"] - brep[k]["final"]["E"]) / abs(rep["final"]["E"]))
         ctx.close()
         del ctx
+
+    # the same comparison over the instances that reach the tolerance in both
+    # solvers: a second batched solve of that subset
+    both = [k for k in range(n_inst) if seq_ok[k] and brep[k]["status"] == "OK"]
+    sub = None
+    if both:
+        bs = solver.Batch([grids[k] for k in both], [params[k] for k in both])
+        for k in both:
+            bs.set_tuning(grids[k], plans[tuple(grids[k]["n"])])
+        sub_psi = [psi0[k] for k in both]
+        bs.solve(sub_psi, dict(opts, max_iter=2), use_graph=use_graph)
+        torch.cuda.synchronize()
+        ev0.record(bs.stream)
+        _, srep = bs.solve(sub_psi, opts, use_graph=use_graph)
+        ev1.record(bs.stream)
+        torch.cuda.synchronize()
+        t_sub = ev0.elapsed_time(ev1) / 1000.0
+        bs.close()
+        del bs
+        t_seq_sub = sum(seq_s[k] for k in both)
+        sub = {"instances": len(both), "batched_s": round(t_sub, 4), "sequential_plain_s": round(t_seq_sub, 4),
+               "speedup": round(t_seq_sub / t_sub, 3), "batched_converged": sum(r["status"] == "OK" for r in srep),
+               "iters_batched_total": sum(r["iters"] for r in srep),
+               "iters_plain_total": sum(seq_iters[k] for k in both)}
     return {"instances": n_inst, "grids": "48^3/64^3/96^3 cycling", "tol_grad": 1e-10,
             "plans": {"x".join(map(str, k)): v for k, v in plans.items()}, "tuning_s": round(t_tune, 3),
             "batched_s": round(t_batch, 4), "sequential_plain_s": round(t_seq, 4),
             "speedup": round(t_seq / t_batch, 3), "graph": use_graph,
             "batched_converged": sum(r["status"] == "OK" for r in brep),
             "max_rel_dE_vs_plain": max_rel,
-            "iters_batched_total": sum(r["iters"] for r in brep), "iters_plain_total": sum(seq_iters)}
+            "iters_batched_total": sum(r["iters"] for r in brep), "iters_plain_total": sum(seq_iters),
+            "stall_window": opts["stall_window"],
+            "status_batched": {st: sum(r["status"] == st for r in brep) for st in sorted({r["status"] for r in brep})},
+            "status_plain": {st: seq_status.count(st) for st in sorted(set(seq_status))},
+            "not_converged": [{"k": k, "g12": round(params[k]["G"][0][1], 2), "batched": brep[k]["status"],
+                               "plain": seq_status[k], "iters": brep[k]["iters"]}
+                              for k in range(n_inst) if brep[k]["status"] != "OK" or seq_status[k] != "OK"],
+            "converged_in_both": sub}
 
 
 def main():
@@ -406,25 +432,28 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=5, help="oracle iterations for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=3, help="oracle iterations per CPU-baseline sample (0: skip)")
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution solve")
     ap.add_argument("--scan", type=int, default=96, help="instances of the batched-vs-plain scan (0: skip)")
     ap.add_argument("--ite-dt", type=float, default=0.01,
                     help="imaginary-time step of the PCG-vs-ITE comparison (0: skip it)")
     ap.add_argument("--precond-study", default=None, metavar="WORKLOAD",
                     help="only run the preconditioner x conjugacy-rule study on this workload and print it")
-    ap.add_argument("--cr52-sweep", action="store_true",
-                    help="only run the P_V vs P_Delta sweep on the 52Cr laboratory setup and print it")
     ap.add_argument("--ite-only", default=None, metavar="WORKLOAD",
                     help="only run the PCG-vs-ITE comparison on this workload (e.g. C2, C3, C5) and print it")
     ap.add_argument("--tuning", choices=("auto", "cache", "default"), default="auto",
                     help="launch plans: autotune now, read the committed cache, or the defaults")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--cpu-leg", nargs=2, type=int, default=None, metavar=("SAMPLE", "REPEATS"),
+                    help="only time the oracle at this process's OpenMP thread count (child of the CPU baseline)")
     ap.add_argument("--pmc-summary", nargs=5, default=None,
                     metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "COPY_MIB"),
                     help="only turn rocprofv3 counter CSVs into the committed traffic summary")
     args = ap.parse_args()
+    if args.cpu_leg:
+        cpu_leg(*args.cpu_leg)
+        return
     if args.pmc_summary:
         a = args.pmc_summary
         pmc_summary(a[0], a[1], a[2], a[3], int(a[4]))
@@ -445,9 +474,6 @@ def main():
         return
     if args.ite_only:
         print(json.dumps(ite_workload(args.ite_only, args.ite_dt)), flush=True)
-        return
-    if args.cr52_sweep:
-        print(json.dumps(cr52_sweep()), flush=True)
         return
 
     cfg = inputs.CONFIGS[WORKLOAD]
@@ -548,7 +574,7 @@ def main():
 
     cpu = None
     if args.cpu_sample > 0:
-        cpu = cpu_baseline(grid, params, psi0_np, args.cpu_sample)
+        cpu = cpu_baseline(args.cpu_sample)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "iter/s", "n_gpus": 1,

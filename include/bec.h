@@ -54,7 +54,8 @@ typedef enum {
     BEC_ENOTCONV = 4,      /* solve stopped at max_iter                          */
     BEC_ESTAGNATED = 5,    /* no descent even after the beta = 0 restart         */
     BEC_ENONFINITE = 6,    /* a reduced scalar was NaN or infinite               */
-    BEC_EUNSUPPORTED = 7   /* axis length not supported                          */
+    BEC_EUNSUPPORTED = 7,  /* axis length not supported                          */
+    BEC_ESTALLED = 8       /* the residual stopped falling (bec_opts.stall_window) */
 } bec_status;
 
 /* Periodic box [lo, hi) with n points per axis (x, y, z). */
@@ -101,6 +102,11 @@ typedef struct {
     int32_t restart_period; /* beta = 0 when iter mod restart_period == 0; 0 off */
     int32_t max_backtrack;  /* Armijo halvings per step                        */
     int32_t flags;          /* BEC_SOLVE_* bits; 0 = default                   */
+    int32_t stall_window;   /* > 0: stop with BEC_ESTALLED when max_i ||r_i||
+                               has not fallen below half of its reference value
+                               within the last stall_window accepted steps (the
+                               reference is reset each time it is halved); 0 off */
+    int32_t reserved;       /* 0                                               */
     double tol_grad;        /* stop when max_i ||H_i psi_i - mu_i psi_i|| < tol */
     double tol_dE;          /* stop when |E_n - E_(n-1)| < tol_dE (0: off)     */
     double sigma;           /* regularising shift of P_V and P_Delta           */
@@ -176,6 +182,14 @@ bec_status bec_hamiltonian(bec_ctx* ctx, const double* psi, double* hpsi, bec_te
  * Synchronises. */
 bec_status bec_gradient(bec_ctx* ctx, const double* psi, double* grad, int32_t projected,
                         bec_terms* out_h);
+
+/* E (Sec. II, Eq. (1)) and the Euclidean gradient 2 N_i dV H_i psi_i of
+ * bec_gradient (projected = 0) without synchronising: every launch is enqueued
+ * on the context stream and the call returns.  E is written to E_dev (device
+ * memory, one double) by the stream, bit for bit the E of bec_energy; a state
+ * with a non-finite energy leaves a non-finite value there (no status).  The
+ * autograd energy uses it so that its forward needs no host round trip. */
+bec_status bec_energy_gradient_async(bec_ctx* ctx, const double* psi, double* grad, double* E_dev);
 
 /* The gradient of bec_gradient without a context and without allocating:
  * for callers that cannot allocate device or pinned host memory at call time

@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.environ.get("ORACLE_LIB_PATH") or os.path.join(_HERE, "liboracle.so")
 _SRC_PATH = os.path.join(_HERE, "oracle.c")
 
-STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 4: "ENOTCONV", 5: "ESTAGNATED", 6: "ENONFINITE"}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 4: "ENOTCONV", 5: "ESTAGNATED", 6: "ENONFINITE", 8: "ESTALLED"}
 
 
 def build(force: bool = True) -> str:
@@ -61,7 +61,7 @@ class Terms(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("pc", C.c_int32), ("beta", C.c_int32), ("max_iter", C.c_int32),
-                ("restart_period", C.c_int32), ("max_backtrack", C.c_int32), ("pad", C.c_int32),
+                ("restart_period", C.c_int32), ("max_backtrack", C.c_int32), ("stall_window", C.c_int32),
                 ("tol_grad", C.c_double), ("tol_dE", C.c_double), ("sigma", C.c_double),
                 ("armijo_c1", C.c_double), ("theta_max", C.c_double), ("tau_rel", C.c_double)]
 

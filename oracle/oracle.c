@@ -79,7 +79,10 @@ typedef struct {
     int32_t max_iter;
     int32_t restart_period; /* K_r: beta = 0 when n mod K_r == 0 (0: never)    */
     int32_t max_backtrack;
-    int32_t pad;
+    int32_t stall_window;   /* > 0: stop (ORC_ESTALLED) when max_i ||r_i|| has not
+                               fallen below half of its reference value within the
+                               last stall_window accepted steps; the reference is
+                               the last value that halved it (0: off)             */
     double tol_grad;        /* stop when max_i ||r_i|| < tol_grad              */
     double tol_dE;          /* stop when |E_n - E_{n-1}| < tol_dE (0: off)     */
     double sigma;           /* regularising shift of the preconditioners      */
@@ -115,7 +118,7 @@ typedef struct {
 } orc_report;
 
 enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_ENOMEM = 2, ORC_ENOTCONV = 4,
-       ORC_ESTAGNATED = 5, ORC_ENONFINITE = 6 };
+       ORC_ESTAGNATED = 5, ORC_ENONFINITE = 6, ORC_ESTALLED = 8 };
 
 /* ------------------------------------------------------------------------- */
 /* Deterministic sums: fixed blocks summed in order (independent of threads)  */
@@ -960,8 +963,8 @@ int orc_solve_trace(const orc_grid *gr, const orc_params *P, const orc_opts *o, 
 
     const double w[2] = { (P->N[0] / (P->N[0] + P->N[1])) * (P->N[0] / (P->N[0] + P->N[1])),
                           (P->N[1] / (P->N[0] + P->N[1])) * (P->N[1] / (P->N[0] + P->N[1])) };
-    int have_prev = 0, n = 0, status = ORC_ENOTCONV;
-    double E_prev = NAN, alpha_prev = 0.0, rz_old = 0.0;
+    int have_prev = 0, n = 0, status = ORC_ENOTCONV, stall_it = 0;
+    double E_prev = NAN, alpha_prev = 0.0, rz_old = 0.0, stall_ref = INFINITY;
 
     for (;;) {
         /* 1. residual r_i = H_i psi_i - mu_i psi_i and convergence (Sec. III) */
@@ -974,6 +977,15 @@ int orc_solve_trace(const orc_grid *gr, const orc_params *P, const orc_opts *o, 
         if (!finite2(cur.t.E, res_max)) { status = ORC_ENONFINITE; break; }
         if (res_max < o->tol_grad) { status = ORC_OK; break; }
         if (o->tol_dE > 0.0 && n > 0 && fabs(cur.t.E - E_prev) < o->tol_dE) { status = ORC_OK; break; }
+        /* stall rule (not in the paper): the residual must halve within
+         * stall_window accepted steps of its last halving */
+        if (res_max < 0.5 * stall_ref) {
+            stall_ref = res_max;
+            stall_it = n;
+        } else if (o->stall_window > 0 && n - stall_it >= o->stall_window) {
+            status = ORC_ESTALLED;
+            break;
+        }
         if (n >= o->max_iter) { status = ORC_ENOTCONV; break; }
 
         /* 2. preconditioned residual z = P^-1 r (Sec. IV.B) */

@@ -11,7 +11,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libbecpcg.so")
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ENOTCONV", 5: "ESTAGNATED",
-          6: "ENONFINITE", 7: "EUNSUPPORTED"}
+          6: "ENONFINITE", 7: "EUNSUPPORTED", 8: "ESTALLED"}
 
 
 class BecError(RuntimeError):
@@ -37,7 +37,7 @@ class Params(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("pc", C.c_int32), ("beta", C.c_int32), ("max_iter", C.c_int32),
                 ("restart_period", C.c_int32), ("max_backtrack", C.c_int32), ("flags", C.c_int32),
-                ("tol_grad", C.c_double), ("tol_dE", C.c_double), ("sigma", C.c_double),
+                ("stall_window", C.c_int32), ("reserved", C.c_int32), ("tol_grad", C.c_double), ("tol_dE", C.c_double), ("sigma", C.c_double),
                 ("armijo_c1", C.c_double), ("theta_max", C.c_double), ("tau_rel", C.c_double)]
 
 
@@ -103,6 +103,7 @@ SIGNATURES = [
     ("bec_energy", C.c_int, [_VP, _VP, C.POINTER(Terms)]),
     ("bec_hamiltonian", C.c_int, [_VP, _VP, _VP, C.POINTER(Terms)]),
     ("bec_gradient", C.c_int, [_VP, _VP, _VP, _I32, C.POINTER(Terms)]),
+    ("bec_energy_gradient_async", C.c_int, [_VP, _VP, _VP, _VP]),
     ("bec_gradient_noalloc", C.c_int, [C.POINTER(Grid), C.POINTER(Params), _VP, _VP, _VP, _I32,
                                        C.POINTER(Terms)]),
     ("bec_precond_apply", C.c_int, [_VP, _I32, _DBL, _VP, _VP, _VP]),

@@ -1448,6 +1448,16 @@ bec_status bec_gradient(bec_ctx* c, const double* psi, double* grad, int32_t pro
     return BEC_OK;
 }
 
+bec_status bec_energy_gradient_async(bec_ctx* c, const double* psi, double* grad, double* E_dev)
+{
+    if (!c || !psi || !grad || !E_dev) return fail(BEC_EINVAL, "null argument");
+    STCHK(heval_launch(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, nullptr, 0));
+    HIPCHK(bec::launch_grad(c->P, c->psi[0], c->hpsi[0], reinterpret_cast<double2*>(grad), 0.0, 0.0,
+                            2.0 * c->p.N[0] * c->dV, 2.0 * c->p.N[1] * c->dV, 0, c->st));
+    HIPCHK(bec::launch_energy_from_sums(c->P, c->dscal + kScalHeval, c->dV, E_dev, c->st));
+    return BEC_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -1620,6 +1630,7 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
     if (!c || !psi_inout || !o) return fail(BEC_EINVAL, "null argument");
     if (o->pc < 0 || o->pc > 4 || o->beta < 0 || o->beta > 2) return fail(BEC_EINVAL, "bad options");
     if (o->flags & ~BEC_SOLVE_SYNCHRONOUS) return fail(BEC_EINVAL, "unknown bits in opts.flags: 0x%x", o->flags);
+    if (o->stall_window < 0) return fail(BEC_EINVAL, "stall_window must be >= 0");
     const auto t0 = std::chrono::steady_clock::now();
     const double dV = c->dV;
     const bec_params& p = c->p;
@@ -1632,9 +1643,9 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
     STCHK(heval(c, c->psi[0], nullptr, kOne, kZero, 0, &ev));
 
     bool have_prev = false;
-    int n = 0;
+    int n = 0, stall_it = 0;
     bec_status status = BEC_ENOTCONV;
-    double E_prev = NAN, alpha_prev = 0.0, rz_old = 0.0;
+    double E_prev = NAN, alpha_prev = 0.0, rz_old = 0.0, stall_ref = INFINITY;
     const int zmode_pc = (o->pc == BEC_PC_V) ? 1 : (o->pc == BEC_PC_NONE ? 0 : (o->pc == BEC_PC_SYMMETRIC ? 3 : 2));
     // Pipelined iterations: the first trial of a step is enqueued at the step
     // the device decides from the model sums, followed by the preconditioned
@@ -1673,6 +1684,13 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
         if (!std::isfinite(res_max) || !std::isfinite(ev.t.E)) { status = BEC_ENONFINITE; break; }
         if (res_max < o->tol_grad) { status = BEC_OK; break; }
         if (o->tol_dE > 0 && n > 0 && std::fabs(ev.t.E - E_prev) < o->tol_dE) { status = BEC_OK; break; }
+        if (res_max < 0.5 * stall_ref) {
+            stall_ref = res_max;
+            stall_it = n;
+        } else if (o->stall_window > 0 && n - stall_it >= o->stall_window) {
+            status = BEC_ESTALLED;
+            break;
+        }
         if (n >= o->max_iter) { status = BEC_ENOTCONV; break; }
 
         // 2. beta (HS+ or PR+), restarts (Sec. IV.C)
@@ -1828,7 +1846,9 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
     rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (out_h) *out_h = rep;
     if (status != BEC_OK && status != BEC_ENOTCONV)
-        fail(status, status == BEC_ESTAGNATED ? "no descent after a beta = 0 restart" : "non-finite state");
+        fail(status, status == BEC_ESTAGNATED ? "no descent after a beta = 0 restart"
+                     : status == BEC_ESTALLED ? "the residual did not halve within stall_window steps"
+                                              : "non-finite state");
     return status;
 }
 
@@ -2326,6 +2346,7 @@ bec::BOpts to_bopts(const bec_opts* o)
     b.max_iter = o->max_iter;
     b.restart_period = o->restart_period;
     b.max_backtrack = o->max_backtrack;
+    b.stall_window = o->stall_window;
     b.tol_grad = o->tol_grad;
     b.tol_dE = o->tol_dE;
     b.sigma = o->sigma;
@@ -2642,7 +2663,8 @@ bec_status bec_batch_solve(bec_batch* b, double* const* psi_inout, const bec_opt
         R.n_backtracks = S.n_backtracks;
         R.status = S.status == bec::kBConverged ? BEC_OK
                    : S.status == bec::kBRunning || S.status == bec::kBNotConv ? BEC_ENOTCONV
-                   : S.status == bec::kBStagnated ? BEC_ESTAGNATED : BEC_ENONFINITE;
+                   : S.status == bec::kBStagnated ? BEC_ESTAGNATED
+                   : S.status == bec::kBStalled ? BEC_ESTALLED : BEC_ENONFINITE;
         bec::BInstParams P;
         instance_params(b->grids[b->perm[i]], p, P);
         const double* H = S.hsum;

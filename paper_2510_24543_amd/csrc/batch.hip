@@ -367,6 +367,8 @@ __global__ void b_decide_init_kernel(int n, const BInstParams* ip, BInstState* s
     S.phase = kBInit;
     S.cur = 0;
     S.iter = S.have_prev = S.level = S.path = S.nbt = S.n_restarts = S.n_backtracks = S.rounds = 0;
+    S.stall_it = 0;
+    S.stall_ref = __builtin_inf();
     S.E_prev = __builtin_nan("");
     S.alpha_prev = S.rz_old = 0.0;
     const double n0 = ip[i].dV * R[kSR + 0], n1 = ip[i].dV * R[kSR + 1];
@@ -402,6 +404,13 @@ __global__ void b_decide_dir_kernel(int n, BOpts o, const BInstParams* ip, BInst
         if (!isfinite(res_max) || !isfinite(S.E)) { S.status = kBNonFinite; return; }
         if (res_max < o.tol_grad) { S.status = kBConverged; return; }
         if (o.tol_dE > 0.0 && S.iter > 0 && fabs(S.E - S.E_prev) < o.tol_dE) { S.status = kBConverged; return; }
+        if (res_max < 0.5 * S.stall_ref) {     // the stall rule of bec_opts.stall_window
+            S.stall_ref = res_max;
+            S.stall_it = S.iter;
+        } else if (o.stall_window > 0 && S.iter - S.stall_it >= o.stall_window) {
+            S.status = kBStalled;
+            return;
+        }
         if (S.iter >= o.max_iter) { S.status = kBNotConv; return; }
         const bool restart = !S.have_prev || o.beta_mode == 2 || (o.restart_period > 0 && S.iter % o.restart_period == 0);
         double beta = 0.0;

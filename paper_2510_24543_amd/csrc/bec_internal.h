@@ -269,6 +269,8 @@ hipError_t launch_scale2(const PwParams& P, const double2* in, double2* out, dou
                          hipStream_t s);
 hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hpsi, double2* out,
                        double mu0, double mu1, double s0, double s1, int projected, hipStream_t s);
+// E from the reduced energy sums (device) into out[0] (device), one thread
+hipError_t launch_energy_from_sums(const PwParams& P, const double* sums, double dV, double* out, hipStream_t s);
 // Closed-form step of the second-order model (Sec. V) from the reduced model
 // sums, on the device, so the trial point can be enqueued before the host has
 // read them.  One thread; writes kStepOut values to out (device) and out_host
@@ -331,19 +333,20 @@ struct BInstParams {
     double lhytab[3 * kLhyTabMax];
 };
 
-enum : int { kBRunning = 0, kBConverged = 1, kBNotConv = 2, kBStagnated = 3, kBNonFinite = 4 };
+enum : int { kBRunning = 0, kBConverged = 1, kBNotConv = 2, kBStagnated = 3, kBNonFinite = 4, kBStalled = 5 };
 enum : int { kBInit = 0, kBNewDir = 1, kBBacktrack = 2, kBRedo = 3 };
 
 struct BInstState {
-    int status, phase, cur, iter, have_prev, level, path, nbt, n_restarts, n_backtracks, rounds, pad;
+    int status, phase, cur, iter, have_prev, level, path, nbt, n_restarts, n_backtracks, rounds, stall_it;
     double E, E_prev, mu[2], shift[2], norm2[2], res[2];
+    double stall_ref;             // reference residual of the stall rule (halved -> reset)
     double beta, c[2], zpsi[2], ppsi[2], rz[2], rz_old, rz_now, alpha, alpha_prev, E1, E2, rp;
     double pnorm[2], psip[2], a[2], b[2];
     double hsum[kHevalSums];      // Hamiltonian sums of the accepted state
 };
 
 struct BOpts {                    // the bec_opts fields the device decisions use
-    int beta_mode, max_iter, restart_period, max_backtrack;
+    int beta_mode, max_iter, restart_period, max_backtrack, stall_window, pad;
     double tol_grad, tol_dE, sigma, armijo_c1, theta_max, tau_rel;
 };
 

@@ -460,6 +460,27 @@ __global__ __launch_bounds__(kPwThreads) void grad_kernel(PwParams P, const doub
     }
 }
 
+// E of Sec. II, Eq. (1) from the reduced energy sums S (kHevalSums), with the
+// products and the order of the host's reading of the same sums, so both give
+// the same bits.  One thread.
+__global__ void energy_from_sums_kernel(PwParams P, const double* __restrict__ S, double dV, double* __restrict__ out)
+{
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double snn[2][2] = {{S[4], S[5]}, {S[5], S[6]}};
+    double E = dV * S[11];
+    for (int i = 0; i < 2; ++i) {
+        const double e_kin = P.Nat[i] * dV * S[i], e_trap = P.Nat[i] * dV * S[2 + i];
+        E += e_kin + e_trap;
+        for (int j = 0; j < 2; ++j) {
+            const double e_c = 0.5 * P.Nat[i] * P.G[i][j] * dV * snn[i][j];
+            const double e_dd = 0.5 * P.Nat[i] * P.Gdd[i][j] * dV * S[7 + 2 * i + j];
+            E += e_c + e_dd;
+        }
+    }
+    out[0] = E;
+}
+
 // One block per scalar: blocks [0, M1) reduce rows of s1.partials (s1.nblk per
 // row) into s1.out, the next M2 blocks rows of s2 into s2.out, the rest rows of
 // s3 into s3.out (and each into its copy when that is set).
@@ -614,6 +635,12 @@ hipError_t launch_grad(const PwParams& P, const double2* psi, const double2* hps
 {
     hipLaunchKernelGGL(grad_kernel, dim3(pw_blocks(P)), dim3(kPwThreads), 0, s, P, psi, hpsi, out, mu0,
                        mu1, s0, s1, projected);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_from_sums(const PwParams& P, const double* sums, double dV, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(energy_from_sums_kernel, dim3(1), dim3(64), 0, s, P, sums, dV, out);
     return hipGetLastError();
 }
 

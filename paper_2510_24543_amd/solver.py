@@ -129,6 +129,19 @@ class Context:
         B.check(B.lib().bec_gradient(self._ctx, _ptr(psi), _ptr(g), int(projected), C.byref(t)), "bec_gradient")
         return g, t.to_dict()
 
+    def energy_gradient_async(self, psi):
+        """(E, grad): E a 0-d float64 tensor on the device and the Euclidean
+        gradient, both produced by the context stream without a host sync."""
+        psi = self.field(psi)
+        g = self.empty()
+        E = torch.empty((), dtype=torch.float64, device=self.device)
+        B.check(B.lib().bec_energy_gradient_async(self._ctx, _ptr(psi), _ptr(g), _ptr(E)),
+                "bec_energy_gradient_async")
+        if self.stream != torch.cuda.current_stream(self.device):
+            for t in (psi, g, E):      # in use on the context stream after this returns
+                t.record_stream(self.stream)
+        return E, g
+
     def precond(self, pc, psi, r, sigma: float = 1e-6) -> torch.Tensor:
         pc = PC[pc] if isinstance(pc, str) else int(pc)
         psi = self.field(psi)
@@ -156,7 +169,7 @@ class Context:
         cap = max(int(log_cap), 0)
         logs = (B.Iter * max(cap, 1))()
         st = B.lib().bec_solve(self._ctx, _ptr(psi), C.byref(B.make_opts(opts)), C.byref(rep), logs, cap)
-        B.check(st, "bec_solve", ok=(0, 4, 5))
+        B.check(st, "bec_solve", ok=(0, 4, 5, 8))
         out = {"iters": rep.iters, "n_restarts": rep.n_restarts, "n_backtracks": rep.n_backtracks,
                "status": B.STATUS[rep.status], "final": rep.final.to_dict(), "seconds": rep.seconds}
         log = [{k: getattr(logs[i], k) for k, _ in B.Iter._fields_} for i in range(min(rep.iters, cap))]
@@ -312,8 +325,9 @@ def params_with_theta(params: dict, theta) -> dict:
 class Energy(torch.autograd.Function):
     """E[psi; theta] of Sec. II, Eq. (1) as a differentiable function.
 
-    forward: one H evaluation on the GPU (bec_gradient) gives E and the
-    Euclidean gradient 2 N_i dV H_i psi_i, kept for backward.
+    forward: one H evaluation on the GPU (bec_energy_gradient_async) gives E as
+    a device tensor and the Euclidean gradient 2 N_i dV H_i psi_i, kept for
+    backward, with no host synchronisation.
     backward: grad_psi = dL/dE * 2 N_i dV H_i psi_i (PyTorch's convention for a
     real function of a complex tensor: dE/dRe + i dE/dIm); grad_theta =
     dL/dE * (dE/dG_ij, dE/dGdd_ij, dE/dc_lhy) from bec_param_grad.  At a
@@ -325,10 +339,10 @@ class Energy(torch.autograd.Function):
         p = params_with_theta(bctx.params, theta.detach().cpu().tolist())
         if theta_of(bctx.params).tolist() != theta_of(p).tolist():
             bctx.set_params(p)
-        grad, terms = bctx.gradient(psi.detach(), projected=False)
+        E, grad = bctx.energy_gradient_async(psi.detach())
         ctx_.bctx = bctx
         ctx_.save_for_backward(psi.detach(), grad)
-        return torch.tensor(terms["E"], dtype=torch.float64, device=psi.device)
+        return E
 
     @staticmethod
     def backward(ctx_, gE: torch.Tensor):

@@ -48,6 +48,20 @@ def test_energy_function_forward_and_psi_gradient(solver, orc):
     assert abs(fd - pred) <= 1e-7 * abs(pred)
 
 
+def test_energy_forward_is_a_device_tensor_without_host_round_trip(solver):
+    """The forward's E comes from the device (bec_energy_gradient_async): a 0-d
+    tensor on the GPU, bit for bit the E of bec_energy, with the gradient of
+    bec_gradient."""
+    ctx = solver.Context(SMALL, P_SMALL)
+    psi = torch.from_numpy(inputs.initial_state(SMALL, P_SMALL["omega"], 35, phase=True)).cuda()
+    E = solver.energy(psi, solver.theta_of(P_SMALL), ctx)
+    assert E.is_cuda and E.dim() == 0 and E.dtype == torch.float64
+    assert E.item() == ctx.energy(psi)["E"]
+    E2, g = ctx.energy_gradient_async(psi)
+    g_ref, t = ctx.gradient(psi, projected=False)
+    assert torch.equal(g, g_ref) and E2.item() == t["E"]
+
+
 def test_energy_function_theta_gradient(solver, orc):
     ctx = solver.Context(SMALL, P_SMALL)
     psi = torch.from_numpy(inputs.initial_state(SMALL, P_SMALL["omega"], 33, phase=True)).cuda()

@@ -221,3 +221,21 @@ def test_scan_instances_batched_against_oracle(solver, orc):
         g = pb.cpu().numpy()
         for i in range(2):
             assert np.max(np.abs(g[i][idx] - psio[i][idx])) <= 1e-10 * np.max(np.abs(psio[i]))
+
+
+# ---------------------------------------------------------------- stall stop
+@pytest.mark.parametrize("scale,window", [(1.0, 3), (10.0, 4)])
+def test_stall_stop_plain_and_batched(solver, orc, scale, window):
+    """bec_opts.stall_window: the plain solver and the batched one stop with
+    ESTALLED at the step the oracle does, with the same log."""
+    params = mixed_params(scale)
+    psi0 = inputs.initial_state(GRID16, params["omega"], 71, phase=True)
+    opts = {"tol_grad": 1e-10, "max_iter": 200, "pc": 1, "stall_window": window}
+    psi, rep, log, psio, repo, logo = run_both(solver, orc, GRID16, params, psi0, opts, 200)
+    assert repo["status"] == rep["status"] == "ESTALLED" and rep["iters"] == repo["iters"]
+    compare_logs(log, logo)
+    b = solver.Batch([GRID16, GRID16], [params, mixed_params(1.0 if scale != 1.0 else 10.0)])
+    other = inputs.initial_state(GRID16, params["omega"], 71, phase=True)
+    _, reps = b.solve([psi0, other], opts, rounds_per_sync=4)
+    assert reps[0]["status"] == "ESTALLED" and reps[0]["iters"] == repo["iters"]
+    assert abs(reps[0]["final"]["E"] - repo["final"]["E"]) <= 1e-11 * abs(repo["final"]["E"])

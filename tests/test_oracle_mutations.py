@@ -83,6 +83,9 @@ MUTANTS = {
         [("if (level == 2) precond_apply(&g, P, &cur, 1, o->sigma, r, z);",
           "if (level == 2) precond_apply(&g, P, &cur, 2, o->sigma, r, z);")],
         [RULES + "test_composite_fallback_ladder"]),
+    "stall reference reset without halving": (
+        [("if (res_max < 0.5 * stall_ref) {", "if (res_max < 0.9 * stall_ref) {")],
+        [RULES + "test_stall_stop_fires_at_the_first_step_its_definition_names"]),
     "failed line search not retried with beta = 0": (
         [("if (level == 0) { level = 1; rep->n_restarts++; path |= 2; continue; }", "")],
         [RULES + "test_beta_zero_retry_after_a_failed_line_search"]),

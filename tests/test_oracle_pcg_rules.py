@@ -364,3 +364,30 @@ def test_composite_fallback_ladder(orc):
             assert E1_of(project(-zv, psi), r, P) >= 0.0   # so does P_V^-1 r
             assert np.array_equal(tr[k]["z"], r)
         assert np.array_equal(tr[k]["d"], -tr[k]["z"])
+
+
+# ---------------------------------------------------------------- stall stop (not in the paper)
+@pytest.mark.parametrize("scale,window", [(1.0, 3), (1.0, 6), (10.0, 4)])
+def test_stall_stop_fires_at_the_first_step_its_definition_names(orc, scale, window):
+    """stall_window W: the solve stops (ESTALLED) at the first step n where
+    max_i ||r_i|| has not fallen below half of its reference value for W steps,
+    the reference being the last value that halved the one before it (the
+    first residual to start with).  Checked against the logged residuals."""
+    import oracle
+    P = _params(scale)
+    psi0 = inputs.initial_state(GRID, P["omega"], 71, phase=True)
+    _, rep, log = oracle.solve(GRID, P, psi0, {"tol_grad": 1e-10, "max_iter": 200, "stall_window": window},
+                               log_cap=200)
+    assert rep["status"] == "ESTALLED"
+    res = [L["res_max"] for L in log] + [max(rep["final"]["res"])]   # residual at the start of steps 0..n
+    ref, ref_it, stop = np.inf, 0, None
+    for k, r in enumerate(res):
+        if r < 0.5 * ref:
+            ref, ref_it = r, k
+        elif k - ref_it >= window:
+            stop = k
+            break
+    assert stop == rep["iters"]
+    # without the rule the same run goes on
+    _, rep0, _ = oracle.solve(GRID, P, psi0, {"tol_grad": 1e-10, "max_iter": rep["iters"] + 5})
+    assert rep0["status"] == "ENOTCONV" and rep0["iters"] == rep["iters"] + 5
