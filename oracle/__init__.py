@@ -41,7 +41,7 @@ class Grid(C.Structure):
 class Params(C.Structure):
     _fields_ = [("N", C.c_double * 2), ("omega", C.c_double * 3),
                 ("G", (C.c_double * 2) * 2), ("Gdd", (C.c_double * 2) * 2),
-                ("c_lhy", C.c_double), ("r_cut", C.c_double), ("n_u", C.c_int32)]
+                ("c_lhy", C.c_double), ("r_cut", C.c_double), ("n_u", C.c_int32), ("dip_cut", C.c_int32)]
 
 
 class Terms(C.Structure):
@@ -140,6 +140,7 @@ def make_params(p: dict) -> Params:
     for d in range(3):
         P.omega[d] = float(p["omega"][d])
     P.c_lhy = float(p["c_lhy"]); P.r_cut = float(p["r_cut"]); P.n_u = int(p["n_u"])
+    P.dip_cut = int(p.get("dip_cut", 0))
     return P
 
 

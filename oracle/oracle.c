@@ -60,8 +60,11 @@ typedef struct {
     double G[2][2];     /* contact couplings G_ij                            */
     double Gdd[2][2];   /* dipolar k-space amplitudes                        */
     double c_lhy;       /* multiplier of the LHY term                        */
-    double r_cut;       /* spherical cutoff radius of the dipolar kernel     */
+    double r_cut;       /* cutoff of the dipolar kernel (radius, or slab half-height) */
     int32_t n_u;        /* Gauss-Legendre nodes for the u integral           */
+    int32_t dip_cut;    /* 0: spherical cutoff of radius r_cut; 1: slab cut,
+                           the interaction kept for |z - z'| < r_cut and
+                           unbounded in the periodic x, y directions          */
 } orc_params;
 
 typedef struct {
@@ -332,6 +335,23 @@ static double cutoff_factor(double q)
     return s;
 }
 
+/* Dipolar kernel cut to the slab |z| < Z (dipoles along z; x and y periodic
+ * and not cut).  With k_rho = sqrt(kx^2 + ky^2), the in-plane transform of the
+ * unit-amplitude kernel at height u is -(3/2) k_rho exp(-k_rho |u|) (from the
+ * plane transform of 1/r^3, 2 pi exp(-k_rho |u|) / |u|) plus the contact part
+ * 2 delta(u) that makes the uncut kernel (3 kz^2/k^2 - 1); integrating over
+ * |u| < Z gives
+ *   Ud = (3 kz^2/k^2 - 1) + 3 exp(-k_rho Z) (k_rho^2 cos(kz Z) - k_rho kz sin(kz Z)) / k^2,
+ * and Ud(0) = 2, the limit along every direction. */
+static double slab_kernel(double kx, double ky, double kz, double Z)
+{
+    double kr2 = kx * kx + ky * ky, k2 = kr2 + kz * kz;
+    if (k2 == 0.0) return 2.0;
+    double kr = sqrt(kr2);
+    return (3.0 * kz * kz / k2 - 1.0) +
+           3.0 * exp(-kr * Z) * (kr2 * cos(kz * Z) - kr * kz * sin(kz * Z)) / k2;
+}
+
 static double kvec(int j, int n, double L)
 {
     int jj = (j < n / 2) ? j : j - n;
@@ -366,7 +386,8 @@ static int geom_init(geom *g, const orc_grid *gr, const orc_params *P)
                                  P->omega[2] * P->omega[2] * z * z);
                 double k2 = kx * kx + ky * ky + kz * kz;
                 g->K2h[i] = 0.5 * k2;
-                if (k2 == 0.0) g->Ud[i] = 0.0;
+                if (P->dip_cut == 1) g->Ud[i] = slab_kernel(kx, ky, kz, P->r_cut);
+                else if (k2 == 0.0) g->Ud[i] = 0.0;
                 else g->Ud[i] = (3.0 * kz * kz / k2 - 1.0) * cutoff_factor(sqrt(k2) * P->r_cut);
             }
         }
@@ -557,6 +578,9 @@ static int check_inputs(const orc_grid *gr, const orc_params *P)
         if (!(gr->hi[d] > gr->lo[d])) return ORC_EINVAL;
     }
     if (P->n_u < 1 || P->N[0] <= 0 || P->N[1] <= 0) return ORC_EINVAL;
+    if (P->dip_cut != 0 && P->dip_cut != 1) return ORC_EINVAL;
+    /* the slab cut is exact on the periodic grid when the cut kernel fits in one period */
+    if (P->dip_cut == 1 && !(P->r_cut > 0.0 && 2.0 * P->r_cut <= gr->hi[2] - gr->lo[2])) return ORC_EINVAL;
     return ORC_OK;
 }
 

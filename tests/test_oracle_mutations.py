@@ -33,7 +33,7 @@ MUTANTS = {
         [("g->K2h[i] = 0.5 * k2;", "g->K2h[i] = k2;")],
         [PINS + "test_plane_wave_is_kinetic_eigenfunction", PINS + "test_gaussian_kinetic_energy_closed_form"]),
     "kx in place of kz in the dipolar kernel": (
-        [("(3.0 * kz * kz / k2 - 1.0)", "(3.0 * kx * kx / k2 - 1.0)")],
+        [("else g->Ud[i] = (3.0 * kz * kz / k2 - 1.0)", "else g->Ud[i] = (3.0 * kx * kx / k2 - 1.0)")],
         [PINS + "test_dipolar_energy_of_cylindrical_gaussian"]),
     "component index in n_2''": (
         [("n2pp = p2 - n2 * gam2inv[1];", "n2pp = p2 - n2 * gam2inv[0];")],
@@ -86,6 +86,12 @@ MUTANTS = {
     "stall reference reset without halving": (
         [("if (res_max < 0.5 * stall_ref) {", "if (res_max < 0.9 * stall_ref) {")],
         [RULES + "test_stall_stop_fires_at_the_first_step_its_definition_names"]),
+    "slab cut: sign of the sin term": (
+        [("(kr2 * cos(kz * Z) - kr * kz * sin(kz * Z))", "(kr2 * cos(kz * Z) + kr * kz * sin(kz * Z))")],
+        ["tests/test_oracle_slab_dipoles.py::test_layer_energy_closed_form"]),
+    "slab cut: zero mode 0 instead of 2": (
+        [("if (k2 == 0.0) return 2.0;", "if (k2 == 0.0) return 0.0;")],
+        ["tests/test_oracle_slab_dipoles.py::test_layer_energy_closed_form"]),
     "failed line search not retried with beta = 0": (
         [("if (level == 0) { level = 1; rep->n_restarts++; path |= 2; continue; }", "")],
         [RULES + "test_beta_zero_retry_after_a_failed_line_search"]),
