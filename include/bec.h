@@ -65,15 +65,25 @@ typedef struct {
 } bec_grid;
 
 /* Physical parameters in harmonic-oscillator units (Sec. II).  N_i G_ij and
- * N_i Gdd_ij must be symmetric (the energy form requires it). */
+ * N_i Gdd_ij must be symmetric (the energy form requires it).
+ * Dipolar truncation (dip_cut):
+ *  0  spherical cutoff of radius r_cut, Ud(k) = (3 kz^2/|k|^2 - 1) c(|k| r_cut),
+ *     Ud(0) = 0, for a condensate isolated in all three directions;
+ *  1  slab cut for a condensate periodic in x and y (the setups of Sec. VI.C):
+ *     the interaction kept for |z - z'| < r_cut, not cut in x, y:
+ *     Ud(k) = (3 kz^2/|k|^2 - 1) + 3 exp(-k_rho r_cut)(k_rho^2 cos(kz r_cut)
+ *             - k_rho kz sin(kz r_cut))/|k|^2, Ud(0) = 2, k_rho^2 = kx^2 + ky^2;
+ *     needs 2 r_cut <= hi[2] - lo[2] (BEC_EINVAL otherwise), where it is the
+ *     exact convolution with the cut kernel on the periodic grid. */
 typedef struct {
     double N[2];        /* atom numbers N_i > 0                                */
     double omega[3];    /* trap ratios lambda_d (Eq. (2))                      */
     double G[2][2];     /* contact couplings G_ij                              */
     double Gdd[2][2];   /* dipolar k-space amplitudes                          */
     double c_lhy;       /* multiplier of the LHY term (1 = the paper)          */
-    double r_cut;       /* dipolar cutoff radius, > 0                          */
+    double r_cut;       /* dipolar cutoff: radius (dip_cut 0) or slab half-height (1), > 0 */
     int32_t n_u;        /* Gauss-Legendre nodes for the u integral, 1..64      */
+    int32_t dip_cut;    /* 0 spherical cutoff, 1 slab cut (periodic x, y)      */
 } bec_params;
 
 /* Preconditioners of Sec. IV.B: identity, real-space diagonal P_V, kinetic
@@ -387,6 +397,7 @@ typedef struct {
     int32_t contact_2pi;    /* 0: G_ij = 4 pi a_ij N_j / l, the contact coupling
                                4 pi hbar^2 a / m that the LHY prefactor of Eq. (1)
                                assumes; 1: the prefactor 2 pi as printed in Sec. II       */
+    int32_t dip_cut;        /* copied to bec_params.dip_cut (0 or 1)                      */
 } bec_physical;
 
 /* Convert laboratory units into the oscillator units of Sec. II (host-only:

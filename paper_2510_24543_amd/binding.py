@@ -27,11 +27,12 @@ class Grid(C.Structure):
 class Params(C.Structure):
     _fields_ = [("N", C.c_double * 2), ("omega", C.c_double * 3),
                 ("G", (C.c_double * 2) * 2), ("Gdd", (C.c_double * 2) * 2),
-                ("c_lhy", C.c_double), ("r_cut", C.c_double), ("n_u", C.c_int32)]
+                ("c_lhy", C.c_double), ("r_cut", C.c_double), ("n_u", C.c_int32), ("dip_cut", C.c_int32)]
 
     def to_dict(self) -> dict:
         return {"N": list(self.N), "omega": list(self.omega), "G": [list(r) for r in self.G],
-                "Gdd": [list(r) for r in self.Gdd], "c_lhy": self.c_lhy, "r_cut": self.r_cut, "n_u": self.n_u}
+                "Gdd": [list(r) for r in self.Gdd], "c_lhy": self.c_lhy, "r_cut": self.r_cut, "n_u": self.n_u,
+                "dip_cut": self.dip_cut}
 
 
 class Opts(C.Structure):
@@ -83,7 +84,8 @@ class Tuning(C.Structure):
 class Physical(C.Structure):
     _fields_ = [("mass_amu", C.c_double), ("a_bohr", (C.c_double * 2) * 2), ("mu_bohr", C.c_double * 2),
                 ("N", C.c_double * 2), ("f0_hz", C.c_double), ("trap_hz", C.c_double * 3),
-                ("c_lhy", C.c_double), ("r_cut_um", C.c_double), ("n_u", C.c_int32), ("contact_2pi", C.c_int32)]
+                ("c_lhy", C.c_double), ("r_cut_um", C.c_double), ("n_u", C.c_int32), ("contact_2pi", C.c_int32),
+                ("dip_cut", C.c_int32)]
 
 
 class KernelStat(C.Structure):
@@ -170,6 +172,7 @@ def make_params(p: dict) -> Params:
     for d in range(3):
         P.omega[d] = float(p["omega"][d])
     P.c_lhy = float(p["c_lhy"]); P.r_cut = float(p["r_cut"]); P.n_u = int(p["n_u"])
+    P.dip_cut = int(p.get("dip_cut", 0))
     return P
 
 

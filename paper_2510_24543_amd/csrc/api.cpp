@@ -149,6 +149,26 @@ long double cutoff_factor(long double q)
     return s;
 }
 
+// Unit-amplitude dipolar kernel at wavevector k (dipoles along z), in long
+// double.  dip_cut 0: (3 kz^2/k^2 - 1) c(|k| r_cut), 0 at k = 0 (spherical
+// cutoff).  dip_cut 1, the slab cut of the periodic-xy setups: the interaction is
+// kept for |z - z'| < Z = r_cut and not cut in x, y; inverting the uncut
+// kernel in kz gives 2 delta(u) - (3/2) k_rho exp(-k_rho |u|) at height u, and
+// its transform over |u| < Z is
+//   (3 kz^2/k^2 - 1) + 3 exp(-k_rho Z)(k_rho^2 cos(kz Z) - k_rho kz sin(kz Z))/k^2,
+// 2 at k = 0.  Even in each component, so the octant table serves all k.
+long double dipolar_kernel(long double kx, long double ky, long double kz, const bec_params& p)
+{
+    const long double kr2 = kx * kx + ky * ky, k2 = kr2 + kz * kz;
+    if (p.dip_cut == 1) {
+        if (k2 == 0.0L) return 2.0L;
+        const long double kr = sqrtl(kr2), Z = (long double)p.r_cut;
+        return (3.0L * kz * kz / k2 - 1.0L) + 3.0L * expl(-kr * Z) * (kr2 * cosl(kz * Z) - kr * kz * sinl(kz * Z)) / k2;
+    }
+    if (k2 == 0.0L) return 0.0L;
+    return (3.0L * kz * kz / k2 - 1.0L) * cutoff_factor(sqrtl(k2) * (long double)p.r_cut);
+}
+
 // Optional per-kernel timing: HIP events recorded on the context stream around
 // every launch, resolved when the statistics are read.
 struct Prof {
@@ -363,12 +383,22 @@ bec_status check_grid(const bec_grid* g)
     return BEC_OK;
 }
 
+// The slab cut is exact on the periodic grid only if the cut kernel fits in
+// one period along z: 2 r_cut <= L_z.
+bec_status check_params_grid(const bec_grid* g, const bec_params* p)
+{
+    if (p->dip_cut == 1 && !(2.0 * p->r_cut <= g->hi[2] - g->lo[2]))
+        return fail(BEC_EINVAL, "slab cut (dip_cut 1) needs 2 r_cut <= hi[2] - lo[2]");
+    return BEC_OK;
+}
+
 bec_status check_params(const bec_params* p)
 {
     if (!p) return fail(BEC_EINVAL, "params is null");
     if (!(p->N[0] > 0) || !(p->N[1] > 0)) return fail(BEC_EINVAL, "atom numbers must be positive");
     if (p->n_u < 1 || p->n_u > bec::kMaxNodes) return fail(BEC_EINVAL, "n_u must be in 1..%d", bec::kMaxNodes);
     if (!(p->r_cut > 0)) return fail(BEC_EINVAL, "r_cut must be positive");
+    if (p->dip_cut != 0 && p->dip_cut != 1) return fail(BEC_EINVAL, "dip_cut must be 0 or 1");
     const double* all[] = {p->omega, &p->G[0][0], &p->Gdd[0][0]};
     const int cnt[] = {3, 4, 4};
     for (int a = 0; a < 3; ++a)
@@ -553,11 +583,7 @@ bec_status upload_params(bec_ctx* c, bool dipolar_table)
                 for (int k = 0; k < az; ++k) {
                     const long double kx = 2.0L * kPiL * i / c->L[0], ky = 2.0L * kPiL * j / c->L[1],
                                       kz = 2.0L * kPiL * k / c->L[2];
-                    const long double k2 = kx * kx + ky * ky + kz * kz;
-                    double v = 0.0;
-                    if (k2 > 0.0L)
-                        v = (double)((3.0L * kz * kz / k2 - 1.0L) * cutoff_factor(sqrtl(k2) * (long double)p.r_cut));
-                    ud[((size_t)i * ay + j) * az + k] = v;
+                    ud[((size_t)i * ay + j) * az + k] = (double)dipolar_kernel(kx, ky, kz, p);
                 }
         HIPCHK(hipMemcpyAsync(c->udtab, ud.data(), ud.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
     }
@@ -1206,6 +1232,7 @@ bec_status bec_params_from_physical(const bec_physical* in, bec_params* out, dou
     if (in->a_bohr[0][1] != in->a_bohr[1][0]) return fail(BEC_EINVAL, "a_12 and a_21 must be equal");
     if (!std::isfinite(in->c_lhy)) return fail(BEC_EINVAL, "non-finite c_lhy");
     if (in->contact_2pi != 0 && in->contact_2pi != 1) return fail(BEC_EINVAL, "contact_2pi must be 0 or 1");
+    if (in->dip_cut != 0 && in->dip_cut != 1) return fail(BEC_EINVAL, "dip_cut must be 0 or 1");
 
     const double m = in->mass_amu * kAmu, w0 = 2.0 * kPi * in->f0_hz;
     const double l = std::sqrt(kHbar / (m * w0));
@@ -1222,6 +1249,7 @@ bec_status bec_params_from_physical(const bec_physical* in, bec_params* out, dou
     for (int d = 0; d < 3; ++d) p.omega[d] = in->trap_hz[d] / in->f0_hz;
     p.c_lhy = in->c_lhy;
     p.r_cut = in->r_cut_um * 1e-6 / l;
+    p.dip_cut = in->dip_cut;
     p.n_u = in->n_u;
     STCHK(check_params(&p));
     *out = p;
@@ -1233,6 +1261,7 @@ bec_status bec_workspace_size(const bec_grid* grid, const bec_params* params, si
 {
     STCHK(check_grid(grid));
     if (params) STCHK(check_params(params));
+    if (params) STCHK(check_params_grid(grid, params));
     if (!bytes) return fail(BEC_EINVAL, "bytes is null");
     *bytes = ws_layout(grid->n, nullptr);
     return BEC_OK;
@@ -1244,6 +1273,7 @@ bec_status bec_create(const bec_grid* grid, const bec_params* params, void* hip_
     try {
         STCHK(check_grid(grid));
         STCHK(check_params(params));
+        STCHK(check_params_grid(grid, params));
         if (!out) return fail(BEC_EINVAL, "out is null");
         if (!workspace) return fail(BEC_EINVAL, "workspace is null");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(BEC_EINVAL, "workspace must be 256-byte aligned");
@@ -1394,7 +1424,8 @@ bec_status bec_set_params(bec_ctx* c, const bec_params* params)
 {
     if (!c) return fail(BEC_EINVAL, "ctx is null");
     STCHK(check_params(params));
-    const bool dip = params->r_cut != c->p.r_cut;
+    STCHK(check_params_grid(&c->g, params));
+    const bool dip = params->r_cut != c->p.r_cut || params->dip_cut != c->p.dip_cut;
     c->p = *params;
     return upload_params(c, dip);
 }
@@ -1488,6 +1519,7 @@ bec_status bec_gradient_noalloc(const bec_grid* grid, const bec_params* params, 
     try {
         STCHK(check_grid(grid));
         STCHK(check_params(params));
+        STCHK(check_params_grid(grid, params));
         if (!psi || !grad) return fail(BEC_EINVAL, "null argument");
         size_t off[32];
         const size_t ws = ws_layout(grid->n, off);
@@ -2046,10 +2078,7 @@ void instance_tables(const bec_grid& gr, const bec_params& p, std::vector<double
         for (int j = 0; j < ay; ++j)
             for (int k = 0; k < az; ++k) {
                 const long double kx = 2.0L * kPiL * i / L[0], ky = 2.0L * kPiL * j / L[1], kz = 2.0L * kPiL * k / L[2];
-                const long double k2 = kx * kx + ky * ky + kz * kz;
-                if (k2 > 0.0L)
-                    ud[((size_t)i * ay + j) * az + k] =
-                        (double)((3.0L * kz * kz / k2 - 1.0L) * cutoff_factor(sqrtl(k2) * (long double)p.r_cut));
+                ud[((size_t)i * ay + j) * az + k] = (double)dipolar_kernel(kx, ky, kz, p);
             }
 }
 
@@ -2183,6 +2212,7 @@ bec_status check_batch_args(int32_t n_inst, const bec_grid* grids, const bec_par
     for (int i = 0; i < n_inst; ++i) {
         STCHK(check_grid(&grids[i]));
         STCHK(check_params(&params[i]));
+        STCHK(check_params_grid(&grids[i], &params[i]));
     }
     return BEC_OK;
 }

@@ -19,7 +19,8 @@ from . import binding as B
 
 
 def physical_params(mass_amu: float, a_bohr, mu_bohr, N, f0_hz: float, trap_hz, r_cut_um: float,
-                    c_lhy: float = 1.0, n_u: int = 16, contact_2pi: bool = False) -> tuple[dict, float]:
+                    c_lhy: float = 1.0, n_u: int = 16, contact_2pi: bool = False,
+                    dip_cut: int = 0) -> tuple[dict, float]:
     """Parameters in oscillator units and the length unit l (m).
 
     mass_amu: atomic mass (u); a_bohr: 2x2 scattering lengths (Bohr radii);
@@ -41,6 +42,7 @@ def physical_params(mass_amu: float, a_bohr, mu_bohr, N, f0_hz: float, trap_hz, 
     ph.r_cut_um = float(r_cut_um)
     ph.n_u = int(n_u)
     ph.contact_2pi = 1 if contact_2pi else 0
+    ph.dip_cut = int(dip_cut)
     P = B.Params()
     l = C.c_double(0.0)
     B.check(B.lib().bec_params_from_physical(C.byref(ph), C.byref(P), C.byref(l)), "bec_params_from_physical")

@@ -7,7 +7,10 @@ couplings of 1e3 to 1e5 in oscillator units.  Unstated inputs are read as:
 52Cr scattering lengths 100 a_0 for every pair (Sec. VI.A gives none); the
 162Dy radial trap 2 pi x 50 Hz (Sec. VI.C gives only omega_z); the Dy-Er mixture
 with one atomic mass (164 u), no radial trap (periodic xy), omega_0 = 2 pi x 900 Hz
-and lambda_z = 0.08, in a 40 x 40 periodic xy box (N / (L_x L_y) = 625).  Grids are
+and lambda_z = 0.08, in a 40 x 40 periodic xy box (N / (L_x L_y) = 625), its
+dipolar interaction cut to the slab |z - z'| < L_z / 2 and not cut in x, y
+(bec_params.dip_cut = 1; the spherical cutoff would suppress the in-plane
+interaction between periodic images).  Grids are
 small so that the oracle finishes in seconds.  Bars as in test_gpu_parity:
 energy terms 1e-12 of the energy scale, H psi 1e-11 in max norm, model 1e-10,
 and the first ten iterates of the solve 1e-11 in energy.
@@ -39,6 +42,7 @@ def setup(name):
                          [0.2, 0.2, 1.0])
     P, l = units.physical_params(164.0, [[118.5, 57.65], [57.65, 58.95]], [10.0, 7.07], [1e6, 1e6],
                                  900.0, [0.0, 0.0, 72.0], r_cut_um=8.0 * 0.26, n_u=16)
+    P = dict(P, dip_cut=1, r_cut=16.0)     # Z = L_z / 2 of the box below
     out["DyEr_VI.C"] = ({"n": [32, 32, 32], "lo": [-20.0, -20.0, -16.0], "hi": [20.0, 20.0, 16.0]}, P,
                         [0.01, 0.01, 0.02])
     return out[name]

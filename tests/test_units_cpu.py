@@ -199,3 +199,14 @@ def test_paper_setups_convert():
                                  100.0, [50.0, 50.0, 250.0], r_cut_um=10.0)
     assert P["G"][0][1] / P["G"][0][0] == pytest.approx(3.0, rel=1e-14)
     assert P["Gdd"][0][0] / P["G"][0][0] > 2.5          # strongly dipolar: eps_dd ~ 2.6
+
+
+def test_dip_cut_is_passed_through_and_checked():
+    from paper_2510_24543_amd import binding as B
+    args = (164.0, [[118.5, 57.65], [57.65, 58.95]], [10.0, 7.07], [1e6, 1e6], 900.0, [0.0, 0.0, 72.0])
+    p, _ = units.physical_params(*args, r_cut_um=2.0, dip_cut=1)
+    assert p["dip_cut"] == 1
+    p, _ = units.physical_params(*args, r_cut_um=2.0)
+    assert p["dip_cut"] == 0
+    with pytest.raises(B.BecError, match="EINVAL"):
+        units.physical_params(*args, r_cut_um=2.0, dip_cut=2)
