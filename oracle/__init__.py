@@ -63,7 +63,8 @@ class Opts(C.Structure):
     _fields_ = [("pc", C.c_int32), ("beta", C.c_int32), ("max_iter", C.c_int32),
                 ("restart_period", C.c_int32), ("max_backtrack", C.c_int32), ("stall_window", C.c_int32),
                 ("tol_grad", C.c_double), ("tol_dE", C.c_double), ("sigma", C.c_double),
-                ("armijo_c1", C.c_double), ("theta_max", C.c_double), ("tau_rel", C.c_double)]
+                ("armijo_c1", C.c_double), ("theta_max", C.c_double), ("tau_rel", C.c_double),
+                ("blend", C.c_double)]
 
 
 class Iter(C.Structure):
@@ -100,7 +101,7 @@ def lib():
         L.orc_lhy_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, dp]
         L.orc_lhy_point.restype = None
         L.orc_heval.argtypes = [C.POINTER(Grid), C.POINTER(Params), dp, dp, dp, dp, C.POINTER(Terms)]
-        L.orc_precond.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int32, C.c_double, dp, dp, dp]
+        L.orc_precond.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int32, C.c_double, C.c_double, dp, dp, dp]
         L.orc_model.argtypes = [C.POINTER(Grid), C.POINTER(Params), dp, dp, dp]
         L.orc_geodesic.argtypes = [C.POINTER(Grid), dp, dp, C.c_double, dp]
         L.orc_param_grad.argtypes = [C.POINTER(Grid), C.POINTER(Params), dp, dp]
@@ -195,11 +196,14 @@ def heval(grid: dict, params: dict, psi: np.ndarray):
     return t.to_dict(), h, phi, mul
 
 
-def precond(grid: dict, params: dict, mode: int, sigma: float, psi: np.ndarray, r: np.ndarray):
+def precond(grid: dict, params: dict, mode: int, sigma: float, psi: np.ndarray, r: np.ndarray,
+            blend: float = -1.0):
+    """z = P^-1 r (mode 0 none, 1 P_V, 2 P_Delta, 3 composite, 4 symmetrised,
+    5 blend with weight `blend` of P_V, < 0 adaptive) at the state psi."""
     g = make_grid(grid["n"], grid["lo"], grid["hi"])
     psi = _field(psi, grid["n"]); r = _field(r, grid["n"])
     z = np.zeros_like(psi)
-    _check(lib().orc_precond(C.byref(g), C.byref(make_params(params)), mode, sigma, _dp(psi),
+    _check(lib().orc_precond(C.byref(g), C.byref(make_params(params)), mode, sigma, blend, _dp(psi),
                              _dp(r), _dp(z)), "precond")
     return z
 
@@ -238,7 +242,7 @@ def param_grad(grid: dict, params: dict, psi: np.ndarray) -> dict:
 
 DEFAULT_OPTS = dict(pc=1, beta=0, max_iter=2000, restart_period=50, max_backtrack=30,
                     tol_grad=1e-10, tol_dE=0.0, sigma=1e-6, armijo_c1=1e-4,
-                    theta_max=np.pi / 2, tau_rel=1e-14)
+                    theta_max=np.pi / 2, tau_rel=1e-14, blend=-1.0)
 
 
 def solve(grid: dict, params: dict, psi0: np.ndarray, opts: dict | None = None, log_cap: int = 0):

@@ -92,6 +92,7 @@ typedef struct {
     double armijo_c1;
     double theta_max;
     double tau_rel;         /* accept band tau = tau_rel |E|                   */
+    double blend;           /* mode 5: weight w of P_V in [0, 1]; < 0 adaptive */
 } orc_opts;
 
 typedef struct {
@@ -660,10 +661,41 @@ static void precond_S(const geom *g, const orc_params *P, const hstate *s, doubl
     free(dh);
 }
 
+/* Weight of P_V in the blended preconditioner for component i: `blend` when
+ * it is in [0, 1]; otherwise (blend < 0) the potential share of the shift,
+ * w_i = P / (P + K) with K = <psi_i, T psi_i> / ||psi_i||^2 the kinetic part
+ * and P = [shift_i - K]_+ the rest (trap, contact, LHY), 1/2 if both vanish. */
+static double blend_weight(const orc_params *Pp, const hstate *s, double blend, int i)
+{
+    if (blend >= 0.0) return blend;
+    double K = s->t.E_kin[i] / (Pp->N[i] * s->t.norm2[i]);
+    double Pot = s->t.shift[i] - K;
+    if (Pot < 0.0) Pot = 0.0;
+    return (Pot + K > 0.0) ? Pot / (Pot + K) : 0.5;
+}
+
+/* Blended preconditioner (a weighted combination of the two preconditioners of
+ * Sec. IV.B, which Sec. III allows; not the composite of Eq. (18)):
+ * z_i = w_i P_V,i^-1 r_i + (1 - w_i) P_Delta,i^-1 r_i, symmetric and positive
+ * definite as a convex combination of two such operators. */
+static void precond_B(const geom *g, const orc_params *P, const hstate *s, double sigma, double blend,
+                      const cplx *r, cplx *z)
+{
+    long N = g->N;
+    cplx *zv = (cplx *)malloc(sizeof(cplx) * 2 * (size_t)N);
+    precond_V(g, P, s, sigma, r, zv);
+    precond_K(g, s, sigma, r, z);
+    for (int i = 0; i < 2; ++i) {
+        double w = blend_weight(P, s, blend, i);
+        for (long x = 0; x < N; ++x) z[i * N + x] = w * zv[i * N + x] + (1.0 - w) * z[i * N + x];
+    }
+    free(zv);
+}
+
 /* z = P^-1 r for mode 0 (identity), 1 (P_V), 2 (P_Delta), 3 (P_Delta P_V),
- * 4 (symmetrised composite) */
+ * 4 (symmetrised composite), 5 (blend of P_V and P_Delta, weight `blend`) */
 static void precond_apply(const geom *g, const orc_params *P, const hstate *s, int mode,
-                          double sigma, const cplx *r, cplx *z)
+                          double sigma, double blend, const cplx *r, cplx *z)
 {
     long N = g->N;
     switch (mode) {
@@ -671,11 +703,12 @@ static void precond_apply(const geom *g, const orc_params *P, const hstate *s, i
     case 2: precond_K(g, s, sigma, r, z); break;
     case 3: precond_V(g, P, s, sigma, r, z); precond_K(g, s, sigma, z, z); break;
     case 4: precond_S(g, P, s, sigma, r, z); break;
+    case 5: precond_B(g, P, s, sigma, blend, r, z); break;
     default: memcpy(z, r, sizeof(cplx) * 2 * (size_t)N); break;
     }
 }
 
-int orc_precond(const orc_grid *gr, const orc_params *P, int32_t mode, double sigma,
+int orc_precond(const orc_grid *gr, const orc_params *P, int32_t mode, double sigma, double blend,
                 const double *psi_d, const double *r_d, double *z_d)
 {
     int st = check_inputs(gr, P);
@@ -685,7 +718,7 @@ int orc_precond(const orc_grid *gr, const orc_params *P, int32_t mode, double si
     hstate s;
     if ((st = hstate_alloc(&s, g.N))) { hstate_free(&s); geom_free(&g); return st; }
     heval(&g, P, (const cplx *)psi_d, &s);
-    precond_apply(&g, P, &s, mode, sigma, (const cplx *)r_d, (cplx *)z_d);
+    precond_apply(&g, P, &s, mode, sigma, blend, (const cplx *)r_d, (cplx *)z_d);
     hstate_free(&s);
     geom_free(&g);
     return ORC_OK;
@@ -1013,7 +1046,7 @@ int orc_solve_trace(const orc_grid *gr, const orc_params *P, const orc_opts *o, 
         if (n >= o->max_iter) { status = ORC_ENOTCONV; break; }
 
         /* 2. preconditioned residual z = P^-1 r (Sec. IV.B) */
-        precond_apply(&g, P, &cur, o->pc, o->sigma, r, z);
+        precond_apply(&g, P, &cur, o->pc, o->sigma, o->blend, r, z);
 
         /* 3. conjugacy parameter: HS+ (default) or PR+ (Sec. IV.C) */
         int restart = !have_prev || o->beta == 2 ||
@@ -1051,7 +1084,7 @@ int orc_solve_trace(const orc_grid *gr, const orc_params *P, const orc_opts *o, 
             double rp = 0.0;
             for (;;) {
                 double b = (level == 0) ? beta : 0.0;
-                if (level == 2) precond_apply(&g, P, &cur, 1, o->sigma, r, z);
+                if (level == 2) precond_apply(&g, P, &cur, 1, o->sigma, 0.0, r, z);
                 if (level == 3) memcpy(z, r, vb);
                 rp = 0.0;
                 for (int i = 0; i < 2; ++i) {

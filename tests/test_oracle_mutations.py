@@ -92,6 +92,13 @@ MUTANTS = {
     "slab cut: zero mode 0 instead of 2": (
         [("if (k2 == 0.0) return 2.0;", "if (k2 == 0.0) return 0.0;")],
         ["tests/test_oracle_slab_dipoles.py::test_layer_energy_closed_form"]),
+    "blend: the weight applied to P_Delta": (
+        [("z[i * N + x] = w * zv[i * N + x] + (1.0 - w) * z[i * N + x];",
+          "z[i * N + x] = (1.0 - w) * zv[i * N + x] + w * z[i * N + x];")],
+        [PINS + "test_blended_preconditioner_end_weights_symmetry_positivity"]),
+    "blend: adaptive weight from the kinetic share": (
+        [("return (Pot + K > 0.0) ? Pot / (Pot + K) : 0.5;", "return (Pot + K > 0.0) ? K / (Pot + K) : 0.5;")],
+        [PINS + "test_blended_preconditioner_on_plane_waves"]),
     "failed line search not retried with beta = 0": (
         [("if (level == 0) { level = 1; rep->n_restarts++; path |= 2; continue; }", "")],
         [RULES + "test_beta_zero_retry_after_a_failed_line_search"]),

@@ -505,6 +505,70 @@ def test_symmetrised_composite_with_constant_diagonal_on_plane_waves(orc):
         assert np.max(np.abs(z[i] - r[i] / (a * (a + k2h)))) < 1e-13 / (a * a)
 
 
+def test_blended_preconditioner_end_weights_symmetry_positivity(orc):
+    """Mode 5, z = w P_V^-1 r + (1 - w) P_Delta^-1 r: the end weights give the two
+    preconditioners bit for bit; any weight gives a symmetric, positive operator
+    (a convex combination of two such operators); the adaptive weight lies in
+    [0, 1] and combines the same two outputs."""
+    grid = make_grid((12, 12, 16), (-6, -6, -6), (6, 6, 6))
+    psi = smooth_state(grid, 4)
+    P = params(omega=(1.0, 1.3, 2.0), G=((10.0, 4.0), (4.0, 8.0)), Gdd=((5.0, 2.0), (2.0, 3.0)), c_lhy=3.0)
+    sigma = 1e-6
+    u, v = smooth_direction(grid, 21), smooth_direction(grid, 22)
+    zv, zk = orc.precond(grid, P, 1, sigma, psi, u), orc.precond(grid, P, 2, sigma, psi, u)
+    assert np.array_equal(orc.precond(grid, P, 5, sigma, psi, u, blend=1.0), zv)
+    assert np.array_equal(orc.precond(grid, P, 5, sigma, psi, u, blend=0.0), zk)
+
+    def ip(a, b):
+        return float(np.sum((np.conj(a) * b).real))
+
+    for w in (0.3, -1.0):
+        Bu, Bv = orc.precond(grid, P, 5, sigma, psi, u, blend=w), orc.precond(grid, P, 5, sigma, psi, v, blend=w)
+        assert abs(ip(u, Bv) - ip(Bu, v)) < 1e-13 * abs(ip(u, Bv))
+        assert ip(u, Bu) > 0 and ip(v, Bv) > 0
+    # the adaptive output is w zv + (1 - w) zk per component with one w_i in [0, 1]
+    Ba = orc.precond(grid, P, 5, sigma, psi, u, blend=-1.0)
+    for i in range(2):
+        d = (zv[i] - zk[i]).ravel()
+        w = float(np.real(np.vdot(d, (Ba[i] - zk[i]).ravel())) / np.real(np.vdot(d, d)))
+        assert 0.0 <= w <= 1.0
+        assert np.max(np.abs(Ba[i] - (w * zv[i] + (1 - w) * zk[i]))) < 1e-13 * np.max(np.abs(Ba[i]))
+
+
+def test_blended_preconditioner_on_plane_waves(orc):
+    """psi_i a plane wave of wavevector k0_i and no trap or LHY: n_i = 1/V, the
+    kinetic share of the shift is |k0_i|^2/2 and the rest sum_j G_ij n_j, the
+    P_V diagonal the constant shift_i + sum_j G_ij n_j; a plane-wave residual of
+    wavevector k is scaled by w_i/(D_i + sigma) + (1 - w_i)/(shift_i + sigma + |k|^2/2)
+    with the adaptive w_i = P/(P + K)."""
+    grid = make_grid((8, 12, 16), (-3, -4, -5), (3, 4, 5))
+    X, Y, Z = mesh(grid)
+    L = [6.0, 8.0, 10.0]
+    Vol = L[0] * L[1] * L[2]
+    G = ((3.0, 1.5), (1.0, 2.0))
+    P = params(N=(1.0, 1.5), G=G, Gdd=((2.0, 1.0), (1.0 / 1.5, 1.0)))
+
+    def wave(m):
+        return np.exp(1j * sum(2 * np.pi * m[d] / L[d] * c for d, c in enumerate((X, Y, Z))))
+
+    k0 = [(1, 0, 2), (0, -1, 1)]
+    psi = np.array([wave(m) / np.sqrt(Vol) for m in k0])
+    m = [(1, -2, 3), (0, 4, -1)]
+    r = np.array([wave(mm) for mm in m])
+    sigma = 1e-3
+    t = orc.heval(grid, P, psi)[0]
+    for blend in (0.25, -1.0):
+        z = orc.precond(grid, P, 5, sigma, psi, r, blend=blend)
+        for i in range(2):
+            K = 0.5 * sum((2 * np.pi * k0[i][d] / L[d]) ** 2 for d in range(3))
+            Pot = (G[i][0] + G[i][1]) / Vol
+            assert abs(t["shift"][i] - (K + Pot)) < 1e-13 * (K + Pot)
+            w = blend if blend >= 0 else Pot / (Pot + K)
+            k2h = 0.5 * sum((2 * np.pi * m[i][d] / L[d]) ** 2 for d in range(3))
+            factor = w / (K + 2 * Pot + sigma) + (1 - w) / (K + Pot + sigma + k2h)
+            assert np.max(np.abs(z[i] - factor * r[i])) < 1e-13 * abs(factor)     # FFT round-off
+
+
 # ---------------------------------------------------------------- P10: manifold
 def test_geodesic_stays_on_the_product_of_spheres(orc):
     psi = smooth_state(SMALL, 13)
@@ -546,7 +610,7 @@ def test_solver_restart_period_one_is_steepest_descent(orc):
 
 def test_all_preconditioners_reach_the_same_ground_state(orc):
     Es = []
-    for pc in (0, 1, 2, 3, 4):
+    for pc in (0, 1, 2, 3, 4, 5):
         _, rep, _ = solve_c1(orc, "C1b", pc=pc)
         assert rep["status"] == "OK"
         Es.append(rep["final"]["E"])
