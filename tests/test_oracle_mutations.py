@@ -80,8 +80,8 @@ MUTANTS = {
         [("if (alpha * pmax > o->theta_max) alpha = o->theta_max / pmax;", "")],
         [RULES + "test_model_step_minimises_the_quadratic_model"]),
     "composite fallback to P_Delta instead of P_V": (
-        [("if (level == 2) precond_apply(&g, P, &cur, 1, o->sigma, r, z);",
-          "if (level == 2) precond_apply(&g, P, &cur, 2, o->sigma, r, z);")],
+        [("if (level == 2) precond_apply(&g, P, &cur, 1, o->sigma, 0.0, r, z);",
+          "if (level == 2) precond_apply(&g, P, &cur, 2, o->sigma, 0.0, r, z);")],
         [RULES + "test_composite_fallback_ladder"]),
     "stall reference reset without halving": (
         [("if (res_max < 0.5 * stall_ref) {", "if (res_max < 0.9 * stall_ref) {")],
