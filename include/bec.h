@@ -90,7 +90,16 @@ typedef struct {
  * P_Delta (Fourier diagonal), and the composite P_Delta^-1 P_V^-1 (Eq. (18));
  * and, beyond the paper, the symmetrised composite D^-1/2 P_Delta^-1 D^-1/2
  * with D the P_V diagonal (symmetric and positive definite, unlike Eq. (18)). */
-typedef enum { BEC_PC_NONE = 0, BEC_PC_V = 1, BEC_PC_KIN = 2, BEC_PC_COMPOSITE = 3, BEC_PC_SYMMETRIC = 4 } bec_precond;
+typedef enum { BEC_PC_NONE = 0, BEC_PC_V = 1, BEC_PC_KIN = 2, BEC_PC_COMPOSITE = 3, BEC_PC_SYMMETRIC = 4,
+               BEC_PC_BLEND = 5 } bec_precond;
+
+/* BEC_PC_BLEND: the weighted combination z_i = w_i P_V,i^-1 r_i + (1 - w_i)
+ * P_Delta,i^-1 r_i of the two preconditioners (Sec. III allows weighted
+ * combinations; the conclusion names dynamic weighting as an extension),
+ * symmetric and positive definite.  w_i = bec_opts.blend in [0, 1], or, for a
+ * negative bec_opts.blend, the potential share of the preconditioner shift:
+ * [shift_i - K_i]_+ / ([shift_i - K_i]_+ + K_i), K_i = <psi_i, T psi_i> / ||psi_i||^2,
+ * recomputed at every iterate (1/2 if both parts vanish). */
 
 /* Conjugacy parameter of Sec. IV.C: Hestenes-Stiefel+, Polak-Ribiere+, or 0. */
 typedef enum { BEC_BETA_HS_PLUS = 0, BEC_BETA_PR_PLUS = 1, BEC_BETA_ZERO = 2 } bec_beta;
@@ -123,6 +132,7 @@ typedef struct {
     double armijo_c1;       /* sufficient-decrease constant                    */
     double theta_max;       /* largest geodesic angle per step                 */
     double tau_rel;         /* a step is accepted when E_new <= E + tau_rel|E| */
+    double blend;           /* BEC_PC_BLEND: weight of P_V in [0, 1]; < 0 adaptive */
 } bec_opts;
 
 /* Energy decomposition at one state (Sec. II, Eq. (1); Sec. III, Eq. (7)). */
@@ -225,6 +235,13 @@ bec_status bec_gradient_noalloc(const bec_grid* grid, const bec_params* params, 
  * sigma).  r and z are device fields (may alias).  Synchronises. */
 bec_status bec_precond_apply(bec_ctx* ctx, int32_t pc, double sigma, const double* psi,
                              const double* r, double* z);
+
+/* z = w P_V^-1 r + (1 - w) P_Delta^-1 r (BEC_PC_BLEND) at psi with the weight
+ * blend in [0, 1], or the adaptive weight when blend < 0 (bec_precond_apply with
+ * BEC_PC_BLEND uses the adaptive weight).  Same conventions as
+ * bec_precond_apply; BEC_EINVAL for blend > 1.  Synchronises. */
+bec_status bec_precond_apply_blend(bec_ctx* ctx, double blend, double sigma, const double* psi, const double* r,
+                                   double* z);
 
 /* One manifold line search (Sec. V): projects d onto the tangent space at psi,
  * builds the second-order energy model, proposes alpha = -E1/E2, validates it

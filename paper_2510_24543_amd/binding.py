@@ -39,7 +39,8 @@ class Opts(C.Structure):
     _fields_ = [("pc", C.c_int32), ("beta", C.c_int32), ("max_iter", C.c_int32),
                 ("restart_period", C.c_int32), ("max_backtrack", C.c_int32), ("flags", C.c_int32),
                 ("stall_window", C.c_int32), ("reserved", C.c_int32), ("tol_grad", C.c_double), ("tol_dE", C.c_double), ("sigma", C.c_double),
-                ("armijo_c1", C.c_double), ("theta_max", C.c_double), ("tau_rel", C.c_double)]
+                ("armijo_c1", C.c_double), ("theta_max", C.c_double), ("tau_rel", C.c_double),
+                ("blend", C.c_double)]
 
 
 class Terms(C.Structure):
@@ -109,6 +110,7 @@ SIGNATURES = [
     ("bec_gradient_noalloc", C.c_int, [C.POINTER(Grid), C.POINTER(Params), _VP, _VP, _VP, _I32,
                                        C.POINTER(Terms)]),
     ("bec_precond_apply", C.c_int, [_VP, _I32, _DBL, _VP, _VP, _VP]),
+    ("bec_precond_apply_blend", C.c_int, [_VP, _DBL, _DBL, _VP, _VP, _VP]),
     ("bec_linesearch", C.c_int, [_VP, _VP, _VP, _VP, C.POINTER(Opts), C.POINTER(LsReport)]),
     ("bec_solve", C.c_int, [_VP, _VP, C.POINTER(Opts), C.POINTER(Report), C.POINTER(Iter), _I32]),
     ("bec_param_grad", C.c_int, [_VP, _VP, C.POINTER(_D22), C.POINTER(_D22), _DP]),
@@ -178,7 +180,7 @@ def make_params(p: dict) -> Params:
 
 DEFAULT_OPTS = dict(pc=1, beta=0, max_iter=2000, restart_period=50, max_backtrack=30, flags=0,
                     tol_grad=1e-10, tol_dE=0.0, sigma=1e-6, armijo_c1=1e-4,
-                    theta_max=1.5707963267948966, tau_rel=1e-14)
+                    theta_max=1.5707963267948966, tau_rel=1e-14, blend=-1.0)
 
 
 def make_opts(o: dict | None) -> Opts:

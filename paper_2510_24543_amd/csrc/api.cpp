@@ -930,7 +930,8 @@ bec::DirArgs dir_args(bec_ctx* c, int set, const Eval& ev, int zmode, double sig
 // Direction reduce pass into the scalar range kScalDir (host and device copy).
 bec_status dir_reduce_launch(bec_ctx* c, const bec::DirArgs& A)
 {
-    const double rb = 64.0 + (A.zmode == 1 ? 16.0 : 0.0) + (A.zmode == 2 ? 32.0 : 0.0) + (A.have_prev ? 64.0 : 0.0);
+    const double rb = 64.0 + (A.zmode == 1 ? 16.0 : 0.0) + (A.zmode == 2 ? 32.0 : 0.0) + (A.zmode >= 3 ? 48.0 : 0.0) +
+                      (A.have_prev ? 64.0 : 0.0);
     LAUNCH(c, "dir_reduce", (double)c->N * rb, bec::launch_dir_reduce(c->P, A, c->nblk_pw, c->st));
     return reduce_pw_copy(c, bec::kDirReduceSums, kScalDir);
 }
@@ -989,7 +990,7 @@ static_assert(kParsevalOut + 2 <= kScalHeval, "Parseval slots overlap the energy
 // Direction write pass (p, r, rho).
 bec_status dir_write_launch(bec_ctx* c, const bec::DirArgs& A)
 {
-    const double wb = 96.0 + (A.beta != 0.0 || A.dev_dir ? 32.0 : 0.0) + (A.zmode == 2 ? 32.0 : 0.0) + 80.0;
+    const double wb = 96.0 + (A.beta != 0.0 || A.dev_dir ? 32.0 : 0.0) + (A.zmode >= 2 ? 32.0 : 0.0) + 80.0;
     LAUNCH(c, "dir_write", (double)c->N * wb, bec::launch_dir_write(c->P, A, c->nblk_pw, c->st));
     return BEC_OK;
 }
@@ -1560,11 +1561,36 @@ bec_status bec_gradient_noalloc(const bec_grid* grid, const bec_params* params, 
     }
 }
 
+bec_status bec_precond_apply_blend(bec_ctx* c, double blend, double sigma, const double* psi, const double* r,
+                                   double* z)
+{
+    if (!c || !psi || !r || !z) return fail(BEC_EINVAL, "null argument");
+    if (!(sigma >= 0)) return fail(BEC_EINVAL, "sigma must be >= 0");
+    if (!(blend <= 1.0)) return fail(BEC_EINVAL, "blend must be <= 1 (negative: adaptive)");
+    Eval ev;
+    STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
+    STCHK(compute_z(c, 0, ev, reinterpret_cast<const double2*>(r), 0, sigma));    // P_Delta^-1 r into c->z
+    bec::MakeRArgs m{};
+    m.psi = c->psi[0];
+    m.aux = c->aux[0];
+    m.rin = reinterpret_cast<const double2*>(r);
+    for (int i = 0; i < 2; ++i) m.diag_shift[i] = ev.t.shift[i];
+    m.sigma = sigma;
+    m.apply_pv = 3;
+    m.zk = c->z;
+    bec::rule_blend(ev.sums, ev.t.shift, blend, m.blend_w);
+    m.out = reinterpret_cast<double2*>(z);
+    HIPCHK(bec::launch_make_r(c->P, m, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return BEC_OK;
+}
+
 bec_status bec_precond_apply(bec_ctx* c, int32_t pc, double sigma, const double* psi, const double* r, double* z)
 {
     if (!c || !psi || !r || !z) return fail(BEC_EINVAL, "null argument");
-    if (pc < 0 || pc > 4) return fail(BEC_EINVAL, "unknown preconditioner %d", pc);
+    if (pc < 0 || pc > 5) return fail(BEC_EINVAL, "unknown preconditioner %d", pc);
     if (!(sigma >= 0)) return fail(BEC_EINVAL, "sigma must be >= 0");
+    if (pc == BEC_PC_BLEND) return bec_precond_apply_blend(c, -1.0, sigma, psi, r, z);
     Eval ev;
     STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
     const double2* rin = reinterpret_cast<const double2*>(r);
@@ -1660,7 +1686,8 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
                      int32_t log_cap)
 {
     if (!c || !psi_inout || !o) return fail(BEC_EINVAL, "null argument");
-    if (o->pc < 0 || o->pc > 4 || o->beta < 0 || o->beta > 2) return fail(BEC_EINVAL, "bad options");
+    if (o->pc < 0 || o->pc > 5 || o->beta < 0 || o->beta > 2) return fail(BEC_EINVAL, "bad options");
+    if (!(o->blend <= 1.0)) return fail(BEC_EINVAL, "blend must be <= 1 (negative: adaptive)");
     if (o->flags & ~BEC_SOLVE_SYNCHRONOUS) return fail(BEC_EINVAL, "unknown bits in opts.flags: 0x%x", o->flags);
     if (o->stall_window < 0) return fail(BEC_EINVAL, "stall_window must be >= 0");
     const auto t0 = std::chrono::steady_clock::now();
@@ -1678,7 +1705,10 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
     int n = 0, stall_it = 0;
     bec_status status = BEC_ENOTCONV;
     double E_prev = NAN, alpha_prev = 0.0, rz_old = 0.0, stall_ref = INFINITY;
-    const int zmode_pc = (o->pc == BEC_PC_V) ? 1 : (o->pc == BEC_PC_NONE ? 0 : (o->pc == BEC_PC_SYMMETRIC ? 3 : 2));
+    const int zmode_pc = o->pc == BEC_PC_V ? 1
+                         : o->pc == BEC_PC_NONE ? 0
+                         : o->pc == BEC_PC_SYMMETRIC ? 3
+                         : o->pc == BEC_PC_BLEND ? 4 : 2;
     // Pipelined iterations: the first trial of a step is enqueued at the step
     // the device decides from the model sums, followed by the preconditioned
     // residual (Fourier / composite preconditioners, into z_next) and the
@@ -1707,6 +1737,8 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
         // 1. residual, preconditioned residual and the conjugacy sums
         if (zmode_pc >= 2 && !R_ready) STCHK(compute_z(c, cur, ev, nullptr, pv_mode, o->sigma));
         bec::DirArgs A = dir_args(c, cur, ev, zmode_pc, o->sigma);
+        A.blend = o->blend;
+        bec::rule_blend(ev.sums, ev.t.shift, o->blend, A.blend_w);
         A.have_prev = have_prev;
         if (!R_ready) STCHK(dir_reduce(c, A, R));
         R_ready = false;
@@ -1763,6 +1795,7 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
                     const int nxt = 1 - cur;
                     STCHK(heval_launch(c, c->psi[cur], c->pdir, nullptr, nullptr, c->dscal + kScalStep, nxt));
                     bec::DirArgs An = dir_args(c, nxt, ev, zmode_pc, o->sigma);
+                    An.blend = o->blend;            // weights from the device sums (dev_state)
                     An.dev_state = c->dscal + kScalHeval;
                     An.have_prev = 1;
                     An.r_old = c->r_new;      // r and p of this step: the pair after the swap

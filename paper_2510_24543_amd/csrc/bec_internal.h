@@ -213,7 +213,10 @@ struct DirArgs {
     double mu[2];
     double diag_shift[2];         // shift_i for P_V
     double sigma;
-    int zmode;                    // 0 identity, 1 P_V, 2 from zbuf, 3 D^-1/2 zbuf (symmetrised composite)
+    int zmode;                    // 0 identity, 1 P_V, 2 from zbuf, 3 D^-1/2 zbuf (symmetrised composite),
+                                  // 4 w P_V^-1 r + (1 - w) zbuf (blend; zbuf = P_Delta^-1 r)
+    double blend;                 // zmode 4: bec_opts.blend (the weights from it when dev_state is set)
+    double blend_w[2];            // zmode 4: weight of P_V per component
     double zsign;                 // d = zsign z + beta p_old
     double beta;
     double c[2];                  // projection coefficients Re<d_i,psi_i>
@@ -239,7 +242,8 @@ constexpr int kDirWriteSums = 18;
 constexpr int kLsEpiSums = 7;    // line-search model epilogue (rho_1 + i rho_2 against K*rho)
 // sums: 0 rho1 rho1; 1 rho1 rho2; 2 rho2 rho2; 3..6 rho_i Phi[rho_j] (11, 12, 21, 22)
 
-struct MakeRArgs {                // out = r, P_V^-1 r (apply_pv 1) or D^-1/2 r (apply_pv 2; D the P_V diagonal)
+struct MakeRArgs {                // out = r, P_V^-1 r (apply_pv 1), D^-1/2 r (apply_pv 2; D the P_V diagonal)
+                                  // or w P_V^-1 r + (1 - w) zk (apply_pv 3, the blend)
     const double2* psi;
     const double2* hpsi;
     const double2* aux;
@@ -248,6 +252,8 @@ struct MakeRArgs {                // out = r, P_V^-1 r (apply_pv 1) or D^-1/2 r 
     double diag_shift[2];
     double sigma;
     int apply_pv;
+    const double2* zk;            // apply_pv 3: P_Delta^-1 r, 2N
+    double blend_w[2];            // apply_pv 3: weight of P_V per component
     double2* out;                 // 2N
     const double* dev_state;      // non-null: mu and diag_shift from these energy sums (rule_mu_shift)
 };

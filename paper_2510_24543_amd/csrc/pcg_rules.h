@@ -26,6 +26,25 @@ __host__ __device__ inline void rule_mu_shift(const double* S, const double Gdd[
     }
 }
 
+// Weight of P_V in the blended preconditioner z = w P_V^-1 r + (1 - w) P_Delta^-1 r
+// for both components: `blend` when it is >= 0, else the potential share of the
+// shift, [shift_i - K_i]_+ / ([shift_i - K_i]_+ + K_i) with the kinetic part
+// K_i = <psi_i, T psi_i> / |psi_i|^2 from the energy sums S (1/2 if both vanish).
+__host__ __device__ inline void rule_blend(const double* S, const double shift[2], double blend, double w[2])
+{
+#pragma clang fp contract(off)
+    for (int i = 0; i < 2; ++i) {
+        if (blend >= 0.0) {
+            w[i] = blend;
+            continue;
+        }
+        const double K = S[i] / S[14 + i];
+        double pot = shift[i] - K;
+        if (pot < 0.0) pot = 0.0;
+        w[i] = (pot + K > 0.0) ? pot / (pot + K) : 0.5;
+    }
+}
+
 // Inputs of the conjugacy rule that the host knows before the reduce sums.
 struct BetaRule {
     int restart;       // beta = 0 (first step, beta rule 0, or the restart period)

@@ -208,6 +208,18 @@ __device__ __forceinline__ RZ resid_precond(const PwParams& P, const DirArgs& A,
         const double2 w1 = A.zbuf[i], w2 = A.zbuf[N + i];
         o.z[0] = make_double2(q1 * w1.x, q1 * w1.y);
         o.z[1] = make_double2(q2 * w2.x, q2 * w2.y);
+    } else if (A.zmode == 4) {
+        const double n1 = sq2(s1), n2 = sq2(s2);
+        const double V = trap_at(P, i);
+        const double2 ml = A.aux[N + i];
+        const double g[2] = {pv_inv(P, 0, A.diag_shift[0], A.sigma, V, n1, n2, ml.x),
+                             pv_inv(P, 1, A.diag_shift[1], A.sigma, V, n1, n2, ml.y)};
+        const double2 zk[2] = {A.zbuf[i], A.zbuf[N + i]};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const double a = A.blend_w[c] * g[c], b = 1.0 - A.blend_w[c];
+            o.z[c] = make_double2(a * o.r[c].x + b * zk[c].x, a * o.r[c].y + b * zk[c].y);
+        }
     } else {
         o.z[0] = o.r[0];
         o.z[1] = o.r[1];
@@ -217,7 +229,10 @@ __device__ __forceinline__ RZ resid_precond(const PwParams& P, const DirArgs& A,
 
 __global__ __launch_bounds__(kPwThreads) void dir_reduce_kernel(PwParams P, DirArgs A)
 {
-    if (A.dev_state) rule_mu_shift(A.dev_state, P.Gdd, A.mu, A.diag_shift);
+    if (A.dev_state) {
+        rule_mu_shift(A.dev_state, P.Gdd, A.mu, A.diag_shift);
+        if (A.zmode == 4) rule_blend(A.dev_state, A.diag_shift, A.blend, A.blend_w);
+    }
     const long long N = P.N;
     double acc[kDirReduceSums];
 #pragma unroll
@@ -274,7 +289,10 @@ __device__ __forceinline__ DirIn dir_load(const DirArgs& A, long long N, long lo
 // Direction write pass with the LHY part of the line-search model.
 __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirArgs A)
 {
-    if (A.dev_state) rule_mu_shift(A.dev_state, P.Gdd, A.mu, A.diag_shift);
+    if (A.dev_state) {
+        rule_mu_shift(A.dev_state, P.Gdd, A.mu, A.diag_shift);
+        if (A.zmode == 4) rule_blend(A.dev_state, A.diag_shift, A.blend, A.blend_w);
+    }
     if (A.dev_dir) {
         A.beta = rule_beta(A.dev_dir, A.rule);
         rule_proj(A.dev_dir, A.beta, A.rule.dV, A.c);
@@ -306,6 +324,12 @@ __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirAr
             for (int c = 0; c < 2; ++c) {
                 const double q = sqrt(pv_inv(P, c, A.diag_shift[c], A.sigma, V, n[0], n[1], mlc[c]));
                 z[c] = make_double2(q * cur.zb[c].x, q * cur.zb[c].y);
+            }
+        } else if (A.zmode == 4) {
+            for (int c = 0; c < 2; ++c) {
+                const double a = A.blend_w[c] * pv_inv(P, c, A.diag_shift[c], A.sigma, V, n[0], n[1], mlc[c]);
+                const double b = 1.0 - A.blend_w[c];
+                z[c] = make_double2(a * r[c].x + b * cur.zb[c].x, a * r[c].y + b * cur.zb[c].y);
             }
         } else {
             z[0] = r[0];
@@ -374,8 +398,16 @@ __global__ __launch_bounds__(kPwThreads) void make_r_kernel(PwParams P, MakeRArg
                 g1 = sqrt(g1);
                 g2 = sqrt(g2);
             }
-            r1 = make_double2(g1 * r1.x, g1 * r1.y);
-            r2 = make_double2(g2 * r2.x, g2 * r2.y);
+            if (A.apply_pv == 3) {   // blend with the kinetic preconditioner's output zk
+                const double a1 = A.blend_w[0] * g1, b1 = 1.0 - A.blend_w[0];
+                const double a2 = A.blend_w[1] * g2, b2 = 1.0 - A.blend_w[1];
+                const double2 k1 = A.zk[i], k2 = A.zk[N + i];
+                r1 = make_double2(a1 * r1.x + b1 * k1.x, a1 * r1.y + b1 * k1.y);
+                r2 = make_double2(a2 * r2.x + b2 * k2.x, a2 * r2.y + b2 * k2.y);
+            } else {
+                r1 = make_double2(g1 * r1.x, g1 * r1.y);
+                r2 = make_double2(g2 * r2.x, g2 * r2.y);
+            }
         }
         A.out[i] = r1;
         A.out[N + i] = r2;

@@ -16,7 +16,7 @@ import torch
 
 from . import binding as B
 
-PC = {"none": 0, "V": 1, "kin": 2, "composite": 3, "symmetric": 4}
+PC = {"none": 0, "V": 1, "kin": 2, "composite": 3, "symmetric": 4, "blend": 5}
 BETA = {"HS+": 0, "PR+": 1, "zero": 2}
 
 
@@ -141,6 +141,15 @@ class Context:
             for t in (psi, g, E):      # in use on the context stream after this returns
                 t.record_stream(self.stream)
         return E, g
+
+    def precond_blend(self, psi, r, blend: float = -1.0, sigma: float = 1e-6) -> torch.Tensor:
+        """z = w P_V^-1 r + (1 - w) P_Delta^-1 r at psi (bec_precond_apply_blend;
+        blend < 0: the adaptive weight)."""
+        psi, r = self.field(psi), self.field(r, "r")
+        z = self.empty()
+        B.check(B.lib().bec_precond_apply_blend(self._ctx, float(blend), float(sigma), _ptr(psi), _ptr(r), _ptr(z)),
+                "bec_precond_apply_blend")
+        return z
 
     def precond(self, pc, psi, r, sigma: float = 1e-6) -> torch.Tensor:
         pc = PC[pc] if isinstance(pc, str) else int(pc)

@@ -266,7 +266,7 @@ def test_lhy_table_matches_node_loop(solver, case):
 
 
 # ---------------------------------------------------------------- preconditioners
-@pytest.mark.parametrize("pc", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("pc", [0, 1, 2, 3, 4, 5])
 def test_preconditioners(solver, orc, pc):
     grid, params = CASES["C1b"]
     psi = _state(grid, params, 14, True)
@@ -274,6 +274,19 @@ def test_preconditioners(solver, orc, pc):
     ctx = solver.Context(grid, params)
     z = ctx.precond(pc, torch.from_numpy(psi), torch.from_numpy(r), sigma=1e-6).cpu().numpy()
     zo = orc.precond(grid, params, pc, 1e-6, psi, r)
+    assert rel(z, zo) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["C1b", "mixedN", "C2"])
+@pytest.mark.parametrize("blend", [0.0, 0.3, 1.0, -1.0])
+def test_blended_preconditioner(solver, orc, case, blend):
+    """z = w P_V^-1 r + (1 - w) P_Delta^-1 r with a fixed weight and the adaptive one."""
+    grid, params = CASES[case]
+    psi = _state(grid, params, 16, True)
+    r = inputs.random_field(grid, 17)
+    ctx = solver.Context(grid, params)
+    z = ctx.precond_blend(torch.from_numpy(psi), torch.from_numpy(r), blend=blend, sigma=1e-6).cpu().numpy()
+    zo = orc.precond(grid, params, 5, 1e-6, psi, r, blend=blend)
     assert rel(z, zo) < 1e-12
 
 
@@ -370,7 +383,7 @@ def test_param_grad(solver, orc, case):
 
 
 # ---------------------------------------------------------------- full solves
-SOLVE_CASES = [("C1a", 1), ("C1b", 1), ("C1b", 0), ("C1b", 2), ("C1b", 3), ("C1b", 4)]
+SOLVE_CASES = [("C1a", 1), ("C1b", 1), ("C1b", 0), ("C1b", 2), ("C1b", 3), ("C1b", 4), ("C1b", 5)]
 
 
 @pytest.mark.parametrize("name,pc", SOLVE_CASES, ids=[f"{n}-pc{p}" for n, p in SOLVE_CASES])
@@ -442,6 +455,8 @@ PIPE_CASES = [
     ("C1b", {"pc": 4, "beta": 0}),
     ("C2", {"pc": 3, "beta": 0, "max_iter": 80}),
     ("C1b", {"pc": 3, "tau_rel": -2e-6, "max_backtrack": 2}),
+    ("C1b", {"pc": 5, "beta": 0}),
+    ("mixedN", {"pc": 5, "beta": 1, "blend": 0.3}),
 ]
 
 
