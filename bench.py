@@ -293,9 +293,10 @@ def ite_workload(name: str, dt: float):
 
 
 def precond_study(name: str, tol: float = 1e-8, max_iter: int = 20000):
-    """The paper's first comparison (Sec. VI.B): the four preconditioners with
-    both conjugacy rules, each from the same seeded start to max_i ||r_i|| < tol;
-    HIP-event times."""
+    """The paper's first comparison (Sec. VI.B): the four preconditioners, the
+    symmetrised composite and the blend of P_V and P_Delta (adaptive and
+    w = 0.5) with both conjugacy rules, each from the same seeded start to
+    max_i ||r_i|| < tol; HIP-event times."""
     import torch
     from paper_2510_24543_amd import inputs, solver, autotune
     cfg = inputs.CONFIGS[name]
@@ -306,9 +307,11 @@ def precond_study(name: str, tol: float = 1e-8, max_iter: int = 20000):
     psi0 = torch.from_numpy(inputs.config_state(name)).cuda()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     rows = []
-    for pc, pname in ((0, "none"), (1, "P_V"), (2, "P_Delta"), (3, "P_Delta P_V"), (4, "symmetrised")):
+    for pc, pname, blend in ((0, "none", -1.0), (1, "P_V", -1.0), (2, "P_Delta", -1.0), (3, "P_Delta P_V", -1.0),
+                             (4, "symmetrised", -1.0), (5, "blend (adaptive)", -1.0), (5, "blend 0.5", 0.5)):
         for beta, bname in ((0, "HS+"), (1, "PR+")):
-            opts = {"pc": pc, "beta": beta, "restart_period": 50, "sigma": 1e-6, "tol_grad": tol, "max_iter": max_iter}
+            opts = {"pc": pc, "beta": beta, "restart_period": 50, "sigma": 1e-6, "tol_grad": tol, "max_iter": max_iter,
+                    "blend": blend}
             torch.cuda.synchronize()
             ev0.record(ctx.stream)
             _, rep, _ = ctx.solve(psi0, opts)
