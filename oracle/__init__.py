@@ -41,7 +41,8 @@ class Grid(C.Structure):
 class Params(C.Structure):
     _fields_ = [("N", C.c_double * 2), ("omega", C.c_double * 3),
                 ("G", (C.c_double * 2) * 2), ("Gdd", (C.c_double * 2) * 2),
-                ("c_lhy", C.c_double), ("r_cut", C.c_double), ("n_u", C.c_int32), ("dip_cut", C.c_int32)]
+                ("c_lhy", C.c_double), ("r_cut", C.c_double), ("n_u", C.c_int32), ("dip_cut", C.c_int32),
+                ("lhy_quad", C.c_int32)]
 
 
 class Terms(C.Structure):
@@ -100,6 +101,7 @@ def lib():
         L.orc_gauss_legendre.argtypes = [C.c_int32, dp, dp]
         L.orc_lhy_point.argtypes = [C.POINTER(Params), C.c_double, C.c_double, dp]
         L.orc_lhy_point.restype = None
+        L.orc_lhy_nodes.argtypes = [C.POINTER(Params), dp, dp, C.c_int32]
         L.orc_heval.argtypes = [C.POINTER(Grid), C.POINTER(Params), dp, dp, dp, dp, C.POINTER(Terms)]
         L.orc_precond.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int32, C.c_double, C.c_double, dp, dp, dp]
         L.orc_model.argtypes = [C.POINTER(Grid), C.POINTER(Params), dp, dp, dp]
@@ -142,6 +144,7 @@ def make_params(p: dict) -> Params:
         P.omega[d] = float(p["omega"][d])
     P.c_lhy = float(p["c_lhy"]); P.r_cut = float(p["r_cut"]); P.n_u = int(p["n_u"])
     P.dip_cut = int(p.get("dip_cut", 0))
+    P.lhy_quad = int(p.get("lhy_quad", 0))
     return P
 
 
@@ -174,6 +177,15 @@ def gauss_legendre(n: int):
     u = np.zeros(n); w = np.zeros(n)
     _check(lib().orc_gauss_legendre(n, _dp(u), _dp(w)), "gauss_legendre")
     return u, w
+
+
+def lhy_nodes(params: dict):
+    """(u, w): the oracle's rule for the u integral of the LHY term."""
+    u = np.zeros(512); w = np.zeros(512)
+    n = lib().orc_lhy_nodes(C.byref(make_params(params)), _dp(u), _dp(w), 512)
+    if n < 0:
+        raise RuntimeError("oracle lhy_nodes: more than 512 nodes")
+    return u[:n], w[:n]
 
 
 def lhy_point(params: dict, n1: float, n2: float):

@@ -65,6 +65,9 @@ typedef struct {
     int32_t dip_cut;    /* 0: spherical cutoff of radius r_cut; 1: slab cut,
                            the interaction kept for |z - z'| < r_cut and
                            unbounded in the periodic x, y directions          */
+    int32_t lhy_quad;   /* u rule: 0 Gauss-Legendre with n_u nodes on [0,1];
+                           1 root-split, n_u nodes on each piece of [0,1]
+                           between the zeros of the branch potentials        */
 } orc_params;
 
 typedef struct {
@@ -359,6 +362,8 @@ static double kvec(int j, int n, double L)
     return 2.0 * M_PI * (double)jj / L;
 }
 
+static int lhy_nodes(const orc_params *P, double **u_out, double **w_out);
+
 static int geom_init(geom *g, const orc_grid *gr, const orc_params *P)
 {
     memset(g, 0, sizeof(*g));
@@ -393,10 +398,7 @@ static int geom_init(geom *g, const orc_grid *gr, const orc_params *P)
             }
         }
     }
-    g->nu = P->n_u;
-    g->uq = (double *)malloc(sizeof(double) * (size_t)P->n_u);
-    g->wq = (double *)malloc(sizeof(double) * (size_t)P->n_u);
-    orc_gauss_legendre(P->n_u, g->uq, g->wq);
+    g->nu = lhy_nodes(P, &g->uq, &g->wq);
     return ORC_OK;
 }
 
@@ -438,12 +440,96 @@ static void lhy_point(const orc_params *P, int nu, const double *uq, const doubl
     out[2] = P->c_lhy / (3.0 * sqrt(2.0) * M_PI * M_PI) * d2;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Root-split rule for the u integral of Eq. (3) (lhy_quad 1).                */
+/* With a = 3u^2 - 1, V_+ V_- = 4 n1 n2 det(a), det = eta_11 eta_22 - eta_12 eta_21 */
+/* quadratic in a, and V_+ + V_- = 2 (eta_11 n1 + eta_22 n2).  Since            */
+/* N_i eta_ij is symmetric, eta_12 eta_21 >= 0 and s >= |delta|, so for n1 n2 > 0 */
+/* a branch changes sign only where det(a) = 0; for n1 n2 = 0 only where        */
+/* eta_11(a) = 0 or eta_22(a) = 0.  None of these depends on the densities.    */
+/* Between two such points every [V]_+^(k/2) is smooth except at the ends,     */
+/* where it behaves as (u - u_b)^(k/2); the map u = p + (q - p)(1 - cos(pi t))/2 */
+/* makes those ends smooth (u - p ~ t^2, du ~ t dt), and n Gauss-Legendre nodes */
+/* in t then converge exponentially.                                           */
+/* ------------------------------------------------------------------------- */
+static int add_root(double a, double *roots, int n)
+{
+    if (isfinite(a) && a > -1.0 && a < 2.0) roots[n++] = sqrt((a + 1.0) / 3.0);
+    return n;
+}
+
+/* u nodes and weights on [0,1] for P (allocated here; returns the count) */
+static int lhy_nodes(const orc_params *P, double **u_out, double **w_out)
+{
+    int n = P->n_u;
+    double br[8];
+    int nb = 0;
+    if (P->lhy_quad == 1) {
+        const double (*G)[2] = P->G, (*D)[2] = P->Gdd;
+        double A = D[0][0] * D[1][1] - D[0][1] * D[1][0];
+        double B = G[0][0] * D[1][1] + D[0][0] * G[1][1] - G[0][1] * D[1][0] - D[0][1] * G[1][0];
+        double C = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+        if (A != 0.0) {
+            double disc = B * B - 4.0 * A * C;
+            if (disc >= 0.0) {
+                double q = -0.5 * (B + copysign(sqrt(disc), B));   /* the stable pair of roots */
+                if (q != 0.0) { nb = add_root(q / A, br, nb); nb = add_root(C / q, br, nb); }
+                else nb = add_root(0.0, br, nb);
+            }
+        } else if (B != 0.0) {
+            nb = add_root(-C / B, br, nb);
+        }
+        for (int i = 0; i < 2; ++i)
+            if (D[i][i] != 0.0) nb = add_root(-G[i][i] / D[i][i], br, nb);
+        /* sort, drop duplicates */
+        for (int i = 1; i < nb; ++i)
+            for (int j = i; j > 0 && br[j] < br[j - 1]; --j) { double t = br[j]; br[j] = br[j - 1]; br[j - 1] = t; }
+        int m = 0;
+        for (int i = 0; i < nb; ++i)
+            if (m == 0 || br[i] > br[m - 1] + 1e-15) br[m++] = br[i];
+        nb = m;
+    }
+    int pieces = nb + 1;
+    int total = (P->lhy_quad == 1) ? n * pieces : n;
+    double *u = (double *)malloc(sizeof(double) * (size_t)total);
+    double *w = (double *)malloc(sizeof(double) * (size_t)total);
+    double *t = (double *)malloc(sizeof(double) * (size_t)n);
+    double *tw = (double *)malloc(sizeof(double) * (size_t)n);
+    orc_gauss_legendre(n, t, tw);
+    if (P->lhy_quad != 1) {
+        memcpy(u, t, sizeof(double) * (size_t)n);
+        memcpy(w, tw, sizeof(double) * (size_t)n);
+    } else {
+        for (int k = 0; k < pieces; ++k) {
+            double p = (k == 0) ? 0.0 : br[k - 1], q = (k == nb) ? 1.0 : br[k];
+            for (int j = 0; j < n; ++j) {
+                u[k * n + j] = p + (q - p) * 0.5 * (1.0 - cos(M_PI * t[j]));
+                w[k * n + j] = tw[j] * (q - p) * 0.5 * M_PI * sin(M_PI * t[j]);
+            }
+        }
+    }
+    free(t); free(tw);
+    *u_out = u; *w_out = w;
+    return total;
+}
+
+/* the u rule of P into u, w (host arrays of cap entries); returns the node count or -1 */
+int orc_lhy_nodes(const orc_params *P, double *u, double *w, int32_t cap)
+{
+    double *uu, *ww;
+    int n = lhy_nodes(P, &uu, &ww);
+    if (n > cap) { free(uu); free(ww); return -1; }
+    memcpy(u, uu, sizeof(double) * (size_t)n);
+    memcpy(w, ww, sizeof(double) * (size_t)n);
+    free(uu); free(ww);
+    return n;
+}
+
 void orc_lhy_point(const orc_params *P, double n1, double n2, double out[3])
 {
-    double *u = (double *)malloc(sizeof(double) * (size_t)P->n_u);
-    double *w = (double *)malloc(sizeof(double) * (size_t)P->n_u);
-    orc_gauss_legendre(P->n_u, u, w);
-    lhy_point(P, P->n_u, u, w, n1, n2, out);
+    double *u, *w;
+    int nu = lhy_nodes(P, &u, &w);
+    lhy_point(P, nu, u, w, n1, n2, out);
     free(u); free(w);
 }
 
@@ -580,6 +666,7 @@ static int check_inputs(const orc_grid *gr, const orc_params *P)
     }
     if (P->n_u < 1 || P->N[0] <= 0 || P->N[1] <= 0) return ORC_EINVAL;
     if (P->dip_cut != 0 && P->dip_cut != 1) return ORC_EINVAL;
+    if (P->lhy_quad != 0 && P->lhy_quad != 1) return ORC_EINVAL;
     /* the slab cut is exact on the periodic grid when the cut kernel fits in one period */
     if (P->dip_cut == 1 && !(P->r_cut > 0.0 && 2.0 * P->r_cut <= gr->hi[2] - gr->lo[2])) return ORC_EINVAL;
     return ORC_OK;

@@ -99,6 +99,10 @@ MUTANTS = {
     "blend: adaptive weight from the kinetic share": (
         [("return (Pot + K > 0.0) ? Pot / (Pot + K) : 0.5;", "return (Pot + K > 0.0) ? K / (Pot + K) : 0.5;")],
         [PINS + "test_blended_preconditioner_on_plane_waves"]),
+    "root-split rule: map without the sine factor in the weights": (
+        [("w[k * n + j] = tw[j] * (q - p) * 0.5 * M_PI * sin(M_PI * t[j]);",
+          "w[k * n + j] = tw[j] * (q - p);")],
+        ["tests/test_oracle_lhy_rule.py::test_single_component_matches_closed_form"]),
     "failed line search not retried with beta = 0": (
         [("if (level == 0) { level = 1; rep->n_restarts++; path |= 2; continue; }", "")],
         [RULES + "test_beta_zero_retry_after_a_failed_line_search"]),
