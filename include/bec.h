@@ -82,8 +82,14 @@ typedef struct {
     double Gdd[2][2];   /* dipolar k-space amplitudes                          */
     double c_lhy;       /* multiplier of the LHY term (1 = the paper)          */
     double r_cut;       /* dipolar cutoff: radius (dip_cut 0) or slab half-height (1), > 0 */
-    int32_t n_u;        /* Gauss-Legendre nodes for the u integral, 1..64      */
+    int32_t n_u;        /* Gauss-Legendre nodes for the u integral, 1..64 (per
+                           piece of [0,1] when lhy_quad = 1)                    */
     int32_t dip_cut;    /* 0 spherical cutoff, 1 slab cut (periodic x, y)      */
+    int32_t lhy_quad;   /* u rule: 0 Gauss-Legendre, n_u nodes on [0,1];
+                           1 root-split, n_u nodes on each piece between the
+                           points where a branch potential can change sign
+                           (zeros of det eta(u) and of eta_11(u), eta_22(u));
+                           at most 64 nodes in all (BEC_EINVAL otherwise)     */
 } bec_params;
 
 /* Preconditioners of Sec. IV.B: identity, real-space diagonal P_V, kinetic

@@ -27,12 +27,13 @@ class Grid(C.Structure):
 class Params(C.Structure):
     _fields_ = [("N", C.c_double * 2), ("omega", C.c_double * 3),
                 ("G", (C.c_double * 2) * 2), ("Gdd", (C.c_double * 2) * 2),
-                ("c_lhy", C.c_double), ("r_cut", C.c_double), ("n_u", C.c_int32), ("dip_cut", C.c_int32)]
+                ("c_lhy", C.c_double), ("r_cut", C.c_double), ("n_u", C.c_int32), ("dip_cut", C.c_int32),
+                ("lhy_quad", C.c_int32)]
 
     def to_dict(self) -> dict:
         return {"N": list(self.N), "omega": list(self.omega), "G": [list(r) for r in self.G],
                 "Gdd": [list(r) for r in self.Gdd], "c_lhy": self.c_lhy, "r_cut": self.r_cut, "n_u": self.n_u,
-                "dip_cut": self.dip_cut}
+                "dip_cut": self.dip_cut, "lhy_quad": self.lhy_quad}
 
 
 class Opts(C.Structure):
@@ -175,6 +176,7 @@ def make_params(p: dict) -> Params:
         P.omega[d] = float(p["omega"][d])
     P.c_lhy = float(p["c_lhy"]); P.r_cut = float(p["r_cut"]); P.n_u = int(p["n_u"])
     P.dip_cut = int(p.get("dip_cut", 0))
+    P.lhy_quad = int(p.get("lhy_quad", 0))
     return P
 
 

@@ -133,6 +133,62 @@ void gauss_legendre01(int n, std::vector<double>& u, std::vector<double>& w)
     }
 }
 
+// Rule for the u integral of the LHY term (Sec. II, Eq. (3)).  lhy_quad 0:
+// n_u Gauss-Legendre nodes on [0,1].  lhy_quad 1, root-split: with a = 3u^2 - 1
+// the branch potentials satisfy V_+ V_- = 4 n1 n2 det(a), det quadratic in a, and
+// (N_i eta_ij being symmetric, eta_12 eta_21 >= 0) change sign only at the zeros
+// of det(a), or of eta_11(a), eta_22(a) when one density vanishes -- points fixed
+// by the couplings alone.  n_u nodes go on each piece between consecutive such
+// points in u, through u = p + (q - p)(1 - cos(pi t))/2, which turns the
+// (u - u_b)^(k/2) ends of the clipped powers into smooth integrands.
+void lhy_rule(const bec_params& p, std::vector<double>& u, std::vector<double>& w)
+{
+    std::vector<double> t, tw;
+    gauss_legendre01(p.n_u, t, tw);
+    if (p.lhy_quad != 1) {
+        u = t;
+        w = tw;
+        return;
+    }
+    std::vector<long double> ub;
+    auto add = [&](long double a) {
+        if (std::isfinite((double)a) && a > -1.0L && a < 2.0L) ub.push_back(sqrtl((a + 1.0L) / 3.0L));
+    };
+    const long double g11 = p.G[0][0], g22 = p.G[1][1], g12 = p.G[0][1], g21 = p.G[1][0];
+    const long double d11 = p.Gdd[0][0], d22 = p.Gdd[1][1], d12 = p.Gdd[0][1], d21 = p.Gdd[1][0];
+    // det(a) = qa a^2 + qb a + qc
+    const long double qa = d11 * d22 - d12 * d21;
+    const long double qb = g11 * d22 + d11 * g22 - g12 * d21 - d12 * g21;
+    const long double qc = g11 * g22 - g12 * g21;
+    if (qa != 0.0L) {
+        const long double disc = qb * qb - 4.0L * qa * qc;
+        if (disc >= 0.0L) {
+            const long double r = sqrtl(disc);
+            add((-qb + r) / (2.0L * qa));
+            add((-qb - r) / (2.0L * qa));
+        }
+    } else if (qb != 0.0L) {
+        add(-qc / qb);
+    }
+    if (d11 != 0.0L) add(-g11 / d11);
+    if (d22 != 0.0L) add(-g22 / d22);
+    std::sort(ub.begin(), ub.end());
+    std::vector<long double> ends{0.0L};
+    for (long double b : ub)
+        if (b > ends.back() + 1e-15L) ends.push_back(b);
+    if (ends.back() < 1.0L) ends.push_back(1.0L);
+    u.clear();
+    w.clear();
+    for (size_t k = 0; k + 1 < ends.size(); ++k) {
+        const long double lo = ends[k], len = ends[k + 1] - ends[k];
+        for (int j = 0; j < p.n_u; ++j) {
+            const long double th = kPiL * (long double)t[j];
+            u.push_back((double)(lo + len * 0.5L * (1.0L - cosl(th))));
+            w.push_back((double)((long double)tw[j] * len * 0.5L * kPiL * sinl(th)));
+        }
+    }
+}
+
 // Spherical cutoff of the dipolar kernel (radius R in real space):
 // c(q) = 1 + 3 cos q / q^2 - 3 sin q / q^3, q = |k| R; below q = 1 its series
 // sum_{m>=1} (-1)^(m+1) 6 (m+1) q^(2m) / (2m+3)! = q^2/10 - q^4/280 + ...,
@@ -399,6 +455,7 @@ bec_status check_params(const bec_params* p)
     if (p->n_u < 1 || p->n_u > bec::kMaxNodes) return fail(BEC_EINVAL, "n_u must be in 1..%d", bec::kMaxNodes);
     if (!(p->r_cut > 0)) return fail(BEC_EINVAL, "r_cut must be positive");
     if (p->dip_cut != 0 && p->dip_cut != 1) return fail(BEC_EINVAL, "dip_cut must be 0 or 1");
+    if (p->lhy_quad != 0 && p->lhy_quad != 1) return fail(BEC_EINVAL, "lhy_quad must be 0 or 1");
     const double* all[] = {p->omega, &p->G[0][0], &p->Gdd[0][0]};
     const int cnt[] = {3, 4, 4};
     for (int a = 0; a < 3; ++a)
@@ -410,6 +467,13 @@ bec_status check_params(const bec_params* p)
     if (std::fabs(a - b) > 1e-12 * std::max(std::fabs(a), std::fabs(b)) ||
         std::fabs(c - d) > 1e-12 * std::max(std::fabs(c), std::fabs(d)))
         return fail(BEC_EINVAL, "N_i G_ij and N_i Gdd_ij must be symmetric");
+    if (p->lhy_quad == 1) {
+        std::vector<double> u, w;
+        lhy_rule(*p, u, w);
+        if ((int)u.size() > bec::kMaxNodes)
+            return fail(BEC_EINVAL, "the root-split u rule needs %zu nodes (n_u on each piece), at most %d", u.size(),
+                        bec::kMaxNodes);
+    }
     return BEC_OK;
 }
 
@@ -421,7 +485,7 @@ void hot_nodes(const bec_params& p, const std::vector<double>& u, const std::vec
                double node5[][5], int* n_a, int* n_b)
 {
     std::vector<std::array<double, 5>> A, B;
-    for (int q = 0; q < p.n_u; ++q) {
+    for (size_t q = 0; q < u.size(); ++q) {
         const double a = 3.0 * u[q] * u[q] - 1.0;
         const double e11 = p.G[0][0] + p.Gdd[0][0] * a, e22 = p.G[1][1] + p.Gdd[1][1] * a;
         const double p12 = (p.G[0][1] + p.Gdd[0][1] * a) * (p.G[1][0] + p.Gdd[1][0] * a);
@@ -545,9 +609,9 @@ bec_status upload_params(bec_ctx* c, bool dipolar_table)
 {
     const bec_params& p = c->p;
     std::vector<double> u, w;
-    gauss_legendre01(p.n_u, u, w);
+    lhy_rule(p, u, w);
     std::vector<double> nodes((size_t)bec::kMaxNodes * bec::kNodeStride, 0.0);
-    for (int q = 0; q < p.n_u; ++q) {
+    for (size_t q = 0; q < u.size(); ++q) {
         const double a = 3.0 * u[q] * u[q] - 1.0;
         double* nd = &nodes[(size_t)q * bec::kNodeStride];
         const double e12 = p.G[0][1] + p.Gdd[0][1] * a, e21 = p.G[1][0] + p.Gdd[1][0] * a;
@@ -605,7 +669,7 @@ bec_status upload_params(bec_ctx* c, bool dipolar_table)
     }
     P.K5 = p.c_lhy * std::sqrt(2.0) / (15.0 * M_PI * M_PI);
     P.K3 = p.c_lhy / (3.0 * std::sqrt(2.0) * M_PI * M_PI);
-    P.n_u = p.n_u;
+    P.n_u = (int)u.size();
     P.lhy_on = p.c_lhy != 0.0;
     P.lhy_tab = c->lhytab;
     P.lhy_K = c->lhy_table_on ? c->lhy_K_built : 0;
@@ -2138,10 +2202,10 @@ void instance_params(const bec_grid& gr, const bec_params& p, bec::BInstParams& 
     P.K3 = p.c_lhy / (3.0 * std::sqrt(2.0) * M_PI * M_PI);
     P.dV = dV;
     P.inv_npts = 1.0 / (double)npts;
-    P.n_u = p.n_u;
     P.lhy_on = p.c_lhy != 0.0;
     std::vector<double> u, w;
-    gauss_legendre01(p.n_u, u, w);
+    lhy_rule(p, u, w);
+    P.n_u = (int)u.size();
     hot_nodes(p, u, w, P.node5, &P.n_a, &P.n_b);
     P.lhy_K = P.lhy_on ? build_lhy_table(P.node5, P.n_a, P.lhytab) : 0;
 }

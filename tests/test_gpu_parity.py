@@ -138,6 +138,14 @@ CASES = {
     "smallcut_aniso": ({"n": [32, 32, 16], "lo": [-16, -12, -4], "hi": [16, 12, 4]},
                        small_params(r_cut=2.5, N=[1.0, 1.6], G=[[100.0, 50.0], [31.25, 90.0]],
                                     Gdd=[[60.0, -45.0], [-28.125, 50.0]])),
+    # the root-split rule for the u integral (lhy_quad 1): the droplet couplings (eps_dd > 1,
+    # three pieces), every node class, and the stripe couplings with N_1 != N_2
+    "C2_rootsplit": (inputs.CONFIGS["C2"]["grid"], dict(inputs.CONFIGS["C2"]["params"], lhy_quad=1)),
+    "allclasses_rootsplit": ({"n": [16, 16, 32], "lo": [-6, -6, -6], "hi": [6, 6, 6]},
+                             small_params(G=[[10.0, 2.0], [2.0, 12.0]], Gdd=[[30.0, 5.0], [5.0, 30.0]], lhy_quad=1)),
+    "stripe_rootsplit": ({"n": [32, 16, 16], "lo": [-8, -6, -6], "hi": [8, 6, 6]},
+                         small_params(N=[1.0, 1.6], G=[[60.0, 70.0], [43.75, 60.0]], Gdd=[[78.0, 91.0], [56.875, 78.0]],
+                                      c_lhy=6.0, lhy_quad=1)),
 }
 
 
@@ -240,7 +248,7 @@ def test_energy_is_bitwise_repeatable(solver):
 # restriction to n1 + n2 = 1 (tuning lhy_table, on by default where the series
 # meet their 2e-14 bar at creation).  Table and node loop agree to ~1e-14 of the
 # LHY terms; the oracle parity tests above run with the table on.
-@pytest.mark.parametrize("case", ["C1b", "mixedN", "allclasses", "nu24_mixedN", "C2"])
+@pytest.mark.parametrize("case", ["C1b", "mixedN", "allclasses", "nu24_mixedN", "C2", "C2_rootsplit"])
 def test_lhy_table_matches_node_loop(solver, case):
     grid, params = CASES[case]
     psi = torch.from_numpy(_state(grid, params, 23, True)).cuda()
@@ -335,7 +343,7 @@ def _tangent(grid, d, psi):
     return np.array([d[i] - dV * np.sum(np.real(np.conj(d[i]) * psi[i])) * psi[i] for i in range(2)])
 
 
-@pytest.mark.parametrize("case", ["C1b", "C2", "mixedN", "allclasses", "nu5"])
+@pytest.mark.parametrize("case", ["C1b", "C2", "mixedN", "allclasses", "nu5", "C2_rootsplit", "stripe_rootsplit"])
 @pytest.mark.parametrize("kind", ["random", "descent"])
 def test_linesearch_model_and_step(solver, orc, case, kind):
     """random: a rough direction (model parity, including E1 > 0 / E2 < 0 and
@@ -384,6 +392,24 @@ def test_param_grad(solver, orc, case):
 
 # ---------------------------------------------------------------- full solves
 SOLVE_CASES = [("C1a", 1), ("C1b", 1), ("C1b", 0), ("C1b", 2), ("C1b", 3), ("C1b", 4), ("C1b", 5)]
+
+
+@pytest.mark.parametrize("case", ["allclasses_rootsplit", "stripe_rootsplit"])
+def test_root_split_solver_steps(solver, orc, case):
+    """Twenty solver steps with the root-split u rule, single context and batch."""
+    grid, params = CASES[case]
+    psi0 = _state(grid, params, 61, False)
+    opts = {"tol_grad": 1e-10, "pc": 1, "max_iter": 20}
+    ctx = solver.Context(grid, params)
+    _, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=20)
+    _, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=20)
+    assert rep["iters"] == repo["iters"] == 20
+    for a, b in zip(log[:10], logo[:10]):
+        assert a["path"] == b["path"] and abs(a["E"] - b["E"]) <= 1e-11 * abs(b["E"])
+    b = solver.Batch([grid], [params])
+    _, reps = b.solve([psi0], opts, rounds_per_sync=4)
+    assert reps[0]["iters"] == 20
+    assert abs(reps[0]["final"]["E"] - repo["final"]["E"]) <= 1e-10 * abs(repo["final"]["E"])
 
 
 @pytest.mark.parametrize("name,pc", SOLVE_CASES, ids=[f"{n}-pc{p}" for n, p in SOLVE_CASES])
