@@ -104,33 +104,46 @@ def tune(ctx, reps: int = 20, iters: int = 8, psi0=None, opts: dict | None = Non
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1) / iters
 
+    best["kin_axes"] = 1
     iter_ms = {}
     for b in [c for c in PW_CHOICES if c <= cap] or [cap]:   # small grids: one block per 256 points
         best["pw_blocks"] = b
         iter_ms[b] = per_iter(best)
     best["pw_blocks"] = int(min(iter_ms, key=iter_ms.get))
-    # the z, y and k-space x variants also run the passes with fused work (the trial
-    # update and the kinetic axis terms, the Parseval axis sums), which the single-pass
-    # timings above do not see: choose them over whole PCG iterations too
     axis_ms = {}
-    for axis, slot in ((2, 0), (1, 0), (0, 1)):
-        L = ctx.grid["n"][axis]
-        if variant_count(L) < 2:
-            continue
+
+    def choose_kin_axes(tag):
+        # the kinetic term from one-axis transforms (less traffic, more transforms per pencil in
+        # the trial pass) against the 3D multiply (pays off on launch-bound small grids)
         t = []
-        for v in range(variant_count(L)):
-            best["fft_variant"][axis][slot] = v
+        for k in (0, 1):
+            best["kin_axes"] = k
             t.append(per_iter(best))
-        best["fft_variant"][axis][slot] = int(min(range(len(t)), key=t.__getitem__))
-        axis_ms[f"axis{axis}" + ("_kspace" if slot else "")] = [round(x, 5) for x in t]
-    # the kinetic term from one-axis transforms (less traffic, more transforms per pencil in
-    # the trial pass) against the 3D multiply (pays off on launch-bound small grids)
-    t = []
-    for k in (0, 1):
-        best["kin_axes"] = k
-        t.append(per_iter(best))
-    best["kin_axes"] = int(t[1] <= t[0])
-    axis_ms["kin_axes"] = [round(x, 5) for x in t]
+        best["kin_axes"] = int(t[1] <= t[0])
+        axis_ms[tag] = [round(x, 5) for x in t]
+
+    def sweep_variants():
+        # the z, y and k-space x variants also run the passes with fused work (the trial
+        # update and, with kin_axes, the kinetic axis terms; the Parseval axis sums),
+        # which the single-pass timings above do not see: choose them over whole PCG
+        # iterations, with the kinetic-term switch already set
+        for axis, slot in ((2, 0), (1, 0), (0, 1)):
+            L = ctx.grid["n"][axis]
+            if variant_count(L) < 2:
+                continue
+            t = []
+            for v in range(variant_count(L)):
+                best["fft_variant"][axis][slot] = v
+                t.append(per_iter(best))
+            best["fft_variant"][axis][slot] = int(min(range(len(t)), key=t.__getitem__))
+            axis_ms[f"axis{axis}" + ("_kspace" if slot else "")] = [round(x, 5) for x in t]
+
+    choose_kin_axes("kin_axes")
+    first = best["kin_axes"]
+    sweep_variants()
+    choose_kin_axes("kin_axes_recheck")          # with the tuned variants
+    if best["kin_axes"] != first:
+        sweep_variants()                          # the variants for the switch that won
     ctx.set_tuning(best)
     return {"tuning": best, "fft_ms": fft_ms, "iter_ms": {str(k): round(v, 5) for k, v in iter_ms.items()},
             "iter_ms_variants": axis_ms, "seconds": round(time.time() - t0, 3)}

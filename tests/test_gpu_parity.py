@@ -186,6 +186,7 @@ def test_autotune_small_grids(solver, orc, shape):
     t = ctx.get_tuning()
     assert t["pw_blocks"] == res["tuning"]["pw_blocks"] <= (int(np.prod(shape)) + 255) // 256
     assert t["kin_axes"] in (0, 1) and len(res["iter_ms_variants"]["kin_axes"]) == 2
+    assert len(res["iter_ms_variants"]["kin_axes_recheck"]) == 2
     psi = _state(grid, params, 21, True)
     h, e = ctx.hamiltonian(torch.from_numpy(psi))
     to, ho, _, _ = orc.heval(grid, params, psi)
@@ -299,13 +300,15 @@ def test_blended_preconditioner(solver, orc, case, blend):
 
 
 @pytest.mark.parametrize("n", [8, 16, 32, 48, 64, 96, 128, 256])
-def test_every_variant_of_the_fused_passes(solver, orc, n):
+@pytest.mark.parametrize("kin_axes", [1, 0])
+def test_every_variant_of_the_fused_passes(solver, orc, n, kin_axes):
     """Every plan variant of the passes with fused work: the x pass with the
     k-space operators (slot [0][1]), the y passes that add the kinetic axis term
     and the Parseval axis sums (slot [1][0]) and the z passes that carry the
     trial update, the kinetic axis term and the line-search epilogue (slot
     [2][0]), on a grid that is n long along that axis; energy, H psi and the
-    line-search model and trial against the oracle."""
+    line-search model and trial against the oracle.  Both kinetic-term paths:
+    the one-axis terms (kin_axes 1) and the 3D multiply in the x pass (0)."""
     from paper_2510_24543_amd import autotune
     params = small_params()
     for axis, slot in ((0, (0, 1)), (1, (1, 0)), (2, (2, 0))):
@@ -322,9 +325,11 @@ def test_every_variant_of_the_fused_passes(solver, orc, n):
         base = ctx.get_tuning()
         for v in range(autotune.variant_count(n)):
             print(f"n {n} axis {axis} variant {v}", flush=True)
-            t = {"fft_variant": [r_[:] for r_ in base["fft_variant"]], "pw_blocks": base["pw_blocks"]}
+            t = {"fft_variant": [r_[:] for r_ in base["fft_variant"]], "pw_blocks": base["pw_blocks"],
+                 "kin_axes": kin_axes}
             t["fft_variant"][slot[0]][slot[1]] = v
             ctx.set_tuning(t)
+            assert ctx.get_tuning()["kin_axes"] == kin_axes
             h, tg = ctx.hamiltonian(torch.from_numpy(psi))
             assert abs(tg["E"] - to["E"]) <= 1e-12 * abs(to["E"]), (axis, v)
             assert rel(h.cpu().numpy(), ho) < 1e-11, (axis, v)
