@@ -135,6 +135,10 @@ struct FftPassArgs {
     const double* prec_state;
     double prec_sigma;
     double prec_Gdd[2][2];
+    // field of blockIdx.y in a fused pass: fields with an inverse transform
+    // first, so that the blocks dispatched last are the light ones (set by the
+    // launcher; the results do not depend on it)
+    int forder[3];
 };
 
 // Forward z pass fused with the geodesic trial update: psi_dst = a_i psi_src +

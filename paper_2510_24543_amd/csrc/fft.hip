@@ -157,9 +157,26 @@ __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
 template <int L>
 constexpr int lds_row() { return L + L / 8 + 1; }
 
+// Ordering of an LDS exchange among the threads of one pencil.  WAVE: the
+// pencil's threads lie in one wavefront (the contiguous z passes: consecutive
+// lanes take consecutive elements of a pencil and T divides 64), whose LDS
+// instructions execute in program order, so only the compiler must keep the
+// writes before the reads (and the reads before the next writes); otherwise the
+// pencil spans wavefronts and needs a workgroup barrier.
+template <bool WAVE>
+__device__ __forceinline__ void pencil_sync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
+
 // Output of stage (R, NS): v[b R + r] goes to Y[(j/NS) NS R + (j mod NS) + r NS].
 // The next stage (radix RN) reads X[t + b T + r L/RN].
-template <int L, int T, int R, int NS, int RN>
+template <int L, int T, int R, int NS, int RN, bool WAVE>
 __device__ __forceinline__ void exchange(double2* v, double2* row, int t)
 {
     constexpr int E = L / T;
@@ -170,45 +187,47 @@ __device__ __forceinline__ void exchange(double2* v, double2* row, int t)
 #pragma unroll
         for (int r = 0; r < R; ++r) row[lds_pad(base + r * NS)] = v[b * R + r];
     }
-    __syncthreads();
+    pencil_sync<WAVE>();
 #pragma unroll
     for (int b = 0; b < E / RN; ++b)
 #pragma unroll
         for (int r = 0; r < RN; ++r) v[b * RN + r] = row[lds_pad(t + b * T + r * (L / RN))];
-    __syncthreads();
+    pencil_sync<WAVE>();
 }
 
 // Full length-L transform of the registers, radices R0 R1 R2 (1 = absent).
 // Input in stage-0 layout of R0, output in natural layout of the last radix.
-template <int L, int T, int R0, int R1, int R2, int D>
+template <int L, int T, int R0, int R1, int R2, int D, bool WAVE>
 __device__ __forceinline__ void run_fft(double2* v, double2* row, int t, const double2* __restrict__ tw)
 {
     stage<L, T, R0, 1, D>(v, t, tw);
     if constexpr (R1 > 1) {
-        exchange<L, T, R0, 1, R1>(v, row, t);
+        exchange<L, T, R0, 1, R1, WAVE>(v, row, t);
         stage<L, T, R1, R0, D>(v, t, tw);
         if constexpr (R2 > 1) {
-            exchange<L, T, R1, R0, R2>(v, row, t);
+            exchange<L, T, R1, R0, R2, WAVE>(v, row, t);
             stage<L, T, R2, R0 * R1, D>(v, t, tw);
         }
     }
 }
 
-template <int L, int T, int R0, int R1, int R2>
+// WAVE: see pencil_sync (true for the contiguous-axis kernels)
+template <int L, int T, int R0, int R1, int R2, bool WAVE = false>
 struct Plan {
+    static_assert(!WAVE || (T <= 64 && 64 % T == 0), "a pencil must not straddle wavefronts");
     static constexpr int RL = R2 > 1 ? R2 : (R1 > 1 ? R1 : R0);   // last forward radix
     static constexpr int E = L / T;
     template <int D>
     __device__ static void fwd_like(double2* v, double2* row, int t, const double2* tw)
     {
-        run_fft<L, T, R0, R1, R2, D>(v, row, t, tw);
+        run_fft<L, T, R0, R1, R2, D, WAVE>(v, row, t, tw);
     }
     // inverse run with reversed radices: starts in the layout the forward ends in
     __device__ static void inv_rev(double2* v, double2* row, int t, const double2* tw)
     {
-        if constexpr (R2 > 1) run_fft<L, T, R2, R1, R0, +1>(v, row, t, tw);
-        else if constexpr (R1 > 1) run_fft<L, T, R1, R0, 1, +1>(v, row, t, tw);
-        else run_fft<L, T, R0, 1, 1, +1>(v, row, t, tw);
+        if constexpr (R2 > 1) run_fft<L, T, R2, R1, R0, +1, WAVE>(v, row, t, tw);
+        else if constexpr (R1 > 1) run_fft<L, T, R1, R0, 1, +1, WAVE>(v, row, t, tw);
+        else run_fft<L, T, R0, 1, 1, +1, WAVE>(v, row, t, tw);
     }
 };
 
@@ -232,7 +251,8 @@ __device__ double block_sum(double v, double* sh)
 // energy evaluation (kinetic axis terms), of the line search (Parseval axis
 // sums) and the other passes separately.
 struct GenericPass {};
-struct EnergyPass {};
+struct EnergyPass {};     // the x pass of the energy evaluation (kinetic axis terms, dipolar multiply)
+struct EnergyPassY {};    // the y pass of the energy evaluation (kinetic axis terms)
 struct LineSearchPass {};
 
 // KMODE: 0 forward plain pass (fields Plain or ParsevalAxis), 1 inverse plain pass, 2 fused pass with
@@ -241,10 +261,10 @@ struct LineSearchPass {};
 template <int L, int T, int R0, int R1, int R2, int NTHR, bool CONTIG, int KMODE, typename KIND>
 __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
 {
-    using PL = Plan<L, T, R0, R1, R2>;
+    using PL = Plan<L, T, R0, R1, R2, CONTIG>;
     constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>();
     __shared__ double2 lds[PB * RS];
-    const int f = blockIdx.y;
+    const int f = KMODE == 2 ? A.forder[blockIdx.y] : (int)blockIdx.y;
     const int inst = A.inst_ids ? A.inst_ids[blockIdx.z] : (int)blockIdx.z;
     if (A.active && A.active[inst] == 0) return;   // uniform per block
     const long long soff = (long long)inst * A.src_stride[f] +
@@ -429,7 +449,7 @@ template <int L, int T, int R0, int R1, int R2>
 __device__ __forceinline__ void kin_z_store(double2* w, double2* row, int t, const FftPassArgs& A, double2* d,
                                             long long base, bool valid)
 {
-    using PL = Plan<L, T, R0, R1, R2>;
+    using PL = Plan<L, T, R0, R1, R2, true>;
     constexpr int E = L / T, RL = PL::RL;
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
@@ -454,7 +474,7 @@ template <int L, int T, int R0, int R1, int R2, int NTHR>
 __device__ __forceinline__ void trial_z_body(const FftPassArgs& A, const TrialZArgs& Z, double2* d0, double2* d1,
                                              double2* d2, double2* lds)
 {
-    using PL = Plan<L, T, R0, R1, R2>;
+    using PL = Plan<L, T, R0, R1, R2, true>;
     constexpr int E = L / T, RS = lds_row<L>(), RL = PL::RL;
     constexpr int PB = NTHR / T;
     const int tid = threadIdx.x;
@@ -584,7 +604,7 @@ template <int L, int T, int R0, int R1, int R2, int NTHR>
 __global__ __launch_bounds__(NTHR) void fft_zinv_ls_kernel(FftPassArgs A, const double2* __restrict__ rho,
                                                             double* __restrict__ partials)
 {
-    using PL = Plan<L, T, R0, R1, R2>;
+    using PL = Plan<L, T, R0, R1, R2, true>;
     constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>(), RL = PL::RL, M = kLsEpiSums;
     __shared__ double2 lds[PB * RS];
     const int tid = threadIdx.x;
@@ -636,8 +656,17 @@ __global__ __launch_bounds__(NTHR) void fft_zinv_ls_kernel(FftPassArgs A, const 
 }
 
 template <int L, int T, int R0, int R1, int R2, int NTHR>
-hipError_t launch_cfg(bool contiguous, const FftPassArgs& A, hipStream_t st)
+hipError_t launch_cfg(bool contiguous, const FftPassArgs& A0, hipStream_t st)
 {
+    FftPassArgs A = A0;
+    {   // fused passes: the fields with an inverse transform dispatched first
+        int k = 0;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int f = 0; f < A.nfield; ++f) {
+                const bool light = A.op[f] == kOpPlain || A.op[f] == kOpParseval || A.op[f] == kOpParsevalAxis;
+                if (light == (pass == 1)) A.forder[k++] = f;
+            }
+    }
     constexpr int PB = NTHR / T;
     dim3 grid((unsigned)((A.npencil + PB - 1) / PB), (unsigned)A.nfield, (unsigned)(A.n_inst > 0 ? A.n_inst : 1));
     // plain: every field Plain or ParsevalAxis (a one-axis pass; ParsevalAxis
@@ -662,7 +691,8 @@ hipError_t launch_cfg(bool contiguous, const FftPassArgs& A, hipStream_t st)
         else if (axis_sums) BEC_LAUNCH_PASS(false, 0, LineSearchPass);
         else BEC_LAUNCH_PASS(false, 0, GenericPass);
     } else if (kin) {
-        BEC_LAUNCH_PASS(false, 2, EnergyPass);
+        if (A.npencil == A.S) BEC_LAUNCH_PASS(false, 2, EnergyPass);     // x: the pencils are the (y, z) columns
+        else BEC_LAUNCH_PASS(false, 2, EnergyPassY);
     } else if (axis_sums) {
         BEC_LAUNCH_PASS(false, 2, LineSearchPass);
     } else {
