@@ -126,28 +126,54 @@ template <int D> struct Dft<16, D> {
     __device__ static void run(double2* v) { dft_split<4, 4, D>(v); }
 };
 
+// Powers w[r] = w1^r, r = 1..R-1, of a twiddle by repeated squaring (at most
+// five products deep for R = 16, a few units in the last place), so that a
+// butterfly loads one twiddle instead of R - 1: the loads, not the arithmetic,
+// are the scarce issue slots of these passes.  D > 0 conjugates w1.
+template <int R, int D>
+__device__ __forceinline__ void twiddle_powers(double2 w1, double2* w)
+{
+    if (D > 0) w1.y = -w1.y;
+    w[1] = w1;
+#pragma unroll
+    for (int r = 2; r < R; ++r) w[r] = (r % 2 == 0) ? cmul(w[r / 2], w[r / 2]) : cmul(w[r - 1], w1);
+}
+
 // Stockham stage of radix R after a span NS of earlier radices.  Thread t owns
 // butterflies j = t + b T; butterfly j reads X[j + r L/R] (registers
 // v[b R + r]), applies W_L^(r k L/(NS R)), k = j mod NS, and a length-R DFT.
+// Where NS divides T every butterfly of the thread has the same k.
 template <int L, int T, int R, int NS, int D>
 __device__ __forceinline__ void stage(double2* v, int t, const double2* __restrict__ tw)
 {
     constexpr int E = L / T, NB = E / R;
     static_assert(E % R == 0, "radix must divide the elements per thread");
+    if constexpr (NS > 1) {
+        constexpr bool same_k = T % NS == 0;
+        double2 w[R];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        if (NS > 1) {
-            const int j = t + b * T;
-            const int k = j % NS;
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                double2 w = tw[r * k * (L / (NS * R))];
-                if (D > 0) w.y = -w.y;
-                v[b * R + r] = cmul(v[b * R + r], w);
+        for (int b = 0; b < NB; ++b) {
+            if (b == 0 || !same_k) {
+                const int k = (int)((unsigned)(t + b * T) % (unsigned)NS);
+                twiddle_powers<R, D>(tw[k * (L / (NS * R))], w);
             }
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], w[r]);
+            Dft<R, D>::run(v + b * R);
         }
-        Dft<R, D>::run(v + b * R);
+    } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) Dft<R, D>::run(v + b * R);
     }
+}
+
+// Wavenumber of index j on a length-L axis, k_j = dk (j < L/2 ? j : j - L), with
+// dk the table's entry for j = 1 (the tables hold the same formula, rounded once
+// instead of twice): computed, so the passes do not load a table entry per element.
+template <int L>
+__device__ __forceinline__ double kwave(double dk, int j)
+{
+    return dk * (double)(j < L / 2 ? j : j - L);
 }
 
 // LDS rows are padded by one element after every 8: the stride-R writes of
@@ -258,11 +284,17 @@ struct LineSearchPass {};
 // KMODE: 0 forward plain pass (fields Plain or ParsevalAxis), 1 inverse plain pass, 2 fused pass with
 // per-field ops: forward, operator, inverse (the x pass; the y pass with kinetic axis terms); its
 // Plain fields are forward only.
-template <int L, int T, int R0, int R1, int R2, int NTHR, bool CONTIG, int KMODE, typename KIND>
+// WLOC (strided axes only): each wavefront holds 64/T whole pencils, lanes with
+// the same t on consecutive pencils (a load instruction covers 64/T adjacent
+// columns per element row), so the LDS exchanges need no workgroup barrier.
+// Otherwise consecutive lanes take consecutive pencils of the whole block and
+// a pencil's threads span wavefronts.
+template <int L, int T, int R0, int R1, int R2, int NTHR, bool CONTIG, int KMODE, typename KIND, bool WLOC>
 __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
 {
-    using PL = Plan<L, T, R0, R1, R2, CONTIG>;
-    constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>();
+    static_assert(!WLOC || (T <= 64 && 64 % T == 0 && NTHR % 64 == 0), "wave-local pencils");
+    using PL = Plan<L, T, R0, R1, R2, CONTIG || WLOC>;
+    constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>(), PW = WLOC ? 64 / T : 1;
     __shared__ double2 lds[PB * RS];
     const int f = KMODE == 2 ? A.forder[blockIdx.y] : (int)blockIdx.y;
     const int inst = A.inst_ids ? A.inst_ids[blockIdx.z] : (int)blockIdx.z;
@@ -271,8 +303,8 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
                            (A.src_sel ? (long long)A.src_sel[inst] * A.src_sel_stride[f] : 0);
     const long long doff = (long long)inst * A.dst_stride[f];
     const int tid = threadIdx.x;
-    const int pl = CONTIG ? tid / T : tid % PB;
-    const int t = CONTIG ? tid % T : tid / PB;
+    const int pl = CONTIG ? tid / T : (WLOC ? (tid >> 6) * PW + (tid & 63) % PW : tid % PB);
+    const int t = CONTIG ? tid % T : (WLOC ? (tid & 63) / PW : tid / PB);
     const long long pg = (long long)blockIdx.x * PB + pl;
     const bool valid = pg < A.npencil;
     const long long S = A.S;
@@ -301,13 +333,14 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
     if (KMODE < 2) {
         PL::template fwd_like<KMODE == 0 ? -1 : +1>(v, row, t, tw);
         if (KMODE == 0 && A.op[f] == kOpParsevalAxis) {      // uniform per block (f = blockIdx.y)
+            const double dka = A.kaxis[(A.per_inst_tab ? (long long)inst * L : 0) + 1];
             double acc = 0.0;
 #pragma unroll
             for (int b = 0; b < E / RL; ++b)
 #pragma unroll
                 for (int r = 0; r < RL; ++r) {
                     const int j = t + b * T + r * (L / RL);
-                    const double k = A.kaxis[(A.per_inst_tab ? (long long)inst * L : 0) + j];
+                    const double k = kwave<L>(dka, j);
                     const double2 w = v[b * RL + r];
                     acc += 0.5 * (k * k) * (w.x * w.x + w.y * w.y);
                 }
@@ -346,7 +379,8 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
         }
         return;
     }
-    const double* __restrict__ kxt = A.kx + (A.per_inst_tab ? (long long)inst * A.nx : 0);
+    const double dkx = A.kx[(A.per_inst_tab ? (long long)inst * A.nx : 0) + 1];
+    const double dka = A.kaxis ? A.kaxis[(A.per_inst_tab ? (long long)inst * L : 0) + 1] : 0.0;
     const double* __restrict__ udt = A.udtab + (A.per_inst_tab ? (long long)inst * A.udsize : 0);
     double ky2 = 0.0, kz2 = 0.0;
     int ay = 0, az = 0;
@@ -366,7 +400,7 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const int j = t + b * T + r * (L / RL);
-                const double kx = kxt[j];
+                const double kx = kwave<L>(op == kOpParsevalAxis ? dka : dkx, j);
                 const double2 w = v[b * RL + r];
                 const double kk = op == kOpParsevalAxis ? kx * kx : kx * kx + ky2 + kz2;
                 acc += 0.5 * kk * (w.x * w.x + w.y * w.y);
@@ -394,19 +428,19 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
             const int j = t + b * T + r * (L / RL);
             double m;
             if (op == kOpMulKin) {
-                const double kx = kxt[j];
+                const double kx = kwave<L>(dkx, j);
                 m = 0.5 * (kx * kx + ky2 + kz2);
             } else if (op == kOpExpKin) {
-                const double kx = kxt[j];
+                const double kx = kwave<L>(dkx, j);
                 m = exp(-pa * 0.5 * (kx * kx + ky2 + kz2));
             } else if (op == kOpMulDip) {
                 const int ax = j <= L / 2 ? j : L - j;
                 m = udt[((long long)ax * (A.ny / 2 + 1) + ay) * (A.nz / 2 + 1) + az];
             } else if (op == kOpKinAxis) {
-                const double k = A.kaxis[(A.per_inst_tab ? (long long)inst * L : 0) + j];
+                const double k = kwave<L>(dka, j);
                 m = 0.5 * (k * k);
             } else {
-                const double kx = kxt[j];
+                const double kx = kwave<L>(dkx, j);
                 m = 1.0 / (pa + 0.5 * (kx * kx + ky2 + kz2));
             }
             v[b * RL + r] = cscale(v[b * RL + r], m * (op == kOpKinAxis ? A.inv_na : inv_n));
@@ -451,11 +485,12 @@ __device__ __forceinline__ void kin_z_store(double2* w, double2* row, int t, con
 {
     using PL = Plan<L, T, R0, R1, R2, true>;
     constexpr int E = L / T, RL = PL::RL;
+    const double dk = A.kaxis[1];
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
-            const double k = A.kaxis[t + b * T + r * (L / RL)];
+            const double k = kwave<L>(dk, t + b * T + r * (L / RL));
             w[b * RL + r] = cscale(w[b * RL + r], 0.5 * (k * k) * A.inv_na);
         }
     PL::inv_rev(w, row, t, A.tw);
@@ -655,7 +690,7 @@ __global__ __launch_bounds__(NTHR) void fft_zinv_ls_kernel(FftPassArgs A, const 
     }
 }
 
-template <int L, int T, int R0, int R1, int R2, int NTHR>
+template <int L, int T, int R0, int R1, int R2, int NTHR, bool WLOC>
 hipError_t launch_cfg(bool contiguous, const FftPassArgs& A0, hipStream_t st)
 {
     FftPassArgs A = A0;
@@ -679,7 +714,7 @@ hipError_t launch_cfg(bool contiguous, const FftPassArgs& A0, hipStream_t st)
     }
     if (plain && axis_sums && A.sign >= 0) return hipErrorInvalidValue;
 #define BEC_LAUNCH_PASS(C, K, KIND) \
-    hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, C, K, KIND>), grid, dim3(NTHR), 0, st, A)
+    hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, C, K, KIND, (C) ? false : WLOC>), grid, dim3(NTHR), 0, st, A)
     if (contiguous) {
         // the contiguous (z) axis never runs the fused mode
         if (!plain) return hipErrorInvalidValue;
@@ -705,32 +740,38 @@ hipError_t launch_cfg(bool contiguous, const FftPassArgs& A0, hipStream_t st)
 }  // namespace
 
 // Plan variants per length: threads per pencil T, radices (R0, R1, R2), threads
-// per workgroup.  Variant 0 is the default; the autotuner picks among them.
+// per workgroup, wave-local pencils on the strided axes (W, see fft_pass_kernel).
+// Variant 0 is the default; the autotuner picks among them.
 struct Variant {
-    int T, R0, R1, R2, nthr;
+    int T, R0, R1, R2, nthr, wloc;
 };
 
 #define BEC_FFT_VARIANTS(X)                                                                          \
-    X(8, 0, 1, 8, 1, 1, 128) X(8, 1, 1, 8, 1, 1, 64) X(8, 2, 1, 8, 1, 1, 256)                        \
-    X(16, 0, 4, 4, 4, 1, 256) X(16, 1, 2, 8, 2, 1, 256) X(16, 2, 4, 4, 4, 1, 128)                    \
-    X(32, 0, 4, 8, 4, 1, 256) X(32, 1, 4, 4, 8, 1, 256) X(32, 2, 4, 8, 4, 1, 128)                    \
-    X(32, 3, 8, 4, 4, 2, 256)                                                                        \
-    X(48, 0, 4, 12, 4, 1, 256) X(48, 1, 4, 4, 12, 1, 256) X(48, 2, 4, 12, 4, 1, 128)                 \
-    X(64, 0, 8, 8, 8, 1, 256) X(64, 1, 4, 16, 4, 1, 256) X(64, 2, 8, 8, 8, 1, 128)                   \
-    X(64, 3, 8, 8, 8, 1, 512) X(64, 4, 16, 4, 4, 4, 256) X(64, 5, 16, 4, 4, 4, 128)                  \
-    X(96, 0, 4, 12, 8, 1, 128) X(96, 1, 4, 12, 8, 1, 256) X(96, 2, 8, 6, 4, 4, 256)                  \
-    X(96, 3, 8, 12, 4, 2, 256)                                                                       \
-    X(128, 0, 8, 16, 8, 1, 256) X(128, 1, 8, 8, 16, 1, 256) X(128, 2, 8, 16, 8, 1, 128)              \
-    X(128, 3, 8, 16, 8, 1, 512) X(128, 4, 16, 8, 4, 4, 256) X(128, 5, 16, 8, 4, 4, 512)              \
-    X(128, 6, 16, 8, 4, 4, 128) X(128, 7, 16, 4, 4, 8, 256)                                          \
-    X(256, 0, 16, 16, 16, 1, 256) X(256, 1, 16, 16, 16, 1, 128) X(256, 2, 16, 16, 16, 1, 512)        \
-    X(256, 3, 32, 8, 8, 4, 256) X(256, 4, 16, 16, 4, 4, 256) X(256, 5, 32, 8, 8, 4, 512)
+    X(8, 0, 1, 8, 1, 1, 128, 0) X(8, 1, 1, 8, 1, 1, 64, 0) X(8, 2, 1, 8, 1, 1, 256, 0)               \
+    X(16, 0, 4, 4, 4, 1, 256, 0) X(16, 1, 2, 8, 2, 1, 256, 0) X(16, 2, 4, 4, 4, 1, 128, 0)           \
+    X(16, 3, 4, 4, 4, 1, 256, 1)                                                                     \
+    X(32, 0, 4, 8, 4, 1, 256, 0) X(32, 1, 4, 4, 8, 1, 256, 0) X(32, 2, 4, 8, 4, 1, 128, 0)           \
+    X(32, 3, 8, 4, 4, 2, 256, 0) X(32, 4, 4, 8, 4, 1, 256, 1)                                        \
+    X(48, 0, 4, 12, 4, 1, 256, 0) X(48, 1, 4, 4, 12, 1, 256, 0) X(48, 2, 4, 12, 4, 1, 128, 0)        \
+    X(48, 3, 4, 12, 4, 1, 256, 1)                                                                    \
+    X(64, 0, 8, 8, 8, 1, 256, 0) X(64, 1, 4, 16, 4, 1, 256, 0) X(64, 2, 8, 8, 8, 1, 128, 0)          \
+    X(64, 3, 8, 8, 8, 1, 512, 0) X(64, 4, 16, 4, 4, 4, 256, 0) X(64, 5, 16, 4, 4, 4, 128, 0)         \
+    X(64, 6, 16, 4, 4, 4, 256, 1) X(64, 7, 8, 8, 8, 1, 256, 1)                                       \
+    X(96, 0, 4, 12, 8, 1, 128, 0) X(96, 1, 4, 12, 8, 1, 256, 0) X(96, 2, 8, 6, 4, 4, 256, 0)         \
+    X(96, 3, 8, 12, 4, 2, 256, 0) X(96, 4, 8, 6, 4, 4, 256, 1) X(96, 5, 8, 12, 4, 2, 256, 1)         \
+    X(128, 0, 8, 16, 8, 1, 256, 0) X(128, 1, 8, 8, 16, 1, 256, 0) X(128, 2, 8, 16, 8, 1, 128, 0)     \
+    X(128, 3, 8, 16, 8, 1, 512, 0) X(128, 4, 16, 8, 4, 4, 256, 0) X(128, 5, 16, 8, 4, 4, 512, 0)     \
+    X(128, 6, 16, 8, 4, 4, 128, 0) X(128, 7, 16, 4, 4, 8, 256, 0) X(128, 8, 16, 8, 4, 4, 256, 1)     \
+    X(128, 9, 16, 8, 4, 4, 128, 1) X(128, 10, 8, 16, 8, 1, 256, 1)                                   \
+    X(256, 0, 16, 16, 16, 1, 256, 0) X(256, 1, 16, 16, 16, 1, 128, 0) X(256, 2, 16, 16, 16, 1, 512, 0) \
+    X(256, 3, 32, 8, 8, 4, 256, 0) X(256, 4, 16, 16, 4, 4, 256, 0) X(256, 5, 32, 8, 8, 4, 512, 0)    \
+    X(256, 6, 16, 16, 16, 1, 256, 1) X(256, 7, 32, 8, 8, 4, 256, 1)
 
 static bool find_variant(int L, int v, Variant* out)
 {
-#define BEC_FIND(LL, VV, T, R0, R1, R2, NT)         \
+#define BEC_FIND(LL, VV, T, R0, R1, R2, NT, W)      \
     if (L == LL && v == VV) {                       \
-        *out = Variant{T, R0, R1, R2, NT};          \
+        *out = Variant{T, R0, R1, R2, NT, W};       \
         return true;                                \
     }
     BEC_FFT_VARIANTS(BEC_FIND)
@@ -770,7 +811,7 @@ int fft_max_blocks(int L, long long npencil)
 hipError_t fft_trial_z_pass(int L, int variant, const FftPassArgs& A, const TrialZArgs& Z, hipStream_t st)
 {
     if (A.S != 1) return hipErrorInvalidValue;
-#define BEC_TCASE(LL, VV, T, R0, R1, R2, NT)                                                            \
+#define BEC_TCASE(LL, VV, T, R0, R1, R2, NT, W)                                                          \
     if (L == LL && variant == VV) {                                                                      \
         const dim3 grid((unsigned)((A.npencil + NT / T - 1) / (NT / T)));                                \
         hipLaunchKernelGGL((fft_trial_z_kernel<LL, T, R0, R1, R2, NT>), grid, dim3(NT), 0, st, A, Z);    \
@@ -784,7 +825,7 @@ hipError_t fft_trial_z_pass(int L, int variant, const FftPassArgs& A, const Tria
 hipError_t fft_btrial_z_pass(int L, int variant, const FftPassArgs& A, const BGroup& g, hipStream_t st)
 {
     if (A.S != 1) return hipErrorInvalidValue;
-#define BEC_BCASE(LL, VV, T, R0, R1, R2, NT)                                                             \
+#define BEC_BCASE(LL, VV, T, R0, R1, R2, NT, W)                                                           \
     if (L == LL && variant == VV) {                                                                       \
         const dim3 grid((unsigned)((A.npencil + NT / T - 1) / (NT / T)), 1u, (unsigned)g.n_ids);          \
         hipLaunchKernelGGL((fft_btrial_z_kernel<LL, T, R0, R1, R2, NT>), grid, dim3(NT), 0, st, A, g);    \
@@ -799,7 +840,7 @@ hipError_t fft_zinv_ls_pass(int L, int variant, const FftPassArgs& A, const doub
                             hipStream_t st)
 {
     if (A.S != 1) return hipErrorInvalidValue;
-#define BEC_LCASE(LL, VV, T, R0, R1, R2, NT)                                                                 \
+#define BEC_LCASE(LL, VV, T, R0, R1, R2, NT, W)                                                               \
     if (L == LL && variant == VV) {                                                                           \
         const dim3 grid((unsigned)((A.npencil + NT / T - 1) / (NT / T)));                                     \
         hipLaunchKernelGGL((fft_zinv_ls_kernel<LL, T, R0, R1, R2, NT>), grid, dim3(NT), 0, st, A, rho, partials); \
@@ -812,8 +853,8 @@ hipError_t fft_zinv_ls_pass(int L, int variant, const FftPassArgs& A, const doub
 
 hipError_t fft_pass(int L, int variant, bool contiguous, const FftPassArgs& A, hipStream_t st)
 {
-#define BEC_CASE(LL, VV, T, R0, R1, R2, NT) \
-    if (L == LL && variant == VV) return launch_cfg<LL, T, R0, R1, R2, NT>(contiguous, A, st);
+#define BEC_CASE(LL, VV, T, R0, R1, R2, NT, W) \
+    if (L == LL && variant == VV) return launch_cfg<LL, T, R0, R1, R2, NT, (W) != 0>(contiguous, A, st);
     BEC_FFT_VARIANTS(BEC_CASE)
 #undef BEC_CASE
     return hipErrorInvalidValue;

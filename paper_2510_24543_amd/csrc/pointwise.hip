@@ -178,195 +178,246 @@ __device__ __forceinline__ double pv_inv(const PwParams& P, int c, double shift,
     return 1.0 / ((g > 0.0 ? g : 0.0) + sigma);
 }
 
-__device__ __forceinline__ RZ resid_precond(const PwParams& P, const DirArgs& A, long long i,
-                                            double2 s1, double2 s2)
+#ifndef BEC_DIR_WRITE_UNROLL
+#define BEC_DIR_WRITE_UNROLL 1
+#endif
+constexpr int kDirWriteUnroll = BEC_DIR_WRITE_UNROLL;   // points per thread and trip of the direction-write pass
+
+// Operands of the direction-reduce pass at one point.  ZM is the
+// preconditioner mode (DirArgs::zmode), PREV whether the previous residual and
+// direction enter (DirArgs::have_prev).
+template <int ZM, bool PREV>
+struct RedIn {
+    double2 s[2], h[2], ml, zb[2], ro[2], po[2];
+};
+
+template <int ZM, bool PREV>
+__device__ __forceinline__ RedIn<ZM, PREV> red_load(const DirArgs& A, long long N, long long i)
 {
-    const long long N = P.N;
+    RedIn<ZM, PREV> v;
+    v.s[0] = A.psi[i];
+    v.s[1] = A.psi[N + i];
+    v.h[0] = A.hpsi[i];
+    v.h[1] = A.hpsi[N + i];
+    if constexpr (ZM == 1 || ZM == 3 || ZM == 4) v.ml = A.aux[N + i];
+    if constexpr (ZM >= 2 && ZM <= 4) {
+        v.zb[0] = A.zbuf[i];
+        v.zb[1] = A.zbuf[N + i];
+    }
+    if constexpr (PREV) {
+        v.ro[0] = A.r_old[i];
+        v.ro[1] = A.r_old[N + i];
+        v.po[0] = A.p[i];
+        v.po[1] = A.p[N + i];
+    }
+    return v;
+}
+
+// residual r = H psi - mu psi and z = P^-1 r at one point (zmode ZM)
+template <int ZM, bool PREV>
+__device__ __forceinline__ RZ red_rz(const PwParams& P, const DirArgs& A, long long i, const RedIn<ZM, PREV>& v)
+{
     RZ o;
-    const double2 h1 = A.hpsi[i], h2 = A.hpsi[N + i];
-    o.r[0] = make_double2(h1.x - A.mu[0] * s1.x, h1.y - A.mu[0] * s1.y);
-    o.r[1] = make_double2(h2.x - A.mu[1] * s2.x, h2.y - A.mu[1] * s2.y);
-    if (A.zmode == 1) {
-        const double n1 = sq2(s1), n2 = sq2(s2);
-        const double V = trap_at(P, i);
-        const double2 ml = A.aux[N + i];
-        double g1 = A.diag_shift[0] + V + P.G[0][0] * n1 + P.G[0][1] * n2 + ml.x;
-        double g2 = A.diag_shift[1] + V + P.G[1][0] * n1 + P.G[1][1] * n2 + ml.y;
-        g1 = 1.0 / ((g1 > 0.0 ? g1 : 0.0) + A.sigma);
-        g2 = 1.0 / ((g2 > 0.0 ? g2 : 0.0) + A.sigma);
-        o.z[0] = make_double2(g1 * o.r[0].x, g1 * o.r[0].y);
-        o.z[1] = make_double2(g2 * o.r[1].x, g2 * o.r[1].y);
-    } else if (A.zmode == 2) {
-        o.z[0] = A.zbuf[i];
-        o.z[1] = A.zbuf[N + i];
-    } else if (A.zmode == 3) {
-        const double n1 = sq2(s1), n2 = sq2(s2);
-        const double V = trap_at(P, i);
-        const double2 ml = A.aux[N + i];
-        const double q1 = sqrt(pv_inv(P, 0, A.diag_shift[0], A.sigma, V, n1, n2, ml.x));
-        const double q2 = sqrt(pv_inv(P, 1, A.diag_shift[1], A.sigma, V, n1, n2, ml.y));
-        const double2 w1 = A.zbuf[i], w2 = A.zbuf[N + i];
-        o.z[0] = make_double2(q1 * w1.x, q1 * w1.y);
-        o.z[1] = make_double2(q2 * w2.x, q2 * w2.y);
-    } else if (A.zmode == 4) {
-        const double n1 = sq2(s1), n2 = sq2(s2);
-        const double V = trap_at(P, i);
-        const double2 ml = A.aux[N + i];
-        const double g[2] = {pv_inv(P, 0, A.diag_shift[0], A.sigma, V, n1, n2, ml.x),
-                             pv_inv(P, 1, A.diag_shift[1], A.sigma, V, n1, n2, ml.y)};
-        const double2 zk[2] = {A.zbuf[i], A.zbuf[N + i]};
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const double a = A.blend_w[c] * g[c], b = 1.0 - A.blend_w[c];
-            o.z[c] = make_double2(a * o.r[c].x + b * zk[c].x, a * o.r[c].y + b * zk[c].y);
-        }
-    } else {
+    for (int c = 0; c < 2; ++c)
+        o.r[c] = make_double2(v.h[c].x - A.mu[c] * v.s[c].x, v.h[c].y - A.mu[c] * v.s[c].y);
+    if constexpr (ZM == 0) {
         o.z[0] = o.r[0];
         o.z[1] = o.r[1];
+    } else if constexpr (ZM == 2) {
+        o.z[0] = v.zb[0];
+        o.z[1] = v.zb[1];
+    } else {
+        const double n1 = sq2(v.s[0]), n2 = sq2(v.s[1]);
+        const double V = trap_at(P, i);
+        const double mlc[2] = {v.ml.x, v.ml.y};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const double g = pv_inv(P, c, A.diag_shift[c], A.sigma, V, n1, n2, mlc[c]);
+            if constexpr (ZM == 1) {
+                o.z[c] = make_double2(g * o.r[c].x, g * o.r[c].y);
+            } else if constexpr (ZM == 3) {
+                const double q = sqrt(g);
+                o.z[c] = make_double2(q * v.zb[c].x, q * v.zb[c].y);
+            } else {
+                const double a = A.blend_w[c] * g, b = 1.0 - A.blend_w[c];
+                o.z[c] = make_double2(a * o.r[c].x + b * v.zb[c].x, a * o.r[c].y + b * v.zb[c].y);
+            }
+        }
     }
     return o;
 }
 
+// Direction-reduce pass: the sums of kDirReduceSums.  Two points per thread and
+// trip, their operands loaded before either is used; each thread adds its points
+// in grid-stride order.
+template <int ZM, bool PREV>
 __global__ __launch_bounds__(kPwThreads) void dir_reduce_kernel(PwParams P, DirArgs A)
 {
     if (A.dev_state) {
         rule_mu_shift(A.dev_state, P.Gdd, A.mu, A.diag_shift);
-        if (A.zmode == 4) rule_blend(A.dev_state, A.diag_shift, A.blend, A.blend_w);
+        if (ZM == 4) rule_blend(A.dev_state, A.diag_shift, A.blend, A.blend_w);
     }
     const long long N = P.N;
+    const long long stride = (long long)gridDim.x * kPwThreads;
     double acc[kDirReduceSums];
 #pragma unroll
     for (int m = 0; m < kDirReduceSums; ++m) acc[m] = 0.0;
-    GRID_STRIDE(i, N)
-    {
-        const double2 s[2] = {A.psi[i], A.psi[N + i]};
-        const RZ q = resid_precond(P, A, i, s[0], s[1]);
+    for (long long i = (long long)blockIdx.x * kPwThreads + threadIdx.x; i < N; i += 2 * stride) {
+        const long long i2 = i + stride < N ? i + stride : i;
+        const RedIn<ZM, PREV> in[2] = {red_load<ZM, PREV>(A, N, i), red_load<ZM, PREV>(A, N, i2)};
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            acc[6 * c + 0] += sq2(q.r[c]);
-            acc[6 * c + 3] += redot(q.z[c], s[c]);
-            acc[6 * c + 5] += redot(q.r[c], q.z[c]);
-            if (A.have_prev) {
-                const double2 ro = A.r_old[c * N + i], po = A.p[c * N + i];
-                const double2 y = make_double2(q.r[c].x - ro.x, q.r[c].y - ro.y);
-                acc[6 * c + 1] += redot(y, q.z[c]);
-                acc[6 * c + 2] += redot(y, po);
-                acc[6 * c + 4] += redot(po, s[c]);
+        for (int u = 0; u < 2; ++u) {
+            if (u == 1 && i2 == i) break;
+            const long long k = u ? i2 : i;
+            const RZ q = red_rz<ZM, PREV>(P, A, k, in[u]);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const double2 s = in[u].s[c];
+                acc[6 * c + 0] += sq2(q.r[c]);
+                acc[6 * c + 3] += redot(q.z[c], s);
+                acc[6 * c + 5] += redot(q.r[c], q.z[c]);
+                if constexpr (PREV) {
+                    const double2 ro = in[u].ro[c], po = in[u].po[c];
+                    const double2 y = make_double2(q.r[c].x - ro.x, q.r[c].y - ro.y);
+                    acc[6 * c + 1] += redot(y, q.z[c]);
+                    acc[6 * c + 2] += redot(y, po);
+                    acc[6 * c + 4] += redot(po, s);
+                }
             }
         }
     }
     block_reduce_store<kDirReduceSums>(acc, A.partials, gridDim.x);
 }
 
+// Operands of the direction-write pass at one point (ZM = DirArgs::zmode).
+template <int ZM>
 struct DirIn {
     double2 s[2], h[2], ph, ml, po[2], zb[2];
 };
 
-__device__ __forceinline__ DirIn dir_load(const DirArgs& A, long long N, long long i)
+template <int ZM>
+__device__ __forceinline__ DirIn<ZM> dir_load(const DirArgs& A, long long N, long long i, bool with_p)
 {
-    DirIn v;
+    DirIn<ZM> v;
     v.s[0] = A.psi[i];
     v.s[1] = A.psi[N + i];
     v.h[0] = A.hpsi[i];
     v.h[1] = A.hpsi[N + i];
     v.ph = A.aux[i];
     v.ml = A.aux[N + i];
-    if (A.beta != 0.0) {
+    if (with_p) {
         v.po[0] = A.p[i];
         v.po[1] = A.p[N + i];
     } else {
         v.po[0] = v.po[1] = make_double2(0.0, 0.0);
     }
-    if (A.zmode >= 2) {
+    if constexpr (ZM >= 2 && ZM <= 4) {
         v.zb[0] = A.zbuf[i];
         v.zb[1] = A.zbuf[N + i];
-    } else {
-        v.zb[0] = v.zb[1] = make_double2(0.0, 0.0);
     }
     return v;
 }
 
-// Direction write pass with the LHY part of the line-search model.
+// One point of the direction-write pass: z, the new direction p (stored with r
+// and rho = Re conj(psi) p) and the line-search model sums.
+template <int ZM, bool LHY>
+__device__ __forceinline__ void dir_point(const PwParams& P, const DirArgs& A, long long N, long long i,
+                                         const DirIn<ZM>& cur, double* acc)
+{
+    const double2* s = cur.s;
+    double2 r[2], z[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) r[c] = make_double2(cur.h[c].x - A.mu[c] * s[c].x, cur.h[c].y - A.mu[c] * s[c].y);
+    const double n[2] = {sq2(s[0]), sq2(s[1])};
+    const double V = trap_at(P, i);
+    const double mlc[2] = {cur.ml.x, cur.ml.y};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        if constexpr (ZM == 0) {
+            z[c] = r[c];
+        } else if constexpr (ZM == 2) {
+            z[c] = cur.zb[c];
+        } else {
+            const double g = pv_inv(P, c, A.diag_shift[c], A.sigma, V, n[0], n[1], mlc[c]);
+            if constexpr (ZM == 1) {
+                z[c] = make_double2(g * r[c].x, g * r[c].y);
+            } else if constexpr (ZM == 3) {
+                const double q = sqrt(g);
+                z[c] = make_double2(q * cur.zb[c].x, q * cur.zb[c].y);
+            } else {
+                const double a = A.blend_w[c] * g, b = 1.0 - A.blend_w[c];
+                z[c] = make_double2(a * r[c].x + b * cur.zb[c].x, a * r[c].y + b * cur.zb[c].y);
+            }
+        }
+    }
+    const double2 ph = cur.ph;
+    double2 p[2];
+    double rho[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        double2 d = make_double2(A.zsign * z[c].x, A.zsign * z[c].y);
+        if (A.beta != 0.0) {
+            d.x += A.beta * cur.po[c].x;
+            d.y += A.beta * cur.po[c].y;
+        }
+        p[c] = make_double2(d.x - A.c[c] * s[c].x, d.y - A.c[c] * s[c].y);
+        A.p_out[c * N + i] = p[c];
+        A.r_out[c * N + i] = r[c];
+        rho[c] = redot(s[c], p[c]);
+        const double2 hmf = make_double2(cur.h[c].x - mlc[c] * s[c].x, cur.h[c].y - mlc[c] * s[c].y);
+        const double U = V + P.G[c][0] * n[0] + P.G[c][1] * n[1] + P.Gdd[c][0] * ph.x + P.Gdd[c][1] * ph.y;
+        const double pp = sq2(p[c]);
+        acc[0 + c] += pp;
+        acc[2 + c] += redot(p[c], r[c]);
+        acc[4 + c] += redot(p[c], hmf);
+        acc[6 + c] += redot(s[c], hmf);
+        acc[8 + c] += U * pp;
+        acc[10 + c] += mlc[c] * pp;
+        acc[12 + c] += mlc[c] * n[c];
+        acc[16 + c] += rho[c];
+    }
+    A.rho[i] = make_double2(rho[0], rho[1]);
+    if constexpr (LHY) {
+        double L1, L2;
+        lhy_model(KernargNodes{P}, LhyTab{P.lhy_tab, P.lhy_K}, P.n_a, P.n_b, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
+        acc[14] += L1;
+        acc[15] += L2;
+    }
+}
+
+// Direction write pass with the LHY part of the line-search model.  UNR points
+// per thread and trip, their operands loaded before the first is used; each
+// thread handles its points in grid-stride order.
+template <int ZM, bool LHY, int UNR>
 __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirArgs A)
 {
     if (A.dev_state) {
         rule_mu_shift(A.dev_state, P.Gdd, A.mu, A.diag_shift);
-        if (A.zmode == 4) rule_blend(A.dev_state, A.diag_shift, A.blend, A.blend_w);
+        if (ZM == 4) rule_blend(A.dev_state, A.diag_shift, A.blend, A.blend_w);
     }
     if (A.dev_dir) {
         A.beta = rule_beta(A.dev_dir, A.rule);
         rule_proj(A.dev_dir, A.beta, A.rule.dV, A.c);
     }
+    const bool with_p = A.beta != 0.0;
     const long long N = P.N;
     const long long stride = (long long)gridDim.x * kPwThreads;
     double acc[kDirWriteSums];
 #pragma unroll
     for (int m = 0; m < kDirWriteSums; ++m) acc[m] = 0.0;
-    long long i = (long long)blockIdx.x * kPwThreads + threadIdx.x;
-    for (; i < N; i += stride) {
-        const DirIn cur = dir_load(A, N, i);
-        const double2* s = cur.s;
-        double2 r[2], z[2];
-        for (int c = 0; c < 2; ++c) r[c] = make_double2(cur.h[c].x - A.mu[c] * s[c].x, cur.h[c].y - A.mu[c] * s[c].y);
-        const double n[2] = {sq2(s[0]), sq2(s[1])};
-        const double V = trap_at(P, i);
-        const double mlc[2] = {cur.ml.x, cur.ml.y};
-        if (A.zmode == 1) {
-            for (int c = 0; c < 2; ++c) {
-                double g = A.diag_shift[c] + V + P.G[c][0] * n[0] + P.G[c][1] * n[1] + mlc[c];
-                g = 1.0 / ((g > 0.0 ? g : 0.0) + A.sigma);
-                z[c] = make_double2(g * r[c].x, g * r[c].y);
-            }
-        } else if (A.zmode == 2) {
-            z[0] = cur.zb[0];
-            z[1] = cur.zb[1];
-        } else if (A.zmode == 3) {
-            for (int c = 0; c < 2; ++c) {
-                const double q = sqrt(pv_inv(P, c, A.diag_shift[c], A.sigma, V, n[0], n[1], mlc[c]));
-                z[c] = make_double2(q * cur.zb[c].x, q * cur.zb[c].y);
-            }
-        } else if (A.zmode == 4) {
-            for (int c = 0; c < 2; ++c) {
-                const double a = A.blend_w[c] * pv_inv(P, c, A.diag_shift[c], A.sigma, V, n[0], n[1], mlc[c]);
-                const double b = 1.0 - A.blend_w[c];
-                z[c] = make_double2(a * r[c].x + b * cur.zb[c].x, a * r[c].y + b * cur.zb[c].y);
-            }
-        } else {
-            z[0] = r[0];
-            z[1] = r[1];
-        }
-        const double2 ph = cur.ph;
-        double2 p[2];
-        double rho[2];
+    for (long long i = (long long)blockIdx.x * kPwThreads + threadIdx.x; i < N; i += UNR * stride) {
+        long long k[UNR];
+        DirIn<ZM> cur[UNR];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            double2 d = make_double2(A.zsign * z[c].x, A.zsign * z[c].y);
-            if (A.beta != 0.0) {
-                d.x += A.beta * cur.po[c].x;
-                d.y += A.beta * cur.po[c].y;
-            }
-            p[c] = make_double2(d.x - A.c[c] * s[c].x, d.y - A.c[c] * s[c].y);
-            A.p_out[c * N + i] = p[c];
-            A.r_out[c * N + i] = r[c];
-            rho[c] = redot(s[c], p[c]);
-            const double2 hmf = make_double2(cur.h[c].x - mlc[c] * s[c].x, cur.h[c].y - mlc[c] * s[c].y);
-            const double U = V + P.G[c][0] * n[0] + P.G[c][1] * n[1] + P.Gdd[c][0] * ph.x + P.Gdd[c][1] * ph.y;
-            const double pp = sq2(p[c]);
-            acc[0 + c] += pp;
-            acc[2 + c] += redot(p[c], r[c]);
-            acc[4 + c] += redot(p[c], hmf);
-            acc[6 + c] += redot(s[c], hmf);
-            acc[8 + c] += U * pp;
-            acc[10 + c] += mlc[c] * pp;
-            acc[12 + c] += mlc[c] * n[c];
-            acc[16 + c] += rho[c];
+        for (int u = 0; u < UNR; ++u) {
+            k[u] = i + u * stride < N ? i + u * stride : i;
+            cur[u] = dir_load<ZM>(A, N, k[u], with_p);
         }
-        A.rho[i] = make_double2(rho[0], rho[1]);
-        if (P.lhy_on) {
-            double L1, L2;
-            lhy_model(KernargNodes{P}, LhyTab{P.lhy_tab, P.lhy_K}, P.n_a, P.n_b, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
-            acc[14] += L1;
-            acc[15] += L2;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            if (u > 0 && k[u] == i) break;
+            dir_point<ZM, LHY>(P, A, N, k[u], cur[u], acc);
         }
     }
     block_reduce_store<kDirWriteSums>(acc, A.partials, gridDim.x);
@@ -627,13 +678,31 @@ hipError_t launch_heval_epi(const PwParams& P, const HevalArgs& a, int nblk, hip
 
 hipError_t launch_dir_reduce(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s)
 {
-    hipLaunchKernelGGL(dir_reduce_kernel, dim3(nblk), dim3(kPwThreads), 0, s, P, a);
+#define BEC_RED(ZM)                                                                              \
+    case ZM:                                                                                     \
+        if (a.have_prev) hipLaunchKernelGGL((dir_reduce_kernel<ZM, true>), dim3(nblk), dim3(kPwThreads), 0, s, P, a); \
+        else hipLaunchKernelGGL((dir_reduce_kernel<ZM, false>), dim3(nblk), dim3(kPwThreads), 0, s, P, a);    \
+        break;
+    switch (a.zmode) {
+        BEC_RED(0) BEC_RED(1) BEC_RED(2) BEC_RED(3) BEC_RED(4)
+        default: return hipErrorInvalidValue;
+    }
+#undef BEC_RED
     return hipGetLastError();
 }
 
 hipError_t launch_dir_write(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s)
 {
-    hipLaunchKernelGGL(dir_write_kernel, dim3(nblk), dim3(kPwThreads), 0, s, P, a);
+#define BEC_DW(ZM)                                                                                          \
+    case ZM:                                                                                                \
+        if (P.lhy_on) hipLaunchKernelGGL((dir_write_kernel<ZM, true, kDirWriteUnroll>), dim3(nblk), dim3(kPwThreads), 0, s, P, a); \
+        else hipLaunchKernelGGL((dir_write_kernel<ZM, false, kDirWriteUnroll>), dim3(nblk), dim3(kPwThreads), 0, s, P, a);       \
+        break;
+    switch (a.zmode) {
+        BEC_DW(0) BEC_DW(1) BEC_DW(2) BEC_DW(3) BEC_DW(4)
+        default: return hipErrorInvalidValue;
+    }
+#undef BEC_DW
     return hipGetLastError();
 }
 
