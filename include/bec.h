@@ -306,11 +306,15 @@ bec_status bec_param_grad(bec_ctx* ctx, const double* psi, double dG[2][2], doub
  * the same grid shape are processed together by every kernel launch) solved by
  * the same preconditioned CG as bec_solve, with the scalar decisions taken on
  * the device so that a round of the iteration needs no host synchronisation.
- * Supported preconditioners: BEC_PC_NONE and BEC_PC_V.
+ * Every preconditioner of bec_opts.pc (Sec. IV.B, Eqs. (14)-(18)); the
+ * k-space ones (BEC_PC_KIN, _COMPOSITE, _SYMMETRIC, _BLEND) transform the
+ * residual of the instances that start a direction in one batched FFT pass
+ * set per round, each instance with its own P_V shift, and the composite
+ * family keeps the fallback z = P_V^-1 r, then z = r, of bec_solve.
  * ------------------------------------------------------------------------- */
 typedef struct bec_batch bec_batch;
 
-/* Device workspace for n_inst instances (grids[i], params[i]); about 330 bytes
+/* Device workspace for n_inst instances (grids[i], params[i]); about 360 bytes
  * per grid point summed over the instances, plus per-instance tables. */
 bec_status bec_batch_workspace_size(int32_t n_inst, const bec_grid* grids, const bec_params* params,
                                     size_t* bytes);
@@ -323,7 +327,8 @@ bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_par
 bec_status bec_batch_destroy(bec_batch* b);
 
 
-/* Solve every instance.  psi_inout: host array of n_inst device pointers, each
+/* Solve every instance.  opts->pc outside 0..5, or a blend weight above 1 with
+ * BEC_PC_BLEND, is BEC_EINVAL.  psi_inout: host array of n_inst device pointers, each
  * an initial state of its instance's grid (normalised on entry) that receives
  * the final state.  rounds_per_sync: iteration rounds enqueued between two
  * host checks of the instance states (0: 16).  use_graph: capture those rounds

@@ -2142,7 +2142,7 @@ struct BatchGroup {
     int nblk_pz = 0, nblk_py = 0;  // blocks of the z and y passes (Parseval axis sums of the line search)
     int var[3] = {0, 0, 0};        // FFT plan variant per axis (the x pass is always the k-space pass)
     double2 *psi = nullptr, *hpsi = nullptr, *aux = nullptr, *p = nullptr, *r_old = nullptr, *rho = nullptr,
-            *W = nullptr;
+            *W = nullptr, *zbuf = nullptr;
     double *partials = nullptr, *fft_partials = nullptr, *udtab = nullptr, *kv[3] = {}, *vv[3] = {};
     double2* tw[3] = {};
     long long udsize = 0;
@@ -2246,7 +2246,7 @@ size_t batch_layout(int n_inst, const bec_grid* grids, std::vector<size_t>* off)
     sizes.push_back(n_inst * sizeof(bec::BInstParams));
     sizes.push_back(n_inst * sizeof(bec::BInstState));
     sizes.push_back((size_t)n_inst * bec::kBSumStride * sizeof(double));
-    sizes.push_back(3 * (size_t)n_inst * sizeof(int));          // act_dir, act_trial, tsel
+    sizes.push_back(4 * (size_t)n_inst * sizeof(int));          // act_dir, act_trial, tsel, act_pre
     sizes.push_back(n_inst * sizeof(double*));                  // user pointers
     const size_t c2 = sizeof(double2);
     for (auto& r : ranges) {
@@ -2261,6 +2261,7 @@ size_t batch_layout(int n_inst, const bec_grid* grids, std::vector<size_t>* off)
         size_t gs[] = {cnt * 4 * N * c2, cnt * 4 * N * c2, cnt * 4 * N * c2,  // psi, hpsi, aux (2 buffers)
                        cnt * 2 * N * c2, cnt * 2 * N * c2, cnt * N * c2,      // p, r_old, rho
                        cnt * 3 * N * c2,                                      // W
+                       cnt * 2 * N * c2,                                      // zbuf
                        (size_t)cnt * bec::kMaxSums * nblk * sizeof(double),   // partials
                        (size_t)cnt * 3 * (nbx + nby + nbz) * sizeof(double),  // fft partials
                        cnt * ud * sizeof(double),                             // dipolar tables
@@ -2292,7 +2293,7 @@ struct bec_batch {
     bec::BInstParams* ip = nullptr;
     bec::BInstState* state = nullptr;
     double* sums = nullptr;
-    int *act_dir = nullptr, *act_trial = nullptr, *tsel = nullptr;
+    int *act_dir = nullptr, *act_trial = nullptr, *tsel = nullptr, *act_pre = nullptr;
     double** psi_user = nullptr;
     bec::BInstState* host_state = nullptr;   // pinned
     double** host_ptrs = nullptr;            // pinned
@@ -2441,9 +2442,42 @@ bec_status batch_trial_and_accept(bec_batch* b, const bec::BOpts& o)
     return BEC_OK;
 }
 
+// z of the k-space preconditioners (zmode >= 2) for the instances in act_pre:
+// make_r writes r, P_V^-1 r or D^-1/2 r to zbuf, then the z, y, x (multiply by
+// 1/([shift_i]_+ + sigma + |k|^2/2), each instance its own shift), y and z passes
+// transform it in place
+bec_status batch_precond_fft(bec_batch* b, const BatchGroup& G)
+{
+    HIPCHK(bec::launch_b_make_r(G.g, b->st));
+    const long long N = G.N;
+    const int axes[5] = {2, 1, 0, 1, 2};
+    const int signs[5] = {-1, -1, -1, +1, +1};
+    for (int k = 0; k < 5; ++k) {
+        FftPassArgs A = batch_pass_args(G, axes[k], b->act_pre);
+        for (int f = 0; f < 2; ++f) {
+            A.src[f] = A.dst[f] = G.zbuf + f * N;
+            A.src_stride[f] = A.dst_stride[f] = 2 * N;
+        }
+        if (axes[k] == 0) {
+            A.op[0] = A.op[1] = bec::kOpMulPrec;
+            A.prec_bst = b->state + G.first;
+            A.prec_sigma = G.g.sigma;
+        }
+        STCHK(bpass(b, G, A, axes[k], 2, signs[k]));
+    }
+    return BEC_OK;
+}
+
 // one round of the iteration for every instance (no host synchronisation)
 bec_status batch_round(bec_batch* b, const bec::BOpts& o)
 {
+    bool kspace = false;
+    for (auto& G : b->groups) kspace = kspace || (G.g.n_ids > 0 && G.g.zmode >= 2);
+    if (kspace) {
+        HIPCHK(bec::launch_b_mark_pre(b->n_inst, b->state, b->act_pre, b->st));
+        for (auto& G : b->groups)
+            if (G.g.n_ids > 0) STCHK(batch_precond_fft(b, G));
+    }
     for (auto& G : b->groups) {
         if (G.g.n_ids == 0) continue;
         HIPCHK(bec::launch_b_dir_reduce(G.g, b->st));
@@ -2480,6 +2514,8 @@ bec::BOpts to_bopts(const bec_opts* o)
     b.armijo_c1 = o->armijo_c1;
     b.theta_max = o->theta_max;
     b.tau_rel = o->tau_rel;
+    b.pc = o->pc;
+    b.blend = o->blend;
     return b;
 }
 
@@ -2522,6 +2558,7 @@ bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_par
         b->act_dir = (int*)(base + off[k++]);
         b->act_trial = b->act_dir + n_inst;
         b->tsel = b->act_dir + 2 * n_inst;
+        b->act_pre = b->act_dir + 3 * n_inst;
         b->psi_user = (double**)(base + off[k++]);
         auto cleanup = [&](bec_status s) {
             if (b->host_state) (void)hipHostFree(b->host_state);
@@ -2558,6 +2595,7 @@ bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_par
             G.r_old = (double2*)(base + off[k++]);
             G.rho = (double2*)(base + off[k++]);
             G.W = (double2*)(base + off[k++]);
+            G.zbuf = (double2*)(base + off[k++]);
             G.partials = (double*)(base + off[k++]);
             G.fft_partials = (double*)(base + off[k++]);
             G.udtab = (double*)(base + off[k++]);
@@ -2628,6 +2666,8 @@ bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_par
             g.r_old = G.r_old;
             g.rho = G.rho;
             g.W = G.W;
+            g.zbuf = G.zbuf;
+            g.act_pre = b->act_pre;
             g.partials = G.partials;
             g.ids = G.ids_all;
             g.n_ids = G.count;
@@ -2680,15 +2720,21 @@ bec_status bec_batch_solve(bec_batch* b, double* const* psi_inout, const bec_opt
                            int32_t use_graph, bec_report* reports_h)
 {
     if (!b || !psi_inout || !o || !reports_h) return fail(BEC_EINVAL, "null argument");
-    if (o->pc != BEC_PC_NONE && o->pc != BEC_PC_V)
-        return fail(BEC_EUNSUPPORTED, "the batched solver supports the identity and P_V preconditioners");
+    if (o->pc < BEC_PC_NONE || o->pc > BEC_PC_BLEND) return fail(BEC_EINVAL, "bad preconditioner %d", o->pc);
+    if (o->pc == BEC_PC_BLEND && !(o->blend <= 1.0)) return fail(BEC_EINVAL, "blend weight must be <= 1");
     if (o->beta < 0 || o->beta > 2) return fail(BEC_EINVAL, "bad beta mode");
     const auto t0 = std::chrono::steady_clock::now();
     const int K = rounds_per_sync > 0 ? rounds_per_sync : 16;
     const bec::BOpts bo = to_bopts(o);
+    // z per preconditioner: P_Delta and the composite read P_Delta^-1 of the
+    // make_r output (r, P_V^-1 r); the symmetrised composite scales it by D^-1/2;
+    // the blend mixes P_V^-1 r into it
+    static const int zmode_of[6] = {0, 1, 2, 2, 3, 4}, papply_of[6] = {0, 0, 0, 1, 2, 0};
     for (auto& G : b->groups) {
-        G.g.zmode = o->pc == BEC_PC_V ? 1 : 0;
+        G.g.zmode = zmode_of[o->pc];
+        G.g.papply = papply_of[o->pc];
         G.g.sigma = o->sigma;
+        G.g.blend = o->blend;
     }
     for (int i = 0; i < b->n_inst; ++i) {
         if (!psi_inout[b->perm[i]]) return fail(BEC_EINVAL, "psi_inout[%d] is null", b->perm[i]);

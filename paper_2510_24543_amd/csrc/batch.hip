@@ -8,6 +8,7 @@
 // apply to them (converged, backtracking, restarting), so the same kernel
 // sequence serves all instances and can be replayed from a graph.
 #include "bec_internal.h"
+#include "pcg_rules.h"
 #include "pw_math.h"
 
 namespace bec {
@@ -138,6 +139,16 @@ struct BRZ {
     double2 r[2], z[2];
 };
 
+// 1 / ([shift_c + V + sum_j G_cj n_j + muLHY_c]_+ + sigma): the inverse P_V diagonal
+__device__ __forceinline__ double b_pv_inv(const BInstParams& P, int c, double shift, double sigma, double V, double n1,
+                                           double n2, double ml)
+{
+    const double q = shift + V + P.G[c][0] * n1 + P.G[c][1] * n2 + ml;
+    return 1.0 / ((q > 0.0 ? q : 0.0) + sigma);
+}
+
+// residual r = H psi - mu psi and z at point i; z by the group's zmode, or by
+// the instance's fallback (S.zlevel 2: P_V^-1 r, 3: r)
 __device__ __forceinline__ BRZ b_resid(const BGroup& g, const BInstParams& P, const BInstState& S, int l,
                                        long long i, const double2* hpsi, const double2* aux, double2 s1, double2 s2)
 {
@@ -146,21 +157,87 @@ __device__ __forceinline__ BRZ b_resid(const BGroup& g, const BInstParams& P, co
     const double2 h1 = hpsi[i], h2 = hpsi[N + i];
     o.r[0] = make_double2(h1.x - S.mu[0] * s1.x, h1.y - S.mu[0] * s1.y);
     o.r[1] = make_double2(h2.x - S.mu[1] * s2.x, h2.y - S.mu[1] * s2.y);
-    if (g.zmode == 1) {
-        const double n1 = sq2(s1), n2 = sq2(s2);
-        const double V = btrap(g, l, i);
-        const double2 ml = aux[N + i];
-        double q1 = S.shift[0] + V + P.G[0][0] * n1 + P.G[0][1] * n2 + ml.x;
-        double q2 = S.shift[1] + V + P.G[1][0] * n1 + P.G[1][1] * n2 + ml.y;
-        q1 = 1.0 / ((q1 > 0.0 ? q1 : 0.0) + g.sigma);
-        q2 = 1.0 / ((q2 > 0.0 ? q2 : 0.0) + g.sigma);
-        o.z[0] = make_double2(q1 * o.r[0].x, q1 * o.r[0].y);
-        o.z[1] = make_double2(q2 * o.r[1].x, q2 * o.r[1].y);
-    } else {
+    const int zm = S.zlevel == 2 ? 1 : S.zlevel == 3 ? 0 : g.zmode;
+    if (zm == 0) {
         o.z[0] = o.r[0];
         o.z[1] = o.r[1];
+        return o;
+    }
+    const double2* zb = g.zbuf + (long long)l * 2 * N;
+    if (zm == 2) {
+        o.z[0] = zb[i];
+        o.z[1] = zb[N + i];
+        return o;
+    }
+    const double n1 = sq2(s1), n2 = sq2(s2);
+    const double V = btrap(g, l, i);
+    const double2 ml = aux[N + i];
+    const double q[2] = {b_pv_inv(P, 0, S.shift[0], g.sigma, V, n1, n2, ml.x),
+                         b_pv_inv(P, 1, S.shift[1], g.sigma, V, n1, n2, ml.y)};
+    double w[2] = {1.0, 1.0};
+    if (zm == 4) rule_blend(S.hsum, S.shift, g.blend, w);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        if (zm == 1) {
+            o.z[c] = make_double2(q[c] * o.r[c].x, q[c] * o.r[c].y);
+        } else if (zm == 3) {
+            const double sq = sqrt(q[c]);
+            const double2 v = zb[c * N + i];
+            o.z[c] = make_double2(sq * v.x, sq * v.y);
+        } else {
+            const double a = w[c] * q[c], b = 1.0 - w[c];
+            const double2 v = zb[c * N + i];
+            o.z[c] = make_double2(a * o.r[c].x + b * v.x, a * o.r[c].y + b * v.y);
+        }
     }
     return o;
+}
+
+// zbuf = r, P_V^-1 r or D^-1/2 r (g.papply) for the instances that compute a
+// new z this round; the k-space passes then apply P_Delta^-1 in place.
+__global__ __launch_bounds__(kPwThreads) void b_make_r_kernel(BGroup g)
+{
+    const int l = g.ids[blockIdx.y], inst = g.first + l;
+    if (!g.act_pre[inst]) return;
+    const BInstState& S = g.st[inst];
+    const BInstParams& P = g.ip[inst];
+    const long long N = g.N;
+    const double2* psi = g.psi + ((long long)l * 2 + S.cur) * 2 * N;
+    const double2* hpsi = g.hpsi + ((long long)l * 2 + S.cur) * 2 * N;
+    const double2* aux = g.aux + ((long long)l * 2 + S.cur) * 2 * N;
+    double2* out = g.zbuf + (long long)l * 2 * N;
+    BSTRIDE(i, N)
+    {
+        const double2 s[2] = {psi[i], psi[N + i]};
+        double2 r[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const double2 h = hpsi[c * N + i];
+            r[c] = make_double2(h.x - S.mu[c] * s[c].x, h.y - S.mu[c] * s[c].y);
+        }
+        if (g.papply != 0) {
+            const double n1 = sq2(s[0]), n2 = sq2(s[1]);
+            const double V = btrap(g, l, i);
+            const double2 ml = aux[N + i];
+            const double mlc[2] = {ml.x, ml.y};
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double q = b_pv_inv(P, c, S.shift[c], g.sigma, V, n1, n2, mlc[c]);
+                if (g.papply == 2) q = sqrt(q);
+                r[c] = make_double2(q * r[c].x, q * r[c].y);
+            }
+        }
+        out[i] = r[0];
+        out[N + i] = r[1];
+    }
+}
+
+__global__ void b_mark_pre_kernel(int n, const BInstState* st, int* act_pre)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const BInstState& S = st[i];
+    act_pre[i] = (S.status == kBRunning && S.phase == kBNewDir && S.zlevel == 0) ? 1 : 0;
 }
 
 __global__ __launch_bounds__(kPwThreads) void b_dir_reduce_kernel(BGroup g)
@@ -368,6 +445,7 @@ __global__ void b_decide_init_kernel(int n, const BInstParams* ip, BInstState* s
     S.cur = 0;
     S.iter = S.have_prev = S.level = S.path = S.nbt = S.n_restarts = S.n_backtracks = S.rounds = 0;
     S.stall_it = 0;
+    S.zlevel = 0;
     S.stall_ref = __builtin_inf();
     S.E_prev = __builtin_nan("");
     S.alpha_prev = S.rz_old = 0.0;
@@ -412,7 +490,10 @@ __global__ void b_decide_dir_kernel(int n, BOpts o, const BInstParams* ip, BInst
             return;
         }
         if (S.iter >= o.max_iter) { S.status = kBNotConv; return; }
-        const bool restart = !S.have_prev || o.beta_mode == 2 || (o.restart_period > 0 && S.iter % o.restart_period == 0);
+        // a fallback z (S.zlevel > 0) is a restart: beta = 0
+        const bool fallback = S.zlevel > 0;
+        const bool restart = fallback || !S.have_prev || o.beta_mode == 2 ||
+                             (o.restart_period > 0 && S.iter % o.restart_period == 0);
         double beta = 0.0;
         if (!restart) {
             double num = 0.0, den = 0.0;
@@ -424,8 +505,8 @@ __global__ void b_decide_dir_kernel(int n, BOpts o, const BInstParams* ip, BInst
             beta = (den > 0.0 && isfinite(den) && isfinite(num)) ? num / den : 0.0;
             if (beta < 0.0) beta = 0.0;
         }
-        S.level = beta > 0.0 ? 0 : 1;
-        S.path = 0;
+        S.level = fallback ? S.zlevel : (beta > 0.0 ? 0 : 1);
+        if (!fallback) S.path = 0;
         S.nbt = 0;
         for (int c = 0; c < 2; ++c) {
             S.zpsi[c] = R[6 * c + 3];
@@ -481,10 +562,19 @@ __global__ void b_decide_step_kernel(int n, BOpts o, const BInstParams* ip, BIns
         S.E1 = E1;
         S.E2 = E2;
         if (!(rp < 0.0 && isfinite(rp))) {
+            // not a descent direction: beta = 0; then, for the composite family
+            // (pc >= 3), z = P_V^-1 r and z = r, each with a new direction reduce
             if (S.level == 0) {
                 S.level = 1;
                 S.n_restarts++;
                 S.phase = kBRedo;
+            } else if (S.level == 1 && o.pc >= 3) {
+                S.zlevel = 2;
+                S.path |= 4;
+                S.phase = kBNewDir;
+            } else if (S.level == 2) {
+                S.zlevel = 3;
+                S.phase = kBNewDir;
             } else {
                 S.status = kBStagnated;
             }
@@ -551,6 +641,7 @@ __global__ void b_decide_accept_kernel(int n, BOpts o, const BInstParams* ip, BI
         S.cur = 1 - S.cur;
         S.phase = kBNewDir;
         S.nbt = 0;
+        S.zlevel = 0;
     } else if (S.nbt < o.max_backtrack) {
         S.phase = kBBacktrack;
     } else if (S.level == 0) {
@@ -583,6 +674,18 @@ hipError_t launch_b_dir_reduce(const BGroup& g, hipStream_t s)
     hipLaunchKernelGGL(b_dir_reduce_kernel, bgrid(g), dim3(kPwThreads), 0, s, g);
     return hipGetLastError();
 }
+hipError_t launch_b_mark_pre(int n_inst, const BInstState* st, int* act_pre, hipStream_t s)
+{
+    hipLaunchKernelGGL(b_mark_pre_kernel, dgrid(n_inst), dim3(64), 0, s, n_inst, st, act_pre);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_make_r(const BGroup& g, hipStream_t s)
+{
+    hipLaunchKernelGGL(b_make_r_kernel, bgrid(g), dim3(kPwThreads), 0, s, g);
+    return hipGetLastError();
+}
+
 hipError_t launch_b_dir_write(const BGroup& g, hipStream_t s)
 {
     hipLaunchKernelGGL(b_dir_write_kernel, bgrid(g), dim3(kPwThreads), 0, s, g);

@@ -93,6 +93,8 @@ enum FftOp : int {
     kOpKinAxis = 7
 };
 
+struct BInstState;
+
 struct FftPassArgs {
     const double2* src[3];
     double2* dst[3];
@@ -134,6 +136,9 @@ struct FftPassArgs {
     // shift_f = rule_mu_shift(prec_state, prec_Gdd) instead of prec_a[f]
     const double* prec_state;
     double prec_sigma;
+    // batched passes: when prec_bst is set, field f < 2 of instance l uses
+    // [prec_bst[l].shift_f]_+ + prec_sigma (the instance's P_V shift)
+    const BInstState* prec_bst;
     double prec_Gdd[2][2];
     // field of blockIdx.y in a fused pass: fields with an inverse transform
     // first, so that the blocks dispatched last are the light ones (set by the
@@ -348,6 +353,8 @@ enum : int { kBInit = 0, kBNewDir = 1, kBBacktrack = 2, kBRedo = 3 };
 
 struct BInstState {
     int status, phase, cur, iter, have_prev, level, path, nbt, n_restarts, n_backtracks, rounds, stall_it;
+    int zlevel;                   // 0: the configured z; 2: z = P_V^-1 r, 3: z = r (fallbacks of the composite family)
+    int pad;
     double E, E_prev, mu[2], shift[2], norm2[2], res[2];
     double stall_ref;             // reference residual of the stall rule (halved -> reset)
     double beta, c[2], zpsi[2], ppsi[2], rz[2], rz_old, rz_now, alpha, alpha_prev, E1, E2, rp;
@@ -356,8 +363,8 @@ struct BInstState {
 };
 
 struct BOpts {                    // the bec_opts fields the device decisions use
-    int beta_mode, max_iter, restart_period, max_backtrack, stall_window, pad;
-    double tol_grad, tol_dE, sigma, armijo_c1, theta_max, tau_rel;
+    int beta_mode, max_iter, restart_period, max_backtrack, stall_window, pc;
+    double tol_grad, tol_dE, sigma, armijo_c1, theta_max, tau_rel, blend;
 };
 
 struct BGroup {
@@ -369,8 +376,11 @@ struct BGroup {
     int s_nyz, s_nz;
     long long N;
     int nblk;                     // pointwise blocks per instance
-    int zmode;                    // 0 identity, 1 P_V
+    int zmode;                    // z: 0 r, 1 P_V^-1 r, 2 zbuf, 3 D^-1/2 zbuf, 4 w P_V^-1 r + (1 - w) zbuf
+    int papply;                   // make_r into zbuf: 0 r, 1 P_V^-1 r, 2 D^-1/2 r (D the P_V diagonal)
     double sigma;
+    double blend;                 // the blended mode's weight (< 0: adaptive)
+    const int* act_pre;           // [n_inst] instances whose z is computed this round
     const BInstParams* ip;        // [n_inst] (global index)
     BInstState* st;               // [n_inst]
     double* sums;                 // [n_inst][kBSumStride]
@@ -387,6 +397,7 @@ struct BGroup {
     double2* r_old;               // [count][2N]
     double2* rho;                 // [count][N]
     double2* W;                   // [count][3N]
+    double2* zbuf;                // [count][2N] P_Delta^-1 of the make_r output (zmode 2..4)
     double* partials;             // [count][kMaxSums][nblk]
 };
 
@@ -397,6 +408,10 @@ hipError_t fft_btrial_z_pass(int L, int variant, const FftPassArgs& args, const 
 hipError_t launch_b_norm2(const BGroup& g, hipStream_t s);
 hipError_t launch_b_heval_epi(const BGroup& g, hipStream_t s);
 hipError_t launch_b_dir_reduce(const BGroup& g, hipStream_t s);
+// act_pre[i] = 1 for the running instances that start a new direction with the configured z
+hipError_t launch_b_mark_pre(int n_inst, const BInstState* st, int* act_pre, hipStream_t s);
+// zbuf = the residual of the instances in act_pre, with the papply factor
+hipError_t launch_b_make_r(const BGroup& g, hipStream_t s);
 hipError_t launch_b_dir_write(const BGroup& g, hipStream_t s);
 hipError_t launch_b_ls_epi(const BGroup& g, hipStream_t s);
 hipError_t launch_b_copy_out(const BGroup& g, hipStream_t s);

@@ -421,6 +421,10 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
         rule_mu_shift(A.prec_state, A.prec_Gdd, mu, sh);
         pa = (sh[f] < 0.0 ? 0.0 : sh[f]) + A.prec_sigma;
     }
+    if (A.prec_bst && op == kOpMulPrec && f < 2) {     // batched: the instance's shift
+        const double sh = A.prec_bst[inst].shift[f];
+        pa = (sh < 0.0 ? 0.0 : sh) + A.prec_sigma;
+    }
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll

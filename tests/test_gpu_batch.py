@@ -140,11 +140,65 @@ def test_batch_reports_stagnation_forced_from_the_host(solver):
     assert reps[0]["n_backtracks"] == rs["n_backtracks"]
 
 
-def test_batch_rejects_kinetic_preconditioner(solver):
+KSPACE_PC = [(2, -1.0), (3, -1.0), (4, -1.0), (5, -1.0), (5, 0.5)]
+
+
+@pytest.mark.parametrize("pc,blend", KSPACE_PC, ids=["kin", "composite", "symmetric", "blend-adaptive", "blend-0.5"])
+def test_batch_kspace_preconditioners_match_oracle(solver, orc, pc, blend):
+    """P_Delta, the composite of Eq. (18), the symmetrised composite and the
+    blend (adaptive weight and w = 0.5) in the batched solver: three instances
+    on three grid shapes, five steps and the converged solve against the oracle."""
+    scan = small_scan(3)
+    grids, params, psi0 = [s[0] for s in scan], [s[1] for s in scan], [s[2] for s in scan]
+    b = solver.Batch(grids, params)
+    for max_iter, tol in ((5, 0.0), (3000, 1e-10)):
+        opts = {"tol_grad": tol, "max_iter": max_iter, "pc": pc, "blend": blend}
+        psis, reps = b.solve(psi0, opts, rounds_per_sync=4)
+        for k, (grid, prm, p0) in enumerate(scan):
+            print(f"pc {pc} blend {blend} max_iter {max_iter} grid {grid['n']}", flush=True)
+            psio, repo, _ = orc.solve(grid, prm, p0, opts)
+            rb = reps[k]
+            assert rb["status"] == repo["status"], (k, rb["status"], repo["status"])
+            if max_iter == 5:
+                assert rb["iters"] == repo["iters"] == 5
+                assert rb["n_restarts"] == repo["n_restarts"] and rb["n_backtracks"] == repo["n_backtracks"]
+                assert abs(rb["final"]["E"] - repo["final"]["E"]) <= 1e-11 * abs(repo["final"]["E"])
+                continue
+            assert abs(rb["final"]["E"] - repo["final"]["E"]) <= 1e-10 * abs(repo["final"]["E"])
+            assert abs(rb["iters"] - repo["iters"]) <= max(3, repo["iters"] // 20)
+            if repo["status"] == "OK":
+                assert max(rb["final"]["res"]) < 1e-10
+                assert np.max(np.abs(np.abs(psis[k].cpu().numpy()) ** 2 - np.abs(psio) ** 2)) < 1e-7
+
+
+def test_batch_composite_fallback_directions(solver, orc):
+    """sigma < 0 drives the composite direction uphill, so the batched solver
+    falls back to z = P_V^-1 r and z = r (a new direction reduce each) as the
+    oracle does: same iteration count and restarts over twelve steps, E to 1e-9
+    (the case is ill-conditioned by construction, see the plain solver's test)."""
+    grid = {"n": [16, 16, 16], "lo": [-6.0] * 3, "hi": [6.0] * 3}
+    params = {"N": [1.0, 1.6], "omega": [1.0, 1.2, 2.6], "G": [[100.0, 50.0], [31.25, 90.0]],
+              "Gdd": [[60.0, 45.0], [28.125, 50.0]], "c_lhy": 5.0, "r_cut": 6.0, "n_u": 16}
+    psi0 = inputs.initial_state(grid, params["omega"], 71, phase=False)
+    opts = {"tol_grad": 1e-10, "max_iter": 12, "pc": 3, "beta": 0, "sigma": -60.0}
+    _, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=12)
+    levels = [L["level"] for L in logo]
+    assert 2 in levels and 3 in levels
+    b = solver.Batch([grid], [params])
+    _, reps = b.solve([psi0], opts, rounds_per_sync=2)
+    rb = reps[0]
+    assert rb["iters"] == repo["iters"] == 12 and rb["status"] == repo["status"]
+    assert rb["n_restarts"] == repo["n_restarts"] and rb["n_backtracks"] == repo["n_backtracks"]
+    assert abs(rb["final"]["E"] - repo["final"]["E"]) <= 1e-9 * abs(repo["final"]["E"])
+
+
+def test_batch_rejects_bad_preconditioner_options(solver):
     grid, params, psi0 = small_scan(1)[0]
     b = solver.Batch([grid], [params])
-    with pytest.raises(solver.B.BecError, match="EUNSUPPORTED"):
-        b.solve([psi0], dict(OPTS, pc=2))
+    with pytest.raises(solver.B.BecError, match="EINVAL"):
+        b.solve([psi0], dict(OPTS, pc=6))
+    with pytest.raises(solver.B.BecError, match="EINVAL"):
+        b.solve([psi0], dict(OPTS, pc=5, blend=1.5))
 
 
 def test_batch_with_other_fft_plans_matches_default_plans(solver):
