@@ -42,8 +42,9 @@ WORKLOAD = "M"
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_128cubed.json")
 # library profiler labels -> kernel function names as rocprofv3 reports them
-LABEL_KERNEL = {"dir_write": "dir_write_kernel", "heval_epilogue": "heval_epi_kernel",
-                "dir_reduce": "dir_reduce_kernel", "trial_pack": "trial_kernel",
+# (the direction kernels as instantiated for P_V with LHY, the benchmark's configuration)
+LABEL_KERNEL = {"dir_write": "dir_write_kernel<1, true, 1>", "heval_epilogue": "heval_epi_kernel",
+                "dir_reduce": "dir_reduce_kernel<1, true>", "trial_pack": "trial_kernel",
                 "ls_epilogue": "ls_epi_kernel", "reduce_final": "reduce_final_kernel",
                 "scale2": "scale2_kernel", "norm2": "norm2_kernel"}
 # sources whose change invalidates the stored counter figures of the pointwise kernels
@@ -148,7 +149,7 @@ def pmc_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib, 
     fetch, write = _pmc_table(fetch_csv, "FETCH_SIZE"), _pmc_table(write_csv, "WRITE_SIZE")
     kernels = {}
     for full in sorted(set(fetch) & set(write)):
-        short = kernel_short_name(full)
+        short = kernel_short_name(full).replace("bec::(anonymous namespace)::", "")
         fb = fetch[full][0] * 1024.0 * f_fac
         wb = write[full][0] * 1024.0 * w_fac
         kernels[short] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
@@ -414,7 +415,31 @@ def scan_comparison(n_inst: int, use_graph: bool = True):
                "speedup": round(t_seq_sub / t_sub, 3), "batched_converged": sum(r["status"] == "OK" for r in srep),
                "iters_batched_total": sum(r["iters"] for r in srep),
                "iters_plain_total": sum(seq_iters[k] for k in both)}
+    # the whole scan once more in the batch with the composite preconditioner
+    # P_Delta^-1 P_V^-1 of Eq. (18) (same plans, tolerance and stall stop)
+    bc = solver.Batch(grids, params)
+    for s in scan:
+        bc.set_tuning(s["grid"], plans[tuple(s["grid"]["n"])])
+    copts = dict(opts, pc=3)
+    bc.solve(psi0, dict(copts, max_iter=2), use_graph=use_graph)
+    torch.cuda.synchronize()
+    ev0.record(bc.stream)
+    _, crep = bc.solve(psi0, copts, use_graph=use_graph)
+    ev1.record(bc.stream)
+    torch.cuda.synchronize()
+    t_comp = ev0.elapsed_time(ev1) / 1000.0
+    bc.close()
+    del bc
+    dE = [abs(crep[k]["final"]["E"] - brep[k]["final"]["E"]) / abs(brep[k]["final"]["E"])
+          for k in range(n_inst) if crep[k]["status"] == "OK" and brep[k]["status"] == "OK"]
+    comp = {"precond": "P_Delta^-1 P_V^-1", "batched_s": round(t_comp, 4),
+            "speedup_vs_batched_P_V": round(t_batch / t_comp, 3),
+            "batched_converged": sum(r["status"] == "OK" for r in crep),
+            "iters_total": sum(r["iters"] for r in crep),
+            "status": {st: sum(r["status"] == st for r in crep) for st in sorted({r["status"] for r in crep})},
+            "max_rel_dE_vs_P_V": max(dE) if dE else None}
     return {"instances": n_inst, "grids": "48^3/64^3/96^3 cycling", "tol_grad": 1e-10,
+            "batched_composite": comp,
             "plans": {"x".join(map(str, k)): v for k, v in plans.items()}, "tuning_s": round(t_tune, 3),
             "batched_s": round(t_batch, 4), "sequential_plain_s": round(t_seq, 4),
             "speedup": round(t_seq / t_batch, 3), "graph": use_graph,
@@ -428,6 +453,24 @@ def scan_comparison(n_inst: int, use_graph: bool = True):
                                "plain": seq_status[k], "iters": brep[k]["iters"]}
                               for k in range(n_inst) if brep[k]["status"] != "OK" or seq_status[k] != "OK"],
             "converged_in_both": sub}
+
+
+def describe_workload(name: str) -> str:
+    """One-line description of a workload of inputs.CONFIGS."""
+    from paper_2510_24543_amd import inputs
+    c = inputs.CONFIGS[name]
+    g, p = c["grid"], c["params"]
+
+    def num(x):
+        return f"{x:g}"
+    n = g["n"]
+    shape = f"{n[0]}^3" if n[0] == n[1] == n[2] else "x".join(map(str, n))
+    box = "x".join(f"[{num(lo)},{num(hi)})" for lo, hi in zip(g["lo"], g["hi"]))
+    G, D = p["G"], p["Gdd"]
+    return (f"{shape} grid x 2 components, box {box}, trap ({','.join(num(w) for w in p['omega'])}), "
+            f"g11={num(G[0][0])} g22={num(G[1][1])} g12={num(G[0][1])}, "
+            f"gdd11={num(D[0][0])} gdd22={num(D[1][1])} gdd12={num(D[0][1])}, LHY {num(p['c_lhy'])}, "
+            f"cutoff {num(p['r_cut'])}, seeded Gaussian+noise start, P_V + HS+ (restart 50), FP64")
 
 
 def main():
@@ -444,6 +487,8 @@ def main():
                     help="only run the preconditioner x conjugacy-rule study on this workload and print it")
     ap.add_argument("--ite-only", default=None, metavar="WORKLOAD",
                     help="only run the PCG-vs-ITE comparison on this workload (e.g. C2, C3, C5) and print it")
+    ap.add_argument("--workload", default=WORKLOAD, choices=("C1a", "C1b", "C2", "M", "C3", "C5"),
+                    help="workload of the timed PCG steps (default: the 128^3 headline workload M)")
     ap.add_argument("--tuning", choices=("auto", "cache", "default"), default="auto",
                     help="launch plans: autotune now, read the committed cache, or the defaults")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -479,9 +524,9 @@ def main():
         print(json.dumps(ite_workload(args.ite_only, args.ite_dt)), flush=True)
         return
 
-    cfg = inputs.CONFIGS[WORKLOAD]
+    cfg = inputs.CONFIGS[args.workload]
     grid, params = cfg["grid"], cfg["params"]
-    psi0_np = inputs.config_state(WORKLOAD)
+    psi0_np = inputs.config_state(args.workload)
     dev = torch.device("cuda:0")
     ctx = solver.Context(grid, params, dev)
     psi0 = torch.from_numpy(psi0_np).to(dev)
@@ -584,9 +629,7 @@ def main():
         "steps": steps_done, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "128^3 grid x 2 components, box [-8,8)^3, trap (1,1,2.6), g11=g22=100, "
-                               "g12=50, gdd=60 all pairs, LHY 5, cutoff 8, seeded Gaussian+noise start, "
-                               "P_V + HS+ (restart 50), FP64",
+        "config": {"workload": describe_workload(args.workload), "name": args.workload,
                    "grid": grid["n"], "points": ctx.N, "components": 2},
         "time_to_solution": tts,
         "time_to_solution_composite_precond": tts_comp,
