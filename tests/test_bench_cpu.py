@@ -51,7 +51,8 @@ def test_pmc_summary_scales_by_the_copy_calibration(tmp_path):
 
 def test_stored_traffic_is_dropped_when_kernel_sources_change(tmp_path, monkeypatch):
     path = tmp_path / "t.json"
-    good = {"source_hash": bench.kernel_source_hash(), "kernels": {"dir_write_kernel": {"bytes_per_launch": 7.0}}}
+    good = {"source_hash": bench.kernel_source_hash(),
+            "kernels": {bench.LABEL_KERNEL["dir_write"]: {"bytes_per_launch": 7.0}}}
     path.write_text(json.dumps(good))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
     assert bench.traffic_from_profiles("dir_write") == 7.0
