@@ -43,13 +43,17 @@ WORKLOAD = "M"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_128cubed.json")
 # library profiler labels -> kernel function names as rocprofv3 reports them
 # (the direction kernels as instantiated for P_V with LHY, the benchmark's configuration)
-LABEL_KERNEL = {"dir_write": "dir_write_kernel<1, true, 1>", "heval_epilogue": "heval_epi_kernel",
+# (a name ending in "<" matches any instantiation: the fused direction write + z pass
+# is instantiated per z plan variant)
+LABEL_KERNEL = {"dir_write": "dir_write_kernel<1, true, 1>", "dir_write_z": "fft_dirwrite_z_kernel<",
+                "heval_epilogue": "heval_epi_kernel",
                 "dir_reduce": "dir_reduce_kernel<1, true>", "trial_pack": "trial_kernel",
                 "ls_epilogue": "ls_epi_kernel", "reduce_final": "reduce_final_kernel",
                 "scale2": "scale2_kernel", "norm2": "norm2_kernel"}
 # sources whose change invalidates the stored counter figures of the pointwise kernels
 KERNEL_SOURCES = ["paper_2510_24543_amd/csrc/pointwise.hip", "paper_2510_24543_amd/csrc/pw_math.h",
-                  "paper_2510_24543_amd/csrc/bec_internal.h"]
+                  "paper_2510_24543_amd/csrc/bec_internal.h", "paper_2510_24543_amd/csrc/dir_point.h",
+                  "paper_2510_24543_amd/csrc/fft_dirz.hip", "paper_2510_24543_amd/csrc/fft_core.h"]
 
 
 def kernel_source_hash() -> str:
@@ -72,7 +76,11 @@ def traffic_from_profiles(label: str):
         data = json.load(open(TRAFFIC_FILE))
         if data.get("source_hash") != kernel_source_hash():
             return None
-        return data["kernels"][LABEL_KERNEL[label]]["bytes_per_launch"]
+        want, kernels = LABEL_KERNEL[label], data["kernels"]
+        if want.endswith("<"):
+            hits = [k for k in kernels if k.startswith(want)]
+            return kernels[hits[0]]["bytes_per_launch"] if len(hits) == 1 else None
+        return kernels[want]["bytes_per_launch"]
     except (KeyError, ValueError):
         return None
 

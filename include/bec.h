@@ -348,8 +348,10 @@ bec_status bec_batch_solve(bec_batch* b, double* const* psi_inout, const bec_opt
  * of the LHY terms.
  * ------------------------------------------------------------------------- */
 typedef struct {
-    int32_t fft_variant[3][2];  /* per axis (x, y, z): [0] plain passes, [1] the x pass with the fused
-                                   k-space operator (only [0][1] is used); 0 = default plan */
+    int32_t fft_variant[3][2];  /* per axis (x, y, z): [0] plain passes; [0][1] the x pass with the
+                                   fused k-space operator; [2][1] the direction write (P_V) fused
+                                   with the line search's forward z pass; [1][1] unused;
+                                   0 = default plan */
     int32_t pw_blocks;          /* workgroups of the pointwise kernels (64 .. 4096) */
     int32_t lhy_table;          /* 1 (default): the class-A part of the LHY node sum from Chebyshev
                                    series of its restriction to n1 + n2 = 1 (it is homogeneous of

@@ -124,10 +124,11 @@ def tune(ctx, reps: int = 20, iters: int = 8, psi0=None, opts: dict | None = Non
 
     def sweep_variants():
         # the z, y and k-space x variants also run the passes with fused work (the trial
-        # update and, with kin_axes, the kinetic axis terms; the Parseval axis sums),
+        # update and, with kin_axes, the kinetic axis terms; the Parseval axis sums; the
+        # z slot 1 is the direction write fused with the line search's z pass),
         # which the single-pass timings above do not see: choose them over whole PCG
         # iterations, with the kinetic-term switch already set
-        for axis, slot in ((2, 0), (1, 0), (0, 1)):
+        for axis, slot in ((2, 0), (1, 0), (0, 1), (2, 1)):
             L = ctx.grid["n"][axis]
             if variant_count(L) < 2:
                 continue
@@ -136,7 +137,7 @@ def tune(ctx, reps: int = 20, iters: int = 8, psi0=None, opts: dict | None = Non
                 best["fft_variant"][axis][slot] = v
                 t.append(per_iter(best))
             best["fft_variant"][axis][slot] = int(min(range(len(t)), key=t.__getitem__))
-            axis_ms[f"axis{axis}" + ("_kspace" if slot else "")] = [round(x, 5) for x in t]
+            axis_ms[f"axis{axis}" + (("_kspace" if axis == 0 else "_dirwrite") if slot else "")] = [round(x, 5) for x in t]
 
     choose_kin_axes("kin_axes")
     first = best["kin_axes"]

@@ -271,6 +271,9 @@ struct bec_ctx {
     int lhy_table_on = 1;      // tuning: use the table when built
     int kin_axes_on = 1;       // tuning: kinetic term of the energy evaluation from one-axis transforms
     int nblk_pw = 0;
+    // the last direction write: fused with the line search's z pass (its partials
+    // then come from dir_nblk z-pass blocks and the model skips that pass)
+    int dir_fused = 0, dir_nblk = 0;
     int nblk_x = 0;
     int fft_var[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // plan variant per axis: [plain, fused k-space]
     PwParams P{};
@@ -407,7 +410,8 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
         n[0] * sizeof(double), n[1] * sizeof(double), n[2] * sizeof(double),        // k
         n[0] * sizeof(double), n[1] * sizeof(double), n[2] * sizeof(double),        // V per axis
         bec::kMaxNodes * bec::kNodeStride * sizeof(double),                         // nodes
-        (size_t)bec::kMaxSums * nb_pw * sizeof(double),                             // partials
+        // partials: the pointwise grid's sums, or the fused direction write's per z-pass block
+        (size_t)std::max<long long>(bec::kMaxSums * nb_pw, bec::kDirWriteSums * nb_z) * sizeof(double),
         (size_t)3 * (nb_x + nb_y + nb_z) * sizeof(double),                          // fft partials
         kScalSlots * sizeof(double),                                                // device scalar copies
         (size_t)bec::kLsEpiSums * nb_z * sizeof(double),                            // line-search partials
@@ -1051,11 +1055,35 @@ static_assert(bec::kIteSums <= kParsevalOut, "imaginary-time sums overlap the Pa
 static_assert(bec::kDirWriteSums + bec::kLsEpiSums <= bec::kMaxSums, "model partials exceed the partials area");
 static_assert(kParsevalOut + 2 <= kScalHeval, "Parseval slots overlap the energy sums");
 
-// Direction write pass (p, r, rho).
+// Direction write pass (p, r, rho).  With P_V (zmode 1) it is fused with the
+// line search's forward z pass (the z-axis Parseval sums of p and the z
+// transform of the packed rho into W + 2N), which model_launch then skips.
 bec_status dir_write_launch(bec_ctx* c, const bec::DirArgs& A)
 {
     const double wb = 96.0 + (A.beta != 0.0 || A.dev_dir ? 32.0 : 0.0) + (A.zmode >= 2 ? 32.0 : 0.0) + 80.0;
+    if (A.zmode == 1) {
+        const long long N = c->N;
+        bec::FftPassArgs Z = pass_args(c, 2);
+        Z.nfield = 3;
+        Z.sign = -1;
+        Z.dst[2] = c->W + 2 * N;
+        // its own plan variant (the z axis has no k-space pass, so the second slot is free)
+        const int var = c->fft_var[2][1];
+        const int nbz = bec::fft_blocks(c->n[2], var, Z.npencil);
+        const int nby = bec::fft_blocks(c->n[1], c->fft_var[1][0], (long long)c->n[0] * c->n[2]);
+        Z.tw = c->tw[2];
+        Z.partials = c->fft_partials;                 // the z slot of the model's Parseval sums
+        Z.nblk_x = nbz + nby + c->nblk_x;
+        Z.pscale = (double)c->n[0] * c->n[1];
+        LAUNCH(c, "dir_write_z", (double)N * (wb + 16.0),
+               bec::fft_dirwrite_z_pass(c->n[2], var, Z, c->P, A, c->st));
+        c->dir_fused = 1;
+        c->dir_nblk = nbz;
+        return BEC_OK;
+    }
     LAUNCH(c, "dir_write", (double)c->N * wb, bec::launch_dir_write(c->P, A, c->nblk_pw, c->st));
+    c->dir_fused = 0;
+    c->dir_nblk = c->nblk_pw;
     return BEC_OK;
 }
 
@@ -1077,13 +1105,14 @@ bec_status model_launch(bec_ctx* c, const double norm2[2], double alpha_prev, do
     double2* dst[3] = {c->W, c->W + N, c->W + 2 * N};    // dst[0..1]: not written
     const int ops_a[3] = {bec::kOpParsevalAxis, bec::kOpParsevalAxis, bec::kOpPlain};
     const int ops[3] = {bec::kOpParsevalAxis, bec::kOpParsevalAxis, bec::kOpMulDip};
-    const int nbz = bec::fft_blocks(c->n[2], c->fft_var[2][0], (long long)c->n[0] * c->n[1]);
+    // the z Parseval slot: blocks of the fused direction write, or of the z pass below
+    const int nbz = c->dir_fused ? c->dir_nblk : bec::fft_blocks(c->n[2], c->fft_var[2][0], (long long)c->n[0] * c->n[1]);
     const int nby = bec::fft_blocks(c->n[1], c->fft_var[1][0], (long long)c->n[0] * c->n[2]);
     const int nbp = nbz + nby + c->nblk_x;
     const ParsevalOut pz{c->fft_partials, nbp, (double)c->n[0] * c->n[1]};
     const ParsevalOut py{c->fft_partials + nbz, nbp, (double)c->n[0] * c->n[2]};
     const ParsevalOut px{c->fft_partials + nbz + nby, nbp, (double)c->n[1] * c->n[2]};
-    STCHK(run_pass(c, 2, src, dst, 3, -1, 1.0, ops_a, nullptr, nullptr, 0.0, &pz));
+    if (!c->dir_fused) STCHK(run_pass(c, 2, src, dst, 3, -1, 1.0, ops_a, nullptr, nullptr, 0.0, &pz));
     STCHK(run_pass(c, 1, src_p, dst, 3, -1, 1.0, ops_a, nullptr, nullptr, 0.0, &py));
     STCHK(run_pass(c, 0, src_p, dst, 3, -1, 1.0, ops, nullptr, nullptr, 0.0, &px));
     STCHK(run_pass(c, 1, dst + 2, dst + 2, 1, +1, 1.0, nullptr, nullptr));
@@ -1095,11 +1124,11 @@ bec_status model_launch(bec_ctx* c, const double norm2[2], double alpha_prev, do
     LAUNCH(c, "fft_z_inv_ls", (double)N * 32.0,
            bec::fft_zinv_ls_pass(c->n[2], c->fft_var[2][0], zA, c->rho, c->ls_partials, c->st));
     const int o = kScalModel;
-    const bec::RedSeg s1{c->partials, c->nblk_pw, bec::kDirWriteSums, c->scal + o, c->dscal + o};
+    const bec::RedSeg s1{c->partials, c->dir_nblk, bec::kDirWriteSums, c->scal + o, c->dscal + o};
     const bec::RedSeg s2{c->fft_partials, nbp, 2, c->scal + o + kParsevalOut, c->dscal + o + kParsevalOut};
     const bec::RedSeg s3{c->ls_partials, nblk_z, bec::kLsEpiSums, c->scal + o + bec::kDirWriteSums,
                          c->dscal + o + bec::kDirWriteSums};
-    LAUNCH(c, "reduce_final", 8.0 * (bec::kDirWriteSums * c->nblk_pw + 2 * nbp + bec::kLsEpiSums * nblk_z),
+    LAUNCH(c, "reduce_final", 8.0 * (bec::kDirWriteSums * c->dir_nblk + 2 * nbp + bec::kLsEpiSums * nblk_z),
            bec::launch_reduce_segs(s1, s2, s3, c->st));
     bec::StepArgs st{};
     st.D = c->dscal + o;

@@ -277,6 +277,14 @@ hipError_t launch_heval_epi(const PwParams& P, const HevalArgs& a, int nblk, hip
 hipError_t launch_ite_epi(const PwParams& P, const IteArgs& a, int nblk, hipStream_t s);
 hipError_t launch_dir_reduce(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s);
 hipError_t launch_dir_write(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s);
+// The direction write (zmode 1 only) fused with the line search's forward z pass:
+// p, r, rho and the kDirWriteSums sums as launch_dir_write (sums into
+// a.partials [sum][block], grid = fft_blocks(L, variant, z.npencil) blocks),
+// plus the z-axis Parseval sums of p_1, p_2 (z.partials[f * z.nblk_x + block]
+// times z.pscale, f = 0, 1) and the forward z transform of the packed rho into
+// z.dst[2].  z: a z-axis pass of the grid (tw, kaxis, npencil, S = 1).
+hipError_t fft_dirwrite_z_pass(int L, int variant, const FftPassArgs& z, const PwParams& P, const DirArgs& a,
+                               hipStream_t s);
 hipError_t launch_make_r(const PwParams& P, const MakeRArgs& a, hipStream_t s);
 hipError_t launch_param_grad(const PwParams& P, const ParamGradArgs& a, int nblk, hipStream_t s);
 hipError_t launch_norm2(const PwParams& P, const double2* f, double* partials, int nblk, hipStream_t s);

@@ -15,27 +15,12 @@
 //   P_V diagonal [alpha_i + V + sum_j G_ij n_j + muLHY_i]_+ + sigma                  (Sec. IV.B)
 //   d = -z + beta p_old, p = d - Re<d,psi> psi                                      (Sec. IV.C, Sec. V)
 //   second-order energy model along the geodesic                                    (Sec. V)
-#include "bec_internal.h"
-#include "pw_math.h"
+#include "dir_point.h"
 
 namespace bec {
 namespace {
 
-__device__ __forceinline__ double trap_at(const PwParams& P, long long i)
-{
-    const uint32_t ii = (uint32_t)i;   // N < 2^31 (checked at creation)
-    const uint32_t ix = (uint32_t)(((uint64_t)ii * P.m_nyz) >> P.s_nyz);
-    const uint32_t rem = ii - ix * (uint32_t)(P.ny * P.nz);
-    const uint32_t iy = (uint32_t)(((uint64_t)rem * P.m_nz) >> P.s_nz);
-    const uint32_t iz = rem - iy * (uint32_t)P.nz;
-    return P.vx[ix] + P.vy[iy] + P.vz[iz];
-}
-
-// node constants read from the kernel-argument block (scalar loads)
-struct KernargNodes {
-    const PwParams& P;
-    __device__ double operator()(int q, int k) const { return P.node5[q][k]; }
-};
+using namespace dirpt;
 
 // Fixed-order workgroup reduction of M per-thread sums into partials[m * nblk + block].
 template <int M>
@@ -170,14 +155,6 @@ struct RZ {
     double2 r[2], z[2];
 };
 
-// 1 / ([shift + V + sum_j G_cj n_j + muLHY_c]_+ + sigma): the inverse P_V diagonal
-__device__ __forceinline__ double pv_inv(const PwParams& P, int c, double shift, double sigma, double V, double n1,
-                                         double n2, double ml)
-{
-    const double g = shift + V + P.G[c][0] * n1 + P.G[c][1] * n2 + ml;
-    return 1.0 / ((g > 0.0 ? g : 0.0) + sigma);
-}
-
 #ifndef BEC_DIR_WRITE_UNROLL
 #define BEC_DIR_WRITE_UNROLL 1
 #endif
@@ -288,102 +265,6 @@ __global__ __launch_bounds__(kPwThreads) void dir_reduce_kernel(PwParams P, DirA
         }
     }
     block_reduce_store<kDirReduceSums>(acc, A.partials, gridDim.x);
-}
-
-// Operands of the direction-write pass at one point (ZM = DirArgs::zmode).
-template <int ZM>
-struct DirIn {
-    double2 s[2], h[2], ph, ml, po[2], zb[2];
-};
-
-template <int ZM>
-__device__ __forceinline__ DirIn<ZM> dir_load(const DirArgs& A, long long N, long long i, bool with_p)
-{
-    DirIn<ZM> v;
-    v.s[0] = A.psi[i];
-    v.s[1] = A.psi[N + i];
-    v.h[0] = A.hpsi[i];
-    v.h[1] = A.hpsi[N + i];
-    v.ph = A.aux[i];
-    v.ml = A.aux[N + i];
-    if (with_p) {
-        v.po[0] = A.p[i];
-        v.po[1] = A.p[N + i];
-    } else {
-        v.po[0] = v.po[1] = make_double2(0.0, 0.0);
-    }
-    if constexpr (ZM >= 2 && ZM <= 4) {
-        v.zb[0] = A.zbuf[i];
-        v.zb[1] = A.zbuf[N + i];
-    }
-    return v;
-}
-
-// One point of the direction-write pass: z, the new direction p (stored with r
-// and rho = Re conj(psi) p) and the line-search model sums.
-template <int ZM, bool LHY>
-__device__ __forceinline__ void dir_point(const PwParams& P, const DirArgs& A, long long N, long long i,
-                                         const DirIn<ZM>& cur, double* acc)
-{
-    const double2* s = cur.s;
-    double2 r[2], z[2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) r[c] = make_double2(cur.h[c].x - A.mu[c] * s[c].x, cur.h[c].y - A.mu[c] * s[c].y);
-    const double n[2] = {sq2(s[0]), sq2(s[1])};
-    const double V = trap_at(P, i);
-    const double mlc[2] = {cur.ml.x, cur.ml.y};
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        if constexpr (ZM == 0) {
-            z[c] = r[c];
-        } else if constexpr (ZM == 2) {
-            z[c] = cur.zb[c];
-        } else {
-            const double g = pv_inv(P, c, A.diag_shift[c], A.sigma, V, n[0], n[1], mlc[c]);
-            if constexpr (ZM == 1) {
-                z[c] = make_double2(g * r[c].x, g * r[c].y);
-            } else if constexpr (ZM == 3) {
-                const double q = sqrt(g);
-                z[c] = make_double2(q * cur.zb[c].x, q * cur.zb[c].y);
-            } else {
-                const double a = A.blend_w[c] * g, b = 1.0 - A.blend_w[c];
-                z[c] = make_double2(a * r[c].x + b * cur.zb[c].x, a * r[c].y + b * cur.zb[c].y);
-            }
-        }
-    }
-    const double2 ph = cur.ph;
-    double2 p[2];
-    double rho[2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        double2 d = make_double2(A.zsign * z[c].x, A.zsign * z[c].y);
-        if (A.beta != 0.0) {
-            d.x += A.beta * cur.po[c].x;
-            d.y += A.beta * cur.po[c].y;
-        }
-        p[c] = make_double2(d.x - A.c[c] * s[c].x, d.y - A.c[c] * s[c].y);
-        A.p_out[c * N + i] = p[c];
-        A.r_out[c * N + i] = r[c];
-        rho[c] = redot(s[c], p[c]);
-        const double2 hmf = make_double2(cur.h[c].x - mlc[c] * s[c].x, cur.h[c].y - mlc[c] * s[c].y);
-        const double U = V + P.G[c][0] * n[0] + P.G[c][1] * n[1] + P.Gdd[c][0] * ph.x + P.Gdd[c][1] * ph.y;
-        const double pp = sq2(p[c]);
-        acc[0 + c] += pp;
-        acc[2 + c] += redot(p[c], r[c]);
-        acc[4 + c] += redot(p[c], hmf);
-        acc[6 + c] += redot(s[c], hmf);
-        acc[8 + c] += U * pp;
-        acc[10 + c] += mlc[c] * pp;
-        acc[12 + c] += mlc[c] * n[c];
-        acc[16 + c] += rho[c];
-    }
-    A.rho[i] = make_double2(rho[0], rho[1]);
-    if constexpr (LHY) {
-        double L1, L2;
-        lhy_model(KernargNodes{P}, LhyTab{P.lhy_tab, P.lhy_K}, P.n_a, P.n_b, n[0], n[1], 2.0 * rho[0], 2.0 * rho[1], L1, L2);
-        acc[14] += L1;
-        acc[15] += L2;
-    }
 }
 
 // Direction write pass with the LHY part of the line-search model.  UNR points

@@ -300,6 +300,36 @@ def test_blended_preconditioner(solver, orc, case, blend):
 
 
 @pytest.mark.parametrize("n", [8, 16, 32, 48, 64, 96, 128, 256])
+def test_every_variant_of_the_fused_direction_write(solver, orc, n):
+    """The direction write with P_V fused with the line search's forward z pass
+    (tuning slot [2][1]) in every plan variant of a z axis n long: four P_V
+    steps of the solver against the oracle's, step by step (E to 1e-11, alpha,
+    beta, E1, E2 to 1e-8, the same decisions)."""
+    from paper_2510_24543_amd import autotune
+    params = small_params()
+    grid = {"n": [8, 16, n], "lo": [-6.0] * 3, "hi": [6.0] * 3}
+    psi0 = inputs.initial_state(grid, params["omega"], 45, phase=True)
+    opts = {"tol_grad": 0.0, "max_iter": 4, "pc": 1}
+    _, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=4)
+    ctx = solver.Context(grid, params)
+    base = ctx.get_tuning()
+    for v in range(autotune.variant_count(n)):
+        print(f"n {n} fused direction-write variant {v}", flush=True)
+        t = {"fft_variant": [r_[:] for r_ in base["fft_variant"]], "pw_blocks": base["pw_blocks"]}
+        t["fft_variant"][2][1] = v
+        ctx.set_tuning(t)
+        _, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=4)
+        assert rep["iters"] == repo["iters"] == 4, v
+        for k in range(4):
+            a, b = log[k], logo[k]
+            for key in ("n_trials", "restarted", "path"):
+                assert a[key] == b[key], (v, k, key)
+            assert abs(a["E"] - b["E"]) <= 1e-11 * abs(b["E"]), (v, k)
+            for key in ("alpha", "beta", "E1", "E2"):
+                assert abs(a[key] - b[key]) <= 1e-8 * max(abs(b[key]), 1e-300), (v, k, key)
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 48, 64, 96, 128, 256])
 @pytest.mark.parametrize("kin_axes", [1, 0])
 def test_every_variant_of_the_fused_passes(solver, orc, n, kin_axes):
     """Every plan variant of the passes with fused work: the x pass with the
