@@ -46,14 +46,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_128cubed.json")
 # (a name ending in "<" matches any instantiation: the fused direction write + z pass
 # is instantiated per z plan variant)
 LABEL_KERNEL = {"dir_write": "dir_write_kernel<1, true, 1>", "dir_write_z": "fft_dirwrite_z_kernel<",
+                "heval_z": "fft_heval_z_kernel<",
                 "heval_epilogue": "heval_epi_kernel",
                 "dir_reduce": "dir_reduce_kernel<1, true>", "trial_pack": "trial_kernel",
                 "ls_epilogue": "ls_epi_kernel", "reduce_final": "reduce_final_kernel",
                 "scale2": "scale2_kernel", "norm2": "norm2_kernel"}
 # sources whose change invalidates the stored counter figures of the pointwise kernels
 KERNEL_SOURCES = ["paper_2510_24543_amd/csrc/pointwise.hip", "paper_2510_24543_amd/csrc/pw_math.h",
-                  "paper_2510_24543_amd/csrc/bec_internal.h", "paper_2510_24543_amd/csrc/dir_point.h",
-                  "paper_2510_24543_amd/csrc/fft_dirz.hip", "paper_2510_24543_amd/csrc/fft_core.h"]
+                  "paper_2510_24543_amd/csrc/bec_internal.h", "paper_2510_24543_amd/csrc/pw_point.h",
+                  "paper_2510_24543_amd/csrc/fft_fused.hip", "paper_2510_24543_amd/csrc/fft_core.h"]
 
 
 def kernel_source_hash() -> str:

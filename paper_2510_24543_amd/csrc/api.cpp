@@ -819,8 +819,10 @@ bec_status kspace_apply(bec_ctx* c, const double2* const* src, double2* const* d
 // y and x passes that carry the density's forward transforms add T_y psi_i and
 // T_x psi_i from one-dimensional transforms of the stored trial point, and the
 // inverse y and z passes carry the density alone.
+// z_left (optional): with the one-axis kinetic terms, leave the last inverse z
+// pass of dst[2] to the caller (set to true when it is left)
 bec_status kspace_apply_trial(bec_ctx* c, const bec::TrialZArgs& Z, double2* const* dst, const int* ops,
-                              const double* prec_a)
+                              const double* prec_a, bool* z_left = nullptr)
 {
     const bool kin_axes =
         c->kin_axes_on && ops[0] == bec::kOpMulKin && ops[1] == bec::kOpMulKin && ops[2] == bec::kOpMulDip;
@@ -844,6 +846,10 @@ bec_status kspace_apply_trial(bec_ctx* c, const bec::TrialZArgs& Z, double2* con
     STCHK(run_pass(c, 1, src, dst, 3, -1, 1.0, ops_y, prec_a, nullptr, 0.0, nullptr, acc));
     STCHK(run_pass(c, 0, src, dst, 3, -1, 1.0, ops_x, prec_a, nullptr, 0.0, nullptr, acc));
     STCHK(run_pass(c, 1, dst + 2, dst + 2, 1, +1, 1.0, nullptr, nullptr));
+    if (z_left) {
+        *z_left = true;
+        return BEC_OK;
+    }
     STCHK(run_pass(c, 2, dst + 2, dst + 2, 1, +1, 1.0, nullptr, nullptr));
     return BEC_OK;
 }
@@ -883,9 +889,10 @@ bec_status reduce_pw(bec_ctx* c, int M, int out_off)
 }
 
 // the same, with a device copy of the results at the same offset of c->dscal
-bec_status reduce_pw_copy(bec_ctx* c, int M, int out_off)
+bec_status reduce_pw_copy(bec_ctx* c, int M, int out_off, int nblk = 0)
 {
-    const bec::RedSeg a{c->partials, c->nblk_pw, M, c->scal + out_off, c->dscal + out_off};
+    if (nblk <= 0) nblk = c->nblk_pw;
+    const bec::RedSeg a{c->partials, nblk, M, c->scal + out_off, c->dscal + out_off};
     const bec::RedSeg none{nullptr, 0, 0, nullptr, nullptr};
     LAUNCH(c, "reduce_final", 8.0 * M * c->nblk_pw, bec::launch_reduce_segs(a, none, none, c->st));
     return BEC_OK;
@@ -918,7 +925,8 @@ bec_status heval_launch(bec_ctx* c, const double2* src, const double2* p, const 
     // half), where the later passes read them
     double2* fdst[3] = {c->W, c->W + N, c->aux[set]};
     const int ops[3] = {bec::kOpMulKin, bec::kOpMulKin, bec::kOpMulDip};
-    STCHK(kspace_apply_trial(c, z, fdst, ops, nullptr));
+    bool z_left = false;
+    STCHK(kspace_apply_trial(c, z, fdst, ops, nullptr, &z_left));
     bec::HevalArgs ha{};
     ha.psi = c->psi[set];
     ha.Tpsi = c->W;
@@ -926,6 +934,16 @@ bec_status heval_launch(bec_ctx* c, const double2* src, const double2* p, const 
     ha.hpsi = c->hpsi[set];
     ha.aux = c->aux[set];
     ha.partials = c->partials;
+    if (z_left) {   // the inverse z pass of Phi fused with the epilogue
+        bec::FftPassArgs Zp = pass_args(c, 2);
+        Zp.nfield = 1;
+        Zp.sign = +1;
+        Zp.src[0] = Zp.dst[0] = c->aux[set];
+        const int nblk = bec::fft_blocks(c->n[2], c->fft_var[2][0], Zp.npencil);
+        LAUNCH(c, "heval_z", (double)c->N * 144.0,
+               bec::fft_heval_z_pass(c->n[2], c->fft_var[2][0], Zp, c->P, ha, c->st));
+        return reduce_pw_copy(c, bec::kHevalSums, kScalHeval, nblk);
+    }
     LAUNCH(c, "heval_epilogue", (double)c->N * 128.0, bec::launch_heval_epi(c->P, ha, c->nblk_pw, c->st));
     return reduce_pw_copy(c, bec::kHevalSums, kScalHeval);
 }

@@ -285,6 +285,13 @@ hipError_t launch_dir_write(const PwParams& P, const DirArgs& a, int nblk, hipSt
 // z.dst[2].  z: a z-axis pass of the grid (tw, kaxis, npencil, S = 1).
 hipError_t fft_dirwrite_z_pass(int L, int variant, const FftPassArgs& z, const PwParams& P, const DirArgs& a,
                                hipStream_t s);
+// The last inverse z pass of the energy evaluation fused with the Hamiltonian
+// epilogue: z.src[0] (= h.aux, in place) holds the packed Phi spectrum after
+// the y inverse pass; stores Phi and H psi, muLHY into h.hpsi, h.aux and the
+// kHevalSums sums into h.partials [sum][block] (grid = fft_blocks(L, variant,
+// z.npencil)).
+hipError_t fft_heval_z_pass(int L, int variant, const FftPassArgs& z, const PwParams& P, const HevalArgs& h,
+                            hipStream_t s);
 hipError_t launch_make_r(const PwParams& P, const MakeRArgs& a, hipStream_t s);
 hipError_t launch_param_grad(const PwParams& P, const ParamGradArgs& a, int nblk, hipStream_t s);
 hipError_t launch_norm2(const PwParams& P, const double2* f, double* partials, int nblk, hipStream_t s);

@@ -1,5 +1,5 @@
 // Building blocks of the FFT passes for gfx950, shared by the pass kernels
-// (fft.hip) and the fused direction-write pass (fft_dirz.hip): complex
+// (fft.hip) and the passes fused with pointwise work (fft_fused.hip): complex
 // helpers, radix 2/3/4/6/8/12/16 butterflies in registers, Stockham stages with
 // their LDS exchanges, the plans of one length, and the table of plan variants.
 #pragma once

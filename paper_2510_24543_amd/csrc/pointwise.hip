@@ -15,12 +15,12 @@
 //   P_V diagonal [alpha_i + V + sum_j G_ij n_j + muLHY_i]_+ + sigma                  (Sec. IV.B)
 //   d = -z + beta p_old, p = d - Re<d,psi> psi                                      (Sec. IV.C, Sec. V)
 //   second-order energy model along the geodesic                                    (Sec. V)
-#include "dir_point.h"
+#include "pw_point.h"
 
 namespace bec {
 namespace {
 
-using namespace dirpt;
+using namespace pwpt;
 
 // Fixed-order workgroup reduction of M per-thread sums into partials[m * nblk + block].
 template <int M>
@@ -70,41 +70,10 @@ __global__ __launch_bounds__(kPwThreads) void heval_epi_kernel(PwParams P, Heval
     double acc[kHevalSums];
 #pragma unroll
     for (int m = 0; m < kHevalSums; ++m) acc[m] = 0.0;
-    long long i = (long long)blockIdx.x * kPwThreads + threadIdx.x;
-    for (; i < N; i += stride) {
+    const bool store_phi = A.phi != A.aux;      // uniform: Phi already in place otherwise
+    for (long long i = (long long)blockIdx.x * kPwThreads + threadIdx.x; i < N; i += stride) {
         const HevalIn cur = heval_load(A, N, i);
-        const double2 s1 = cur.s1, s2 = cur.s2, t1 = cur.t1, t2 = cur.t2, ph = cur.ph;
-        const double n1 = sq2(s1), n2 = sq2(s2);
-        const double V = trap_at(P, i);
-        double e = 0.0, d1 = 0.0, d2 = 0.0;
-        if (P.lhy_on) lhy_point(KernargNodes{P}, LhyTab{P.lhy_tab, P.lhy_K}, P.n_a, P.n_b, P.K5, P.K3, n1, n2, e, d1, d2);
-        const double m1 = d1 / P.Nat[0], m2 = d2 / P.Nat[1];
-        const double U1 = V + P.G[0][0] * n1 + P.G[0][1] * n2 + P.Gdd[0][0] * ph.x + P.Gdd[0][1] * ph.y + m1;
-        const double U2 = V + P.G[1][0] * n1 + P.G[1][1] * n2 + P.Gdd[1][0] * ph.x + P.Gdd[1][1] * ph.y + m2;
-        const double2 h1 = make_double2(t1.x + U1 * s1.x, t1.y + U1 * s1.y);
-        const double2 h2 = make_double2(t2.x + U2 * s2.x, t2.y + U2 * s2.y);
-        A.hpsi[i] = h1;
-        A.hpsi[N + i] = h2;
-        if (A.phi != A.aux) A.aux[i] = ph;      // uniform: Phi already in place otherwise
-        A.aux[N + i] = make_double2(m1, m2);
-        acc[0] += redot(s1, t1);
-        acc[1] += redot(s2, t2);
-        acc[2] += V * n1;
-        acc[3] += V * n2;
-        acc[4] += n1 * n1;
-        acc[5] += n1 * n2;
-        acc[6] += n2 * n2;
-        acc[7] += n1 * ph.x;
-        acc[8] += n1 * ph.y;
-        acc[9] += n2 * ph.x;
-        acc[10] += n2 * ph.y;
-        acc[11] += e;
-        acc[12] += redot(s1, h1);
-        acc[13] += redot(s2, h2);
-        acc[14] += n1;
-        acc[15] += n2;
-        acc[16] += m1 * n1;
-        acc[17] += m2 * n2;
+        heval_point(P, A, N, i, cur.s1, cur.s2, cur.t1, cur.t2, cur.ph, store_phi, acc);
     }
     block_reduce_store<kHevalSums>(acc, A.partials, gridDim.x);
 }

@@ -1,7 +1,8 @@
-// Per-point algebra of the direction-write pass (Sec. IV.B-IV.C, Sec. V),
-// shared by the grid-stride kernel (pointwise.hip) and the pass that fuses it
-// with the first forward transform of the line search (fft_dirz.hip): the trap
-// at a point, the inverse P_V diagonal, the operand loads, and the point's z,
+// Per-point algebra of the Hamiltonian epilogue (Sec. II, Eqs. (1), (3), (5),
+// (6)) and of the direction-write pass (Sec. IV.B-IV.C, Sec. V), shared by the
+// grid-stride kernels (pointwise.hip) and the passes that fuse them with a z
+// transform (fft_fused.hip): the trap at a point, the inverse P_V diagonal, the
+// operand loads, H psi with muLHY and the energy sums, and the point's z,
 // direction p, residual r, rho = Re(conj(psi) p) and model sums.
 #pragma once
 
@@ -10,7 +11,7 @@
 #include "pw_math.h"
 
 namespace bec {
-namespace dirpt {
+namespace pwpt {
 
 __device__ __forceinline__ double trap_at(const PwParams& P, long long i)
 {
@@ -27,6 +28,46 @@ struct KernargNodes {
     const PwParams& P;
     __device__ double operator()(int q, int k) const { return P.node5[q][k]; }
 };
+
+// H psi_i = T psi_i + [V + sum_j (G_ij n_j + Gdd_ij Phi_j) + muLHY_i] psi_i at
+// point i from psi (s1, s2), T psi (t1, t2) and Phi_1 + i Phi_2 (ph); stores
+// H psi and muLHY (and Phi when store_phi) and adds the kHevalSums energy sums.
+__device__ __forceinline__ void heval_point(const PwParams& P, const HevalArgs& A, long long N, long long i,
+                                            double2 s1, double2 s2, double2 t1, double2 t2, double2 ph,
+                                            bool store_phi, double* acc)
+{
+    const double n1 = sq2(s1), n2 = sq2(s2);
+    const double V = trap_at(P, i);
+    double e = 0.0, d1 = 0.0, d2 = 0.0;
+    if (P.lhy_on) lhy_point(KernargNodes{P}, LhyTab{P.lhy_tab, P.lhy_K}, P.n_a, P.n_b, P.K5, P.K3, n1, n2, e, d1, d2);
+    const double m1 = d1 / P.Nat[0], m2 = d2 / P.Nat[1];
+    const double U1 = V + P.G[0][0] * n1 + P.G[0][1] * n2 + P.Gdd[0][0] * ph.x + P.Gdd[0][1] * ph.y + m1;
+    const double U2 = V + P.G[1][0] * n1 + P.G[1][1] * n2 + P.Gdd[1][0] * ph.x + P.Gdd[1][1] * ph.y + m2;
+    const double2 h1 = make_double2(t1.x + U1 * s1.x, t1.y + U1 * s1.y);
+    const double2 h2 = make_double2(t2.x + U2 * s2.x, t2.y + U2 * s2.y);
+    A.hpsi[i] = h1;
+    A.hpsi[N + i] = h2;
+    if (store_phi) A.aux[i] = ph;
+    A.aux[N + i] = make_double2(m1, m2);
+    acc[0] += redot(s1, t1);
+    acc[1] += redot(s2, t2);
+    acc[2] += V * n1;
+    acc[3] += V * n2;
+    acc[4] += n1 * n1;
+    acc[5] += n1 * n2;
+    acc[6] += n2 * n2;
+    acc[7] += n1 * ph.x;
+    acc[8] += n1 * ph.y;
+    acc[9] += n2 * ph.x;
+    acc[10] += n2 * ph.y;
+    acc[11] += e;
+    acc[12] += redot(s1, h1);
+    acc[13] += redot(s2, h2);
+    acc[14] += n1;
+    acc[15] += n2;
+    acc[16] += m1 * n1;
+    acc[17] += m2 * n2;
+}
 
 // 1 / ([shift + V + sum_j G_cj n_j + muLHY_c]_+ + sigma): the inverse P_V diagonal
 __device__ __forceinline__ double pv_inv(const PwParams& P, int c, double shift, double sigma, double V, double n1,
@@ -139,5 +180,5 @@ __device__ __forceinline__ void dir_point(const PwParams& P, const DirArgs& A, l
     }
 }
 
-}  // namespace dirpt
+}  // namespace pwpt
 }  // namespace bec
