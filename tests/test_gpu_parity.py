@@ -547,26 +547,34 @@ def test_pipelined_solve_is_bitwise_the_synchronous_one(solver, name, extra):
 @pytest.mark.timeout(900)
 def test_headline_grid_first_iterations(solver, orc):
     """128^3 x 2 (the benchmark workload): energy terms of the seeded state and the
-    first three accepted steps against the oracle."""
+    first three accepted steps against the oracle, with the default plans and with
+    the cached tuned plans the benchmark runs (the fused z kernels in their tuned
+    variants)."""
+    from paper_2510_24543_amd import autotune
     c = inputs.CONFIGS["M"]
     grid, params = c["grid"], c["params"]
     psi0 = inputs.config_state("M")
-    ctx = solver.Context(grid, params)
-    t = ctx.energy(torch.from_numpy(psi0))
     to = orc.heval(grid, params, psi0)[0]
-    assert abs(t["E"] - to["E"]) <= 1e-12 * abs(to["E"])
     opts = {"tol_grad": 0.0, "max_iter": 3}
-    psi, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=3)
     psio, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=3)
-    assert rep["iters"] == repo["iters"] == 3
-    for a, b in zip(log, logo):
-        assert abs(a["E"] - b["E"]) <= 1e-11 * abs(b["E"])
-    # sampled points of the state after three steps
     rng = np.random.default_rng(5)
     idx = tuple(rng.integers(0, n, 4096) for n in grid["n"])
-    g = psi.cpu().numpy()
-    for i in range(2):
-        assert np.max(np.abs(g[i][idx] - psio[i][idx])) <= 1e-10 * np.max(np.abs(psio[i]))
+    ctx = solver.Context(grid, params)
+    cached = autotune.load_cached(grid)
+    for plan in [None] + ([cached] if cached else []):
+        print(f"plan {plan}", flush=True)
+        if plan:
+            ctx.set_tuning(plan)
+        t = ctx.energy(torch.from_numpy(psi0))
+        assert abs(t["E"] - to["E"]) <= 1e-12 * abs(to["E"])
+        psi, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=3)
+        assert rep["iters"] == repo["iters"] == 3
+        for a, b in zip(log, logo):
+            assert abs(a["E"] - b["E"]) <= 1e-11 * abs(b["E"])
+        # sampled points of the state after three steps
+        g = psi.cpu().numpy()
+        for i in range(2):
+            assert np.max(np.abs(g[i][idx] - psio[i][idx])) <= 1e-10 * np.max(np.abs(psio[i]))
 
 
 @pytest.mark.timeout(900)
@@ -590,10 +598,16 @@ def test_largest_grid_energy_hamiltonian_and_first_step(solver, orc):
     for i in range(2):
         assert np.max(np.abs(hg[i][idx] - ho[i][idx])) <= 1e-11 * np.max(np.abs(ho[i]))
     opts = {"tol_grad": 0.0, "max_iter": 1}
-    _, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=1)
     _, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=1)
-    assert abs(log[0]["E"] - logo[0]["E"]) <= 1e-11 * abs(logo[0]["E"])
-    assert abs(log[0]["alpha"] - logo[0]["alpha"]) <= 1e-8 * abs(logo[0]["alpha"])
+    from paper_2510_24543_amd import autotune
+    cached = autotune.load_cached(grid)
+    for plan in [None] + ([cached] if cached else []):      # default plans, then the cached tuned ones
+        print(f"plan {plan}", flush=True)
+        if plan:
+            ctx.set_tuning(plan)
+        _, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=1)
+        assert abs(log[0]["E"] - logo[0]["E"]) <= 1e-11 * abs(logo[0]["E"])
+        assert abs(log[0]["alpha"] - logo[0]["alpha"]) <= 1e-8 * abs(logo[0]["alpha"])
 
 
 # ---------------------------------------------------------------- errors and edge cases
