@@ -1255,6 +1255,7 @@ void ctx_attach(bec_ctx* c, const bec_grid* grid, const bec_params* params, void
     }
     c->N = (long long)c->n[0] * c->n[1] * c->n[2];
     c->dV = c->h[0] * c->h[1] * c->h[2];
+    c->fft_var[2][1] = bec::fft_fused_default_variant(c->n[2]);   // the fused direction write's plan
     auto at = [&](int i) { return base + off[i]; };
     c->psi[0] = (double2*)at(0);
     c->psi[1] = (double2*)at(1);

@@ -180,6 +180,7 @@ bool fft_supported(int L);
 int fft_num_variants(int L);
 int fft_blocks(int L, int variant, long long npencil);   // grid.x of a pass
 int fft_max_blocks(int L, long long npencil);            // over all variants
+int fft_fused_default_variant(int L);                     // default plan of the fused z kernels
 
 // ---------------------------------------------------------------- pointwise kernels
 

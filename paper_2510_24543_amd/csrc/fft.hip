@@ -530,6 +530,25 @@ int fft_blocks(int L, int variant, long long npencil)
     return (int)((npencil + pb - 1) / pb);
 }
 
+int fft_fused_default_variant(int L)
+{
+    // the most threads per pencil that still keep a pencil inside one wavefront
+    // (fewest elements per thread: the fused kernels hold three fields), in
+    // 256-thread blocks where there is a choice
+    int best = 0, bestT = 0, bestN = 0;
+    Variant v;
+    for (int k = 0; find_variant(L, k, &v); ++k) {
+        if (v.T > 64 || 64 % v.T != 0) continue;
+        const bool better = v.T > bestT || (v.T == bestT && v.nthr == 256 && bestN != 256);
+        if (better) {
+            best = k;
+            bestT = v.T;
+            bestN = v.nthr;
+        }
+    }
+    return best;
+}
+
 int fft_max_blocks(int L, long long npencil)
 {
     int m = 0;
