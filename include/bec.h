@@ -363,6 +363,14 @@ typedef struct {
                                    y and x passes; 0: the 3D multiply in the x pass (fewer
                                    transforms per pencil: faster on small, launch-bound grids).
                                    Not used by bec_batch_set_tuning */
+    int32_t fuse_z;             /* bit 0 (default on): the direction write with P_V fused with the line
+                                   search's forward z pass; bit 1 (default on): the energy
+                                   evaluation's last inverse z pass fused with the Hamiltonian
+                                   epilogue (with kin_axes).  A fused pass owns whole z pencils per
+                                   workgroup, so on small grids it launches fewer workgroups than the
+                                   chip has compute units; off, the grid-stride kernels run instead.
+                                   Same results up to rounding order.  Not used by
+                                   bec_batch_set_tuning */
 } bec_tuning;
 
 bec_status bec_get_tuning(bec_ctx* ctx, bec_tuning* out_h);

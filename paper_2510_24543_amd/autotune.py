@@ -3,7 +3,9 @@
 For every axis of a grid it times each FFT plan variant of the plain passes
 (forward + inverse) and, for the x axis, of the pass with the fused k-space
 operators (bec_time_fft_pass, HIP events); then it times whole PCG iterations
-(bec_solve) for each candidate grid size of the pointwise kernels.  The
+(bec_solve) for each candidate grid size of the pointwise kernels, for the
+kinetic-term switch, for the plans of the passes with fused work and for the
+fused z kernels against the grid-stride kernels they replace.  The
 fastest choices are set on the context and can be stored in a JSON cache keyed
 by device architecture and grid shape.  Every choice computes the same result
 up to rounding order.
@@ -105,6 +107,7 @@ def tune(ctx, reps: int = 20, iters: int = 8, psi0=None, opts: dict | None = Non
         return ev0.elapsed_time(ev1) / iters
 
     best["kin_axes"] = 1
+    best["fuse_z"] = 3
     iter_ms = {}
     for b in [c for c in PW_CHOICES if c <= cap] or [cap]:   # small grids: one block per 256 points
         best["pw_blocks"] = b
@@ -139,12 +142,24 @@ def tune(ctx, reps: int = 20, iters: int = 8, psi0=None, opts: dict | None = Non
             best["fft_variant"][axis][slot] = int(min(range(len(t)), key=t.__getitem__))
             axis_ms[f"axis{axis}" + (("_kspace" if axis == 0 else "_dirwrite") if slot else "")] = [round(x, 5) for x in t]
 
+    def choose_fuse_z():
+        # the pencil-owning fused z kernels against the grid-stride kernels they replace
+        # (bit 1 acts only with the one-axis kinetic terms): the fused ones move fewer
+        # bytes but launch a workgroup per few pencils, too few to fill the chip on small grids
+        t = {}
+        for f in ((3, 2, 1, 0) if best["kin_axes"] else (3, 2)):
+            best["fuse_z"] = f
+            t[f] = per_iter(best)
+        best["fuse_z"] = min(t, key=t.get)
+        axis_ms["fuse_z"] = {str(k): round(v, 5) for k, v in t.items()}
+
     choose_kin_axes("kin_axes")
     first = best["kin_axes"]
     sweep_variants()
     choose_kin_axes("kin_axes_recheck")          # with the tuned variants
     if best["kin_axes"] != first:
         sweep_variants()                          # the variants for the switch that won
+    choose_fuse_z()
     ctx.set_tuning(best)
     return {"tuning": best, "fft_ms": fft_ms, "iter_ms": {str(k): round(v, 5) for k, v in iter_ms.items()},
             "iter_ms_variants": axis_ms, "seconds": round(time.time() - t0, 3)}

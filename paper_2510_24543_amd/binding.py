@@ -80,7 +80,8 @@ class Report(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("fft_variant", (C.c_int32 * 2) * 3), ("pw_blocks", C.c_int32), ("lhy_table", C.c_int32),
-                ("lhy_terms", C.c_int32), ("kin_axes", C.c_int32)]
+                ("lhy_terms", C.c_int32), ("kin_axes", C.c_int32),
+                ("fuse_z", C.c_int32)]
 
 
 class Physical(C.Structure):

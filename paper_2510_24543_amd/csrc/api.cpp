@@ -270,6 +270,7 @@ struct bec_ctx {
     int lhy_K_built = 0;       // terms per series of the built table (0: none met the bar)
     int lhy_table_on = 1;      // tuning: use the table when built
     int kin_axes_on = 1;       // tuning: kinetic term of the energy evaluation from one-axis transforms
+    int fuse_z = 3;            // tuning: bit 0 fused direction write + z pass, bit 1 fused z pass + epilogue
     int nblk_pw = 0;
     // the last direction write: fused with the line search's z pass (its partials
     // then come from dir_nblk z-pass blocks and the model skips that pass)
@@ -926,7 +927,7 @@ bec_status heval_launch(bec_ctx* c, const double2* src, const double2* p, const 
     double2* fdst[3] = {c->W, c->W + N, c->aux[set]};
     const int ops[3] = {bec::kOpMulKin, bec::kOpMulKin, bec::kOpMulDip};
     bool z_left = false;
-    STCHK(kspace_apply_trial(c, z, fdst, ops, nullptr, &z_left));
+    STCHK(kspace_apply_trial(c, z, fdst, ops, nullptr, (c->fuse_z & 2) ? &z_left : nullptr));
     bec::HevalArgs ha{};
     ha.psi = c->psi[set];
     ha.Tpsi = c->W;
@@ -1073,13 +1074,13 @@ static_assert(bec::kIteSums <= kParsevalOut, "imaginary-time sums overlap the Pa
 static_assert(bec::kDirWriteSums + bec::kLsEpiSums <= bec::kMaxSums, "model partials exceed the partials area");
 static_assert(kParsevalOut + 2 <= kScalHeval, "Parseval slots overlap the energy sums");
 
-// Direction write pass (p, r, rho).  With P_V (zmode 1) it is fused with the
-// line search's forward z pass (the z-axis Parseval sums of p and the z
+// Direction write pass (p, r, rho).  With P_V (zmode 1) and fuse_z bit 0 it is
+// fused with the line search's forward z pass (the z-axis Parseval sums of p and the z
 // transform of the packed rho into W + 2N), which model_launch then skips.
 bec_status dir_write_launch(bec_ctx* c, const bec::DirArgs& A)
 {
     const double wb = 96.0 + (A.beta != 0.0 || A.dev_dir ? 32.0 : 0.0) + (A.zmode >= 2 ? 32.0 : 0.0) + 80.0;
-    if (A.zmode == 1) {
+    if (A.zmode == 1 && (c->fuse_z & 1)) {
         const long long N = c->N;
         bec::FftPassArgs Z = pass_args(c, 2);
         Z.nfield = 3;
@@ -1429,6 +1430,7 @@ bec_status bec_get_tuning(bec_ctx* c, bec_tuning* t)
     t->lhy_table = c->lhy_table_on;
     t->lhy_terms = c->P.lhy_K;
     t->kin_axes = c->kin_axes_on;
+    t->fuse_z = c->fuse_z;
     return BEC_OK;
 }
 
@@ -1441,6 +1443,7 @@ bec_status bec_set_tuning(bec_ctx* c, const bec_tuning* t)
                 return fail(BEC_EINVAL, "axis %d has no plan variant %d", a, t->fft_variant[a][k]);
     const long long cap = std::min<long long>((c->N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwMaxBlocks);
     if (t->pw_blocks < 1 || t->pw_blocks > cap) return fail(BEC_EINVAL, "pw_blocks must be in 1..%lld", cap);
+    if (t->fuse_z < 0 || t->fuse_z > 3) return fail(BEC_EINVAL, "fuse_z must be in 0..3");
     for (int a = 0; a < 3; ++a)
         for (int k = 0; k < 2; ++k) c->fft_var[a][k] = t->fft_variant[a][k];
     c->nblk_pw = t->pw_blocks;
@@ -1448,6 +1451,7 @@ bec_status bec_set_tuning(bec_ctx* c, const bec_tuning* t)
     c->lhy_table_on = t->lhy_table != 0;
     c->P.lhy_K = c->lhy_table_on ? c->lhy_K_built : 0;
     c->kin_axes_on = t->kin_axes != 0;
+    c->fuse_z = t->fuse_z;
     c->nblk_x = bec::fft_blocks(c->n[0], c->fft_var[0][1], (long long)c->n[1] * c->n[2]);
     return BEC_OK;
 }

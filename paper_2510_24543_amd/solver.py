@@ -205,7 +205,7 @@ class Context:
         B.check(B.lib().bec_get_tuning(self._ctx, C.byref(t)), "bec_get_tuning")
         return {"fft_variant": [[t.fft_variant[a][k] for k in range(2)] for a in range(3)],
                 "pw_blocks": t.pw_blocks, "lhy_table": t.lhy_table, "lhy_terms": t.lhy_terms,
-                "kin_axes": t.kin_axes}
+                "kin_axes": t.kin_axes, "fuse_z": t.fuse_z}
 
     def set_tuning(self, tuning: dict):
         t = B.Tuning()
@@ -215,6 +215,7 @@ class Context:
         t.pw_blocks = int(tuning["pw_blocks"])
         t.lhy_table = int(tuning.get("lhy_table", 1))
         t.kin_axes = int(tuning.get("kin_axes", 1))
+        t.fuse_z = int(tuning.get("fuse_z", 3))
         B.check(B.lib().bec_set_tuning(self._ctx, C.byref(t)), "bec_set_tuning")
 
     def time_fft_pass(self, axis: int, kind: int, variant: int, reps: int = 20) -> float:

@@ -187,6 +187,7 @@ def test_autotune_small_grids(solver, orc, shape):
     assert t["pw_blocks"] == res["tuning"]["pw_blocks"] <= (int(np.prod(shape)) + 255) // 256
     assert t["kin_axes"] in (0, 1) and len(res["iter_ms_variants"]["kin_axes"]) == 2
     assert len(res["iter_ms_variants"]["kin_axes_recheck"]) == 2
+    assert t["fuse_z"] in (0, 1, 2, 3) and str(t["fuse_z"]) in res["iter_ms_variants"]["fuse_z"]
     psi = _state(grid, params, 21, True)
     h, e = ctx.hamiltonian(torch.from_numpy(psi))
     to, ho, _, _ = orc.heval(grid, params, psi)
@@ -219,6 +220,40 @@ def test_kinetic_3d_multiply_path(solver, orc, case):
     assert rep["iters"] == repo["iters"]
     for a, b in zip(log, logo):
         assert abs(a["E"] - b["E"]) <= 1e-11 * abs(b["E"])
+
+
+@pytest.mark.parametrize("fuse_z", [0, 1, 2])
+def test_grid_stride_kernels_in_place_of_the_fused_z_kernels(solver, orc, fuse_z):
+    """fuse_z with a bit off (the autotuner's choice where the pencil-owning fused
+    z kernels leave the chip underfilled): the grid-stride direction write and
+    Hamiltonian epilogue with separate z passes, against the oracle: energy and
+    H psi, then four P_V steps of the solver (E to 1e-11, alpha, beta, E1, E2 to
+    1e-8, the same decisions)."""
+    grid, params = CASES["C1b"]
+    ctx = solver.Context(grid, params)
+    t = ctx.get_tuning()
+    assert t["fuse_z"] == 3
+    ctx.set_tuning(dict(t, fuse_z=fuse_z))
+    assert ctx.get_tuning()["fuse_z"] == fuse_z
+    psi = _state(grid, params, 23, True)
+    h, e = ctx.hamiltonian(torch.from_numpy(psi))
+    to, ho, _, _ = orc.heval(grid, params, psi)
+    assert abs(e["E"] - to["E"]) <= 1e-12 * abs(to["E"])
+    assert rel(h.cpu().numpy(), ho) < 1e-11
+    psi0 = inputs.initial_state(grid, params["omega"], 46, phase=True)
+    opts = {"tol_grad": 0.0, "max_iter": 4, "pc": 1}
+    _, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=4)
+    _, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=4)
+    assert rep["iters"] == repo["iters"] == 4
+    for k in range(4):
+        a, b = log[k], logo[k]
+        for key in ("n_trials", "restarted", "path"):
+            assert a[key] == b[key], (k, key)
+        assert abs(a["E"] - b["E"]) <= 1e-11 * abs(b["E"]), k
+        for key in ("alpha", "beta", "E1", "E2"):
+            assert abs(a[key] - b[key]) <= 1e-8 * max(abs(b[key]), 1e-300), (k, key)
+    with pytest.raises(RuntimeError):
+        ctx.set_tuning(dict(t, fuse_z=4))
 
 
 @pytest.mark.parametrize("case", ["C1b", "mixedN"])
