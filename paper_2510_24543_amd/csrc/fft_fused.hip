@@ -21,6 +21,10 @@
 //    potentials Phi_1 + i Phi_2; the workgroup inverts their z pencils in
 //    registers, stores Phi and evaluates H psi, muLHY and the energy sums at
 //    the same points, so Phi is written once and never read back.
+//
+// On plans of at most 8 points per thread the direction write loads the
+// operands of a thread's next point before computing the current one, so that
+// a wave keeps loads in flight through the per-point arithmetic.
 #include "pw_point.h"
 #include "fft_core.h"
 
@@ -30,8 +34,15 @@ namespace {
 using namespace fftcore;
 using namespace pwpt;
 
+// Plans with at most 8 points per thread load the operands of the next point
+// before the current one is computed (register budget of two waves per SIMD);
+// larger ones keep one point's operands at a time.
+template <int L, int T>
+constexpr bool dirwrite_prefetch() { return L / T <= 8; }
+
 template <int L, int T, int R0, int R1, int R2, int NTHR, bool LHY>
-__global__ __launch_bounds__(NTHR) void fft_dirwrite_z_kernel(FftPassArgs Z, PwParams P, DirArgs A)
+__global__ __launch_bounds__(NTHR, (dirwrite_prefetch<L, T>() ? 2 : 1)) void fft_dirwrite_z_kernel(FftPassArgs Z,
+                                                                                                PwParams P, DirArgs A)
 {
     using PL = Plan<L, T, R0, R1, R2, true>;
     constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>(), RL = PL::RL, M = kDirWriteSums;
@@ -56,23 +67,25 @@ __global__ __launch_bounds__(NTHR) void fft_dirwrite_z_kernel(FftPassArgs Z, PwP
 #pragma unroll
     for (int m = 0; m < M + 2; ++m) acc[m] = 0.0;
     double2 v0[E], v1[E], v2[E];
+    constexpr bool PF = dirwrite_prefetch<L, T>();
+    auto pt_index = [&](int k) { return base + t + (k / R0) * T + (k % R0) * (L / R0); };
+    DirIn<1> nxt{};
+    if (PF && valid) nxt = dir_load<1>(P, A, N, pt_index(0), with_p);
 #pragma unroll
-    for (int b = 0; b < E / R0; ++b)
-#pragma unroll
-        for (int r = 0; r < R0; ++r) {
-            const int k = b * R0 + r;
-            v0[k] = v1[k] = v2[k] = make_double2(0.0, 0.0);
-            if (valid) {
-                const long long i = base + t + b * T + r * (L / R0);
-                const DirIn<1> cur = dir_load<1>(A, N, i, with_p);
-                double2 pp[2];
-                double rr[2];
-                dir_point<1, LHY>(P, A, N, i, cur, acc, pp, rr);
-                v0[k] = pp[0];
-                v1[k] = pp[1];
-                v2[k] = make_double2(rr[0], rr[1]);
-            }
+    for (int k = 0; k < E; ++k) {
+        v0[k] = v1[k] = v2[k] = make_double2(0.0, 0.0);
+        DirIn<1> cur = nxt;
+        if (PF && valid && k + 1 < E) nxt = dir_load<1>(P, A, N, pt_index(k + 1), with_p);
+        if (!PF && valid) cur = dir_load<1>(P, A, N, pt_index(k), with_p);
+        if (valid) {
+            double2 pp[2];
+            double rr[2];
+            dir_point<1, LHY>(P, A, N, pt_index(k), cur, acc, pp, rr);
+            v0[k] = pp[0];
+            v1[k] = pp[1];
+            v2[k] = make_double2(rr[0], rr[1]);
         }
+    }
 
     // one-axis Parseval sums of p_1, p_2 along z, then the packed density's transform
     const double dk = Z.kaxis[1];

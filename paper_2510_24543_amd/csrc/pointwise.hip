@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kPwThreads) void dir_write_kernel(PwParams P, DirAr
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             k[u] = i + u * stride < N ? i + u * stride : i;
-            cur[u] = dir_load<ZM>(A, N, k[u], with_p);
+            cur[u] = dir_load<ZM>(P, A, N, k[u], with_p);
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {

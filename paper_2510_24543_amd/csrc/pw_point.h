@@ -23,6 +23,19 @@ __device__ __forceinline__ double trap_at(const PwParams& P, long long i)
     return P.vx[ix] + P.vy[iy] + P.vz[iz];
 }
 
+// the three table values of trap_at, unsummed
+__device__ __forceinline__ void trap_parts(const PwParams& P, long long i, double* v)
+{
+    const uint32_t ii = (uint32_t)i;
+    const uint32_t ix = (uint32_t)(((uint64_t)ii * P.m_nyz) >> P.s_nyz);
+    const uint32_t rem = ii - ix * (uint32_t)(P.ny * P.nz);
+    const uint32_t iy = (uint32_t)(((uint64_t)rem * P.m_nz) >> P.s_nz);
+    const uint32_t iz = rem - iy * (uint32_t)P.nz;
+    v[0] = P.vx[ix];
+    v[1] = P.vy[iy];
+    v[2] = P.vz[iz];
+}
+
 // node constants read from the kernel-argument block (scalar loads)
 struct KernargNodes {
     const PwParams& P;
@@ -81,12 +94,16 @@ __device__ __forceinline__ double pv_inv(const PwParams& P, int c, double shift,
 template <int ZM>
 struct DirIn {
     double2 s[2], h[2], ph, ml, po[2], zb[2];
+    double vt[3];   // the trap potential's x, y and z table values (summed where used, so the
+                    // loads of a prefetched point are not waited for early)
 };
 
 template <int ZM>
-__device__ __forceinline__ DirIn<ZM> dir_load(const DirArgs& A, long long N, long long i, bool with_p)
+__device__ __forceinline__ DirIn<ZM> dir_load(const PwParams& P, const DirArgs& A, long long N, long long i,
+                                              bool with_p)
 {
     DirIn<ZM> v;
+    trap_parts(P, i, v.vt);
     v.s[0] = A.psi[i];
     v.s[1] = A.psi[N + i];
     v.h[0] = A.hpsi[i];
@@ -118,7 +135,7 @@ __device__ __forceinline__ void dir_point(const PwParams& P, const DirArgs& A, l
 #pragma unroll
     for (int c = 0; c < 2; ++c) r[c] = make_double2(cur.h[c].x - A.mu[c] * s[c].x, cur.h[c].y - A.mu[c] * s[c].y);
     const double n[2] = {sq2(s[0]), sq2(s[1])};
-    const double V = trap_at(P, i);
+    const double V = cur.vt[0] + cur.vt[1] + cur.vt[2];
     const double mlc[2] = {cur.ml.x, cur.ml.y};
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
