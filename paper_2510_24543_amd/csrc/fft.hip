@@ -47,7 +47,8 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
 {
     static_assert(!WLOC || (T <= 64 && 64 % T == 0 && NTHR % 64 == 0), "wave-local pencils");
     using PL = Plan<L, T, R0, R1, R2, CONTIG || WLOC>;
-    constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>(), PW = WLOC ? 64 / T : 1;
+    constexpr int E = L / T, PB = NTHR / T, PW = WLOC ? 64 / T : 1;
+    constexpr int RS = WLOC ? lds_row_wave<L, PW>() : lds_row<L>();
     __shared__ double2 lds[PB * RS];
     const int f = KMODE == 2 ? A.forder[blockIdx.y] : (int)blockIdx.y;
     const int inst = A.inst_ids ? A.inst_ids[blockIdx.z] : (int)blockIdx.z;

@@ -169,6 +169,23 @@ __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
 template <int L>
 constexpr int lds_row() { return L + L / 8 + 1; }
 
+// Row stride for PW pencils per wavefront side by side on the strided axes
+// (lane = t PW + pencil): a 16-byte LDS access serves 8 lanes per cycle, i.e.
+// 8 / PW element indices t of each of PW pencils when PW < 8.  A stride of
+// 8 / PW modulo 8 (in 16-byte units) puts those lanes on distinct banks for the
+// stride-R writes and unit-stride reads of the exchanges (an odd stride when
+// PW >= 8, where the 8 lanes are 8 pencils at the same index).
+template <int L, int PW>
+constexpr int lds_row_wave()
+{
+    if constexpr (PW >= 8) {
+        return lds_row<L>() % 2 ? lds_row<L>() : lds_row<L>() + 1;
+    } else {
+        constexpr int base = L + L / 8;              // > lds_pad(L - 1)
+        return base + ((8 / PW - base % 8) % 8 + 8) % 8;
+    }
+}
+
 // Ordering of an LDS exchange among the threads of one pencil.  WAVE: the
 // pencil's threads lie in one wavefront (the contiguous z passes: consecutive
 // lanes take consecutive elements of a pencil and T divides 64), whose LDS
