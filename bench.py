@@ -54,7 +54,8 @@ LABEL_KERNEL = {"dir_write": "dir_write_kernel<1, true, 1>", "dir_write_z": "fft
 # sources whose change invalidates the stored counter figures of the pointwise kernels
 KERNEL_SOURCES = ["paper_2510_24543_amd/csrc/pointwise.hip", "paper_2510_24543_amd/csrc/pw_math.h",
                   "paper_2510_24543_amd/csrc/bec_internal.h", "paper_2510_24543_amd/csrc/pw_point.h",
-                  "paper_2510_24543_amd/csrc/fft_fused.hip", "paper_2510_24543_amd/csrc/fft_core.h"]
+                  "paper_2510_24543_amd/csrc/fft_fused.hip", "paper_2510_24543_amd/csrc/fft_core.h",
+                  "paper_2510_24543_amd/csrc/fft_dirwrite.h", "paper_2510_24543_amd/csrc/fft_fused_composite.hip"]
 
 
 def kernel_source_hash() -> str:

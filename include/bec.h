@@ -349,7 +349,7 @@ bec_status bec_batch_solve(bec_batch* b, double* const* psi_inout, const bec_opt
  * ------------------------------------------------------------------------- */
 typedef struct {
     int32_t fft_variant[3][2];  /* per axis (x, y, z): [0] plain passes; [0][1] the x pass with the
-                                   fused k-space operator; [2][1] the direction write (P_V) fused
+                                   fused k-space operator; [2][1] the direction write (P_V, composite) fused
                                    with the line search's forward z pass; [1][1] unused;
                                    0 = default plan */
     int32_t pw_blocks;          /* workgroups of the pointwise kernels (64 .. 4096) */
@@ -363,8 +363,8 @@ typedef struct {
                                    y and x passes; 0: the 3D multiply in the x pass (fewer
                                    transforms per pencil: faster on small, launch-bound grids).
                                    Not used by bec_batch_set_tuning */
-    int32_t fuse_z;             /* bit 0 (default on): the direction write with P_V fused with the line
-                                   search's forward z pass; bit 1 (default on): the energy
+    int32_t fuse_z;             /* bit 0 (default on): the direction write with P_V or the composite
+                                   P_Delta^-1 P_V^-1 fused with the line search's forward z pass; bit 1 (default on): the energy
                                    evaluation's last inverse z pass fused with the Hamiltonian
                                    epilogue (with kin_axes).  A fused pass owns whole z pencils per
                                    workgroup, so on small grids it launches fewer workgroups than the

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIB_DIR, "libbecpcg.so")
-SOURCES = ["fft.hip", "fft_fused.hip", "pointwise.hip", "batch.hip", "api.cpp"]
+SOURCES = ["fft.hip", "fft_fused.hip", "fft_fused_composite.hip", "pointwise.hip", "batch.hip", "api.cpp"]
 ARCH = os.environ.get("BEC_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code.

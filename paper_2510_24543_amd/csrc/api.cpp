@@ -1074,13 +1074,13 @@ static_assert(bec::kIteSums <= kParsevalOut, "imaginary-time sums overlap the Pa
 static_assert(bec::kDirWriteSums + bec::kLsEpiSums <= bec::kMaxSums, "model partials exceed the partials area");
 static_assert(kParsevalOut + 2 <= kScalHeval, "Parseval slots overlap the energy sums");
 
-// Direction write pass (p, r, rho).  With P_V (zmode 1) and fuse_z bit 0 it is
-// fused with the line search's forward z pass (the z-axis Parseval sums of p and the z
+// Direction write pass (p, r, rho).  With P_V or the composite (zmode 1, 2) and
+// fuse_z bit 0 it is fused with the line search's forward z pass (the z-axis Parseval sums of p and the z
 // transform of the packed rho into W + 2N), which model_launch then skips.
 bec_status dir_write_launch(bec_ctx* c, const bec::DirArgs& A)
 {
     const double wb = 96.0 + (A.beta != 0.0 || A.dev_dir ? 32.0 : 0.0) + (A.zmode >= 2 ? 32.0 : 0.0) + 80.0;
-    if (A.zmode == 1 && (c->fuse_z & 1)) {
+    if ((A.zmode == 1 || A.zmode == 2) && (c->fuse_z & 1)) {
         const long long N = c->N;
         bec::FftPassArgs Z = pass_args(c, 2);
         Z.nfield = 3;

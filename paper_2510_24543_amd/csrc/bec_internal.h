@@ -278,7 +278,7 @@ hipError_t launch_heval_epi(const PwParams& P, const HevalArgs& a, int nblk, hip
 hipError_t launch_ite_epi(const PwParams& P, const IteArgs& a, int nblk, hipStream_t s);
 hipError_t launch_dir_reduce(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s);
 hipError_t launch_dir_write(const PwParams& P, const DirArgs& a, int nblk, hipStream_t s);
-// The direction write (zmode 1 only) fused with the line search's forward z pass:
+// The direction write (zmode 1 or 2) fused with the line search's forward z pass:
 // p, r, rho and the kDirWriteSums sums as launch_dir_write (sums into
 // a.partials [sum][block], grid = fft_blocks(L, variant, z.npencil) blocks),
 // plus the z-axis Parseval sums of p_1, p_2 (z.partials[f * z.nblk_x + block]
@@ -286,6 +286,9 @@ hipError_t launch_dir_write(const PwParams& P, const DirArgs& a, int nblk, hipSt
 // z.dst[2].  z: a z-axis pass of the grid (tw, kaxis, npencil, S = 1).
 hipError_t fft_dirwrite_z_pass(int L, int variant, const FftPassArgs& z, const PwParams& P, const DirArgs& a,
                                hipStream_t s);
+// its zmode 2 instantiations (fft_fused_composite.hip)
+hipError_t fft_dirwrite_z_pass_composite(int L, int variant, const FftPassArgs& z, const PwParams& P,
+                                         const DirArgs& a, hipStream_t s);
 // The last inverse z pass of the energy evaluation fused with the Hamiltonian
 // epilogue: z.src[0] (= h.aux, in place) holds the packed Phi spectrum after
 // the y inverse pass; stores Phi and H psi, muLHY into h.hpsi, h.aux and the

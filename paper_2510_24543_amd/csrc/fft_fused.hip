@@ -1,19 +1,11 @@
 // Pointwise passes fused with a z transform, for gfx950 (arXiv:2510.24543).
 //
 // 1. The direction-write pass fused with the first forward transform of the
-//    line search (Sec. IV.C, Sec. V).
-// A workgroup owns whole z pencils.  Each thread computes, at the points of its
-// pencil slots, what the grid-stride direction write computes there (the
-// direction p = d - Re<d,psi> psi with d = -z + beta p_old, the residual r,
-// rho_i = Re(conj(psi_i) p_i) and the model sums), stores p, r and rho as that
-// pass does, and keeps p_1, p_2 and the packed rho_1 + i rho_2 in registers.
-// It then transforms them along z: the one-axis Parseval sums of p_i
-// (<p_i, T_z p_i> by |k_z|^2/2 |p^_i|^2, no store) and the forward z transform
-// of the packed density, which the line search's y pass continues.  The
-// separate z pass of the line search -- a second read of p and rho -- is gone.
-//
-// P_V (zmode 1) only, the benchmark's and the paper's recommended
-// preconditioner; the other modes keep the two-kernel form.
+//    line search (Sec. IV.C, Sec. V), kernel in fft_dirwrite.h: P_V (zmode 1),
+//    the benchmark's and the paper's recommended preconditioner, instantiated
+//    here; the composite P_Delta^-1 P_V^-1 (zmode 2: z read from the k-space
+//    passes' output) in fft_fused_composite.hip; the other modes keep the
+//    two-kernel form.
 //
 // 2. The Hamiltonian epilogue fused with the last inverse transform of the
 //    energy evaluation (Sec. II, Eq. (6)): with the kinetic term taken from
@@ -21,115 +13,10 @@
 //    potentials Phi_1 + i Phi_2; the workgroup inverts their z pencils in
 //    registers, stores Phi and evaluates H psi, muLHY and the energy sums at
 //    the same points, so Phi is written once and never read back.
-//
-// On plans of at most 8 points per thread the direction write loads the
-// operands of a thread's next point before computing the current one, so that
-// a wave keeps loads in flight through the per-point arithmetic.
-#include "pw_point.h"
-#include "fft_core.h"
+#include "fft_dirwrite.h"
 
 namespace bec {
 namespace {
-
-using namespace fftcore;
-using namespace pwpt;
-
-// Plans with at most 8 points per thread load the operands of the next point
-// before the current one is computed (register budget of two waves per SIMD);
-// larger ones keep one point's operands at a time.
-template <int L, int T>
-constexpr bool dirwrite_prefetch() { return L / T <= 8; }
-
-template <int L, int T, int R0, int R1, int R2, int NTHR, bool LHY>
-__global__ __launch_bounds__(NTHR, (dirwrite_prefetch<L, T>() ? 2 : 1)) void fft_dirwrite_z_kernel(FftPassArgs Z,
-                                                                                                PwParams P, DirArgs A)
-{
-    using PL = Plan<L, T, R0, R1, R2, true>;
-    constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>(), RL = PL::RL, M = kDirWriteSums;
-    constexpr int NW = NTHR / 64;
-    static_assert((M + 2) * NW * sizeof(double) <= PB * RS * sizeof(double2), "reduction fits the LDS rows");
-    __shared__ double2 lds[PB * RS];
-    if (A.dev_state) rule_mu_shift(A.dev_state, P.Gdd, A.mu, A.diag_shift);
-    if (A.dev_dir) {
-        A.beta = rule_beta(A.dev_dir, A.rule);
-        rule_proj(A.dev_dir, A.beta, A.rule.dV, A.c);
-    }
-    const bool with_p = A.beta != 0.0;
-    const long long N = P.N;
-    const int tid = threadIdx.x;
-    const int pl = tid / T, t = tid % T;
-    const long long pg = (long long)blockIdx.x * PB + pl;
-    const bool valid = pg < Z.npencil;
-    const long long base = valid ? pg * (long long)L : 0;
-    double2* row = lds + pl * RS;
-
-    double acc[M + 2];
-#pragma unroll
-    for (int m = 0; m < M + 2; ++m) acc[m] = 0.0;
-    double2 v0[E], v1[E], v2[E];
-    constexpr bool PF = dirwrite_prefetch<L, T>();
-    auto pt_index = [&](int k) { return base + t + (k / R0) * T + (k % R0) * (L / R0); };
-    DirIn<1> nxt{};
-    if (PF && valid) nxt = dir_load<1>(P, A, N, pt_index(0), with_p);
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-        v0[k] = v1[k] = v2[k] = make_double2(0.0, 0.0);
-        DirIn<1> cur = nxt;
-        if (PF && valid && k + 1 < E) nxt = dir_load<1>(P, A, N, pt_index(k + 1), with_p);
-        if (!PF && valid) cur = dir_load<1>(P, A, N, pt_index(k), with_p);
-        if (valid) {
-            double2 pp[2];
-            double rr[2];
-            dir_point<1, LHY>(P, A, N, pt_index(k), cur, acc, pp, rr);
-            v0[k] = pp[0];
-            v1[k] = pp[1];
-            v2[k] = make_double2(rr[0], rr[1]);
-        }
-    }
-
-    // one-axis Parseval sums of p_1, p_2 along z, then the packed density's transform
-    const double dk = Z.kaxis[1];
-    double2* vs[2] = {v0, v1};
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        PL::template fwd_like<-1>(vs[c], row, t, Z.tw);
-        double s = 0.0;
-#pragma unroll
-        for (int b = 0; b < E / RL; ++b)
-#pragma unroll
-            for (int r = 0; r < RL; ++r) {
-                const double k = kwave<L>(dk, t + b * T + r * (L / RL));
-                const double2 w = vs[c][b * RL + r];
-                s += 0.5 * (k * k) * (w.x * w.x + w.y * w.y);
-            }
-        acc[M + c] = valid ? s : 0.0;
-    }
-    PL::template fwd_like<-1>(v2, row, t, Z.tw);
-    if (valid) {
-        double2* d = Z.dst[2];
-#pragma unroll
-        for (int b = 0; b < E / RL; ++b)
-#pragma unroll
-            for (int r = 0; r < RL; ++r) d[base + t + b * T + r * (L / RL)] = v2[b * RL + r];
-    }
-
-    // fixed-order block reduction: the M direction sums into A.partials
-    // [m][block], the two Parseval sums into Z.partials [field][block]
-    double* sh = reinterpret_cast<double*>(lds);
-    const int lane = tid & 63, w = tid >> 6;
-    __syncthreads();
-    wave_sum_down(acc);
-    if (lane == 0)
-#pragma unroll
-        for (int m = 0; m < M + 2; ++m) sh[m * NW + w] = acc[m];
-    __syncthreads();
-    if (tid < M + 2) {
-        double s = 0.0;
-        for (int k = 0; k < NW; ++k) s += sh[tid * NW + k];
-        if (tid < M) A.partials[(long long)tid * gridDim.x + blockIdx.x] = s;
-        else Z.partials[(long long)(tid - M) * Z.nblk_x + blockIdx.x] = s * Z.pscale;
-    }
-}
 
 template <int L, int T, int R0, int R1, int R2, int NTHR>
 __global__ __launch_bounds__(NTHR) void fft_heval_z_kernel(FftPassArgs Z, PwParams P, HevalArgs H)
@@ -209,18 +96,8 @@ hipError_t fft_heval_z_pass(int L, int variant, const FftPassArgs& Z, const PwPa
 hipError_t fft_dirwrite_z_pass(int L, int variant, const FftPassArgs& Z, const PwParams& P, const DirArgs& A,
                                hipStream_t st)
 {
-    if (Z.S != 1 || A.zmode != 1 || !Z.partials || !Z.kaxis) return hipErrorInvalidValue;
-#define BEC_DCASE(LL, VV, T, R0, R1, R2, NT, W)                                                              \
-    if (L == LL && variant == VV) {                                                                           \
-        const dim3 grid((unsigned)((Z.npencil + NT / T - 1) / (NT / T)));                                     \
-        if (P.lhy_on)                                                                                         \
-            hipLaunchKernelGGL((fft_dirwrite_z_kernel<LL, T, R0, R1, R2, NT, true>), grid, dim3(NT), 0, st, Z, P, A); \
-        else                                                                                                  \
-            hipLaunchKernelGGL((fft_dirwrite_z_kernel<LL, T, R0, R1, R2, NT, false>), grid, dim3(NT), 0, st, Z, P, A); \
-        return hipGetLastError();                                                                             \
-    }
-    BEC_FFT_VARIANTS(BEC_DCASE)
-#undef BEC_DCASE
+    if (A.zmode == 1) return dirwrite_z_launch<1>(L, variant, Z, P, A, st);
+    if (A.zmode == 2) return fft_dirwrite_z_pass_composite(L, variant, Z, P, A, st);
     return hipErrorInvalidValue;
 }
 

@@ -241,17 +241,18 @@ def test_grid_stride_kernels_in_place_of_the_fused_z_kernels(solver, orc, fuse_z
     assert abs(e["E"] - to["E"]) <= 1e-12 * abs(to["E"])
     assert rel(h.cpu().numpy(), ho) < 1e-11
     psi0 = inputs.initial_state(grid, params["omega"], 46, phase=True)
-    opts = {"tol_grad": 0.0, "max_iter": 4, "pc": 1}
-    _, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=4)
-    _, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=4)
-    assert rep["iters"] == repo["iters"] == 4
-    for k in range(4):
-        a, b = log[k], logo[k]
-        for key in ("n_trials", "restarted", "path"):
-            assert a[key] == b[key], (k, key)
-        assert abs(a["E"] - b["E"]) <= 1e-11 * abs(b["E"]), k
-        for key in ("alpha", "beta", "E1", "E2"):
-            assert abs(a[key] - b[key]) <= 1e-8 * max(abs(b[key]), 1e-300), (k, key)
+    for pc in (1, 3):     # P_V and the composite (z from the k-space passes)
+        opts = {"tol_grad": 0.0, "max_iter": 4, "pc": pc}
+        _, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=4)
+        _, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=4)
+        assert rep["iters"] == repo["iters"] == 4
+        for k in range(4):
+            a, b = log[k], logo[k]
+            for key in ("n_trials", "restarted", "path"):
+                assert a[key] == b[key], (pc, k, key)
+            assert abs(a["E"] - b["E"]) <= 1e-11 * abs(b["E"]), (pc, k)
+            for key in ("alpha", "beta", "E1", "E2"):
+                assert abs(a[key] - b[key]) <= 1e-8 * max(abs(b[key]), 1e-300), (pc, k, key)
     with pytest.raises(RuntimeError):
         ctx.set_tuning(dict(t, fuse_z=4))
 
@@ -335,21 +336,23 @@ def test_blended_preconditioner(solver, orc, case, blend):
 
 
 @pytest.mark.parametrize("n", [8, 16, 32, 48, 64, 96, 128, 256])
-def test_every_variant_of_the_fused_direction_write(solver, orc, n):
-    """The direction write with P_V fused with the line search's forward z pass
-    (tuning slot [2][1]) in every plan variant of a z axis n long: four P_V
-    steps of the solver against the oracle's, step by step (E to 1e-11, alpha,
-    beta, E1, E2 to 1e-8, the same decisions)."""
+@pytest.mark.parametrize("pc", [1, 3, 2])
+def test_every_variant_of_the_fused_direction_write(solver, orc, n, pc):
+    """The direction write fused with the line search's forward z pass (tuning
+    slot [2][1]) in every plan variant of a z axis n long, with P_V (pc 1) and
+    with z from the k-space passes (pc 3 the composite P_Delta^-1 P_V^-1, pc 2
+    P_Delta^-1): four steps of the solver against the oracle's, step by step
+    (E to 1e-11, alpha, beta, E1, E2 to 1e-8, the same decisions)."""
     from paper_2510_24543_amd import autotune
     params = small_params()
     grid = {"n": [8, 16, n], "lo": [-6.0] * 3, "hi": [6.0] * 3}
     psi0 = inputs.initial_state(grid, params["omega"], 45, phase=True)
-    opts = {"tol_grad": 0.0, "max_iter": 4, "pc": 1}
+    opts = {"tol_grad": 0.0, "max_iter": 4, "pc": pc}
     _, repo, logo = orc.solve(grid, params, psi0, opts, log_cap=4)
     ctx = solver.Context(grid, params)
     base = ctx.get_tuning()
     for v in range(autotune.variant_count(n)):
-        print(f"n {n} fused direction-write variant {v}", flush=True)
+        print(f"n {n} pc {pc} fused direction-write variant {v}", flush=True)
         t = {"fft_variant": [r_[:] for r_ in base["fft_variant"]], "pw_blocks": base["pw_blocks"]}
         t["fft_variant"][2][1] = v
         ctx.set_tuning(t)
