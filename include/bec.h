@@ -364,7 +364,9 @@ typedef struct {
                                    transforms per pencil: faster on small, launch-bound grids).
                                    Not used by bec_batch_set_tuning */
     int32_t fuse_z;             /* bit 0 (default on): the direction write with P_V or the composite
-                                   P_Delta^-1 P_V^-1 fused with the line search's forward z pass; bit 1 (default on): the energy
+                                   P_Delta^-1 P_V^-1 fused with the line search's forward z pass,
+                                   and the input of the k-space preconditioners formed in their
+                                   first forward z pass; bit 1 (default on): the energy
                                    evaluation's last inverse z pass fused with the Hamiltonian
                                    epilogue (with kin_axes).  A fused pass owns whole z pencils per
                                    workgroup, so on small grids it launches fewer workgroups than the

@@ -1052,12 +1052,19 @@ bec_status compute_z(bec_ctx* c, int set, const Eval& ev, const double2* rin, in
     m.apply_pv = apply_pv;
     m.out = out;
     m.dev_state = dev_state;
-    LAUNCH(c, "make_r", (double)c->N * 112.0, bec::launch_make_r(c->P, m, c->st));
     const long long N = c->N;
     const double2* src[2] = {out, out + N};
     double2* dst[2] = {out, out + N};
     const int ops[2] = {bec::kOpMulPrec, bec::kOpMulPrec};
     const double pa[2] = {std::max(ev.t.shift[0], 0.0) + sigma, std::max(ev.t.shift[1], 0.0) + sigma};
+    if (!rin && apply_pv <= 2 && (c->fuse_z & 1)) {   // make_r and the first z pass in one kernel
+        bec::FftPassArgs Z = pass_args(c, 2);
+        Z.tw = c->tw[2];
+        LAUNCH(c, "make_r_z", (double)N * (apply_pv ? 112.0 : 96.0),
+               bec::fft_maker_z_pass(c->n[2], c->fft_var[2][0], Z, c->P, m, c->st));
+        return kspace_after_z(c, dst, 2, ops, pa, dev_state, sigma);
+    }
+    LAUNCH(c, "make_r", (double)N * 112.0, bec::launch_make_r(c->P, m, c->st));
     return kspace_apply(c, src, dst, 2, ops, pa, dev_state, sigma);
 }
 

@@ -286,6 +286,12 @@ hipError_t launch_dir_write(const PwParams& P, const DirArgs& a, int nblk, hipSt
 // z.dst[2].  z: a z-axis pass of the grid (tw, kaxis, npencil, S = 1).
 hipError_t fft_dirwrite_z_pass(int L, int variant, const FftPassArgs& z, const PwParams& P, const DirArgs& a,
                                hipStream_t s);
+// The make_r pass (rin = null, apply_pv 0..2) fused with the forward z pass of
+// the k-space preconditioner that follows: a.out (2N) receives the residual
+// input already transformed along z.  z: a z-axis pass of the grid (tw,
+// npencil, S = 1).
+hipError_t fft_maker_z_pass(int L, int variant, const FftPassArgs& z, const PwParams& P, const MakeRArgs& a,
+                            hipStream_t s);
 // its zmode 2 instantiations (fft_fused_composite.hip)
 hipError_t fft_dirwrite_z_pass_composite(int L, int variant, const FftPassArgs& z, const PwParams& P,
                                          const DirArgs& a, hipStream_t s);

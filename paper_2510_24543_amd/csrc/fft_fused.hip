@@ -13,6 +13,9 @@
 //    potentials Phi_1 + i Phi_2; the workgroup inverts their z pencils in
 //    registers, stores Phi and evaluates H psi, muLHY and the energy sums at
 //    the same points, so Phi is written once and never read back.
+//
+// 3. The input of the k-space preconditioners fused with their first forward
+//    z transform (Sec. IV.B).
 #include "fft_dirwrite.h"
 
 namespace bec {
@@ -76,7 +79,64 @@ __global__ __launch_bounds__(NTHR) void fft_heval_z_kernel(FftPassArgs Z, PwPara
     }
 }
 
+// 3. The input of the k-space preconditioners fused with their first forward
+//    transform (Sec. IV.B): the residual, times P_V^-1 for the composite
+//    (apply_pv 1) or D^-1/2 for the symmetrised form (apply_pv 2), computed at
+//    the points of whole z pencils and transformed along z in registers; the
+//    field is written once, already z-transformed, for the y pass that follows.
+template <int L, int T, int R0, int R1, int R2, int NTHR>
+__global__ __launch_bounds__(NTHR) void fft_maker_z_kernel(FftPassArgs Z, PwParams P, MakeRArgs A)
+{
+    using PL = Plan<L, T, R0, R1, R2, true>;
+    constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>(), RL = PL::RL;
+    __shared__ double2 lds[PB * RS];
+    if (A.dev_state) rule_mu_shift(A.dev_state, P.Gdd, A.mu, A.diag_shift);
+    const long long N = P.N;
+    const int tid = threadIdx.x;
+    const int pl = tid / T, t = tid % T;
+    const long long pg = (long long)blockIdx.x * PB + pl;
+    const bool valid = pg < Z.npencil;
+    const long long base = valid ? pg * (long long)L : 0;
+    double2* row = lds + pl * RS;
+    double2 v0[E], v1[E];
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = b * R0 + r;
+            v0[k] = v1[k] = make_double2(0.0, 0.0);
+            if (valid) make_r_point(P, A, N, base + t + b * T + r * (L / R0), v0[k], v1[k]);
+        }
+    PL::template fwd_like<-1>(v0, row, t, Z.tw);
+    PL::template fwd_like<-1>(v1, row, t, Z.tw);
+    if (valid) {
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const long long i = base + t + b * T + r * (L / RL);
+                A.out[i] = v0[b * RL + r];
+                A.out[N + i] = v1[b * RL + r];
+            }
+    }
+}
+
 }  // namespace
+
+hipError_t fft_maker_z_pass(int L, int variant, const FftPassArgs& Z, const PwParams& P, const MakeRArgs& A,
+                            hipStream_t st)
+{
+    if (Z.S != 1 || !A.out || A.rin || A.apply_pv < 0 || A.apply_pv > 2) return hipErrorInvalidValue;
+#define BEC_MCASE(LL, VV, T, R0, R1, R2, NT, W)                                                              \
+    if (L == LL && variant == VV) {                                                                           \
+        const dim3 grid((unsigned)((Z.npencil + NT / T - 1) / (NT / T)));                                     \
+        hipLaunchKernelGGL((fft_maker_z_kernel<LL, T, R0, R1, R2, NT>), grid, dim3(NT), 0, st, Z, P, A);       \
+        return hipGetLastError();                                                                             \
+    }
+    BEC_FFT_VARIANTS(BEC_MCASE)
+#undef BEC_MCASE
+    return hipErrorInvalidValue;
+}
 
 hipError_t fft_heval_z_pass(int L, int variant, const FftPassArgs& Z, const PwParams& P, const HevalArgs& H,
                             hipStream_t st)

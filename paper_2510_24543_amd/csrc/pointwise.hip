@@ -279,37 +279,8 @@ __global__ __launch_bounds__(kPwThreads) void make_r_kernel(PwParams P, MakeRArg
     const long long N = P.N;
     GRID_STRIDE(i, N)
     {
-        const double2 s1 = A.psi[i], s2 = A.psi[N + i];
         double2 r1, r2;
-        if (A.rin) {
-            r1 = A.rin[i];
-            r2 = A.rin[N + i];
-        } else {
-            const double2 h1 = A.hpsi[i], h2 = A.hpsi[N + i];
-            r1 = make_double2(h1.x - A.mu[0] * s1.x, h1.y - A.mu[0] * s1.y);
-            r2 = make_double2(h2.x - A.mu[1] * s2.x, h2.y - A.mu[1] * s2.y);
-        }
-        if (A.apply_pv) {
-            const double n1 = sq2(s1), n2 = sq2(s2);
-            const double V = trap_at(P, i);
-            const double2 ml = A.aux[N + i];
-            double g1 = pv_inv(P, 0, A.diag_shift[0], A.sigma, V, n1, n2, ml.x);
-            double g2 = pv_inv(P, 1, A.diag_shift[1], A.sigma, V, n1, n2, ml.y);
-            if (A.apply_pv == 2) {
-                g1 = sqrt(g1);
-                g2 = sqrt(g2);
-            }
-            if (A.apply_pv == 3) {   // blend with the kinetic preconditioner's output zk
-                const double a1 = A.blend_w[0] * g1, b1 = 1.0 - A.blend_w[0];
-                const double a2 = A.blend_w[1] * g2, b2 = 1.0 - A.blend_w[1];
-                const double2 k1 = A.zk[i], k2 = A.zk[N + i];
-                r1 = make_double2(a1 * r1.x + b1 * k1.x, a1 * r1.y + b1 * k1.y);
-                r2 = make_double2(a2 * r2.x + b2 * k2.x, a2 * r2.y + b2 * k2.y);
-            } else {
-                r1 = make_double2(g1 * r1.x, g1 * r1.y);
-                r2 = make_double2(g2 * r2.x, g2 * r2.y);
-            }
-        }
+        make_r_point(P, A, N, i, r1, r2);
         A.out[i] = r1;
         A.out[N + i] = r2;
     }

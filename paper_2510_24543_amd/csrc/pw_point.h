@@ -90,6 +90,44 @@ __device__ __forceinline__ double pv_inv(const PwParams& P, int c, double shift,
     return 1.0 / ((g > 0.0 ? g : 0.0) + sigma);
 }
 
+// The input of the k-space preconditioners at point i (see MakeRArgs): the
+// residual r = H psi - mu psi (or the given r) as is, times P_V^-1, times
+// D^-1/2, or blended with the kinetic preconditioner's output.
+__device__ __forceinline__ void make_r_point(const PwParams& P, const MakeRArgs& A, long long N, long long i,
+                                             double2& r1, double2& r2)
+{
+    const double2 s1 = A.psi[i], s2 = A.psi[N + i];
+    if (A.rin) {
+        r1 = A.rin[i];
+        r2 = A.rin[N + i];
+    } else {
+        const double2 h1 = A.hpsi[i], h2 = A.hpsi[N + i];
+        r1 = make_double2(h1.x - A.mu[0] * s1.x, h1.y - A.mu[0] * s1.y);
+        r2 = make_double2(h2.x - A.mu[1] * s2.x, h2.y - A.mu[1] * s2.y);
+    }
+    if (A.apply_pv) {
+        const double n1 = sq2(s1), n2 = sq2(s2);
+        const double V = trap_at(P, i);
+        const double2 ml = A.aux[N + i];
+        double g1 = pv_inv(P, 0, A.diag_shift[0], A.sigma, V, n1, n2, ml.x);
+        double g2 = pv_inv(P, 1, A.diag_shift[1], A.sigma, V, n1, n2, ml.y);
+        if (A.apply_pv == 2) {
+            g1 = sqrt(g1);
+            g2 = sqrt(g2);
+        }
+        if (A.apply_pv == 3) {   // blend with the kinetic preconditioner's output zk
+            const double a1 = A.blend_w[0] * g1, b1 = 1.0 - A.blend_w[0];
+            const double a2 = A.blend_w[1] * g2, b2 = 1.0 - A.blend_w[1];
+            const double2 k1 = A.zk[i], k2 = A.zk[N + i];
+            r1 = make_double2(a1 * r1.x + b1 * k1.x, a1 * r1.y + b1 * k1.y);
+            r2 = make_double2(a2 * r2.x + b2 * k2.x, a2 * r2.y + b2 * k2.y);
+        } else {
+            r1 = make_double2(g1 * r1.x, g1 * r1.y);
+            r2 = make_double2(g2 * r2.x, g2 * r2.y);
+        }
+    }
+}
+
 // Operands of the direction-write pass at one point (ZM = DirArgs::zmode).
 template <int ZM>
 struct DirIn {

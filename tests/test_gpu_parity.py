@@ -341,8 +341,10 @@ def test_every_variant_of_the_fused_direction_write(solver, orc, n, pc):
     """The direction write fused with the line search's forward z pass (tuning
     slot [2][1]) in every plan variant of a z axis n long, with P_V (pc 1) and
     with z from the k-space passes (pc 3 the composite P_Delta^-1 P_V^-1, pc 2
-    P_Delta^-1): four steps of the solver against the oracle's, step by step
-    (E to 1e-11, alpha, beta, E1, E2 to 1e-8, the same decisions)."""
+    P_Delta^-1, whose input is formed in the fused first z pass of slot [2][0],
+    set to the same variant): four steps of the solver against the oracle's,
+    step by step (E to 1e-11, alpha, beta, E1, E2 to 1e-8, the same
+    decisions)."""
     from paper_2510_24543_amd import autotune
     params = small_params()
     grid = {"n": [8, 16, n], "lo": [-6.0] * 3, "hi": [6.0] * 3}
@@ -355,6 +357,8 @@ def test_every_variant_of_the_fused_direction_write(solver, orc, n, pc):
         print(f"n {n} pc {pc} fused direction-write variant {v}", flush=True)
         t = {"fft_variant": [r_[:] for r_ in base["fft_variant"]], "pw_blocks": base["pw_blocks"]}
         t["fft_variant"][2][1] = v
+        if pc != 1:
+            t["fft_variant"][2][0] = v
         ctx.set_tuning(t)
         _, rep, log = ctx.solve(torch.from_numpy(psi0), opts, log_cap=4)
         assert rep["iters"] == repo["iters"] == 4, v
