@@ -394,9 +394,10 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
     const long long N = (long long)n[0] * n[1] * n[2];
     const size_t c2 = sizeof(double2);
     const long long nb_pw = std::min<long long>((N + bec::kPwThreads - 1) / bec::kPwThreads, bec::kPwMaxBlocks);
-    const long long nb_x = bec::fft_max_blocks(n[0], (long long)n[1] * n[2]);
+    // x and y blocks over the line search's half-spectrum geometry (z extent n_z + 2), the larger
+    const long long nb_x = bec::fft_max_blocks(n[0], (long long)n[1] * (n[2] + 2));
     const long long nb_z = bec::fft_max_blocks(n[2], (long long)n[0] * n[1]);
-    const long long nb_y = bec::fft_max_blocks(n[1], (long long)n[0] * n[2]);
+    const long long nb_y = bec::fft_max_blocks(n[1], (long long)n[0] * (n[2] + 2));
     size_t sizes[] = {
         2 * N * c2, 2 * N * c2,                    // psi[0], psi[1]
         2 * N * c2, 2 * N * c2,                    // hpsi[0], hpsi[1]
@@ -404,7 +405,7 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
         2 * N * c2,                                // pdir
         2 * N * c2,                                // r_old
         2 * N * c2,                                // z
-        N * c2,                                    // rho
+        (size_t)n[0] * n[1] * (n[2] + 2) * c2,     // rho (or the line search's half spectra, z extent n_z + 2)
         3 * N * c2,                                // W
         (size_t)(n[0] / 2 + 1) * (n[1] / 2 + 1) * (n[2] / 2 + 1) * sizeof(double),   // udtab
         n[0] * c2, n[1] * c2, n[2] * c2,           // twiddles
@@ -415,7 +416,7 @@ size_t ws_layout(const int n[3], size_t* off /* nullable, 32 entries */)
         (size_t)std::max<long long>(bec::kMaxSums * nb_pw, bec::kDirWriteSums * nb_z) * sizeof(double),
         (size_t)3 * (nb_x + nb_y + nb_z) * sizeof(double),                          // fft partials
         kScalSlots * sizeof(double),                                                // device scalar copies
-        (size_t)bec::kLsEpiSums * nb_z * sizeof(double),                            // line-search partials
+        (size_t)bec::kLsEpiSums * std::max(nb_z, nb_x) * sizeof(double),           // line-search partials
         2 * N * c2,                                                                 // pold
         2 * N * c2,                                                                 // r_new
         2 * N * c2,                                                                 // z_next
@@ -1081,9 +1082,20 @@ static_assert(bec::kIteSums <= kParsevalOut, "imaginary-time sums overlap the Pa
 static_assert(bec::kDirWriteSums + bec::kLsEpiSums <= bec::kMaxSums, "model partials exceed the partials area");
 static_assert(kParsevalOut + 2 <= kScalHeval, "Parseval slots overlap the energy sums");
 
+// Blocks of the line search's z (fused direction write), y and x passes when the
+// densities travel as half spectra (z extent n_z + 2 in the y and x passes).
+void ls_half_blocks(bec_ctx* c, int* nbz, int* nby, int* nbx)
+{
+    const long long nzh = c->n[2] + 2;
+    *nbz = bec::fft_blocks(c->n[2], c->fft_var[2][1], (long long)c->n[0] * c->n[1]);
+    *nby = bec::fft_blocks(c->n[1], c->fft_var[1][0], (long long)c->n[0] * nzh);
+    *nbx = bec::fft_blocks(c->n[0], c->fft_var[0][1], (long long)c->n[1] * nzh);
+}
+
 // Direction write pass (p, r, rho).  With P_V or the composite (zmode 1, 2) and
-// fuse_z bit 0 it is fused with the line search's forward z pass (the z-axis Parseval sums of p and the z
-// transform of the packed rho into W + 2N), which model_launch then skips.
+// fuse_z bit 0 it is fused with the line search's forward z pass (the z-axis
+// Parseval sums of p, and the z transforms of rho_1, rho_2 as half spectra in
+// the rho buffer instead of rho itself), which model_launch then continues.
 bec_status dir_write_launch(bec_ctx* c, const bec::DirArgs& A)
 {
     const double wb = 96.0 + (A.beta != 0.0 || A.dev_dir ? 32.0 : 0.0) + (A.zmode >= 2 ? 32.0 : 0.0) + 80.0;
@@ -1092,17 +1104,19 @@ bec_status dir_write_launch(bec_ctx* c, const bec::DirArgs& A)
         bec::FftPassArgs Z = pass_args(c, 2);
         Z.nfield = 3;
         Z.sign = -1;
-        Z.dst[2] = c->W + 2 * N;
+        Z.dst[2] = c->rho;                            // half spectra, z extent n_z + 2
         // its own plan variant (the z axis has no k-space pass, so the second slot is free)
         const int var = c->fft_var[2][1];
-        const int nbz = bec::fft_blocks(c->n[2], var, Z.npencil);
-        const int nby = bec::fft_blocks(c->n[1], c->fft_var[1][0], (long long)c->n[0] * c->n[2]);
+        int nbz, nby, nbx;
+        ls_half_blocks(c, &nbz, &nby, &nbx);
         Z.tw = c->tw[2];
         Z.partials = c->fft_partials;                 // the z slot of the model's Parseval sums
-        Z.nblk_x = nbz + nby + c->nblk_x;
+        Z.nblk_x = nbz + nby + nbx;
         Z.pscale = (double)c->n[0] * c->n[1];
-        LAUNCH(c, "dir_write_z", (double)N * (wb + 16.0),
-               bec::fft_dirwrite_z_pass(c->n[2], var, Z, c->P, A, c->st));
+        bec::DirArgs Af = A;
+        Af.rho = nullptr;                             // rho itself is not needed on this path
+        LAUNCH(c, "dir_write_z", (double)N * (wb - 16.0) + 16.0 * c->n[0] * c->n[1] * (c->n[2] + 2),
+               bec::fft_dirwrite_z_pass(c->n[2], var, Z, c->P, Af, c->st));
         c->dir_fused = 1;
         c->dir_nblk = nbz;
         return BEC_OK;
@@ -1117,9 +1131,52 @@ bec_status dir_write_launch(bec_ctx* c, const bec::DirArgs& A)
 // of the direction-write, Parseval and epilogue partials (host and device
 // copies), then the step decision on the device (kScalStep) from the state's
 // norms, the previous step and the angle cap.
+bec_status model_finish(bec_ctx* c, int nbp, int nls, const double norm2[2], double alpha_prev, double theta_max);
+
+// The line-search passes after the fused direction write, which left rho_1, rho_2
+// as half spectra along z in c->rho: one y pass (the y-axis Parseval sums of p and
+// the forward y transform of the half spectra) and one x pass (the x-axis Parseval
+// sums of p and, from the forward x transform of the half spectra, the model's
+// density sums in k-space, kOpDipSums); no inverse transform, nothing stored but
+// the y pass's spectra.  Field 2 has its own geometry (z extent n_z + 2).
+bec_status ls_half_passes(bec_ctx* c, int nbz, int nby, int nbx)
+{
+    const long long N = c->N, nzh = c->n[2] + 2, half = (long long)c->n[0] * c->n[1] * nzh;
+    const int nbp = nbz + nby + nbx;
+    for (int axis = 1; axis >= 0; --axis) {
+        bec::FftPassArgs A = pass_args(c, axis);
+        A.nfield = 3;
+        A.sign = -1;
+        A.src[0] = c->pdir;
+        A.src[1] = c->pdir + N;
+        A.src[2] = c->rho;
+        A.dst[0] = A.dst[1] = nullptr;                // Parseval fields: no store
+        A.dst[2] = c->rho;
+        A.op[0] = A.op[1] = bec::kOpParsevalAxis;
+        A.op[2] = axis == 1 ? bec::kOpPlain : bec::kOpDipSums;
+        A.S2 = axis == 1 ? nzh : (long long)c->n[1] * nzh;
+        A.npencil2 = axis == 1 ? (long long)c->n[0] * nzh : A.S2;
+        A.partials = c->fft_partials + (axis == 1 ? nbz : nbz + nby);
+        A.nblk_x = nbp;
+        A.pscale = axis == 1 ? (double)c->n[0] * c->n[2] : (double)c->n[1] * c->n[2];
+        A.ls_partials = c->ls_partials;
+        const int var = c->fft_var[axis][axis == 0 ? 1 : 0];
+        const double bytes = 32.0 * N + (axis == 1 ? 32.0 : 16.0) * half;
+        LAUNCH(c, axis == 1 ? "fft_y_fwd_ls" : "fft_x_ls", bytes,
+               bec::fft_pass(c->n[axis], var, false, A, c->st));
+    }
+    return BEC_OK;
+}
+
 bec_status model_launch(bec_ctx* c, const double norm2[2], double alpha_prev, double theta_max)
 {
     const long long N = c->N;
+    if (c->dir_fused) {
+        int nbz, nby, nbx;
+        ls_half_blocks(c, &nbz, &nby, &nbx);
+        STCHK(ls_half_passes(c, nbz, nby, nbx));
+        return model_finish(c, nbz + nby + nbx, nbx, norm2, alpha_prev, theta_max);
+    }
     // <p_i, T p_i> = sum over the axes a of <p_i, T_a p_i> (T is separable), each
     // from the one-dimensional transform of p itself along a: read-only fields
     // (kOpParsevalAxis) of the z, y and x passes that carry the packed
@@ -1131,14 +1188,13 @@ bec_status model_launch(bec_ctx* c, const double norm2[2], double alpha_prev, do
     double2* dst[3] = {c->W, c->W + N, c->W + 2 * N};    // dst[0..1]: not written
     const int ops_a[3] = {bec::kOpParsevalAxis, bec::kOpParsevalAxis, bec::kOpPlain};
     const int ops[3] = {bec::kOpParsevalAxis, bec::kOpParsevalAxis, bec::kOpMulDip};
-    // the z Parseval slot: blocks of the fused direction write, or of the z pass below
-    const int nbz = c->dir_fused ? c->dir_nblk : bec::fft_blocks(c->n[2], c->fft_var[2][0], (long long)c->n[0] * c->n[1]);
+    const int nbz = bec::fft_blocks(c->n[2], c->fft_var[2][0], (long long)c->n[0] * c->n[1]);
     const int nby = bec::fft_blocks(c->n[1], c->fft_var[1][0], (long long)c->n[0] * c->n[2]);
     const int nbp = nbz + nby + c->nblk_x;
     const ParsevalOut pz{c->fft_partials, nbp, (double)c->n[0] * c->n[1]};
     const ParsevalOut py{c->fft_partials + nbz, nbp, (double)c->n[0] * c->n[2]};
     const ParsevalOut px{c->fft_partials + nbz + nby, nbp, (double)c->n[1] * c->n[2]};
-    if (!c->dir_fused) STCHK(run_pass(c, 2, src, dst, 3, -1, 1.0, ops_a, nullptr, nullptr, 0.0, &pz));
+    STCHK(run_pass(c, 2, src, dst, 3, -1, 1.0, ops_a, nullptr, nullptr, 0.0, &pz));
     STCHK(run_pass(c, 1, src_p, dst, 3, -1, 1.0, ops_a, nullptr, nullptr, 0.0, &py));
     STCHK(run_pass(c, 0, src_p, dst, 3, -1, 1.0, ops, nullptr, nullptr, 0.0, &px));
     STCHK(run_pass(c, 1, dst + 2, dst + 2, 1, +1, 1.0, nullptr, nullptr));
@@ -1149,12 +1205,20 @@ bec_status model_launch(bec_ctx* c, const double norm2[2], double alpha_prev, do
     const int nblk_z = bec::fft_blocks(c->n[2], c->fft_var[2][0], zA.npencil);
     LAUNCH(c, "fft_z_inv_ls", (double)N * 32.0,
            bec::fft_zinv_ls_pass(c->n[2], c->fft_var[2][0], zA, c->rho, c->ls_partials, c->st));
+    return model_finish(c, nbp, nblk_z, norm2, alpha_prev, theta_max);
+}
+
+// One reduction of the direction-write, Parseval (nbp blocks per field) and
+// line-search (nls blocks) partials, then the step decision on the device.
+bec_status model_finish(bec_ctx* c, int nbp, int nls, const double norm2[2], double alpha_prev, double theta_max)
+{
+    const long long N = c->N;
     const int o = kScalModel;
     const bec::RedSeg s1{c->partials, c->dir_nblk, bec::kDirWriteSums, c->scal + o, c->dscal + o};
     const bec::RedSeg s2{c->fft_partials, nbp, 2, c->scal + o + kParsevalOut, c->dscal + o + kParsevalOut};
-    const bec::RedSeg s3{c->ls_partials, nblk_z, bec::kLsEpiSums, c->scal + o + bec::kDirWriteSums,
+    const bec::RedSeg s3{c->ls_partials, nls, bec::kLsEpiSums, c->scal + o + bec::kDirWriteSums,
                          c->dscal + o + bec::kDirWriteSums};
-    LAUNCH(c, "reduce_final", 8.0 * (bec::kDirWriteSums * c->dir_nblk + 2 * nbp + bec::kLsEpiSums * nblk_z),
+    LAUNCH(c, "reduce_final", 8.0 * (bec::kDirWriteSums * c->dir_nblk + 2 * nbp + bec::kLsEpiSums * nls),
            bec::launch_reduce_segs(s1, s2, s3, c->st));
     bec::StepArgs st{};
     st.D = c->dscal + o;

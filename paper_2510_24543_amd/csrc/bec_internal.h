@@ -90,7 +90,14 @@ enum FftOp : int {
     kOpParsevalAxis = 6,
     // forward along the pass axis, times k_a^2/2 / n_a, inverse, plus acc[f] (if set), store:
     // the axis term T_a of the separable kinetic operator, accumulated over the passes
-    kOpKinAxis = 7
+    kOpKinAxis = 7,
+    // x pass of the line search's densities held as half spectra (field 2 with its own
+    // geometry, see S2): forward x, then the kLsEpiSums model sums in k-space, no store.
+    // Pencil 2m holds rho^_1 and pencil 2m+1 rho^_2 at the same (k_y, k_z), k_z = 0..n_z/2;
+    // with w = 1 at k_z = 0, n_z/2 and 2 between (Hermitian symmetry of real fields) and
+    // Parseval, sum_n rho_a rho_b = 1/N sum_k w Re(conj(rho^_a) rho^_b) and
+    // sum_n rho_a (U * rho_b) = 1/N sum_k w Ud(k) Re(conj(rho^_a) rho^_b)
+    kOpDipSums = 8
 };
 
 struct BInstState;
@@ -144,6 +151,11 @@ struct FftPassArgs {
     // first, so that the blocks dispatched last are the light ones (set by the
     // launcher; the results do not depend on it)
     int forder[3];
+    // S2 > 0: field 2 has its own geometry, stride S2 and npencil2 pencils (the
+    // line search's half spectra, z extent n_z + 2); grid.x covers the larger
+    // count and blocks beyond a field's pencils contribute nothing
+    long long S2, npencil2;
+    double* ls_partials;   // kOpDipSums: the kLsEpiSums block sums, [sum][block]
 };
 
 // Forward z pass fused with the geodesic trial update: psi_dst = a_i psi_src +
@@ -282,8 +294,10 @@ hipError_t launch_dir_write(const PwParams& P, const DirArgs& a, int nblk, hipSt
 // p, r, rho and the kDirWriteSums sums as launch_dir_write (sums into
 // a.partials [sum][block], grid = fft_blocks(L, variant, z.npencil) blocks),
 // plus the z-axis Parseval sums of p_1, p_2 (z.partials[f * z.nblk_x + block]
-// times z.pscale, f = 0, 1) and the forward z transform of the packed rho into
-// z.dst[2].  z: a z-axis pass of the grid (tw, kaxis, npencil, S = 1).
+// times z.pscale, f = 0, 1) and the z transforms of rho_1 and rho_2 as half
+// spectra: z.dst[2][pencil (L + 2) + 2 k + c] = rho^_(c+1)(k), k = 0..L/2
+// (unpacked from the transform of rho_1 + i rho_2).  z: a z-axis pass of the
+// grid (tw, kaxis, npencil, S = 1).
 hipError_t fft_dirwrite_z_pass(int L, int variant, const FftPassArgs& z, const PwParams& P, const DirArgs& a,
                                hipStream_t s);
 // The make_r pass (rin = null, apply_pv 0..2) fused with the forward z pass of

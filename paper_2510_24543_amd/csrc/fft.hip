@@ -60,8 +60,9 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
     const int pl = CONTIG ? tid / T : (WLOC ? (tid >> 6) * PW + (tid & 63) % PW : tid % PB);
     const int t = CONTIG ? tid % T : (WLOC ? (tid & 63) / PW : tid / PB);
     const long long pg = (long long)blockIdx.x * PB + pl;
-    const bool valid = pg < A.npencil;
-    const long long S = A.S;
+    const bool geo2 = A.S2 > 0 && f == 2;           // field 2 with its own geometry (uniform per block)
+    const long long S = geo2 ? A.S2 : A.S;
+    const bool valid = pg < (geo2 ? A.npencil2 : A.npencil);
     long long base = 0, s = 0;
     if (valid) {
         const long long o = pg / S;
@@ -130,6 +131,60 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
                     const int j = t + b * T + r * (L / RL);
                     dst[base + (long long)j * S] = sc == 1.0 ? v[b * RL + r] : cscale(v[b * RL + r], sc);
                 }
+        }
+        return;
+    }
+    if (op == kOpDipSums) {
+        // the line search's model sums in k-space: this pencil holds rho^_1 (even slot) or
+        // rho^_2 (odd slot) at k_z = slot / 2; the other density at the same k is on the
+        // lane one up or down (pencils 2m, 2m + 1 share a wavefront, same element index)
+        static_assert(!WLOC || PW >= 2, "a density pair shares a wavefront");
+        constexpr int M = kLsEpiSums;
+        const long long nzh = A.nz + 2;
+        const int iy = (int)(s / nzh), slot = (int)(s - (long long)iy * nzh), kz = slot >> 1;
+        const bool first = (slot & 1) == 0;
+        const int ay = iy <= A.ny / 2 ? iy : A.ny - iy;
+        const double* __restrict__ udk = A.udtab;
+        double acc[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[m] = 0.0;
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int j = t + b * T + r * (L / RL);
+                const double2 a = v[b * RL + r];
+                const double2 o = make_double2(__shfl_xor(a.x, 1, 64), __shfl_xor(a.y, 1, 64));
+                if (valid && first) {
+                    const int ax = j <= L / 2 ? j : L - j;
+                    const double u = udk[((long long)ax * (A.ny / 2 + 1) + ay) * (A.nz / 2 + 1) + kz];
+                    const double p11 = a.x * a.x + a.y * a.y, p12 = a.x * o.x + a.y * o.y;
+                    const double p22 = o.x * o.x + o.y * o.y;
+                    acc[0] += p11;
+                    acc[1] += p12;
+                    acc[2] += p22;
+                    acc[3] += u * p11;
+                    acc[4] += u * p12;
+                    acc[6] += u * p22;
+                }
+            }
+        const double wt = ((kz == 0 || 2 * kz == A.nz) ? 1.0 : 2.0) * A.inv_n;
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[m] *= wt;
+        acc[5] = acc[4];                               // sum rho_2 (U * rho_1) = sum rho_1 (U * rho_2)
+        // fixed-order block reduction of the M sums into ls_partials [m][block]
+        double* sh = reinterpret_cast<double*>(lds);
+        const int lane = tid & 63, w = tid >> 6;
+        __syncthreads();
+        wave_sum_down(acc);
+        if (lane == 0)
+#pragma unroll
+            for (int m = 0; m < M; ++m) sh[m * (NTHR / 64) + w] = acc[m];
+        __syncthreads();
+        if (tid < M) {
+            double sum = 0.0;
+            for (int k = 0; k < NTHR / 64; ++k) sum += sh[tid * (NTHR / 64) + k];
+            A.ls_partials[(long long)tid * gridDim.x + blockIdx.x] = sum;
         }
         return;
     }
@@ -461,7 +516,8 @@ hipError_t launch_cfg(bool contiguous, const FftPassArgs& A0, hipStream_t st)
             }
     }
     constexpr int PB = NTHR / T;
-    dim3 grid((unsigned)((A.npencil + PB - 1) / PB), (unsigned)A.nfield, (unsigned)(A.n_inst > 0 ? A.n_inst : 1));
+    const long long np = A.S2 > 0 && A.nfield > 2 ? std::max(A.npencil, A.npencil2) : A.npencil;
+    dim3 grid((unsigned)((np + PB - 1) / PB), (unsigned)A.nfield, (unsigned)(A.n_inst > 0 ? A.n_inst : 1));
     // plain: every field Plain or ParsevalAxis (a one-axis pass; ParsevalAxis
     // fields only in a forward pass); otherwise the fused pass (mode 2)
     bool plain = true, axis_sums = false, kin = false;

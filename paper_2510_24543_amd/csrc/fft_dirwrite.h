@@ -10,8 +10,10 @@
 // pass does, and keeps p_1, p_2 and the packed rho_1 + i rho_2 in registers.
 // It then transforms them along z: the one-axis Parseval sums of p_i
 // (<p_i, T_z p_i> by |k_z|^2/2 |p^_i|^2, no store) and the forward z transform
-// of the packed density, which the line search's y pass continues.  The
-// separate z pass of the line search -- a second read of p and rho -- is gone.
+// of the packed density, unpacked into the half spectra of rho_1 and rho_2,
+// which the line search's y and x passes continue (the x pass takes the model's
+// density sums in k-space, so no inverse transform follows).  The separate z
+// pass of the line search -- a second read of p and rho -- is gone.
 #pragma once
 
 #include "pw_point.h"
@@ -96,12 +98,22 @@ __global__ __launch_bounds__(NTHR, (dirwrite_prefetch<L, T, ZM>() ? 2 : 1)) void
         acc[M + c] = valid ? s : 0.0;
     }
     PL::template fwd_like<-1>(v2, row, t, Z.tw);
+    // rho_1 and rho_2 are real: with F the transform of rho_1 + i rho_2,
+    // rho^_1(k) = (F(k) + conj F(-k)) / 2 and rho^_2(k) = (F(k) - conj F(-k)) / (2i),
+    // stored for k = 0..L/2 only (the rest is their conjugate mirror), interleaved
+    // per k; F(-k) comes from the pencil's LDS row
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) row[lds_pad(t + b * T + r * (L / RL))] = v2[b * RL + r];
+    pencil_sync<true>();
     if (valid) {
-        double2* d = Z.dst[2];
-#pragma unroll
-        for (int b = 0; b < E / RL; ++b)
-#pragma unroll
-            for (int r = 0; r < RL; ++r) d[base + t + b * T + r * (L / RL)] = v2[b * RL + r];
+        double2* d = Z.dst[2] + pg * (long long)(L + 2);
+        for (int k = t; k <= L / 2; k += T) {
+            const double2 fk = row[lds_pad(k)], fm = row[lds_pad(k == 0 ? 0 : L - k)];
+            d[2 * k] = make_double2(0.5 * (fk.x + fm.x), 0.5 * (fk.y - fm.y));
+            d[2 * k + 1] = make_double2(0.5 * (fk.y + fm.y), -0.5 * (fk.x - fm.x));
+        }
     }
 
     // fixed-order block reduction: the M direction sums into A.partials

@@ -220,7 +220,7 @@ __device__ __forceinline__ void dir_point(const PwParams& P, const DirArgs& A, l
         acc[12 + c] += mlc[c] * n[c];
         acc[16 + c] += rho[c];
     }
-    A.rho[i] = make_double2(rho[0], rho[1]);
+    if (A.rho) A.rho[i] = make_double2(rho[0], rho[1]);
     if (p_pt) {                      // the point's p and rho for a caller that transforms them
         p_pt[0] = p[0];
         p_pt[1] = p[1];
