@@ -1133,13 +1133,13 @@ bec_status dir_write_launch(bec_ctx* c, const bec::DirArgs& A)
 // norms, the previous step and the angle cap.
 bec_status model_finish(bec_ctx* c, int nbp, int nls, const double norm2[2], double alpha_prev, double theta_max);
 
-// The line-search passes after the fused direction write, which left rho_1, rho_2
-// as half spectra along z in c->rho: one y pass (the y-axis Parseval sums of p and
+// The line-search passes once rho_1, rho_2 are half spectra along z in hs (left
+// there by the fused direction write, or by the z pass of model_launch): one y pass (the y-axis Parseval sums of p and
 // the forward y transform of the half spectra) and one x pass (the x-axis Parseval
 // sums of p and, from the forward x transform of the half spectra, the model's
 // density sums in k-space, kOpDipSums); no inverse transform, nothing stored but
 // the y pass's spectra.  Field 2 has its own geometry (z extent n_z + 2).
-bec_status ls_half_passes(bec_ctx* c, int nbz, int nby, int nbx)
+bec_status ls_half_passes(bec_ctx* c, double2* hs, int nbz, int nby, int nbx)
 {
     const long long N = c->N, nzh = c->n[2] + 2, half = (long long)c->n[0] * c->n[1] * nzh;
     const int nbp = nbz + nby + nbx;
@@ -1149,9 +1149,9 @@ bec_status ls_half_passes(bec_ctx* c, int nbz, int nby, int nbx)
         A.sign = -1;
         A.src[0] = c->pdir;
         A.src[1] = c->pdir + N;
-        A.src[2] = c->rho;
+        A.src[2] = hs;
         A.dst[0] = A.dst[1] = nullptr;                // Parseval fields: no store
-        A.dst[2] = c->rho;
+        A.dst[2] = hs;
         A.op[0] = A.op[1] = bec::kOpParsevalAxis;
         A.op[2] = axis == 1 ? bec::kOpPlain : bec::kOpDipSums;
         A.S2 = axis == 1 ? nzh : (long long)c->n[1] * nzh;
@@ -1171,41 +1171,25 @@ bec_status ls_half_passes(bec_ctx* c, int nbz, int nby, int nbx)
 bec_status model_launch(bec_ctx* c, const double norm2[2], double alpha_prev, double theta_max)
 {
     const long long N = c->N;
+    int nbz, nby, nbx;
+    ls_half_blocks(c, &nbz, &nby, &nbx);
     if (c->dir_fused) {
-        int nbz, nby, nbx;
-        ls_half_blocks(c, &nbz, &nby, &nbx);
-        STCHK(ls_half_passes(c, nbz, nby, nbx));
+        STCHK(ls_half_passes(c, c->rho, nbz, nby, nbx));
         return model_finish(c, nbz + nby + nbx, nbx, norm2, alpha_prev, theta_max);
     }
-    // <p_i, T p_i> = sum over the axes a of <p_i, T_a p_i> (T is separable), each
-    // from the one-dimensional transform of p itself along a: read-only fields
-    // (kOpParsevalAxis) of the z, y and x passes that carry the packed
-    // rho_1 + i rho_2 through the dipolar kernel; its last inverse pass is fused
-    // with the model epilogue (K*rho is never stored).  The three passes write
-    // their block sums side by side, summed by one reduction.
-    const double2* src[3] = {c->pdir, c->pdir + N, c->rho};
-    const double2* src_p[3] = {c->pdir, c->pdir + N, c->W + 2 * N};
-    double2* dst[3] = {c->W, c->W + N, c->W + 2 * N};    // dst[0..1]: not written
-    const int ops_a[3] = {bec::kOpParsevalAxis, bec::kOpParsevalAxis, bec::kOpPlain};
-    const int ops[3] = {bec::kOpParsevalAxis, bec::kOpParsevalAxis, bec::kOpMulDip};
-    const int nbz = bec::fft_blocks(c->n[2], c->fft_var[2][0], (long long)c->n[0] * c->n[1]);
-    const int nby = bec::fft_blocks(c->n[1], c->fft_var[1][0], (long long)c->n[0] * c->n[2]);
-    const int nbp = nbz + nby + c->nblk_x;
-    const ParsevalOut pz{c->fft_partials, nbp, (double)c->n[0] * c->n[1]};
-    const ParsevalOut py{c->fft_partials + nbz, nbp, (double)c->n[0] * c->n[2]};
-    const ParsevalOut px{c->fft_partials + nbz + nby, nbp, (double)c->n[1] * c->n[2]};
-    STCHK(run_pass(c, 2, src, dst, 3, -1, 1.0, ops_a, nullptr, nullptr, 0.0, &pz));
-    STCHK(run_pass(c, 1, src_p, dst, 3, -1, 1.0, ops_a, nullptr, nullptr, 0.0, &py));
-    STCHK(run_pass(c, 0, src_p, dst, 3, -1, 1.0, ops, nullptr, nullptr, 0.0, &px));
-    STCHK(run_pass(c, 1, dst + 2, dst + 2, 1, +1, 1.0, nullptr, nullptr));
-    bec::FftPassArgs zA = pass_args(c, 2);
-    zA.nfield = 1;
-    zA.sign = +1;
-    zA.src[0] = zA.dst[0] = dst[2];
-    const int nblk_z = bec::fft_blocks(c->n[2], c->fft_var[2][0], zA.npencil);
-    LAUNCH(c, "fft_z_inv_ls", (double)N * 32.0,
-           bec::fft_zinv_ls_pass(c->n[2], c->fft_var[2][0], zA, c->rho, c->ls_partials, c->st));
-    return model_finish(c, nbp, nblk_z, norm2, alpha_prev, theta_max);
+    // after the grid-stride direction write: a z pass with the z-axis Parseval sums of p
+    // and the half spectra of rho (from the packed rho it stored) into W + N, then the same
+    // y and x passes (no launch between them and the z pass writes W)
+    nbz = bec::fft_blocks(c->n[2], c->fft_var[2][0], (long long)c->n[0] * c->n[1]);
+    {
+        const double2* src[3] = {c->pdir, c->pdir + N, c->rho};
+        double2* dst[3] = {nullptr, nullptr, c->W + N};
+        const int ops[3] = {bec::kOpParsevalAxis, bec::kOpParsevalAxis, bec::kOpHalfSpectra};
+        const ParsevalOut pz{c->fft_partials, nbz + nby + nbx, (double)c->n[0] * c->n[1]};
+        STCHK(run_pass(c, 2, src, dst, 3, -1, 1.0, ops, nullptr, nullptr, 0.0, &pz));
+    }
+    STCHK(ls_half_passes(c, c->W + N, nbz, nby, nbx));
+    return model_finish(c, nbz + nby + nbx, nbx, norm2, alpha_prev, theta_max);
 }
 
 // One reduction of the direction-write, Parseval (nbp blocks per field) and
@@ -2262,11 +2246,13 @@ struct BatchGroup {
     int n[3] = {0, 0, 0};
     long long N = 0;
     int first = 0, count = 0, nblk = 0, nblk_x = 0;
-    int nblk_pz = 0, nblk_py = 0;  // blocks of the z and y passes (Parseval axis sums of the line search)
+    int nblk_pz = 0, nblk_py = 0;  // blocks of the z and y passes (Parseval axis sums of the line search);
+                                   // nblk_x, nblk_py over the half-spectrum geometry (z extent n_z + 2)
     int var[3] = {0, 0, 0};        // FFT plan variant per axis (the x pass is always the k-space pass)
     double2 *psi = nullptr, *hpsi = nullptr, *aux = nullptr, *p = nullptr, *r_old = nullptr, *rho = nullptr,
             *W = nullptr, *zbuf = nullptr;
     double *partials = nullptr, *fft_partials = nullptr, *udtab = nullptr, *kv[3] = {}, *vv[3] = {};
+    double* ls_partials = nullptr;  // the line search's k-space sums, [instance][sum][x-pass block]
     double2* tw[3] = {};
     long long udsize = 0;
     int* ids_all = nullptr;        // device: 0..count-1
@@ -2377,8 +2363,9 @@ size_t batch_layout(int n_inst, const bec_grid* grids, std::vector<size_t>* off)
         const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
         const long long cnt = r.second;
         const int nblk = group_nblk(N);
-        const int nbx = bec::fft_max_blocks(g.n[0], (long long)g.n[1] * g.n[2]);   // any plan variant
-        const int nby = bec::fft_max_blocks(g.n[1], (long long)g.n[0] * g.n[2]);
+        // any plan variant; x and y over the line search's half spectra (z extent n_z + 2)
+        const int nbx = bec::fft_max_blocks(g.n[0], (long long)g.n[1] * (g.n[2] + 2));
+        const int nby = bec::fft_max_blocks(g.n[1], (long long)g.n[0] * (g.n[2] + 2));
         const int nbz = bec::fft_max_blocks(g.n[2], (long long)g.n[0] * g.n[1]);
         const size_t ud = (size_t)(g.n[0] / 2 + 1) * (g.n[1] / 2 + 1) * (g.n[2] / 2 + 1);
         size_t gs[] = {cnt * 4 * N * c2, cnt * 4 * N * c2, cnt * 4 * N * c2,  // psi, hpsi, aux (2 buffers)
@@ -2387,6 +2374,7 @@ size_t batch_layout(int n_inst, const bec_grid* grids, std::vector<size_t>* off)
                        cnt * 2 * N * c2,                                      // zbuf
                        (size_t)cnt * bec::kMaxSums * nblk * sizeof(double),   // partials
                        (size_t)cnt * 3 * (nbx + nby + nbz) * sizeof(double),  // fft partials
+                       (size_t)cnt * bec::kLsEpiSums * nbx * sizeof(double),  // line-search k-space sums
                        cnt * ud * sizeof(double),                             // dipolar tables
                        cnt * g.n[0] * sizeof(double), cnt * g.n[1] * sizeof(double), cnt * g.n[2] * sizeof(double),
                        cnt * g.n[0] * sizeof(double), cnt * g.n[1] * sizeof(double), cnt * g.n[2] * sizeof(double),
@@ -2517,10 +2505,13 @@ int batch_parseval_stride(const BatchGroup& G) { return G.nblk_pz + G.nblk_py + 
 
 // line-search FFTs: <p_i, T p_i> as the sum of its one-axis terms (kOpParsevalAxis:
 // p_1, p_2 read by each forward pass, nothing stored) while the passes carry the
-// packed dipolar convolution of rho
+// densities: the z pass unpacks the transform of the packed rho_1 + i rho_2 into
+// their half spectra (W + N of each instance, z extent n_z + 2), the y pass
+// carries those, and the x pass forms the model's density sums in k-space
+// (kOpDipSums, into ls_partials); no inverse transform
 bec_status batch_ls_fft(bec_batch* b, const BatchGroup& G)
 {
-    const long long N = G.N;
+    const long long N = G.N, nzh = G.n[2] + 2;
     const int T = batch_parseval_stride(G);
     const long long off[3] = {G.nblk_pz + G.nblk_py, G.nblk_pz, 0};   // per axis x, y, z
     for (int axis = 2; axis >= 0; --axis) {
@@ -2528,22 +2519,24 @@ bec_status batch_ls_fft(bec_batch* b, const BatchGroup& G)
         A.src[0] = G.p;
         A.src[1] = G.p + N;
         A.src_stride[0] = A.src_stride[1] = 2 * N;
-        A.src[2] = axis == 2 ? G.rho : G.W + 2 * N;
+        A.src[2] = axis == 2 ? G.rho : G.W + N;
         A.src_stride[2] = axis == 2 ? N : 3 * N;
-        for (int f = 0; f < 3; ++f) A.dst[f] = G.W + f * N;
+        A.dst[0] = A.dst[1] = nullptr;               // Parseval fields: no store
+        A.dst[2] = G.W + N;
+        A.dst_stride[2] = 3 * N;
         A.op[0] = A.op[1] = bec::kOpParsevalAxis;
-        A.op[2] = axis == 0 ? bec::kOpMulDip : bec::kOpPlain;
+        A.op[2] = axis == 2 ? bec::kOpHalfSpectra : axis == 1 ? bec::kOpPlain : bec::kOpDipSums;
+        if (axis < 2) {
+            A.S2 = axis == 1 ? nzh : (long long)G.n[1] * nzh;
+            A.npencil2 = axis == 1 ? (long long)G.n[0] * nzh : A.S2;
+        }
+        A.ls_partials = G.ls_partials;
         A.partials = G.fft_partials + off[axis];
         A.nblk_x = T;
         A.pscale = (double)(N / G.n[axis]);
         STCHK(bpass(b, G, A, axis, 3, -1));
     }
-    FftPassArgs A = batch_pass_args(G, 1, b->act_dir);
-    A.src[0] = A.dst[0] = G.W + 2 * N;
-    STCHK(bpass(b, G, A, 1, 1, +1));
-    A = batch_pass_args(G, 2, b->act_dir);
-    A.src[0] = A.dst[0] = G.W + 2 * N;
-    return bpass(b, G, A, 2, 1, +1);
+    return BEC_OK;
 }
 
 bec_status breduce(bec_batch* b, const BatchGroup& G, int M, int off)
@@ -2612,8 +2605,9 @@ bec_status batch_round(bec_batch* b, const bec::BOpts& o)
         HIPCHK(bec::launch_b_dir_write(G.g, b->st));
         STCHK(breduce(b, G, bec::kDirWriteSums, bec::kSW));
         STCHK(batch_ls_fft(b, G));
-        HIPCHK(bec::launch_b_ls_epi(G.g, b->st));
-        STCHK(breduce(b, G, bec::kLsEpiSums, bec::kSL));
+        HIPCHK(bec::launch_b_reduce(G.ls_partials, (long long)bec::kLsEpiSums * G.nblk_x, G.nblk_x, G.nblk_x,
+                                    bec::kLsEpiSums, G.g.ids, G.g.n_ids,
+                                    b->sums + (long long)G.first * bec::kBSumStride, bec::kSL, b->st));
         const int T = batch_parseval_stride(G);
         HIPCHK(bec::launch_b_reduce(G.fft_partials, 3LL * T, T, T, 2, G.g.ids, G.g.n_ids,
                                     b->sums + (long long)G.first * bec::kBSumStride, bec::kSP, b->st));
@@ -2707,8 +2701,8 @@ bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_par
             G.first = r.first;
             G.count = r.second;
             G.nblk = group_nblk(G.N);
-            G.nblk_x = bec::fft_blocks(G.n[0], 0, (long long)G.n[1] * G.n[2]);
-            G.nblk_py = bec::fft_blocks(G.n[1], 0, (long long)G.n[0] * G.n[2]);
+            G.nblk_x = bec::fft_blocks(G.n[0], 0, (long long)G.n[1] * (G.n[2] + 2));
+            G.nblk_py = bec::fft_blocks(G.n[1], 0, (long long)G.n[0] * (G.n[2] + 2));
             G.nblk_pz = bec::fft_blocks(G.n[2], 0, (long long)G.n[0] * G.n[1]);
             G.udsize = (long long)(G.n[0] / 2 + 1) * (G.n[1] / 2 + 1) * (G.n[2] / 2 + 1);
             G.psi = (double2*)(base + off[k++]);
@@ -2721,6 +2715,7 @@ bec_status bec_batch_create(int32_t n_inst, const bec_grid* grids, const bec_par
             G.zbuf = (double2*)(base + off[k++]);
             G.partials = (double*)(base + off[k++]);
             G.fft_partials = (double*)(base + off[k++]);
+            G.ls_partials = (double*)(base + off[k++]);
             G.udtab = (double*)(base + off[k++]);
             for (int d = 0; d < 3; ++d) G.kv[d] = (double*)(base + off[k++]);
             for (int d = 0; d < 3; ++d) G.vv[d] = (double*)(base + off[k++]);
@@ -2826,8 +2821,8 @@ bec_status bec_batch_set_tuning(bec_batch* b, const bec_grid* grid, const bec_tu
             if (v[d] < 0 || v[d] >= bec::fft_num_variants(G.n[d]))
                 return fail(BEC_EINVAL, "axis %d: plan variant %d of length %d does not exist", d, v[d], G.n[d]);
         for (int d = 0; d < 3; ++d) G.var[d] = v[d];
-        G.nblk_x = bec::fft_blocks(G.n[0], G.var[0], (long long)G.n[1] * G.n[2]);
-        G.nblk_py = bec::fft_blocks(G.n[1], G.var[1], (long long)G.n[0] * G.n[2]);
+        G.nblk_x = bec::fft_blocks(G.n[0], G.var[0], (long long)G.n[1] * (G.n[2] + 2));
+        G.nblk_py = bec::fft_blocks(G.n[1], G.var[1], (long long)G.n[0] * (G.n[2] + 2));
         G.nblk_pz = bec::fft_blocks(G.n[2], G.var[2], (long long)G.n[0] * G.n[1]);
         ++matched;
     }

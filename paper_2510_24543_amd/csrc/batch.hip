@@ -346,30 +346,6 @@ __global__ __launch_bounds__(kPwThreads) void b_dir_write_kernel(BGroup g)
     bblock_store<kDirWriteSums>(acc, g.partials + (long long)l * kMaxSums * g.nblk, g.nblk);
 }
 
-__global__ __launch_bounds__(kPwThreads) void b_ls_epi_kernel(BGroup g)
-{
-    const int l = g.ids[blockIdx.y], inst = g.first + l;
-    if (!g.act_dir[inst]) return;
-    const long long N = g.N;
-    const double2* rho = g.rho + (long long)l * N;
-    const double2* phr = g.W + (long long)l * 3 * N + 2 * N;
-    double acc[kLsEpiSums];
-#pragma unroll
-    for (int m = 0; m < kLsEpiSums; ++m) acc[m] = 0.0;
-    BSTRIDE(i, N)
-    {
-        const double2 r = rho[i], f = phr[i];
-        acc[0] += r.x * r.x;
-        acc[1] += r.x * r.y;
-        acc[2] += r.y * r.y;
-        acc[3] += r.x * f.x;
-        acc[4] += r.x * f.y;
-        acc[5] += r.y * f.x;
-        acc[6] += r.y * f.y;
-    }
-    bblock_store<kLsEpiSums>(acc, g.partials + (long long)l * kMaxSums * g.nblk, g.nblk);
-}
-
 __global__ __launch_bounds__(kPwThreads) void b_copy_out_kernel(BGroup g)
 {
     const int l = g.ids[blockIdx.y], inst = g.first + l;
@@ -689,11 +665,6 @@ hipError_t launch_b_make_r(const BGroup& g, hipStream_t s)
 hipError_t launch_b_dir_write(const BGroup& g, hipStream_t s)
 {
     hipLaunchKernelGGL(b_dir_write_kernel, bgrid(g), dim3(kPwThreads), 0, s, g);
-    return hipGetLastError();
-}
-hipError_t launch_b_ls_epi(const BGroup& g, hipStream_t s)
-{
-    hipLaunchKernelGGL(b_ls_epi_kernel, bgrid(g), dim3(kPwThreads), 0, s, g);
     return hipGetLastError();
 }
 hipError_t launch_b_copy_out(const BGroup& g, hipStream_t s)

@@ -97,7 +97,11 @@ enum FftOp : int {
     // with w = 1 at k_z = 0, n_z/2 and 2 between (Hermitian symmetry of real fields) and
     // Parseval, sum_n rho_a rho_b = 1/N sum_k w Re(conj(rho^_a) rho^_b) and
     // sum_n rho_a (U * rho_b) = 1/N sum_k w Ud(k) Re(conj(rho^_a) rho^_b)
-    kOpDipSums = 8
+    kOpDipSums = 8,
+    // forward along the contiguous z axis of the packed rho_1 + i rho_2 (sign -1), then the
+    // half spectra of the two real densities stored with z extent n_z + 2: dst[pencil (L + 2)
+    // + 2 k + c] = rho^_(c+1)(k), k = 0..L/2 (the input of the y and x passes of kOpDipSums)
+    kOpHalfSpectra = 9
 };
 
 struct BInstState;
@@ -155,7 +159,7 @@ struct FftPassArgs {
     // line search's half spectra, z extent n_z + 2); grid.x covers the larger
     // count and blocks beyond a field's pencils contribute nothing
     long long S2, npencil2;
-    double* ls_partials;   // kOpDipSums: the kLsEpiSums block sums, [sum][block]
+    double* ls_partials;   // kOpDipSums: the kLsEpiSums block sums, [instance][sum][block]
 };
 
 // Forward z pass fused with the geodesic trial update: psi_dst = a_i psi_src +
@@ -175,15 +179,6 @@ struct TrialZArgs {
                                   // i = 1, 2 instead of their forward z transforms
 };
 hipError_t fft_trial_z_pass(int L, int variant, const FftPassArgs& args, const TrialZArgs& z, hipStream_t s);
-
-// Last inverse pass (z) of the packed line-search density transform fused with
-// the model epilogue: transforms field 0 of args (args.src[0], in place), and
-// instead of storing K*rho accumulates the kLsEpiSums sums (0 rho1 rho1,
-// 1 rho1 rho2, 2 rho2 rho2, 3..6 rho_i (K*rho)_j for ij = 11, 12, 21, 22) into
-// partials[m * grid + block]; grid = fft_blocks(L, variant, args.npencil).
-// args is a z-axis pass (S = 1).
-hipError_t fft_zinv_ls_pass(int L, int variant, const FftPassArgs& args, const double2* rho, double* partials,
-                            hipStream_t s);
 
 // Launch one axis pass of length L over args.nfield fields with plan variant
 // `variant` (0 = default); `contiguous` for the z axis.
@@ -452,7 +447,6 @@ hipError_t launch_b_mark_pre(int n_inst, const BInstState* st, int* act_pre, hip
 // zbuf = the residual of the instances in act_pre, with the papply factor
 hipError_t launch_b_make_r(const BGroup& g, hipStream_t s);
 hipError_t launch_b_dir_write(const BGroup& g, hipStream_t s);
-hipError_t launch_b_ls_epi(const BGroup& g, hipStream_t s);
 hipError_t launch_b_copy_out(const BGroup& g, hipStream_t s);
 // for l = ids[y], y < n_ids: sums[first + l][off + m] = sum_b partials[l * inst_stride + m * row_stride + b]
 hipError_t launch_b_reduce(const double* partials, long long inst_stride, long long row_stride, int nblk, int M,

@@ -87,6 +87,24 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
     constexpr int RL = PL::RL;
     if (KMODE < 2) {
         PL::template fwd_like<KMODE == 0 ? -1 : +1>(v, row, t, tw);
+        if (CONTIG && KMODE == 0 && A.op[f] == kOpHalfSpectra) {   // uniform per block
+            // rho^_1(k) = (F(k) + conj F(-k)) / 2, rho^_2(k) = (F(k) - conj F(-k)) / (2i), k = 0..L/2,
+            // F(-k) through the pencil's LDS row
+#pragma unroll
+            for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+                for (int r = 0; r < RL; ++r) row[lds_pad(t + b * T + r * (L / RL))] = v[b * RL + r];
+            pencil_sync<true>();
+            if (valid) {
+                double2* d = dst + pg * (long long)(L + 2);
+                for (int k = t; k <= L / 2; k += T) {
+                    const double2 fk = row[lds_pad(k)], fm = row[lds_pad(k == 0 ? 0 : L - k)];
+                    d[2 * k] = make_double2(0.5 * (fk.x + fm.x), 0.5 * (fk.y - fm.y));
+                    d[2 * k + 1] = make_double2(0.5 * (fk.y + fm.y), -0.5 * (fk.x - fm.x));
+                }
+            }
+            return;
+        }
         if (KMODE == 0 && A.op[f] == kOpParsevalAxis) {      // uniform per block (f = blockIdx.y)
             const double dka = A.kaxis[(A.per_inst_tab ? (long long)inst * L : 0) + 1];
             double acc = 0.0;
@@ -144,7 +162,7 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
         const int iy = (int)(s / nzh), slot = (int)(s - (long long)iy * nzh), kz = slot >> 1;
         const bool first = (slot & 1) == 0;
         const int ay = iy <= A.ny / 2 ? iy : A.ny - iy;
-        const double* __restrict__ udk = A.udtab;
+        const double* __restrict__ udk = A.udtab + (A.per_inst_tab ? (long long)inst * A.udsize : 0);
         double acc[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) acc[m] = 0.0;
@@ -184,7 +202,7 @@ __global__ __launch_bounds__(NTHR) void fft_pass_kernel(FftPassArgs A)
         if (tid < M) {
             double sum = 0.0;
             for (int k = 0; k < NTHR / 64; ++k) sum += sh[tid * (NTHR / 64) + k];
-            A.ls_partials[(long long)tid * gridDim.x + blockIdx.x] = sum;
+            A.ls_partials[((long long)inst * M + tid) * gridDim.x + blockIdx.x] = sum;
         }
         return;
     }
@@ -448,61 +466,6 @@ __global__ __launch_bounds__(NTHR) void fft_btrial_z_kernel(FftPassArgs A, BGrou
     trial_z_body<L, T, R0, R1, R2, NTHR>(A, Z, w, w + N, w + 2 * N, lds);
 }
 
-template <int L, int T, int R0, int R1, int R2, int NTHR>
-__global__ __launch_bounds__(NTHR) void fft_zinv_ls_kernel(FftPassArgs A, const double2* __restrict__ rho,
-                                                            double* __restrict__ partials)
-{
-    using PL = Plan<L, T, R0, R1, R2, true>;
-    constexpr int E = L / T, PB = NTHR / T, RS = lds_row<L>(), RL = PL::RL, M = kLsEpiSums;
-    __shared__ double2 lds[PB * RS];
-    const int tid = threadIdx.x;
-    const int pl = tid / T, t = tid % T;
-    const long long pg = (long long)blockIdx.x * PB + pl;
-    const bool valid = pg < A.npencil;
-    const long long base = valid ? pg * (long long)L : 0;
-    const double2* __restrict__ src = A.src[0];
-    double2* row = lds + pl * RS;
-    double2 v[E];
-#pragma unroll
-    for (int b = 0; b < E / R0; ++b)
-#pragma unroll
-        for (int r = 0; r < R0; ++r)
-            v[b * R0 + r] = valid ? src[base + t + b * T + r * (L / R0)] : make_double2(0.0, 0.0);
-    PL::template fwd_like<+1>(v, row, t, A.tw);
-    double acc[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) acc[m] = 0.0;
-    if (valid) {
-#pragma unroll
-        for (int b = 0; b < E / RL; ++b)
-#pragma unroll
-            for (int r = 0; r < RL; ++r) {
-                const double2 q = rho[base + t + b * T + r * (L / RL)], f = v[b * RL + r];
-                acc[0] += q.x * q.x;
-                acc[1] += q.x * q.y;
-                acc[2] += q.y * q.y;
-                acc[3] += q.x * f.x;
-                acc[4] += q.x * f.y;
-                acc[5] += q.y * f.x;
-                acc[6] += q.y * f.y;
-            }
-    }
-    // fixed-order block reduction of the M sums
-    double* sh = reinterpret_cast<double*>(lds);
-    const int lane = tid & 63, w = tid >> 6;
-    __syncthreads();
-    wave_sum_down(acc);
-    if (lane == 0)
-#pragma unroll
-        for (int m = 0; m < M; ++m) sh[m * (NTHR / 64) + w] = acc[m];
-    __syncthreads();
-    if (tid < M) {
-        double s = 0.0;
-        for (int k = 0; k < NTHR / 64; ++k) s += sh[tid * (NTHR / 64) + k];
-        partials[(long long)tid * gridDim.x + blockIdx.x] = s;
-    }
-}
-
 template <int L, int T, int R0, int R1, int R2, int NTHR, bool WLOC>
 hipError_t launch_cfg(bool contiguous, const FftPassArgs& A0, hipStream_t st)
 {
@@ -520,13 +483,15 @@ hipError_t launch_cfg(bool contiguous, const FftPassArgs& A0, hipStream_t st)
     dim3 grid((unsigned)((np + PB - 1) / PB), (unsigned)A.nfield, (unsigned)(A.n_inst > 0 ? A.n_inst : 1));
     // plain: every field Plain or ParsevalAxis (a one-axis pass; ParsevalAxis
     // fields only in a forward pass); otherwise the fused pass (mode 2)
-    bool plain = true, axis_sums = false, kin = false;
+    bool plain = true, axis_sums = false, kin = false, halfs = false;
     for (int f = 0; f < A.nfield; ++f) {
-        plain = plain && (A.op[f] == kOpPlain || A.op[f] == kOpParsevalAxis);
+        plain = plain && (A.op[f] == kOpPlain || A.op[f] == kOpParsevalAxis || A.op[f] == kOpHalfSpectra);
         axis_sums = axis_sums || A.op[f] == kOpParsevalAxis;
         kin = kin || A.op[f] == kOpKinAxis;
+        halfs = halfs || A.op[f] == kOpHalfSpectra;
     }
     if (plain && axis_sums && A.sign >= 0) return hipErrorInvalidValue;
+    if (halfs && (!contiguous || A.sign >= 0)) return hipErrorInvalidValue;   // a forward z pass only
 #define BEC_LAUNCH_PASS(C, K, KIND) \
     hipLaunchKernelGGL((fft_pass_kernel<L, T, R0, R1, R2, NTHR, C, K, KIND, (C) ? false : WLOC>), grid, dim3(NTHR), 0, st, A)
     if (contiguous) {
@@ -638,21 +603,6 @@ hipError_t fft_btrial_z_pass(int L, int variant, const FftPassArgs& A, const BGr
     }
     BEC_FFT_VARIANTS(BEC_BCASE)
 #undef BEC_BCASE
-    return hipErrorInvalidValue;
-}
-
-hipError_t fft_zinv_ls_pass(int L, int variant, const FftPassArgs& A, const double2* rho, double* partials,
-                            hipStream_t st)
-{
-    if (A.S != 1) return hipErrorInvalidValue;
-#define BEC_LCASE(LL, VV, T, R0, R1, R2, NT, W)                                                               \
-    if (L == LL && variant == VV) {                                                                           \
-        const dim3 grid((unsigned)((A.npencil + NT / T - 1) / (NT / T)));                                     \
-        hipLaunchKernelGGL((fft_zinv_ls_kernel<LL, T, R0, R1, R2, NT>), grid, dim3(NT), 0, st, A, rho, partials); \
-        return hipGetLastError();                                                                             \
-    }
-    BEC_FFT_VARIANTS(BEC_LCASE)
-#undef BEC_LCASE
     return hipErrorInvalidValue;
 }
 
