@@ -1127,10 +1127,6 @@ bec_status dir_write_launch(bec_ctx* c, const bec::DirArgs& A)
     return BEC_OK;
 }
 
-// Parseval FFT of p, dipolar FFT of rho with the model epilogue, one reduction
-// of the direction-write, Parseval and epilogue partials (host and device
-// copies), then the step decision on the device (kScalStep) from the state's
-// norms, the previous step and the angle cap.
 bec_status model_finish(bec_ctx* c, int nbp, int nls, const double norm2[2], double alpha_prev, double theta_max);
 
 // The line-search passes once rho_1, rho_2 are half spectra along z in hs (left
@@ -1168,6 +1164,11 @@ bec_status ls_half_passes(bec_ctx* c, double2* hs, int nbz, int nby, int nbx)
     return BEC_OK;
 }
 
+// The line-search model after a direction write: the one-axis Parseval sums of p
+// and the densities' sums in k-space (half spectra from the fused direction
+// write, or from a z pass here), one reduction of the direction-write, Parseval
+// and density partials (host and device copies), then the step decision on the
+// device (kScalStep) from the state's norms, the previous step and the angle cap.
 bec_status model_launch(bec_ctx* c, const double norm2[2], double alpha_prev, double theta_max)
 {
     const long long N = c->N;
