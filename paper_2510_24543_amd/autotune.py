@@ -57,6 +57,9 @@ def load_cached(grid: dict, path: str | None = None):
 
 def store(grid: dict, result: dict, path: str | None = None):
     path = path or cache_path()
+    # the LHY table's term count follows from the physical parameters, not from the grid's
+    # launch plan (get_tuning reports it; set_tuning ignores it): not stored
+    result = dict(result, tuning={k: v for k, v in result["tuning"].items() if k != "lhy_terms"})
     data = {}
     if os.path.exists(path):
         try:

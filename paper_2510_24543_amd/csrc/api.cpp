@@ -540,7 +540,7 @@ ClassAVals class_a_sums(const double node5[][5], int n_a, long double n1, long d
 }
 
 // Chebyshev series of f, f', f'' in y = (sqrt x - sqrt(1-x))/(sqrt x + sqrt(1-x))
-// (x = (1+y)^2 / (2 (1+y^2))): the smallest K in 24, 32, ..., kLhyTabMax whose
+// (x = (1+y)^2 / (2 (1+y^2))): the smallest K in 24, 28, ..., kLhyTabMax whose
 // series, summed in double as on the device, stay within 2e-14 of the long-double
 // sums (relative to each function's largest value) at 257 points of [-1, 1].
 // Returns K, or 0 when no K meets that bar (the device keeps the node loop).
@@ -564,7 +564,7 @@ int build_lhy_table(const double node5[][5], int n_a, double* coef /* 3 * kLhyTa
         fmax[1] = std::max(fmax[1], fabsl(ref[m].f1));
         fmax[2] = std::max(fmax[2], fabsl(ref[m].f2));
     }
-    for (int K = 24; K <= bec::kLhyTabMax; K += 8) {
+    for (int K = 24; K <= bec::kLhyTabMax; K += 4) {   // even: the device sums two terms per trip
         std::vector<ClassAVals> v(K);
         for (int k = 0; k < K; ++k) {
             long double x1, x2;
@@ -591,13 +591,15 @@ int build_lhy_table(const double node5[][5], int n_a, double* coef /* 3 * kLhyTa
             const long double want[3] = {ref[m].f, ref[m].f1, ref[m].f2};
             for (int sidx = 0; sidx < 3 && ok; ++sidx) {
                 const double* cs = c.data() + sidx * bec::kLhyTabMax;
-                double pp = 0.0, qq = 0.0;   // the device's order (lhy_cheb in pw_math.h)
-                for (int k = K - 1; k >= 2; k -= 2) {
-                    qq = std::fma(y + y, pp, cs[k] - qq);
-                    pp = std::fma(y + y, qq, cs[k - 1] - pp);
+                // the device's order (lhy_cheb in pw_math.h): ascending k, T_k by recurrence
+                double got = std::fma(cs[1], y, cs[0]), tm = 1.0, tk = y;
+                for (int k = 2; k < K; k += 2) {
+                    const double ta = std::fma(y + y, tk, -tm), tb = std::fma(y + y, ta, -tk);
+                    got = std::fma(cs[k], ta, got);
+                    got = std::fma(cs[k + 1], tb, got);
+                    tm = ta;
+                    tk = tb;
                 }
-                const double b1 = std::fma(y + y, pp, cs[1] - qq);
-                const double got = std::fma(y, b1, cs[0] - pp);
                 if (!(fabsl((long double)got - want[sidx]) <= 2e-14L * fmax[sidx])) ok = false;
             }
         }

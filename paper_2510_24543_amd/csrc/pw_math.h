@@ -56,31 +56,35 @@ struct LhyTab {
     int K;             // terms per series; 0: no table (class-A loop)
 };
 
-// Clenshaw sums of the first NS series at y; the coefficients are uniform across
-// the wavefront and read through the scalar cache (constant address space).
+// Sums of the first NS series at y, sum_k c_k T_k(y) in ascending k, with
+// T_k(y) from the three-term recurrence T_(k+1) = 2y T_k - T_(k-1): one FMA per
+// term for T_k and one per series (Clenshaw's backward form takes two
+// operations per term and series).  K is even: two terms per trip.  The
+// coefficients are uniform across the wavefront and read through the scalar
+// cache (constant address space).
 template <int NS>
 __device__ __forceinline__ void lhy_cheb(const LhyTab& T, double y, double (&g)[NS])
 {
     using cptr = const __attribute__((address_space(4))) double*;
     const cptr c = (cptr)T.c;
-    // b_k = c_k + 2y b_(k+1) - b_(k+2), two terms per trip with the roles of the
-    // two registers alternating (no copies); K is even, so K - 2 terms run in
-    // pairs and b_1 is the last step before f = c_0 + y b_1 - b_2
-    double p[NS], q[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) p[s] = q[s] = 0.0;
     const double y2 = y + y;
-    for (int k = T.K - 1; k >= 2; k -= 2)
+    double s[NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            q[s] = fma(y2, p[s], c[s * kLhyTabMax + k] - q[s]);        // b_k
-            p[s] = fma(y2, q[s], c[s * kLhyTabMax + k - 1] - p[s]);    // b_(k-1)
+    for (int q = 0; q < NS; ++q) s[q] = fma(c[q * kLhyTabMax + 1], y, c[q * kLhyTabMax]);
+    double tm = 1.0, tk = y;   // T_(k-2), T_(k-1)
+    for (int k = 2; k < T.K; k += 2) {
+        const double ta = fma(y2, tk, -tm);   // T_k
+        const double tb = fma(y2, ta, -tk);   // T_(k+1)
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            s[q] = fma(c[q * kLhyTabMax + k], ta, s[q]);
+            s[q] = fma(c[q * kLhyTabMax + k + 1], tb, s[q]);
         }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const double b1 = fma(y2, p[s], c[s * kLhyTabMax + 1] - q[s]);  // p = b_2 here
-        g[s] = fma(y, b1, c[s * kLhyTabMax] - p[s]);
+        tm = ta;
+        tk = tb;
     }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) g[q] = s[q];
 }
 
 // LHY energy density e and de/dn_i at one point.  Values below kTiny are
