@@ -117,8 +117,20 @@ typedef enum { BEC_BETA_HS_PLUS = 0, BEC_BETA_PR_PLUS = 1, BEC_BETA_ZERO = 2 } b
  * from the reduced sums it has just produced, and the host waits once per
  * iteration and checks every decision against the same rules; restarts and
  * backtracking fall back to synchronous launches.  Both give the same iterates
- * bit for bit.  Other bits are rejected (BEC_EINVAL). */
+ * bit for bit.  Bits other than these two are rejected (BEC_EINVAL). */
 #define BEC_SOLVE_SYNCHRONOUS 1
+/* BEC_SOLVE_CONTINUE: continue the iteration the last bec_solve call on this
+ * context stopped at its max_iter (status BEC_ENOTCONV) instead of starting
+ * one: no normalisation, first Hamiltonian or first reduce, and the work that
+ * call had already enqueued for the next step is used.  That call must have had
+ * the same pc, beta, restart_period, sigma, blend and BEC_SOLVE_SYNCHRONOUS bit,
+ * and no other call may have used the context since (else BEC_EINVAL).
+ * psi_inout is only written (the final iterate); max_iter counts this call's
+ * steps, the log starts at its first step (bec_iter.iter keeps the running
+ * index, which the restart period and the stall window use), and report.iters
+ * counts this call's steps.  A solve split this way gives the iterates of one
+ * uninterrupted solve bit for bit. */
+#define BEC_SOLVE_CONTINUE 2
 
 typedef struct {
     int32_t pc;             /* bec_precond                                     */

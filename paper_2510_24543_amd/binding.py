@@ -181,6 +181,10 @@ def make_params(p: dict) -> Params:
     return P
 
 
+# bec_opts.flags bits (include/bec.h)
+SOLVE_SYNCHRONOUS = 1
+SOLVE_CONTINUE = 2
+
 DEFAULT_OPTS = dict(pc=1, beta=0, max_iter=2000, restart_period=50, max_backtrack=30, flags=0,
                     tol_grad=1e-10, tol_dE=0.0, sigma=1e-6, armijo_c1=1e-4,
                     theta_max=1.5707963267948966, tau_rel=1e-14, blend=-1.0)

@@ -277,6 +277,18 @@ struct bec_ctx {
     int dir_fused = 0, dir_nblk = 0;
     int nblk_x = 0;
     int fft_var[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // plan variant per axis: [plain, fused k-space]
+    // the iteration state a bec_solve stopped at its max_iter leaves for BEC_SOLVE_CONTINUE;
+    // every other call that uses the context clears `valid`
+    struct {
+        bool valid = false;
+        bec_opts o{};
+        int cur = 0, n = 0, stall_it = 0;
+        bool have_prev = false, spec_write = false;
+        double E_prev = 0.0, alpha_prev = 0.0, rz_old = 0.0, stall_ref = 0.0;
+        double R[bec::kDirReduceSums] = {};
+        bec_terms t{};
+        double sums[bec::kHevalSums] = {};
+    } resume;
     PwParams P{};
     Prof prof;
 };
@@ -1494,6 +1506,7 @@ bec_status bec_get_tuning(bec_ctx* c, bec_tuning* t)
 
 bec_status bec_set_tuning(bec_ctx* c, const bec_tuning* t)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c || !t) return fail(BEC_EINVAL, "null argument");
     for (int a = 0; a < 3; ++a)
         for (int k = 0; k < 2; ++k)
@@ -1523,6 +1536,7 @@ bec_status bec_fft_variant_count(int32_t L, int32_t* count)
 
 bec_status bec_time_fft_pass(bec_ctx* c, int32_t axis, int32_t kind, int32_t variant, int32_t reps, double* ms_out)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c || !ms_out) return fail(BEC_EINVAL, "null argument");
     if (axis < 0 || axis > 2 || kind < 0 || kind > 2 || (kind == 2 && axis != 0) || reps < 1)
         return fail(BEC_EINVAL, "bad axis / kind / reps");
@@ -1597,6 +1611,7 @@ bec_status bec_destroy(bec_ctx* ctx)
 
 bec_status bec_set_params(bec_ctx* c, const bec_params* params)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c) return fail(BEC_EINVAL, "ctx is null");
     STCHK(check_params(params));
     STCHK(check_params_grid(&c->g, params));
@@ -1607,6 +1622,7 @@ bec_status bec_set_params(bec_ctx* c, const bec_params* params)
 
 bec_status bec_fft3d(bec_ctx* c, const double* in, double* out, int32_t nfield, int32_t sign)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c || !in || !out) return fail(BEC_EINVAL, "null argument");
     if (nfield < 1 || nfield > 3) return fail(BEC_EINVAL, "nfield must be 1..3");
     if (sign != -1 && sign != 1) return fail(BEC_EINVAL, "sign must be -1 or +1");
@@ -1621,6 +1637,7 @@ bec_status bec_fft3d(bec_ctx* c, const double* in, double* out, int32_t nfield, 
 
 bec_status bec_energy(bec_ctx* c, const double* psi, bec_terms* out_h)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c || !psi || !out_h) return fail(BEC_EINVAL, "null argument");
     Eval ev;
     STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
@@ -1631,6 +1648,7 @@ bec_status bec_energy(bec_ctx* c, const double* psi, bec_terms* out_h)
 
 bec_status bec_hamiltonian(bec_ctx* c, const double* psi, double* hpsi, bec_terms* out_h)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c || !psi || !hpsi) return fail(BEC_EINVAL, "null argument");
     Eval ev;
     STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
@@ -1643,6 +1661,7 @@ bec_status bec_hamiltonian(bec_ctx* c, const double* psi, double* hpsi, bec_term
 
 bec_status bec_gradient(bec_ctx* c, const double* psi, double* grad, int32_t projected, bec_terms* out_h)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c || !psi || !grad) return fail(BEC_EINVAL, "null argument");
     Eval ev;
     STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));
@@ -1656,6 +1675,7 @@ bec_status bec_gradient(bec_ctx* c, const double* psi, double* grad, int32_t pro
 
 bec_status bec_energy_gradient_async(bec_ctx* c, const double* psi, double* grad, double* E_dev)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c || !psi || !grad || !E_dev) return fail(BEC_EINVAL, "null argument");
     STCHK(heval_launch(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, nullptr, 0));
     HIPCHK(bec::launch_grad(c->P, c->psi[0], c->hpsi[0], reinterpret_cast<double2*>(grad), 0.0, 0.0,
@@ -1738,6 +1758,7 @@ bec_status bec_gradient_noalloc(const bec_grid* grid, const bec_params* params, 
 bec_status bec_precond_apply_blend(bec_ctx* c, double blend, double sigma, const double* psi, const double* r,
                                    double* z)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c || !psi || !r || !z) return fail(BEC_EINVAL, "null argument");
     if (!(sigma >= 0)) return fail(BEC_EINVAL, "sigma must be >= 0");
     if (!(blend <= 1.0)) return fail(BEC_EINVAL, "blend must be <= 1 (negative: adaptive)");
@@ -1761,6 +1782,7 @@ bec_status bec_precond_apply_blend(bec_ctx* c, double blend, double sigma, const
 
 bec_status bec_precond_apply(bec_ctx* c, int32_t pc, double sigma, const double* psi, const double* r, double* z)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c || !psi || !r || !z) return fail(BEC_EINVAL, "null argument");
     if (pc < 0 || pc > 5) return fail(BEC_EINVAL, "unknown preconditioner %d", pc);
     if (!(sigma >= 0)) return fail(BEC_EINVAL, "sigma must be >= 0");
@@ -1805,6 +1827,7 @@ bec_status bec_precond_apply(bec_ctx* c, int32_t pc, double sigma, const double*
 bec_status bec_linesearch(bec_ctx* c, const double* psi, const double* d, double* psi_out, const bec_opts* o,
                           bec_ls_report* out_h)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c || !psi || !d || !psi_out || !o) return fail(BEC_EINVAL, "null argument");
     if (psi_out == psi) return fail(BEC_EINVAL, "psi_out may not alias psi");
     Eval ev;
@@ -1860,10 +1883,24 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
                      int32_t log_cap)
 {
     if (!c || !psi_inout || !o) return fail(BEC_EINVAL, "null argument");
+    const bool resumable = c->resume.valid;
+    c->resume.valid = false;
     if (o->pc < 0 || o->pc > 5 || o->beta < 0 || o->beta > 2) return fail(BEC_EINVAL, "bad options");
     if (!(o->blend <= 1.0)) return fail(BEC_EINVAL, "blend must be <= 1 (negative: adaptive)");
-    if (o->flags & ~BEC_SOLVE_SYNCHRONOUS) return fail(BEC_EINVAL, "unknown bits in opts.flags: 0x%x", o->flags);
+    if (o->flags & ~(BEC_SOLVE_SYNCHRONOUS | BEC_SOLVE_CONTINUE))
+        return fail(BEC_EINVAL, "unknown bits in opts.flags: 0x%x", o->flags);
     if (o->stall_window < 0) return fail(BEC_EINVAL, "stall_window must be >= 0");
+    const bool cont = (o->flags & BEC_SOLVE_CONTINUE) != 0;
+    if (cont) {
+        const bec_opts& q = c->resume.o;
+        if (!resumable)
+            return fail(BEC_EINVAL, "BEC_SOLVE_CONTINUE: the last call on this context was not a solve stopped at "
+                                    "its max_iter");
+        if (q.pc != o->pc || q.beta != o->beta || q.restart_period != o->restart_period || q.sigma != o->sigma ||
+            q.blend != o->blend || ((q.flags ^ o->flags) & BEC_SOLVE_SYNCHRONOUS))
+            return fail(BEC_EINVAL, "BEC_SOLVE_CONTINUE: pc, beta, restart_period, sigma, blend and the "
+                                    "synchronous bit must be those of the solve it continues");
+    }
     const auto t0 = std::chrono::steady_clock::now();
     const double dV = c->dV;
     const bec_params& p = c->p;
@@ -1871,10 +1908,7 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
     const double wS[2] = {(p.N[0] / Ntot) * (p.N[0] / Ntot), (p.N[1] / Ntot) * (p.N[1] / Ntot)};
     bec_report rep{};
     int cur = 0;
-    STCHK(normalise_into(c, reinterpret_cast<const double2*>(psi_inout), 0));
     Eval ev;
-    STCHK(heval(c, c->psi[0], nullptr, kOne, kZero, 0, &ev));
-
     bool have_prev = false;
     int n = 0, stall_it = 0;
     bec_status status = BEC_ENOTCONV;
@@ -1906,6 +1940,26 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
     double R[bec::kDirReduceSums];
     bool R_ready = false;      // R holds the direction-reduce sums of the current state
     bool spec_write = false;   // the current state's direction write (device beta) is already enqueued
+    if (cont) {   // the state the last solve stopped at: its z and reduce sums are current
+        const auto& s = c->resume;
+        cur = s.cur;
+        n = s.n;
+        stall_it = s.stall_it;
+        have_prev = s.have_prev;
+        spec_write = s.spec_write;
+        E_prev = s.E_prev;
+        alpha_prev = s.alpha_prev;
+        rz_old = s.rz_old;
+        stall_ref = s.stall_ref;
+        std::memcpy(R, s.R, sizeof(R));
+        R_ready = true;
+        ev.t = s.t;
+        std::memcpy(ev.sums, s.sums, sizeof(ev.sums));
+    } else {
+        STCHK(normalise_into(c, reinterpret_cast<const double2*>(psi_inout), 0));
+        STCHK(heval(c, c->psi[0], nullptr, kOne, kZero, 0, &ev));
+    }
+    const int n0 = n;   // steps before this call
 
     for (;;) {
         // 1. residual, preconditioned residual and the conjugacy sums
@@ -1929,7 +1983,7 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
             status = BEC_ESTALLED;
             break;
         }
-        if (n >= o->max_iter) { status = BEC_ENOTCONV; break; }
+        if (n - n0 >= o->max_iter) { status = BEC_ENOTCONV; break; }
 
         // 2. beta (HS+ or PR+), restarts (Sec. IV.C)
         const double beta = bec::rule_beta(R, beta_rule(n, have_prev, rz_old));
@@ -2048,8 +2102,8 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
         if (stagnated) { status = BEC_ESTAGNATED; break; }
 
         // 6. accept
-        if (log_h && n < log_cap) {
-            bec_iter& L = log_h[n];
+        if (log_h && n - n0 < log_cap) {
+            bec_iter& L = log_h[n - n0];
             L.iter = n;
             L.n_trials = trials;
             L.restarted = level >= 1;
@@ -2079,7 +2133,24 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
     }
     HIPCHK(hipMemcpyAsync(psi_inout, c->psi[cur], 2 * c->N * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
-    rep.iters = n;
+    if (status == BEC_ENOTCONV) {   // stopped at max_iter: R (and z) belong to the current state
+        auto& s = c->resume;
+        s.o = *o;
+        s.cur = cur;
+        s.n = n;
+        s.stall_it = stall_it;
+        s.have_prev = have_prev;
+        s.spec_write = spec_write;
+        s.E_prev = E_prev;
+        s.alpha_prev = alpha_prev;
+        s.rz_old = rz_old;
+        s.stall_ref = stall_ref;
+        std::memcpy(s.R, R, sizeof(R));
+        s.t = ev.t;
+        std::memcpy(s.sums, ev.sums, sizeof(ev.sums));
+        s.valid = true;
+    }
+    rep.iters = n - n0;
     rep.status = status;
     rep.final = ev.t;
     rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -2094,6 +2165,7 @@ bec_status bec_solve(bec_ctx* c, double* psi_inout, const bec_opts* o, bec_repor
 bec_status bec_ite_solve(bec_ctx* c, double* psi_inout, const bec_ite_opts* o, bec_report* out_h, double* log_E,
                          int32_t log_cap)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c || !psi_inout || !o) return fail(BEC_EINVAL, "null argument");
     if (!(o->dt > 0.0) || !std::isfinite(o->dt) || o->max_iter < 0 || !(o->tol_dE >= 0.0))
         return fail(BEC_EINVAL, "need dt > 0, tol_dE >= 0, max_iter >= 0");
@@ -2218,6 +2290,7 @@ bec_status bec_ite_solve(bec_ctx* c, double* psi_inout, const bec_ite_opts* o, b
 
 bec_status bec_param_grad(bec_ctx* c, const double* psi, double dG[2][2], double dGdd[2][2], double* dc_lhy)
 {
+    if (c) c->resume.valid = false;   // the context's buffers change
     if (!c || !psi || !dG || !dGdd || !dc_lhy) return fail(BEC_EINVAL, "null argument");
     Eval ev;
     STCHK(heval(c, reinterpret_cast<const double2*>(psi), nullptr, kOne, kZero, 0, &ev));

@@ -172,12 +172,20 @@ class Context:
                      for k, _ in B.LsReport._fields_} | {"status": B.STATUS[st]}
 
     def solve(self, psi0, opts: dict | None = None, log_cap: int = 0):
-        """Preconditioned nonlinear CG; returns (psi, report, log)."""
-        psi = self.field(psi0).clone()
+        """Preconditioned nonlinear CG; returns (psi, report, log).  With
+        opts["flags"] containing SOLVE_CONTINUE the call continues the last solve
+        on this context, which stopped at its max_iter, and psi0 may be None."""
+        o = B.make_opts(opts)
+        if psi0 is None:
+            if not o.flags & B.SOLVE_CONTINUE:
+                raise ValueError("psi0 is needed unless opts['flags'] has SOLVE_CONTINUE")
+            psi = self.empty()
+        else:
+            psi = self.field(psi0).clone()
         rep = B.Report()
         cap = max(int(log_cap), 0)
         logs = (B.Iter * max(cap, 1))()
-        st = B.lib().bec_solve(self._ctx, _ptr(psi), C.byref(B.make_opts(opts)), C.byref(rep), logs, cap)
+        st = B.lib().bec_solve(self._ctx, _ptr(psi), C.byref(o), C.byref(rep), logs, cap)
         B.check(st, "bec_solve", ok=(0, 4, 5, 8))
         out = {"iters": rep.iters, "n_restarts": rep.n_restarts, "n_backtracks": rep.n_backtracks,
                "status": B.STATUS[rep.status], "final": rep.final.to_dict(), "seconds": rep.seconds}
