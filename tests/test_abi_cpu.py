@@ -53,6 +53,12 @@ def test_struct_layouts_match_the_header(tmp_path):
             assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
 
 
+def test_solve_flag_values_match_the_header():
+    src = open(os.path.join(ROOT, "include", "bec.h")).read()
+    defs = dict(re.findall(r"^#define (BEC_SOLVE_\w+) (\d+)", src, flags=re.M))
+    assert defs == {"BEC_SOLVE_SYNCHRONOUS": str(B.SOLVE_SYNCHRONOUS), "BEC_SOLVE_CONTINUE": str(B.SOLVE_CONTINUE)}
+
+
 def grid(n=(32, 32, 32)):
     return B.make_grid({"n": list(n), "lo": [-8.0] * 3, "hi": [8.0] * 3})
 
