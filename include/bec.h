@@ -124,7 +124,9 @@ typedef enum { BEC_BETA_HS_PLUS = 0, BEC_BETA_PR_PLUS = 1, BEC_BETA_ZERO = 2 } b
  * one: no normalisation, first Hamiltonian or first reduce, and the work that
  * call had already enqueued for the next step is used.  That call must have had
  * the same pc, beta, restart_period, sigma, blend and BEC_SOLVE_SYNCHRONOUS bit,
- * and no other call may have used the context since (else BEC_EINVAL).
+ * and no call that computes on the context may have come in between (every
+ * call but bec_get_tuning, bec_profile_enable and bec_profile_read ends the
+ * continuable state; else BEC_EINVAL).
  * psi_inout is only written (the final iterate); max_iter counts this call's
  * steps, the log starts at its first step (bec_iter.iter keeps the running
  * index, which the restart period and the stall window use), and report.iters
